@@ -1,0 +1,174 @@
+/*
+ * erq.h -- C ABI of the MI355X (gfx950) implementation of Extended RaBitQ
+ * (Gao et al., arXiv 2409.09913): B-bit quantisation of rotated vectors and
+ * IVF search on the codes with an int8 x int8 -> int32 matrix-core scan.
+ *
+ * Conventions for every call:
+ *  - All array arguments are DEVICE pointers (memory of the current HIP
+ *    device, e.g. from torch tensors) unless the comment says "host".
+ *    Arrays are dense and row-major.  Vectors live in dp dimensions, where dp
+ *    is the data dimension zero-padded to a multiple of 64 (Sec. 5.1); the
+ *    caller pads.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Device work is
+ *    enqueued asynchronously on it; arguments are validated synchronously
+ *    before anything is enqueued.  Device faults surface at the next
+ *    synchronising call.
+ *  - The caller owns every input, output and workspace buffer; no call keeps
+ *    a caller pointer after it returns.  An erq_index owns the copies it
+ *    makes and frees them in erq_index_destroy.
+ *  - Every call returns an erq_status; on a non-zero status nothing was
+ *    enqueued and erq_last_error() (thread-local) describes the problem.
+ *  - Sizes: dp in [64, 4096] and a multiple of 64; bits (B) in [1, 8];
+ *    n, nq < 2^31.
+ */
+#ifndef ERQ_H
+#define ERQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ERQ_OK = 0,
+    ERQ_EINVAL = 1,        /* null pointer, negative or inconsistent size */
+    ERQ_ESHAPE = 2,        /* dp not a multiple of 64, out of range, ... */
+    ERQ_ENOMEM = 3,        /* allocation failed or workspace too small */
+    ERQ_EUNSUPPORTED = 4,  /* parameter outside what the kernels implement */
+    ERQ_EDEVICE = 5        /* HIP runtime error (message has the HIP text) */
+} erq_status;
+
+/* Thread-local description of the last non-zero status of this thread. */
+const char* erq_last_error(void);
+
+/* ABI version (major*100 + minor). */
+int erq_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* Rotation (Sec. 3.2.1, Sec. 3.4): out = x * P, i.e. every row r of x is    */
+/* replaced by P^T r = P^{-1} r for the random orthogonal P.                 */
+/* x: n x dp, P: dp x dp, out: n x dp (FP32).  precision 0 = FP32 matrix     */
+/* cores, 1 = BF16 inputs with FP32 accumulation.  out must not alias x.     */
+/* ------------------------------------------------------------------------ */
+int erq_rotate(const float* x, int64_t n, int32_t dp, const float* P,
+               int32_t precision, float* out, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Quantisation, Algorithm 1 (Sec. 3.2.2) and the per-vector factors       */
+/* (Sec. 3.3, Sec. 5.1).  rrot: n x dp rotated residuals r' = P^T (o_r - c). */
+/* norm2: n values ||o_r - c||^2, or NULL to use ||r'||^2.                   */
+/* Outputs: codes n x dp uint8 holding y_u in [0, 2^B) (unpacked),            */
+/*   f_add[n] = ||r||^2, f_rescale[n] = -2 ||r||^2 / <y_bar, r'>, so that     */
+/*   est = f_add + ||s||^2 + f_rescale * <y_bar, s'> (Eq. eq:dis to ip with  */
+/*   Eq. eq 3.3: represent); cos_oo[n] = <o_bar, o> (may be NULL).           */
+/* The codeword is the exact maximiser of <y/||y||, r'> over the grid G    */
+/* found by enumerating the critical values in ascending order; equal        */
+/* critical values are taken in ascending dimension order and the first     */
+/* strict maximum wins.  A zero residual gives y_u = 2^{B-1} and zero        */
+/* factors.                                                                  */
+/* ------------------------------------------------------------------------ */
+int erq_quantize(const float* rrot, int64_t n, int32_t dp, int32_t bits,
+                 const float* norm2, uint8_t* codes, float* f_add,
+                 float* f_rescale, float* cos_oo, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Coarse probe of IVF (Sec. 4.1): for every query the nprobe nearest list   */
+/* centroids by squared Euclidean distance (FP32 matrix cores), ascending   */
+/* by (distance, list id).  q: nq x dp raw queries, centroids: nlist x dp.  */
+/* probes: nq x nprobe int32 (output), pdist: nq x nprobe FP32 or NULL.       */
+/* nprobe in [1, min(nlist, 1024)].  workspace: erq_probe_workspace_size.    */
+/* ------------------------------------------------------------------------ */
+int erq_probe_workspace_size(int64_t nq, int64_t nlist, int32_t nprobe, size_t* bytes);
+int erq_coarse_probe(const float* q, int64_t nq, const float* centroids, int64_t nlist,
+                     int32_t dp, int32_t nprobe, int32_t* probes, float* pdist,
+                     void* workspace, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Index: the IVF lists of Sec. 4.1 with the quantisation codes of every     */
+/* member, stored packed for the int8 matrix-core scan, plus the rotation P, */
+/* raw and rotated centroids, ids and factors.  Optionally the raw vectors   */
+/* for an exact re-rank (the paper's setting keeps none, Sec. 2.1).          */
+/* ------------------------------------------------------------------------ */
+typedef struct erq_index_s* erq_index;
+
+/* Empty index for dp-dimensional vectors, B = bits, nlist lists.  P (device,
+   dp x dp FP32) is copied. */
+int erq_index_create(int32_t dp, int32_t bits, int64_t nlist, const float* P,
+                     void* stream, erq_index* out);
+int erq_index_destroy(erq_index idx);
+
+/* Fills the index from caller-made contents (no quantisation on the device):
+   list_off: nlist+1 int64 offsets into the list-ordered arrays; ids: n int64
+   row ids; codes: n x dp uint8 y_u in list order; f_add, f_rescale: n FP32;
+   centroids, centroids_rot: nlist x dp FP32 (centroids_rot = P^T c; NULL ->
+   computed with erq_rotate in FP32).  Replaces previous contents. */
+int erq_index_import(erq_index idx, int64_t n, const int64_t* list_off, const int64_t* ids,
+                     const uint8_t* codes, const float* f_add, const float* f_rescale,
+                     const float* centroids, const float* centroids_rot, void* stream);
+
+/* Index phase on the device (Sec. 3.4 with IVF centring, Sec. 4.1, 5.1):
+   x: n x dp raw vectors (row i has id i); centroids: nlist x dp; assign: n
+   list ids, or NULL to assign every row to its nearest centroid.  Per row:
+   r = x - c, ||r||^2, r' = P^T r (precision as in erq_rotate), Algorithm 1,
+   factors, packing.  keep_raw != 0 keeps a copy of x for erq_rerank.
+   Synchronises `stream` before returning. */
+int erq_index_build(erq_index idx, const float* x, int64_t n, const float* centroids,
+                    const int32_t* assign, int32_t precision, int32_t keep_raw, void* stream);
+
+/* Copies raw vectors (n x dp, id order) into the index for erq_rerank. */
+int erq_index_set_raw(erq_index idx, const float* x, int64_t n, void* stream);
+
+/* Sizes of the index (host outputs; any may be NULL). */
+int erq_index_info(erq_index idx, int64_t* n, int32_t* dp, int32_t* bits, int64_t* nlist,
+                   int64_t* code_bytes);
+
+/* Reads the contents back in list order: list_off (nlist+1), ids (n),
+   codes (n x dp, y_u unpacked from the packed layout), f_add, f_rescale (n),
+   centroids_rot (nlist x dp).  Any output may be NULL. */
+int erq_index_export(erq_index idx, int64_t* list_off, int64_t* ids, uint8_t* codes,
+                     float* f_add, float* f_rescale, float* centroids_rot, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Scan (Sec. 3.3, Sec. 4.1): estimated squared distances of every member of */
+/* the probed lists, kept as the kk smallest per query.                     */
+/* qrot: nq x dp rotated queries q' = P^T q_r; probes: nq x nprobe list ids  */
+/* (entries < 0 are skipped, so queries may probe fewer lists).  Per (query, */
+/* list): s' = q' - c' (FP32), symmetric int8 quantisation of s' with        */
+/* delta = max|s'|/127, s_i = rint(s'_i * 127/max|s'|); <y_u, s_int> exact    */
+/* in int32 on the matrix cores; est = f_add + ||s'||^2 + f_rescale * delta/2 */
+/* * (2 <y_u, s_int> - (2^B - 1) sum s_int) in FP32.                          */
+/* Output: out_ids, out_est nq x kk ascending by (est, id); missing entries  */
+/* are (-1, +inf).  kk in [1, 64].  workspace: erq_scan_workspace_size.      */
+/* ------------------------------------------------------------------------ */
+int erq_scan_workspace_size(erq_index idx, int64_t nq, int32_t nprobe, int32_t kk, size_t* bytes);
+int erq_scan(erq_index idx, const float* qrot, int64_t nq, const int32_t* probes,
+             int32_t nprobe, int32_t kk, int64_t* out_ids, float* out_est,
+             void* workspace, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Exact re-rank: squared Euclidean distance (FP32) between each raw query   */
+/* and its kc candidate rows (ids < 0 skipped), the k smallest ascending by  */
+/* (distance, id).  Needs raw vectors in the index.  q: nq x dp, cand: nq x  */
+/* kc int64; out: nq x k (-1, +inf padded).  kc in [1, 256], k <= kc.        */
+/* ------------------------------------------------------------------------ */
+int erq_rerank(erq_index idx, const float* q, int64_t nq, const int64_t* cand, int32_t kc,
+               int32_t k, int64_t* out_ids, float* out_dist, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Whole query path: rotate, coarse probe, scan, and (rerank_k > 0) exact    */
+/* re-rank of the rerank_k best estimates.  Output nq x k: estimated squared */
+/* distances without re-rank, exact ones with it.  k <= 64, rerank_k <= 64.  */
+/* workspace: erq_search_workspace_size.                                     */
+/* ------------------------------------------------------------------------ */
+int erq_search_workspace_size(erq_index idx, int64_t nq, int32_t nprobe, int32_t k,
+                              int32_t rerank_k, size_t* bytes);
+int erq_search(erq_index idx, const float* q, int64_t nq, int32_t nprobe, int32_t k,
+               int32_t rerank_k, int64_t* out_ids, float* out_dist,
+               void* workspace, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ERQ_H */

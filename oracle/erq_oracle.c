@@ -417,7 +417,8 @@ int orc_search(const int64_t* list_off, const int64_t* ids, const uint8_t* codes
             int64_t nc = 0;
             for (int p = 0; p < nprobe; ++p) {
                 int32_t l = probes[iq * nprobe + p];
-                if (l < 0 || l >= C) { bad = 1; continue; }
+                if (l < 0) continue;                 /* padding: the query probes fewer lists */
+                if (l >= C) { bad = 1; continue; }
                 const float* qv = qrot + iq * (int64_t)dp;
                 const float* cv = crot + (int64_t)l * dp;
                 double ns2 = 0.0;

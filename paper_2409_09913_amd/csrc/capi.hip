@@ -1,0 +1,451 @@
+// C ABI of liberq.so: argument validation, the index object, and the order
+// in which the kernels of each call are enqueued.
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+
+#include "erq_common.h"
+
+namespace erq {
+
+// launchers defined in the other translation units
+hipError_t launch_row_sqnorm(const float* X, int64_t n, int K, float* out, hipStream_t st);
+hipError_t launch_sqdist_pre(const float* A, int64_t n, const float* Bm, int64_t N, int K,
+                             const float* an2, const float* bn2, float* out, hipStream_t st);
+hipError_t launch_pack_n(const uint8_t* codes, const int64_t* list_off, const int64_t* tile_off,
+                         int64_t nlist, int dp, int bits, int64_t ntiles, uint8_t* packed, hipStream_t st);
+hipError_t launch_unpack_n(const uint8_t* packed, const int64_t* list_off, const int64_t* tile_off,
+                           int64_t nlist, int dp, int bits, int64_t ntiles, uint8_t* codes, hipStream_t st);
+hipError_t launch_count(const int32_t* assign, int64_t n, int64_t nlist, int32_t* cnt, int32_t* bad, hipStream_t st);
+hipError_t launch_scatter(const int32_t* assign, int64_t n, const int64_t* off, int32_t* fill, int32_t* ids32,
+                          hipStream_t st);
+hipError_t launch_sort_lists(const int64_t* off, int64_t nlist, int32_t* ids32, int64_t* ids64, hipStream_t st);
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+int fail(int code, const std::string& msg) { g_err = msg; return code; }
+
+void free_index_storage(Index* ix)
+{
+    hipFree(ix->cent); hipFree(ix->cent_rot); hipFree(ix->list_off); hipFree(ix->tile_off);
+    hipFree(ix->list_order); hipFree(ix->ids); hipFree(ix->fac); hipFree(ix->codes);
+    ix->cent = ix->cent_rot = nullptr; ix->list_off = ix->tile_off = nullptr; ix->list_order = nullptr;
+    ix->ids = nullptr; ix->fac = nullptr; ix->codes = nullptr;
+    ix->n = 0; ix->ntiles = 0; ix->h_list_off.clear(); ix->max_list = 0;
+}
+
+namespace {
+
+__global__ void interleave_fac_kernel(const float* a, const float* b, int64_t n, float2* out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = make_float2(a[i], b[i]);
+}
+__global__ void split_fac_kernel(const float2* f, int64_t n, float* a, float* b) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) { if (a) a[i] = f[i].x; if (b) b[i] = f[i].y; }
+}
+__global__ void fill_i32(int32_t* p, int64_t n, int32_t v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+__global__ void gather_topk_kernel(const int32_t* idx, int64_t n, int k, int32_t* out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = idx[i * k];
+}
+__global__ void copy_cols_kernel(const int64_t* ids, const float* est, int64_t nq, int kin, int kout,
+                                 int64_t* oi, float* oe) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nq * kout) return;
+    int64_t q = i / kout; int t = (int)(i % kout);
+    oi[i] = ids[q * kin + t]; oe[i] = est[q * kin + t];
+}
+
+inline unsigned blocks(int64_t n, int th = 256) { return (unsigned)((n + th - 1) / th); }
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int check_dp(int dp, const char* who) {
+    if (dp < 64 || dp > kMaxDp || dp % 64 != 0)
+        return fail(ERQ_ESHAPE, std::string(who) + ": dp must be a multiple of 64 in [64, 4096]");
+    return ERQ_OK;
+}
+
+// host-side list metadata: tile offsets and the longest-first order
+int set_list_meta(Index* ix, const std::vector<int64_t>& off, hipStream_t st) {
+    const int64_t C = ix->nlist;
+    std::vector<int64_t> toff(C + 1, 0);
+    int64_t mx = 0;
+    for (int64_t l = 0; l < C; ++l) {
+        int64_t sz = off[l + 1] - off[l];
+        if (sz < 0) return fail(ERQ_EINVAL, "list offsets must be non-decreasing");
+        mx = std::max(mx, sz);
+        toff[l + 1] = toff[l] + (sz + kTileV - 1) / kTileV;
+    }
+    std::vector<int32_t> order(C);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        return (off[a + 1] - off[a]) > (off[b + 1] - off[b]);
+    });
+    ix->h_list_off = off;
+    ix->max_list = mx;
+    ix->ntiles = toff[C];
+    ERQ_HIP(hipMalloc(&ix->list_off, sizeof(int64_t) * (C + 1)));
+    ERQ_HIP(hipMalloc(&ix->tile_off, sizeof(int64_t) * (C + 1)));
+    ERQ_HIP(hipMalloc(&ix->list_order, sizeof(int32_t) * std::max<int64_t>(C, 1)));
+    ERQ_HIP(hipMemcpyAsync(ix->list_off, off.data(), sizeof(int64_t) * (C + 1), hipMemcpyHostToDevice, st));
+    ERQ_HIP(hipMemcpyAsync(ix->tile_off, toff.data(), sizeof(int64_t) * (C + 1), hipMemcpyHostToDevice, st));
+    ERQ_HIP(hipMemcpyAsync(ix->list_order, order.data(), sizeof(int32_t) * C, hipMemcpyHostToDevice, st));
+    ERQ_HIP(hipStreamSynchronize(st));       // host vectors go out of scope
+    return ERQ_OK;
+}
+
+int probe_impl(const float* q, int64_t nq, const float* cent, int64_t nlist, int dp, int nprobe,
+               int32_t* probes, float* pdist, void* ws, size_t ws_bytes, hipStream_t st);
+
+size_t probe_ws(int64_t nq, int64_t nlist) {
+    return align256(sizeof(float) * nq * nlist) + align256(sizeof(float) * nq) + align256(sizeof(float) * nlist);
+}
+
+int probe_impl(const float* q, int64_t nq, const float* cent, int64_t nlist, int dp, int nprobe,
+               int32_t* probes, float* pdist, void* ws, size_t ws_bytes, hipStream_t st)
+{
+    if (ws_bytes < probe_ws(nq, nlist)) return fail(ERQ_ENOMEM, "coarse probe: workspace too small");
+    char* w = (char*)ws;
+    float* D = (float*)w; w += align256(sizeof(float) * nq * nlist);
+    float* qn = (float*)w; w += align256(sizeof(float) * nq);
+    float* cn = (float*)w;
+    ERQ_HIP(launch_row_sqnorm(q, nq, dp, qn, st));
+    ERQ_HIP(launch_row_sqnorm(cent, nlist, dp, cn, st));
+    ERQ_HIP(launch_sqdist_pre(q, nq, cent, nlist, dp, qn, cn, D, st));
+    ERQ_HIP(launch_row_topk(D, nq, nlist, nprobe, probes, pdist, st));
+    return ERQ_OK;
+}
+
+}  // namespace
+}  // namespace erq
+
+using namespace erq;
+
+struct erq_index_s : public Index {};
+
+extern "C" {
+
+const char* erq_last_error(void) { return g_err.c_str(); }
+int erq_version(void) { return 100; }
+
+int erq_rotate(const float* x, int64_t n, int32_t dp, const float* P, int32_t precision, float* out, void* stream)
+{
+    if (int rc = check_dp(dp, "erq_rotate")) return rc;
+    if (n < 0 || (n > 0 && (!x || !P || !out))) return fail(ERQ_EINVAL, "erq_rotate: null pointer or n < 0");
+    if (precision != 0 && precision != 1) return fail(ERQ_EUNSUPPORTED, "erq_rotate: precision must be 0 or 1");
+    if (x == out) return fail(ERQ_EINVAL, "erq_rotate: out must not alias x");
+    ERQ_HIP(launch_gemm(x, n, dp, P, dp, 0, precision, out, dp, (hipStream_t)stream));
+    return ERQ_OK;
+}
+
+int erq_quantize(const float* rrot, int64_t n, int32_t dp, int32_t bits, const float* norm2,
+                 uint8_t* codes, float* f_add, float* f_rescale, float* cos_oo, void* stream)
+{
+    if (int rc = check_dp(dp, "erq_quantize")) return rc;
+    if (dp > 3072) return fail(ERQ_EUNSUPPORTED, "erq_quantize: dp > 3072 exceeds the LDS window");
+    if (bits < 1 || bits > 8) return fail(ERQ_EUNSUPPORTED, "erq_quantize: bits must be in [1, 8]");
+    if (n < 0 || (n > 0 && (!rrot || !codes))) return fail(ERQ_EINVAL, "erq_quantize: null pointer or n < 0");
+    ERQ_HIP(launch_quantize(rrot, n, dp, bits, norm2, codes, f_add, f_rescale, cos_oo, nullptr, (hipStream_t)stream));
+    return ERQ_OK;
+}
+
+int erq_probe_workspace_size(int64_t nq, int64_t nlist, int32_t nprobe, size_t* bytes)
+{
+    if (!bytes || nq < 0 || nlist < 1 || nprobe < 1) return fail(ERQ_EINVAL, "erq_probe_workspace_size: bad arguments");
+    *bytes = probe_ws(nq, nlist);
+    return ERQ_OK;
+}
+
+int erq_coarse_probe(const float* q, int64_t nq, const float* centroids, int64_t nlist, int32_t dp,
+                     int32_t nprobe, int32_t* probes, float* pdist, void* workspace, size_t ws_bytes, void* stream)
+{
+    if (int rc = check_dp(dp, "erq_coarse_probe")) return rc;
+    if (nq < 0 || nlist < 1 || nlist > (1LL << 31) - 1) return fail(ERQ_EINVAL, "erq_coarse_probe: bad sizes");
+    if (nprobe < 1 || nprobe > 1024 || nprobe > nlist) return fail(ERQ_EUNSUPPORTED, "erq_coarse_probe: nprobe must be in [1, min(nlist, 1024)]");
+    if (nq > 0 && (!q || !centroids || !probes || !workspace)) return fail(ERQ_EINVAL, "erq_coarse_probe: null pointer");
+    return probe_impl(q, nq, centroids, nlist, dp, nprobe, probes, pdist, workspace, ws_bytes, (hipStream_t)stream);
+}
+
+int erq_index_create(int32_t dp, int32_t bits, int64_t nlist, const float* P, void* stream, erq_index* out)
+{
+    if (int rc = check_dp(dp, "erq_index_create")) return rc;
+    if (bits < 1 || bits > 8) return fail(ERQ_EUNSUPPORTED, "erq_index_create: bits must be in [1, 8]");
+    if (nlist < 1 || nlist > (1 << 24)) return fail(ERQ_EINVAL, "erq_index_create: nlist must be in [1, 2^24]");
+    if (!P || !out) return fail(ERQ_EINVAL, "erq_index_create: null pointer");
+    erq_index_s* ix = new (std::nothrow) erq_index_s();
+    if (!ix) return fail(ERQ_ENOMEM, "erq_index_create: out of host memory");
+    ix->dp = dp; ix->bits = bits; ix->nlist = nlist;
+    hipGetDevice(&ix->device);
+    if (hipMalloc(&ix->P, sizeof(float) * dp * dp) != hipSuccess) { delete ix; return fail(ERQ_ENOMEM, "erq_index_create: hipMalloc failed"); }
+    hipError_t e = hipMemcpyAsync(ix->P, P, sizeof(float) * dp * dp, hipMemcpyDeviceToDevice, (hipStream_t)stream);
+    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) { hipFree(ix->P); delete ix; return fail(ERQ_EDEVICE, std::string("erq_index_create: ") + hipGetErrorString(e)); }
+    *out = ix;
+    return ERQ_OK;
+}
+
+int erq_index_destroy(erq_index ix)
+{
+    if (!ix) return ERQ_OK;
+    hipDeviceSynchronize();
+    free_index_storage(ix);
+    hipFree(ix->P);
+    hipFree(ix->raw);
+    delete ix;
+    return ERQ_OK;
+}
+
+int erq_index_import(erq_index ix, int64_t n, const int64_t* list_off, const int64_t* ids,
+                     const uint8_t* codes, const float* f_add, const float* f_rescale,
+                     const float* centroids, const float* centroids_rot, void* stream)
+{
+    if (!ix) return fail(ERQ_EINVAL, "erq_index_import: null index");
+    if (n < 0 || n > (1LL << 31) - 1) return fail(ERQ_EINVAL, "erq_index_import: n out of range");
+    if (!list_off || !centroids || (n > 0 && (!ids || !codes || !f_add || !f_rescale)))
+        return fail(ERQ_EINVAL, "erq_index_import: null pointer");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t C = ix->nlist;
+    const int dp = ix->dp;
+    std::vector<int64_t> off(C + 1);
+    ERQ_HIP(hipMemcpyAsync(off.data(), list_off, sizeof(int64_t) * (C + 1), hipMemcpyDeviceToHost, st));
+    ERQ_HIP(hipStreamSynchronize(st));
+    if (off[0] != 0 || off[C] != n) return fail(ERQ_EINVAL, "erq_index_import: list_off must start at 0 and end at n");
+    free_index_storage(ix);
+    if (int rc = set_list_meta(ix, off, st)) return rc;
+    ix->n = n;
+    ERQ_HIP(hipMalloc(&ix->ids, sizeof(int64_t) * std::max<int64_t>(n, 1)));
+    ERQ_HIP(hipMalloc(&ix->fac, sizeof(float2) * std::max<int64_t>(n, 1)));
+    ERQ_HIP(hipMalloc(&ix->codes, std::max<int64_t>((int64_t)4 * dp * ix->bits * ix->ntiles, 256)));
+    ERQ_HIP(hipMalloc(&ix->cent, sizeof(float) * C * dp));
+    ERQ_HIP(hipMalloc(&ix->cent_rot, sizeof(float) * C * dp));
+    if (n > 0) {
+        ERQ_HIP(hipMemcpyAsync(ix->ids, ids, sizeof(int64_t) * n, hipMemcpyDeviceToDevice, st));
+        hipLaunchKernelGGL(interleave_fac_kernel, dim3(blocks(n)), dim3(256), 0, st, f_add, f_rescale, n, ix->fac);
+        ERQ_HIP(hipGetLastError());
+        ERQ_HIP(launch_pack_n(codes, ix->list_off, ix->tile_off, C, dp, ix->bits, ix->ntiles, ix->codes, st));
+    }
+    ERQ_HIP(hipMemcpyAsync(ix->cent, centroids, sizeof(float) * C * dp, hipMemcpyDeviceToDevice, st));
+    if (centroids_rot)
+        ERQ_HIP(hipMemcpyAsync(ix->cent_rot, centroids_rot, sizeof(float) * C * dp, hipMemcpyDeviceToDevice, st));
+    else
+        ERQ_HIP(launch_gemm(ix->cent, C, dp, ix->P, dp, 0, 0, ix->cent_rot, dp, st));
+    ERQ_HIP(hipStreamSynchronize(st));
+    return ERQ_OK;
+}
+
+int erq_index_set_raw(erq_index ix, const float* x, int64_t n, void* stream)
+{
+    if (!ix || !x) return fail(ERQ_EINVAL, "erq_index_set_raw: null pointer");
+    if (n != ix->n) return fail(ERQ_ESHAPE, "erq_index_set_raw: n differs from the index size");
+    hipFree(ix->raw);
+    ix->raw = nullptr;
+    ERQ_HIP(hipMalloc(&ix->raw, sizeof(float) * std::max<int64_t>(n, 1) * ix->dp));
+    ERQ_HIP(hipMemcpyAsync(ix->raw, x, sizeof(float) * n * ix->dp, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    ERQ_HIP(hipStreamSynchronize((hipStream_t)stream));
+    return ERQ_OK;
+}
+
+int erq_index_build(erq_index ix, const float* x, int64_t n, const float* centroids, const int32_t* assign,
+                    int32_t precision, int32_t keep_raw, void* stream)
+{
+    if (!ix) return fail(ERQ_EINVAL, "erq_index_build: null index");
+    if (n < 0 || n > (1LL << 31) - 1) return fail(ERQ_EINVAL, "erq_index_build: n out of range");
+    if (!centroids || (n > 0 && !x)) return fail(ERQ_EINVAL, "erq_index_build: null pointer");
+    if (precision != 0 && precision != 1) return fail(ERQ_EUNSUPPORTED, "erq_index_build: precision must be 0 or 1");
+    if (ix->dp > 3072) return fail(ERQ_EUNSUPPORTED, "erq_index_build: dp > 3072 exceeds the LDS window");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t C = ix->nlist;
+    const int dp = ix->dp;
+    free_index_storage(ix);
+    hipFree(ix->raw);
+    ix->raw = nullptr;
+    ERQ_HIP(hipMalloc(&ix->cent, sizeof(float) * C * dp));
+    ERQ_HIP(hipMalloc(&ix->cent_rot, sizeof(float) * C * dp));
+    ERQ_HIP(hipMemcpyAsync(ix->cent, centroids, sizeof(float) * C * dp, hipMemcpyDeviceToDevice, st));
+    ERQ_HIP(launch_gemm(ix->cent, C, dp, ix->P, dp, 0, 0, ix->cent_rot, dp, st));
+
+    // assignment (nearest centroid when not given)
+    int32_t* asg = nullptr;
+    int32_t* aux = nullptr;     // cnt | fill | bad
+    ERQ_HIP(hipMalloc(&asg, sizeof(int32_t) * std::max<int64_t>(n, 1)));
+    ERQ_HIP(hipMalloc(&aux, sizeof(int32_t) * (2 * C + 1)));
+    struct Guard { std::vector<void*> p; ~Guard() { for (void* q : p) hipFree(q); } } guard;
+    guard.p.push_back(asg); guard.p.push_back(aux);
+    if (assign) {
+        ERQ_HIP(hipMemcpyAsync(asg, assign, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, st));
+    } else if (n > 0) {
+        const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(n, (int64_t)(1LL << 28) / C));
+        void* pws = nullptr;
+        size_t pb = probe_ws(chunk, C);
+        ERQ_HIP(hipMalloc(&pws, pb));
+        guard.p.push_back(pws);
+        for (int64_t r0 = 0; r0 < n; r0 += chunk) {
+            int64_t m = std::min(chunk, n - r0);
+            if (int rc = probe_impl(x + r0 * dp, m, ix->cent, C, dp, 1, asg + r0, nullptr, pws, pb, st)) return rc;
+        }
+    }
+    int32_t* cnt = aux;
+    int32_t* fillc = aux + C;
+    int32_t* bad = aux + 2 * C;
+    hipLaunchKernelGGL(fill_i32, dim3(blocks(2 * C + 1)), dim3(256), 0, st, aux, 2 * C + 1, 0);
+    ERQ_HIP(launch_count(asg, n, C, cnt, bad, st));
+    std::vector<int32_t> hc(C);
+    int32_t hbad = 0;
+    ERQ_HIP(hipMemcpyAsync(hc.data(), cnt, sizeof(int32_t) * C, hipMemcpyDeviceToHost, st));
+    ERQ_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    ERQ_HIP(hipStreamSynchronize(st));
+    if (hbad != 0) return fail(ERQ_EINVAL, "erq_index_build: assignment outside [0, nlist)");
+    std::vector<int64_t> off(C + 1, 0);
+    for (int64_t l = 0; l < C; ++l) off[l + 1] = off[l] + hc[l];
+    if (int rc = set_list_meta(ix, off, st)) return rc;
+    if (ix->max_list > 16384) return fail(ERQ_EUNSUPPORTED, "erq_index_build: a list holds more than 16384 vectors");
+    ix->n = n;
+    int32_t* ids32 = nullptr;
+    ERQ_HIP(hipMalloc(&ids32, sizeof(int32_t) * std::max<int64_t>(n, 1)));
+    guard.p.push_back(ids32);
+    ERQ_HIP(hipMalloc(&ix->ids, sizeof(int64_t) * std::max<int64_t>(n, 1)));
+    ERQ_HIP(hipMalloc(&ix->fac, sizeof(float2) * std::max<int64_t>(n, 1)));
+    ERQ_HIP(hipMalloc(&ix->codes, std::max<int64_t>((int64_t)4 * dp * ix->bits * ix->ntiles, 256)));
+    ERQ_HIP(launch_scatter(asg, n, ix->list_off, fillc, ids32, st));
+    ERQ_HIP(launch_sort_lists(ix->list_off, C, ids32, ix->ids, st));
+
+    // residual -> rotate -> quantise, in batches, list order
+    uint8_t* codes_u = nullptr;
+    ERQ_HIP(hipMalloc(&codes_u, std::max<int64_t>(n, 1) * dp));
+    guard.p.push_back(codes_u);
+    const int64_t bt = std::max<int64_t>(1, std::min<int64_t>(n, 131072));
+    float *res = nullptr, *rot = nullptr, *nrm = nullptr;
+    ERQ_HIP(hipMalloc(&res, sizeof(float) * bt * dp));
+    ERQ_HIP(hipMalloc(&rot, sizeof(float) * bt * dp));
+    ERQ_HIP(hipMalloc(&nrm, sizeof(float) * bt));
+    guard.p.push_back(res); guard.p.push_back(rot); guard.p.push_back(nrm);
+    for (int64_t v0 = 0; v0 < n; v0 += bt) {
+        int64_t m = std::min(bt, n - v0);
+        ERQ_HIP(launch_residual(x, ix->ids + v0, asg, ix->cent, m, dp, res, nrm, st));
+        ERQ_HIP(launch_gemm(res, m, dp, ix->P, dp, 0, precision, rot, dp, st));
+        ERQ_HIP(launch_quantize(rot, m, dp, ix->bits, nrm, codes_u + v0 * dp, nullptr, nullptr, nullptr,
+                                ix->fac + v0, st));
+    }
+    ERQ_HIP(launch_pack_n(codes_u, ix->list_off, ix->tile_off, C, dp, ix->bits, ix->ntiles, ix->codes, st));
+    if (keep_raw && n > 0) {
+        ERQ_HIP(hipMalloc(&ix->raw, sizeof(float) * n * dp));
+        ERQ_HIP(hipMemcpyAsync(ix->raw, x, sizeof(float) * n * dp, hipMemcpyDeviceToDevice, st));
+    }
+    ERQ_HIP(hipStreamSynchronize(st));
+    return ERQ_OK;
+}
+
+int erq_index_info(erq_index ix, int64_t* n, int32_t* dp, int32_t* bits, int64_t* nlist, int64_t* code_bytes)
+{
+    if (!ix) return fail(ERQ_EINVAL, "erq_index_info: null index");
+    if (n) *n = ix->n;
+    if (dp) *dp = ix->dp;
+    if (bits) *bits = ix->bits;
+    if (nlist) *nlist = ix->nlist;
+    if (code_bytes) *code_bytes = (int64_t)4 * ix->dp * ix->bits * ix->ntiles;
+    return ERQ_OK;
+}
+
+int erq_index_export(erq_index ix, int64_t* list_off, int64_t* ids, uint8_t* codes, float* f_add,
+                     float* f_rescale, float* centroids_rot, void* stream)
+{
+    if (!ix) return fail(ERQ_EINVAL, "erq_index_export: null index");
+    if (!ix->list_off) return fail(ERQ_EINVAL, "erq_index_export: empty index");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t n = ix->n, C = ix->nlist;
+    if (list_off) ERQ_HIP(hipMemcpyAsync(list_off, ix->list_off, sizeof(int64_t) * (C + 1), hipMemcpyDeviceToDevice, st));
+    if (ids && n) ERQ_HIP(hipMemcpyAsync(ids, ix->ids, sizeof(int64_t) * n, hipMemcpyDeviceToDevice, st));
+    if (codes && n) ERQ_HIP(launch_unpack_n(ix->codes, ix->list_off, ix->tile_off, C, ix->dp, ix->bits, ix->ntiles, codes, st));
+    if ((f_add || f_rescale) && n) {
+        hipLaunchKernelGGL(split_fac_kernel, dim3(blocks(n)), dim3(256), 0, st, ix->fac, n, f_add, f_rescale);
+        ERQ_HIP(hipGetLastError());
+    }
+    if (centroids_rot) ERQ_HIP(hipMemcpyAsync(centroids_rot, ix->cent_rot, sizeof(float) * C * ix->dp, hipMemcpyDeviceToDevice, st));
+    return ERQ_OK;
+}
+
+int erq_scan_workspace_size(erq_index ix, int64_t nq, int32_t nprobe, int32_t kk, size_t* bytes)
+{
+    if (!ix || !bytes || nq < 0 || nprobe < 1 || kk < 1) return fail(ERQ_EINVAL, "erq_scan_workspace_size: bad arguments");
+    *bytes = scan_workspace_bytes(nq, nprobe, ix->nlist, kk);
+    return ERQ_OK;
+}
+
+int erq_scan(erq_index ix, const float* qrot, int64_t nq, const int32_t* probes, int32_t nprobe, int32_t kk,
+             int64_t* out_ids, float* out_est, void* workspace, size_t ws_bytes, void* stream)
+{
+    if (!ix || !ix->codes) return fail(ERQ_EINVAL, "erq_scan: index is empty");
+    if (nq < 0 || nq * (int64_t)std::max(nprobe, 1) > (1LL << 31) - 1) return fail(ERQ_EINVAL, "erq_scan: nq out of range");
+    if (nprobe < 1 || nprobe > 1024) return fail(ERQ_EUNSUPPORTED, "erq_scan: nprobe must be in [1, 1024]");
+    if (kk < 1 || kk > 64) return fail(ERQ_EUNSUPPORTED, "erq_scan: kk must be in [1, 64]");
+    if (nq > 0 && (!qrot || !probes || !out_ids || !out_est || !workspace)) return fail(ERQ_EINVAL, "erq_scan: null pointer");
+    if (ix->nlist > 1000000) return fail(ERQ_EUNSUPPORTED, "erq_scan: more than 10^6 lists");
+    return run_scan(ix, qrot, nq, probes, nprobe, kk, out_ids, out_est, workspace, ws_bytes, (hipStream_t)stream);
+}
+
+int erq_rerank(erq_index ix, const float* q, int64_t nq, const int64_t* cand, int32_t kc, int32_t k,
+               int64_t* out_ids, float* out_dist, void* stream)
+{
+    if (!ix || !ix->raw) return fail(ERQ_EINVAL, "erq_rerank: the index holds no raw vectors");
+    if (kc < 1 || kc > 256 || k < 1 || k > kc) return fail(ERQ_EUNSUPPORTED, "erq_rerank: need 1 <= k <= kc <= 256");
+    if (nq < 0 || (nq > 0 && (!q || !cand || !out_ids || !out_dist))) return fail(ERQ_EINVAL, "erq_rerank: bad arguments");
+    ERQ_HIP(launch_rerank(ix->raw, ix->dp, q, nq, cand, kc, k, out_ids, out_dist, (hipStream_t)stream));
+    return ERQ_OK;
+}
+
+static size_t search_ws(Index* ix, int64_t nq, int nprobe, int k, int rerank_k) {
+    const int kk = rerank_k > 0 ? rerank_k : k;
+    size_t b = 0;
+    b += align256(sizeof(float) * nq * ix->dp);           // qrot
+    b += align256(sizeof(int32_t) * nq * nprobe);         // probes
+    b += align256(sizeof(int64_t) * nq * kk);             // candidate ids
+    b += align256(sizeof(float) * nq * kk);               // candidate estimates
+    b += std::max(probe_ws(nq, ix->nlist), scan_workspace_bytes(nq, nprobe, ix->nlist, kk));
+    return b;
+}
+
+int erq_search_workspace_size(erq_index ix, int64_t nq, int32_t nprobe, int32_t k, int32_t rerank_k, size_t* bytes)
+{
+    if (!ix || !bytes || nq < 0 || nprobe < 1 || k < 1 || rerank_k < 0) return fail(ERQ_EINVAL, "erq_search_workspace_size: bad arguments");
+    *bytes = search_ws(ix, nq, nprobe, k, rerank_k);
+    return ERQ_OK;
+}
+
+int erq_search(erq_index ix, const float* q, int64_t nq, int32_t nprobe, int32_t k, int32_t rerank_k,
+               int64_t* out_ids, float* out_dist, void* workspace, size_t ws_bytes, void* stream)
+{
+    if (!ix || !ix->codes) return fail(ERQ_EINVAL, "erq_search: index is empty");
+    if (k < 1 || k > 64) return fail(ERQ_EUNSUPPORTED, "erq_search: k must be in [1, 64]");
+    if (rerank_k < 0 || rerank_k > 64 || (rerank_k > 0 && rerank_k < k)) return fail(ERQ_EUNSUPPORTED, "erq_search: rerank_k must be 0 or in [k, 64]");
+    if (rerank_k > 0 && !ix->raw) return fail(ERQ_EINVAL, "erq_search: re-rank needs raw vectors in the index");
+    if (nprobe < 1 || nprobe > 1024 || nprobe > ix->nlist) return fail(ERQ_EUNSUPPORTED, "erq_search: nprobe must be in [1, min(nlist, 1024)]");
+    if (nq < 0 || nq * (int64_t)nprobe > (1LL << 31) - 1) return fail(ERQ_EINVAL, "erq_search: nq out of range");
+    if (nq == 0) return ERQ_OK;
+    if (!q || !out_ids || !out_dist || !workspace) return fail(ERQ_EINVAL, "erq_search: null pointer");
+    if (ws_bytes < search_ws(ix, nq, nprobe, k, rerank_k)) return fail(ERQ_ENOMEM, "erq_search: workspace too small");
+    hipStream_t st = (hipStream_t)stream;
+    const int kk = rerank_k > 0 ? rerank_k : k;
+    char* w = (char*)workspace;
+    float* qrot = (float*)w; w += align256(sizeof(float) * nq * ix->dp);
+    int32_t* probes = (int32_t*)w; w += align256(sizeof(int32_t) * nq * nprobe);
+    int64_t* cid = (int64_t*)w; w += align256(sizeof(int64_t) * nq * kk);
+    float* cest = (float*)w; w += align256(sizeof(float) * nq * kk);
+    size_t rest = ws_bytes - (size_t)(w - (char*)workspace);
+    ERQ_HIP(launch_gemm(q, nq, ix->dp, ix->P, ix->dp, 0, 0, qrot, ix->dp, st));
+    if (int rc = probe_impl(q, nq, ix->cent, ix->nlist, ix->dp, nprobe, probes, nullptr, w, rest, st)) return rc;
+    if (int rc = run_scan(ix, qrot, nq, probes, nprobe, kk, cid, cest, w, rest, st)) return rc;
+    if (rerank_k > 0) {
+        ERQ_HIP(launch_rerank(ix->raw, ix->dp, q, nq, cid, kk, k, out_ids, out_dist, st));
+    } else {
+        hipLaunchKernelGGL(copy_cols_kernel, dim3(blocks(nq * k)), dim3(256), 0, st, cid, cest, nq, kk, k, out_ids, out_dist);
+        ERQ_HIP(hipGetLastError());
+    }
+    return ERQ_OK;
+}
+
+}  // extern "C"

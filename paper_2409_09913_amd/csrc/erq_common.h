@@ -1,0 +1,105 @@
+// Internal declarations shared by the HIP translation units of liberq.so.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+#include <vector>
+
+#include "../../include/erq.h"
+
+namespace erq {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+constexpr int kWave = 64;
+constexpr int kTileV = 32;      // vectors per packed code tile (rows of one 32x32 MFMA tile)
+constexpr int kMaxDp = 4096;
+
+// ---- status plumbing -------------------------------------------------------
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+#define ERQ_HIP(call)                                                              \
+    do {                                                                           \
+        hipError_t _e = (call);                                                    \
+        if (_e != hipSuccess)                                                      \
+            return ::erq::fail(ERQ_EDEVICE, std::string(#call) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+
+// ---- packed code layout -----------------------------------------------------
+// Codes of one list are stored in tiles of 32 vectors.  A tile holds dp/64
+// K-blocks of 64 dimensions; a K-block holds, for each power-of-two part of
+// the code (see parts_of), 64 lanes x (4*w) bytes, where lane L covers
+// vector (L % 32) and dimensions kb*64 + s*32 + (L/32)*16 + j, s in {0,1},
+// j in [0,16).  Total bytes per tile: 4 * dp * B.
+struct Parts {
+    int n;            // number of parts
+    int w[3];         // width in bits of each part
+    int pos[3];       // bit position of each part inside y_u
+};
+__host__ __device__ inline Parts parts_of(int bits) {
+    Parts p{};
+    switch (bits) {
+        case 1: p.n = 1; p.w[0] = 1; p.pos[0] = 0; break;
+        case 2: p.n = 1; p.w[0] = 2; p.pos[0] = 0; break;
+        case 3: p.n = 2; p.w[0] = 2; p.pos[0] = 0; p.w[1] = 1; p.pos[1] = 2; break;
+        case 4: p.n = 1; p.w[0] = 4; p.pos[0] = 0; break;
+        case 5: p.n = 2; p.w[0] = 4; p.pos[0] = 0; p.w[1] = 1; p.pos[1] = 4; break;
+        case 6: p.n = 2; p.w[0] = 4; p.pos[0] = 0; p.w[1] = 2; p.pos[1] = 4; break;
+        case 7: p.n = 3; p.w[0] = 4; p.pos[0] = 0; p.w[1] = 2; p.pos[1] = 4; p.w[2] = 1; p.pos[2] = 6; break;
+        default: p.n = 1; p.w[0] = 8; p.pos[0] = 0; break;
+    }
+    return p;
+}
+// Stored byte value is y_u for B <= 7 and y_u - 128 (two's complement) for B = 8,
+// so that it is a valid signed int8 for the matrix cores.
+__host__ __device__ inline int stored_offset(int bits) { return bits == 8 ? 128 : 0; }
+
+// ---- the index ---------------------------------------------------------------
+struct Index {
+    int dp = 0, bits = 0;
+    int64_t nlist = 0, n = 0;
+    int device = 0;
+    float* P = nullptr;            // dp x dp
+    float* cent = nullptr;         // nlist x dp raw centroids
+    float* cent_rot = nullptr;     // nlist x dp rotated centroids
+    int64_t* list_off = nullptr;   // nlist + 1 (device)
+    int64_t* tile_off = nullptr;   // nlist + 1, offset of each list's first tile (device)
+    int32_t* list_order = nullptr; // lists by decreasing size (device)
+    int64_t* ids = nullptr;        // n, list order
+    float2* fac = nullptr;         // n, (f_add, f_rescale), list order
+    uint8_t* codes = nullptr;      // ntiles * 4 * dp * bits bytes
+    float* raw = nullptr;          // n x dp raw vectors (id order) or null
+    int64_t ntiles = 0;
+    std::vector<int64_t> h_list_off;
+    int64_t max_list = 0;
+};
+
+void free_index_storage(Index* ix);
+
+// ---- launchers (each returns hipError_t of the launch) ------------------------
+// out[n x N] = A[n x K] * B where B is K x N row-major (b_trans = 0) or N x K
+// row-major (b_trans = 1).  precision 0 = FP32 MFMA, 1 = BF16 MFMA.
+hipError_t launch_gemm(const float* A, int64_t n, int K, const float* B, int N, int b_trans,
+                       int precision, float* out, int64_t ldo, hipStream_t st);
+// per-row k smallest of a n x N FP32 matrix, ascending by (value, column).
+hipError_t launch_row_topk(const float* D, int64_t n, int64_t N, int k, int32_t* idx,
+                           float* val, hipStream_t st);
+hipError_t launch_quantize(const float* rrot, int64_t n, int dp, int bits, const float* norm2,
+                           uint8_t* codes, float* f_add, float* f_rescale, float* cos_oo,
+                           float2* fac, hipStream_t st);
+
+// scan pipeline
+size_t scan_workspace_bytes(int64_t nq, int nprobe, int64_t nlist, int kk);
+int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, int nprobe, int kk,
+             int64_t* out_ids, float* out_est, void* ws, size_t ws_bytes, hipStream_t st);
+hipError_t launch_rerank(const float* raw, int dp, const float* q, int64_t nq, const int64_t* cand,
+                         int kc, int k, int64_t* out_ids, float* out_d, hipStream_t st);
+
+// list building
+hipError_t launch_residual(const float* x, const int64_t* ids, const int32_t* assign, const float* cent,
+                           int64_t n, int dp, float* res, float* norm2, hipStream_t st);
+
+}  // namespace erq

@@ -1,0 +1,207 @@
+// Dense FP32 / BF16 matrix-core GEMM for the rotation by P (Sec. 3.4: the
+// data and the queries are multiplied by P^{-1} = P^T) and for the squared
+// distances of the coarse IVF probe (Sec. 4.1).
+//
+// Workgroup tile 128 x 128, 4 waves each owning 64 x 64 = 2 x 2 tiles of the
+// 32 x 32 MFMA.  FP32: v_mfma_f32_32x32x2_f32, K staged 16 at a time.
+// BF16: v_mfma_f32_32x32x16_bf16 with FP32 accumulation, K staged 32 at a
+// time, inputs rounded to BF16 (nearest even) while staging.
+#include "erq_common.h"
+
+namespace erq {
+
+namespace {
+
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+constexpr int BM = 128, BN = 128;
+
+// 32x32 MFMA output element (lane, reg) -> (row, col) within the tile
+__device__ inline int out_row(int lane, int r) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
+
+__device__ inline unsigned short f2bf(float f) {
+    unsigned u = __float_as_uint(f);
+    if ((u & 0x7F800000u) == 0x7F800000u) return (unsigned short)(u >> 16);   // inf / nan
+    unsigned r = u + 0x7FFFu + ((u >> 16) & 1u);
+    return (unsigned short)(r >> 16);
+}
+
+// EPI: 0 = store C; 1 = store ||a||^2 + ||b||^2 - 2 C
+template <int EPI>
+__global__ __launch_bounds__(256) void gemm_f32_kernel(
+    const float* __restrict__ A, int64_t n, int K, const float* __restrict__ B, int N, int b_trans,
+    float* __restrict__ out, int64_t ldo, const float* __restrict__ an2, const float* __restrict__ bn2)
+{
+    constexpr int BK = 16;
+    __shared__ float As[BK][BM + 4];
+    __shared__ float Bs[BK][BN + 4];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int64_t row0 = (int64_t)blockIdx.y * BM;
+    const int col0 = blockIdx.x * BN;
+    const int wm = (wid >> 1) * 64, wn = (wid & 1) * 64;
+    v16f acc[2][2];
+    for (int a = 0; a < 2; ++a) for (int b = 0; b < 2; ++b) for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
+
+    for (int k0 = 0; k0 < K; k0 += BK) {
+        // A tile: 128 rows x 16 k -> As[k][m]
+        for (int e = tid; e < BM * BK / 4; e += 256) {
+            int m = e >> 2, kq = (e & 3) * 4;
+            int64_t gr = row0 + m;
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (gr < n && k0 + kq < K) v = *(const float4*)(A + gr * (int64_t)K + k0 + kq);
+            As[kq + 0][m] = v.x; As[kq + 1][m] = v.y; As[kq + 2][m] = v.z; As[kq + 3][m] = v.w;
+        }
+        if (!b_trans) {
+            // B is K x N: rows k, 128 contiguous columns
+            for (int e = tid; e < BK * BN / 4; e += 256) {
+                int kk = e / (BN / 4), nq = (e % (BN / 4)) * 4;
+                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (k0 + kk < K && col0 + nq < N) v = *(const float4*)(B + (int64_t)(k0 + kk) * N + col0 + nq);
+                *(float4*)&Bs[kk][nq] = v;
+            }
+        } else {
+            // B is N x K: like A
+            for (int e = tid; e < BN * BK / 4; e += 256) {
+                int nn = e >> 2, kq = (e & 3) * 4;
+                int gc = col0 + nn;
+                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (gc < N && k0 + kq < K) v = *(const float4*)(B + (int64_t)gc * K + k0 + kq);
+                Bs[kq + 0][nn] = v.x; Bs[kq + 1][nn] = v.y; Bs[kq + 2][nn] = v.z; Bs[kq + 3][nn] = v.w;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < BK; ks += 2) {
+            float a0 = As[ks + (lane >> 5)][wm + (lane & 31)];
+            float a1 = As[ks + (lane >> 5)][wm + 32 + (lane & 31)];
+            float b0 = Bs[ks + (lane >> 5)][wn + (lane & 31)];
+            float b1 = Bs[ks + (lane >> 5)][wn + 32 + (lane & 31)];
+            acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+            const int gc = col0 + wn + 32 * b + (lane & 31);
+            if (gc >= N) continue;
+            for (int r = 0; r < 16; ++r) {
+                const int64_t gr = row0 + wm + 32 * a + out_row(lane, r);
+                if (gr >= n) continue;
+                float v = acc[a][b][r];
+                if (EPI == 1) v = (an2[gr] + bn2[gc]) - 2.0f * v;
+                out[gr * ldo + gc] = v;
+            }
+        }
+}
+
+__global__ __launch_bounds__(256) void gemm_bf16_kernel(
+    const float* __restrict__ A, int64_t n, int K, const float* __restrict__ B, int N, int b_trans,
+    float* __restrict__ out, int64_t ldo)
+{
+    constexpr int BK = 32;
+    // row-major by the contraction index so that a lane reads 8 consecutive k
+    __shared__ unsigned short As[BM][BK + 8];
+    __shared__ unsigned short Bs[BN][BK + 8];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int64_t row0 = (int64_t)blockIdx.y * BM;
+    const int col0 = blockIdx.x * BN;
+    const int wm = (wid >> 1) * 64, wn = (wid & 1) * 64;
+    v16f acc[2][2];
+    for (int a = 0; a < 2; ++a) for (int b = 0; b < 2; ++b) for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
+    for (int k0 = 0; k0 < K; k0 += BK) {
+        for (int e = tid; e < BM * BK / 4; e += 256) {
+            int m = e / (BK / 4), kq = (e % (BK / 4)) * 4;
+            int64_t gr = row0 + m;
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (gr < n && k0 + kq < K) v = *(const float4*)(A + gr * (int64_t)K + k0 + kq);
+            As[m][kq + 0] = f2bf(v.x); As[m][kq + 1] = f2bf(v.y); As[m][kq + 2] = f2bf(v.z); As[m][kq + 3] = f2bf(v.w);
+        }
+        if (!b_trans) {
+            for (int e = tid; e < BK * BN / 4; e += 256) {
+                int kk = e / (BN / 4), nq = (e % (BN / 4)) * 4;
+                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (k0 + kk < K && col0 + nq < N) v = *(const float4*)(B + (int64_t)(k0 + kk) * N + col0 + nq);
+                Bs[nq + 0][kk] = f2bf(v.x); Bs[nq + 1][kk] = f2bf(v.y); Bs[nq + 2][kk] = f2bf(v.z); Bs[nq + 3][kk] = f2bf(v.w);
+            }
+        } else {
+            for (int e = tid; e < BN * BK / 4; e += 256) {
+                int nn = e / (BK / 4), kq = (e % (BK / 4)) * 4;
+                int gc = col0 + nn;
+                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (gc < N && k0 + kq < K) v = *(const float4*)(B + (int64_t)gc * K + k0 + kq);
+                Bs[nn][kq + 0] = f2bf(v.x); Bs[nn][kq + 1] = f2bf(v.y); Bs[nn][kq + 2] = f2bf(v.z); Bs[nn][kq + 3] = f2bf(v.w);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < BK; ks += 16) {
+            const int kk = ks + 8 * (lane >> 5);
+            v8bf a0, a1, b0, b1;
+            __builtin_memcpy(&a0, &As[wm + (lane & 31)][kk], 16);
+            __builtin_memcpy(&a1, &As[wm + 32 + (lane & 31)][kk], 16);
+            __builtin_memcpy(&b0, &Bs[wn + (lane & 31)][kk], 16);
+            __builtin_memcpy(&b1, &Bs[wn + 32 + (lane & 31)][kk], 16);
+            acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc[1][1], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+            const int gc = col0 + wn + 32 * b + (lane & 31);
+            if (gc >= N) continue;
+            for (int r = 0; r < 16; ++r) {
+                const int64_t gr = row0 + wm + 32 * a + out_row(lane, r);
+                if (gr < n) out[gr * ldo + gc] = acc[a][b][r];
+            }
+        }
+}
+
+__global__ void row_sqnorm_kernel(const float* __restrict__ X, int64_t n, int K, float* __restrict__ out)
+{
+    int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    int lane = threadIdx.x & 63;
+    if (r >= n) return;
+    float s = 0.0f;
+    for (int k = lane; k < K; k += 64) { float v = X[r * (int64_t)K + k]; s += v * v; }
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) out[r] = s;
+}
+
+}  // namespace
+
+hipError_t launch_gemm(const float* A, int64_t n, int K, const float* B, int N, int b_trans,
+                       int precision, float* out, int64_t ldo, hipStream_t st)
+{
+    if (n <= 0 || N <= 0) return hipSuccess;
+    dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((n + BM - 1) / BM));
+    if (precision == 1)
+        hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, st, A, n, K, B, N, b_trans, out, ldo);
+    else
+        hipLaunchKernelGGL(gemm_f32_kernel<0>, grid, dim3(256), 0, st, A, n, K, B, N, b_trans, out, ldo,
+                           (const float*)nullptr, (const float*)nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_row_sqnorm(const float* X, int64_t n, int K, float* out, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(row_sqnorm_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, X, n, K, out);
+    return hipGetLastError();
+}
+
+// dist = ||a||^2 + ||b||^2 - 2 a.b, with norms an2 (n) and bn2 (N) precomputed
+hipError_t launch_sqdist_pre(const float* A, int64_t n, const float* Bm, int64_t N, int K,
+                             const float* an2, const float* bn2, float* out, hipStream_t st)
+{
+    if (n <= 0 || N <= 0) return hipSuccess;
+    dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((n + BM - 1) / BM));
+    hipLaunchKernelGGL(gemm_f32_kernel<1>, grid, dim3(256), 0, st, A, n, K, Bm, (int)N, 1, out, N, an2, bn2);
+    return hipGetLastError();
+}
+
+}  // namespace erq

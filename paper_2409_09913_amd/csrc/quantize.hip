@@ -1,0 +1,392 @@
+// Algorithm 1 (Quantize) of Extended RaBitQ, Sec. 3.2.2, on gfx950.
+//
+// One workgroup of 256 threads per vector.  In the orthant of r' every
+// coordinate has magnitude a_i; level k_i in [0, K] (K = 2^{B-1}-1) means
+// y_i = +-(k_i + 1/2).  Level k_i moves to m at the critical value
+// t = m / a_i.  Instead of a heap, the critical values are taken in
+// ascending order window by window:
+//   1. sort a descending (ties: dimension ascending) in LDS;
+//   2. a window is the set of events whose key d = a/m (d descending ==
+//      t ascending) lies in [x, d_cur); x is found by bisection on the bit
+//      pattern of the double x, counting events with one binary search per
+//      level; a window holds at most CAP events (CAP >= 2 dp, and an exact
+//      tie group has at most dp events, so bisection always succeeds);
+//   3. the window's events are gathered, bitonic-sorted by (d desc, dim asc),
+//      and prefix-summed in integers: 2<y,r'> as int64 fixed point (a scaled
+//      by the power of two that puts max a in [1,2), 40 fractional bits) and
+//      4||y||^2 exactly; the objective double(2S1)/sqrt(double(4S2)) of every
+//      event is compared, keeping the first strict maximum;
+//   4. the levels of the best event's state are recovered by one binary
+//      search per level (a replay of the enumeration up to that event).
+// Keys d = a/m are correctly rounded doubles of an FP32 a and m <= 127;
+// distinct ratios differ by more than 2^-39 relative, so the double keys order
+// the events exactly as the exact critical values do.
+#include "erq_common.h"
+
+namespace erq {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ inline double wave_sum_d(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+__device__ inline long long wave_sum_ll(long long v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+__device__ inline float wave_max_f(float v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+    return v;
+}
+
+// events before x in key order: d = a/m with the larger d first.
+__device__ inline bool key_before(double d1, int i1, double d2, int i2) {
+    return d1 > d2 || (d1 == d2 && i1 < i2);
+}
+
+// number of j in [0, n) with fl(A[j]/m) >= x  (A sorted descending)
+__device__ inline int count_ge(const float* A, int n, int m, double x) {
+    int lo = 0, hi = n;
+    const double dm = (double)m;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if ((double)A[mid] / dm >= x) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// number of j with (fl(A[j]/m), I[j]) at or before (d, i) in key order
+__device__ inline int count_upto(const float* A, const int* I, int n, int m, double d, int i) {
+    int lo = 0, hi = n;
+    const double dm = (double)m;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        double k = (double)A[mid] / dm;
+        bool le = (k > d) || (k == d && I[mid] <= i);
+        if (le) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+struct Smem {
+    float* A; int* I; long long* afx; double* key; unsigned* pay;
+    int* cprev; int* cnext; int* loff;
+    long long* red_ll; double* red_d; float* red_f; int* misc;
+};
+
+__device__ inline Smem carve(char* base, int SA, int dp, int cap) {
+    Smem s;
+    size_t o = 0;
+    s.key = (double*)(base + o); o += sizeof(double) * cap;
+    s.afx = (long long*)(base + o); o += sizeof(long long) * dp;
+    s.red_ll = (long long*)(base + o); o += sizeof(long long) * 2 * (kThreads + 8);
+    s.red_d = (double*)(base + o); o += sizeof(double) * 8;
+    s.A = (float*)(base + o); o += sizeof(float) * SA;
+    s.I = (int*)(base + o); o += sizeof(int) * SA;
+    s.pay = (unsigned*)(base + o); o += sizeof(unsigned) * cap;
+    s.cprev = (int*)(base + o); o += sizeof(int) * 128;
+    s.cnext = (int*)(base + o); o += sizeof(int) * 128;
+    s.loff = (int*)(base + o); o += sizeof(int) * 132;
+    s.red_f = (float*)(base + o); o += sizeof(float) * 8;
+    s.misc = (int*)(base + o); o += sizeof(int) * 16;
+    return s;
+}
+
+__host__ __device__ inline size_t smem_bytes(int SA, int dp, int cap) {
+    return sizeof(double) * cap + sizeof(long long) * dp + sizeof(long long) * 2 * (kThreads + 8) +
+           sizeof(double) * 8 + sizeof(float) * SA + sizeof(int) * SA + sizeof(unsigned) * cap +
+           sizeof(int) * (128 + 128 + 132) + sizeof(float) * 8 + sizeof(int) * 16;
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(kThreads) void quantize_kernel(
+    const float* __restrict__ rrot, int64_t n_vec, int dp, int bits, int SA, int cap,
+    const float* __restrict__ norm2, uint8_t* __restrict__ codes, float* __restrict__ f_add,
+    float* __restrict__ f_rescale, float* __restrict__ cos_oo, float2* __restrict__ fac)
+{
+    extern __shared__ __align__(16) char smem_raw[];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wid = tid >> 6;
+    const int64_t row = blockIdx.x;
+    if (row >= n_vec) return;
+    Smem s = carve(smem_raw, SA, dp, cap);
+    const float* r = rrot + row * (int64_t)dp;
+    const int K = (1 << (bits - 1)) - 1;
+    const int half = 1 << (bits - 1);
+
+    // ---- load, magnitudes, max ------------------------------------------
+    float lmax = 0.0f;
+    for (int i = tid; i < SA; i += kThreads) {
+        float a = (i < dp) ? fabsf(r[i]) : -1.0f;
+        s.A[i] = a; s.I[i] = i;
+        lmax = fmaxf(lmax, a);
+    }
+    lmax = wave_max_f(lmax);
+    if (lane == 0) s.red_f[wid] = lmax;
+    __syncthreads();
+    const float amax = fmaxf(fmaxf(s.red_f[0], s.red_f[1]), fmaxf(s.red_f[2], s.red_f[3]));
+
+    // ---- fixed point of a (by dimension) ---------------------------------
+    int ex = 0;
+    if (amax > 0.0f) { (void)frexp((double)amax, &ex); ex -= 1; }   // amax in [2^ex, 2^{ex+1})
+    long long s1part = 0;
+    for (int i = tid; i < dp; i += kThreads) {
+        long long v = 0;
+        if (amax > 0.0f) v = (long long)rint(ldexp((double)fabsf(r[i]), 40 - ex));
+        s.afx[i] = v;
+        s1part += v;
+    }
+    s1part = wave_sum_ll(s1part);
+    __syncthreads();                 // red_f reads done before reuse below
+    if (lane == 0) s.red_ll[wid] = s1part;
+
+    // ---- sort a descending, ties by dimension ascending (bitonic) ---------
+    for (int k = 2; k <= SA; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            __syncthreads();
+            for (int t = tid; t < SA / 2; t += kThreads) {
+                int i = 2 * t - (t & (j - 1));
+                int p = i + j;
+                bool up = ((i & k) == 0);          // "up" = descending-by-key block
+                float a0 = s.A[i], a1 = s.A[p];
+                int i0 = s.I[i], i1 = s.I[p];
+                bool first0 = (a0 > a1) || (a0 == a1 && i0 < i1);   // element i before p
+                if (first0 != up) {
+                    s.A[i] = a1; s.A[p] = a0; s.I[i] = i1; s.I[p] = i0;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    long long s1base = s.red_ll[0] + s.red_ll[1] + s.red_ll[2] + s.red_ll[3];
+    long long s2base = dp;
+    // n = number of non-zero magnitudes
+    if (tid == 0) {
+        int lo = 0, hi = dp;
+        while (lo < hi) { int mid = (lo + hi) >> 1; if (s.A[mid] > 0.0f) lo = mid + 1; else hi = mid; }
+        s.misc[0] = lo;
+    }
+    for (int m = tid; m < 128; m += kThreads) s.cprev[m] = 0;
+    __syncthreads();
+    const int nnz = s.misc[0];
+    const long long total = (long long)nnz * K;
+
+    // ---- windows ------------------------------------------------------------
+    long long done = 0;
+    double d_cur = __builtin_huge_val();
+    double best_v = 0.0;            // strict improvement over 0 needed (v_max starts at 0)
+    double best_d = 0.0;
+    int best_i = -1;
+    long long best_s2 = dp;
+    const double xmin = (nnz > 0 && K > 0) ? (double)s.A[nnz - 1] / (double)K : 0.0;
+
+    for (int guard = 0; done < total && guard < (1 << 22); ++guard) {
+        // choose x: all remaining if they fit, else bisect on the bit pattern
+        double x;
+        {
+            const long long remain = total - done;
+            if (remain <= cap) {
+                x = xmin;
+            } else {
+                unsigned long long lo_b = __double_as_longlong(xmin);   // cnt(lo) - done > cap
+                unsigned long long hi_b = __double_as_longlong(d_cur);  // cnt(hi) - done == 0 (or small)
+                x = d_cur;
+                while (true) {
+                    unsigned long long mid_b = lo_b + ((hi_b - lo_b) >> 1);
+                    double xm = __longlong_as_double(mid_b);
+                    if (tid == 0) s.misc[1] = 0;
+                    __syncthreads();
+                    if (tid < K) atomicAdd(&s.misc[1], count_ge(s.A, nnz, tid + 1, xm));
+                    __syncthreads();
+                    long long c = (long long)s.misc[1] - done;
+                    __syncthreads();
+                    if (c > cap) lo_b = mid_b;
+                    else {
+                        hi_b = mid_b;
+                        x = xm;
+                        if (2 * c >= cap) break;
+                    }
+                    if (hi_b - lo_b <= 1) break;
+                }
+            }
+        }
+        // per-level ranges [cprev[m], cnext[m]) and their offsets
+        if (tid < K) s.cnext[tid] = count_ge(s.A, nnz, tid + 1, x);
+        __syncthreads();
+        if (tid == 0) {
+            int acc = 0;
+            for (int m = 0; m < K; ++m) { s.loff[m] = acc; acc += s.cnext[m] - s.cprev[m]; }
+            s.loff[K] = acc;
+        }
+        __syncthreads();
+        const int W = s.loff[K];
+        if (W <= 0) break;            // cannot happen (a tie group has <= dp <= cap/2 events); never spin
+        int S = 1;
+        while (S < W) S <<= 1;
+        // gather
+        for (int t = tid; t < S; t += kThreads) {
+            if (t < W) {
+                int lo = 0, hi = K;            // largest m with loff[m] <= t
+                while (hi - lo > 1) { int mid = (lo + hi) >> 1; if (s.loff[mid] <= t) lo = mid; else hi = mid; }
+                int m = lo + 1;
+                int j = s.cprev[lo] + (t - s.loff[lo]);
+                s.key[t] = (double)s.A[j] / (double)m;
+                s.pay[t] = ((unsigned)m << 12) | (unsigned)s.I[j];
+            } else {
+                s.key[t] = -1.0;
+                s.pay[t] = 0xFFFFFu;
+            }
+        }
+        // bitonic sort of the window by (d desc, dim asc)
+        for (int k = 2; k <= S; k <<= 1) {
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                __syncthreads();
+                for (int t = tid; t < S / 2; t += kThreads) {
+                    int i = 2 * t - (t & (j - 1));
+                    int p = i + j;
+                    bool up = ((i & k) == 0);
+                    double k0 = s.key[i], k1 = s.key[p];
+                    unsigned p0 = s.pay[i], p1 = s.pay[p];
+                    bool first0 = key_before(k0, (int)(p0 & 0xFFFu), k1, (int)(p1 & 0xFFFu));
+                    if (first0 != up) { s.key[i] = k1; s.key[p] = k0; s.pay[i] = p1; s.pay[p] = p0; }
+                }
+            }
+        }
+        __syncthreads();
+        // integer prefix sums over the window; each thread owns a contiguous chunk
+        const int L = (S + kThreads - 1) / kThreads;
+        const int beg = tid * L, end = min(W, beg + L);
+        long long ls1 = 0, ls2 = 0;
+        for (int t = beg; t < end; ++t) {
+            unsigned pp = s.pay[t];
+            ls1 += 2 * s.afx[pp & 0xFFFu];
+            ls2 += 8 * (long long)(pp >> 12);
+        }
+        // block exclusive scan of (ls1, ls2)
+        long long i1 = ls1, i2 = ls2;
+        for (int o = 1; o < 64; o <<= 1) {
+            long long u1 = __shfl_up(i1, o), u2 = __shfl_up(i2, o);
+            if (lane >= o) { i1 += u1; i2 += u2; }
+        }
+        if (lane == 63) { s.red_ll[2 * wid] = i1; s.red_ll[2 * wid + 1] = i2; }
+        __syncthreads();
+        long long w1 = 0, w2 = 0;
+        for (int w = 0; w < wid; ++w) { w1 += s.red_ll[2 * w]; w2 += s.red_ll[2 * w + 1]; }
+        const long long tot1 = s.red_ll[0] + s.red_ll[2] + s.red_ll[4] + s.red_ll[6];
+        const long long tot2 = s.red_ll[1] + s.red_ll[3] + s.red_ll[5] + s.red_ll[7];
+        long long c1 = s1base + w1 + i1 - ls1;
+        long long c2 = s2base + w2 + i2 - ls2;
+        double tb = 0.0; int tpos = -1; long long ts2 = 0;
+        for (int t = beg; t < end; ++t) {
+            unsigned pp = s.pay[t];
+            c1 += 2 * s.afx[pp & 0xFFFu];
+            c2 += 8 * (long long)(pp >> 12);
+            double v = (double)c1 / sqrt((double)c2);
+            if (v > tb) { tb = v; tpos = t; ts2 = c2; }
+        }
+        // block argmax: largest v, earliest position
+        __syncthreads();
+        {
+            double bv = tb; int bp = (tpos < 0) ? 0x7FFFFFFF : tpos; long long bs2 = ts2;
+            for (int o = 32; o > 0; o >>= 1) {
+                double ov = __shfl_xor(bv, o);
+                int op = __shfl_xor(bp, o);
+                long long os2 = __shfl_xor(bs2, o);
+                if (ov > bv || (ov == bv && op < bp)) { bv = ov; bp = op; bs2 = os2; }
+            }
+            if (lane == 0) { s.red_d[wid] = bv; s.misc[4 + wid] = bp; s.red_ll[16 + wid] = bs2; }
+        }
+        __syncthreads();
+        {
+            double bv = s.red_d[0]; int bp = s.misc[4]; long long bs2 = s.red_ll[16];
+            for (int w = 1; w < 4; ++w) {
+                double ov = s.red_d[w]; int op = s.misc[4 + w];
+                if (ov > bv || (ov == bv && op < bp)) { bv = ov; bp = op; bs2 = s.red_ll[16 + w]; }
+            }
+            if (bp != 0x7FFFFFFF && bv > best_v) {
+                best_v = bv;
+                best_d = s.key[bp];
+                best_i = (int)(s.pay[bp] & 0xFFFu);
+                best_s2 = bs2;
+            }
+        }
+        s1base += tot1;
+        s2base += tot2;
+        done += W;
+        d_cur = x;
+        __syncthreads();
+        if (tid < K) s.cprev[tid] = s.cnext[tid];
+        __syncthreads();
+    }
+
+    // ---- replay: levels of the state at the best event ------------------------
+    if (tid < K) s.cnext[tid] = (best_i >= 0) ? count_upto(s.A, s.I, nnz, tid + 1, best_d, best_i) : 0;
+    __syncthreads();
+    double ip = 0.0;
+    uint8_t* crow = codes + row * (int64_t)dp;
+    for (int j = tid; j < dp; j += kThreads) {
+        int lev = 0;
+        if (j < nnz && K > 0) {
+            int lo = 0, hi = K;            // k = #{m : cnext[m-1] > j}, non-increasing in m
+            while (lo < hi) { int mid = (lo + hi + 1) >> 1; if (s.cnext[mid - 1] > j) lo = mid; else hi = mid - 1; }
+            lev = lo;
+        }
+        int dim = s.I[j];
+        float rv = r[dim];
+        bool pos = !(rv < 0.0f);
+        crow[dim] = (uint8_t)(pos ? half + lev : half - 1 - lev);
+        ip += ((double)lev + 0.5) * (double)fabsf(rv);
+    }
+    // ||r||^2
+    double nr = 0.0;
+    if (norm2 == nullptr)
+        for (int i = tid; i < dp; i += kThreads) { double v = (double)r[i]; nr += v * v; }
+    ip = wave_sum_d(ip);
+    nr = wave_sum_d(nr);
+    __syncthreads();
+    if (lane == 0) { s.red_d[wid] = ip; s.red_d[4 + wid] = nr; }
+    __syncthreads();
+    if (tid == 0) {
+        double ipt = (s.red_d[0] + s.red_d[1]) + (s.red_d[2] + s.red_d[3]);
+        double nr2 = norm2 ? (double)norm2[row] : (s.red_d[4] + s.red_d[5]) + (s.red_d[6] + s.red_d[7]);
+        double ny = (double)best_s2 * 0.25;
+        if (best_i < 0) ny = 0.25 * dp;
+        float fa = 0.0f, fr = 0.0f, co = 1.0f;
+        if (nr2 > 0.0 && ipt > 0.0) {
+            fa = (float)nr2;
+            fr = (float)(-2.0 * nr2 / ipt);
+            co = (float)(ipt / (sqrt(ny) * sqrt(nr2)));
+        }
+        if (f_add) f_add[row] = fa;
+        if (f_rescale) f_rescale[row] = fr;
+        if (cos_oo) cos_oo[row] = co;
+        if (fac) fac[row] = make_float2(fa, fr);
+    }
+}
+
+hipError_t launch_quantize(const float* rrot, int64_t n, int dp, int bits, const float* norm2,
+                           uint8_t* codes, float* f_add, float* f_rescale, float* cos_oo,
+                           float2* fac, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    int SA = 1;
+    while (SA < dp) SA <<= 1;
+    int cap = 1;
+    while (cap < 2 * dp) cap <<= 1;
+    if (cap < 4096) cap = 4096;
+    size_t sm = smem_bytes(SA, dp, cap);
+    if (sm > 48 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void*)quantize_kernel,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(quantize_kernel, dim3((unsigned)n), dim3(kThreads), sm, st,
+                       rrot, n, dp, bits, SA, cap, norm2, codes, f_add, f_rescale, cos_oo, fac);
+    return hipGetLastError();
+}
+
+}  // namespace erq

@@ -1,0 +1,227 @@
+// Selection and list building:
+//  * row_topk: the k smallest entries of each row of a distance matrix,
+//    ascending by (value, column) -- the nprobe nearest centroids of the IVF
+//    probe (Sec. 4.1) and the nearest centroid of a k-means assignment.
+//    Exact radix select on the order-preserving integer image of the floats
+//    (4 passes of 8 bits), then a stable compaction and a bitonic sort.
+//  * IVF list construction: count, scan, scatter, per-list sort of ids.
+//  * residuals r = x - c and ||r||^2 (FP64 accumulate) in list order.
+#include "erq_common.h"
+
+namespace erq {
+
+namespace {
+
+__device__ inline unsigned f2key(float f) {
+    unsigned u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+constexpr int kSelThreads = 256;
+constexpr int kSelMaxK = 1024;
+
+__global__ __launch_bounds__(kSelThreads) void row_topk_kernel(
+    const float* __restrict__ D, int64_t N, int k, int32_t* __restrict__ oidx, float* __restrict__ oval)
+{
+    __shared__ unsigned hist[256];
+    __shared__ unsigned skey[kSelMaxK];
+    __shared__ int sidx[kSelMaxK];
+    __shared__ unsigned scan_l[kSelThreads], scan_e[kSelThreads];
+    __shared__ unsigned s_prefix, s_kr;
+    const int tid = threadIdx.x;
+    const int64_t row = blockIdx.x;
+    const float* d = D + row * N;
+    const int kk = (int)min<int64_t>(k, N);
+    unsigned prefix = 0, mask = 0;
+    unsigned kr = (unsigned)kk;                 // rank (1-based) still to locate
+    for (int pass = 0; pass < 4 && kk > 0; ++pass) {
+        const int shift = 24 - 8 * pass;
+        for (int i = tid; i < 256; i += kSelThreads) hist[i] = 0;
+        __syncthreads();
+        for (int64_t j = tid; j < N; j += kSelThreads) {
+            unsigned key = f2key(d[j]);
+            if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 0xFF], 1u);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            unsigned acc = 0;
+            int dg = 0;
+            for (; dg < 256; ++dg) {
+                if (acc + hist[dg] >= kr) break;
+                acc += hist[dg];
+            }
+            s_prefix = prefix | ((unsigned)dg << shift);
+            s_kr = kr - acc;
+        }
+        __syncthreads();
+        prefix = s_prefix;
+        kr = s_kr;
+        mask |= 0xFFu << shift;
+        __syncthreads();
+    }
+    const unsigned kth = prefix;                // key of the k-th smallest
+    const unsigned need_eq = kr;                // how many equal to kth are taken
+    // stable compaction over contiguous chunks
+    const int64_t chunk = (N + kSelThreads - 1) / kSelThreads;
+    const int64_t beg = tid * chunk, end = min(N, beg + chunk);
+    unsigned nl = 0, ne = 0;
+    for (int64_t j = beg; j < end; ++j) {
+        unsigned key = f2key(d[j]);
+        nl += key < kth;
+        ne += key == kth;
+    }
+    scan_l[tid] = nl; scan_e[tid] = ne;
+    __syncthreads();
+    if (tid == 0) {
+        unsigned a = 0, b = 0;
+        for (int t = 0; t < kSelThreads; ++t) {
+            unsigned x = scan_l[t], y = scan_e[t];
+            scan_l[t] = a; scan_e[t] = b;
+            a += x; b += y;
+        }
+    }
+    __syncthreads();
+    const unsigned nless = (unsigned)kk - need_eq;
+    unsigned pl = scan_l[tid], pe = scan_e[tid];
+    for (int64_t j = beg; j < end && kk > 0; ++j) {
+        unsigned key = f2key(d[j]);
+        if (key < kth) { skey[pl] = key; sidx[pl] = (int)j; ++pl; }
+        else if (key == kth) { if (pe < need_eq) { skey[nless + pe] = key; sidx[nless + pe] = (int)j; } ++pe; }
+    }
+    int S = 1;
+    while (S < kk) S <<= 1;
+    for (int t = kk + tid; t < S; t += kSelThreads) { skey[t] = 0xFFFFFFFFu; sidx[t] = 0x7FFFFFFF; }
+    for (int kb = 2; kb <= S; kb <<= 1)
+        for (int j = kb >> 1; j > 0; j >>= 1) {
+            __syncthreads();
+            for (int t = tid; t < S / 2; t += kSelThreads) {
+                int i = 2 * t - (t & (j - 1)), p = i + j;
+                bool up = (i & kb) == 0;
+                unsigned k0 = skey[i], k1 = skey[p];
+                int i0 = sidx[i], i1 = sidx[p];
+                bool first0 = k0 < k1 || (k0 == k1 && i0 < i1);
+                if (first0 != up) { skey[i] = k1; skey[p] = k0; sidx[i] = i1; sidx[p] = i0; }
+            }
+        }
+    __syncthreads();
+    for (int t = tid; t < k; t += kSelThreads) {
+        if (t < kk) {
+            oidx[row * k + t] = sidx[t];
+            if (oval) oval[row * k + t] = d[sidx[t]];
+        } else {
+            oidx[row * k + t] = -1;
+            if (oval) oval[row * k + t] = __builtin_huge_valf();
+        }
+    }
+}
+
+// ---- list construction ---------------------------------------------------
+__global__ void count_kernel(const int32_t* __restrict__ assign, int64_t n, int64_t nlist, int32_t* __restrict__ cnt,
+                             int32_t* __restrict__ bad)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t l = assign[i];
+    if (l < 0 || l >= nlist) { atomicOr(bad, 1); return; }
+    atomicAdd(&cnt[l], 1);
+}
+
+__global__ void scatter_kernel(const int32_t* __restrict__ assign, int64_t n, const int64_t* __restrict__ off,
+                               int32_t* __restrict__ fill, int32_t* __restrict__ ids32)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t l = assign[i];
+    int32_t p = atomicAdd(&fill[l], 1);
+    ids32[off[l] + p] = (int32_t)i;
+}
+
+// per-list ascending sort of the ids (one workgroup per list, lists <= 16384)
+__global__ __launch_bounds__(1024) void sort_lists_kernel(const int64_t* __restrict__ off, int32_t* __restrict__ ids32,
+                                                          int64_t* __restrict__ ids64)
+{
+    __shared__ int s[16384];
+    const int l = blockIdx.x;
+    const int64_t lo = off[l];
+    const int n = (int)(off[l + 1] - lo);
+    int S = 1;
+    while (S < n) S <<= 1;
+    for (int t = threadIdx.x; t < S; t += blockDim.x) s[t] = (t < n) ? ids32[lo + t] : 0x7FFFFFFF;
+    for (int kb = 2; kb <= S; kb <<= 1)
+        for (int j = kb >> 1; j > 0; j >>= 1) {
+            __syncthreads();
+            for (int t = threadIdx.x; t < S / 2; t += blockDim.x) {
+                int i = 2 * t - (t & (j - 1)), p = i + j;
+                bool up = (i & kb) == 0;
+                int a = s[i], b = s[p];
+                if ((a < b) != up) { s[i] = b; s[p] = a; }
+            }
+        }
+    __syncthreads();
+    for (int t = threadIdx.x; t < n; t += blockDim.x) ids64[lo + t] = s[t];
+}
+
+// residual rows in list order: res[v] = x[ids[v]] - cent[assign[ids[v]]]; norm2 in FP64
+__global__ void residual_kernel(const float* __restrict__ x, const int64_t* __restrict__ ids,
+                                const int32_t* __restrict__ assign, const float* __restrict__ cent,
+                                int64_t n, int dp, float* __restrict__ res, float* __restrict__ norm2)
+{
+    int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    int lane = threadIdx.x & 63;
+    if (v >= n) return;
+    int64_t id = ids[v];
+    const float* xr = x + id * (int64_t)dp;
+    const float* cr = cent + (int64_t)assign[id] * dp;
+    float* rr = res + v * (int64_t)dp;
+    double s = 0.0;
+    for (int i = lane; i < dp; i += 64) {
+        float t = xr[i] - cr[i];
+        rr[i] = t;
+        s += (double)t * (double)t;
+    }
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) norm2[v] = (float)s;
+}
+
+}  // namespace
+
+hipError_t launch_row_topk(const float* D, int64_t n, int64_t N, int k, int32_t* idx, float* val,
+                           hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(row_topk_kernel, dim3((unsigned)n), dim3(kSelThreads), 0, st, D, N, k, idx, val);
+    return hipGetLastError();
+}
+
+hipError_t launch_count(const int32_t* assign, int64_t n, int64_t nlist, int32_t* cnt, int32_t* bad, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(count_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, assign, n, nlist, cnt, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(const int32_t* assign, int64_t n, const int64_t* off, int32_t* fill, int32_t* ids32,
+                          hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, assign, n, off, fill, ids32);
+    return hipGetLastError();
+}
+
+hipError_t launch_sort_lists(const int64_t* off, int64_t nlist, int32_t* ids32, int64_t* ids64, hipStream_t st)
+{
+    if (nlist <= 0) return hipSuccess;
+    hipLaunchKernelGGL(sort_lists_kernel, dim3((unsigned)nlist), dim3(1024), 0, st, off, ids32, ids64);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual(const float* x, const int64_t* ids, const int32_t* assign, const float* cent,
+                           int64_t n, int dp, float* res, float* norm2, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(residual_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, x, ids, assign, cent,
+                       n, dp, res, norm2);
+    return hipGetLastError();
+}
+
+}  // namespace erq

@@ -1,0 +1,227 @@
+"""Thin ctypes binding of liberq.so (include/erq.h).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  Tensors must be contiguous CUDA(HIP) tensors of the stated dtype;
+work is enqueued on torch's current stream.  If liberq.so is missing the
+first call raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liberq.so")
+
+ERQ_OK, ERQ_EINVAL, ERQ_ESHAPE, ERQ_ENOMEM, ERQ_EUNSUPPORTED, ERQ_EDEVICE = range(6)
+
+# name -> (restype, argtypes) for every symbol of include/erq.h
+_p, _i32, _i64, _sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
+SIGNATURES = {
+    "erq_last_error": (C.c_char_p, []),
+    "erq_version": (C.c_int, []),
+    "erq_rotate": (C.c_int, [_p, _i64, _i32, _p, _i32, _p, _p]),
+    "erq_quantize": (C.c_int, [_p, _i64, _i32, _i32, _p, _p, _p, _p, _p, _p]),
+    "erq_probe_workspace_size": (C.c_int, [_i64, _i64, _i32, C.POINTER(_sz)]),
+    "erq_coarse_probe": (C.c_int, [_p, _i64, _p, _i64, _i32, _i32, _p, _p, _p, _sz, _p]),
+    "erq_index_create": (C.c_int, [_i32, _i32, _i64, _p, _p, C.POINTER(_p)]),
+    "erq_index_destroy": (C.c_int, [_p]),
+    "erq_index_import": (C.c_int, [_p, _i64, _p, _p, _p, _p, _p, _p, _p, _p]),
+    "erq_index_build": (C.c_int, [_p, _p, _i64, _p, _p, _i32, _i32, _p]),
+    "erq_index_set_raw": (C.c_int, [_p, _p, _i64, _p]),
+    "erq_index_info": (C.c_int, [_p, C.POINTER(_i64), C.POINTER(_i32), C.POINTER(_i32),
+                                 C.POINTER(_i64), C.POINTER(_i64)]),
+    "erq_index_export": (C.c_int, [_p, _p, _p, _p, _p, _p, _p, _p]),
+    "erq_scan_workspace_size": (C.c_int, [_p, _i64, _i32, _i32, C.POINTER(_sz)]),
+    "erq_scan": (C.c_int, [_p, _p, _i64, _p, _i32, _i32, _p, _p, _p, _sz, _p]),
+    "erq_rerank": (C.c_int, [_p, _p, _i64, _p, _i32, _i32, _p, _p, _p]),
+    "erq_search_workspace_size": (C.c_int, [_p, _i64, _i32, _i32, _i32, C.POINTER(_sz)]),
+    "erq_search": (C.c_int, [_p, _p, _i64, _i32, _i32, _i32, _p, _p, _p, _sz, _p]),
+}
+
+_lib = None
+
+
+class ErqError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"erq status {code}: {msg}")
+        self.code = code
+
+
+def load(path: str = LIB_PATH):
+    """Loads liberq.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is missing: run `python -m paper_2409_09913_amd.build` "
+                               "(there is no CPU fallback)")
+        lib = C.CDLL(path)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(rc):
+    if rc != ERQ_OK:
+        raise ErqError(rc, load().erq_last_error().decode())
+
+
+def _ptr(t, dtype=None, name="tensor"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t.data_ptr()
+
+
+def _stream():
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _ws(nbytes: int, device):
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+# --------------------------------------------------------------------------
+def rotate(x, P, precision: int = 0, out=None):
+    """Rows of x times P (= P^T applied to each row), FP32 or BF16 matrix cores."""
+    n, dp = x.shape
+    if out is None:
+        out = torch.empty_like(x)
+    _check(load().erq_rotate(_ptr(x, torch.float32, "x"), n, dp, _ptr(P, torch.float32, "P"),
+                             precision, _ptr(out, torch.float32, "out"), _stream()))
+    return out
+
+
+def quantize(rrot, bits: int, norm2=None):
+    """Algorithm 1 on rotated rows; returns (codes uint8, f_add, f_rescale, cos_oo)."""
+    n, dp = rrot.shape
+    dev = rrot.device
+    codes = torch.empty((n, dp), dtype=torch.uint8, device=dev)
+    fa = torch.empty(n, dtype=torch.float32, device=dev)
+    fr = torch.empty(n, dtype=torch.float32, device=dev)
+    co = torch.empty(n, dtype=torch.float32, device=dev)
+    _check(load().erq_quantize(_ptr(rrot, torch.float32, "rrot"), n, dp, bits,
+                               _ptr(norm2, torch.float32, "norm2"), _ptr(codes, torch.uint8),
+                               _ptr(fa), _ptr(fr), _ptr(co), _stream()))
+    return codes, fa, fr, co
+
+
+def coarse_probe(q, centroids, nprobe: int, with_dist: bool = False):
+    nq, dp = q.shape
+    nl = centroids.shape[0]
+    sz = C.c_size_t()
+    _check(load().erq_probe_workspace_size(nq, nl, nprobe, C.byref(sz)))
+    ws = _ws(sz.value, q.device)
+    probes = torch.empty((nq, nprobe), dtype=torch.int32, device=q.device)
+    pd = torch.empty((nq, nprobe), dtype=torch.float32, device=q.device) if with_dist else None
+    _check(load().erq_coarse_probe(_ptr(q, torch.float32, "q"), nq, _ptr(centroids, torch.float32, "centroids"),
+                                   nl, dp, nprobe, _ptr(probes), _ptr(pd), _ptr(ws), ws.numel(), _stream()))
+    return (probes, pd) if with_dist else probes
+
+
+class Index:
+    """Owner of an erq_index handle (lists, packed codes, factors, P, centroids)."""
+
+    def __init__(self, dp: int, bits: int, nlist: int, P):
+        self.dp, self.bits, self.nlist = dp, bits, nlist
+        h = C.c_void_p()
+        _check(load().erq_index_create(dp, bits, nlist, _ptr(P, torch.float32, "P"), _stream(), C.byref(h)))
+        self.h = h
+        self.device = P.device
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            load().erq_index_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def import_(self, list_off, ids, codes, f_add, f_rescale, centroids, centroids_rot=None):
+        n = ids.shape[0]
+        _check(load().erq_index_import(self.h, n, _ptr(list_off, torch.int64, "list_off"), _ptr(ids, torch.int64, "ids"),
+                                       _ptr(codes, torch.uint8, "codes"), _ptr(f_add, torch.float32, "f_add"),
+                                       _ptr(f_rescale, torch.float32, "f_rescale"),
+                                       _ptr(centroids, torch.float32, "centroids"),
+                                       _ptr(centroids_rot, torch.float32, "centroids_rot"), _stream()))
+
+    def build(self, x, centroids, assign=None, precision: int = 0, keep_raw: bool = False):
+        _check(load().erq_index_build(self.h, _ptr(x, torch.float32, "x"), x.shape[0],
+                                      _ptr(centroids, torch.float32, "centroids"),
+                                      _ptr(assign, torch.int32, "assign"), precision, int(keep_raw), _stream()))
+
+    def set_raw(self, x):
+        _check(load().erq_index_set_raw(self.h, _ptr(x, torch.float32, "x"), x.shape[0], _stream()))
+
+    def info(self):
+        n, dp, b, nl, cb = C.c_int64(), C.c_int32(), C.c_int32(), C.c_int64(), C.c_int64()
+        _check(load().erq_index_info(self.h, C.byref(n), C.byref(dp), C.byref(b), C.byref(nl), C.byref(cb)))
+        return dict(n=n.value, dp=dp.value, bits=b.value, nlist=nl.value, code_bytes=cb.value)
+
+    def export(self):
+        inf = self.info()
+        n, dp, nl = inf["n"], inf["dp"], inf["nlist"]
+        dev = self.device
+        off = torch.empty(nl + 1, dtype=torch.int64, device=dev)
+        ids = torch.empty(n, dtype=torch.int64, device=dev)
+        codes = torch.empty((n, dp), dtype=torch.uint8, device=dev)
+        fa = torch.empty(n, dtype=torch.float32, device=dev)
+        fr = torch.empty(n, dtype=torch.float32, device=dev)
+        cr = torch.empty((nl, dp), dtype=torch.float32, device=dev)
+        _check(load().erq_index_export(self.h, _ptr(off), _ptr(ids), _ptr(codes), _ptr(fa), _ptr(fr), _ptr(cr),
+                                       _stream()))
+        return off, ids, codes, fa, fr, cr
+
+    def scan_workspace_size(self, nq, nprobe, kk):
+        sz = C.c_size_t()
+        _check(load().erq_scan_workspace_size(self.h, nq, nprobe, kk, C.byref(sz)))
+        return sz.value
+
+    def scan(self, qrot, probes, kk: int, ws=None):
+        nq = qrot.shape[0]
+        nprobe = probes.shape[1]
+        if ws is None:
+            ws = _ws(self.scan_workspace_size(nq, nprobe, kk), qrot.device)
+        ids = torch.empty((nq, kk), dtype=torch.int64, device=qrot.device)
+        est = torch.empty((nq, kk), dtype=torch.float32, device=qrot.device)
+        _check(load().erq_scan(self.h, _ptr(qrot, torch.float32, "qrot"), nq, _ptr(probes, torch.int32, "probes"),
+                               nprobe, kk, _ptr(ids), _ptr(est), _ptr(ws), ws.numel(), _stream()))
+        return ids, est
+
+    def rerank(self, q, cand, k: int):
+        nq, kc = cand.shape
+        ids = torch.empty((nq, k), dtype=torch.int64, device=q.device)
+        d = torch.empty((nq, k), dtype=torch.float32, device=q.device)
+        _check(load().erq_rerank(self.h, _ptr(q, torch.float32, "q"), nq, _ptr(cand, torch.int64, "cand"), kc, k,
+                                 _ptr(ids), _ptr(d), _stream()))
+        return ids, d
+
+    def search_workspace_size(self, nq, nprobe, k, rerank_k=0):
+        sz = C.c_size_t()
+        _check(load().erq_search_workspace_size(self.h, nq, nprobe, k, rerank_k, C.byref(sz)))
+        return sz.value
+
+    def search(self, q, nprobe: int, k: int, rerank_k: int = 0, ws=None, out=None):
+        nq = q.shape[0]
+        if ws is None:
+            ws = _ws(self.search_workspace_size(nq, nprobe, k, rerank_k), q.device)
+        if out is None:
+            out = (torch.empty((nq, k), dtype=torch.int64, device=q.device),
+                   torch.empty((nq, k), dtype=torch.float32, device=q.device))
+        ids, d = out
+        _check(load().erq_search(self.h, _ptr(q, torch.float32, "q"), nq, nprobe, k, rerank_k, _ptr(ids), _ptr(d),
+                                 _ptr(ws), ws.numel(), _stream()))
+        return ids, d

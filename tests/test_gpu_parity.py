@@ -1,0 +1,320 @@
+"""GPU parity of every stage of the hot path against the CPU oracle, called
+through the C ABI on identical seeded inputs.
+
+Bars: codes, ids and integer products bit-exact; FP32 distances within
+1e-4 relative to the magnitude of the terms that form them (a difference of
+large terms can be close to 0 or negative); rotations within the forward
+error bound of an FP32 (or BF16-input) dot product of length dp.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2409_09913_amd import erq, synth
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+DEV = torch.device("cuda:0")
+U32 = 2.0 ** -24
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+# ---------------------------------------------------------------------------
+# rotation
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dp,n", [(64, 33), (128, 300), (768, 517), (1536, 130)])
+def test_rotate_fp32_error_bound(dp, n):
+    say("rotate fp32", dp, n)
+    P = synth.haar_orthogonal(dp, seed=dp).astype(np.float32)
+    x = synth.gmm(n, dp, 8, 0.3, seed=dp, dp=dp)
+    got = erq.rotate(dev(x), dev(P)).cpu().numpy().astype(np.float64)
+    ref = oracle.rotate(x, P)
+    mag = np.abs(x).astype(np.float64) @ np.abs(P).astype(np.float64)
+    gam = dp * U32 / (1 - dp * U32)
+    assert np.all(np.abs(got - ref) <= gam * mag + 1e-30)
+    say("  max rel err", float(np.max(np.abs(got - ref) / (mag + 1e-30))))
+
+
+def test_rotate_bf16_error_bound():
+    dp, n = 768, 257
+    P = synth.haar_orthogonal(dp, seed=3).astype(np.float32)
+    x = synth.gmm(n, dp, 8, 0.3, seed=4, dp=dp)
+    got = erq.rotate(dev(x), dev(P), precision=1).cpu().numpy().astype(np.float64)
+    ref = oracle.rotate(x, P)
+    mag = np.abs(x).astype(np.float64) @ np.abs(P).astype(np.float64)
+    # inputs rounded to BF16 (rel. 2^-9 each), products exact, FP32 accumulation
+    bound = (2 * 2.0 ** -9 + 2.0 ** -18) * mag + (dp * U32 / (1 - dp * U32)) * mag * (1 + 2.0 ** -7)
+    assert np.all(np.abs(got - ref) <= bound)
+    rel = np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    say("  bf16 mean row rel err", float(rel.mean()))
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 1
+# ---------------------------------------------------------------------------
+def _quantize_compare(r, B, norm2=None):
+    codes, fa, fr, co = erq.quantize(dev(r), B, None if norm2 is None else dev(norm2.astype(np.float32)))
+    torch.cuda.synchronize()
+    codes = codes.cpu().numpy()
+    rc, rfa, rfr, rco = oracle.quantize(r.astype(np.float64), B,
+                                        None if norm2 is None else norm2.astype(np.float32).astype(np.float64))
+    bad = np.nonzero((codes != rc).any(1))[0]
+    assert bad.size == 0, f"B={B}: {bad.size} rows differ, first {bad[:5]}"
+    np.testing.assert_allclose(fa.cpu().numpy(), rfa.astype(np.float32), rtol=2e-7, atol=0)
+    np.testing.assert_allclose(fr.cpu().numpy(), rfr.astype(np.float32), rtol=4e-7, atol=0)
+    np.testing.assert_allclose(co.cpu().numpy(), rco.astype(np.float32), rtol=4e-7, atol=0)
+
+
+@pytest.mark.parametrize("B", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_quantize_bitexact_dp128(B):
+    say("quantize dp128 B", B)
+    r = synth.random_rotated(200, 128, seed=B)
+    _quantize_compare(r, B)
+
+
+@pytest.mark.parametrize("dp,B,n", [(64, 4, 100), (768, 4, 300), (768, 8, 40), (960, 3, 64), (960, 7, 16),
+                                    (1536, 5, 24), (3072, 4, 12), (3072, 2, 8)])
+def test_quantize_bitexact_sizes(dp, B, n):
+    say("quantize", dp, B, n)
+    g = np.random.default_rng(dp + B)
+    r = synth.random_rotated(n, dp, seed=dp * 10 + B)
+    norm2 = (r.astype(np.float64) ** 2).sum(1) * g.uniform(0.5, 2.0, n)
+    _quantize_compare(r, B, norm2)
+
+
+@pytest.mark.parametrize("B", [1, 2, 4, 8])
+def test_quantize_edge_rows(B):
+    say("quantize edge rows B", B)
+    for dp in (64, 192):
+        r = synth.edge_rows(dp, seed=B)
+        _quantize_compare(r, B)
+
+
+def test_quantize_anisotropic_and_ties():
+    """Rows built to create long runs of exactly tied critical values."""
+    g = np.random.default_rng(5)
+    rows = []
+    for _ in range(20):
+        v = (2.0 ** g.integers(-4, 4, 256)) * np.where(g.random(256) < 0.5, -1, 1)
+        rows.append(v)
+    for _ in range(10):
+        rows.append(g.integers(-3, 4, 256).astype(np.float64))
+    r = np.asarray(rows, np.float32)
+    for B in (3, 5, 8):
+        _quantize_compare(r, B)
+
+
+# ---------------------------------------------------------------------------
+# packing round trip
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("B", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_pack_roundtrip(B):
+    dp, n, nl = 192, 1000, 9
+    sizes = np.array([0, 1, 31, 32, 33, 100, 203, 300, 300])
+    off, ids, codes, fa, fr, crot = synth.random_index(n, nl, dp, B, seed=B, sizes=sizes)
+    P = synth.haar_orthogonal(dp, seed=1).astype(np.float32)
+    ix = erq.Index(dp, B, nl, dev(P))
+    cent = np.zeros((nl, dp), np.float32)
+    ix.import_(dev(off), dev(ids), dev(codes), dev(fa), dev(fr), dev(cent), dev(crot))
+    o2, i2, c2, fa2, fr2, cr2 = [t.cpu().numpy() for t in ix.export()]
+    np.testing.assert_array_equal(o2, off)
+    np.testing.assert_array_equal(i2, ids)
+    np.testing.assert_array_equal(c2, codes)
+    np.testing.assert_array_equal(fa2, fa)
+    np.testing.assert_array_equal(fr2, fr)
+    assert ix.info()["code_bytes"] == 4 * dp * B * sum((s + 31) // 32 for s in sizes)
+    ix.close()
+
+
+# ---------------------------------------------------------------------------
+# scan (int8 matrix cores + estimator + top-k)
+# ---------------------------------------------------------------------------
+def _term_scale(codes, fa, fr, crot, qrot, off, ids_o, q_ids, probes, B):
+    """Per query: the largest |f_add| + ||s||^2 + |f_rescale <y,s'>| over its candidates."""
+    out = np.zeros(qrot.shape[0])
+    yb = codes.astype(np.float64) - ((1 << B) - 1) / 2.0
+    for iq in range(qrot.shape[0]):
+        m = 0.0
+        for l in probes[iq]:
+            if l < 0:
+                continue
+            s = qrot[iq].astype(np.float64) - crot[l].astype(np.float64)
+            lo, hi = off[l], off[l + 1]
+            if hi > lo:
+                t = np.abs(fa[lo:hi]) + s @ s + np.abs(fr[lo:hi] * (yb[lo:hi] @ s))
+                m = max(m, float(t.max()))
+        out[iq] = m
+    return out
+
+
+def _compare_topk(gi, ge, oi, oe, scale, rel=1e-4):
+    for q in range(gi.shape[0]):
+        tol = rel * scale[q] + 1e-30
+        valid_o = oi[q] >= 0
+        valid_g = gi[q] >= 0
+        np.testing.assert_array_equal(valid_g, valid_o)
+        assert np.all(np.abs(ge[q][valid_g] - oe[q][valid_o]) <= tol), (q, ge[q], oe[q])
+        sg, so = set(gi[q][valid_g].tolist()), set(oi[q][valid_o].tolist())
+        if sg != so:
+            kth = oe[q][valid_o][-1]
+            for i in sg ^ so:
+                # an id that is in one list only must sit at the boundary (near-tie)
+                pos = np.nonzero(gi[q] == i)[0]
+                val = ge[q][pos[0]] if pos.size else oe[q][np.nonzero(oi[q] == i)[0][0]]
+                assert abs(val - kth) <= 2 * tol, (q, i, val, kth)
+
+
+def _scan_case(n, nl, dp, B, nq, nprobe, kk, seed, sizes=None, empty_lists=0, pad_probes=0, q_at_centroid=0):
+    off, ids, codes, fa, fr, crot = synth.random_index(n, nl, dp, B, seed=seed, sizes=sizes,
+                                                       empty_lists=empty_lists)
+    qrot = synth.random_rotated(nq, dp, seed=seed + 7)
+    probes = synth.random_probes(nq, nl, nprobe, seed=seed)
+    for i in range(pad_probes):
+        probes[i, nprobe // 2:] = -1
+    for i in range(q_at_centroid):
+        qrot[nq - 1 - i] = crot[probes[nq - 1 - i, 0]]
+    P = synth.haar_orthogonal(dp, seed=2).astype(np.float32)
+    ix = erq.Index(dp, B, nl, dev(P))
+    ix.import_(dev(off), dev(ids), dev(codes), dev(fa), dev(fr), dev(np.zeros((nl, dp), np.float32)), dev(crot))
+    gi, ge = ix.scan(dev(qrot), dev(probes), kk)
+    torch.cuda.synchronize()
+    gi, ge = gi.cpu().numpy(), ge.cpu().numpy()
+    oi, oe = oracle.search(off, ids, codes, fa, fr, crot, qrot, probes, B, kk, est_mode=0)
+    scale = _term_scale(codes, fa, fr, crot, qrot, off, ids, None, probes, B)
+    _compare_topk(gi, ge, oi, oe, scale)
+    ix.close()
+    return gi, oi
+
+
+@pytest.mark.parametrize("B", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_scan_parity_bits(B):
+    say("scan B", B)
+    gi, oi = _scan_case(n=6000, nl=24, dp=128, B=B, nq=70, nprobe=6, kk=10, seed=B)
+    assert (gi == oi).mean() > 0.99
+
+
+@pytest.mark.parametrize("kk", [1, 10, 16, 17, 32, 40, 64])
+def test_scan_parity_kk(kk):
+    say("scan kk", kk)
+    _scan_case(n=8000, nl=16, dp=192, B=4, nq=50, nprobe=5, kk=kk, seed=100 + kk)
+
+
+def test_scan_parity_dp768_many_tiles():
+    say("scan dp768")
+    sizes = np.array([1, 2, 31, 32, 33, 64, 65, 500, 1000, 1500, 2000, 3000, 1871, 0, 17, 384])
+    _scan_case(n=int(sizes.sum()), nl=len(sizes), dp=768, B=4, nq=120, nprobe=8, kk=20, seed=7, sizes=sizes)
+
+
+def test_scan_edge_cases():
+    """Empty lists, padded probe rows (-1), queries equal to a centroid
+    (s' = 0, delta = 0), kk larger than the candidate count."""
+    say("scan edges")
+    _scan_case(n=3000, nl=32, dp=128, B=5, nq=40, nprobe=4, kk=10, seed=11, empty_lists=6,
+               pad_probes=5, q_at_centroid=3)
+    sizes = np.array([3, 0, 2, 1])
+    gi, oi = _scan_case(n=6, nl=4, dp=64, B=8, nq=5, nprobe=2, kk=16, seed=12, sizes=sizes)
+    assert (gi == -1).any()
+
+
+def test_scan_many_queries_per_list():
+    """More than 32 queries per list (several query tiles per list)."""
+    say("scan many queries")
+    _scan_case(n=4000, nl=8, dp=256, B=3, nq=300, nprobe=4, kk=10, seed=13)
+
+
+# ---------------------------------------------------------------------------
+# coarse probe, rerank
+# ---------------------------------------------------------------------------
+def test_coarse_probe_parity():
+    say("probe")
+    dp, nl, nq, nprobe = 256, 300, 200, 17
+    cent = synth.gmm(nl, 200, 30, 0.5, seed=21, dp=dp)
+    q = synth.gmm(nq, 200, 30, 0.5, seed=21, stream=synth.S_QUERY, dp=dp)
+    pg, dg = erq.coarse_probe(dev(q), dev(cent), nprobe, with_dist=True)
+    pg, dg = pg.cpu().numpy(), dg.cpu().numpy()
+    po, do = oracle.probe(q, cent, nprobe)
+    # FP32 error bound of ||q||^2 + ||c||^2 - 2 q.c
+    qn = (q.astype(np.float64) ** 2).sum(1)
+    cn = (cent.astype(np.float64) ** 2).sum(1)
+    for i in range(nq):
+        tol = 4 * dp * U32 * (qn[i] + cn.max()) + 1e-12
+        assert np.all(np.abs(dg[i] - do[i]) <= tol)
+        if set(pg[i]) != set(po[i]):
+            kth = do[i][-1]
+            for j in set(pg[i]) ^ set(po[i]):
+                dd = ((q[i].astype(np.float64) - cent[j].astype(np.float64)) ** 2).sum()
+                assert abs(dd - kth) <= 2 * tol
+        else:
+            np.testing.assert_array_equal(np.sort(pg[i]), np.sort(po[i]))
+
+
+def test_rerank_parity():
+    say("rerank")
+    dp, n, nq, kc, k = 192, 2000, 30, 50, 10
+    x = synth.gmm(n, dp, 10, 0.5, seed=31, dp=dp)
+    q = synth.gmm(nq, dp, 10, 0.5, seed=31, stream=synth.S_QUERY, dp=dp)
+    g = np.random.default_rng(3)
+    cand = np.stack([g.choice(n, kc, replace=False) for _ in range(nq)]).astype(np.int64)
+    cand[0, :5] = -1
+    P = synth.haar_orthogonal(dp, seed=2).astype(np.float32)
+    ix = erq.Index(dp, 4, 1, dev(P))
+    off = np.array([0, n], np.int64)
+    ix.import_(dev(off), dev(np.arange(n, dtype=np.int64)), dev(np.zeros((n, dp), np.uint8)),
+               dev(np.ones(n, np.float32)), dev(-np.ones(n, np.float32)), dev(np.zeros((1, dp), np.float32)))
+    ix.set_raw(dev(x))
+    gi, gd = ix.rerank(dev(q), dev(cand), k)
+    gi, gd = gi.cpu().numpy(), gd.cpu().numpy()
+    oi, od = oracle.rerank(x, q, cand, k)
+    np.testing.assert_allclose(gd, od, rtol=1e-5)
+    assert (gi == oi).mean() > 0.999
+    ix.close()
+
+
+# ---------------------------------------------------------------------------
+# end to end on the tiny GMM workload (10,000 x 128, B = 4)
+# ---------------------------------------------------------------------------
+def test_end_to_end_tiny():
+    say("end to end tiny")
+    x, q = synth.tiny_gmm()
+    dp = x.shape[1]
+    P = synth.haar_orthogonal(dp).astype(np.float32)
+    c = x.astype(np.float64).mean(0, keepdims=True).astype(np.float32)
+    ix = erq.Index(dp, 4, 1, dev(P))
+    ix.build(dev(x), dev(c), keep_raw=True)
+    off, ids, codes, fa, fr, crot = [t.cpu().numpy() for t in ix.export()]
+    assert np.array_equal(ids, np.arange(x.shape[0]))
+    # codes against the oracle's FP64 pipeline: rotation rounding may move a
+    # coordinate across a boundary, so compare the objective they attain
+    oc, ofa, ofr, oco, orr = oracle.encode(x, c.astype(np.float64), np.zeros(len(x), np.int32), P, 4)
+    same = (codes == oc).all(1).mean()
+    obj_g = np.array([oracle.objective(orr[i], 4, codes[i]) for i in range(0, len(x), 50)])
+    obj_o = np.array([oracle.objective(orr[i], 4, oc[i]) for i in range(0, len(x), 50)])
+    assert np.all(obj_g >= obj_o * (1 - 1e-6))
+    np.testing.assert_allclose(fa, ofa.astype(np.float32), rtol=1e-5)
+    say("  identical code rows", same)
+    # search: estimated top-10 and re-ranked top-10 against exact k-NN
+    ti, td = oracle.knn(x, q, 10)
+    ids0, d0 = ix.search(dev(q), 1, 10, 0)
+    ids1, d1 = ix.search(dev(q), 1, 10, 40)
+    ids0, ids1 = ids0.cpu().numpy(), ids1.cpu().numpy()
+    r0 = np.mean([len(set(a) & set(b)) / 10 for a, b in zip(ids0, ti)])
+    r1 = np.mean([len(set(a) & set(b)) / 10 for a, b in zip(ids1, ti)])
+    say("  recall@10 no rerank", r0, "rerank40", r1)
+    assert r0 > 0.6 and r1 > 0.97
+    np.testing.assert_allclose(d1.cpu().numpy()[:, 0], td[:, 0], rtol=1e-4)
+    ix.close()
