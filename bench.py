@@ -1,0 +1,317 @@
+#!/usr/bin/env python
+"""Benchmark of the Extended RaBitQ hot path on one MI355X.
+
+Workload (embed768): N = 1,000,000 x D = 768 FP32 rows of a 1024-component
+Gaussian mixture with Zipf weights, sigma 0.3, every row rescaled to a
+LogNormal(0, 0.2) norm; 10,000 queries from the same mixture; IVF with 4096
+k-means lists; B = 4 codes (B = 8 reported beside it); k = 10.
+
+A step is one search of the whole query batch through the C ABI
+(erq_search: rotation, coarse probe, pair build, int8 matrix-core scan with
+estimator and top-k, merge, exact re-rank), with the index and the queries
+resident in HBM.  The operating point (nprobe, re-rank depth) is the fastest
+one whose recall@10 against exact FP32 brute force is >= 0.95.  Encode
+throughput is the time of erq_index_build (residuals, rotation, Algorithm 1,
+factors, packing) over the 1M rows.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+INT8_PEAK_TOPS = 5000.0        # dense int8 matrix cores
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def recall_at(ids, truth, k=10):
+    ids = ids[:, :k]
+    hit = 0
+    for a, b in zip(ids, truth[:, :k]):
+        hit += len(set(a.tolist()) & set(b.tolist()))
+    return hit / (k * len(ids))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--nq", type=int, default=10_000)
+    ap.add_argument("--nlist", type=int, default=4096)
+    ap.add_argument("--bits", type=int, default=4)
+    ap.add_argument("--bits2", type=int, default=8, help="second code width reported as context (0 = skip)")
+    ap.add_argument("--k", type=int, default=10)
+    ap.add_argument("--kmeans-iters", type=int, default=10)
+    ap.add_argument("--target-recall", type=float, default=0.95)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-queries", type=int, default=32)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2409_09913_amd import erq, ivf, synth
+
+    dev = torch.device("cuda:0")
+    erq.load()
+    t0 = time.time()
+    log("generating data", args.n, "x 768 and", args.nq, "queries")
+    x_np, q_np = synth.embed768(args.n, args.nq)
+    dp = x_np.shape[1]
+    P_np = synth.haar_orthogonal(dp).astype(np.float32)
+    x = torch.from_numpy(x_np).to(dev)
+    q = torch.from_numpy(q_np).to(dev)
+    P = torch.from_numpy(P_np).to(dev)
+    log("data ready %.1fs" % (time.time() - t0))
+
+    log("k-means", args.nlist, "lists,", args.kmeans_iters, "iterations")
+    cent, assign = ivf.kmeans(x, args.nlist, iters=args.kmeans_iters)
+    torch.cuda.synchronize()
+    sizes = torch.bincount(assign.long(), minlength=args.nlist).cpu().numpy()
+    log("k-means done %.1fs; list sizes min %d mean %.1f max %d" % (time.time() - t0, sizes.min(), sizes.mean(),
+                                                                    sizes.max()))
+
+    # ---- warm the kernels on a small build, then time the encode ---------------------
+    def build_index(B, keep_raw):
+        ix = erq.Index(dp, B, args.nlist, P)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        ix.build(x, cent, assign, precision=0, keep_raw=False)
+        torch.cuda.synchronize()
+        te = time.perf_counter()
+        if keep_raw:
+            ix.set_raw(x)
+        return ix, te - ts
+
+    warm = erq.Index(dp, args.bits, args.nlist, P)
+    warm.build(x[:20000].contiguous(), cent, assign[:20000].contiguous())
+    if args.bits2:
+        warm2 = erq.Index(dp, args.bits2, args.nlist, P)
+        warm2.build(x[:4000].contiguous(), cent, assign[:4000].contiguous())
+        warm2.close()
+    warm.close()
+    ix, t_enc = build_index(args.bits, keep_raw=True)
+    enc_rate = args.n / t_enc
+    log("encode B=%d: %.3fs -> %.3g codes/s" % (args.bits, t_enc, enc_rate))
+    enc_rate2 = None
+    if args.bits2:
+        ix2, t_enc2 = build_index(args.bits2, keep_raw=False)
+        enc_rate2 = args.n / t_enc2
+        log("encode B=%d: %.3fs -> %.3g codes/s" % (args.bits2, t_enc2, enc_rate2))
+
+    # ---- exact FP32 brute force (library GEMM) : ground truth and comparator -----------
+    def brute(qb, k):
+        xn = (x * x).sum(1)
+        out = torch.empty((qb.shape[0], k), dtype=torch.int64, device=dev)
+        for i in range(0, qb.shape[0], 1000):
+            d = xn[None, :] - 2.0 * (qb[i:i + 1000] @ x.T)
+            out[i:i + 1000] = torch.topk(d, k, dim=1, largest=False).indices
+        return out
+
+    truth = brute(q, args.k)
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    truth = brute(q, args.k)
+    torch.cuda.synchronize()
+    flat_qps = args.nq / (time.perf_counter() - tb)
+    truth_np = truth.cpu().numpy()
+    log("FP32 brute force: %.0f QPS" % flat_qps)
+
+    # ---- sweep the operating point ---------------------------------------------------
+    def timed_search(index, nprobe, rr, reps):
+        ws = torch.empty(index.search_workspace_size(args.nq, nprobe, args.k, rr), dtype=torch.uint8, device=dev)
+        out = (torch.empty((args.nq, args.k), dtype=torch.int64, device=dev),
+               torch.empty((args.nq, args.k), dtype=torch.float32, device=dev))
+        index.search(q, nprobe, args.k, rr, ws=ws, out=out)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        for _ in range(reps):
+            index.search(q, nprobe, args.k, rr, ws=ws, out=out)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - ts) / reps
+        return out[0].cpu().numpy(), args.nq / dt
+
+    def sweep(index, label):
+        rows = []
+        for nprobe in (8, 16, 32, 64, 128):
+            for rr in (0, 20, 40):
+                ids, qps = timed_search(index, nprobe, rr, 3)
+                rec = recall_at(ids, truth_np, args.k)
+                rows.append((nprobe, rr, rec, qps))
+                log("%s nprobe %3d rerank %2d recall@10 %.4f QPS %.0f" % (label, nprobe, rr, rec, qps))
+        ok = [r for r in rows if r[2] >= args.target_recall]
+        best = max(ok, key=lambda r: r[3]) if ok else max(rows, key=lambda r: r[2])
+        return best, rows
+
+    best, rows = sweep(ix, "B=%d" % args.bits)
+    nprobe, rr, rec, _ = best
+    best2 = None
+    if args.bits2:
+        best2, _ = sweep(ix2, "B=%d" % args.bits2)
+
+    # ---- timed region -----------------------------------------------------------------
+    ws = torch.empty(ix.search_workspace_size(args.nq, nprobe, args.k, rr), dtype=torch.uint8, device=dev)
+    out = (torch.empty((args.nq, args.k), dtype=torch.int64, device=dev),
+           torch.empty((args.nq, args.k), dtype=torch.float32, device=dev))
+    for _ in range(args.warmup):
+        ix.search(q, nprobe, args.k, rr, ws=ws, out=out)
+    torch.cuda.synchronize()
+    erq.profile_enable(True)
+    erq.profile_read("scan", reset=True)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    for _ in range(args.steps):
+        ix.search(q, nprobe, args.k, rr, ws=ws, out=out)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - ts
+    scan_ms, scan_n = erq.profile_read("scan")
+    tot = {}
+    for kname in ("rotate", "probe", "scan", "merge", "rerank"):
+        ms, nl = erq.profile_read(kname)
+        tot[kname] = ms / max(nl, 1)
+    erq.profile_read("scan", reset=True)
+    erq.profile_enable(False)
+    qps = args.steps * args.nq / dt
+    ms_per_step = 1000 * dt / args.steps
+    rec_final = recall_at(out[0].cpu().numpy(), truth_np, args.k)
+    log("timed: %.0f QPS, %.3f ms/step, recall %.4f; per-launch ms %s" % (qps, ms_per_step, rec_final, tot))
+
+    # ---- roofline of the scan kernel ------------------------------------------------------
+    probes = erq.coarse_probe(q, cent, nprobe).cpu().numpy()
+    lists, pair_cnt = np.unique(probes, return_counts=True)
+    nb = args.bits * dp // 8 + 8
+    bytes_alg = float(sizes[lists].sum()) * nb
+    ops_alg = float((sizes[lists] * pair_cnt).sum()) * 2 * dp
+    avg_s = scan_ms / max(scan_n, 1) / 1000.0
+    hbm_t = bytes_alg / (HBM_PEAK_GBS * 1e9)
+    mma_t = ops_alg / (INT8_PEAK_TOPS * 1e12)
+    src = open(os.path.join(ROOT, "paper_2409_09913_amd", "csrc", "scan.hip"), "rb").read()
+    sha = hashlib.sha256(src).hexdigest()[:16]
+    traffic = None
+    tf = os.path.join(ROOT, "profiles", "scan_traffic.json")
+    if os.path.exists(tf):
+        try:
+            t = json.load(open(tf))
+            if t.get("scan_hip_sha256_16") == sha and t.get("nprobe") == nprobe and t.get("bits") == args.bits:
+                traffic = t.get("hbm_bytes_per_launch")
+        except Exception:
+            traffic = None
+    if hbm_t >= mma_t:
+        roof = {"bound": "hbm", "achieved": bytes_alg / avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    else:
+        roof = {"bound": "mfma", "achieved": ops_alg / avg_s / 1e12, "peak": INT8_PEAK_TOPS, "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = traffic
+    roof.update({"kernel": "scan_kernel (int8 MFMA scan + estimator + top-k)", "avg_launch_ms": avg_s * 1e3,
+                 "alg_bytes_per_launch": bytes_alg, "alg_int8_ops_per_launch": ops_alg,
+                 "mfma_frac": ops_alg / avg_s / 1e12 / INT8_PEAK_TOPS,
+                 "hbm_frac": bytes_alg / avg_s / 1e9 / HBM_PEAK_GBS, "scan_hip_sha256_16": sha})
+    log("roofline", roof)
+
+    # ---- CPU baseline: the oracle on a bounded sample ------------------------------------
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(args, x_np, q_np, P_np, cent.cpu().numpy(), assign.cpu().numpy(), nprobe, rr)
+
+    res = {
+        "metric": "QPS at recall@10>=0.95 (int8-MFMA scan vs FP32 scan), encode codes/s",
+        "value": qps, "unit": "QPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int8", "data": "synthetic",
+        "config": {"workload": "embed768: N=%d x D=768 GMM(1024 comps, Zipf, sigma 0.3, LogNormal(0,0.2) norms), "
+                               "IVF %d k-means lists, B=%d, %d queries, k=%d" % (args.n, args.nlist, args.bits,
+                                                                                args.nq, args.k),
+                   "global_batch": args.nq, "nprobe": nprobe, "rerank_k": rr, "recall@10": rec_final,
+                   "parallelism": "single GPU"},
+        "encode_codes_per_s": enc_rate,
+        "fp32_bruteforce_qps": flat_qps,
+        "per_launch_ms": tot,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "sweep": [{"nprobe": a, "rerank_k": b, "recall@10": c, "qps": d} for a, b, c, d in rows],
+    }
+    if args.bits2:
+        res["bits2"] = {"bits": args.bits2, "encode_codes_per_s": enc_rate2,
+                        "best": {"nprobe": best2[0], "rerank_k": best2[1], "recall@10": best2[2], "qps": best2[3]}}
+    log("total %.1fs" % (time.time() - t0))
+    print(json.dumps(res), flush=True)
+
+
+def cpu_baseline(args, x_np, q_np, P_np, cent_np, assign_np, nprobe, rr):
+    """The oracle as it stands on a bounded sample: the first S queries are
+    probed over all centroids (FP64), their probed lists are encoded by the
+    oracle, scanned with the int8 estimator and re-ranked exactly."""
+    import oracle
+    S = args.cpu_sample_queries
+    sizes = np.bincount(assign_np, minlength=cent_np.shape[0])
+    probes_all, _ = oracle.probe(q_np[:S], cent_np, nprobe)
+    # bound the oracle's encoding work: keep the first queries whose lists hold <= 100k rows
+    seen, rows_needed, keep = set(), 0, 0
+    for i in range(S):
+        new = set(probes_all[i].tolist()) - seen
+        add = int(sizes[list(new)].sum()) if new else 0
+        if keep >= 4 and rows_needed + add > 100_000:
+            break
+        seen |= new
+        rows_needed += add
+        keep += 1
+    S = keep
+    qs = q_np[:S]
+    probes = probes_all[:S]
+    lists = np.unique(probes)
+    remap = -np.ones(cent_np.shape[0], np.int64)
+    remap[lists] = np.arange(len(lists))
+    members = [np.nonzero(assign_np == l)[0] for l in lists]
+    ids = np.concatenate(members).astype(np.int64)
+    off = np.zeros(len(lists) + 1, np.int64)
+    off[1:] = np.cumsum([len(m) for m in members])
+    asg_local = np.repeat(np.arange(len(lists), dtype=np.int32), [len(m) for m in members])
+    log("cpu baseline: encoding %d rows of %d lists with the oracle" % (len(ids), len(lists)))
+    t1 = time.perf_counter()
+    codes, fa, fr, co, _ = oracle.encode(x_np[ids], cent_np[lists].astype(np.float64), asg_local,
+                                         P_np.astype(np.float64), args.bits)
+    t_enc = time.perf_counter() - t1
+    crot = oracle.rotate(cent_np[lists], P_np).astype(np.float32)
+    kk = rr if rr > 0 else args.k
+    fa32, fr32 = fa.astype(np.float32), fr.astype(np.float32)
+    reps, t_search = 0, 0.0
+    while t_search < 2.0 or reps < 2:          # the whole query path, repeated for a stable rate
+        t2 = time.perf_counter()
+        pr, _ = oracle.probe(qs, cent_np, nprobe)
+        qrot = oracle.rotate(qs, P_np).astype(np.float32)
+        oi, od = oracle.search(off, ids, codes, fa32, fr32, crot, qrot, remap[pr].astype(np.int32), args.bits, kk)
+        if rr > 0:
+            oi, od = oracle.rerank(x_np, qs, oi, args.k)
+        t_search += time.perf_counter() - t2
+        reps += 1
+    cores = oracle.num_threads()
+    qps = S * reps / t_search
+    log("cpu baseline: %.1f QPS (%d queries, %.2fs), encode %.0f codes/s, %d threads" %
+        (qps, S, t_search, len(ids) / t_enc, cores))
+    return {"value": qps, "unit": "QPS", "cores": cores, "kind": "oracle",
+            "sample": "%d queries: FP64 probe over %d centroids, int8-estimator scan of nprobe=%d lists, "
+                      "re-rank %d; lists encoded by the oracle (%d rows)" % (S, cent_np.shape[0], nprobe, rr, len(ids)),
+            "encode_codes_per_s": len(ids) / t_enc}
+
+
+if __name__ == "__main__":
+    main()

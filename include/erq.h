@@ -168,6 +168,18 @@ int erq_search(erq_index idx, const float* q, int64_t nq, int32_t nprobe, int32_
                int32_t rerank_k, int64_t* out_ids, float* out_dist,
                void* workspace, size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------------------------ */
+/* Kernel timing (measurement support, not part of the method).  While       */
+/* enabled, every launch of the named kernels is bracketed by two HIP events */
+/* recorded on the stream it is launched on.  Names: "scan" (the int8 matrix- */
+/* core scan kernel), "quantize", "rotate", "probe", "merge", "rerank".       */
+/* erq_profile_read waits for the recorded events and returns the summed     */
+/* duration (ms) and launch count of one kernel (host outputs); reset != 0   */
+/* drops the records of every kernel.                                        */
+/* ------------------------------------------------------------------------ */
+int erq_profile_enable(int32_t on);
+int erq_profile_read(const char* kernel, double* total_ms, int64_t* launches, int32_t reset);
+
 #ifdef __cplusplus
 }
 #endif

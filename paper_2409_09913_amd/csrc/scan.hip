@@ -544,6 +544,7 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, in
     ERQ_HIP(hipGetLastError());
     const int64_t max_items = (P + kQT - 1) / kQT + nlist;
     hipError_t e = hipSuccess;
+    const int pr = prof_begin(PK_SCAN, st);
     if (P > 0) {
         switch (ix->bits) {
             case 1: e = launch_scan_b<1>(ix, qrot, pair_off, pair_q, pair_slot, item_off, max_items, kk, res_est, res_id, st); break;
@@ -556,11 +557,14 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, in
             default: e = launch_scan_b<8>(ix, qrot, pair_off, pair_q, pair_slot, item_off, max_items, kk, res_est, res_id, st); break;
         }
     }
+    prof_end(pr, st);
     if (e != hipSuccess) return fail(ERQ_EDEVICE, std::string("scan launch: ") + hipGetErrorString(e));
+    const int pm = prof_begin(PK_MERGE, st);
     if (nq > 0) {
         hipLaunchKernelGGL(merge_kernel, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, st, probes, nq, nprobe,
                            (int)nlist, kk, res_est, res_id, out_ids, out_est);
     }
+    prof_end(pm, st);
     ERQ_HIP(hipGetLastError());
     return ERQ_OK;
 }

@@ -144,6 +144,10 @@ __global__ __launch_bounds__(1024) void sort_lists_kernel(const int64_t* __restr
     const int l = blockIdx.x;
     const int64_t lo = off[l];
     const int n = (int)(off[l + 1] - lo);
+    if (n > 16384) {            // too long for one LDS sort: keep the scatter order
+        for (int t = threadIdx.x; t < n; t += blockDim.x) ids64[lo + t] = ids32[lo + t];
+        return;
+    }
     int S = 1;
     while (S < n) S <<= 1;
     for (int t = threadIdx.x; t < S; t += blockDim.x) s[t] = (t < n) ? ids32[lo + t] : 0x7FFFFFFF;

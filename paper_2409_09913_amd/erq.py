@@ -39,6 +39,8 @@ SIGNATURES = {
     "erq_rerank": (C.c_int, [_p, _p, _i64, _p, _i32, _i32, _p, _p, _p]),
     "erq_search_workspace_size": (C.c_int, [_p, _i64, _i32, _i32, _i32, C.POINTER(_sz)]),
     "erq_search": (C.c_int, [_p, _p, _i64, _i32, _i32, _i32, _p, _p, _p, _sz, _p]),
+    "erq_profile_enable": (C.c_int, [_i32]),
+    "erq_profile_read": (C.c_int, [C.c_char_p, C.POINTER(C.c_double), C.POINTER(_i64), _i32]),
 }
 
 _lib = None
@@ -225,3 +227,15 @@ class Index:
         _check(load().erq_search(self.h, _ptr(q, torch.float32, "q"), nq, nprobe, k, rerank_k, _ptr(ids), _ptr(d),
                                  _ptr(ws), ws.numel(), _stream()))
         return ids, d
+
+
+def profile_enable(on: bool = True):
+    """Bracket the library's kernels with HIP events on their launch stream."""
+    _check(load().erq_profile_enable(int(on)))
+
+
+def profile_read(kernel: str, reset: bool = False):
+    """(total milliseconds, launches) recorded for one kernel since the last reset."""
+    ms, n = C.c_double(), C.c_int64()
+    _check(load().erq_profile_read(kernel.encode(), C.byref(ms), C.byref(n), int(reset)))
+    return ms.value, n.value
