@@ -61,6 +61,8 @@ def main():
     ap.add_argument("--target-recall", type=float, default=0.95)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-queries", type=int, default=32)
+    ap.add_argument("--nprobe", type=int, default=0, help="fixed operating point (skips the sweep)")
+    ap.add_argument("--rerank", type=int, default=-1, help="fixed re-rank depth (with --nprobe)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -114,7 +116,7 @@ def main():
     log("encode B=%d: %.3fs -> %.3g codes/s" % (args.bits, t_enc, enc_rate))
     enc_rate2 = None
     if args.bits2:
-        ix2, t_enc2 = build_index(args.bits2, keep_raw=False)
+        ix2, t_enc2 = build_index(args.bits2, keep_raw=True)
         enc_rate2 = args.n / t_enc2
         log("encode B=%d: %.3fs -> %.3g codes/s" % (args.bits2, t_enc2, enc_rate2))
 
@@ -152,8 +154,10 @@ def main():
 
     def sweep(index, label):
         rows = []
-        for nprobe in (8, 16, 32, 64, 128):
-            for rr in (0, 20, 40):
+        grid = [(args.nprobe, max(args.rerank, 0))] if args.nprobe > 0 else \
+            [(n_, r_) for n_ in (8, 16, 32, 64, 128, 256) for r_ in (0, 10, 20, 30)]
+        for nprobe, rr in grid:
+            if True:
                 ids, qps = timed_search(index, nprobe, rr, 3)
                 rec = recall_at(ids, truth_np, args.k)
                 rows.append((nprobe, rr, rec, qps))
@@ -185,9 +189,16 @@ def main():
     dt = time.perf_counter() - ts
     scan_ms, scan_n = erq.profile_read("scan")
     tot = {}
-    for kname in ("rotate", "probe", "scan", "merge", "rerank"):
+    for kname in ("rotate", "probe", "scan", "scan_a", "scan_b", "scan_c", "merge", "rerank"):
         ms, nl = erq.profile_read(kname)
         tot[kname] = ms / max(nl, 1)
+    erq.profile_read("scan", reset=True)
+    erq.profile_enable(2)                       # one extra search: count the pairs re-scanned in pass C
+    erq.profile_read("scan_redo_pairs", reset=True)
+    ix.search(q, nprobe, args.k, rr, ws=ws, out=out)
+    torch.cuda.synchronize()
+    redo, _ = erq.profile_read("scan_redo_pairs", reset=True)
+    tot["redo_pairs"] = redo
     erq.profile_read("scan", reset=True)
     erq.profile_enable(False)
     qps = args.steps * args.nq / dt

@@ -140,7 +140,7 @@ int erq_index_export(erq_index idx, int64_t* list_off, int64_t* ids, uint8_t* co
 /* in int32 on the matrix cores; est = f_add + ||s'||^2 + f_rescale * delta/2 */
 /* * (2 <y_u, s_int> - (2^B - 1) sum s_int) in FP32.                          */
 /* Output: out_ids, out_est nq x kk ascending by (est, id); missing entries  */
-/* are (-1, +inf).  kk in [1, 64].  workspace: erq_scan_workspace_size.      */
+/* are (-1, +inf).  kk in [1, 32].  workspace: erq_scan_workspace_size.      */
 /* ------------------------------------------------------------------------ */
 int erq_scan_workspace_size(erq_index idx, int64_t nq, int32_t nprobe, int32_t kk, size_t* bytes);
 int erq_scan(erq_index idx, const float* qrot, int64_t nq, const int32_t* probes,
@@ -159,7 +159,7 @@ int erq_rerank(erq_index idx, const float* q, int64_t nq, const int64_t* cand, i
 /* ------------------------------------------------------------------------ */
 /* Whole query path: rotate, coarse probe, scan, and (rerank_k > 0) exact    */
 /* re-rank of the rerank_k best estimates.  Output nq x k: estimated squared */
-/* distances without re-rank, exact ones with it.  k <= 64, rerank_k <= 64.  */
+/* distances without re-rank, exact ones with it.  k <= 32, rerank_k <= 32.  */
 /* workspace: erq_search_workspace_size.                                     */
 /* ------------------------------------------------------------------------ */
 int erq_search_workspace_size(erq_index idx, int64_t nq, int32_t nprobe, int32_t k,
@@ -172,7 +172,10 @@ int erq_search(erq_index idx, const float* q, int64_t nq, int32_t nprobe, int32_
 /* Kernel timing (measurement support, not part of the method).  While       */
 /* enabled, every launch of the named kernels is bracketed by two HIP events */
 /* recorded on the stream it is launched on.  Names: "scan" (the int8 matrix- */
-/* core scan kernel), "quantize", "rotate", "probe", "merge", "rerank".       */
+/* core scan, all passes), "scan_a", "scan_b", "scan_c" (its passes),         */
+/* "quantize", "rotate", "probe", "merge", "rerank".  "scan_redo_pairs"      */
+/* returns in total_ms the number of pairs re-scanned exactly in pass C;    */
+/* it is counted only with on == 2, which synchronises after each scan.     */
 /* erq_profile_read waits for the recorded events and returns the summed     */
 /* duration (ms) and launch count of one kernel (host outputs); reset != 0   */
 /* drops the records of every kernel.                                        */

@@ -33,7 +33,10 @@ struct ProfRec { int kernel; hipEvent_t a, b; };
 std::mutex g_prof_mu;
 std::vector<ProfRec> g_prof;
 bool g_prof_on = false;
-const char* const kProfNames[PK_COUNT] = {"scan", "quantize", "rotate", "probe", "merge", "rerank"};
+bool g_prof_stats = false;     // also count pass-C pairs (synchronises after each scan)
+const char* const kProfNames[PK_COUNT] = {"scan", "quantize", "rotate", "probe", "merge", "rerank",
+                                          "scan_a", "scan_b", "scan_c"};
+int64_t g_redo_total = 0, g_redo_calls = 0;
 }  // namespace
 
 int prof_begin(int kernel, hipStream_t st)
@@ -45,6 +48,20 @@ int prof_begin(int kernel, hipStream_t st)
     hipEventRecord(r.a, st);
     g_prof.push_back(r);
     return (int)g_prof.size() - 1;
+}
+
+void prof_note_redo(const int32_t* dev_count, hipStream_t st)
+{
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        if (!g_prof_on || !g_prof_stats) return;
+    }
+    int32_t h = 0;
+    if (hipMemcpyAsync(&h, dev_count, sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess) return;
+    if (hipStreamSynchronize(st) != hipSuccess) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_redo_total += h;
+    g_redo_calls += 1;
 }
 
 void prof_end(int rec, hipStream_t st)
@@ -419,7 +436,7 @@ int erq_scan(erq_index ix, const float* qrot, int64_t nq, const int32_t* probes,
     if (!ix || !ix->codes) return fail(ERQ_EINVAL, "erq_scan: index is empty");
     if (nq < 0 || nq * (int64_t)std::max(nprobe, 1) > (1LL << 31) - 1) return fail(ERQ_EINVAL, "erq_scan: nq out of range");
     if (nprobe < 1 || nprobe > 1024) return fail(ERQ_EUNSUPPORTED, "erq_scan: nprobe must be in [1, 1024]");
-    if (kk < 1 || kk > 64) return fail(ERQ_EUNSUPPORTED, "erq_scan: kk must be in [1, 64]");
+    if (kk < 1 || kk > 32) return fail(ERQ_EUNSUPPORTED, "erq_scan: kk must be in [1, 32]");
     if (nq > 0 && (!qrot || !probes || !out_ids || !out_est || !workspace)) return fail(ERQ_EINVAL, "erq_scan: null pointer");
     if (ix->nlist > 1000000) return fail(ERQ_EUNSUPPORTED, "erq_scan: more than 10^6 lists");
     return run_scan(ix, qrot, nq, probes, nprobe, kk, out_ids, out_est, workspace, ws_bytes, (hipStream_t)stream);
@@ -459,8 +476,8 @@ int erq_search(erq_index ix, const float* q, int64_t nq, int32_t nprobe, int32_t
                int64_t* out_ids, float* out_dist, void* workspace, size_t ws_bytes, void* stream)
 {
     if (!ix || !ix->codes) return fail(ERQ_EINVAL, "erq_search: index is empty");
-    if (k < 1 || k > 64) return fail(ERQ_EUNSUPPORTED, "erq_search: k must be in [1, 64]");
-    if (rerank_k < 0 || rerank_k > 64 || (rerank_k > 0 && rerank_k < k)) return fail(ERQ_EUNSUPPORTED, "erq_search: rerank_k must be 0 or in [k, 64]");
+    if (k < 1 || k > 32) return fail(ERQ_EUNSUPPORTED, "erq_search: k must be in [1, 32]");
+    if (rerank_k < 0 || rerank_k > 32 || (rerank_k > 0 && rerank_k < k)) return fail(ERQ_EUNSUPPORTED, "erq_search: rerank_k must be 0 or in [k, 32]");
     if (rerank_k > 0 && !ix->raw) return fail(ERQ_EINVAL, "erq_search: re-rank needs raw vectors in the index");
     if (nprobe < 1 || nprobe > 1024 || nprobe > ix->nlist) return fail(ERQ_EUNSUPPORTED, "erq_search: nprobe must be in [1, min(nlist, 1024)]");
     if (nq < 0 || nq * (int64_t)nprobe > (1LL << 31) - 1) return fail(ERQ_EINVAL, "erq_search: nq out of range");
@@ -495,12 +512,20 @@ int erq_profile_enable(int32_t on)
 {
     std::lock_guard<std::mutex> lk(g_prof_mu);
     g_prof_on = on != 0;
+    g_prof_stats = on >= 2;
     return ERQ_OK;
 }
 
 int erq_profile_read(const char* kernel, double* total_ms, int64_t* launches, int32_t reset)
 {
     if (!kernel) return fail(ERQ_EINVAL, "erq_profile_read: null name");
+    if (std::strcmp(kernel, "scan_redo_pairs") == 0) {        // pairs sent to pass C, summed over scans
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        if (total_ms) *total_ms = (double)g_redo_total;
+        if (launches) *launches = g_redo_calls;
+        if (reset) { g_redo_total = 0; g_redo_calls = 0; }
+        return ERQ_OK;
+    }
     int kid = -1;
     for (int i = 0; i < PK_COUNT; ++i) if (std::strcmp(kernel, kProfNames[i]) == 0) kid = i;
     if (kid < 0) return fail(ERQ_EINVAL, std::string("erq_profile_read: unknown kernel ") + kernel);

@@ -80,7 +80,10 @@ struct Index {
 void free_index_storage(Index* ix);
 
 // ---- kernel timing (see erq_profile_enable) ---------------------------------
-enum ProfKernel { PK_SCAN = 0, PK_QUANTIZE, PK_ROTATE, PK_PROBE, PK_MERGE, PK_RERANK, PK_COUNT };
+enum ProfKernel { PK_SCAN = 0, PK_QUANTIZE, PK_ROTATE, PK_PROBE, PK_MERGE, PK_RERANK, PK_SCAN_A, PK_SCAN_B,
+                  PK_SCAN_C, PK_COUNT };
+// diagnostics of the last scan while profiling is on (pairs queued to pass C)
+void prof_note_redo(const int32_t* dev_count, hipStream_t st);
 // returns a started record (or -1 when profiling is off); prof_end closes it
 int prof_begin(int kernel, hipStream_t st);
 void prof_end(int rec, hipStream_t st);

@@ -1,21 +1,30 @@
 // IVF scan of Extended RaBitQ codes on the int8 matrix cores (Sec. 3.3,
-// Sec. 4.1), in three steps per query batch:
+// Sec. 4.1).  For every (query, probed list) pair the estimated squared
+// distance of every member is
+//     est = f_add + ||s'||^2 + f_rescale * delta/2 * (2 <y_u, s_int> - (2^B - 1) sum s_int)
+// (Eq. eq:dis to ip with Eq. eq 3.3: represent), where s' = q' - c' is the
+// rotated query residual of the list, quantised to int8 per pair
+// (symmetric, delta = max|s'|/127), and <y_u, s_int> is accumulated exactly in
+// int32 by v_mfma_i32_32x32x32_i8.  The kk smallest (est, id) per query are
+// returned.  One query batch runs as:
 //
-//  1. pair build: (query, list) pairs of the probe table grouped by list
-//     (count, exclusive scan, scatter); the work items are (list, tile of up
-//     to 32 of its queries), enumerated longest list first.
-//  2. scan: one workgroup (4 waves) per work item.  Prologue: for each of
-//     its queries s' = q' - c' (FP32), int8 quantisation (symmetric, scale
-//     max|s'|/127), ||s'||^2 and sum(s_int), written to LDS in the layout of
-//     the B operand of v_mfma_i32_32x32x32_i8.  Main loop: every wave takes
-//     32-vector code tiles of the list, unpacks the packed B-bit codes to
-//     int8 in registers and accumulates <y_u, s_int> exactly in int32.
-//     Epilogue: est = f_add + ||s||^2 + f_rescale * delta/2 *
-//     (2 <y_u, s_int> - (2^B - 1) sum s_int)  (Eq. eq:dis to ip with Eq.
-//     eq 3.3: represent), kept per lane in a sorted register list of the best
-//     KK (est, id) with a threshold shared through LDS; the lists of the
-//     8 lanes that saw a query are merged into its top-kk for this list.
-//  3. merge: per query, the kk best over its probed lists.
+//  1. pair build: (query, probe) pairs grouped by list (count, scan,
+//     scatter); work items are (list, tile of its queries), longest list
+//     first.  Pass A takes the pairs of the query's kRankA nearest probes.
+//  2. pass A (a bound): exact top-kk of the first kVecA members of those
+//     lists, with sorted per-lane register lists; per query, the kk-th best
+//     of these estimates, tau_q.  Any subset of a query's candidates gives a
+//     valid bound: every member of the final top-kk has est <= tau_q.
+//  3. pass B (the scan): every pair, every member, 64 vectors x 64 queries per
+//     wave step.  Estimates above tau_q are dropped with one compare; the
+//     rest are staged in a per-query LDS buffer (spilling straight to global
+//     memory when it is full) and appended to the query's candidate buffer
+//     in HBM.  Each item lowers tau_q to the kk-th best it found.
+//  4. select: per query, the exact kk smallest (est, id) of its candidates.
+//  5. fallback: a query whose candidate buffer overflowed is scanned again
+//     pair by pair with the exact per-lane-list kernel and merged.
+#include <algorithm>
+
 #include "erq_common.h"
 
 namespace erq {
@@ -23,7 +32,11 @@ namespace erq {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kQT = 32;        // queries per work item (columns of the MFMA tile)
+constexpr int kQT = 32;        // queries per MFMA column tile
+constexpr int kCapB = 48;      // per-query survivor buffer of a pass-B item (LDS)
+constexpr int kRankA = 8;      // pass A: nearest probes per query ...
+constexpr int kVecA = 128;     // ... and members per list used for the bound
+constexpr int kCapQ = 4096;    // candidate buffer per query (HBM)
 
 __device__ inline unsigned f2key(float f) {
     unsigned u = __float_as_uint(f);
@@ -113,227 +126,469 @@ __device__ inline float kth_of(const float* le, int kk) {
     return c;
 }
 
+__device__ inline int out_row(int lane, int r) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
+
+// Item of a pair table grouped by list: largest rank r with item_off[r] <= item.
+__device__ inline void decode_item(int item, const int32_t* item_off, const int32_t* list_order, int nlist,
+                                   int* l, int* t) {
+    int lo = 0, hi = nlist;
+    while (hi - lo > 1) { int mid = (lo + hi) >> 1; if (item_off[mid] <= item) lo = mid; else hi = mid; }
+    while (lo + 1 < nlist && item_off[lo + 1] <= item) ++lo;
+    *l = list_order[lo];
+    *t = item - item_off[lo];
+}
+
+// Prologue shared by both passes: int8 residual queries of one item into LDS,
+// laid out as the B operand: query qi = qt*32 + j, 16-dim chunk c = 2 ks + h at
+// byte ((ks*NQT + qt)*64 + h*32 + j)*16.
+template <int NQT>
+__device__ inline void load_queries(int8_t* qs, float* s_s2, float* s_hd, int* s_ss, int* s_slot, int* s_q,
+                                    const float* __restrict__ qrot, const float* __restrict__ cv, int dp,
+                                    const int32_t* __restrict__ pq, const int32_t* __restrict__ pslot, int mq,
+                                    int wid, int lane)
+{
+    const int nch = dp / 16;
+    for (int qi = wid; qi < kQT * NQT; qi += 4) {
+        const int qt = qi >> 5, j = qi & 31;
+        if (qi >= mq) {
+            for (int c = lane; c < nch; c += 64) {
+                const int ks = c >> 1, h = c & 1;
+                *(uint4*)(qs + ((ks * NQT + qt) * 64 + h * 32 + j) * 16) = make_uint4(0, 0, 0, 0);
+            }
+            continue;
+        }
+        const int q = pq[qi];
+        const float* qv = qrot + (int64_t)q * dp;
+        // first pass: max |s'| and ||s'||^2; second pass: quantise (re-reads hit the caches)
+        float amax = 0.0f, s2 = 0.0f;
+        for (int c = lane; c < nch; c += 64) {
+#pragma unroll
+            for (int e = 0; e < 16; e += 4) {
+                float4 a = *(const float4*)(qv + c * 16 + e);
+                float4 b = *(const float4*)(cv + c * 16 + e);
+                float d0 = a.x - b.x, d1 = a.y - b.y, d2 = a.z - b.z, d3 = a.w - b.w;
+                amax = fmaxf(amax, fmaxf(fmaxf(fabsf(d0), fabsf(d1)), fmaxf(fabsf(d2), fabsf(d3))));
+                s2 += d0 * d0; s2 += d1 * d1; s2 += d2 * d2; s2 += d3 * d3;
+            }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            amax = fmaxf(amax, __shfl_xor(amax, o));
+            s2 += __shfl_xor(s2, o);
+        }
+        const float inv = (amax > 0.0f) ? __fdiv_rn(127.0f, amax) : 0.0f;
+        int ssum = 0;
+        for (int c = lane; c < nch; c += 64) {
+            uint32_t w4[4];
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                float4 a = *(const float4*)(qv + c * 16 + 4 * d);
+                float4 b = *(const float4*)(cv + c * 16 + 4 * d);
+                const float sd[4] = {a.x - b.x, a.y - b.y, a.z - b.z, a.w - b.w};
+                uint32_t wd = 0;
+#pragma unroll
+                for (int bb = 0; bb < 4; ++bb) {
+                    int v = (int)rintf(sd[bb] * inv);
+                    v = max(-127, min(127, v));
+                    ssum += v;
+                    wd |= ((uint32_t)(v & 0xFF)) << (8 * bb);
+                }
+                w4[d] = wd;
+            }
+            const int ks = c >> 1, h = c & 1;
+            *(uint4*)(qs + ((ks * NQT + qt) * 64 + h * 32 + j) * 16) = make_uint4(w4[0], w4[1], w4[2], w4[3]);
+        }
+        for (int o = 32; o > 0; o >>= 1) ssum += __shfl_xor(ssum, o);
+        if (lane == 0) {
+            s_s2[qi] = s2;
+            s_hd[qi] = 0.5f * ((amax > 0.0f) ? __fdiv_rn(amax, 127.0f) : 0.0f);
+            s_ss[qi] = ssum;
+            s_slot[qi] = pslot[qi];
+            s_q[qi] = q;
+        }
+    }
+}
+
+template <int BITS>
+__device__ inline float estimate(float2 f, int acc, float s2, float hd, int ss) {
+    constexpr int corr = 2 * (BITS == 8 ? 128 : 0) - ((1 << BITS) - 1);
+    const int ip2 = 2 * acc + corr * ss;
+    return (f.x + s2) + f.y * (hd * (float)ip2);
+}
+
+// ---------------------------------------------------------------------------
+// Pass A / fallback: exact per-pair top-kk, 32 queries per item, per-lane
+// lists; only the first vmax members of each list are scanned.  Items come
+// from a pair table grouped by list (redo == nullptr) or one item per queued
+// pair.  Grid-stride loop over items.
 // ---------------------------------------------------------------------------
 template <int BITS, int KK>
-__global__ __launch_bounds__(kThreads, 2) void scan_kernel(
+__global__ __launch_bounds__(kThreads, 2) void scanA_kernel(
     const uint8_t* __restrict__ codes, const int64_t* __restrict__ tile_off,
     const int64_t* __restrict__ list_off, const float2* __restrict__ fac,
     const int64_t* __restrict__ ids, const float* __restrict__ cent_rot, int dp,
     const float* __restrict__ qrot, const int32_t* __restrict__ pair_off,
     const int32_t* __restrict__ pair_q, const int32_t* __restrict__ pair_slot,
     const int32_t* __restrict__ item_off, const int32_t* __restrict__ list_order, int nlist,
+    const int32_t* __restrict__ redo_l, const int32_t* __restrict__ redo_n, int vmax,
     int kk, float* __restrict__ res_est, int32_t* __restrict__ res_id)
 {
     extern __shared__ __align__(16) char smem[];
     __shared__ float s_s2[kQT], s_hd[kQT];
-    __shared__ int s_ss[kQT], s_slot[kQT];
+    __shared__ int s_ss[kQT], s_slot[kQT], s_q[kQT];
     __shared__ unsigned s_thr[kQT];
-    __shared__ int s_item[2];
+    __shared__ int s_item[3];
+
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int n_items = redo_l ? *redo_n : item_off[nlist];
+    const int nkb = dp / 64;
+    int8_t* qs = (int8_t*)smem;
+    const v4i* qb = (const v4i*)qs;
+    const int64_t tile_bytes = (int64_t)4 * dp * BITS;
+
+    for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
+        __syncthreads();                               // LDS of the previous item is free
+        if (tid == 0) {
+            if (redo_l) {
+                s_item[0] = redo_l[item]; s_item[1] = item; s_item[2] = 1;
+            } else {
+                int l, t;
+                decode_item(item, item_off, list_order, nlist, &l, &t);
+                const int p0 = pair_off[l] + t * kQT;
+                s_item[0] = l; s_item[1] = p0; s_item[2] = min(kQT, pair_off[l + 1] - p0);
+            }
+        }
+        if (tid < kQT) s_thr[tid] = 0xFFFFFFFFu;
+        __syncthreads();
+        const int l = s_item[0], p0 = s_item[1], mq = s_item[2];
+        load_queries<1>(qs, s_s2, s_hd, s_ss, s_slot, s_q, qrot, cent_rot + (int64_t)l * dp, dp,
+                        pair_q + p0, pair_slot + p0, mq, wid, lane);
+        __syncthreads();
+
+        const int j = lane & 31;
+        const bool qvalid = j < mq;
+        const float qs2 = qvalid ? s_s2[j] : 0.0f;
+        const float qhd = qvalid ? s_hd[j] : 0.0f;
+        const int qss = qvalid ? s_ss[j] : 0;
+        float le[KK];
+        int li[KK];
+#pragma unroll
+        for (int t = 0; t < KK; ++t) { le[t] = __builtin_huge_valf(); li[t] = 0x7FFFFFFF; }
+        float cut = __builtin_huge_valf();
+        const int64_t lbase = list_off[l];
+        const int nl = min((int)(list_off[l + 1] - lbase), vmax);
+        const int ntile = (nl + 31) >> 5;
+        const int64_t tbase = tile_off[l];
+
+        for (int tt = wid; tt < ntile; tt += 4) {
+            const uint8_t* tp = codes + (tbase + tt) * tile_bytes;
+            v16i acc;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[r] = 0;
+            for (int kb = 0; kb < nkb; ++kb) {
+                v4i a0, a1;
+                load_codes<BITS>(tp + (int64_t)kb * 256 * BITS, lane, a0, a1);
+                v4i b0 = qb[(kb * 2 + 0) * 64 + lane];
+                v4i b1 = qb[(kb * 2 + 1) * 64 + lane];
+                acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, b0, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, b1, acc, 0, 0, 0);
+            }
+            const float c0 = fminf(cut, key2f(s_thr[j]));
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int v = tt * 32 + out_row(lane, r);
+                const bool ok = qvalid && v < nl;
+                float est = __builtin_huge_valf();
+                if (ok) est = estimate<BITS>(fac[lbase + v], acc[r], qs2, qhd, qss);
+                const bool pass = ok && est <= c0;
+                if (__any(pass)) {
+                    int id = 0x7FFFFFFF;
+                    if (pass) id = (int)ids[lbase + v];
+                    else est = __builtin_huge_valf();
+                    insert_sorted<KK>(le, li, est, id);
+                }
+            }
+            cut = kth_of<KK>(le, kk);
+            if (qvalid && cut < __builtin_huge_valf()) atomicMin(&s_thr[j], f2key(cut));
+        }
+        __syncthreads();                           // done with the B operand: reuse LDS
+
+        // lanes j and j+32 hold the same query: keep the KK smallest of both
+        {
+            float oe[KK]; int oi[KK];
+#pragma unroll
+            for (int t = 0; t < KK; ++t) { oe[t] = __shfl_xor(le[t], 32); oi[t] = __shfl_xor(li[t], 32); }
+#pragma unroll
+            for (int t = 0; t < KK; ++t) {
+                bool take = lt(oe[KK - 1 - t], oi[KK - 1 - t], le[t], li[t]);
+                float e = take ? oe[KK - 1 - t] : le[t];
+                int i = take ? oi[KK - 1 - t] : li[t];
+                le[t] = e; li[t] = i;
+            }
+#pragma unroll
+            for (int jj = KK / 2; jj > 0; jj >>= 1) {
+#pragma unroll
+                for (int t = 0; t < KK; ++t) {
+                    if ((t & jj) == 0) {
+                        const int p = t + jj;
+                        if (lt(le[p], li[p], le[t], li[t])) {
+                            float e = le[t]; le[t] = le[p]; le[p] = e;
+                            int i = li[t]; li[t] = li[p]; li[p] = i;
+                        }
+                    }
+                }
+            }
+        }
+        float* me = (float*)smem;                         // [4][32][KK]
+        int* mi = (int*)(smem + sizeof(float) * 4 * kQT * KK);
+        if (lane < 32) {
+#pragma unroll
+            for (int t = 0; t < KK; ++t) {
+                me[(wid * kQT + lane) * KK + t] = le[t];
+                mi[(wid * kQT + lane) * KK + t] = li[t];
+            }
+        }
+        __syncthreads();
+        if (tid < mq) {
+            int h[4] = {0, 0, 0, 0};
+            const int slot = s_slot[tid];
+            for (int o = 0; o < kk; ++o) {
+                int bw = 0;
+                float be = me[(0 * kQT + tid) * KK + h[0]];
+                int bi = mi[(0 * kQT + tid) * KK + h[0]];
+                for (int w = 1; w < 4; ++w) {
+                    float e = me[(w * kQT + tid) * KK + h[w]];
+                    int i = mi[(w * kQT + tid) * KK + h[w]];
+                    if (lt(e, i, be, bi)) { be = e; bi = i; bw = w; }
+                }
+                if (h[bw] < KK - 1) ++h[bw];
+                else { me[(bw * kQT + tid) * KK + h[bw]] = __builtin_huge_valf(); mi[(bw * kQT + tid) * KK + h[bw]] = 0x7FFFFFFF; }
+                res_est[(int64_t)slot * kk + o] = be;
+                res_id[(int64_t)slot * kk + o] = (be < __builtin_huge_valf()) ? bi : -1;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Pass B: items of 32*NQT queries; each wave step is 64 vectors (two code
+// tiles) x 32*NQT queries, so every unpacked code fragment feeds 2*NQT MFMAs
+// and every query fragment 2.  Estimates above the query's bound are dropped
+// with one compare; survivors go to the query's candidate buffer in HBM
+// (staged in LDS; straight to HBM once the LDS stage is full).
+// ---------------------------------------------------------------------------
+template <int BITS, int NQT>
+__global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
+    const uint8_t* __restrict__ codes, const int64_t* __restrict__ tile_off,
+    const int64_t* __restrict__ list_off, const float2* __restrict__ fac,
+    const int64_t* __restrict__ ids, const float* __restrict__ cent_rot, int dp,
+    const float* __restrict__ qrot, const int32_t* __restrict__ pair_off,
+    const int32_t* __restrict__ pair_q, const int32_t* __restrict__ pair_slot,
+    const int32_t* __restrict__ item_off, const int32_t* __restrict__ list_order, int nlist,
+    int kk, unsigned* __restrict__ tau_key, int32_t* __restrict__ gcnt,
+    float* __restrict__ gbuf_e, int32_t* __restrict__ gbuf_i)
+{
+    constexpr int QPI = kQT * NQT;
+    extern __shared__ __align__(16) char smem[];
+    __shared__ float s_s2[QPI], s_hd[QPI];
+    __shared__ int s_ss[QPI], s_slot[QPI], s_q[QPI], s_cnt[QPI], s_base[QPI];
+    __shared__ float s_be[QPI][kCapB];
+    __shared__ int s_bi[QPI][kCapB];
+    __shared__ unsigned s_tau[QPI];
+    __shared__ int s_item[3];
 
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int item = blockIdx.x;
     if (item >= item_off[nlist]) return;
     if (tid == 0) {
-        int lo = 0, hi = nlist;                    // largest r with item_off[r] <= item
-        while (hi - lo > 1) { int mid = (lo + hi) >> 1; if (item_off[mid] <= item) lo = mid; else hi = mid; }
-        while (lo + 1 < nlist && item_off[lo + 1] <= item) ++lo;
-        s_item[0] = list_order[lo];
-        s_item[1] = item - item_off[lo];
+        int l, t;
+        decode_item(item, item_off, list_order, nlist, &l, &t);
+        const int p0 = pair_off[l] + t * QPI;
+        s_item[0] = l; s_item[1] = p0; s_item[2] = min(QPI, pair_off[l + 1] - p0);
     }
-    if (tid < kQT) s_thr[tid] = 0xFFFFFFFFu;
+    if (tid < QPI) s_cnt[tid] = 0;
     __syncthreads();
-    const int l = s_item[0];
-    const int qtile = s_item[1];
-    const int p0 = pair_off[l] + qtile * kQT;
-    const int mq = min(kQT, pair_off[l + 1] - p0);
+    const int l = s_item[0], p0 = s_item[1], mq = s_item[2];
+    int8_t* qs = (int8_t*)smem;
+    load_queries<NQT>(qs, s_s2, s_hd, s_ss, s_slot, s_q, qrot, cent_rot + (int64_t)l * dp, dp,
+                      pair_q + p0, pair_slot + p0, mq, wid, lane);
+    __syncthreads();
+    // columns without a query take -inf so that nothing passes
+    if (tid < QPI) s_tau[tid] = (tid < mq) ? tau_key[s_q[tid]] : 0u;
+    __syncthreads();
+
     const int nkb = dp / 64;
-    int8_t* qs = (int8_t*)smem;                  // B operand: (ks*64 + lane) * 16 bytes
-
-    // ---- prologue: int8 residual queries ---------------------------------
-    {
-        const float* cv = cent_rot + (int64_t)l * dp;
-        const int nch = dp / 16;                  // 16-dim chunks
-        for (int jj = wid; jj < kQT; jj += 4) {
-            if (jj >= mq) {
-                for (int c = lane; c < nch; c += 64) {
-                    const int ks = c >> 1, h = c & 1;
-                    *(uint4*)(qs + ((ks * 2 + h) * kQT + jj) * 16) = make_uint4(0, 0, 0, 0);
-                }
-                continue;
-            }
-            const int q = pair_q[p0 + jj];
-            const float* qv = qrot + (int64_t)q * dp;
-            float sv[4][16];
-            float amax = 0.0f, s2 = 0.0f;
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int c = lane + 64 * u;
-                if (c < nch) {
-#pragma unroll
-                    for (int e = 0; e < 16; e += 4) {
-                        float4 a = *(const float4*)(qv + c * 16 + e);
-                        float4 b = *(const float4*)(cv + c * 16 + e);
-                        sv[u][e + 0] = a.x - b.x; sv[u][e + 1] = a.y - b.y;
-                        sv[u][e + 2] = a.z - b.z; sv[u][e + 3] = a.w - b.w;
-                    }
-#pragma unroll
-                    for (int e = 0; e < 16; ++e) { amax = fmaxf(amax, fabsf(sv[u][e])); s2 += sv[u][e] * sv[u][e]; }
-                }
-            }
-            for (int o = 32; o > 0; o >>= 1) {
-                amax = fmaxf(amax, __shfl_xor(amax, o));
-                s2 += __shfl_xor(s2, o);
-            }
-            const float inv = (amax > 0.0f) ? __fdiv_rn(127.0f, amax) : 0.0f;
-            int ssum = 0;
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int c = lane + 64 * u;
-                if (c < nch) {
-                    uint32_t w4[4];
-#pragma unroll
-                    for (int d = 0; d < 4; ++d) {
-                        uint32_t wd = 0;
-#pragma unroll
-                        for (int b = 0; b < 4; ++b) {
-                            int v = (int)rintf(sv[u][4 * d + b] * inv);
-                            v = max(-127, min(127, v));
-                            ssum += v;
-                            wd |= ((uint32_t)(v & 0xFF)) << (8 * b);
-                        }
-                        w4[d] = wd;
-                    }
-                    const int ks = c >> 1, h = c & 1;
-                    *(uint4*)(qs + ((ks * 2 + h) * kQT + jj) * 16) = make_uint4(w4[0], w4[1], w4[2], w4[3]);
-                }
-            }
-            for (int o = 32; o > 0; o >>= 1) ssum += __shfl_xor(ssum, o);
-            if (lane == 0) {
-                s_s2[jj] = s2;
-                s_hd[jj] = 0.5f * ((amax > 0.0f) ? __fdiv_rn(amax, 127.0f) : 0.0f);
-                s_ss[jj] = ssum;
-                s_slot[jj] = pair_slot[p0 + jj];
-            }
-        }
-    }
-    __syncthreads();
-
-    // ---- main loop -------------------------------------------------------------
-    constexpr int corr = 2 * (BITS == 8 ? 128 : 0) - ((1 << BITS) - 1);
-    const int j = lane & 31;                     // query column of this lane
-    const bool qvalid = j < mq;
-    const float qs2 = qvalid ? s_s2[j] : 0.0f;
-    const float qhd = qvalid ? s_hd[j] : 0.0f;
-    const int qss = qvalid ? s_ss[j] : 0;
-    float le[KK];
-    int li[KK];
-#pragma unroll
-    for (int t = 0; t < KK; ++t) { le[t] = __builtin_huge_valf(); li[t] = 0x7FFFFFFF; }
-    float cut = __builtin_huge_valf();
-
+    const v4i* qb = (const v4i*)qs;
+    const int64_t tile_bytes = (int64_t)4 * dp * BITS;
     const int64_t lbase = list_off[l];
     const int nl = (int)(list_off[l + 1] - lbase);
     const int ntile = (nl + 31) >> 5;
+    const int ngroup = (ntile + 1) >> 1;
     const int64_t tbase = tile_off[l];
-    const int64_t tile_bytes = (int64_t)4 * dp * BITS;
-    const v4i* qb = (const v4i*)qs;
-
-    for (int tt = wid; tt < ntile; tt += 4) {
-        const uint8_t* tp = codes + (tbase + tt) * tile_bytes;
-        v16i acc;
+    const int j = lane & 31;
+    float qs2[NQT], qhd[NQT], qtau[NQT];
+    int qss[NQT];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) acc[r] = 0;
-        for (int kb = 0; kb < nkb; ++kb) {
-            v4i a0, a1;
-            load_codes<BITS>(tp + (int64_t)kb * 256 * BITS, lane, a0, a1);
-            v4i b0 = qb[(kb * 2 + 0) * 64 + lane];
-            v4i b1 = qb[(kb * 2 + 1) * 64 + lane];
-            acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, b0, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, b1, acc, 0, 0, 0);
-        }
-        // epilogue
-        const float shared_cut = key2f(s_thr[j]);
-        const float c0 = fminf(cut, shared_cut);
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int row = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-            const int v = tt * 32 + row;
-            const bool ok = qvalid && v < nl;
-            float est = __builtin_huge_valf();
-            if (ok) {
-                float2 f = fac[lbase + v];
-                const int ip2 = 2 * acc[r] + corr * qss;
-                est = (f.x + qs2) + f.y * (qhd * (float)ip2);
-            }
-            const bool pass = ok && est <= c0;
-            if (__any(pass)) {
-                int id = 0x7FFFFFFF;
-                if (pass) id = (int)ids[lbase + v];
-                else est = __builtin_huge_valf();
-                insert_sorted<KK>(le, li, est, id);
-            }
-        }
-        cut = kth_of<KK>(le, kk);
-        if (qvalid && cut < __builtin_huge_valf()) atomicMin(&s_thr[j], f2key(cut));
+    for (int qt = 0; qt < NQT; ++qt) {
+        const int qi = qt * kQT + j;
+        qs2[qt] = s_s2[qi]; qhd[qt] = s_hd[qi]; qss[qt] = s_ss[qi];
+        qtau[qt] = (qi < mq) ? key2f(s_tau[qi]) : -__builtin_huge_valf();
     }
-    __syncthreads();                           // done with the B operand: reuse LDS
 
-    // ---- merge the 8 lane lists of every query -----------------------------------
-    // lanes j and j+32 of a wave hold the same query: keep the KK smallest of both
-    {
-        float oe[KK]; int oi[KK];
+    for (int g = wid; g < ngroup; g += 4) {
+        const int t0 = 2 * g, t1 = 2 * g + 1;
+        const bool has1 = t1 < ntile;
+        const uint8_t* tp0 = codes + (tbase + t0) * tile_bytes;
+        const uint8_t* tp1 = has1 ? codes + (tbase + t1) * tile_bytes : tp0;
+        v16i acc[2][NQT];
 #pragma unroll
-        for (int t = 0; t < KK; ++t) { oe[t] = __shfl_xor(le[t], 32); oi[t] = __shfl_xor(li[t], 32); }
-        // smallest KK of two sorted lists: min(le[t], oe[KK-1-t]) is bitonic, then sort
+        for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int t = 0; t < KK; ++t) {
-            bool take = lt(oe[KK - 1 - t], oi[KK - 1 - t], le[t], li[t]);
-            float e = take ? oe[KK - 1 - t] : le[t];
-            int i = take ? oi[KK - 1 - t] : li[t];
-            le[t] = e; li[t] = i;
+            for (int qt = 0; qt < NQT; ++qt)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[a][qt][r] = 0;
+        for (int kb = 0; kb < nkb; ++kb) {
+            v4i a00, a01, a10, a11;
+            load_codes<BITS>(tp0 + (int64_t)kb * 256 * BITS, lane, a00, a01);
+            load_codes<BITS>(tp1 + (int64_t)kb * 256 * BITS, lane, a10, a11);
+#pragma unroll
+            for (int qt = 0; qt < NQT; ++qt) {
+                v4i b0 = qb[((2 * kb + 0) * NQT + qt) * 64 + lane];
+                v4i b1 = qb[((2 * kb + 1) * NQT + qt) * 64 + lane];
+                acc[0][qt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a00, b0, acc[0][qt], 0, 0, 0);
+                acc[1][qt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a10, b0, acc[1][qt], 0, 0, 0);
+                acc[0][qt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a01, b1, acc[0][qt], 0, 0, 0);
+                acc[1][qt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a11, b1, acc[1][qt], 0, 0, 0);
+            }
         }
 #pragma unroll
-        for (int jj = KK / 2; jj > 0; jj >>= 1) {
+        for (int a = 0; a < 2; ++a) {
+            if (a == 1 && !has1) break;
+            const int tt = 2 * g + a;
 #pragma unroll
-            for (int t = 0; t < KK; ++t) {
-                if ((t & jj) == 0) {
-                    const int p = t + jj;
-                    if (lt(le[p], li[p], le[t], li[t])) {
-                        float e = le[t]; le[t] = le[p]; le[p] = e;
-                        int i = li[t]; li[t] = li[p]; li[p] = i;
+            for (int r = 0; r < 16; ++r) {
+                const int v = tt * 32 + out_row(lane, r);
+                const bool ok = v < nl;
+                const float2 f = ok ? fac[lbase + v] : make_float2(0.0f, 0.0f);
+#pragma unroll
+                for (int qt = 0; qt < NQT; ++qt) {
+                    const float est = estimate<BITS>(f, acc[a][qt][r], qs2[qt], qhd[qt], qss[qt]);
+                    const bool pass = ok && est <= qtau[qt];
+                    if (__any(pass)) {
+                        if (pass) {
+                            const int qi = qt * kQT + j;
+                            const int id = (int)ids[lbase + v];
+                            const int pos = atomicAdd(&s_cnt[qi], 1);
+                            if (pos < kCapB) {
+                                s_be[qi][pos] = est; s_bi[qi][pos] = id;
+                            } else {                       // stage full: straight to HBM
+                                const int q = s_q[qi];
+                                const int gp = atomicAdd(&gcnt[q], 1);
+                                if (gp < kCapQ) {
+                                    gbuf_e[(int64_t)q * kCapQ + gp] = est;
+                                    gbuf_i[(int64_t)q * kCapQ + gp] = id;
+                                }
+                            }
+                        }
                     }
                 }
             }
         }
     }
-    float* me = (float*)smem;                         // [4][32][KK]
-    int* mi = (int*)(smem + sizeof(float) * 4 * kQT * KK);
-    if (lane < 32) {
-#pragma unroll
-        for (int t = 0; t < KK; ++t) {
-            me[(wid * kQT + lane) * KK + t] = le[t];
-            mi[(wid * kQT + lane) * KK + t] = li[t];
-        }
+    __syncthreads();
+    // flush the LDS stage; the item's kk-th best lowers the query's bound
+    const int qi = tid >> 2, sub = tid & 3;
+    if (qi < mq) {
+        const int q = s_q[qi];
+        const int m = min(s_cnt[qi], kCapB);
+        if (sub == 0) s_base[qi] = (m > 0) ? atomicAdd(&gcnt[q], m) : 0;
     }
     __syncthreads();
-    if (tid < mq) {
-        int h[4] = {0, 0, 0, 0};
-        const int slot = s_slot[tid];
-        for (int o = 0; o < kk; ++o) {
-            int bw = 0;
-            float be = me[(0 * kQT + tid) * KK + h[0]];
-            int bi = mi[(0 * kQT + tid) * KK + h[0]];
-            for (int w = 1; w < 4; ++w) {
-                float e = me[(w * kQT + tid) * KK + h[w]];
-                int i = mi[(w * kQT + tid) * KK + h[w]];
-                if (lt(e, i, be, bi)) { be = e; bi = i; bw = w; }
+    if (qi < mq) {
+        const int q = s_q[qi];
+        const int m = min(s_cnt[qi], kCapB);
+        const int base = s_base[qi];
+        for (int e = sub; e < m; e += 4) {
+            const float ve = s_be[qi][e];
+            const int vi = s_bi[qi][e];
+            if (base + e < kCapQ) {
+                gbuf_e[(int64_t)q * kCapQ + base + e] = ve;
+                gbuf_i[(int64_t)q * kCapQ + base + e] = vi;
             }
-            if (h[bw] < KK - 1) ++h[bw];
-            else { me[(bw * kQT + tid) * KK + h[bw]] = __builtin_huge_valf(); mi[(bw * kQT + tid) * KK + h[bw]] = 0x7FFFFFFF; }
-            res_est[(int64_t)slot * kk + o] = be;
-            res_id[(int64_t)slot * kk + o] = (be < __builtin_huge_valf()) ? bi : -1;
+            if (s_cnt[qi] <= kCapB && m >= kk) {
+                int rank = 0;
+                for (int f = 0; f < m; ++f) rank += lt(s_be[qi][f], s_bi[qi][f], ve, vi);
+                if (rank == kk - 1) atomicMin(&tau_key[q], f2key(ve));
+            }
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Exact top-kk of each query's candidate buffer: bitonic sort in LDS of the
+// next power of two >= the count (<= kCapQ).  Queries whose buffer overflowed
+// are left to the fallback (flag set).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void select_kernel(const int32_t* __restrict__ gcnt, const float* __restrict__ gbuf_e,
+                                                     const int32_t* __restrict__ gbuf_i, int kk,
+                                                     int32_t* __restrict__ ovf, int64_t* __restrict__ out_ids,
+                                                     float* __restrict__ out_est)
+{
+    __shared__ float se[kCapQ];
+    __shared__ int si[kCapQ];
+    const int64_t q = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int c = gcnt[q];
+    if (c > kCapQ) {
+        if (tid == 0) ovf[q] = 1;
+        return;
+    }
+    if (tid == 0) ovf[q] = 0;
+    int S = 1;
+    while (S < c) S <<= 1;
+    for (int t = tid; t < S; t += 256) {
+        se[t] = (t < c) ? gbuf_e[q * kCapQ + t] : __builtin_huge_valf();
+        si[t] = (t < c) ? gbuf_i[q * kCapQ + t] : 0x7FFFFFFF;
+    }
+    for (int kb = 2; kb <= S; kb <<= 1)
+        for (int jj = kb >> 1; jj > 0; jj >>= 1) {
+            __syncthreads();
+            for (int t = tid; t < S / 2; t += 256) {
+                int i = 2 * t - (t & (jj - 1)), p = i + jj;
+                bool up = (i & kb) == 0;
+                float e0 = se[i], e1 = se[p];
+                int i0 = si[i], i1 = si[p];
+                bool first0 = lt(e0, i0, e1, i1);
+                if (first0 != up) { se[i] = e1; se[p] = e0; si[i] = i1; si[p] = i0; }
+            }
+        }
+    __syncthreads();
+    for (int t = tid; t < kk; t += 256) {
+        const bool valid = t < c;
+        out_ids[q * kk + t] = valid ? (int64_t)si[t] : -1;
+        out_est[q * kk + t] = valid ? se[t] : __builtin_huge_valf();
+    }
+}
+
+__global__ void tau_key_kernel(const float* __restrict__ tau_est, int64_t nq, int kk, unsigned* __restrict__ key)
+{
+    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < nq) key[q] = f2key(tau_est[q * kk + kk - 1]);
+}
+
+// fallback queue: every pair of an overflowed query
+__global__ void redo_build_kernel(const int32_t* __restrict__ probes, int64_t np, int nprobe, int nlist,
+                                  const int32_t* __restrict__ ovf, int32_t* __restrict__ redo_l,
+                                  int32_t* __restrict__ redo_q, int32_t* __restrict__ redo_slot,
+                                  int32_t* __restrict__ redo_n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= np) return;
+    const int64_t q = i / nprobe;
+    if (!ovf[q]) return;
+    int l = probes[i];
+    if (l < 0 || l >= nlist) return;
+    int pos = atomicAdd(redo_n, 1);
+    redo_l[pos] = l; redo_q[pos] = (int32_t)q; redo_slot[pos] = (int32_t)i;
 }
 
 // ---------------------------------------------------------------------------
@@ -342,18 +597,21 @@ __global__ void fill_i32_kernel(int32_t* p, int64_t n, int32_t v) {
     if (i < n) p[i] = v;
 }
 
-__global__ void pair_count_kernel(const int32_t* __restrict__ probes, int64_t np, int nlist,
-                                  int32_t* __restrict__ cnt)
+__global__ void pair_count_kernel(const int32_t* __restrict__ probes, int64_t np, int nprobe, int nlist,
+                                  int rankA, int32_t* __restrict__ cntA, int32_t* __restrict__ cntB)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= np) return;
     int l = probes[i];
-    if (l >= 0 && l < nlist) atomicAdd(&cnt[l], 1);
+    if (l < 0 || l >= nlist) return;
+    const int p = (int)(i % nprobe);
+    if (p < rankA) atomicAdd(&cntA[l], 1);
+    atomicAdd(&cntB[l], 1);
 }
 
 // single workgroup: pair_off (by list id) and item_off (by rank of list_order)
 __global__ __launch_bounds__(1024) void pair_scan_kernel(const int32_t* __restrict__ cnt, int nlist,
-                                                         const int32_t* __restrict__ list_order,
+                                                         const int32_t* __restrict__ list_order, int qpi,
                                                          int32_t* __restrict__ pair_off,
                                                          int32_t* __restrict__ item_off)
 {
@@ -362,7 +620,7 @@ __global__ __launch_bounds__(1024) void pair_scan_kernel(const int32_t* __restri
     const int chunk = (nlist + 1023) / 1024;
     const int beg = tid * chunk, end = min(nlist, beg + chunk);
     int sa = 0, sb = 0;
-    for (int i = beg; i < end; ++i) { sa += cnt[i]; sb += (cnt[list_order[i]] + kQT - 1) / kQT; }
+    for (int i = beg; i < end; ++i) { sa += cnt[i]; sb += (cnt[list_order[i]] + qpi - 1) / qpi; }
     part_a[tid] = sa; part_b[tid] = sb;
     __syncthreads();
     for (int o = 1; o < 1024; o <<= 1) {
@@ -375,33 +633,44 @@ __global__ __launch_bounds__(1024) void pair_scan_kernel(const int32_t* __restri
     int ra = part_a[tid] - sa, rb = part_b[tid] - sb;
     for (int i = beg; i < end; ++i) {
         pair_off[i] = ra; ra += cnt[i];
-        item_off[i] = rb; rb += (cnt[list_order[i]] + kQT - 1) / kQT;
+        item_off[i] = rb; rb += (cnt[list_order[i]] + qpi - 1) / qpi;
     }
     if (tid == 1023) { pair_off[nlist] = part_a[1023]; item_off[nlist] = part_b[1023]; }
 }
 
 __global__ void pair_scatter_kernel(const int32_t* __restrict__ probes, int64_t np, int nprobe, int nlist,
-                                    const int32_t* __restrict__ pair_off, int32_t* __restrict__ fill,
-                                    int32_t* __restrict__ pair_q, int32_t* __restrict__ pair_slot)
+                                    int rankA,
+                                    const int32_t* __restrict__ offA, int32_t* __restrict__ fillA,
+                                    int32_t* __restrict__ qA, int32_t* __restrict__ slotA,
+                                    const int32_t* __restrict__ offB, int32_t* __restrict__ fillB,
+                                    int32_t* __restrict__ qB, int32_t* __restrict__ slotB)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= np) return;
     int l = probes[i];
     if (l < 0 || l >= nlist) return;
-    int pos = pair_off[l] + atomicAdd(&fill[l], 1);
-    pair_q[pos] = (int32_t)(i / nprobe);
-    pair_slot[pos] = (int32_t)i;
+    const int64_t q = i / nprobe;
+    const int p = (int)(i - q * nprobe);
+    if (p < rankA) {
+        int pos = offA[l] + atomicAdd(&fillA[l], 1);
+        qA[pos] = (int32_t)q; slotA[pos] = (int32_t)i;
+    }
+    int pos = offB[l] + atomicAdd(&fillB[l], 1);
+    qB[pos] = (int32_t)q; slotB[pos] = (int32_t)i;
 }
 
-// one wave per query: the kk best of its probed lists' top-kk lists
+// one wave per query: the kk best of its probed lists' top-kk lists (pairs
+// with probe rank >= rlim are left out; with qmask only flagged queries)
 __global__ __launch_bounds__(256) void merge_kernel(const int32_t* __restrict__ probes, int64_t nq, int nprobe,
-                                                    int nlist, int kk, const float* __restrict__ res_est,
+                                                    int nlist, int kk, int rlim, const int32_t* __restrict__ qmask,
+                                                    const float* __restrict__ res_est,
                                                     const int32_t* __restrict__ res_id,
                                                     int64_t* __restrict__ out_ids, float* __restrict__ out_est)
 {
     const int lane = threadIdx.x & 63;
     const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (q >= nq) return;
+    if (qmask && !qmask[q]) return;
     constexpr int U = 16;                 // nprobe <= 1024
     int hp[U];
     float he[U];
@@ -412,14 +681,13 @@ __global__ __launch_bounds__(256) void merge_kernel(const int32_t* __restrict__ 
         hp[u] = 0;
         he[u] = __builtin_huge_valf();
         hi[u] = 0x7FFFFFFF;
-        if (p < nprobe) {
+        if (p < nprobe && p < rlim) {
             int l = probes[q * nprobe + p];
             if (l >= 0 && l < nlist) {
                 const int64_t s = q * nprobe + p;
-                he[u] = res_est[s * kk];
                 int id = res_id[s * kk];
+                he[u] = id < 0 ? __builtin_huge_valf() : res_est[s * kk];
                 hi[u] = id < 0 ? 0x7FFFFFFF : id;
-                if (id < 0) he[u] = __builtin_huge_valf();
             }
         }
     }
@@ -438,7 +706,7 @@ __global__ __launch_bounds__(256) void merge_kernel(const int32_t* __restrict__ 
         }
         if (lane == 0) {
             const bool valid = ge < __builtin_huge_valf();
-            out_ids[q * kk + o] = valid ? (int64_t)gi : -1;
+            if (out_ids) out_ids[q * kk + o] = valid ? (int64_t)gi : -1;
             out_est[q * kk + o] = valid ? ge : __builtin_huge_valf();
         }
         if (lane == gl && bu >= 0) {
@@ -461,34 +729,94 @@ __global__ __launch_bounds__(256) void merge_kernel(const int32_t* __restrict__ 
     }
 }
 
+struct ScanArgs {
+    const float* qrot;
+    const int32_t *pair_off, *pair_q, *pair_slot, *item_off;
+    const int32_t *redo_l, *redo_n;
+    int64_t grid;
+    int vmax;
+    int kk;
+    float* res_est;
+    int32_t* res_id;
+};
+
 template <int BITS, int KK>
-hipError_t launch_scan_t(const Index* ix, const float* qrot, const int32_t* pair_off, const int32_t* pair_q,
-                         const int32_t* pair_slot, const int32_t* item_off, int64_t max_items, int kk,
-                         float* res_est, int32_t* res_id, hipStream_t st)
+hipError_t launchA_t(const Index* ix, const ScanArgs& a, hipStream_t st)
 {
-    size_t sm = (size_t)ix->dp * 32;
+    size_t sm = (size_t)ix->dp * kQT;
     size_t mb = (size_t)4 * kQT * KK * 8;
     if (mb > sm) sm = mb;
     if (sm > 48 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void*)scan_kernel<BITS, KK>,
+        hipError_t e = hipFuncSetAttribute((const void*)scanA_kernel<BITS, KK>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((scan_kernel<BITS, KK>), dim3((unsigned)max_items), dim3(kThreads), sm, st,
+    hipLaunchKernelGGL((scanA_kernel<BITS, KK>), dim3((unsigned)a.grid), dim3(kThreads), sm, st,
                        ix->codes, ix->tile_off, ix->list_off, ix->fac, ix->ids, ix->cent_rot, ix->dp,
-                       qrot, pair_off, pair_q, pair_slot, item_off, ix->list_order, (int)ix->nlist,
-                       kk, res_est, res_id);
+                       a.qrot, a.pair_off, a.pair_q, a.pair_slot, a.item_off, ix->list_order, (int)ix->nlist,
+                       a.redo_l, a.redo_n, a.vmax, a.kk, a.res_est, a.res_id);
     return hipGetLastError();
 }
 
 template <int BITS>
-hipError_t launch_scan_b(const Index* ix, const float* qrot, const int32_t* pair_off, const int32_t* pair_q,
-                         const int32_t* pair_slot, const int32_t* item_off, int64_t max_items, int kk,
-                         float* res_est, int32_t* res_id, hipStream_t st)
+hipError_t launchA_b(const Index* ix, const ScanArgs& a, hipStream_t st)
 {
-    if (kk <= 16) return launch_scan_t<BITS, 16>(ix, qrot, pair_off, pair_q, pair_slot, item_off, max_items, kk, res_est, res_id, st);
-    if (kk <= 32) return launch_scan_t<BITS, 32>(ix, qrot, pair_off, pair_q, pair_slot, item_off, max_items, kk, res_est, res_id, st);
-    return launch_scan_t<BITS, 64>(ix, qrot, pair_off, pair_q, pair_slot, item_off, max_items, kk, res_est, res_id, st);
+    // kk <= 32 (checked at the ABI); a 64-entry register list spills to scratch
+    if (a.kk <= 16) return launchA_t<BITS, 16>(ix, a, st);
+    return launchA_t<BITS, 32>(ix, a, st);
+}
+
+struct BArgs { unsigned* tau_key; int32_t* gcnt; float* gbuf_e; int32_t* gbuf_i; };
+
+template <int BITS, int NQT>
+hipError_t launchB_t(const Index* ix, const ScanArgs& a, const BArgs& b, hipStream_t st)
+{
+    const size_t sm = (size_t)ix->dp * kQT * NQT;
+    if (sm > 48 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void*)scanB_kernel<BITS, NQT>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((scanB_kernel<BITS, NQT>), dim3((unsigned)a.grid), dim3(kThreads), sm, st,
+                       ix->codes, ix->tile_off, ix->list_off, ix->fac, ix->ids, ix->cent_rot, ix->dp,
+                       a.qrot, a.pair_off, a.pair_q, a.pair_slot, a.item_off, ix->list_order, (int)ix->nlist,
+                       a.kk, b.tau_key, b.gcnt, b.gbuf_e, b.gbuf_i);
+    return hipGetLastError();
+}
+
+template <int BITS>
+hipError_t launchB_b(const Index* ix, const ScanArgs& a, const BArgs& b, hipStream_t st)
+{
+    if (ix->dp <= 768) return launchB_t<BITS, 2>(ix, a, b, st);
+    return launchB_t<BITS, 1>(ix, a, b, st);
+}
+
+hipError_t launchA(const Index* ix, const ScanArgs& a, hipStream_t st)
+{
+    switch (ix->bits) {
+        case 1: return launchA_b<1>(ix, a, st);
+        case 2: return launchA_b<2>(ix, a, st);
+        case 3: return launchA_b<3>(ix, a, st);
+        case 4: return launchA_b<4>(ix, a, st);
+        case 5: return launchA_b<5>(ix, a, st);
+        case 6: return launchA_b<6>(ix, a, st);
+        case 7: return launchA_b<7>(ix, a, st);
+        default: return launchA_b<8>(ix, a, st);
+    }
+}
+
+hipError_t launchB(const Index* ix, const ScanArgs& a, const BArgs& b, hipStream_t st)
+{
+    switch (ix->bits) {
+        case 1: return launchB_b<1>(ix, a, b, st);
+        case 2: return launchB_b<2>(ix, a, b, st);
+        case 3: return launchB_b<3>(ix, a, b, st);
+        case 4: return launchB_b<4>(ix, a, b, st);
+        case 5: return launchB_b<5>(ix, a, b, st);
+        case 6: return launchB_b<6>(ix, a, b, st);
+        case 7: return launchB_b<7>(ix, a, b, st);
+        default: return launchB_b<8>(ix, a, b, st);
+    }
 }
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -499,14 +827,18 @@ size_t scan_workspace_bytes(int64_t nq, int nprobe, int64_t nlist, int kk)
 {
     const int64_t P = nq * nprobe;
     size_t b = 0;
-    b += align256(sizeof(int32_t) * nlist);            // cnt
-    b += align256(sizeof(int32_t) * nlist);            // fill
-    b += align256(sizeof(int32_t) * (nlist + 1));      // pair_off
-    b += align256(sizeof(int32_t) * (nlist + 1));      // item_off
-    b += align256(sizeof(int32_t) * P);                // pair_q
-    b += align256(sizeof(int32_t) * P);                // pair_slot
-    b += align256(sizeof(float) * P * kk);             // res_est
-    b += align256(sizeof(int32_t) * P * kk);           // res_id
+    b += 4 * align256(sizeof(int32_t) * nlist);            // cntA, cntB, fillA, fillB
+    b += 4 * align256(sizeof(int32_t) * (nlist + 1));      // pair/item offsets of A and B
+    b += 4 * align256(sizeof(int32_t) * P);                // pairs of A and B
+    b += 3 * align256(sizeof(int32_t) * P);                // fallback queue
+    b += align256(sizeof(int32_t));                        // fallback count
+    b += align256(sizeof(float) * nq * kk);                // pass-A top-kk per query
+    b += align256(sizeof(unsigned) * nq);                  // bound per query
+    b += 2 * align256(sizeof(int32_t) * nq);               // candidate counts, overflow flags
+    b += align256(sizeof(float) * nq * kCapQ);             // candidate buffers
+    b += align256(sizeof(int32_t) * nq * kCapQ);
+    b += align256(sizeof(float) * P * kk);                 // per-pair top-kk (pass A, fallback)
+    b += align256(sizeof(int32_t) * P * kk);
     return b;
 }
 
@@ -519,53 +851,99 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, in
         return fail(ERQ_ENOMEM, "erq_scan: workspace too small");
     char* w = (char*)ws;
     auto take = [&](size_t bytes) { char* p = w; w += align256(bytes); return p; };
-    int32_t* cnt = (int32_t*)take(sizeof(int32_t) * nlist);
-    int32_t* fill = (int32_t*)take(sizeof(int32_t) * nlist);
-    int32_t* pair_off = (int32_t*)take(sizeof(int32_t) * (nlist + 1));
-    int32_t* item_off = (int32_t*)take(sizeof(int32_t) * (nlist + 1));
-    int32_t* pair_q = (int32_t*)take(sizeof(int32_t) * P);
-    int32_t* pair_slot = (int32_t*)take(sizeof(int32_t) * P);
+    int32_t* cntA = (int32_t*)take(sizeof(int32_t) * nlist);
+    int32_t* cntB = (int32_t*)take(sizeof(int32_t) * nlist);
+    int32_t* fillA = (int32_t*)take(sizeof(int32_t) * nlist);
+    int32_t* fillB = (int32_t*)take(sizeof(int32_t) * nlist);
+    int32_t* offA = (int32_t*)take(sizeof(int32_t) * (nlist + 1));
+    int32_t* itemA = (int32_t*)take(sizeof(int32_t) * (nlist + 1));
+    int32_t* offB = (int32_t*)take(sizeof(int32_t) * (nlist + 1));
+    int32_t* itemB = (int32_t*)take(sizeof(int32_t) * (nlist + 1));
+    int32_t* qA = (int32_t*)take(sizeof(int32_t) * P);
+    int32_t* sA = (int32_t*)take(sizeof(int32_t) * P);
+    int32_t* qB = (int32_t*)take(sizeof(int32_t) * P);
+    int32_t* sB = (int32_t*)take(sizeof(int32_t) * P);
+    int32_t* rl = (int32_t*)take(sizeof(int32_t) * P);
+    int32_t* rq = (int32_t*)take(sizeof(int32_t) * P);
+    int32_t* rs = (int32_t*)take(sizeof(int32_t) * P);
+    int32_t* rn = (int32_t*)take(sizeof(int32_t));
+    float* tau = (float*)take(sizeof(float) * nq * kk);
+    unsigned* tkey = (unsigned*)take(sizeof(unsigned) * nq);
+    int32_t* gcnt = (int32_t*)take(sizeof(int32_t) * nq);
+    int32_t* ovf = (int32_t*)take(sizeof(int32_t) * nq);
+    float* gbe = (float*)take(sizeof(float) * nq * kCapQ);
+    int32_t* gbi = (int32_t*)take(sizeof(int32_t) * nq * kCapQ);
     float* res_est = (float*)take(sizeof(float) * P * kk);
     int32_t* res_id = (int32_t*)take(sizeof(int32_t) * P * kk);
 
     const int th = 256;
-    hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)((nlist + th - 1) / th)), dim3(th), 0, st, fill, nlist, 0);
-    hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)((nlist + th - 1) / th)), dim3(th), 0, st, cnt, nlist, 0);
+    auto zero = [&](int32_t* p, int64_t n) {
+        if (n > 0) hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)((n + th - 1) / th)), dim3(th), 0, st, p, n, 0);
+    };
+    const int rankA = std::min(nprobe, kRankA);
+    zero(cntA, nlist); zero(cntB, nlist); zero(fillA, nlist); zero(fillB, nlist); zero(rn, 1); zero(gcnt, nq);
     if (P > 0) {
         hipLaunchKernelGGL(pair_count_kernel, dim3((unsigned)((P + th - 1) / th)), dim3(th), 0, st,
-                           probes, P, (int)nlist, cnt);
+                           probes, P, nprobe, (int)nlist, rankA, cntA, cntB);
     }
-    hipLaunchKernelGGL(pair_scan_kernel, dim3(1), dim3(1024), 0, st, cnt, (int)nlist, ix->list_order,
-                       pair_off, item_off);
+    const int qpiB = (ix->dp <= 768) ? 2 * kQT : kQT;
+    hipLaunchKernelGGL(pair_scan_kernel, dim3(1), dim3(1024), 0, st, cntA, (int)nlist, ix->list_order, kQT, offA, itemA);
+    hipLaunchKernelGGL(pair_scan_kernel, dim3(1), dim3(1024), 0, st, cntB, (int)nlist, ix->list_order, qpiB, offB, itemB);
     if (P > 0) {
         hipLaunchKernelGGL(pair_scatter_kernel, dim3((unsigned)((P + th - 1) / th)), dim3(th), 0, st,
-                           probes, P, nprobe, (int)nlist, pair_off, fill, pair_q, pair_slot);
+                           probes, P, nprobe, (int)nlist, rankA, offA, fillA, qA, sA, offB, fillB, qB, sB);
     }
     ERQ_HIP(hipGetLastError());
-    const int64_t max_items = (P + kQT - 1) / kQT + nlist;
-    hipError_t e = hipSuccess;
     const int pr = prof_begin(PK_SCAN, st);
+    hipError_t e = hipSuccess;
     if (P > 0) {
-        switch (ix->bits) {
-            case 1: e = launch_scan_b<1>(ix, qrot, pair_off, pair_q, pair_slot, item_off, max_items, kk, res_est, res_id, st); break;
-            case 2: e = launch_scan_b<2>(ix, qrot, pair_off, pair_q, pair_slot, item_off, max_items, kk, res_est, res_id, st); break;
-            case 3: e = launch_scan_b<3>(ix, qrot, pair_off, pair_q, pair_slot, item_off, max_items, kk, res_est, res_id, st); break;
-            case 4: e = launch_scan_b<4>(ix, qrot, pair_off, pair_q, pair_slot, item_off, max_items, kk, res_est, res_id, st); break;
-            case 5: e = launch_scan_b<5>(ix, qrot, pair_off, pair_q, pair_slot, item_off, max_items, kk, res_est, res_id, st); break;
-            case 6: e = launch_scan_b<6>(ix, qrot, pair_off, pair_q, pair_slot, item_off, max_items, kk, res_est, res_id, st); break;
-            case 7: e = launch_scan_b<7>(ix, qrot, pair_off, pair_q, pair_slot, item_off, max_items, kk, res_est, res_id, st); break;
-            default: e = launch_scan_b<8>(ix, qrot, pair_off, pair_q, pair_slot, item_off, max_items, kk, res_est, res_id, st); break;
+        // pass A: the bound
+        const int64_t PA = nq * (int64_t)rankA;
+        ScanArgs a{qrot, offA, qA, sA, itemA, nullptr, nullptr, (PA + kQT - 1) / kQT + nlist, kVecA, kk, res_est, res_id};
+        int pp = prof_begin(PK_SCAN_A, st);
+        e = launchA(ix, a, st);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(merge_kernel, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, st, probes, nq, nprobe,
+                               (int)nlist, kk, rankA, (const int32_t*)nullptr, res_est, res_id, (int64_t*)nullptr, tau);
+            hipLaunchKernelGGL(tau_key_kernel, dim3((unsigned)((nq + th - 1) / th)), dim3(th), 0, st, tau, nq, kk, tkey);
+            e = hipGetLastError();
         }
+        prof_end(pp, st);
+        // pass B: the scan
+        if (e == hipSuccess) {
+            ScanArgs b{qrot, offB, qB, sB, itemB, nullptr, nullptr, (P + qpiB - 1) / qpiB + nlist, 0, kk, nullptr, nullptr};
+            BArgs bb{tkey, gcnt, gbe, gbi};
+            pp = prof_begin(PK_SCAN_B, st);
+            e = launchB(ix, b, bb, st);
+            prof_end(pp, st);
+        }
+        // select, then the exact fallback for overflowed queries
+        if (e == hipSuccess) {
+            pp = prof_begin(PK_SCAN_C, st);
+            hipLaunchKernelGGL(select_kernel, dim3((unsigned)nq), dim3(256), 0, st, gcnt, gbe, gbi, kk, ovf,
+                               out_ids, out_est);
+            hipLaunchKernelGGL(redo_build_kernel, dim3((unsigned)((P + th - 1) / th)), dim3(th), 0, st, probes, P,
+                               nprobe, (int)nlist, ovf, rl, rq, rs, rn);
+            e = hipGetLastError();
+            if (e == hipSuccess) {
+                ScanArgs c{qrot, nullptr, rq, rs, nullptr, rl, rn, 1024, 0x7FFFFFFF, kk, res_est, res_id};
+                e = launchA(ix, c, st);
+            }
+            if (e == hipSuccess) {
+                hipLaunchKernelGGL(merge_kernel, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, st, probes, nq,
+                                   nprobe, (int)nlist, kk, nprobe, ovf, res_est, res_id, out_ids, out_est);
+                e = hipGetLastError();
+            }
+            prof_end(pp, st);
+        }
+    } else if (nq > 0) {
+        hipLaunchKernelGGL(select_kernel, dim3((unsigned)nq), dim3(256), 0, st, gcnt, gbe, gbi, kk, ovf,
+                           out_ids, out_est);
+        e = hipGetLastError();
     }
     prof_end(pr, st);
     if (e != hipSuccess) return fail(ERQ_EDEVICE, std::string("scan launch: ") + hipGetErrorString(e));
-    const int pm = prof_begin(PK_MERGE, st);
-    if (nq > 0) {
-        hipLaunchKernelGGL(merge_kernel, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, st, probes, nq, nprobe,
-                           (int)nlist, kk, res_est, res_id, out_ids, out_est);
-    }
-    prof_end(pm, st);
-    ERQ_HIP(hipGetLastError());
+    if (P > 0) prof_note_redo(rn, st);
     return ERQ_OK;
 }
 

@@ -229,8 +229,9 @@ class Index:
         return ids, d
 
 
-def profile_enable(on: bool = True):
-    """Bracket the library's kernels with HIP events on their launch stream."""
+def profile_enable(on=True):
+    """Bracket the library's kernels with HIP events on their launch stream
+    (2: also count the pairs re-scanned in pass C, synchronising per scan)."""
     _check(load().erq_profile_enable(int(on)))
 
 

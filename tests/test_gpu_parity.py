@@ -208,10 +208,27 @@ def test_scan_parity_bits(B):
     assert (gi == oi).mean() > 0.99
 
 
-@pytest.mark.parametrize("kk", [1, 10, 16, 17, 32, 40, 64])
+@pytest.mark.parametrize("kk", [1, 10, 16, 17, 32])
 def test_scan_parity_kk(kk):
     say("scan kk", kk)
     _scan_case(n=8000, nl=16, dp=192, B=4, nq=50, nprobe=5, kk=kk, seed=100 + kk)
+
+
+@pytest.mark.parametrize("kk", [33, 64])
+def test_scan_rejects_kk_above_32(kk):
+    """kk > 32 is switched off: a run of the 64-entry register-list kernel
+    (the only one that spills to scratch) ended in a GPU memory fault whose
+    cause was not found; the call must fail before any launch."""
+    say("scan kk rejected", kk)
+    dp, nl, n = 128, 4, 200
+    off, ids, codes, fa, fr, crot = synth.random_index(n, nl, dp, 4, seed=1)
+    P = synth.haar_orthogonal(dp, seed=2).astype(np.float32)
+    ix = erq.Index(dp, 4, nl, dev(P))
+    ix.import_(dev(off), dev(ids), dev(codes), dev(fa), dev(fr), dev(np.zeros((nl, dp), np.float32)), dev(crot))
+    with pytest.raises(erq.ErqError) as e:
+        ix.scan(dev(synth.random_rotated(3, dp, seed=3)), dev(synth.random_probes(3, nl, 2, seed=4)), kk)
+    assert e.value.code == erq.ERQ_EUNSUPPORTED
+    ix.close()
 
 
 def test_scan_parity_dp768_many_tiles():
