@@ -138,9 +138,28 @@ __device__ inline void decode_item(int item, const int32_t* item_off, const int3
     *t = item - item_off[lo];
 }
 
-// Prologue shared by both passes: int8 residual queries of one item into LDS,
-// laid out as the B operand: query qi = qt*32 + j, 16-dim chunk c = 2 ks + h at
-// byte ((ks*NQT + qt)*64 + h*32 + j)*16.
+// Prologue shared by the scan kernels: int8 residual queries of one item into
+// LDS, laid out as the B operand: query qi = qt*32 + j, 16-dim chunk
+// c = 2 ks + h at byte ((ks*NQT + qt)*64 + h*32 + j)*16.  For dp <= 1024 every
+// lane owns at most one chunk, kept in registers (one read of q' and c');
+// larger dp takes two passes (max and norm, then quantise).
+__device__ inline void quant_chunk(const float* sd, float inv, int* ssum, uint4* out) {
+    uint32_t w4[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        uint32_t wd = 0;
+#pragma unroll
+        for (int bb = 0; bb < 4; ++bb) {
+            int v = (int)rintf(sd[4 * d + bb] * inv);
+            v = max(-127, min(127, v));
+            *ssum += v;
+            wd |= ((uint32_t)(v & 0xFF)) << (8 * bb);
+        }
+        w4[d] = wd;
+    }
+    *out = make_uint4(w4[0], w4[1], w4[2], w4[3]);
+}
+
 template <int NQT>
 __device__ inline void load_queries(int8_t* qs, float* s_s2, float* s_hd, int* s_ss, int* s_slot, int* s_q,
                                     const float* __restrict__ qrot, const float* __restrict__ cv, int dp,
@@ -159,43 +178,61 @@ __device__ inline void load_queries(int8_t* qs, float* s_s2, float* s_hd, int* s
         }
         const int q = pq[qi];
         const float* qv = qrot + (int64_t)q * dp;
-        // first pass: max |s'| and ||s'||^2; second pass: quantise (re-reads hit the caches)
         float amax = 0.0f, s2 = 0.0f;
-        for (int c = lane; c < nch; c += 64) {
-#pragma unroll
-            for (int e = 0; e < 16; e += 4) {
-                float4 a = *(const float4*)(qv + c * 16 + e);
-                float4 b = *(const float4*)(cv + c * 16 + e);
-                float d0 = a.x - b.x, d1 = a.y - b.y, d2 = a.z - b.z, d3 = a.w - b.w;
-                amax = fmaxf(amax, fmaxf(fmaxf(fabsf(d0), fabsf(d1)), fmaxf(fabsf(d2), fabsf(d3))));
-                s2 += d0 * d0; s2 += d1 * d1; s2 += d2 * d2; s2 += d3 * d3;
-            }
-        }
-        for (int o = 32; o > 0; o >>= 1) {
-            amax = fmaxf(amax, __shfl_xor(amax, o));
-            s2 += __shfl_xor(s2, o);
-        }
-        const float inv = (amax > 0.0f) ? __fdiv_rn(127.0f, amax) : 0.0f;
         int ssum = 0;
-        for (int c = lane; c < nch; c += 64) {
-            uint32_t w4[4];
+        if (nch <= 64) {
+            float sd[16];
+            const bool own = lane < nch;
+            if (own) {
 #pragma unroll
-            for (int d = 0; d < 4; ++d) {
-                float4 a = *(const float4*)(qv + c * 16 + 4 * d);
-                float4 b = *(const float4*)(cv + c * 16 + 4 * d);
-                const float sd[4] = {a.x - b.x, a.y - b.y, a.z - b.z, a.w - b.w};
-                uint32_t wd = 0;
-#pragma unroll
-                for (int bb = 0; bb < 4; ++bb) {
-                    int v = (int)rintf(sd[bb] * inv);
-                    v = max(-127, min(127, v));
-                    ssum += v;
-                    wd |= ((uint32_t)(v & 0xFF)) << (8 * bb);
+                for (int e = 0; e < 16; e += 4) {
+                    float4 a = *(const float4*)(qv + lane * 16 + e);
+                    float4 b = *(const float4*)(cv + lane * 16 + e);
+                    sd[e + 0] = a.x - b.x; sd[e + 1] = a.y - b.y; sd[e + 2] = a.z - b.z; sd[e + 3] = a.w - b.w;
                 }
-                w4[d] = wd;
+#pragma unroll
+                for (int e = 0; e < 16; ++e) { amax = fmaxf(amax, fabsf(sd[e])); s2 += sd[e] * sd[e]; }
             }
-            const int ks = c >> 1, h = c & 1;
-            *(uint4*)(qs + ((ks * NQT + qt) * 64 + h * 32 + j) * 16) = make_uint4(w4[0], w4[1], w4[2], w4[3]);
+            for (int o = 32; o > 0; o >>= 1) {
+                amax = fmaxf(amax, __shfl_xor(amax, o));
+                s2 += __shfl_xor(s2, o);
+            }
+            const float inv = (amax > 0.0f) ? __fdiv_rn(127.0f, amax) : 0.0f;
+            if (own) {
+                uint4 w;
+                quant_chunk(sd, inv, &ssum, &w);
+                const int ks = lane >> 1, h = lane & 1;
+                *(uint4*)(qs + ((ks * NQT + qt) * 64 + h * 32 + j) * 16) = w;
+            }
+        } else {
+            for (int c = lane; c < nch; c += 64) {
+#pragma unroll
+                for (int e = 0; e < 16; e += 4) {
+                    float4 a = *(const float4*)(qv + c * 16 + e);
+                    float4 b = *(const float4*)(cv + c * 16 + e);
+                    float d0 = a.x - b.x, d1 = a.y - b.y, d2 = a.z - b.z, d3 = a.w - b.w;
+                    amax = fmaxf(amax, fmaxf(fmaxf(fabsf(d0), fabsf(d1)), fmaxf(fabsf(d2), fabsf(d3))));
+                    s2 += d0 * d0; s2 += d1 * d1; s2 += d2 * d2; s2 += d3 * d3;
+                }
+            }
+            for (int o = 32; o > 0; o >>= 1) {
+                amax = fmaxf(amax, __shfl_xor(amax, o));
+                s2 += __shfl_xor(s2, o);
+            }
+            const float inv = (amax > 0.0f) ? __fdiv_rn(127.0f, amax) : 0.0f;
+            for (int c = lane; c < nch; c += 64) {
+                float sd[16];
+#pragma unroll
+                for (int e = 0; e < 16; e += 4) {
+                    float4 a = *(const float4*)(qv + c * 16 + e);
+                    float4 b = *(const float4*)(cv + c * 16 + e);
+                    sd[e + 0] = a.x - b.x; sd[e + 1] = a.y - b.y; sd[e + 2] = a.z - b.z; sd[e + 3] = a.w - b.w;
+                }
+                uint4 w;
+                quant_chunk(sd, inv, &ssum, &w);
+                const int ks = c >> 1, h = c & 1;
+                *(uint4*)(qs + ((ks * NQT + qt) * 64 + h * 32 + j) * 16) = w;
+            }
         }
         for (int o = 32; o > 0; o >>= 1) ssum += __shfl_xor(ssum, o);
         if (lane == 0) {
@@ -218,8 +255,7 @@ __device__ inline float estimate(float2 f, int acc, float s2, float hd, int ss) 
 // ---------------------------------------------------------------------------
 // Pass A / fallback: exact per-pair top-kk, 32 queries per item, per-lane
 // lists; only the first vmax members of each list are scanned.  Items come
-// from a pair table grouped by list (redo == nullptr) or one item per queued
-// pair.  Grid-stride loop over items.
+// from a pair table grouped by list; grid-stride loop over items.
 // ---------------------------------------------------------------------------
 template <int BITS, int KK>
 __global__ __launch_bounds__(kThreads, 2) void scanA_kernel(
@@ -228,8 +264,7 @@ __global__ __launch_bounds__(kThreads, 2) void scanA_kernel(
     const int64_t* __restrict__ ids, const float* __restrict__ cent_rot, int dp,
     const float* __restrict__ qrot, const int32_t* __restrict__ pair_off,
     const int32_t* __restrict__ pair_q, const int32_t* __restrict__ pair_slot,
-    const int32_t* __restrict__ item_off, const int32_t* __restrict__ list_order, int nlist,
-    const int32_t* __restrict__ redo_l, const int32_t* __restrict__ redo_n, int vmax,
+    const int32_t* __restrict__ item_off, const int32_t* __restrict__ list_order, int nlist, int vmax,
     int kk, float* __restrict__ res_est, int32_t* __restrict__ res_id)
 {
     extern __shared__ __align__(16) char smem[];
@@ -239,7 +274,7 @@ __global__ __launch_bounds__(kThreads, 2) void scanA_kernel(
     __shared__ int s_item[3];
 
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int n_items = redo_l ? *redo_n : item_off[nlist];
+    const int n_items = item_off[nlist];
     const int nkb = dp / 64;
     int8_t* qs = (int8_t*)smem;
     const v4i* qb = (const v4i*)qs;
@@ -248,14 +283,10 @@ __global__ __launch_bounds__(kThreads, 2) void scanA_kernel(
     for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
         __syncthreads();                               // LDS of the previous item is free
         if (tid == 0) {
-            if (redo_l) {
-                s_item[0] = redo_l[item]; s_item[1] = item; s_item[2] = 1;
-            } else {
-                int l, t;
-                decode_item(item, item_off, list_order, nlist, &l, &t);
-                const int p0 = pair_off[l] + t * kQT;
-                s_item[0] = l; s_item[1] = p0; s_item[2] = min(kQT, pair_off[l + 1] - p0);
-            }
+            int l, t;
+            decode_item(item, item_off, list_order, nlist, &l, &t);
+            const int p0 = pair_off[l] + t * kQT;
+            s_item[0] = l; s_item[1] = p0; s_item[2] = min(kQT, pair_off[l + 1] - p0);
         }
         if (tid < kQT) s_thr[tid] = 0xFFFFFFFFu;
         __syncthreads();
@@ -412,7 +443,6 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
     load_queries<NQT>(qs, s_s2, s_hd, s_ss, s_slot, s_q, qrot, cent_rot + (int64_t)l * dp, dp,
                       pair_q + p0, pair_slot + p0, mq, wid, lane);
     __syncthreads();
-    // columns without a query take -inf so that nothing passes
     if (tid < QPI) s_tau[tid] = (tid < mq) ? tau_key[s_q[tid]] : 0u;
     __syncthreads();
 
@@ -425,13 +455,19 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
     const int ngroup = (ntile + 1) >> 1;
     const int64_t tbase = tile_off[l];
     const int j = lane & 31;
+    // Columns without a query (qi >= mq) have no LDS terms: they take zeros
+    // and are excluded from the pass test by qok, not by their estimate.
     float qs2[NQT], qhd[NQT], qtau[NQT];
     int qss[NQT];
+    bool qok[NQT];
 #pragma unroll
     for (int qt = 0; qt < NQT; ++qt) {
         const int qi = qt * kQT + j;
-        qs2[qt] = s_s2[qi]; qhd[qt] = s_hd[qi]; qss[qt] = s_ss[qi];
-        qtau[qt] = (qi < mq) ? key2f(s_tau[qi]) : -__builtin_huge_valf();
+        qok[qt] = qi < mq;
+        qs2[qt] = qok[qt] ? s_s2[qi] : 0.0f;
+        qhd[qt] = qok[qt] ? s_hd[qi] : 0.0f;
+        qss[qt] = qok[qt] ? s_ss[qi] : 0;
+        qtau[qt] = qok[qt] ? key2f(s_tau[qi]) : 0.0f;
     }
 
     for (int g = wid; g < ngroup; g += 4) {
@@ -472,7 +508,7 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
 #pragma unroll
                 for (int qt = 0; qt < NQT; ++qt) {
                     const float est = estimate<BITS>(f, acc[a][qt][r], qs2[qt], qhd[qt], qss[qt]);
-                    const bool pass = ok && est <= qtau[qt];
+                    const bool pass = ok && qok[qt] && est <= qtau[qt];
                     if (__any(pass)) {
                         if (pass) {
                             const int qi = qt * kQT + j;
@@ -495,12 +531,11 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
         }
     }
     __syncthreads();
-    // flush the LDS stage; the item's kk-th best lowers the query's bound
+    // flush the LDS stage to the query's candidate buffer
     const int qi = tid >> 2, sub = tid & 3;
-    if (qi < mq) {
-        const int q = s_q[qi];
+    if (qi < mq && sub == 0) {
         const int m = min(s_cnt[qi], kCapB);
-        if (sub == 0) s_base[qi] = (m > 0) ? atomicAdd(&gcnt[q], m) : 0;
+        s_base[qi] = (m > 0) ? atomicAdd(&gcnt[s_q[qi]], m) : 0;
     }
     __syncthreads();
     if (qi < mq) {
@@ -508,47 +543,94 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
         const int m = min(s_cnt[qi], kCapB);
         const int base = s_base[qi];
         for (int e = sub; e < m; e += 4) {
-            const float ve = s_be[qi][e];
-            const int vi = s_bi[qi][e];
             if (base + e < kCapQ) {
-                gbuf_e[(int64_t)q * kCapQ + base + e] = ve;
-                gbuf_i[(int64_t)q * kCapQ + base + e] = vi;
-            }
-            if (s_cnt[qi] <= kCapB && m >= kk) {
-                int rank = 0;
-                for (int f = 0; f < m; ++f) rank += lt(s_be[qi][f], s_bi[qi][f], ve, vi);
-                if (rank == kk - 1) atomicMin(&tau_key[q], f2key(ve));
+                gbuf_e[(int64_t)q * kCapQ + base + e] = s_be[qi][e];
+                gbuf_i[(int64_t)q * kCapQ + base + e] = s_bi[qi][e];
             }
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// Exact top-kk of each query's candidate buffer: bitonic sort in LDS of the
-// next power of two >= the count (<= kCapQ).  Queries whose buffer overflowed
-// are left to the fallback (flag set).
+// Per query, over its candidate buffer (count c): radix select of the key of
+// the kk-th smallest estimate (4 passes of 8 bits).  mode 0 lowers the
+// query's bound to it (the kk-th best candidate seen so far); mode 1 writes
+// the exact top-kk ascending by (est, id): the candidates with key <= that of
+// the kk-th are compacted and sorted.  A buffer that overflowed raises the
+// query's flag and is left to the fallback.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void select_kernel(const int32_t* __restrict__ gcnt, const float* __restrict__ gbuf_e,
-                                                     const int32_t* __restrict__ gbuf_i, int kk,
-                                                     int32_t* __restrict__ ovf, int64_t* __restrict__ out_ids,
-                                                     float* __restrict__ out_est)
+__global__ __launch_bounds__(256) void buf_select_kernel(const int32_t* __restrict__ gcnt,
+                                                         const float* __restrict__ gbuf_e,
+                                                         const int32_t* __restrict__ gbuf_i, int kk, int mode,
+                                                         unsigned* __restrict__ tau_key, int32_t* __restrict__ ovf,
+                                                         int64_t* __restrict__ out_ids, float* __restrict__ out_est)
 {
+    __shared__ unsigned hist[256];
+    __shared__ unsigned s_prefix, s_kr;
+    __shared__ int s_m;
     __shared__ float se[kCapQ];
     __shared__ int si[kCapQ];
     const int64_t q = blockIdx.x;
     const int tid = threadIdx.x;
-    const int c = gcnt[q];
-    if (c > kCapQ) {
-        if (tid == 0) ovf[q] = 1;
+    const int craw = gcnt[q];
+    if (craw > kCapQ) {
+        if (mode == 1 && tid == 0) ovf[q] = 1;
         return;
     }
-    if (tid == 0) ovf[q] = 0;
-    int S = 1;
-    while (S < c) S <<= 1;
-    for (int t = tid; t < S; t += 256) {
-        se[t] = (t < c) ? gbuf_e[q * kCapQ + t] : __builtin_huge_valf();
-        si[t] = (t < c) ? gbuf_i[q * kCapQ + t] : 0x7FFFFFFF;
+    if (mode == 1 && tid == 0) ovf[q] = 0;
+    const int c = craw;
+    const float* be = gbuf_e + q * kCapQ;
+    const int* bi = gbuf_i + q * kCapQ;
+    if (mode == 0 && c < kk) return;                 // fewer than kk candidates: no bound yet
+    unsigned kth = 0xFFFFFFFFu;
+    if (c >= kk) {
+        unsigned prefix = 0, mask = 0, kr = (unsigned)kk;
+        for (int pass = 0; pass < 4; ++pass) {
+            const int shift = 24 - 8 * pass;
+            for (int i = tid; i < 256; i += 256) hist[i] = 0;
+            __syncthreads();
+            for (int t = tid; t < c; t += 256) {
+                const unsigned key = f2key(be[t]);
+                if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 0xFF], 1u);
+            }
+            __syncthreads();
+            if (tid == 0) {
+                unsigned acc = 0;
+                int dg = 0;
+                for (; dg < 256; ++dg) {
+                    if (acc + hist[dg] >= kr) break;
+                    acc += hist[dg];
+                }
+                s_prefix = prefix | ((unsigned)dg << shift);
+                s_kr = kr - acc;
+            }
+            __syncthreads();
+            prefix = s_prefix;
+            kr = s_kr;
+            mask |= 0xFFu << shift;
+        }
+        kth = prefix;
     }
+    if (mode == 0) {
+        if (tid == 0) atomicMin(&tau_key[q], kth);
+        return;
+    }
+    // compaction of the candidates with key <= kth, then an exact sort
+    if (tid == 0) s_m = 0;
+    __syncthreads();
+    for (int t = tid; t < c; t += 256) {
+        const float e = be[t];
+        if (f2key(e) <= kth) {
+            const int pos = atomicAdd(&s_m, 1);
+            se[pos] = e;
+            si[pos] = bi[t];
+        }
+    }
+    __syncthreads();
+    const int m = s_m;
+    int S = 1;
+    while (S < m) S <<= 1;
+    for (int t = m + tid; t < S; t += 256) { se[t] = __builtin_huge_valf(); si[t] = 0x7FFFFFFF; }
     for (int kb = 2; kb <= S; kb <<= 1)
         for (int jj = kb >> 1; jj > 0; jj >>= 1) {
             __syncthreads();
@@ -563,7 +645,7 @@ __global__ __launch_bounds__(256) void select_kernel(const int32_t* __restrict__
         }
     __syncthreads();
     for (int t = tid; t < kk; t += 256) {
-        const bool valid = t < c;
+        const bool valid = t < m;
         out_ids[q * kk + t] = valid ? (int64_t)si[t] : -1;
         out_est[q * kk + t] = valid ? se[t] : __builtin_huge_valf();
     }
@@ -575,38 +657,46 @@ __global__ void tau_key_kernel(const float* __restrict__ tau_est, int64_t nq, in
     if (q < nq) key[q] = f2key(tau_est[q * kk + kk - 1]);
 }
 
-// fallback queue: every pair of an overflowed query
-__global__ void redo_build_kernel(const int32_t* __restrict__ probes, int64_t np, int nprobe, int nlist,
-                                  const int32_t* __restrict__ ovf, int32_t* __restrict__ redo_l,
-                                  int32_t* __restrict__ redo_q, int32_t* __restrict__ redo_slot,
-                                  int32_t* __restrict__ redo_n)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= np) return;
-    const int64_t q = i / nprobe;
-    if (!ovf[q]) return;
-    int l = probes[i];
-    if (l < 0 || l >= nlist) return;
-    int pos = atomicAdd(redo_n, 1);
-    redo_l[pos] = l; redo_q[pos] = (int32_t)q; redo_slot[pos] = (int32_t)i;
-}
-
 // ---------------------------------------------------------------------------
 __global__ void fill_i32_kernel(int32_t* p, int64_t n, int32_t v) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
 }
 
+// pairs with probe rank in [rlo, rhi) (and, with qmask, of flagged queries only)
+__device__ inline bool pair_sel(const int32_t* probes, int64_t i, int nprobe, int nlist, int rlo, int rhi,
+                                const int32_t* qmask, int* l_out, int64_t* q_out) {
+    const int l = probes[i];
+    if (l < 0 || l >= nlist) return false;
+    const int64_t q = i / nprobe;
+    const int p = (int)(i - q * nprobe);
+    if (p < rlo || p >= rhi) return false;
+    if (qmask && !qmask[q]) return false;
+    *l_out = l; *q_out = q;
+    return true;
+}
+
 __global__ void pair_count_kernel(const int32_t* __restrict__ probes, int64_t np, int nprobe, int nlist,
-                                  int rankA, int32_t* __restrict__ cntA, int32_t* __restrict__ cntB)
+                                  int rlo, int rhi, const int32_t* __restrict__ qmask, int32_t* __restrict__ cnt)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= np) return;
-    int l = probes[i];
-    if (l < 0 || l >= nlist) return;
-    const int p = (int)(i % nprobe);
-    if (p < rankA) atomicAdd(&cntA[l], 1);
-    atomicAdd(&cntB[l], 1);
+    int l; int64_t q;
+    if (pair_sel(probes, i, nprobe, nlist, rlo, rhi, qmask, &l, &q)) atomicAdd(&cnt[l], 1);
+}
+
+__global__ void pair_scatter_kernel(const int32_t* __restrict__ probes, int64_t np, int nprobe, int nlist,
+                                    int rlo, int rhi, const int32_t* __restrict__ qmask,
+                                    const int32_t* __restrict__ off, int32_t* __restrict__ fill,
+                                    int32_t* __restrict__ pq, int32_t* __restrict__ pslot)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= np) return;
+    int l; int64_t q;
+    if (!pair_sel(probes, i, nprobe, nlist, rlo, rhi, qmask, &l, &q)) return;
+    const int pos = off[l] + atomicAdd(&fill[l], 1);
+    pq[pos] = (int32_t)q;
+    pslot[pos] = (int32_t)i;
 }
 
 // single workgroup: pair_off (by list id) and item_off (by rank of list_order)
@@ -636,27 +726,6 @@ __global__ __launch_bounds__(1024) void pair_scan_kernel(const int32_t* __restri
         item_off[i] = rb; rb += (cnt[list_order[i]] + qpi - 1) / qpi;
     }
     if (tid == 1023) { pair_off[nlist] = part_a[1023]; item_off[nlist] = part_b[1023]; }
-}
-
-__global__ void pair_scatter_kernel(const int32_t* __restrict__ probes, int64_t np, int nprobe, int nlist,
-                                    int rankA,
-                                    const int32_t* __restrict__ offA, int32_t* __restrict__ fillA,
-                                    int32_t* __restrict__ qA, int32_t* __restrict__ slotA,
-                                    const int32_t* __restrict__ offB, int32_t* __restrict__ fillB,
-                                    int32_t* __restrict__ qB, int32_t* __restrict__ slotB)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= np) return;
-    int l = probes[i];
-    if (l < 0 || l >= nlist) return;
-    const int64_t q = i / nprobe;
-    const int p = (int)(i - q * nprobe);
-    if (p < rankA) {
-        int pos = offA[l] + atomicAdd(&fillA[l], 1);
-        qA[pos] = (int32_t)q; slotA[pos] = (int32_t)i;
-    }
-    int pos = offB[l] + atomicAdd(&fillB[l], 1);
-    qB[pos] = (int32_t)q; slotB[pos] = (int32_t)i;
 }
 
 // one wave per query: the kk best of its probed lists' top-kk lists (pairs
@@ -732,7 +801,6 @@ __global__ __launch_bounds__(256) void merge_kernel(const int32_t* __restrict__ 
 struct ScanArgs {
     const float* qrot;
     const int32_t *pair_off, *pair_q, *pair_slot, *item_off;
-    const int32_t *redo_l, *redo_n;
     int64_t grid;
     int vmax;
     int kk;
@@ -754,7 +822,7 @@ hipError_t launchA_t(const Index* ix, const ScanArgs& a, hipStream_t st)
     hipLaunchKernelGGL((scanA_kernel<BITS, KK>), dim3((unsigned)a.grid), dim3(kThreads), sm, st,
                        ix->codes, ix->tile_off, ix->list_off, ix->fac, ix->ids, ix->cent_rot, ix->dp,
                        a.qrot, a.pair_off, a.pair_q, a.pair_slot, a.item_off, ix->list_order, (int)ix->nlist,
-                       a.redo_l, a.redo_n, a.vmax, a.kk, a.res_est, a.res_id);
+                       a.vmax, a.kk, a.res_est, a.res_id);
     return hipGetLastError();
 }
 
@@ -827,11 +895,9 @@ size_t scan_workspace_bytes(int64_t nq, int nprobe, int64_t nlist, int kk)
 {
     const int64_t P = nq * nprobe;
     size_t b = 0;
-    b += 4 * align256(sizeof(int32_t) * nlist);            // cntA, cntB, fillA, fillB
-    b += 4 * align256(sizeof(int32_t) * (nlist + 1));      // pair/item offsets of A and B
-    b += 4 * align256(sizeof(int32_t) * P);                // pairs of A and B
-    b += 3 * align256(sizeof(int32_t) * P);                // fallback queue
-    b += align256(sizeof(int32_t));                        // fallback count
+    b += 2 * align256(sizeof(int32_t) * nlist);            // cnt, fill
+    b += 2 * align256(sizeof(int32_t) * (nlist + 1));      // pair / item offsets
+    b += 2 * align256(sizeof(int32_t) * P);                // pair table (query, slot)
     b += align256(sizeof(float) * nq * kk);                // pass-A top-kk per query
     b += align256(sizeof(unsigned) * nq);                  // bound per query
     b += 2 * align256(sizeof(int32_t) * nq);               // candidate counts, overflow flags
@@ -851,22 +917,12 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, in
         return fail(ERQ_ENOMEM, "erq_scan: workspace too small");
     char* w = (char*)ws;
     auto take = [&](size_t bytes) { char* p = w; w += align256(bytes); return p; };
-    int32_t* cntA = (int32_t*)take(sizeof(int32_t) * nlist);
-    int32_t* cntB = (int32_t*)take(sizeof(int32_t) * nlist);
-    int32_t* fillA = (int32_t*)take(sizeof(int32_t) * nlist);
-    int32_t* fillB = (int32_t*)take(sizeof(int32_t) * nlist);
-    int32_t* offA = (int32_t*)take(sizeof(int32_t) * (nlist + 1));
-    int32_t* itemA = (int32_t*)take(sizeof(int32_t) * (nlist + 1));
-    int32_t* offB = (int32_t*)take(sizeof(int32_t) * (nlist + 1));
-    int32_t* itemB = (int32_t*)take(sizeof(int32_t) * (nlist + 1));
-    int32_t* qA = (int32_t*)take(sizeof(int32_t) * P);
-    int32_t* sA = (int32_t*)take(sizeof(int32_t) * P);
-    int32_t* qB = (int32_t*)take(sizeof(int32_t) * P);
-    int32_t* sB = (int32_t*)take(sizeof(int32_t) * P);
-    int32_t* rl = (int32_t*)take(sizeof(int32_t) * P);
-    int32_t* rq = (int32_t*)take(sizeof(int32_t) * P);
-    int32_t* rs = (int32_t*)take(sizeof(int32_t) * P);
-    int32_t* rn = (int32_t*)take(sizeof(int32_t));
+    int32_t* cnt = (int32_t*)take(sizeof(int32_t) * nlist);
+    int32_t* fill = (int32_t*)take(sizeof(int32_t) * nlist);
+    int32_t* poff = (int32_t*)take(sizeof(int32_t) * (nlist + 1));
+    int32_t* ioff = (int32_t*)take(sizeof(int32_t) * (nlist + 1));
+    int32_t* pq = (int32_t*)take(sizeof(int32_t) * P);
+    int32_t* ps = (int32_t*)take(sizeof(int32_t) * P);
     float* tau = (float*)take(sizeof(float) * nq * kk);
     unsigned* tkey = (unsigned*)take(sizeof(unsigned) * nq);
     int32_t* gcnt = (int32_t*)take(sizeof(int32_t) * nq);
@@ -880,70 +936,81 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, in
     auto zero = [&](int32_t* p, int64_t n) {
         if (n > 0) hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)((n + th - 1) / th)), dim3(th), 0, st, p, n, 0);
     };
-    const int rankA = std::min(nprobe, kRankA);
-    zero(cntA, nlist); zero(cntB, nlist); zero(fillA, nlist); zero(fillB, nlist); zero(rn, 1); zero(gcnt, nq);
-    if (P > 0) {
-        hipLaunchKernelGGL(pair_count_kernel, dim3((unsigned)((P + th - 1) / th)), dim3(th), 0, st,
-                           probes, P, nprobe, (int)nlist, rankA, cntA, cntB);
-    }
+    const unsigned pblocks = (unsigned)((P + th - 1) / th);
+    // pair table of the probes with rank in [rlo, rhi) (of flagged queries with qmask), grouped by list
+    auto build_pairs = [&](int rlo, int rhi, const int32_t* qmask, int qpi) {
+        zero(cnt, nlist); zero(fill, nlist);
+        hipLaunchKernelGGL(pair_count_kernel, dim3(pblocks), dim3(th), 0, st, probes, P, nprobe, (int)nlist,
+                           rlo, rhi, qmask, cnt);
+        hipLaunchKernelGGL(pair_scan_kernel, dim3(1), dim3(1024), 0, st, cnt, (int)nlist, ix->list_order, qpi,
+                           poff, ioff);
+        hipLaunchKernelGGL(pair_scatter_kernel, dim3(pblocks), dim3(th), 0, st, probes, P, nprobe, (int)nlist,
+                           rlo, rhi, qmask, poff, fill, pq, ps);
+        return hipGetLastError();
+    };
+    if (nq == 0) return ERQ_OK;
+    zero(gcnt, nq);
     const int qpiB = (ix->dp <= 768) ? 2 * kQT : kQT;
-    hipLaunchKernelGGL(pair_scan_kernel, dim3(1), dim3(1024), 0, st, cntA, (int)nlist, ix->list_order, kQT, offA, itemA);
-    hipLaunchKernelGGL(pair_scan_kernel, dim3(1), dim3(1024), 0, st, cntB, (int)nlist, ix->list_order, qpiB, offB, itemB);
-    if (P > 0) {
-        hipLaunchKernelGGL(pair_scatter_kernel, dim3((unsigned)((P + th - 1) / th)), dim3(th), 0, st,
-                           probes, P, nprobe, (int)nlist, rankA, offA, fillA, qA, sA, offB, fillB, qB, sB);
-    }
-    ERQ_HIP(hipGetLastError());
+    const int r1 = std::min(nprobe, kRankA);
     const int pr = prof_begin(PK_SCAN, st);
     hipError_t e = hipSuccess;
-    if (P > 0) {
-        // pass A: the bound
-        const int64_t PA = nq * (int64_t)rankA;
-        ScanArgs a{qrot, offA, qA, sA, itemA, nullptr, nullptr, (PA + kQT - 1) / kQT + nlist, kVecA, kk, res_est, res_id};
-        int pp = prof_begin(PK_SCAN_A, st);
+    // pass A: the first bound, from the first kVecA members of the r1 nearest probed lists
+    int pp = prof_begin(PK_SCAN_A, st);
+    e = build_pairs(0, r1, nullptr, kQT);
+    if (e == hipSuccess) {
+        ScanArgs a{qrot, poff, pq, ps, ioff, std::min<int64_t>((nq * r1 + kQT - 1) / kQT + nlist, 8192), kVecA, kk,
+                   res_est, res_id};
         e = launchA(ix, a, st);
-        if (e == hipSuccess) {
-            hipLaunchKernelGGL(merge_kernel, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, st, probes, nq, nprobe,
-                               (int)nlist, kk, rankA, (const int32_t*)nullptr, res_est, res_id, (int64_t*)nullptr, tau);
-            hipLaunchKernelGGL(tau_key_kernel, dim3((unsigned)((nq + th - 1) / th)), dim3(th), 0, st, tau, nq, kk, tkey);
-            e = hipGetLastError();
-        }
-        prof_end(pp, st);
-        // pass B: the scan
-        if (e == hipSuccess) {
-            ScanArgs b{qrot, offB, qB, sB, itemB, nullptr, nullptr, (P + qpiB - 1) / qpiB + nlist, 0, kk, nullptr, nullptr};
-            BArgs bb{tkey, gcnt, gbe, gbi};
-            pp = prof_begin(PK_SCAN_B, st);
-            e = launchB(ix, b, bb, st);
-            prof_end(pp, st);
-        }
-        // select, then the exact fallback for overflowed queries
-        if (e == hipSuccess) {
-            pp = prof_begin(PK_SCAN_C, st);
-            hipLaunchKernelGGL(select_kernel, dim3((unsigned)nq), dim3(256), 0, st, gcnt, gbe, gbi, kk, ovf,
-                               out_ids, out_est);
-            hipLaunchKernelGGL(redo_build_kernel, dim3((unsigned)((P + th - 1) / th)), dim3(th), 0, st, probes, P,
-                               nprobe, (int)nlist, ovf, rl, rq, rs, rn);
-            e = hipGetLastError();
-            if (e == hipSuccess) {
-                ScanArgs c{qrot, nullptr, rq, rs, nullptr, rl, rn, 1024, 0x7FFFFFFF, kk, res_est, res_id};
-                e = launchA(ix, c, st);
-            }
-            if (e == hipSuccess) {
-                hipLaunchKernelGGL(merge_kernel, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, st, probes, nq,
-                                   nprobe, (int)nlist, kk, nprobe, ovf, res_est, res_id, out_ids, out_est);
-                e = hipGetLastError();
-            }
-            prof_end(pp, st);
-        }
-    } else if (nq > 0) {
-        hipLaunchKernelGGL(select_kernel, dim3((unsigned)nq), dim3(256), 0, st, gcnt, gbe, gbi, kk, ovf,
-                           out_ids, out_est);
+    }
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(merge_kernel, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, st, probes, nq, nprobe,
+                           (int)nlist, kk, r1, (const int32_t*)nullptr, res_est, res_id, (int64_t*)nullptr, tau);
+        hipLaunchKernelGGL(tau_key_kernel, dim3((unsigned)((nq + th - 1) / th)), dim3(th), 0, st, tau, nq, kk, tkey);
         e = hipGetLastError();
     }
+    prof_end(pp, st);
+    // pass B in rounds of increasing probe rank; after each round the bound
+    // drops to the kk-th best candidate found so far
+    pp = prof_begin(PK_SCAN_B, st);
+    const int bounds[4] = {0, r1, std::min(nprobe, 4 * kRankA), nprobe};
+    for (int r = 0; r < 3 && e == hipSuccess; ++r) {
+        const int rlo = bounds[r], rhi = bounds[r + 1];
+        if (rhi <= rlo) continue;
+        e = build_pairs(rlo, rhi, nullptr, qpiB);
+        if (e != hipSuccess) break;
+        ScanArgs b{qrot, poff, pq, ps, ioff, (nq * (int64_t)(rhi - rlo) + qpiB - 1) / qpiB + nlist,
+                   0, kk, nullptr, nullptr};
+        BArgs bb{tkey, gcnt, gbe, gbi};
+        e = launchB(ix, b, bb, st);
+        if (e == hipSuccess && rhi < nprobe) {
+            hipLaunchKernelGGL(buf_select_kernel, dim3((unsigned)nq), dim3(256), 0, st, gcnt, gbe, gbi, kk, 0,
+                               tkey, ovf, (int64_t*)nullptr, (float*)nullptr);
+            e = hipGetLastError();
+        }
+    }
+    prof_end(pp, st);
+    // exact top-kk per query; queries whose buffer overflowed: pair by pair
+    pp = prof_begin(PK_SCAN_C, st);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(buf_select_kernel, dim3((unsigned)nq), dim3(256), 0, st, gcnt, gbe, gbi, kk, 1,
+                           tkey, ovf, out_ids, out_est);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = build_pairs(0, nprobe, ovf, kQT);
+    if (e == hipSuccess) {
+        ScanArgs c{qrot, poff, pq, ps, ioff, std::min<int64_t>((P + kQT - 1) / kQT + nlist, 4096), 0x7FFFFFFF, kk,
+                   res_est, res_id};
+        e = launchA(ix, c, st);
+    }
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(merge_kernel, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, st, probes, nq, nprobe,
+                           (int)nlist, kk, nprobe, ovf, res_est, res_id, out_ids, out_est);
+        e = hipGetLastError();
+    }
+    prof_end(pp, st);
     prof_end(pr, st);
     if (e != hipSuccess) return fail(ERQ_EDEVICE, std::string("scan launch: ") + hipGetErrorString(e));
-    if (P > 0) prof_note_redo(rn, st);
+    prof_note_redo(poff + nlist, st);       // pairs rescanned by the fallback
     return ERQ_OK;
 }
 
