@@ -9,20 +9,25 @@
 // returned.  One query batch runs as:
 //
 //  1. pair build: (query, probe) pairs grouped by list (count, scan,
-//     scatter); work items are (list, tile of its queries), longest list
-//     first.  Pass A takes the pairs of the query's kRankA nearest probes.
-//  2. pass A (a bound): exact top-kk of the first kVecA members of those
-//     lists, with sorted per-lane register lists; per query, the kk-th best
-//     of these estimates, tau_q.  Any subset of a query's candidates gives a
-//     valid bound: every member of the final top-kk has est <= tau_q.
-//  3. pass B (the scan): every pair, every member, 64 vectors x 64 queries per
-//     wave step.  Estimates above tau_q are dropped with one compare; the
-//     rest are staged in a per-query LDS buffer (spilling straight to global
-//     memory when it is full) and appended to the query's candidate buffer
-//     in HBM.  Each item lowers tau_q to the kk-th best it found.
+//     scatter) for a range of probe ranks; work items are (list, tile of its
+//     queries[, chunk of kVch members]), longest list first.
+//  2. pass A (a bound): exact top-kk of the first kVecA members of the
+//     kRankA nearest probed lists, with sorted per-lane register lists; per
+//     query, the kk-th best of these estimates, tau_q.  Any subset of a
+//     query's candidates gives a valid bound: every member of the final
+//     top-kk has est <= tau_q.
+//  3. pass B (the scan) in two rounds of probe rank, [0, 2 kRankA) and the
+//     rest: 64 vectors x 64 queries per wave step.  Estimates above tau_q are
+//     dropped with one compare; the rest are staged in a per-query LDS
+//     buffer (spilling straight to global memory when it is full) and
+//     appended to the query's candidate buffer in HBM.  A query whose buffer
+//     overflowed in a round gets back the count it had before the round,
+//     tau_q drops to the kk-th best of its kCapQ stored candidates, and the
+//     round's pairs of those queries are scanned again.  After a round tau_q
+//     drops to the kk-th best candidate so far.
 //  4. select: per query, the exact kk smallest (est, id) of its candidates.
-//  5. fallback: a query whose candidate buffer overflowed is scanned again
-//     pair by pair with the exact per-lane-list kernel and merged.
+//  5. fallback: a query whose buffer still overflowed is scanned pair by
+//     pair with the exact per-lane-list kernel and merged.
 #include <algorithm>
 
 #include "erq_common.h"
@@ -37,6 +42,7 @@ constexpr int kCapB = 48;      // per-query survivor buffer of a pass-B item (LD
 constexpr int kRankA = 8;      // pass A: nearest probes per query ...
 constexpr int kVecA = 128;     // ... and members per list used for the bound
 constexpr int kCapQ = 4096;    // candidate buffer per query (HBM)
+constexpr int kVch = 2048;     // pass-B members per item (long lists are split)
 
 __device__ inline unsigned f2key(float f) {
     unsigned u = __float_as_uint(f);
@@ -166,8 +172,87 @@ __device__ inline void load_queries(int8_t* qs, float* s_s2, float* s_hd, int* s
                                     const int32_t* __restrict__ pq, const int32_t* __restrict__ pslot, int mq,
                                     int wid, int lane)
 {
+    constexpr int QPI = kQT * NQT;
     const int nch = dp / 16;
-    for (int qi = wid; qi < kQT * NQT; qi += 4) {
+    if (nch <= 64) {
+        // Wave wid quantises queries qi = wid + 4 k, kQB at a time: every
+        // load of a batch is issued before the first use.  Lanes past nch and
+        // columns past mq load valid rows and are masked to zero.
+        constexpr int kQB = 4;
+        const bool own = lane < nch;
+        const int ch = own ? lane : 0;
+        float cr[16];
+#pragma unroll
+        for (int e = 0; e < 16; e += 4) {
+            const float4 b = *(const float4*)(cv + ch * 16 + e);
+            cr[e] = b.x; cr[e + 1] = b.y; cr[e + 2] = b.z; cr[e + 3] = b.w;
+        }
+        for (int k0 = 0; k0 < QPI / 4; k0 += kQB) {
+            float sd[kQB][16];
+            float amax[kQB], s2[kQB];
+            int ssum[kQB];
+#pragma unroll
+            for (int b = 0; b < kQB; ++b) {
+                const int qi = wid + 4 * (k0 + b);
+                const bool use = own && qi < mq;
+                const int q = pq[min(qi, mq - 1)];
+                const float* qv = qrot + (int64_t)q * dp + ch * 16;
+#pragma unroll
+                for (int e = 0; e < 16; e += 4) {
+                    const float4 a = *(const float4*)(qv + e);
+                    sd[b][e + 0] = use ? a.x - cr[e + 0] : 0.0f;
+                    sd[b][e + 1] = use ? a.y - cr[e + 1] : 0.0f;
+                    sd[b][e + 2] = use ? a.z - cr[e + 2] : 0.0f;
+                    sd[b][e + 3] = use ? a.w - cr[e + 3] : 0.0f;
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < kQB; ++b) {
+                amax[b] = 0.0f; s2[b] = 0.0f; ssum[b] = 0;
+#pragma unroll
+                for (int e = 0; e < 16; ++e) { amax[b] = fmaxf(amax[b], fabsf(sd[b][e])); s2[b] += sd[b][e] * sd[b][e]; }
+            }
+            for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+                for (int b = 0; b < kQB; ++b) {
+                    amax[b] = fmaxf(amax[b], __shfl_xor(amax[b], o));
+                    s2[b] += __shfl_xor(s2[b], o);
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < kQB; ++b) {
+                const int qi = wid + 4 * (k0 + b);
+                const int qt = qi >> 5, j = qi & 31;
+                const float inv = (amax[b] > 0.0f) ? __fdiv_rn(127.0f, amax[b]) : 0.0f;
+                uint4 w;
+                quant_chunk(sd[b], inv, &ssum[b], &w);
+                if (own) {
+                    const int ks = lane >> 1, h = lane & 1;
+                    *(uint4*)(qs + ((ks * NQT + qt) * 64 + h * 32 + j) * 16) = w;
+                }
+            }
+            for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+                for (int b = 0; b < kQB; ++b) ssum[b] += __shfl_xor(ssum[b], o);
+            }
+            if (lane == 0) {
+#pragma unroll
+                for (int b = 0; b < kQB; ++b) {
+                    const int qi = wid + 4 * (k0 + b);
+                    if (qi < mq) {
+                        s_s2[qi] = s2[b];
+                        s_hd[qi] = 0.5f * ((amax[b] > 0.0f) ? __fdiv_rn(amax[b], 127.0f) : 0.0f);
+                        s_ss[qi] = ssum[b];
+                        s_slot[qi] = pslot[qi];
+                        s_q[qi] = pq[qi];
+                    }
+                }
+            }
+        }
+        return;
+    }
+    // dp > 1024: two passes per query (max and norm, then quantise)
+    for (int qi = wid; qi < QPI; qi += 4) {
         const int qt = qi >> 5, j = qi & 31;
         if (qi >= mq) {
             for (int c = lane; c < nch; c += 64) {
@@ -180,59 +265,33 @@ __device__ inline void load_queries(int8_t* qs, float* s_s2, float* s_hd, int* s
         const float* qv = qrot + (int64_t)q * dp;
         float amax = 0.0f, s2 = 0.0f;
         int ssum = 0;
-        if (nch <= 64) {
+        for (int c = lane; c < nch; c += 64) {
+#pragma unroll
+            for (int e = 0; e < 16; e += 4) {
+                float4 a = *(const float4*)(qv + c * 16 + e);
+                float4 b = *(const float4*)(cv + c * 16 + e);
+                float d0 = a.x - b.x, d1 = a.y - b.y, d2 = a.z - b.z, d3 = a.w - b.w;
+                amax = fmaxf(amax, fmaxf(fmaxf(fabsf(d0), fabsf(d1)), fmaxf(fabsf(d2), fabsf(d3))));
+                s2 += d0 * d0; s2 += d1 * d1; s2 += d2 * d2; s2 += d3 * d3;
+            }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            amax = fmaxf(amax, __shfl_xor(amax, o));
+            s2 += __shfl_xor(s2, o);
+        }
+        const float inv = (amax > 0.0f) ? __fdiv_rn(127.0f, amax) : 0.0f;
+        for (int c = lane; c < nch; c += 64) {
             float sd[16];
-            const bool own = lane < nch;
-            if (own) {
 #pragma unroll
-                for (int e = 0; e < 16; e += 4) {
-                    float4 a = *(const float4*)(qv + lane * 16 + e);
-                    float4 b = *(const float4*)(cv + lane * 16 + e);
-                    sd[e + 0] = a.x - b.x; sd[e + 1] = a.y - b.y; sd[e + 2] = a.z - b.z; sd[e + 3] = a.w - b.w;
-                }
-#pragma unroll
-                for (int e = 0; e < 16; ++e) { amax = fmaxf(amax, fabsf(sd[e])); s2 += sd[e] * sd[e]; }
+            for (int e = 0; e < 16; e += 4) {
+                float4 a = *(const float4*)(qv + c * 16 + e);
+                float4 b = *(const float4*)(cv + c * 16 + e);
+                sd[e + 0] = a.x - b.x; sd[e + 1] = a.y - b.y; sd[e + 2] = a.z - b.z; sd[e + 3] = a.w - b.w;
             }
-            for (int o = 32; o > 0; o >>= 1) {
-                amax = fmaxf(amax, __shfl_xor(amax, o));
-                s2 += __shfl_xor(s2, o);
-            }
-            const float inv = (amax > 0.0f) ? __fdiv_rn(127.0f, amax) : 0.0f;
-            if (own) {
-                uint4 w;
-                quant_chunk(sd, inv, &ssum, &w);
-                const int ks = lane >> 1, h = lane & 1;
-                *(uint4*)(qs + ((ks * NQT + qt) * 64 + h * 32 + j) * 16) = w;
-            }
-        } else {
-            for (int c = lane; c < nch; c += 64) {
-#pragma unroll
-                for (int e = 0; e < 16; e += 4) {
-                    float4 a = *(const float4*)(qv + c * 16 + e);
-                    float4 b = *(const float4*)(cv + c * 16 + e);
-                    float d0 = a.x - b.x, d1 = a.y - b.y, d2 = a.z - b.z, d3 = a.w - b.w;
-                    amax = fmaxf(amax, fmaxf(fmaxf(fabsf(d0), fabsf(d1)), fmaxf(fabsf(d2), fabsf(d3))));
-                    s2 += d0 * d0; s2 += d1 * d1; s2 += d2 * d2; s2 += d3 * d3;
-                }
-            }
-            for (int o = 32; o > 0; o >>= 1) {
-                amax = fmaxf(amax, __shfl_xor(amax, o));
-                s2 += __shfl_xor(s2, o);
-            }
-            const float inv = (amax > 0.0f) ? __fdiv_rn(127.0f, amax) : 0.0f;
-            for (int c = lane; c < nch; c += 64) {
-                float sd[16];
-#pragma unroll
-                for (int e = 0; e < 16; e += 4) {
-                    float4 a = *(const float4*)(qv + c * 16 + e);
-                    float4 b = *(const float4*)(cv + c * 16 + e);
-                    sd[e + 0] = a.x - b.x; sd[e + 1] = a.y - b.y; sd[e + 2] = a.z - b.z; sd[e + 3] = a.w - b.w;
-                }
-                uint4 w;
-                quant_chunk(sd, inv, &ssum, &w);
-                const int ks = c >> 1, h = c & 1;
-                *(uint4*)(qs + ((ks * NQT + qt) * 64 + h * 32 + j) * 16) = w;
-            }
+            uint4 w;
+            quant_chunk(sd, inv, &ssum, &w);
+            const int ks = c >> 1, h = c & 1;
+            *(uint4*)(qs + ((ks * NQT + qt) * 64 + h * 32 + j) * 16) = w;
         }
         for (int o = 32; o > 0; o >>= 1) ssum += __shfl_xor(ssum, o);
         if (lane == 0) {
@@ -416,7 +475,7 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
     const int32_t* __restrict__ pair_q, const int32_t* __restrict__ pair_slot,
     const int32_t* __restrict__ item_off, const int32_t* __restrict__ list_order, int nlist,
     int kk, unsigned* __restrict__ tau_key, int32_t* __restrict__ gcnt,
-    float* __restrict__ gbuf_e, int32_t* __restrict__ gbuf_i)
+    float* __restrict__ gbuf_e, int32_t* __restrict__ gbuf_i, int32_t* __restrict__ work)
 {
     constexpr int QPI = kQT * NQT;
     extern __shared__ __align__(16) char smem[];
@@ -425,20 +484,31 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
     __shared__ float s_be[QPI][kCapB];
     __shared__ int s_bi[QPI][kCapB];
     __shared__ unsigned s_tau[QPI];
-    __shared__ int s_item[3];
+    __shared__ int s_item[5];
 
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int item = blockIdx.x;
-    if (item >= item_off[nlist]) return;
+    const int n_items = item_off[nlist];
+    // items are taken from a shared counter until it passes n_items
+    for (;;) {
+    __syncthreads();                               // LDS of the previous item is free
     if (tid == 0) {
-        int l, t;
-        decode_item(item, item_off, list_order, nlist, &l, &t);
-        const int p0 = pair_off[l] + t * QPI;
-        s_item[0] = l; s_item[1] = p0; s_item[2] = min(QPI, pair_off[l + 1] - p0);
+        const int item = atomicAdd(work, 1);
+        s_item[4] = item;
+        if (item < n_items) {
+            int l, t;
+            decode_item(item, item_off, list_order, nlist, &l, &t);
+            const int nv = (int)(list_off[l + 1] - list_off[l]);
+            const int nvc = max(1, (nv + kVch - 1) / kVch);
+            const int qtile = t / nvc, vc = t - qtile * nvc;
+            const int p0 = pair_off[l] + qtile * QPI;
+            s_item[0] = l; s_item[1] = p0; s_item[2] = min(QPI, pair_off[l + 1] - p0);
+            s_item[3] = vc * kVch;
+        }
     }
     if (tid < QPI) s_cnt[tid] = 0;
     __syncthreads();
-    const int l = s_item[0], p0 = s_item[1], mq = s_item[2];
+    if (s_item[4] >= n_items) break;
+    const int l = s_item[0], p0 = s_item[1], mq = s_item[2], v0 = s_item[3];
     int8_t* qs = (int8_t*)smem;
     load_queries<NQT>(qs, s_s2, s_hd, s_ss, s_slot, s_q, qrot, cent_rot + (int64_t)l * dp, dp,
                       pair_q + p0, pair_slot + p0, mq, wid, lane);
@@ -449,11 +519,12 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
     const int nkb = dp / 64;
     const v4i* qb = (const v4i*)qs;
     const int64_t tile_bytes = (int64_t)4 * dp * BITS;
-    const int64_t lbase = list_off[l];
-    const int nl = (int)(list_off[l + 1] - lbase);
+    // members [v0, v0 + nl) of list l (v0 is a multiple of 64: whole tile pairs)
+    const int64_t lbase = list_off[l] + v0;
+    const int nl = min((int)(list_off[l + 1] - list_off[l]) - v0, kVch);
     const int ntile = (nl + 31) >> 5;
     const int ngroup = (ntile + 1) >> 1;
-    const int64_t tbase = tile_off[l];
+    const int64_t tbase = tile_off[l] + (v0 >> 5);
     const int j = lane & 31;
     // Columns without a query (qi >= mq) have no LDS terms: they take zeros
     // and are excluded from the pass test by qok, not by their estimate.
@@ -549,63 +620,84 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
             }
         }
     }
+    }
+}
+
+// 256 threads, one histogram bin each: the digit d whose bin holds the kr-th
+// smallest entry (exclusive prefix < kr <= inclusive prefix) and the rank
+// kr - exclusive prefix within that bin.  Ends with a barrier.
+__device__ inline void digit_of_rank(const unsigned* hist, unsigned kr, unsigned* s_digit, unsigned* s_kr,
+                                     unsigned* s_wsum) {
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const unsigned v = hist[tid];
+    unsigned x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) s_wsum[wid] = x;
+    __syncthreads();
+    unsigned base = 0;
+    for (int w = 0; w < wid; ++w) base += s_wsum[w];
+    const unsigned incl = base + x, excl = incl - v;
+    if (excl < kr && kr <= incl) { *s_digit = (unsigned)tid; *s_kr = kr - excl; }
+    __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
 // Per query, over its candidate buffer (count c): radix select of the key of
-// the kk-th smallest estimate (4 passes of 8 bits).  mode 0 lowers the
-// query's bound to it (the kk-th best candidate seen so far); mode 1 writes
-// the exact top-kk ascending by (est, id): the candidates with key <= that of
-// the kk-th are compacted and sorted.  A buffer that overflowed raises the
-// query's flag and is left to the fallback.
+// the kk-th smallest estimate (4 passes of 8 bits).
+//   mode 0: lowers the query's bound to it (the kk-th best candidate so far).
+//   mode 1: writes the exact top-kk ascending by (est, id): the candidates
+//           with key <= that of the kk-th are compacted and sorted.  A buffer
+//           that overflowed raises the query's flag for the fallback.
+//   mode 2: after a round; a buffer that overflowed raises the flag, gets back
+//           the count gprev it had before the round, and the bound drops to
+//           the kk-th best of its kCapQ stored candidates (all of them real
+//           estimates of distinct members, so still a valid bound).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void buf_select_kernel(const int32_t* __restrict__ gcnt,
+__global__ __launch_bounds__(256) void buf_select_kernel(int32_t* __restrict__ gcnt,
+                                                         const int32_t* __restrict__ gprev,
                                                          const float* __restrict__ gbuf_e,
                                                          const int32_t* __restrict__ gbuf_i, int kk, int mode,
                                                          unsigned* __restrict__ tau_key, int32_t* __restrict__ ovf,
                                                          int64_t* __restrict__ out_ids, float* __restrict__ out_est)
 {
     __shared__ unsigned hist[256];
-    __shared__ unsigned s_prefix, s_kr;
+    __shared__ unsigned s_digit, s_kr, s_wsum[4];
     __shared__ int s_m;
     __shared__ float se[kCapQ];
     __shared__ int si[kCapQ];
     const int64_t q = blockIdx.x;
     const int tid = threadIdx.x;
     const int craw = gcnt[q];
-    if (craw > kCapQ) {
-        if (mode == 1 && tid == 0) ovf[q] = 1;
+    const bool over = craw > kCapQ;
+    if (mode == 1 && over) {
+        if (tid == 0) ovf[q] = 1;
         return;
     }
-    if (mode == 1 && tid == 0) ovf[q] = 0;
-    const int c = craw;
+    if (mode != 0 && !over) {
+        if (tid == 0) ovf[q] = 0;
+        if (mode == 2) return;
+    }
+    if (mode == 0 && (over || craw < kk)) return;    // no (new) bound from this buffer
+    const int c = over ? kCapQ : craw;
     const float* be = gbuf_e + q * kCapQ;
     const int* bi = gbuf_i + q * kCapQ;
-    if (mode == 0 && c < kk) return;                 // fewer than kk candidates: no bound yet
     unsigned kth = 0xFFFFFFFFu;
     if (c >= kk) {
         unsigned prefix = 0, mask = 0, kr = (unsigned)kk;
         for (int pass = 0; pass < 4; ++pass) {
             const int shift = 24 - 8 * pass;
-            for (int i = tid; i < 256; i += 256) hist[i] = 0;
+            hist[tid] = 0;
             __syncthreads();
             for (int t = tid; t < c; t += 256) {
                 const unsigned key = f2key(be[t]);
                 if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 0xFF], 1u);
             }
             __syncthreads();
-            if (tid == 0) {
-                unsigned acc = 0;
-                int dg = 0;
-                for (; dg < 256; ++dg) {
-                    if (acc + hist[dg] >= kr) break;
-                    acc += hist[dg];
-                }
-                s_prefix = prefix | ((unsigned)dg << shift);
-                s_kr = kr - acc;
-            }
-            __syncthreads();
-            prefix = s_prefix;
+            digit_of_rank(hist, kr, &s_digit, &s_kr, s_wsum);
+            prefix |= s_digit << shift;
             kr = s_kr;
             mask |= 0xFFu << shift;
         }
@@ -613,6 +705,14 @@ __global__ __launch_bounds__(256) void buf_select_kernel(const int32_t* __restri
     }
     if (mode == 0) {
         if (tid == 0) atomicMin(&tau_key[q], kth);
+        return;
+    }
+    if (mode == 2) {                                  // over: kCapQ >= kk entries were ranked
+        if (tid == 0) {
+            atomicMin(&tau_key[q], kth);
+            gcnt[q] = gprev[q];
+            ovf[q] = 1;
+        }
         return;
     }
     // compaction of the candidates with key <= kth, then an exact sort
@@ -658,6 +758,11 @@ __global__ void tau_key_kernel(const float* __restrict__ tau_est, int64_t nq, in
 }
 
 // ---------------------------------------------------------------------------
+__global__ void copy_i32_kernel(const int32_t* __restrict__ src, int32_t* __restrict__ dst, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
 __global__ void fill_i32_kernel(int32_t* p, int64_t n, int32_t v) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -699,9 +804,20 @@ __global__ void pair_scatter_kernel(const int32_t* __restrict__ probes, int64_t 
     pslot[pos] = (int32_t)i;
 }
 
+// Items of list l: ceil(cnt/qpi) query tiles, times ceil(n_l/vch) member
+// chunks when vch > 0 (none for an empty list); with vch == 0 one item per
+// query tile, empty lists included (their pairs still get an output row).
+__device__ inline int items_of(const int32_t* cnt, const int64_t* list_off, int l, int qpi, int vch) {
+    const int tiles = (cnt[l] + qpi - 1) / qpi;
+    if (vch <= 0) return tiles;
+    const int nv = (int)(list_off[l + 1] - list_off[l]);
+    return tiles * ((nv + vch - 1) / vch);
+}
+
 // single workgroup: pair_off (by list id) and item_off (by rank of list_order)
 __global__ __launch_bounds__(1024) void pair_scan_kernel(const int32_t* __restrict__ cnt, int nlist,
-                                                         const int32_t* __restrict__ list_order, int qpi,
+                                                         const int32_t* __restrict__ list_order,
+                                                         const int64_t* __restrict__ list_off, int qpi, int vch,
                                                          int32_t* __restrict__ pair_off,
                                                          int32_t* __restrict__ item_off)
 {
@@ -710,7 +826,7 @@ __global__ __launch_bounds__(1024) void pair_scan_kernel(const int32_t* __restri
     const int chunk = (nlist + 1023) / 1024;
     const int beg = tid * chunk, end = min(nlist, beg + chunk);
     int sa = 0, sb = 0;
-    for (int i = beg; i < end; ++i) { sa += cnt[i]; sb += (cnt[list_order[i]] + qpi - 1) / qpi; }
+    for (int i = beg; i < end; ++i) { sa += cnt[i]; sb += items_of(cnt, list_off, list_order[i], qpi, vch); }
     part_a[tid] = sa; part_b[tid] = sb;
     __syncthreads();
     for (int o = 1; o < 1024; o <<= 1) {
@@ -723,7 +839,7 @@ __global__ __launch_bounds__(1024) void pair_scan_kernel(const int32_t* __restri
     int ra = part_a[tid] - sa, rb = part_b[tid] - sb;
     for (int i = beg; i < end; ++i) {
         pair_off[i] = ra; ra += cnt[i];
-        item_off[i] = rb; rb += (cnt[list_order[i]] + qpi - 1) / qpi;
+        item_off[i] = rb; rb += items_of(cnt, list_off, list_order[i], qpi, vch);
     }
     if (tid == 1023) { pair_off[nlist] = part_a[1023]; item_off[nlist] = part_b[1023]; }
 }
@@ -834,7 +950,7 @@ hipError_t launchA_b(const Index* ix, const ScanArgs& a, hipStream_t st)
     return launchA_t<BITS, 32>(ix, a, st);
 }
 
-struct BArgs { unsigned* tau_key; int32_t* gcnt; float* gbuf_e; int32_t* gbuf_i; };
+struct BArgs { unsigned* tau_key; int32_t* gcnt; float* gbuf_e; int32_t* gbuf_i; int32_t* work; };
 
 template <int BITS, int NQT>
 hipError_t launchB_t(const Index* ix, const ScanArgs& a, const BArgs& b, hipStream_t st)
@@ -845,10 +961,18 @@ hipError_t launchB_t(const Index* ix, const ScanArgs& a, const BArgs& b, hipStre
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((scanB_kernel<BITS, NQT>), dim3((unsigned)a.grid), dim3(kThreads), sm, st,
+    // resident blocks only: the kernel takes items from a work counter
+    int per_cu = 0, dev = 0, ncu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)scanB_kernel<BITS, NQT>,
+                                                                kThreads, sm);
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    const int64_t grid = std::min<int64_t>(a.grid, (int64_t)std::max(per_cu, 1) * std::max(ncu, 1));
+    hipLaunchKernelGGL((scanB_kernel<BITS, NQT>), dim3((unsigned)grid), dim3(kThreads), sm, st,
                        ix->codes, ix->tile_off, ix->list_off, ix->fac, ix->ids, ix->cent_rot, ix->dp,
                        a.qrot, a.pair_off, a.pair_q, a.pair_slot, a.item_off, ix->list_order, (int)ix->nlist,
-                       a.kk, b.tau_key, b.gcnt, b.gbuf_e, b.gbuf_i);
+                       a.kk, b.tau_key, b.gcnt, b.gbuf_e, b.gbuf_i, b.work);
     return hipGetLastError();
 }
 
@@ -900,7 +1024,8 @@ size_t scan_workspace_bytes(int64_t nq, int nprobe, int64_t nlist, int kk)
     b += 2 * align256(sizeof(int32_t) * P);                // pair table (query, slot)
     b += align256(sizeof(float) * nq * kk);                // pass-A top-kk per query
     b += align256(sizeof(unsigned) * nq);                  // bound per query
-    b += 2 * align256(sizeof(int32_t) * nq);               // candidate counts, overflow flags
+    b += 3 * align256(sizeof(int32_t) * nq);               // candidate counts, counts before a round, flags
+    b += align256(sizeof(int32_t));                        // pass-B work counter
     b += align256(sizeof(float) * nq * kCapQ);             // candidate buffers
     b += align256(sizeof(int32_t) * nq * kCapQ);
     b += align256(sizeof(float) * P * kk);                 // per-pair top-kk (pass A, fallback)
@@ -915,6 +1040,7 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, in
     const int64_t nlist = ix->nlist;
     if (ws_bytes < scan_workspace_bytes(nq, nprobe, nlist, kk))
         return fail(ERQ_ENOMEM, "erq_scan: workspace too small");
+    if (nq == 0) return ERQ_OK;
     char* w = (char*)ws;
     auto take = [&](size_t bytes) { char* p = w; w += align256(bytes); return p; };
     int32_t* cnt = (int32_t*)take(sizeof(int32_t) * nlist);
@@ -926,37 +1052,47 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, in
     float* tau = (float*)take(sizeof(float) * nq * kk);
     unsigned* tkey = (unsigned*)take(sizeof(unsigned) * nq);
     int32_t* gcnt = (int32_t*)take(sizeof(int32_t) * nq);
+    int32_t* gprev = (int32_t*)take(sizeof(int32_t) * nq);
     int32_t* ovf = (int32_t*)take(sizeof(int32_t) * nq);
+    int32_t* work = (int32_t*)take(sizeof(int32_t));
     float* gbe = (float*)take(sizeof(float) * nq * kCapQ);
     int32_t* gbi = (int32_t*)take(sizeof(int32_t) * nq * kCapQ);
     float* res_est = (float*)take(sizeof(float) * P * kk);
     int32_t* res_id = (int32_t*)take(sizeof(int32_t) * P * kk);
 
     const int th = 256;
+    const unsigned qblocks = (unsigned)((nq + th - 1) / th);
     auto zero = [&](int32_t* p, int64_t n) {
         if (n > 0) hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)((n + th - 1) / th)), dim3(th), 0, st, p, n, 0);
     };
     const unsigned pblocks = (unsigned)((P + th - 1) / th);
-    // pair table of the probes with rank in [rlo, rhi) (of flagged queries with qmask), grouped by list
-    auto build_pairs = [&](int rlo, int rhi, const int32_t* qmask, int qpi) {
+    // pair table of the probes with rank in [rlo, rhi) (of flagged queries with
+    // qmask), grouped by list; items split lists into chunks of vch members when vch > 0
+    auto build_pairs = [&](int rlo, int rhi, const int32_t* qmask, int qpi, int vch) {
         zero(cnt, nlist); zero(fill, nlist);
-        hipLaunchKernelGGL(pair_count_kernel, dim3(pblocks), dim3(th), 0, st, probes, P, nprobe, (int)nlist,
-                           rlo, rhi, qmask, cnt);
-        hipLaunchKernelGGL(pair_scan_kernel, dim3(1), dim3(1024), 0, st, cnt, (int)nlist, ix->list_order, qpi,
-                           poff, ioff);
-        hipLaunchKernelGGL(pair_scatter_kernel, dim3(pblocks), dim3(th), 0, st, probes, P, nprobe, (int)nlist,
-                           rlo, rhi, qmask, poff, fill, pq, ps);
+        if (P > 0)
+            hipLaunchKernelGGL(pair_count_kernel, dim3(pblocks), dim3(th), 0, st, probes, P, nprobe, (int)nlist,
+                               rlo, rhi, qmask, cnt);
+        hipLaunchKernelGGL(pair_scan_kernel, dim3(1), dim3(1024), 0, st, cnt, (int)nlist, ix->list_order,
+                           ix->list_off, qpi, vch, poff, ioff);
+        if (P > 0)
+            hipLaunchKernelGGL(pair_scatter_kernel, dim3(pblocks), dim3(th), 0, st, probes, P, nprobe, (int)nlist,
+                               rlo, rhi, qmask, poff, fill, pq, ps);
         return hipGetLastError();
     };
-    if (nq == 0) return ERQ_OK;
-    zero(gcnt, nq);
+    auto select = [&](int mode, int64_t* oi, float* oe) {
+        hipLaunchKernelGGL(buf_select_kernel, dim3((unsigned)nq), dim3(256), 0, st, gcnt, gprev, gbe, gbi, kk,
+                           mode, tkey, ovf, oi, oe);
+        return hipGetLastError();
+    };
     const int qpiB = (ix->dp <= 768) ? 2 * kQT : kQT;
     const int r1 = std::min(nprobe, kRankA);
     const int pr = prof_begin(PK_SCAN, st);
     hipError_t e = hipSuccess;
+    zero(gcnt, nq);
     // pass A: the first bound, from the first kVecA members of the r1 nearest probed lists
     int pp = prof_begin(PK_SCAN_A, st);
-    e = build_pairs(0, r1, nullptr, kQT);
+    e = build_pairs(0, r1, nullptr, kQT, 0);
     if (e == hipSuccess) {
         ScanArgs a{qrot, poff, pq, ps, ioff, std::min<int64_t>((nq * r1 + kQT - 1) / kQT + nlist, 8192), kVecA, kk,
                    res_est, res_id};
@@ -965,38 +1101,38 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, in
     if (e == hipSuccess) {
         hipLaunchKernelGGL(merge_kernel, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, st, probes, nq, nprobe,
                            (int)nlist, kk, r1, (const int32_t*)nullptr, res_est, res_id, (int64_t*)nullptr, tau);
-        hipLaunchKernelGGL(tau_key_kernel, dim3((unsigned)((nq + th - 1) / th)), dim3(th), 0, st, tau, nq, kk, tkey);
+        hipLaunchKernelGGL(tau_key_kernel, dim3(qblocks), dim3(th), 0, st, tau, nq, kk, tkey);
         e = hipGetLastError();
     }
     prof_end(pp, st);
-    // pass B in rounds of increasing probe rank; after each round the bound
-    // drops to the kk-th best candidate found so far
-    pp = prof_begin(PK_SCAN_B, st);
-    const int bounds[4] = {0, r1, std::min(nprobe, 4 * kRankA), nprobe};
-    for (int r = 0; r < 3 && e == hipSuccess; ++r) {
+    // pass B in rounds of increasing probe rank
+    const int bounds[3] = {0, std::min(nprobe, 2 * kRankA), nprobe};
+    const int64_t gridB = 1 << 20;                    // capped at the resident blocks
+    auto scan_round = [&](int rlo, int rhi, const int32_t* qmask) {
+        hipError_t er = build_pairs(rlo, rhi, qmask, qpiB, kVch);
+        if (er != hipSuccess) return er;
+        zero(work, 1);
+        ScanArgs b{qrot, poff, pq, ps, ioff, gridB, 0, kk, nullptr, nullptr};
+        BArgs bb{tkey, gcnt, gbe, gbi, work};
+        const int rec = prof_begin(PK_SCAN_B, st);   // one record per pass-B launch
+        er = launchB(ix, b, bb, st);
+        prof_end(rec, st);
+        return er;
+    };
+    for (int r = 0; r < 2 && e == hipSuccess; ++r) {
         const int rlo = bounds[r], rhi = bounds[r + 1];
         if (rhi <= rlo) continue;
-        e = build_pairs(rlo, rhi, nullptr, qpiB);
-        if (e != hipSuccess) break;
-        ScanArgs b{qrot, poff, pq, ps, ioff, (nq * (int64_t)(rhi - rlo) + qpiB - 1) / qpiB + nlist,
-                   0, kk, nullptr, nullptr};
-        BArgs bb{tkey, gcnt, gbe, gbi};
-        e = launchB(ix, b, bb, st);
-        if (e == hipSuccess && rhi < nprobe) {
-            hipLaunchKernelGGL(buf_select_kernel, dim3((unsigned)nq), dim3(256), 0, st, gcnt, gbe, gbi, kk, 0,
-                               tkey, ovf, (int64_t*)nullptr, (float*)nullptr);
-            e = hipGetLastError();
-        }
+        hipLaunchKernelGGL(copy_i32_kernel, dim3(qblocks), dim3(th), 0, st, gcnt, gprev, nq);
+        e = scan_round(rlo, rhi, nullptr);
+        // queries that overflowed: back to their count before the round, tighter bound, rescan the round
+        if (e == hipSuccess) e = select(2, nullptr, nullptr);
+        if (e == hipSuccess) e = scan_round(rlo, rhi, ovf);
+        if (e == hipSuccess && rhi < nprobe) e = select(0, nullptr, nullptr);
     }
-    prof_end(pp, st);
-    // exact top-kk per query; queries whose buffer overflowed: pair by pair
+    // exact top-kk per query; queries whose buffer still overflowed: pair by pair
     pp = prof_begin(PK_SCAN_C, st);
-    if (e == hipSuccess) {
-        hipLaunchKernelGGL(buf_select_kernel, dim3((unsigned)nq), dim3(256), 0, st, gcnt, gbe, gbi, kk, 1,
-                           tkey, ovf, out_ids, out_est);
-        e = hipGetLastError();
-    }
-    if (e == hipSuccess) e = build_pairs(0, nprobe, ovf, kQT);
+    if (e == hipSuccess) e = select(1, out_ids, out_est);
+    if (e == hipSuccess) e = build_pairs(0, nprobe, ovf, kQT, 0);
     if (e == hipSuccess) {
         ScanArgs c{qrot, poff, pq, ps, ioff, std::min<int64_t>((P + kQT - 1) / kQT + nlist, 4096), 0x7FFFFFFF, kk,
                    res_est, res_id};

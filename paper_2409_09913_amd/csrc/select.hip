@@ -27,7 +27,7 @@ __global__ __launch_bounds__(kSelThreads) void row_topk_kernel(
     __shared__ unsigned skey[kSelMaxK];
     __shared__ int sidx[kSelMaxK];
     __shared__ unsigned scan_l[kSelThreads], scan_e[kSelThreads];
-    __shared__ unsigned s_prefix, s_kr;
+    __shared__ unsigned s_digit, s_kr, s_wsum[kSelThreads / 64];
     const int tid = threadIdx.x;
     const int64_t row = blockIdx.x;
     const float* d = D + row * N;
@@ -43,21 +43,26 @@ __global__ __launch_bounds__(kSelThreads) void row_topk_kernel(
             if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 0xFF], 1u);
         }
         __syncthreads();
-        if (tid == 0) {
-            unsigned acc = 0;
-            int dg = 0;
-            for (; dg < 256; ++dg) {
-                if (acc + hist[dg] >= kr) break;
-                acc += hist[dg];
+        // bin of the kr-th smallest: one bin per thread, block-wide prefix sum
+        {
+            const int lane = tid & 63, wid = tid >> 6;
+            const unsigned v = hist[tid];
+            unsigned x = v;
+            for (int o = 1; o < 64; o <<= 1) {
+                const unsigned y = __shfl_up(x, o);
+                if (lane >= o) x += y;
             }
-            s_prefix = prefix | ((unsigned)dg << shift);
-            s_kr = kr - acc;
+            if (lane == 63) s_wsum[wid] = x;
+            __syncthreads();
+            unsigned base = 0;
+            for (int w = 0; w < wid; ++w) base += s_wsum[w];
+            const unsigned incl = base + x, excl = incl - v;
+            if (excl < kr && kr <= incl) { s_digit = (unsigned)tid; s_kr = kr - excl; }
+            __syncthreads();
         }
-        __syncthreads();
-        prefix = s_prefix;
+        prefix |= s_digit << shift;
         kr = s_kr;
         mask |= 0xFFu << shift;
-        __syncthreads();
     }
     const unsigned kth = prefix;                // key of the k-th smallest
     const unsigned need_eq = kr;                // how many equal to kth are taken

@@ -257,6 +257,23 @@ def test_scan_many_queries_per_list():
 # ---------------------------------------------------------------------------
 # coarse probe, rerank
 # ---------------------------------------------------------------------------
+def test_scan_long_lists_buffer_overflow():
+    # lists of 20000 members are split into chunks of 2048 members per work
+    # item; with kk = 32 the first bound (from 8 x 128 members) lets about
+    # 10k candidates per query through, more than a query's buffer holds, so
+    # the overflowing round is rescanned with the tighter bound
+    say("scan long lists + overflow")
+    sizes = np.full(16, 20000, np.int64)
+    _scan_case(n=int(sizes.sum()), nl=16, dp=64, B=4, nq=70, nprobe=16, kk=32, seed=77, sizes=sizes)
+
+
+def test_scan_one_huge_list():
+    # one list far longer than the rest (a skewed k-means partition)
+    say("scan huge list")
+    sizes = np.array([37696] + [300] * 23, np.int64)
+    _scan_case(n=int(sizes.sum()), nl=24, dp=128, B=4, nq=90, nprobe=3, kk=10, seed=78, sizes=sizes)
+
+
 def test_coarse_probe_parity():
     say("probe")
     dp, nl, nq, nprobe = 256, 300, 200, 17
