@@ -38,11 +38,11 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kQT = 32;        // queries per MFMA column tile
-constexpr int kCapB = 48;      // per-query survivor buffer of a pass-B item (LDS)
+constexpr int kCapB = 32;      // per-query survivor buffer of a pass-B item (LDS)
 constexpr int kRankA = 8;      // pass A: nearest probes per query ...
 constexpr int kVecA = 128;     // ... and members per list used for the bound
 constexpr int kCapQ = 4096;    // candidate buffer per query (HBM)
-constexpr int kVch = 2048;     // pass-B members per item (long lists are split)
+constexpr int kVch = 1024;     // pass-B members per item (long lists are split)
 
 __device__ inline unsigned f2key(float f) {
     unsigned u = __float_as_uint(f);
@@ -113,6 +113,27 @@ __device__ inline void load_codes(const uint8_t* kb, int lane, v4i& a0, v4i& a1)
     a1 = v4i{(int)U[4], (int)U[5], (int)U[6], (int)U[7]};
 }
 
+// raw packed words of one K-block (64 dims) of a tile for this lane: BITS dwords
+template <int BITS>
+__device__ inline void load_raw(const uint8_t* kbp, int lane, uint32_t* d) {
+    constexpr PartsC P = parts_c<BITS>();
+    load_part<P.w[0]>(kbp + lane * 4 * P.w[0], d);
+    if constexpr (P.n > 1) load_part<P.w[1]>(kbp + P.w[0] * 256 + lane * 4 * P.w[1], d + P.w[0]);
+    if constexpr (P.n > 2)
+        load_part<P.w[2]>(kbp + (P.w[0] + P.w[1]) * 256 + lane * 4 * P.w[2], d + P.w[0] + P.w[1]);
+}
+
+template <int BITS>
+__device__ inline void unpack_raw(const uint32_t* d, v4i& a0, v4i& a1) {
+    constexpr PartsC P = parts_c<BITS>();
+    uint32_t U[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    unpack_part<P.w[0], P.pos[0]>(d, U);
+    if constexpr (P.n > 1) unpack_part<P.w[1], P.pos[1]>(d + P.w[0], U);
+    if constexpr (P.n > 2) unpack_part<P.w[2], P.pos[2]>(d + P.w[0] + P.w[1], U);
+    a0 = v4i{(int)U[0], (int)U[1], (int)U[2], (int)U[3]};
+    a1 = v4i{(int)U[4], (int)U[5], (int)U[6], (int)U[7]};
+}
+
 template <int KK>
 __device__ inline void insert_sorted(float* le, int* li, float e, int i) {
 #pragma unroll
@@ -178,7 +199,7 @@ __device__ inline void load_queries(int8_t* qs, float* s_s2, float* s_hd, int* s
         // Wave wid quantises queries qi = wid + 4 k, kQB at a time: every
         // load of a batch is issued before the first use.  Lanes past nch and
         // columns past mq load valid rows and are masked to zero.
-        constexpr int kQB = 4;
+        constexpr int kQB = 2;
         const bool own = lane < nch;
         const int ch = own ? lane : 0;
         float cr[16];
@@ -466,7 +487,7 @@ __global__ __launch_bounds__(kThreads, 2) void scanA_kernel(
 // with one compare; survivors go to the query's candidate buffer in HBM
 // (staged in LDS; straight to HBM once the LDS stage is full).
 // ---------------------------------------------------------------------------
-template <int BITS, int NQT>
+template <int BITS, int NQT, int PD>
 __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
     const uint8_t* __restrict__ codes, const int64_t* __restrict__ tile_off,
     const int64_t* __restrict__ list_off, const float2* __restrict__ fac,
@@ -484,9 +505,11 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
     __shared__ float s_be[QPI][kCapB];
     __shared__ int s_bi[QPI][kCapB];
     __shared__ unsigned s_tau[QPI];
+    __shared__ float2 s_fac[kVch];
     __shared__ int s_item[5];
 
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform: scalar
     const int n_items = item_off[nlist];
     // items are taken from a shared counter until it passes n_items
     for (;;) {
@@ -512,6 +535,11 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
     int8_t* qs = (int8_t*)smem;
     load_queries<NQT>(qs, s_s2, s_hd, s_ss, s_slot, s_q, qrot, cent_rot + (int64_t)l * dp, dp,
                       pair_q + p0, pair_slot + p0, mq, wid, lane);
+    {   // factors of the item's members
+        const int64_t fb = list_off[l] + v0;
+        const int nf = min((int)(list_off[l + 1] - list_off[l]) - v0, kVch);
+        for (int t = tid; t < nf; t += kThreads) s_fac[t] = fac[fb + t];
+    }
     __syncthreads();
     if (tid < QPI) s_tau[tid] = (tid < mq) ? tau_key[s_q[tid]] : 0u;
     __syncthreads();
@@ -541,58 +569,92 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
         qtau[qt] = qok[qt] ? key2f(s_tau[qi]) : 0.0f;
     }
 
-    for (int g = wid; g < ngroup; g += 4) {
-        const int t0 = 2 * g, t1 = 2 * g + 1;
-        const bool has1 = t1 < ntile;
-        const uint8_t* tp0 = codes + (tbase + t0) * tile_bytes;
-        const uint8_t* tp1 = has1 ? codes + (tbase + t1) * tile_bytes : tp0;
-        v16i acc[2][NQT];
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int qt = 0; qt < NQT; ++qt)
-#pragma unroll
-                for (int r = 0; r < 16; ++r) acc[a][qt][r] = 0;
-        for (int kb = 0; kb < nkb; ++kb) {
-            v4i a00, a01, a10, a11;
-            load_codes<BITS>(tp0 + (int64_t)kb * 256 * BITS, lane, a00, a01);
-            load_codes<BITS>(tp1 + (int64_t)kb * 256 * BITS, lane, a10, a11);
-#pragma unroll
-            for (int qt = 0; qt < NQT; ++qt) {
-                v4i b0 = qb[((2 * kb + 0) * NQT + qt) * 64 + lane];
-                v4i b1 = qb[((2 * kb + 1) * NQT + qt) * 64 + lane];
-                acc[0][qt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a00, b0, acc[0][qt], 0, 0, 0);
-                acc[1][qt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a10, b0, acc[1][qt], 0, 0, 0);
-                acc[0][qt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a01, b1, acc[0][qt], 0, 0, 0);
-                acc[1][qt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a11, b1, acc[1][qt], 0, 0, 0);
+    // The wave's groups g = wid + 4 i (two tiles each) are walked as one
+    // sequence of K-steps (group, kb).  The packed codes of step s + PD are
+    // loaded while step s runs: a ring of PD slots of raw words in registers,
+    // unrolled by PD so that each slot is consumed and refilled in place (no
+    // copy of a register whose load is in flight).  PD divides nkb, so a group
+    // always ends with the last slot.  Past the end the last step is loaded
+    // again, so no load is conditional.
+    const int ngw = (ngroup > wid) ? (ngroup - 1 - wid) / 4 + 1 : 0;
+    const int total = ngw * nkb;
+    if (total > 0) {
+        uint32_t ring[PD][2 * BITS];
+        int pg = 0, pkb = 0, pleft = total;          // next step to load
+        auto load_step = [&](uint32_t* d) {
+            const int t0 = 2 * (wid + 4 * pg);
+            const int t1 = (t0 + 1 < ntile) ? t0 + 1 : t0;
+            const int64_t off = (int64_t)pkb * 256 * BITS;
+            load_raw<BITS>(codes + (tbase + t0) * tile_bytes + off, lane, d);
+            load_raw<BITS>(codes + (tbase + t1) * tile_bytes + off, lane, d + BITS);
+            if (pleft > 1) {
+                --pleft;
+                if (++pkb == nkb) { pkb = 0; ++pg; }
             }
-        }
+        };
 #pragma unroll
-        for (int a = 0; a < 2; ++a) {
-            if (a == 1 && !has1) break;
-            const int tt = 2 * g + a;
+        for (int p = 0; p < PD; ++p) load_step(ring[p]);
+        v16i acc[2][NQT];
+        int gi = 0, kb0 = 0;
+        for (int st0 = 0; st0 < total; st0 += PD) {
+            if (kb0 == 0) {
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int v = tt * 32 + out_row(lane, r);
-                const bool ok = v < nl;
-                const float2 f = ok ? fac[lbase + v] : make_float2(0.0f, 0.0f);
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int qt = 0; qt < NQT; ++qt)
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) acc[a][qt][r] = 0;
+            }
+#pragma unroll
+            for (int p = 0; p < PD; ++p) {
+                v4i a00, a01, a10, a11;
+                unpack_raw<BITS>(ring[p], a00, a01);
+                unpack_raw<BITS>(ring[p] + BITS, a10, a11);
+                load_step(ring[p]);
+                const int kb = kb0 + p;
 #pragma unroll
                 for (int qt = 0; qt < NQT; ++qt) {
-                    const float est = estimate<BITS>(f, acc[a][qt][r], qs2[qt], qhd[qt], qss[qt]);
-                    const bool pass = ok && qok[qt] && est <= qtau[qt];
-                    if (__any(pass)) {
-                        if (pass) {
-                            const int qi = qt * kQT + j;
-                            const int id = (int)ids[lbase + v];
-                            const int pos = atomicAdd(&s_cnt[qi], 1);
-                            if (pos < kCapB) {
-                                s_be[qi][pos] = est; s_bi[qi][pos] = id;
-                            } else {                       // stage full: straight to HBM
-                                const int q = s_q[qi];
-                                const int gp = atomicAdd(&gcnt[q], 1);
-                                if (gp < kCapQ) {
-                                    gbuf_e[(int64_t)q * kCapQ + gp] = est;
-                                    gbuf_i[(int64_t)q * kCapQ + gp] = id;
+                    v4i b0 = qb[((2 * kb + 0) * NQT + qt) * 64 + lane];
+                    v4i b1 = qb[((2 * kb + 1) * NQT + qt) * 64 + lane];
+                    acc[0][qt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a00, b0, acc[0][qt], 0, 0, 0);
+                    acc[1][qt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a10, b0, acc[1][qt], 0, 0, 0);
+                    acc[0][qt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a01, b1, acc[0][qt], 0, 0, 0);
+                    acc[1][qt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a11, b1, acc[1][qt], 0, 0, 0);
+                }
+            }
+            kb0 += PD;
+            if (kb0 < nkb) continue;                // next K-steps of the same group
+            kb0 = 0;
+            const int g = wid + 4 * gi;
+            ++gi;
+            // epilogue of group g: estimates, bound test, survivors to the stage
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                const int tt = 2 * g + a;
+                if (tt >= ntile) break;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int v = tt * 32 + out_row(lane, r);
+                    const bool ok = v < nl;
+                    const float2 f = s_fac[ok ? v : 0];
+#pragma unroll
+                    for (int qt = 0; qt < NQT; ++qt) {
+                        const float est = estimate<BITS>(f, acc[a][qt][r], qs2[qt], qhd[qt], qss[qt]);
+                        const bool pass = ok && qok[qt] && est <= qtau[qt];
+                        if (__any(pass)) {
+                            if (pass) {
+                                const int qi = qt * kQT + j;
+                                const int id = (int)ids[lbase + v];
+                                const int pos = atomicAdd(&s_cnt[qi], 1);
+                                if (pos < kCapB) {
+                                    s_be[qi][pos] = est; s_bi[qi][pos] = id;
+                                } else {                       // stage full: straight to HBM
+                                    const int q = s_q[qi];
+                                    const int gp = atomicAdd(&gcnt[q], 1);
+                                    if (gp < kCapQ) {
+                                        gbuf_e[(int64_t)q * kCapQ + gp] = est;
+                                        gbuf_i[(int64_t)q * kCapQ + gp] = id;
+                                    }
                                 }
                             }
                         }
@@ -952,35 +1014,45 @@ hipError_t launchA_b(const Index* ix, const ScanArgs& a, hipStream_t st)
 
 struct BArgs { unsigned* tau_key; int32_t* gcnt; float* gbuf_e; int32_t* gbuf_i; int32_t* work; };
 
-template <int BITS, int NQT>
+template <int BITS, int NQT, int PD>
 hipError_t launchB_t(const Index* ix, const ScanArgs& a, const BArgs& b, hipStream_t st)
 {
+    const void* kern = (const void*)scanB_kernel<BITS, NQT, PD>;
     const size_t sm = (size_t)ix->dp * kQT * NQT;
     if (sm > 48 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void*)scanB_kernel<BITS, NQT>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+        hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
         if (e != hipSuccess) return e;
     }
     // resident blocks only: the kernel takes items from a work counter
     int per_cu = 0, dev = 0, ncu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)scanB_kernel<BITS, NQT>,
-                                                                kThreads, sm);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kThreads, sm);
     if (e == hipSuccess) e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
     const int64_t grid = std::min<int64_t>(a.grid, (int64_t)std::max(per_cu, 1) * std::max(ncu, 1));
-    hipLaunchKernelGGL((scanB_kernel<BITS, NQT>), dim3((unsigned)grid), dim3(kThreads), sm, st,
+    hipLaunchKernelGGL((scanB_kernel<BITS, NQT, PD>), dim3((unsigned)grid), dim3(kThreads), sm, st,
                        ix->codes, ix->tile_off, ix->list_off, ix->fac, ix->ids, ix->cent_rot, ix->dp,
                        a.qrot, a.pair_off, a.pair_q, a.pair_slot, a.item_off, ix->list_order, (int)ix->nlist,
                        a.kk, b.tau_key, b.gcnt, b.gbuf_e, b.gbuf_i, b.work);
     return hipGetLastError();
 }
 
+// ring depth: the largest of 4, 3, 2, 1 that divides the K-steps per group
+template <int BITS, int NQT>
+hipError_t launchB_n(const Index* ix, const ScanArgs& a, const BArgs& b, hipStream_t st)
+{
+    const int nkb = ix->dp / 64;
+    if (nkb % 4 == 0) return launchB_t<BITS, NQT, 4>(ix, a, b, st);
+    if (nkb % 3 == 0) return launchB_t<BITS, NQT, 3>(ix, a, b, st);
+    if (nkb % 2 == 0) return launchB_t<BITS, NQT, 2>(ix, a, b, st);
+    return launchB_t<BITS, NQT, 1>(ix, a, b, st);
+}
+
 template <int BITS>
 hipError_t launchB_b(const Index* ix, const ScanArgs& a, const BArgs& b, hipStream_t st)
 {
-    if (ix->dp <= 768) return launchB_t<BITS, 2>(ix, a, b, st);
-    return launchB_t<BITS, 1>(ix, a, b, st);
+    if (ix->dp <= 768) return launchB_n<BITS, 2>(ix, a, b, st);
+    return launchB_n<BITS, 1>(ix, a, b, st);
 }
 
 hipError_t launchA(const Index* ix, const ScanArgs& a, hipStream_t st)
