@@ -271,11 +271,12 @@ int orc_encode(const double* x, int64_t n, int dp, const double* cent,
 /* Query side.                                                               */
 /* ------------------------------------------------------------------------ */
 
-/* int8 quantisation of a rotated query residual s' = q' - c' (FP32).  The
+/* int8 quantisation of a rotated query q' (FP32), once per query.  The
    paper keeps q' in floating point (Sec. 3.3); the symmetric int8 form is
-   this implementation's addition, decided in FP32 exactly as the kernel does:
-   amax = max|s'_i|, inv = 127/amax, s_i = clamp(rint(s'_i * inv), -127, 127)
-   (round half to even), delta = amax/127; amax = 0 gives zeros. */
+   this implementation's addition (reading), decided in FP32 exactly as the
+   kernel does: amax = max|q'_i|, inv = 127/amax,
+   q_i = clamp(rint(q'_i * inv), -127, 127) (round half to even),
+   delta = amax/127; amax = 0 gives zeros. */
 void orc_query_quant(const float* s, int dp, int8_t* sq, float* delta, int32_t* ssum)
 {
     float amax = 0.0f;
@@ -325,15 +326,18 @@ double orc_est_paper(const uint8_t* code, int dp, int B, const double* s,
     return norm_r2 + ns2 - 2.0 * sqrt(norm_r2) * ns * obq / cos_oo;
 }
 
-/* Estimated squared distance with the int8 query (factor form), FP64:
-     2<y, s'> ~= delta * ( 2<y_u, s_int> - (2^B-1) * sum s_int )
-     est = f_add + ||s||^2 + f_rescale * <y, s'>.
-   ip_u = <y_u, s_int> is an exact integer. */
-static double orc_est_int8(int64_t ip_u, int32_t ssum, int B, double delta,
+/* Estimated squared distance with the int8 query (factor form), FP64.
+   The residual of the list is s' = q' - c' (rotation is linear), so
+     <y, s'> = <y, q'> - <y, c'>,   y = y_u - (2^B-1)/2 (centred code),
+   and with q' ~= delta * q_int:
+     2<y, q'> ~= delta * ( 2<y_u, q_int> - (2^B-1) * sum q_int )
+     est = f_add + ||s||^2 + f_rescale * <y, s'>          (Eq. eq:dis to ip).
+   ip_u = <y_u, q_int> is an exact integer; ybc = <y, c'>. */
+static double orc_est_int8(int64_t ip_u, int32_t qsum, int B, double delta, double ybc,
                            double ns2, double f_add, double f_rescale)
 {
-    double two_ip = delta * (double)(2 * ip_u - (int64_t)((1 << B) - 1) * ssum);
-    return f_add + ns2 + f_rescale * 0.5 * two_ip;
+    double two_ip = delta * (double)(2 * ip_u - (int64_t)((1 << B) - 1) * qsum);
+    return f_add + ns2 + f_rescale * (0.5 * two_ip - ybc);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -392,11 +396,11 @@ void orc_probe(const float* q, int64_t nq, const float* cent, int64_t C, int dp,
 /* IVF search with the int8 estimator (Sec. 4.1 with Sec. 3.3).  Index:
    list_off[C+1], ids[N] (row ids), codes[N x dp] (y_u, list order),
    f_add/f_rescale[N] (FP32 as stored), crot[C x dp] rotated centroids (FP32).
-   Queries: qrot[nq x dp] rotated (FP32), probes[nq x nprobe].  For every
-   probed list: s' = q' - c' in FP32, int8 quantisation, ||s||^2 in FP64;
-   every member gets an estimate; the kk smallest (est, id) are returned.
-   est_mode 0 = int8 query (factor form), 1 = float query (paper form, uses
-   cos_oo and the FP32 s'). */
+   Queries: qrot[nq x dp] rotated (FP32), probes[nq x nprobe].  Every query
+   is quantised to int8 once; for every probed list s' = q' - c' and ||s||^2
+   in FP64 (exact differences of the FP32 inputs); every member gets an
+   estimate; the kk smallest (est, id) are returned.  est_mode 0 = int8 query
+   (factor form), 1 = float query (paper form, uses cos_oo). */
 int orc_search(const int64_t* list_off, const int64_t* ids, const uint8_t* codes,
                const float* f_add, const float* f_rescale, const double* cos_oo,
                const float* crot, int64_t C, int dp, int B,
@@ -407,14 +411,16 @@ int orc_search(const int64_t* list_off, const int64_t* ids, const uint8_t* codes
     int bad = 0;
     #pragma omp parallel reduction(|:bad)
     {
-        float* s = (float*)malloc(sizeof(float) * dp);
         double* sd = (double*)malloc(sizeof(double) * dp);
-        int8_t* sq = (int8_t*)malloc((size_t)dp);
+        int8_t* qq = (int8_t*)malloc((size_t)dp);
+        const double half = ((double)((1 << B) - 1)) / 2.0;
         int64_t cap = 1024;
         orc_cand* cand = (orc_cand*)malloc(sizeof(orc_cand) * (size_t)cap);
         #pragma omp for schedule(dynamic, 1)
         for (int64_t iq = 0; iq < nq; ++iq) {
             int64_t nc = 0;
+            float delta; int32_t qsum;
+            orc_query_quant(qrot + iq * (int64_t)dp, dp, qq, &delta, &qsum);
             for (int p = 0; p < nprobe; ++p) {
                 int32_t l = probes[iq * nprobe + p];
                 if (l < 0) continue;                 /* padding: the query probes fewer lists */
@@ -422,9 +428,7 @@ int orc_search(const int64_t* list_off, const int64_t* ids, const uint8_t* codes
                 const float* qv = qrot + iq * (int64_t)dp;
                 const float* cv = crot + (int64_t)l * dp;
                 double ns2 = 0.0;
-                for (int i = 0; i < dp; ++i) { s[i] = qv[i] - cv[i]; sd[i] = (double)s[i]; ns2 += sd[i] * sd[i]; }
-                float delta; int32_t ssum;
-                orc_query_quant(s, dp, sq, &delta, &ssum);
+                for (int i = 0; i < dp; ++i) { sd[i] = (double)qv[i] - (double)cv[i]; ns2 += sd[i] * sd[i]; }
                 int64_t lo = list_off[l], hi = list_off[l + 1];
                 if (nc + (hi - lo) > cap) {
                     while (nc + (hi - lo) > cap) cap *= 2;
@@ -435,8 +439,12 @@ int orc_search(const int64_t* list_off, const int64_t* ids, const uint8_t* codes
                     double est;
                     if (est_mode == 0) {
                         int64_t ip = 0;
-                        for (int i = 0; i < dp; ++i) ip += (int64_t)cd[i] * (int64_t)sq[i];
-                        est = orc_est_int8(ip, ssum, B, (double)delta, ns2,
+                        double ybc = 0.0;
+                        for (int i = 0; i < dp; ++i) {
+                            ip += (int64_t)cd[i] * (int64_t)qq[i];
+                            ybc += ((double)cd[i] - half) * (double)cv[i];
+                        }
+                        est = orc_est_int8(ip, qsum, B, (double)delta, ybc, ns2,
                                            (double)f_add[v], (double)f_rescale[v]);
                     } else {
                         est = orc_est_paper(cd, dp, B, sd, (double)f_add[v], cos_oo[v]);
@@ -446,7 +454,7 @@ int orc_search(const int64_t* list_off, const int64_t* ids, const uint8_t* codes
             }
             orc_take_k(cand, nc, kk, out_ids + iq * kk, out_d + iq * kk);
         }
-        free(s); free(sd); free(sq); free(cand);
+        free(sd); free(qq); free(cand);
     }
     return bad ? -1 : 0;
 }

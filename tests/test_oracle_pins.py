@@ -280,8 +280,9 @@ def _numpy_search(off, ids, codes, fa, fr, crot, qrot, probes, B, kk, est_mode, 
 
 def test_search_matches_bruteforce_and_int8_bound():
     """IVF scan (Sec. 4.1): the oracle's float-query scan equals a brute-force
-    re-statement; the int8-query estimate differs from it by at most the
-    quantisation bound |f_rescale| * delta/2 * ||y_bar||_1."""
+    re-statement; the int8-query estimate (q' quantised once per query, the
+    list term <y_bar, c'> taken exactly by linearity of s' = q' - c') differs
+    from it by at most the quantisation bound |f_rescale| * delta/2 * ||y_bar||_1."""
     B, dp, n, nl, nq = 4, 128, 3000, 12, 8
     off, ids, codes, fa, fr, crot = synth.random_index(n, nl, dp, B, seed=3)
     qrot = synth.random_rotated(nq, dp, seed=3)
@@ -293,13 +294,35 @@ def test_search_matches_bruteforce_and_int8_bound():
     for iq in range(nq):
         ref_ids = [c[1] for c in bf[iq]]
         ref_d = np.array([c[0] for c in bf[iq]])
-        tol = 0.0
-        for l in probes[iq]:
-            _, d, _ = oracle.query_quant((qrot[iq] - crot[l]).astype(np.float32))
-            tol = max(tol, np.abs(fr).max() * d / 2 * ymax)
+        _, d, _ = oracle.query_quant(qrot[iq].astype(np.float32))
+        tol = np.abs(fr).max() * d / 2 * ymax
         # the k-th smallest of perturbed values moves by at most the perturbation
         assert np.all(np.abs(od[iq] - ref_d) <= tol + 1e-6)
         assert len(set(oi[iq]) & set(ref_ids)) >= 7
+
+
+def test_int8_estimate_exact_for_grid_queries():
+    """When every coordinate of q' is an integer multiple k_i * 2^-6 of the
+    grid with max |k_i| = 127, the int8 quantisation is lossless, so the int8
+    estimate must equal the float-query estimate f_add + ||q'-c'||^2 +
+    f_rescale <y_bar, q'-c'> (Eq. eq:dis to ip) up to FP64 rounding; a
+    dropped or mis-signed list term <y_bar, c'> or a wrong code offset fails."""
+    g = np.random.default_rng(5)
+    for B in (1, 3, 4, 8):
+        dp, n, nl, nq = 64, 600, 6, 5
+        off, ids, codes, fa, fr, crot = synth.random_index(n, nl, dp, B, seed=40 + B)
+        k = g.integers(-127, 128, (nq, dp))
+        k[:, 0] = 127
+        qrot = (k * 2.0 ** -6).astype(np.float32)
+        probes = np.array([g.choice(nl, 3, replace=False) for _ in range(nq)], np.int32)
+        bf = _numpy_search(off, ids, codes, fa, fr, crot, qrot, probes, B, 600, 1)
+        oi, od = oracle.search(off, ids, codes, fa, fr, crot, qrot, probes, B, 600, est_mode=0)
+        for iq in range(nq):
+            ref = dict((int(c[1]), c[0]) for c in bf[iq])
+            got = dict((int(i), float(e)) for i, e in zip(oi[iq], od[iq]) if i >= 0)
+            assert set(got) == set(ref)
+            for i, e in got.items():
+                assert abs(e - ref[i]) <= 1e-9 * (1.0 + abs(ref[i]))
 
 
 def test_probe_knn_rerank_match_numpy():
