@@ -74,9 +74,9 @@ void prof_end(int rec, hipStream_t st)
 void free_index_storage(Index* ix)
 {
     hipFree(ix->cent); hipFree(ix->cent_rot); hipFree(ix->list_off); hipFree(ix->tile_off);
-    hipFree(ix->list_order); hipFree(ix->ids); hipFree(ix->fac); hipFree(ix->codes);
+    hipFree(ix->list_order); hipFree(ix->ids); hipFree(ix->fac); hipFree(ix->sfac); hipFree(ix->codes);
     ix->cent = ix->cent_rot = nullptr; ix->list_off = ix->tile_off = nullptr; ix->list_order = nullptr;
-    ix->ids = nullptr; ix->fac = nullptr; ix->codes = nullptr;
+    ix->ids = nullptr; ix->fac = nullptr; ix->sfac = nullptr; ix->codes = nullptr;
     ix->n = 0; ix->ntiles = 0; ix->h_list_off.clear(); ix->max_list = 0;
 }
 
@@ -271,20 +271,22 @@ int erq_index_import(erq_index ix, int64_t n, const int64_t* list_off, const int
     ix->n = n;
     ERQ_HIP(hipMalloc(&ix->ids, sizeof(int64_t) * std::max<int64_t>(n, 1)));
     ERQ_HIP(hipMalloc(&ix->fac, sizeof(float2) * std::max<int64_t>(n, 1)));
+    ERQ_HIP(hipMalloc(&ix->sfac, sizeof(float2) * std::max<int64_t>(n, 1)));
     ERQ_HIP(hipMalloc(&ix->codes, std::max<int64_t>((int64_t)4 * dp * ix->bits * ix->ntiles, 256)));
     ERQ_HIP(hipMalloc(&ix->cent, sizeof(float) * C * dp));
     ERQ_HIP(hipMalloc(&ix->cent_rot, sizeof(float) * C * dp));
-    if (n > 0) {
-        ERQ_HIP(hipMemcpyAsync(ix->ids, ids, sizeof(int64_t) * n, hipMemcpyDeviceToDevice, st));
-        hipLaunchKernelGGL(interleave_fac_kernel, dim3(blocks(n)), dim3(256), 0, st, f_add, f_rescale, n, ix->fac);
-        ERQ_HIP(hipGetLastError());
-        ERQ_HIP(launch_pack_n(codes, ix->list_off, ix->tile_off, C, dp, ix->bits, ix->ntiles, ix->codes, st));
-    }
     ERQ_HIP(hipMemcpyAsync(ix->cent, centroids, sizeof(float) * C * dp, hipMemcpyDeviceToDevice, st));
     if (centroids_rot)
         ERQ_HIP(hipMemcpyAsync(ix->cent_rot, centroids_rot, sizeof(float) * C * dp, hipMemcpyDeviceToDevice, st));
     else
         ERQ_HIP(launch_gemm(ix->cent, C, dp, ix->P, dp, 0, 0, ix->cent_rot, dp, st));
+    if (n > 0) {
+        ERQ_HIP(hipMemcpyAsync(ix->ids, ids, sizeof(int64_t) * n, hipMemcpyDeviceToDevice, st));
+        hipLaunchKernelGGL(interleave_fac_kernel, dim3(blocks(n)), dim3(256), 0, st, f_add, f_rescale, n, ix->fac);
+        ERQ_HIP(hipGetLastError());
+        ERQ_HIP(launch_pack_n(codes, ix->list_off, ix->tile_off, C, dp, ix->bits, ix->ntiles, ix->codes, st));
+        ERQ_HIP(launch_scan_fac(codes, ix->list_off, C, ix->cent_rot, ix->fac, n, dp, ix->bits, ix->sfac, st));
+    }
     ERQ_HIP(hipStreamSynchronize(st));
     return ERQ_OK;
 }
@@ -360,6 +362,7 @@ int erq_index_build(erq_index ix, const float* x, int64_t n, const float* centro
     guard.p.push_back(ids32);
     ERQ_HIP(hipMalloc(&ix->ids, sizeof(int64_t) * std::max<int64_t>(n, 1)));
     ERQ_HIP(hipMalloc(&ix->fac, sizeof(float2) * std::max<int64_t>(n, 1)));
+    ERQ_HIP(hipMalloc(&ix->sfac, sizeof(float2) * std::max<int64_t>(n, 1)));
     ERQ_HIP(hipMalloc(&ix->codes, std::max<int64_t>((int64_t)4 * dp * ix->bits * ix->ntiles, 256)));
     ERQ_HIP(launch_scatter(asg, n, ix->list_off, fillc, ids32, st));
     ERQ_HIP(launch_sort_lists(ix->list_off, C, ids32, ix->ids, st));
@@ -386,6 +389,7 @@ int erq_index_build(erq_index ix, const float* x, int64_t n, const float* centro
         prof_end(pr, st);
     }
     ERQ_HIP(launch_pack_n(codes_u, ix->list_off, ix->tile_off, C, dp, ix->bits, ix->ntiles, ix->codes, st));
+    ERQ_HIP(launch_scan_fac(codes_u, ix->list_off, C, ix->cent_rot, ix->fac, n, dp, ix->bits, ix->sfac, st));
     if (keep_raw && n > 0) {
         ERQ_HIP(hipMalloc(&ix->raw, sizeof(float) * n * dp));
         ERQ_HIP(hipMemcpyAsync(ix->raw, x, sizeof(float) * n * dp, hipMemcpyDeviceToDevice, st));
@@ -426,7 +430,7 @@ int erq_index_export(erq_index ix, int64_t* list_off, int64_t* ids, uint8_t* cod
 int erq_scan_workspace_size(erq_index ix, int64_t nq, int32_t nprobe, int32_t kk, size_t* bytes)
 {
     if (!ix || !bytes || nq < 0 || nprobe < 1 || kk < 1) return fail(ERQ_EINVAL, "erq_scan_workspace_size: bad arguments");
-    *bytes = scan_workspace_bytes(nq, nprobe, ix->nlist, kk);
+    *bytes = scan_workspace_bytes(nq, nprobe, ix->nlist, kk, ix->dp);
     return ERQ_OK;
 }
 
@@ -439,7 +443,8 @@ int erq_scan(erq_index ix, const float* qrot, int64_t nq, const int32_t* probes,
     if (kk < 1 || kk > 32) return fail(ERQ_EUNSUPPORTED, "erq_scan: kk must be in [1, 32]");
     if (nq > 0 && (!qrot || !probes || !out_ids || !out_est || !workspace)) return fail(ERQ_EINVAL, "erq_scan: null pointer");
     if (ix->nlist > 1000000) return fail(ERQ_EUNSUPPORTED, "erq_scan: more than 10^6 lists");
-    return run_scan(ix, qrot, nq, probes, nprobe, kk, out_ids, out_est, workspace, ws_bytes, (hipStream_t)stream);
+    return run_scan(ix, qrot, nq, probes, nullptr, nprobe, kk, out_ids, out_est, workspace, ws_bytes,
+                    (hipStream_t)stream);
 }
 
 int erq_rerank(erq_index ix, const float* q, int64_t nq, const int64_t* cand, int32_t kc, int32_t k,
@@ -459,9 +464,10 @@ static size_t search_ws(Index* ix, int64_t nq, int nprobe, int k, int rerank_k) 
     size_t b = 0;
     b += align256(sizeof(float) * nq * ix->dp);           // qrot
     b += align256(sizeof(int32_t) * nq * nprobe);         // probes
+    b += align256(sizeof(float) * nq * nprobe);           // probe distances ||q - c||^2
     b += align256(sizeof(int64_t) * nq * kk);             // candidate ids
     b += align256(sizeof(float) * nq * kk);               // candidate estimates
-    b += std::max(probe_ws(nq, ix->nlist), scan_workspace_bytes(nq, nprobe, ix->nlist, kk));
+    b += std::max(probe_ws(nq, ix->nlist), scan_workspace_bytes(nq, nprobe, ix->nlist, kk, ix->dp));
     return b;
 }
 
@@ -489,14 +495,16 @@ int erq_search(erq_index ix, const float* q, int64_t nq, int32_t nprobe, int32_t
     char* w = (char*)workspace;
     float* qrot = (float*)w; w += align256(sizeof(float) * nq * ix->dp);
     int32_t* probes = (int32_t*)w; w += align256(sizeof(int32_t) * nq * nprobe);
+    float* pdist = (float*)w; w += align256(sizeof(float) * nq * nprobe);
     int64_t* cid = (int64_t*)w; w += align256(sizeof(int64_t) * nq * kk);
     float* cest = (float*)w; w += align256(sizeof(float) * nq * kk);
     size_t rest = ws_bytes - (size_t)(w - (char*)workspace);
     int pr = prof_begin(PK_ROTATE, st);
     ERQ_HIP(launch_gemm(q, nq, ix->dp, ix->P, ix->dp, 0, 0, qrot, ix->dp, st));
     prof_end(pr, st);
-    if (int rc = probe_impl(q, nq, ix->cent, ix->nlist, ix->dp, nprobe, probes, nullptr, w, rest, st)) return rc;
-    if (int rc = run_scan(ix, qrot, nq, probes, nprobe, kk, cid, cest, w, rest, st)) return rc;
+    // the probe's ||q - c||^2 = ||q' - c'||^2 (P orthogonal) is the scan's ||s||^2
+    if (int rc = probe_impl(q, nq, ix->cent, ix->nlist, ix->dp, nprobe, probes, pdist, w, rest, st)) return rc;
+    if (int rc = run_scan(ix, qrot, nq, probes, pdist, nprobe, kk, cid, cest, w, rest, st)) return rc;
     if (rerank_k > 0) {
         int pr2 = prof_begin(PK_RERANK, st);
         ERQ_HIP(launch_rerank(ix->raw, ix->dp, q, nq, cid, kk, k, out_ids, out_dist, st));

@@ -70,6 +70,7 @@ struct Index {
     int32_t* list_order = nullptr; // lists by decreasing size (device)
     int64_t* ids = nullptr;        // n, list order
     float2* fac = nullptr;         // n, (f_add, f_rescale), list order
+    float2* sfac = nullptr;        // n, (f_add - f_rescale <y_bar, c'>, f_rescale): the scan's factors
     uint8_t* codes = nullptr;      // ntiles * 4 * dp * bits bytes
     float* raw = nullptr;          // n x dp raw vectors (id order) or null
     int64_t ntiles = 0;
@@ -101,9 +102,13 @@ hipError_t launch_quantize(const float* rrot, int64_t n, int dp, int bits, const
                            float2* fac, hipStream_t st);
 
 // scan pipeline
-size_t scan_workspace_bytes(int64_t nq, int nprobe, int64_t nlist, int kk);
-int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, int nprobe, int kk,
-             int64_t* out_ids, float* out_est, void* ws, size_t ws_bytes, hipStream_t st);
+size_t scan_workspace_bytes(int64_t nq, int nprobe, int64_t nlist, int kk, int dp);
+// pdist: ||q' - c'||^2 per (query, probe) (nq x nprobe) or null to compute it
+int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, const float* pdist, int nprobe,
+             int kk, int64_t* out_ids, float* out_est, void* ws, size_t ws_bytes, hipStream_t st);
+// scan factors from unpacked codes (list order) and (f_add, f_rescale)
+hipError_t launch_scan_fac(const uint8_t* codes_u, const int64_t* list_off, int64_t nlist, const float* cent_rot,
+                           const float2* fac, int64_t n, int dp, int bits, float2* sfac, hipStream_t st);
 hipError_t launch_rerank(const float* raw, int dp, const float* q, int64_t nq, const int64_t* cand,
                          int kc, int k, int64_t* out_ids, float* out_d, hipStream_t st);
 

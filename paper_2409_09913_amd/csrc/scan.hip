@@ -165,163 +165,44 @@ __device__ inline void decode_item(int item, const int32_t* item_off, const int3
     *t = item - item_off[lo];
 }
 
-// Prologue shared by the scan kernels: int8 residual queries of one item into
-// LDS, laid out as the B operand: query qi = qt*32 + j, 16-dim chunk
-// c = 2 ks + h at byte ((ks*NQT + qt)*64 + h*32 + j)*16.  For dp <= 1024 every
-// lane owns at most one chunk, kept in registers (one read of q' and c');
-// larger dp takes two passes (max and norm, then quantise).
-__device__ inline void quant_chunk(const float* sd, float inv, int* ssum, uint4* out) {
-    uint32_t w4[4];
-#pragma unroll
-    for (int d = 0; d < 4; ++d) {
-        uint32_t wd = 0;
-#pragma unroll
-        for (int bb = 0; bb < 4; ++bb) {
-            int v = (int)rintf(sd[4 * d + bb] * inv);
-            v = max(-127, min(127, v));
-            *ssum += v;
-            wd |= ((uint32_t)(v & 0xFF)) << (8 * bb);
-        }
-        w4[d] = wd;
-    }
-    *out = make_uint4(w4[0], w4[1], w4[2], w4[3]);
-}
+// Queries of a scan, prepared once per batch: q' quantised to int8 (qint,
+// nq x dp), delta/2 (qhd) and the sum of the int8 values (qss) per query,
+// and ||s||^2 = ||q' - c'||^2 per (query, probe) pair (sdist).
+struct QArgs {
+    const int8_t* qint;
+    const float* qhd;
+    const int32_t* qss;
+    const float* sdist;
+};
 
+// Prologue shared by the scan kernels: the int8 queries of one item into LDS,
+// row-major with a row stride of dp + 16 bytes (query qi at qs + qi*qstride).
+// Rows past mq are zero.  The 16-byte pad spreads the B-fragment reads of the
+// 32 columns over all LDS banks.  Per-query scalars go to s_*.
 template <int NQT>
-__device__ inline void load_queries(int8_t* qs, float* s_s2, float* s_hd, int* s_ss, int* s_slot, int* s_q,
-                                    const float* __restrict__ qrot, const float* __restrict__ cv, int dp,
-                                    const int32_t* __restrict__ pq, const int32_t* __restrict__ pslot, int mq,
-                                    int wid, int lane)
+__device__ inline void load_queries(int8_t* qs, int qstride, float* s_s2, float* s_hd, int* s_ss, int* s_slot,
+                                    int* s_q, const QArgs& qa, int dp, const int32_t* __restrict__ pq,
+                                    const int32_t* __restrict__ pslot, int mq, int tid)
 {
     constexpr int QPI = kQT * NQT;
-    const int nch = dp / 16;
-    if (nch <= 64) {
-        // Wave wid quantises queries qi = wid + 4 k, kQB at a time: every
-        // load of a batch is issued before the first use.  Lanes past nch and
-        // columns past mq load valid rows and are masked to zero.
-        constexpr int kQB = 2;
-        const bool own = lane < nch;
-        const int ch = own ? lane : 0;
-        float cr[16];
-#pragma unroll
-        for (int e = 0; e < 16; e += 4) {
-            const float4 b = *(const float4*)(cv + ch * 16 + e);
-            cr[e] = b.x; cr[e + 1] = b.y; cr[e + 2] = b.z; cr[e + 3] = b.w;
-        }
-        for (int k0 = 0; k0 < QPI / 4; k0 += kQB) {
-            float sd[kQB][16];
-            float amax[kQB], s2[kQB];
-            int ssum[kQB];
-#pragma unroll
-            for (int b = 0; b < kQB; ++b) {
-                const int qi = wid + 4 * (k0 + b);
-                const bool use = own && qi < mq;
-                const int q = pq[min(qi, mq - 1)];
-                const float* qv = qrot + (int64_t)q * dp + ch * 16;
-#pragma unroll
-                for (int e = 0; e < 16; e += 4) {
-                    const float4 a = *(const float4*)(qv + e);
-                    sd[b][e + 0] = use ? a.x - cr[e + 0] : 0.0f;
-                    sd[b][e + 1] = use ? a.y - cr[e + 1] : 0.0f;
-                    sd[b][e + 2] = use ? a.z - cr[e + 2] : 0.0f;
-                    sd[b][e + 3] = use ? a.w - cr[e + 3] : 0.0f;
-                }
-            }
-#pragma unroll
-            for (int b = 0; b < kQB; ++b) {
-                amax[b] = 0.0f; s2[b] = 0.0f; ssum[b] = 0;
-#pragma unroll
-                for (int e = 0; e < 16; ++e) { amax[b] = fmaxf(amax[b], fabsf(sd[b][e])); s2[b] += sd[b][e] * sd[b][e]; }
-            }
-            for (int o = 32; o > 0; o >>= 1) {
-#pragma unroll
-                for (int b = 0; b < kQB; ++b) {
-                    amax[b] = fmaxf(amax[b], __shfl_xor(amax[b], o));
-                    s2[b] += __shfl_xor(s2[b], o);
-                }
-            }
-#pragma unroll
-            for (int b = 0; b < kQB; ++b) {
-                const int qi = wid + 4 * (k0 + b);
-                const int qt = qi >> 5, j = qi & 31;
-                const float inv = (amax[b] > 0.0f) ? __fdiv_rn(127.0f, amax[b]) : 0.0f;
-                uint4 w;
-                quant_chunk(sd[b], inv, &ssum[b], &w);
-                if (own) {
-                    const int ks = lane >> 1, h = lane & 1;
-                    *(uint4*)(qs + ((ks * NQT + qt) * 64 + h * 32 + j) * 16) = w;
-                }
-            }
-            for (int o = 32; o > 0; o >>= 1) {
-#pragma unroll
-                for (int b = 0; b < kQB; ++b) ssum[b] += __shfl_xor(ssum[b], o);
-            }
-            if (lane == 0) {
-#pragma unroll
-                for (int b = 0; b < kQB; ++b) {
-                    const int qi = wid + 4 * (k0 + b);
-                    if (qi < mq) {
-                        s_s2[qi] = s2[b];
-                        s_hd[qi] = 0.5f * ((amax[b] > 0.0f) ? __fdiv_rn(amax[b], 127.0f) : 0.0f);
-                        s_ss[qi] = ssum[b];
-                        s_slot[qi] = pslot[qi];
-                        s_q[qi] = pq[qi];
-                    }
-                }
-            }
-        }
-        return;
+    const int nch = dp >> 4;                       // 16-byte chunks per row
+    const float rnch = 1.0f / (float)nch;          // u / nch below is exact: u < 2^16, gap >= 0.5/nch
+    const int units = QPI * nch;
+#pragma unroll 4
+    for (int u = tid; u < units; u += kThreads) {
+        const int qi = (int)(((float)u + 0.5f) * rnch);
+        const int c = u - qi * nch;
+        uint4 w = make_uint4(0, 0, 0, 0);
+        if (qi < mq) w = *(const uint4*)(qa.qint + (int64_t)pq[qi] * dp + 16 * c);
+        *(uint4*)(qs + qi * qstride + 16 * c) = w;
     }
-    // dp > 1024: two passes per query (max and norm, then quantise)
-    for (int qi = wid; qi < QPI; qi += 4) {
-        const int qt = qi >> 5, j = qi & 31;
-        if (qi >= mq) {
-            for (int c = lane; c < nch; c += 64) {
-                const int ks = c >> 1, h = c & 1;
-                *(uint4*)(qs + ((ks * NQT + qt) * 64 + h * 32 + j) * 16) = make_uint4(0, 0, 0, 0);
-            }
-            continue;
-        }
-        const int q = pq[qi];
-        const float* qv = qrot + (int64_t)q * dp;
-        float amax = 0.0f, s2 = 0.0f;
-        int ssum = 0;
-        for (int c = lane; c < nch; c += 64) {
-#pragma unroll
-            for (int e = 0; e < 16; e += 4) {
-                float4 a = *(const float4*)(qv + c * 16 + e);
-                float4 b = *(const float4*)(cv + c * 16 + e);
-                float d0 = a.x - b.x, d1 = a.y - b.y, d2 = a.z - b.z, d3 = a.w - b.w;
-                amax = fmaxf(amax, fmaxf(fmaxf(fabsf(d0), fabsf(d1)), fmaxf(fabsf(d2), fabsf(d3))));
-                s2 += d0 * d0; s2 += d1 * d1; s2 += d2 * d2; s2 += d3 * d3;
-            }
-        }
-        for (int o = 32; o > 0; o >>= 1) {
-            amax = fmaxf(amax, __shfl_xor(amax, o));
-            s2 += __shfl_xor(s2, o);
-        }
-        const float inv = (amax > 0.0f) ? __fdiv_rn(127.0f, amax) : 0.0f;
-        for (int c = lane; c < nch; c += 64) {
-            float sd[16];
-#pragma unroll
-            for (int e = 0; e < 16; e += 4) {
-                float4 a = *(const float4*)(qv + c * 16 + e);
-                float4 b = *(const float4*)(cv + c * 16 + e);
-                sd[e + 0] = a.x - b.x; sd[e + 1] = a.y - b.y; sd[e + 2] = a.z - b.z; sd[e + 3] = a.w - b.w;
-            }
-            uint4 w;
-            quant_chunk(sd, inv, &ssum, &w);
-            const int ks = c >> 1, h = c & 1;
-            *(uint4*)(qs + ((ks * NQT + qt) * 64 + h * 32 + j) * 16) = w;
-        }
-        for (int o = 32; o > 0; o >>= 1) ssum += __shfl_xor(ssum, o);
-        if (lane == 0) {
-            s_s2[qi] = s2;
-            s_hd[qi] = 0.5f * ((amax > 0.0f) ? __fdiv_rn(amax, 127.0f) : 0.0f);
-            s_ss[qi] = ssum;
-            s_slot[qi] = pslot[qi];
-            s_q[qi] = q;
-        }
+    if (tid < mq) {
+        const int q = pq[tid], slot = pslot[tid];
+        s_s2[tid] = qa.sdist[slot];
+        s_hd[tid] = qa.qhd[q];
+        s_ss[tid] = qa.qss[q];
+        s_slot[tid] = slot;
+        s_q[tid] = q;
     }
 }
 
@@ -341,8 +222,7 @@ template <int BITS, int KK>
 __global__ __launch_bounds__(kThreads, 2) void scanA_kernel(
     const uint8_t* __restrict__ codes, const int64_t* __restrict__ tile_off,
     const int64_t* __restrict__ list_off, const float2* __restrict__ fac,
-    const int64_t* __restrict__ ids, const float* __restrict__ cent_rot, int dp,
-    const float* __restrict__ qrot, const int32_t* __restrict__ pair_off,
+    const int64_t* __restrict__ ids, int dp, QArgs qa, const int32_t* __restrict__ pair_off,
     const int32_t* __restrict__ pair_q, const int32_t* __restrict__ pair_slot,
     const int32_t* __restrict__ item_off, const int32_t* __restrict__ list_order, int nlist, int vmax,
     int kk, float* __restrict__ res_est, int32_t* __restrict__ res_id)
@@ -357,8 +237,10 @@ __global__ __launch_bounds__(kThreads, 2) void scanA_kernel(
     const int n_items = item_off[nlist];
     const int nkb = dp / 64;
     int8_t* qs = (int8_t*)smem;
-    const v4i* qb = (const v4i*)qs;
+    const int qstride = dp + 16;
     const int64_t tile_bytes = (int64_t)4 * dp * BITS;
+    // B fragment of lane (h = lane/32, j = lane%32): query j, bytes 16h.. of each 32-dim block
+    const int8_t* qrow = qs + (lane & 31) * qstride + 16 * (lane >> 5);
 
     for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
         __syncthreads();                               // LDS of the previous item is free
@@ -371,8 +253,7 @@ __global__ __launch_bounds__(kThreads, 2) void scanA_kernel(
         if (tid < kQT) s_thr[tid] = 0xFFFFFFFFu;
         __syncthreads();
         const int l = s_item[0], p0 = s_item[1], mq = s_item[2];
-        load_queries<1>(qs, s_s2, s_hd, s_ss, s_slot, s_q, qrot, cent_rot + (int64_t)l * dp, dp,
-                        pair_q + p0, pair_slot + p0, mq, wid, lane);
+        load_queries<1>(qs, qstride, s_s2, s_hd, s_ss, s_slot, s_q, qa, dp, pair_q + p0, pair_slot + p0, mq, tid);
         __syncthreads();
 
         const int j = lane & 31;
@@ -398,8 +279,8 @@ __global__ __launch_bounds__(kThreads, 2) void scanA_kernel(
             for (int kb = 0; kb < nkb; ++kb) {
                 v4i a0, a1;
                 load_codes<BITS>(tp + (int64_t)kb * 256 * BITS, lane, a0, a1);
-                v4i b0 = qb[(kb * 2 + 0) * 64 + lane];
-                v4i b1 = qb[(kb * 2 + 1) * 64 + lane];
+                const v4i b0 = *(const v4i*)(qrow + 64 * kb);
+                const v4i b1 = *(const v4i*)(qrow + 64 * kb + 32);
                 acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, b0, acc, 0, 0, 0);
                 acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, b1, acc, 0, 0, 0);
             }
@@ -491,8 +372,7 @@ template <int BITS, int NQT, int PD>
 __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
     const uint8_t* __restrict__ codes, const int64_t* __restrict__ tile_off,
     const int64_t* __restrict__ list_off, const float2* __restrict__ fac,
-    const int64_t* __restrict__ ids, const float* __restrict__ cent_rot, int dp,
-    const float* __restrict__ qrot, const int32_t* __restrict__ pair_off,
+    const int64_t* __restrict__ ids, int dp, QArgs qa, const int32_t* __restrict__ pair_off,
     const int32_t* __restrict__ pair_q, const int32_t* __restrict__ pair_slot,
     const int32_t* __restrict__ item_off, const int32_t* __restrict__ list_order, int nlist,
     int kk, unsigned* __restrict__ tau_key, int32_t* __restrict__ gcnt,
@@ -533,8 +413,8 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
     if (s_item[4] >= n_items) break;
     const int l = s_item[0], p0 = s_item[1], mq = s_item[2], v0 = s_item[3];
     int8_t* qs = (int8_t*)smem;
-    load_queries<NQT>(qs, s_s2, s_hd, s_ss, s_slot, s_q, qrot, cent_rot + (int64_t)l * dp, dp,
-                      pair_q + p0, pair_slot + p0, mq, wid, lane);
+    const int qstride = dp + 16;
+    load_queries<NQT>(qs, qstride, s_s2, s_hd, s_ss, s_slot, s_q, qa, dp, pair_q + p0, pair_slot + p0, mq, tid);
     {   // factors of the item's members
         const int64_t fb = list_off[l] + v0;
         const int nf = min((int)(list_off[l + 1] - list_off[l]) - v0, kVch);
@@ -545,7 +425,9 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
     __syncthreads();
 
     const int nkb = dp / 64;
-    const v4i* qb = (const v4i*)qs;
+    // B fragment of lane (h = lane/32, j = lane%32) for query tile qt: query
+    // qt*32 + j, bytes 16h.. of each 32-dim block
+    const int8_t* qrow = qs + (lane & 31) * qstride + 16 * (lane >> 5);
     const int64_t tile_bytes = (int64_t)4 * dp * BITS;
     // members [v0, v0 + nl) of list l (v0 is a multiple of 64: whole tile pairs)
     const int64_t lbase = list_off[l] + v0;
@@ -614,8 +496,8 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
                 const int kb = kb0 + p;
 #pragma unroll
                 for (int qt = 0; qt < NQT; ++qt) {
-                    v4i b0 = qb[((2 * kb + 0) * NQT + qt) * 64 + lane];
-                    v4i b1 = qb[((2 * kb + 1) * NQT + qt) * 64 + lane];
+                    const v4i b0 = *(const v4i*)(qrow + qt * kQT * qstride + 64 * kb);
+                    const v4i b1 = *(const v4i*)(qrow + qt * kQT * qstride + 64 * kb + 32);
                     acc[0][qt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a00, b0, acc[0][qt], 0, 0, 0);
                     acc[1][qt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a10, b0, acc[1][qt], 0, 0, 0);
                     acc[0][qt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a01, b1, acc[0][qt], 0, 0, 0);
@@ -813,6 +695,83 @@ __global__ __launch_bounds__(256) void buf_select_kernel(int32_t* __restrict__ g
     }
 }
 
+// q' -> int8 once per query (symmetric: inv = 127/max|q'|, round half to
+// even, clamp to +-127), delta/2 and the sum of the int8 values; one wave per query
+__global__ __launch_bounds__(256) void qprep_kernel(const float* __restrict__ qrot, int64_t nq, int dp,
+                                                    int8_t* __restrict__ qint, float* __restrict__ qhd,
+                                                    int32_t* __restrict__ qss)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (q >= nq) return;
+    const float* qv = qrot + q * dp;
+    float amax = 0.0f;
+    for (int i = lane; i < dp; i += 64) amax = fmaxf(amax, fabsf(qv[i]));
+    for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o));
+    const float inv = (amax > 0.0f) ? __fdiv_rn(127.0f, amax) : 0.0f;
+    int ssum = 0;
+    for (int i = lane; i < dp; i += 64) {
+        int v = (int)rintf(qv[i] * inv);
+        v = max(-127, min(127, v));
+        qint[q * dp + i] = (int8_t)v;
+        ssum += v;
+    }
+    for (int o = 32; o > 0; o >>= 1) ssum += __shfl_xor(ssum, o);
+    if (lane == 0) {
+        qhd[q] = 0.5f * ((amax > 0.0f) ? __fdiv_rn(amax, 127.0f) : 0.0f);
+        qss[q] = ssum;
+    }
+}
+
+// ||q' - c'||^2 of every (query, probe) pair in FP32; one wave per pair
+// (used when the caller has no probe distances)
+__global__ __launch_bounds__(256) void pair_s2_kernel(const float* __restrict__ qrot,
+                                                      const float* __restrict__ cent_rot,
+                                                      const int32_t* __restrict__ probes, int64_t np, int nprobe,
+                                                      int nlist, int dp, float* __restrict__ sdist)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= np) return;
+    const int l = probes[i];
+    float s = 0.0f;
+    if (l >= 0 && l < nlist) {
+        const float* qv = qrot + (i / nprobe) * dp;
+        const float* cv = cent_rot + (int64_t)l * dp;
+        for (int d = lane; d < dp; d += 64) { const float t = qv[d] - cv[d]; s += t * t; }
+    }
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) sdist[i] = s;
+}
+
+// Scan factors of every member: (g_add, f_rescale) with
+// g_add = f_add - f_rescale * <y_bar, c'>, y_bar = y_u - (2^B-1)/2 and c' the
+// rotated centroid of the member's list, <y_bar, c'> accumulated in FP64.
+// Then est = g_add + ||s||^2 + f_rescale * <y_bar, q'> for s' = q' - c'.
+// codes_u: n x dp unpacked y_u in list order; one wave per member.
+__global__ __launch_bounds__(256) void scan_fac_kernel(const uint8_t* __restrict__ codes_u,
+                                                       const int64_t* __restrict__ list_off, int nlist,
+                                                       const float* __restrict__ cent_rot,
+                                                       const float2* __restrict__ fac, int64_t n, int dp,
+                                                       int bits, float2* __restrict__ sfac)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (v >= n) return;
+    int lo = 0, hi = nlist;                        // list of member v: last l with list_off[l] <= v
+    while (hi - lo > 1) { const int mid = (lo + hi) >> 1; if (list_off[mid] <= v) lo = mid; else hi = mid; }
+    const uint8_t* y = codes_u + v * dp;
+    const float* c = cent_rot + (int64_t)lo * dp;
+    const double half = 0.5 * (double)((1 << bits) - 1);
+    double acc = 0.0;
+    for (int d = lane; d < dp; d += 64) acc += ((double)y[d] - half) * (double)c[d];
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if (lane == 0) {
+        const float2 f = fac[v];
+        sfac[v] = make_float2((float)((double)f.x - (double)f.y * acc), f.y);
+    }
+}
+
 __global__ void tau_key_kernel(const float* __restrict__ tau_est, int64_t nq, int kk, unsigned* __restrict__ key)
 {
     int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -977,7 +936,7 @@ __global__ __launch_bounds__(256) void merge_kernel(const int32_t* __restrict__ 
 }
 
 struct ScanArgs {
-    const float* qrot;
+    QArgs qa;
     const int32_t *pair_off, *pair_q, *pair_slot, *item_off;
     int64_t grid;
     int vmax;
@@ -989,7 +948,7 @@ struct ScanArgs {
 template <int BITS, int KK>
 hipError_t launchA_t(const Index* ix, const ScanArgs& a, hipStream_t st)
 {
-    size_t sm = (size_t)ix->dp * kQT;
+    size_t sm = (size_t)(ix->dp + 16) * kQT;
     size_t mb = (size_t)4 * kQT * KK * 8;
     if (mb > sm) sm = mb;
     if (sm > 48 * 1024) {
@@ -998,8 +957,8 @@ hipError_t launchA_t(const Index* ix, const ScanArgs& a, hipStream_t st)
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL((scanA_kernel<BITS, KK>), dim3((unsigned)a.grid), dim3(kThreads), sm, st,
-                       ix->codes, ix->tile_off, ix->list_off, ix->fac, ix->ids, ix->cent_rot, ix->dp,
-                       a.qrot, a.pair_off, a.pair_q, a.pair_slot, a.item_off, ix->list_order, (int)ix->nlist,
+                       ix->codes, ix->tile_off, ix->list_off, ix->sfac, ix->ids, ix->dp,
+                       a.qa, a.pair_off, a.pair_q, a.pair_slot, a.item_off, ix->list_order, (int)ix->nlist,
                        a.vmax, a.kk, a.res_est, a.res_id);
     return hipGetLastError();
 }
@@ -1018,7 +977,7 @@ template <int BITS, int NQT, int PD>
 hipError_t launchB_t(const Index* ix, const ScanArgs& a, const BArgs& b, hipStream_t st)
 {
     const void* kern = (const void*)scanB_kernel<BITS, NQT, PD>;
-    const size_t sm = (size_t)ix->dp * kQT * NQT;
+    const size_t sm = (size_t)(ix->dp + 16) * kQT * NQT;
     if (sm > 48 * 1024) {
         hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
         if (e != hipSuccess) return e;
@@ -1031,8 +990,8 @@ hipError_t launchB_t(const Index* ix, const ScanArgs& a, const BArgs& b, hipStre
     if (e != hipSuccess) return e;
     const int64_t grid = std::min<int64_t>(a.grid, (int64_t)std::max(per_cu, 1) * std::max(ncu, 1));
     hipLaunchKernelGGL((scanB_kernel<BITS, NQT, PD>), dim3((unsigned)grid), dim3(kThreads), sm, st,
-                       ix->codes, ix->tile_off, ix->list_off, ix->fac, ix->ids, ix->cent_rot, ix->dp,
-                       a.qrot, a.pair_off, a.pair_q, a.pair_slot, a.item_off, ix->list_order, (int)ix->nlist,
+                       ix->codes, ix->tile_off, ix->list_off, ix->sfac, ix->ids, ix->dp,
+                       a.qa, a.pair_off, a.pair_q, a.pair_slot, a.item_off, ix->list_order, (int)ix->nlist,
                        a.kk, b.tau_key, b.gcnt, b.gbuf_e, b.gbuf_i, b.work);
     return hipGetLastError();
 }
@@ -1087,7 +1046,16 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
 
-size_t scan_workspace_bytes(int64_t nq, int nprobe, int64_t nlist, int kk)
+hipError_t launch_scan_fac(const uint8_t* codes_u, const int64_t* list_off, int64_t nlist, const float* cent_rot,
+                           const float2* fac, int64_t n, int dp, int bits, float2* sfac, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(scan_fac_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, codes_u, list_off,
+                       (int)nlist, cent_rot, fac, n, dp, bits, sfac);
+    return hipGetLastError();
+}
+
+size_t scan_workspace_bytes(int64_t nq, int nprobe, int64_t nlist, int kk, int dp)
 {
     const int64_t P = nq * nprobe;
     size_t b = 0;
@@ -1102,15 +1070,19 @@ size_t scan_workspace_bytes(int64_t nq, int nprobe, int64_t nlist, int kk)
     b += align256(sizeof(int32_t) * nq * kCapQ);
     b += align256(sizeof(float) * P * kk);                 // per-pair top-kk (pass A, fallback)
     b += align256(sizeof(int32_t) * P * kk);
+    b += align256((size_t)nq * dp);                        // int8 queries
+    b += 2 * align256(sizeof(float) * nq);                 // delta/2, sum of int8 values
+    b += align256(sizeof(float) * P);                      // ||s||^2 per pair
     return b;
 }
 
-int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, int nprobe, int kk,
-             int64_t* out_ids, float* out_est, void* ws, size_t ws_bytes, hipStream_t st)
+int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, const float* pdist, int nprobe,
+             int kk, int64_t* out_ids, float* out_est, void* ws, size_t ws_bytes, hipStream_t st)
 {
     const int64_t P = nq * nprobe;
     const int64_t nlist = ix->nlist;
-    if (ws_bytes < scan_workspace_bytes(nq, nprobe, nlist, kk))
+    const int dp = ix->dp;
+    if (ws_bytes < scan_workspace_bytes(nq, nprobe, nlist, kk, dp))
         return fail(ERQ_ENOMEM, "erq_scan: workspace too small");
     if (nq == 0) return ERQ_OK;
     char* w = (char*)ws;
@@ -1131,6 +1103,10 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, in
     int32_t* gbi = (int32_t*)take(sizeof(int32_t) * nq * kCapQ);
     float* res_est = (float*)take(sizeof(float) * P * kk);
     int32_t* res_id = (int32_t*)take(sizeof(int32_t) * P * kk);
+    int8_t* qint = (int8_t*)take((size_t)nq * dp);
+    float* qhd = (float*)take(sizeof(float) * nq);
+    int32_t* qss = (int32_t*)take(sizeof(int32_t) * nq);
+    float* sdist_ws = (float*)take(sizeof(float) * P);
 
     const int th = 256;
     const unsigned qblocks = (unsigned)((nq + th - 1) / th);
@@ -1161,12 +1137,21 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, in
     const int r1 = std::min(nprobe, kRankA);
     const int pr = prof_begin(PK_SCAN, st);
     hipError_t e = hipSuccess;
+    // queries to int8 once; ||s||^2 per pair from the probe distances, else computed
+    hipLaunchKernelGGL(qprep_kernel, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, st, qrot, nq, dp, qint, qhd, qss);
+    const float* sdist = pdist;
+    if (!sdist && P > 0) {
+        hipLaunchKernelGGL(pair_s2_kernel, dim3((unsigned)((P + 3) / 4)), dim3(256), 0, st, qrot, ix->cent_rot,
+                           probes, P, nprobe, (int)nlist, dp, sdist_ws);
+        sdist = sdist_ws;
+    }
+    const QArgs qa{qint, qhd, qss, sdist};
     zero(gcnt, nq);
     // pass A: the first bound, from the first kVecA members of the r1 nearest probed lists
     int pp = prof_begin(PK_SCAN_A, st);
     e = build_pairs(0, r1, nullptr, kQT, 0);
     if (e == hipSuccess) {
-        ScanArgs a{qrot, poff, pq, ps, ioff, std::min<int64_t>((nq * r1 + kQT - 1) / kQT + nlist, 8192), kVecA, kk,
+        ScanArgs a{qa, poff, pq, ps, ioff, std::min<int64_t>((nq * r1 + kQT - 1) / kQT + nlist, 8192), kVecA, kk,
                    res_est, res_id};
         e = launchA(ix, a, st);
     }
@@ -1184,7 +1169,7 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, in
         hipError_t er = build_pairs(rlo, rhi, qmask, qpiB, kVch);
         if (er != hipSuccess) return er;
         zero(work, 1);
-        ScanArgs b{qrot, poff, pq, ps, ioff, gridB, 0, kk, nullptr, nullptr};
+        ScanArgs b{qa, poff, pq, ps, ioff, gridB, 0, kk, nullptr, nullptr};
         BArgs bb{tkey, gcnt, gbe, gbi, work};
         const int rec = prof_begin(PK_SCAN_B, st);   // one record per pass-B launch
         er = launchB(ix, b, bb, st);
@@ -1206,7 +1191,7 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, in
     if (e == hipSuccess) e = select(1, out_ids, out_est);
     if (e == hipSuccess) e = build_pairs(0, nprobe, ovf, kQT, 0);
     if (e == hipSuccess) {
-        ScanArgs c{qrot, poff, pq, ps, ioff, std::min<int64_t>((P + kQT - 1) / kQT + nlist, 4096), 0x7FFFFFFF, kk,
+        ScanArgs c{qa, poff, pq, ps, ioff, std::min<int64_t>((P + kQT - 1) / kQT + nlist, 4096), 0x7FFFFFFF, kk,
                    res_est, res_id};
         e = launchA(ix, c, st);
     }
