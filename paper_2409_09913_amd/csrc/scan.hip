@@ -11,12 +11,12 @@
 //  1. pair build: (query, probe) pairs grouped by list (count, scan,
 //     scatter) for a range of probe ranks; work items are (list, tile of its
 //     queries[, chunk of kVch members]), longest list first.
-//  2. pass A (a bound): exact top-kk of the first kVecA members of the
-//     kRankA nearest probed lists, with sorted per-lane register lists; per
-//     query, the kk-th best of these estimates, tau_q.  Any subset of a
-//     query's candidates gives a valid bound: every member of the final
-//     top-kk has est <= tau_q.
-//  3. pass B (the scan) in two rounds of probe rank, [0, 2 kRankA) and the
+//  2. first bound: every estimate of the first kDenseV members of the kDenseR
+//     nearest probed lists is written to fixed slots of the query's
+//     candidate buffer; tau_q is the kk-th best of them (radix select).  Any
+//     subset of a query's candidates gives a valid bound: every member of the
+//     final top-kk has est <= tau_q.  The buffer is then emptied.
+//  3. pass B (the scan) in two rounds of probe rank, [0, kRound1) and the
 //     rest: 64 vectors x 64 queries per wave step.  Estimates above tau_q are
 //     dropped with one compare; the rest are staged in a per-query LDS
 //     buffer (spilling straight to global memory when it is full) and
@@ -39,8 +39,9 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kQT = 32;        // queries per MFMA column tile
 constexpr int kCapB = 32;      // per-query survivor buffer of a pass-B item (LDS)
-constexpr int kRankA = 8;      // pass A: nearest probes per query ...
-constexpr int kVecA = 128;     // ... and members per list used for the bound
+constexpr int kDenseR = 2;     // first bound: nearest probes per query ...
+constexpr int kDenseV = 256;   // ... and members per list (all estimates kept)
+constexpr int kRound1 = 16;    // pass B, round 1: probe ranks [0, kRound1)
 constexpr int kCapQ = 4096;    // candidate buffer per query (HBM)
 constexpr int kVch = 1024;     // pass-B members per item (long lists are split)
 
@@ -376,8 +377,12 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
     const int32_t* __restrict__ pair_q, const int32_t* __restrict__ pair_slot,
     const int32_t* __restrict__ item_off, const int32_t* __restrict__ list_order, int nlist,
     int kk, unsigned* __restrict__ tau_key, int32_t* __restrict__ gcnt,
-    float* __restrict__ gbuf_e, int32_t* __restrict__ gbuf_i, int32_t* __restrict__ work)
+    float* __restrict__ gbuf_e, int32_t* __restrict__ gbuf_i, int32_t* __restrict__ work,
+    int vch, int dense, int nprobe)
 {
+    // dense != 0 (first bound): only the first kDenseV members of each list,
+    // no bound test, every estimate written to slot rank*kDenseV + member of
+    // the query's buffer (rank = probe rank of the pair, < kDenseR)
     constexpr int QPI = kQT * NQT;
     extern __shared__ __align__(16) char smem[];
     __shared__ float s_s2[QPI], s_hd[QPI];
@@ -401,11 +406,11 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
             int l, t;
             decode_item(item, item_off, list_order, nlist, &l, &t);
             const int nv = (int)(list_off[l + 1] - list_off[l]);
-            const int nvc = max(1, (nv + kVch - 1) / kVch);
+            const int nvc = (vch > 0) ? max(1, (nv + vch - 1) / vch) : 1;
             const int qtile = t / nvc, vc = t - qtile * nvc;
             const int p0 = pair_off[l] + qtile * QPI;
             s_item[0] = l; s_item[1] = p0; s_item[2] = min(QPI, pair_off[l + 1] - p0);
-            s_item[3] = vc * kVch;
+            s_item[3] = vc * vch;
         }
     }
     if (tid < QPI) s_cnt[tid] = 0;
@@ -417,7 +422,7 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
     load_queries<NQT>(qs, qstride, s_s2, s_hd, s_ss, s_slot, s_q, qa, dp, pair_q + p0, pair_slot + p0, mq, tid);
     {   // factors of the item's members
         const int64_t fb = list_off[l] + v0;
-        const int nf = min((int)(list_off[l + 1] - list_off[l]) - v0, kVch);
+        const int nf = min((int)(list_off[l + 1] - list_off[l]) - v0, dense ? kDenseV : kVch);
         for (int t = tid; t < nf; t += kThreads) s_fac[t] = fac[fb + t];
     }
     __syncthreads();
@@ -431,7 +436,7 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
     const int64_t tile_bytes = (int64_t)4 * dp * BITS;
     // members [v0, v0 + nl) of list l (v0 is a multiple of 64: whole tile pairs)
     const int64_t lbase = list_off[l] + v0;
-    const int nl = min((int)(list_off[l + 1] - list_off[l]) - v0, kVch);
+    const int nl = min((int)(list_off[l + 1] - list_off[l]) - v0, dense ? kDenseV : kVch);
     const int ntile = (nl + 31) >> 5;
     const int ngroup = (ntile + 1) >> 1;
     const int64_t tbase = tile_off[l] + (v0 >> 5);
@@ -440,6 +445,7 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
     // and are excluded from the pass test by qok, not by their estimate.
     float qs2[NQT], qhd[NQT], qtau[NQT];
     int qss[NQT];
+    int64_t qslot0[NQT];
     bool qok[NQT];
 #pragma unroll
     for (int qt = 0; qt < NQT; ++qt) {
@@ -449,6 +455,14 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
         qhd[qt] = qok[qt] ? s_hd[qi] : 0.0f;
         qss[qt] = qok[qt] ? s_ss[qi] : 0;
         qtau[qt] = qok[qt] ? key2f(s_tau[qi]) : 0.0f;
+        // dense mode: first buffer slot of this pair, q * kCapQ + rank * kDenseV
+        int64_t sl = 0;
+        if (dense && qok[qt]) {
+            const int slot = s_slot[qi];
+            const int q = s_q[qi];
+            sl = (int64_t)q * kCapQ + (slot - q * nprobe) * kDenseV;
+        }
+        qslot0[qt] = sl;
     }
 
     // The wave's groups g = wid + 4 i (two tiles each) are walked as one
@@ -522,6 +536,13 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
 #pragma unroll
                     for (int qt = 0; qt < NQT; ++qt) {
                         const float est = estimate<BITS>(f, acc[a][qt][r], qs2[qt], qhd[qt], qss[qt]);
+                        if (dense) {                        // first bound: keep every estimate
+                            if (ok && qok[qt]) {
+                                gbuf_e[(int64_t)qslot0[qt] + v] = est;
+                                gbuf_i[(int64_t)qslot0[qt] + v] = (int)ids[lbase + v];
+                            }
+                            continue;
+                        }
                         const bool pass = ok && qok[qt] && est <= qtau[qt];
                         if (__any(pass)) {
                             if (pass) {
@@ -772,11 +793,19 @@ __global__ __launch_bounds__(256) void scan_fac_kernel(const uint8_t* __restrict
     }
 }
 
-__global__ void tau_key_kernel(const float* __restrict__ tau_est, int64_t nq, int kk, unsigned* __restrict__ key)
+// before the first bound: slots [0, kDenseR*kDenseV) of every query's buffer
+// hold +inf, the count covers them, and the bound is +inf
+__global__ void fill_dense_kernel(float* __restrict__ gbuf_e, int64_t nq, int32_t* __restrict__ gcnt,
+                                  unsigned* __restrict__ tau_key)
 {
-    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q < nq) key[q] = f2key(tau_est[q * kk + kk - 1]);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    constexpr int W = kDenseR * kDenseV;
+    if (i >= nq * W) return;
+    const int64_t q = i / W;
+    gbuf_e[q * kCapQ + (i - q * W)] = __builtin_huge_valf();
+    if (i - q * W == 0) { gcnt[q] = W; tau_key[q] = 0xFFFFFFFFu; }
 }
+
 
 // ---------------------------------------------------------------------------
 __global__ void copy_i32_kernel(const int32_t* __restrict__ src, int32_t* __restrict__ dst, int64_t n) {
@@ -833,6 +862,69 @@ __device__ inline int items_of(const int32_t* cnt, const int64_t* list_off, int 
     if (vch <= 0) return tiles;
     const int nv = (int)(list_off[l + 1] - list_off[l]);
     return tiles * ((nv + vch - 1) / vch);
+}
+
+// Counting sort of the selected pairs by list without global atomics, for
+// nlist <= kHistMax: block b of kPairBlocks takes a contiguous range of pairs,
+// counts them per list in LDS (cnt2[b][l]); a per-list exclusive prefix over
+// the blocks gives every block its first slot in each list; each block then
+// places its pairs with LDS atomics.
+constexpr int kPairBlocks = 128;
+constexpr int kHistMax = 16384;
+
+__global__ __launch_bounds__(1024) void pair_hist_kernel(const int32_t* __restrict__ probes, int64_t np, int nprobe,
+                                                         int nlist, int rlo, int rhi,
+                                                         const int32_t* __restrict__ qmask,
+                                                         int32_t* __restrict__ cnt2)
+{
+    __shared__ int hist[kHistMax];
+    const int b = blockIdx.x;
+    for (int l = threadIdx.x; l < nlist; l += blockDim.x) hist[l] = 0;
+    __syncthreads();
+    const int64_t chunk = (np + gridDim.x - 1) / gridDim.x;
+    const int64_t i0 = b * chunk, i1 = min(np, i0 + chunk);
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+        int l; int64_t q;
+        if (pair_sel(probes, i, nprobe, nlist, rlo, rhi, qmask, &l, &q)) atomicAdd(&hist[l], 1);
+    }
+    __syncthreads();
+    for (int l = threadIdx.x; l < nlist; l += blockDim.x) cnt2[(int64_t)b * nlist + l] = hist[l];
+}
+
+// per list: exclusive prefix of cnt2 over the blocks (in place) and the total
+__global__ void pair_colsum_kernel(int32_t* __restrict__ cnt2, int nblocks, int nlist, int32_t* __restrict__ cnt)
+{
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= nlist) return;
+    int run = 0;
+    for (int b = 0; b < nblocks; ++b) {
+        const int v = cnt2[(int64_t)b * nlist + l];
+        cnt2[(int64_t)b * nlist + l] = run;
+        run += v;
+    }
+    cnt[l] = run;
+}
+
+__global__ __launch_bounds__(1024) void pair_place_kernel(const int32_t* __restrict__ probes, int64_t np, int nprobe,
+                                                          int nlist, int rlo, int rhi,
+                                                          const int32_t* __restrict__ qmask,
+                                                          const int32_t* __restrict__ cnt2,
+                                                          const int32_t* __restrict__ off,
+                                                          int32_t* __restrict__ pq, int32_t* __restrict__ pslot)
+{
+    __shared__ int base[kHistMax];
+    const int b = blockIdx.x;
+    for (int l = threadIdx.x; l < nlist; l += blockDim.x) base[l] = off[l] + cnt2[(int64_t)b * nlist + l];
+    __syncthreads();
+    const int64_t chunk = (np + gridDim.x - 1) / gridDim.x;
+    const int64_t i0 = b * chunk, i1 = min(np, i0 + chunk);
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+        int l; int64_t q;
+        if (!pair_sel(probes, i, nprobe, nlist, rlo, rhi, qmask, &l, &q)) continue;
+        const int pos = atomicAdd(&base[l], 1);
+        pq[pos] = (int32_t)q;
+        pslot[pos] = (int32_t)i;
+    }
 }
 
 // single workgroup: pair_off (by list id) and item_off (by rank of list_order)
@@ -971,7 +1063,8 @@ hipError_t launchA_b(const Index* ix, const ScanArgs& a, hipStream_t st)
     return launchA_t<BITS, 32>(ix, a, st);
 }
 
-struct BArgs { unsigned* tau_key; int32_t* gcnt; float* gbuf_e; int32_t* gbuf_i; int32_t* work; };
+struct BArgs { unsigned* tau_key; int32_t* gcnt; float* gbuf_e; int32_t* gbuf_i; int32_t* work;
+               int vch, dense, nprobe; };
 
 template <int BITS, int NQT, int PD>
 hipError_t launchB_t(const Index* ix, const ScanArgs& a, const BArgs& b, hipStream_t st)
@@ -992,7 +1085,7 @@ hipError_t launchB_t(const Index* ix, const ScanArgs& a, const BArgs& b, hipStre
     hipLaunchKernelGGL((scanB_kernel<BITS, NQT, PD>), dim3((unsigned)grid), dim3(kThreads), sm, st,
                        ix->codes, ix->tile_off, ix->list_off, ix->sfac, ix->ids, ix->dp,
                        a.qa, a.pair_off, a.pair_q, a.pair_slot, a.item_off, ix->list_order, (int)ix->nlist,
-                       a.kk, b.tau_key, b.gcnt, b.gbuf_e, b.gbuf_i, b.work);
+                       a.kk, b.tau_key, b.gcnt, b.gbuf_e, b.gbuf_i, b.work, b.vch, b.dense, b.nprobe);
     return hipGetLastError();
 }
 
@@ -1060,9 +1153,9 @@ size_t scan_workspace_bytes(int64_t nq, int nprobe, int64_t nlist, int kk, int d
     const int64_t P = nq * nprobe;
     size_t b = 0;
     b += 2 * align256(sizeof(int32_t) * nlist);            // cnt, fill
+    b += align256(sizeof(int32_t) * kPairBlocks * nlist);  // per-block list counts
     b += 2 * align256(sizeof(int32_t) * (nlist + 1));      // pair / item offsets
     b += 2 * align256(sizeof(int32_t) * P);                // pair table (query, slot)
-    b += align256(sizeof(float) * nq * kk);                // pass-A top-kk per query
     b += align256(sizeof(unsigned) * nq);                  // bound per query
     b += 3 * align256(sizeof(int32_t) * nq);               // candidate counts, counts before a round, flags
     b += align256(sizeof(int32_t));                        // pass-B work counter
@@ -1089,11 +1182,11 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, co
     auto take = [&](size_t bytes) { char* p = w; w += align256(bytes); return p; };
     int32_t* cnt = (int32_t*)take(sizeof(int32_t) * nlist);
     int32_t* fill = (int32_t*)take(sizeof(int32_t) * nlist);
+    int32_t* cnt2 = (int32_t*)take(sizeof(int32_t) * kPairBlocks * nlist);
     int32_t* poff = (int32_t*)take(sizeof(int32_t) * (nlist + 1));
     int32_t* ioff = (int32_t*)take(sizeof(int32_t) * (nlist + 1));
     int32_t* pq = (int32_t*)take(sizeof(int32_t) * P);
     int32_t* ps = (int32_t*)take(sizeof(int32_t) * P);
-    float* tau = (float*)take(sizeof(float) * nq * kk);
     unsigned* tkey = (unsigned*)take(sizeof(unsigned) * nq);
     int32_t* gcnt = (int32_t*)take(sizeof(int32_t) * nq);
     int32_t* gprev = (int32_t*)take(sizeof(int32_t) * nq);
@@ -1116,16 +1209,28 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, co
     const unsigned pblocks = (unsigned)((P + th - 1) / th);
     // pair table of the probes with rank in [rlo, rhi) (of flagged queries with
     // qmask), grouped by list; items split lists into chunks of vch members when vch > 0
+    const bool lds_sort = nlist <= kHistMax;
     auto build_pairs = [&](int rlo, int rhi, const int32_t* qmask, int qpi, int vch) {
-        zero(cnt, nlist); zero(fill, nlist);
-        if (P > 0)
-            hipLaunchKernelGGL(pair_count_kernel, dim3(pblocks), dim3(th), 0, st, probes, P, nprobe, (int)nlist,
-                               rlo, rhi, qmask, cnt);
+        if (lds_sort) {
+            hipLaunchKernelGGL(pair_hist_kernel, dim3(kPairBlocks), dim3(1024), 0, st, probes, P, nprobe,
+                               (int)nlist, rlo, rhi, qmask, cnt2);
+            hipLaunchKernelGGL(pair_colsum_kernel, dim3((unsigned)((nlist + th - 1) / th)), dim3(th), 0, st, cnt2,
+                               kPairBlocks, (int)nlist, cnt);
+        } else {
+            zero(cnt, nlist); zero(fill, nlist);
+            if (P > 0)
+                hipLaunchKernelGGL(pair_count_kernel, dim3(pblocks), dim3(th), 0, st, probes, P, nprobe, (int)nlist,
+                                   rlo, rhi, qmask, cnt);
+        }
         hipLaunchKernelGGL(pair_scan_kernel, dim3(1), dim3(1024), 0, st, cnt, (int)nlist, ix->list_order,
                            ix->list_off, qpi, vch, poff, ioff);
-        if (P > 0)
+        if (lds_sort) {
+            hipLaunchKernelGGL(pair_place_kernel, dim3(kPairBlocks), dim3(1024), 0, st, probes, P, nprobe,
+                               (int)nlist, rlo, rhi, qmask, cnt2, poff, pq, ps);
+        } else if (P > 0) {
             hipLaunchKernelGGL(pair_scatter_kernel, dim3(pblocks), dim3(th), 0, st, probes, P, nprobe, (int)nlist,
                                rlo, rhi, qmask, poff, fill, pq, ps);
+        }
         return hipGetLastError();
     };
     auto select = [&](int mode, int64_t* oi, float* oe) {
@@ -1134,7 +1239,6 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, co
         return hipGetLastError();
     };
     const int qpiB = (ix->dp <= 768) ? 2 * kQT : kQT;
-    const int r1 = std::min(nprobe, kRankA);
     const int pr = prof_begin(PK_SCAN, st);
     hipError_t e = hipSuccess;
     // queries to int8 once; ||s||^2 per pair from the probe distances, else computed
@@ -1146,48 +1250,43 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, co
         sdist = sdist_ws;
     }
     const QArgs qa{qint, qhd, qss, sdist};
-    zero(gcnt, nq);
-    // pass A: the first bound, from the first kVecA members of the r1 nearest probed lists
-    int pp = prof_begin(PK_SCAN_A, st);
-    e = build_pairs(0, r1, nullptr, kQT, 0);
-    if (e == hipSuccess) {
-        ScanArgs a{qa, poff, pq, ps, ioff, std::min<int64_t>((nq * r1 + kQT - 1) / kQT + nlist, 8192), kVecA, kk,
-                   res_est, res_id};
-        e = launchA(ix, a, st);
-    }
-    if (e == hipSuccess) {
-        hipLaunchKernelGGL(merge_kernel, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, st, probes, nq, nprobe,
-                           (int)nlist, kk, r1, (const int32_t*)nullptr, res_est, res_id, (int64_t*)nullptr, tau);
-        hipLaunchKernelGGL(tau_key_kernel, dim3(qblocks), dim3(th), 0, st, tau, nq, kk, tkey);
-        e = hipGetLastError();
-    }
-    prof_end(pp, st);
-    // pass B in rounds of increasing probe rank
-    const int bounds[3] = {0, std::min(nprobe, 2 * kRankA), nprobe};
     const int64_t gridB = 1 << 20;                    // capped at the resident blocks
-    auto scan_round = [&](int rlo, int rhi, const int32_t* qmask) {
-        hipError_t er = build_pairs(rlo, rhi, qmask, qpiB, kVch);
+    // a pass-B launch over the pairs of probe ranks [rlo, rhi) (of flagged
+    // queries with qmask); dense = the first-bound mode
+    auto scan_round = [&](int rlo, int rhi, const int32_t* qmask, int dense) {
+        hipError_t er = build_pairs(rlo, rhi, qmask, qpiB, dense ? 0 : kVch);
         if (er != hipSuccess) return er;
         zero(work, 1);
         ScanArgs b{qa, poff, pq, ps, ioff, gridB, 0, kk, nullptr, nullptr};
-        BArgs bb{tkey, gcnt, gbe, gbi, work};
-        const int rec = prof_begin(PK_SCAN_B, st);   // one record per pass-B launch
+        BArgs bb{tkey, gcnt, gbe, gbi, work, dense ? 0 : kVch, dense, nprobe};
+        const int rec = prof_begin(dense ? PK_SCAN_A : PK_SCAN_B, st);   // one record per launch
         er = launchB(ix, b, bb, st);
         prof_end(rec, st);
         return er;
     };
+    // first bound: all estimates of the first kDenseV members of the r0
+    // nearest lists, in fixed buffer slots (+inf where a list is shorter)
+    const int r0 = std::min(nprobe, kDenseR);
+    hipLaunchKernelGGL(fill_dense_kernel, dim3((unsigned)((nq * kDenseR * kDenseV + th - 1) / th)), dim3(th), 0, st,
+                       gbe, nq, gcnt, tkey);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = scan_round(0, r0, nullptr, 1);
+    if (e == hipSuccess) e = select(0, nullptr, nullptr);
+    zero(gcnt, nq);                                  // the dense entries are found again by the rounds
+    // pass B in rounds of increasing probe rank
+    const int bounds[3] = {0, std::min(nprobe, kRound1), nprobe};
     for (int r = 0; r < 2 && e == hipSuccess; ++r) {
         const int rlo = bounds[r], rhi = bounds[r + 1];
         if (rhi <= rlo) continue;
         hipLaunchKernelGGL(copy_i32_kernel, dim3(qblocks), dim3(th), 0, st, gcnt, gprev, nq);
-        e = scan_round(rlo, rhi, nullptr);
+        e = scan_round(rlo, rhi, nullptr, 0);
         // queries that overflowed: back to their count before the round, tighter bound, rescan the round
         if (e == hipSuccess) e = select(2, nullptr, nullptr);
-        if (e == hipSuccess) e = scan_round(rlo, rhi, ovf);
+        if (e == hipSuccess) e = scan_round(rlo, rhi, ovf, 0);
         if (e == hipSuccess && rhi < nprobe) e = select(0, nullptr, nullptr);
     }
     // exact top-kk per query; queries whose buffer still overflowed: pair by pair
-    pp = prof_begin(PK_SCAN_C, st);
+    const int pc = prof_begin(PK_SCAN_C, st);
     if (e == hipSuccess) e = select(1, out_ids, out_est);
     if (e == hipSuccess) e = build_pairs(0, nprobe, ovf, kQT, 0);
     if (e == hipSuccess) {
@@ -1200,7 +1299,7 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, co
                            (int)nlist, kk, nprobe, ovf, res_est, res_id, out_ids, out_est);
         e = hipGetLastError();
     }
-    prof_end(pp, st);
+    prof_end(pc, st);
     prof_end(pr, st);
     if (e != hipSuccess) return fail(ERQ_EDEVICE, std::string("scan launch: ") + hipGetErrorString(e));
     prof_note_redo(poff + nlist, st);       // pairs rescanned by the fallback
