@@ -464,6 +464,20 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
         }
         qslot0[qt] = sl;
     }
+    // Epilogue constants per column: est = (g + fr * (H2 * acc + HC)) + s2 with
+    // H2 = 2 delta/2 and HC = delta/2 * corr * sum(q_int); the bound test
+    // compares the part before + s2 with AQ = tau - s2 rounded up by a margin
+    // above the rounding of both subtractions, so it never drops a candidate
+    // whose final estimate is <= tau.  Columns without a query take AQ = -inf.
+    constexpr int corr = 2 * (BITS == 8 ? 128 : 0) - ((1 << BITS) - 1);
+    float cH2[NQT], cHC[NQT], cAQ[NQT];
+#pragma unroll
+    for (int qt = 0; qt < NQT; ++qt) {
+        cH2[qt] = 2.0f * qhd[qt];
+        cHC[qt] = qhd[qt] * (float)(corr * qss[qt]);
+        const float aq = qtau[qt] - qs2[qt];
+        cAQ[qt] = qok[qt] ? aq + (fabsf(qtau[qt]) + fabsf(qs2[qt])) * 0x1p-20f : -__builtin_huge_valf();
+    }
 
     // The wave's groups g = wid + 4 i (two tiles each) are walked as one
     // sequence of K-steps (group, kb).  The packed codes of step s + PD are
@@ -476,16 +490,24 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
     const int total = ngw * nkb;
     if (total > 0) {
         uint32_t ring[PD][2 * BITS];
-        int pg = 0, pkb = 0, pleft = total;          // next step to load
+        // next step to load: group tile t0 at p0 (second tile p0 + d1, or p0
+        // itself for an odd last tile), K-block offset koff
+        int t0 = 2 * wid, pleft = total;
+        const uint8_t* p0 = codes + (tbase + t0) * tile_bytes;
+        int64_t d1 = (t0 + 1 < ntile) ? tile_bytes : 0;
+        int64_t koff = 0;
         auto load_step = [&](uint32_t* d) {
-            const int t0 = 2 * (wid + 4 * pg);
-            const int t1 = (t0 + 1 < ntile) ? t0 + 1 : t0;
-            const int64_t off = (int64_t)pkb * 256 * BITS;
-            load_raw<BITS>(codes + (tbase + t0) * tile_bytes + off, lane, d);
-            load_raw<BITS>(codes + (tbase + t1) * tile_bytes + off, lane, d + BITS);
+            load_raw<BITS>(p0 + koff, lane, d);
+            load_raw<BITS>(p0 + d1 + koff, lane, d + BITS);
             if (pleft > 1) {
                 --pleft;
-                if (++pkb == nkb) { pkb = 0; ++pg; }
+                koff += 256 * BITS;
+                if (koff == tile_bytes) {
+                    koff = 0;
+                    t0 += 8;
+                    p0 += 8 * tile_bytes;
+                    d1 = (t0 + 1 < ntile) ? tile_bytes : 0;
+                }
             }
         };
 #pragma unroll
@@ -533,32 +555,42 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
                     const int v = tt * 32 + out_row(lane, r);
                     const bool ok = v < nl;
                     const float2 f = s_fac[ok ? v : 0];
+                    const float gv = ok ? f.x : __builtin_nanf("");   // NaN never passes
+                    float e[NQT];
+                    bool pass[NQT], anyp = false;
 #pragma unroll
                     for (int qt = 0; qt < NQT; ++qt) {
-                        const float est = estimate<BITS>(f, acc[a][qt][r], qs2[qt], qhd[qt], qss[qt]);
-                        if (dense) {                        // first bound: keep every estimate
+                        const float y = __fmaf_rn(cH2[qt], (float)acc[a][qt][r], cHC[qt]);
+                        e[qt] = __fmaf_rn(f.y, y, gv);
+                        pass[qt] = e[qt] <= cAQ[qt];
+                        anyp = anyp || pass[qt];
+                    }
+                    if (dense) {                            // first bound: keep every estimate
+#pragma unroll
+                        for (int qt = 0; qt < NQT; ++qt) {
                             if (ok && qok[qt]) {
-                                gbuf_e[(int64_t)qslot0[qt] + v] = est;
-                                gbuf_i[(int64_t)qslot0[qt] + v] = (int)ids[lbase + v];
+                                gbuf_e[qslot0[qt] + v] = e[qt] + qs2[qt];
+                                gbuf_i[qslot0[qt] + v] = (int)ids[lbase + v];
                             }
-                            continue;
                         }
-                        const bool pass = ok && qok[qt] && est <= qtau[qt];
-                        if (__any(pass)) {
-                            if (pass) {
-                                const int qi = qt * kQT + j;
-                                const int id = (int)ids[lbase + v];
-                                const int pos = atomicAdd(&s_cnt[qi], 1);
-                                if (pos < kCapB) {
-                                    s_be[qi][pos] = est; s_bi[qi][pos] = id;
-                                } else {                       // stage full: straight to HBM
-                                    const int q = s_q[qi];
-                                    const int gp = atomicAdd(&gcnt[q], 1);
-                                    if (gp < kCapQ) {
-                                        gbuf_e[(int64_t)q * kCapQ + gp] = est;
-                                        gbuf_i[(int64_t)q * kCapQ + gp] = id;
-                                    }
-                                }
+                        continue;
+                    }
+                    if (!__any(anyp)) continue;
+#pragma unroll
+                    for (int qt = 0; qt < NQT; ++qt) {
+                        if (!pass[qt]) continue;
+                        const float est = e[qt] + qs2[qt];
+                        const int qi = qt * kQT + j;
+                        const int id = (int)ids[lbase + v];
+                        const int pos = atomicAdd(&s_cnt[qi], 1);
+                        if (pos < kCapB) {
+                            s_be[qi][pos] = est; s_bi[qi][pos] = id;
+                        } else {                            // stage full: straight to HBM
+                            const int q = s_q[qi];
+                            const int gp = atomicAdd(&gcnt[q], 1);
+                            if (gp < kCapQ) {
+                                gbuf_e[(int64_t)q * kCapQ + gp] = est;
+                                gbuf_i[(int64_t)q * kCapQ + gp] = id;
                             }
                         }
                     }
@@ -891,18 +923,34 @@ __global__ __launch_bounds__(1024) void pair_hist_kernel(const int32_t* __restri
     for (int l = threadIdx.x; l < nlist; l += blockDim.x) cnt2[(int64_t)b * nlist + l] = hist[l];
 }
 
-// per list: exclusive prefix of cnt2 over the blocks (in place) and the total
-__global__ void pair_colsum_kernel(int32_t* __restrict__ cnt2, int nblocks, int nlist, int32_t* __restrict__ cnt)
+// per list: exclusive prefix of cnt2 over the blocks (in place) and the total.
+// 64 lists per workgroup; thread (list, quarter) loads its quarter of the
+// blocks at once, quarter sums are combined in LDS
+__global__ __launch_bounds__(256) void pair_colsum_kernel(int32_t* __restrict__ cnt2, int nlist,
+                                                          int32_t* __restrict__ cnt)
 {
-    const int l = blockIdx.x * blockDim.x + threadIdx.x;
-    if (l >= nlist) return;
-    int run = 0;
-    for (int b = 0; b < nblocks; ++b) {
-        const int v = cnt2[(int64_t)b * nlist + l];
-        cnt2[(int64_t)b * nlist + l] = run;
-        run += v;
+    constexpr int BQ = kPairBlocks / 4;
+    __shared__ int part[4][64];
+    const int lq = threadIdx.x & 63, bq = threadIdx.x >> 6;
+    const int l = blockIdx.x * 64 + lq;
+    int v[BQ];
+    int sum = 0;
+#pragma unroll
+    for (int t = 0; t < BQ; ++t) {
+        v[t] = (l < nlist) ? cnt2[(int64_t)(bq * BQ + t) * nlist + l] : 0;
+        sum += v[t];
     }
-    cnt[l] = run;
+    part[bq][lq] = sum;
+    __syncthreads();
+    int run = 0;
+    for (int w = 0; w < bq; ++w) run += part[w][lq];
+    if (l >= nlist) return;
+#pragma unroll
+    for (int t = 0; t < BQ; ++t) {
+        cnt2[(int64_t)(bq * BQ + t) * nlist + l] = run;
+        run += v[t];
+    }
+    if (bq == 3) cnt[l] = run;
 }
 
 __global__ __launch_bounds__(1024) void pair_place_kernel(const int32_t* __restrict__ probes, int64_t np, int nprobe,
@@ -1089,11 +1137,15 @@ hipError_t launchB_t(const Index* ix, const ScanArgs& a, const BArgs& b, hipStre
     return hipGetLastError();
 }
 
-// ring depth: the largest of 4, 3, 2, 1 that divides the K-steps per group
+// ring depth: 6 when it divides the K-steps per group and the raw words are
+// small (B <= 4), else the largest of 4, 3, 2, 1 that divides them
 template <int BITS, int NQT>
 hipError_t launchB_n(const Index* ix, const ScanArgs& a, const BArgs& b, hipStream_t st)
 {
     const int nkb = ix->dp / 64;
+    if constexpr (BITS <= 4) {
+        if (nkb % 6 == 0) return launchB_t<BITS, NQT, 6>(ix, a, b, st);
+    }
     if (nkb % 4 == 0) return launchB_t<BITS, NQT, 4>(ix, a, b, st);
     if (nkb % 3 == 0) return launchB_t<BITS, NQT, 3>(ix, a, b, st);
     if (nkb % 2 == 0) return launchB_t<BITS, NQT, 2>(ix, a, b, st);
@@ -1214,8 +1266,8 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, co
         if (lds_sort) {
             hipLaunchKernelGGL(pair_hist_kernel, dim3(kPairBlocks), dim3(1024), 0, st, probes, P, nprobe,
                                (int)nlist, rlo, rhi, qmask, cnt2);
-            hipLaunchKernelGGL(pair_colsum_kernel, dim3((unsigned)((nlist + th - 1) / th)), dim3(th), 0, st, cnt2,
-                               kPairBlocks, (int)nlist, cnt);
+            hipLaunchKernelGGL(pair_colsum_kernel, dim3((unsigned)((nlist + 63) / 64)), dim3(256), 0, st, cnt2,
+                               (int)nlist, cnt);
         } else {
             zero(cnt, nlist); zero(fill, nlist);
             if (P > 0)
