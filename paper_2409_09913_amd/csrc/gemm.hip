@@ -32,8 +32,10 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(
     float* __restrict__ out, int64_t ldo, const float* __restrict__ an2, const float* __restrict__ bn2)
 {
     constexpr int BK = 16;
-    __shared__ float As[BK][BM + 4];
-    __shared__ float Bs[BK][BN + 4];
+    // two LDS buffers: the next K-tile is loaded into registers while the
+    // current one is multiplied, then stored to the other buffer
+    __shared__ float As[2][BK][BM + 4];
+    __shared__ float Bs[2][BK][BN + 4];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int64_t row0 = (int64_t)blockIdx.y * BM;
     const int col0 = blockIdx.x * BN;
@@ -41,46 +43,64 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(
     v16f acc[2][2];
     for (int a = 0; a < 2; ++a) for (int b = 0; b < 2; ++b) for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
 
+    // 128 x 16 floats per operand = 2 float4 per thread
+    float4 ra[2], rb[2];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int e = tid + 256 * i;
+            const int m = e >> 2, kq = (e & 3) * 4;
+            const int64_t gr = row0 + m;
+            ra[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (gr < n && k0 + kq < K) ra[i] = *(const float4*)(A + gr * (int64_t)K + k0 + kq);
+            if (!b_trans) {
+                const int kk = e / (BN / 4), nq = (e % (BN / 4)) * 4;
+                rb[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (k0 + kk < K && col0 + nq < N) rb[i] = *(const float4*)(B + (int64_t)(k0 + kk) * N + col0 + nq);
+            } else {
+                const int gc = col0 + m;
+                rb[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (gc < N && k0 + kq < K) rb[i] = *(const float4*)(B + (int64_t)gc * K + k0 + kq);
+            }
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int e = tid + 256 * i;
+            const int m = e >> 2, kq = (e & 3) * 4;
+            As[buf][kq + 0][m] = ra[i].x; As[buf][kq + 1][m] = ra[i].y;
+            As[buf][kq + 2][m] = ra[i].z; As[buf][kq + 3][m] = ra[i].w;
+            if (!b_trans) {
+                const int kk = e / (BN / 4), nq = (e % (BN / 4)) * 4;
+                *(float4*)&Bs[buf][kk][nq] = rb[i];
+            } else {
+                Bs[buf][kq + 0][m] = rb[i].x; Bs[buf][kq + 1][m] = rb[i].y;
+                Bs[buf][kq + 2][m] = rb[i].z; Bs[buf][kq + 3][m] = rb[i].w;
+            }
+        }
+    };
+    load(0);
+    store(0);
+    __syncthreads();
+    int cur = 0;
     for (int k0 = 0; k0 < K; k0 += BK) {
-        // A tile: 128 rows x 16 k -> As[k][m]
-        for (int e = tid; e < BM * BK / 4; e += 256) {
-            int m = e >> 2, kq = (e & 3) * 4;
-            int64_t gr = row0 + m;
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (gr < n && k0 + kq < K) v = *(const float4*)(A + gr * (int64_t)K + k0 + kq);
-            As[kq + 0][m] = v.x; As[kq + 1][m] = v.y; As[kq + 2][m] = v.z; As[kq + 3][m] = v.w;
-        }
-        if (!b_trans) {
-            // B is K x N: rows k, 128 contiguous columns
-            for (int e = tid; e < BK * BN / 4; e += 256) {
-                int kk = e / (BN / 4), nq = (e % (BN / 4)) * 4;
-                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (k0 + kk < K && col0 + nq < N) v = *(const float4*)(B + (int64_t)(k0 + kk) * N + col0 + nq);
-                *(float4*)&Bs[kk][nq] = v;
-            }
-        } else {
-            // B is N x K: like A
-            for (int e = tid; e < BN * BK / 4; e += 256) {
-                int nn = e >> 2, kq = (e & 3) * 4;
-                int gc = col0 + nn;
-                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (gc < N && k0 + kq < K) v = *(const float4*)(B + (int64_t)gc * K + k0 + kq);
-                Bs[kq + 0][nn] = v.x; Bs[kq + 1][nn] = v.y; Bs[kq + 2][nn] = v.z; Bs[kq + 3][nn] = v.w;
-            }
-        }
-        __syncthreads();
+        const bool more = k0 + BK < K;
+        if (more) load(k0 + BK);
 #pragma unroll
         for (int ks = 0; ks < BK; ks += 2) {
-            float a0 = As[ks + (lane >> 5)][wm + (lane & 31)];
-            float a1 = As[ks + (lane >> 5)][wm + 32 + (lane & 31)];
-            float b0 = Bs[ks + (lane >> 5)][wn + (lane & 31)];
-            float b1 = Bs[ks + (lane >> 5)][wn + 32 + (lane & 31)];
+            float a0 = As[cur][ks + (lane >> 5)][wm + (lane & 31)];
+            float a1 = As[cur][ks + (lane >> 5)][wm + 32 + (lane & 31)];
+            float b0 = Bs[cur][ks + (lane >> 5)][wn + (lane & 31)];
+            float b1 = Bs[cur][ks + (lane >> 5)][wn + 32 + (lane & 31)];
             acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
             acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
             acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
             acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
         }
+        if (more) store(cur ^ 1);
         __syncthreads();
+        cur ^= 1;
     }
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b) {

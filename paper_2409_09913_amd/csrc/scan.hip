@@ -688,10 +688,18 @@ __global__ __launch_bounds__(256) void buf_select_kernel(int32_t* __restrict__ g
             const int shift = 24 - 8 * pass;
             hist[tid] = 0;
             __syncthreads();
+            unsigned run_d = 0xFFFFFFFFu, run_n = 0;     // runs of equal digits counted in a register
             for (int t = tid; t < c; t += 256) {
                 const unsigned key = f2key(be[t]);
-                if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 0xFF], 1u);
+                if ((key & mask) != prefix) continue;
+                const unsigned dg = (key >> shift) & 0xFF;
+                if (dg != run_d) {
+                    if (run_n) atomicAdd(&hist[run_d], run_n);
+                    run_d = dg; run_n = 0;
+                }
+                ++run_n;
             }
+            if (run_n) atomicAdd(&hist[run_d], run_n);
             __syncthreads();
             digit_of_rank(hist, kr, &s_digit, &s_kr, s_wsum);
             prefix |= s_digit << shift;

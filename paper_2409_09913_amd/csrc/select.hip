@@ -20,6 +20,11 @@ __device__ inline unsigned f2key(float f) {
 constexpr int kSelThreads = 256;
 constexpr int kSelMaxK = 1024;
 
+// R > 0: thread t keeps keys [t*R, t*R + R) of the row in registers (N <=
+// 256*R), so the row is read from memory once; R == 0: every pass reads the
+// row from memory.  Both use contiguous per-thread chunks, which keeps the
+// compaction stable (ties in value go by column index).
+template <int R>
 __global__ __launch_bounds__(kSelThreads) void row_topk_kernel(
     const float* __restrict__ D, int64_t N, int k, int32_t* __restrict__ oidx, float* __restrict__ oval)
 {
@@ -32,16 +37,44 @@ __global__ __launch_bounds__(kSelThreads) void row_topk_kernel(
     const int64_t row = blockIdx.x;
     const float* d = D + row * N;
     const int kk = (int)min<int64_t>(k, N);
+    const int64_t chunk = R > 0 ? R : (N + kSelThreads - 1) / kSelThreads;
+    const int64_t beg = min<int64_t>(N, tid * chunk), end = min(N, beg + chunk);
+    constexpr int RR = R > 0 ? R : 1;
+    unsigned kreg[RR];
+    if constexpr (R > 0) {
+#pragma unroll
+        for (int u = 0; u < R; ++u) kreg[u] = (beg + u < end) ? f2key(d[beg + u]) : 0u;
+    }
+    auto key_at = [&](int64_t j, int u) -> unsigned {
+        if constexpr (R > 0) return kreg[u];
+        else return f2key(d[j]);
+    };
     unsigned prefix = 0, mask = 0;
     unsigned kr = (unsigned)kk;                 // rank (1-based) still to locate
     for (int pass = 0; pass < 4 && kk > 0; ++pass) {
         const int shift = 24 - 8 * pass;
-        for (int i = tid; i < 256; i += kSelThreads) hist[i] = 0;
+        hist[tid] = 0;
         __syncthreads();
-        for (int64_t j = tid; j < N; j += kSelThreads) {
-            unsigned key = f2key(d[j]);
-            if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 0xFF], 1u);
+        // runs of equal digits are counted in a register first: the leading
+        // digit of similar distances is nearly constant, and one LDS bin hit
+        // by every thread would serialise the atomics
+        unsigned run_d = 0xFFFFFFFFu, run_n = 0;
+#pragma unroll
+        for (int u = 0; u < RR; ++u) {
+            for (int64_t j = beg + u; j < end; j += RR) {
+                const unsigned key = key_at(j, u);
+                if ((key & mask) == prefix) {
+                    const unsigned dg = (key >> shift) & 0xFF;
+                    if (dg != run_d) {
+                        if (run_n) atomicAdd(&hist[run_d], run_n);
+                        run_d = dg; run_n = 0;
+                    }
+                    ++run_n;
+                }
+                if (R > 0) break;
+            }
         }
+        if (run_n) atomicAdd(&hist[run_d], run_n);
         __syncthreads();
         // bin of the kr-th smallest: one bin per thread, block-wide prefix sum
         {
@@ -66,14 +99,16 @@ __global__ __launch_bounds__(kSelThreads) void row_topk_kernel(
     }
     const unsigned kth = prefix;                // key of the k-th smallest
     const unsigned need_eq = kr;                // how many equal to kth are taken
-    // stable compaction over contiguous chunks
-    const int64_t chunk = (N + kSelThreads - 1) / kSelThreads;
-    const int64_t beg = tid * chunk, end = min(N, beg + chunk);
+    // stable compaction over the contiguous chunks
     unsigned nl = 0, ne = 0;
-    for (int64_t j = beg; j < end; ++j) {
-        unsigned key = f2key(d[j]);
-        nl += key < kth;
-        ne += key == kth;
+#pragma unroll
+    for (int u = 0; u < RR; ++u) {
+        for (int64_t j = beg + u; j < end; j += RR) {
+            const unsigned key = key_at(j, u);
+            nl += key < kth;
+            ne += key == kth;
+            if (R > 0) break;
+        }
     }
     scan_l[tid] = nl; scan_e[tid] = ne;
     __syncthreads();
@@ -88,10 +123,19 @@ __global__ __launch_bounds__(kSelThreads) void row_topk_kernel(
     __syncthreads();
     const unsigned nless = (unsigned)kk - need_eq;
     unsigned pl = scan_l[tid], pe = scan_e[tid];
-    for (int64_t j = beg; j < end && kk > 0; ++j) {
-        unsigned key = f2key(d[j]);
-        if (key < kth) { skey[pl] = key; sidx[pl] = (int)j; ++pl; }
-        else if (key == kth) { if (pe < need_eq) { skey[nless + pe] = key; sidx[nless + pe] = (int)j; } ++pe; }
+    if (kk > 0) {
+#pragma unroll
+        for (int u = 0; u < RR; ++u) {
+            for (int64_t j = beg + u; j < end; j += RR) {
+                const unsigned key = key_at(j, u);
+                if (key < kth) { skey[pl] = key; sidx[pl] = (int)j; ++pl; }
+                else if (key == kth) {
+                    if (pe < need_eq) { skey[nless + pe] = key; sidx[nless + pe] = (int)j; }
+                    ++pe;
+                }
+                if (R > 0) break;
+            }
+        }
     }
     int S = 1;
     while (S < kk) S <<= 1;
@@ -198,7 +242,12 @@ hipError_t launch_row_topk(const float* D, int64_t n, int64_t N, int k, int32_t*
                            hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(row_topk_kernel, dim3((unsigned)n), dim3(kSelThreads), 0, st, D, N, k, idx, val);
+    const dim3 g((unsigned)n), b(kSelThreads);
+    if (N <= 4 * kSelThreads) hipLaunchKernelGGL(row_topk_kernel<4>, g, b, 0, st, D, N, k, idx, val);
+    else if (N <= 8 * kSelThreads) hipLaunchKernelGGL(row_topk_kernel<8>, g, b, 0, st, D, N, k, idx, val);
+    else if (N <= 16 * kSelThreads) hipLaunchKernelGGL(row_topk_kernel<16>, g, b, 0, st, D, N, k, idx, val);
+    else if (N <= 32 * kSelThreads) hipLaunchKernelGGL(row_topk_kernel<32>, g, b, 0, st, D, N, k, idx, val);
+    else hipLaunchKernelGGL(row_topk_kernel<0>, g, b, 0, st, D, N, k, idx, val);
     return hipGetLastError();
 }
 
