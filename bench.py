@@ -159,7 +159,7 @@ def main():
     def sweep(index, label):
         rows = []
         grid = [(args.nprobe, max(args.rerank, 0))] if args.nprobe > 0 else \
-            [(n_, r_) for n_ in (8, 16, 32, 64, 128, 256) for r_ in (0, 10, 20, 30)]
+            [(n_, r_) for n_ in (16, 32, 64, 80, 96, 112, 128, 160, 256) for r_ in (0, 10, 20, 32)]
         for nprobe, rr in grid:
             if True:
                 ids, qps = timed_search(index, nprobe, rr, 3)

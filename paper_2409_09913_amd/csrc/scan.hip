@@ -663,8 +663,11 @@ __global__ __launch_bounds__(256) void buf_select_kernel(int32_t* __restrict__ g
     __shared__ unsigned hist[256];
     __shared__ unsigned s_digit, s_kr, s_wsum[4];
     __shared__ int s_m;
-    __shared__ float se[kCapQ];
-    __shared__ int si[kCapQ];
+    // sort arrays (kCapQ estimates and ids) only for mode 1: dynamic LDS, so
+    // that the bound modes keep many blocks per CU
+    extern __shared__ __align__(16) char sort_lds[];
+    float* se = (float*)sort_lds;
+    int* si = (int*)(sort_lds + sizeof(float) * kCapQ);
     const int64_t q = blockIdx.x;
     const int tid = threadIdx.x;
     const int craw = gcnt[q];
@@ -681,6 +684,14 @@ __global__ __launch_bounds__(256) void buf_select_kernel(int32_t* __restrict__ g
     const int c = over ? kCapQ : craw;
     const float* be = gbuf_e + q * kCapQ;
     const int* bi = gbuf_i + q * kCapQ;
+    // the buffer is read once: thread t keeps the keys of entries t + 256 u
+    constexpr int RK = kCapQ / 256;
+    unsigned kreg[RK];
+#pragma unroll
+    for (int u = 0; u < RK; ++u) {
+        const int t = tid + 256 * u;
+        kreg[u] = (t < c) ? f2key(be[t]) : 0u;
+    }
     unsigned kth = 0xFFFFFFFFu;
     if (c >= kk) {
         unsigned prefix = 0, mask = 0, kr = (unsigned)kk;
@@ -689,15 +700,17 @@ __global__ __launch_bounds__(256) void buf_select_kernel(int32_t* __restrict__ g
             hist[tid] = 0;
             __syncthreads();
             unsigned run_d = 0xFFFFFFFFu, run_n = 0;     // runs of equal digits counted in a register
-            for (int t = tid; t < c; t += 256) {
-                const unsigned key = f2key(be[t]);
-                if ((key & mask) != prefix) continue;
-                const unsigned dg = (key >> shift) & 0xFF;
-                if (dg != run_d) {
-                    if (run_n) atomicAdd(&hist[run_d], run_n);
-                    run_d = dg; run_n = 0;
+#pragma unroll
+            for (int u = 0; u < RK; ++u) {
+                const unsigned key = kreg[u];
+                if (tid + 256 * u < c && (key & mask) == prefix) {
+                    const unsigned dg = (key >> shift) & 0xFF;
+                    if (dg != run_d) {
+                        if (run_n) atomicAdd(&hist[run_d], run_n);
+                        run_d = dg; run_n = 0;
+                    }
+                    ++run_n;
                 }
-                ++run_n;
             }
             if (run_n) atomicAdd(&hist[run_d], run_n);
             __syncthreads();
@@ -723,11 +736,12 @@ __global__ __launch_bounds__(256) void buf_select_kernel(int32_t* __restrict__ g
     // compaction of the candidates with key <= kth, then an exact sort
     if (tid == 0) s_m = 0;
     __syncthreads();
-    for (int t = tid; t < c; t += 256) {
-        const float e = be[t];
-        if (f2key(e) <= kth) {
+#pragma unroll
+    for (int u = 0; u < RK; ++u) {
+        const int t = tid + 256 * u;
+        if (t < c && kreg[u] <= kth) {
             const int pos = atomicAdd(&s_m, 1);
-            se[pos] = e;
+            se[pos] = key2f(kreg[u]);
             si[pos] = bi[t];
         }
     }
@@ -1294,7 +1308,8 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, co
         return hipGetLastError();
     };
     auto select = [&](int mode, int64_t* oi, float* oe) {
-        hipLaunchKernelGGL(buf_select_kernel, dim3((unsigned)nq), dim3(256), 0, st, gcnt, gprev, gbe, gbi, kk,
+        const size_t sm = (mode == 1) ? (sizeof(float) + sizeof(int)) * kCapQ : 0;
+        hipLaunchKernelGGL(buf_select_kernel, dim3((unsigned)nq), dim3(256), sm, st, gcnt, gprev, gbe, gbi, kk,
                            mode, tkey, ovf, oi, oe);
         return hipGetLastError();
     };
