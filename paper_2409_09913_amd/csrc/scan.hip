@@ -41,7 +41,7 @@ constexpr int kQT = 32;        // queries per MFMA column tile
 constexpr int kCapB = 32;      // per-query survivor buffer of a pass-B item (LDS)
 constexpr int kDenseR = 2;     // first bound: nearest probes per query ...
 constexpr int kDenseV = 256;   // ... and members per list (all estimates kept)
-constexpr int kRound1 = 16;    // pass B, round 1: probe ranks [0, kRound1)
+constexpr int kRound1 = 8;     // pass B, round 1: probe ranks [0, kRound1)
 constexpr int kCapQ = 4096;    // candidate buffer per query (HBM)
 constexpr int kVch = 1024;     // pass-B members per item (long lists are split)
 
