@@ -18,6 +18,12 @@
 //      event is compared, keeping the first strict maximum;
 //   4. the levels of the best event's state are recovered by one binary
 //      search per level (a replay of the enumeration up to that event).
+// Pruning (B >= 5): in a range of events S1 and S2 only grow, so every
+// objective in it is at most S1(end)/sqrt(S2(start)); prefix sums of the
+// fixed-point magnitudes give both ends from the per-level counts.  A range
+// whose bound is <= the best so far, or below the best of a few grid points
+// k_i = min(K, floor(t a_i)) (minus a 1e-12 margin), holds no first strict
+// maximum and is skipped without enumeration.
 // Keys d = a/m are correctly rounded doubles of an FP32 a and m <= 127;
 // distinct ratios differ by more than 2^-39 relative, so the double keys order
 // the events exactly as the exact critical values do.
@@ -71,17 +77,31 @@ __device__ inline int count_upto(const float* A, const int* I, int n, int m, dou
     return lo;
 }
 
+// block-wide sums of three int64 values (all threads get the totals); uses
+// red[32, 44) of the reduction scratch; ends with a barrier
+__device__ inline void block_sum3(long long* red, long long& a, long long& b, long long& c) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    a = wave_sum_ll(a); b = wave_sum_ll(b); c = wave_sum_ll(c);
+    if (lane == 0) { red[32 + 3 * wid] = a; red[33 + 3 * wid] = b; red[34 + 3 * wid] = c; }
+    __syncthreads();
+    a = red[32] + red[35] + red[38] + red[41];
+    b = red[33] + red[36] + red[39] + red[42];
+    c = red[34] + red[37] + red[40] + red[43];
+    __syncthreads();
+}
+
 struct Smem {
-    float* A; int* I; long long* afx; double* key; unsigned* pay;
+    float* A; int* I; long long* afx; long long* ps; double* key; unsigned* pay;
     int* cprev; int* cnext; int* loff;
     long long* red_ll; double* red_d; float* red_f; int* misc;
 };
 
-__device__ inline Smem carve(char* base, int SA, int dp, int cap) {
+__device__ inline Smem carve(char* base, int SA, int dp, int cap, int bb) {
     Smem s;
     size_t o = 0;
     s.key = (double*)(base + o); o += sizeof(double) * cap;
     s.afx = (long long*)(base + o); o += sizeof(long long) * dp;
+    s.ps = (long long*)(base + o); o += bb ? sizeof(long long) * (SA + 1) : 0;
     s.red_ll = (long long*)(base + o); o += sizeof(long long) * 2 * (kThreads + 8);
     s.red_d = (double*)(base + o); o += sizeof(double) * 8;
     s.A = (float*)(base + o); o += sizeof(float) * SA;
@@ -95,8 +115,9 @@ __device__ inline Smem carve(char* base, int SA, int dp, int cap) {
     return s;
 }
 
-__host__ __device__ inline size_t smem_bytes(int SA, int dp, int cap) {
-    return sizeof(double) * cap + sizeof(long long) * dp + sizeof(long long) * 2 * (kThreads + 8) +
+__host__ __device__ inline size_t smem_bytes(int SA, int dp, int cap, int bb) {
+    return sizeof(double) * cap + sizeof(long long) * dp + (bb ? sizeof(long long) * (SA + 1) : 0) +
+           sizeof(long long) * 2 * (kThreads + 8) +
            sizeof(double) * 8 + sizeof(float) * SA + sizeof(int) * SA + sizeof(unsigned) * cap +
            sizeof(int) * (128 + 128 + 132) + sizeof(float) * 8 + sizeof(int) * 16;
 }
@@ -106,14 +127,15 @@ __host__ __device__ inline size_t smem_bytes(int SA, int dp, int cap) {
 __global__ __launch_bounds__(kThreads) void quantize_kernel(
     const float* __restrict__ rrot, int64_t n_vec, int dp, int bits, int SA, int cap,
     const float* __restrict__ norm2, uint8_t* __restrict__ codes, float* __restrict__ f_add,
-    float* __restrict__ f_rescale, float* __restrict__ cos_oo, float2* __restrict__ fac)
+    float* __restrict__ f_rescale, float* __restrict__ cos_oo, float2* __restrict__ fac, int bb)
 {
+    // bb != 0: windows are pruned by the bound below (needs SA+1 prefix sums in LDS)
     extern __shared__ __align__(16) char smem_raw[];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wid = tid >> 6;
     const int64_t row = blockIdx.x;
     if (row >= n_vec) return;
-    Smem s = carve(smem_raw, SA, dp, cap);
+    Smem s = carve(smem_raw, SA, dp, cap, bb);
     const float* r = rrot + row * (int64_t)dp;
     const int K = (1 << (bits - 1)) - 1;
     const int half = 1 << (bits - 1);
@@ -175,6 +197,58 @@ __global__ __launch_bounds__(kThreads) void quantize_kernel(
     const int nnz = s.misc[0];
     const long long total = (long long)nnz * K;
 
+    // ---- prefix sums of the fixed-point magnitudes in sorted order ------------
+    // ps[j] = sum of afx over the j largest magnitudes, so the state after all
+    // events with key >= x follows from the per-level counts alone
+    if (bb) {
+        const int L = (SA + kThreads - 1) / kThreads;
+        const int b0 = tid * L;
+        long long loc = 0;
+        for (int t = 0; t < L; ++t) { const int j = b0 + t; if (j < nnz) loc += s.afx[s.I[j]]; }
+        long long inc = loc;
+        for (int o = 1; o < 64; o <<= 1) { const long long u = __shfl_up(inc, o); if (lane >= o) inc += u; }
+        if (lane == 63) s.red_ll[24 + wid] = inc;
+        __syncthreads();
+        long long run = inc - loc;
+        for (int w = 0; w < wid; ++w) run += s.red_ll[24 + w];
+        for (int t = 0; t < L; ++t) {
+            const int j = b0 + t;
+            if (j < SA) s.ps[j] = run;
+            if (j < nnz) run += s.afx[s.I[j]];
+        }
+        if (tid == kThreads - 1) s.ps[SA] = run;     // the last thread's run is the total
+        __syncthreads();
+    }
+    // ---- seed: the best of a few grid points k_i = min(K, floor(t a_i)) ------
+    // Any grid point's objective is at most the maximum over the critical
+    // values (Algorithm 1 is exact over G), so v_seed bounds the maximum from
+    // below; it only prunes, the recorded argmax still comes from enumeration.
+    constexpr int kSeeds = 8;
+    double v_seed = 0.0;
+    if (bb && K > 0 && amax > 0.0f) {
+        const double fs[kSeeds] = {0.6, 0.75, 0.85, 0.95, 1.05, 1.15, 1.3, 1.5};
+        long long c1[kSeeds], c2[kSeeds];
+        for (int q = 0; q < kSeeds; ++q) { c1[q] = 0; c2[q] = 0; }
+        for (int i = tid; i < dp; i += kThreads) {
+            const double a = (double)fabsf(r[i]);
+            const long long fx = s.afx[i];
+            for (int q = 0; q < kSeeds; ++q) {
+                const double t = fs[q] * ((double)K + 0.5) / (double)amax;
+                const long long k = (long long)fmin((double)K, floor(t * a));
+                c1[q] += fx * (2 * k + 1);
+                c2[q] += (2 * k + 1) * (2 * k + 1);
+            }
+        }
+        for (int q = 0; q < kSeeds; q += 1) {
+            long long z = 0;
+            block_sum3(s.red_ll, c1[q], c2[q], z);
+            const double v = (double)c1[q] / sqrt((double)c2[q]);
+            v_seed = fmax(v_seed, v);
+        }
+    }
+    // prune below this; the margin covers rounding in the objective
+    const double v_thr = v_seed * (1.0 - 1e-12);
+
     // ---- windows ------------------------------------------------------------
     long long done = 0;
     double d_cur = __builtin_huge_val();
@@ -183,6 +257,52 @@ __global__ __launch_bounds__(kThreads) void quantize_kernel(
     int best_i = -1;
     long long best_s2 = dp;
     const double xmin = (nnz > 0 && K > 0) ? (double)s.A[nnz - 1] / (double)K : 0.0;
+
+    // bound of a range [xx, d_cur): S1 at its end over sqrt(S2 at its start)
+    // (both only grow event by event); d1, d2, dn: the range's S1, S2 and
+    // event count from the per-level counts and the prefix sums
+    auto ub_at = [&](double xx, long long& d1, long long& d2, long long& dn) {
+        d1 = 0; d2 = 0; dn = 0;
+        if (tid < K) {
+            const int hi = count_ge(s.A, nnz, tid + 1, xx), lo = s.cprev[tid];
+            d1 = 2 * (s.ps[hi] - s.ps[lo]);
+            d2 = 8 * (long long)(tid + 1) * (hi - lo);
+            dn = hi - lo;
+        }
+        block_sum3(s.red_ll, d1, d2, dn);
+        return (double)(s1base + d1) / sqrt((double)s2base);
+    };
+    // no event of a range with this bound can be the first strict maximum:
+    // ub <= best_v cannot improve strictly; ub < v_thr lies below the seed
+    auto prunable = [&](double ub) { return ub <= best_v || ub < v_thr; };
+    // skip every event with key in [xs, d_cur): the state advances without enumeration
+    auto skip_to = [&](double xs) {
+        long long d1, d2, dn;
+        if (tid < K) s.cnext[tid] = count_ge(s.A, nnz, tid + 1, xs);
+        ub_at(xs, d1, d2, dn);
+        s1base += d1;
+        s2base += d2;
+        done += dn;
+        d_cur = xs;
+        __syncthreads();
+        if (tid < K) s.cprev[tid] = s.cnext[tid];
+        __syncthreads();
+        return dn;
+    };
+    // the smallest x in [xmin, xhi] whose range [x, d_cur) is prunable, given
+    // that [xhi, d_cur) is (bisection on the bit pattern of the double)
+    auto farthest_prunable = [&](double xhi) {
+        long long e1, e2, en;
+        if (prunable(ub_at(xmin, e1, e2, en))) return xmin;
+        unsigned long long lo_b = __double_as_longlong(xmin);
+        unsigned long long hi_b = __double_as_longlong(xhi);
+        for (int it = 0; it < 40 && hi_b - lo_b > 1; ++it) {
+            const unsigned long long mid_b = lo_b + ((hi_b - lo_b) >> 1);
+            if (prunable(ub_at(__longlong_as_double(mid_b), e1, e2, en))) hi_b = mid_b;
+            else lo_b = mid_b;
+        }
+        return __longlong_as_double(hi_b);
+    };
 
     for (int guard = 0; done < total && guard < (1 << 22); ++guard) {
         // choose x: all remaining if they fit, else bisect on the bit pattern
@@ -225,6 +345,18 @@ __global__ __launch_bounds__(kThreads) void quantize_kernel(
         __syncthreads();
         const int W = s.loff[K];
         if (W <= 0) break;            // cannot happen (a tie group has <= dp <= cap/2 events); never spin
+        // ---- bound: every objective in the window is at most
+        //      UB = (S1 at its end) / sqrt(S2 at its start); S1, S2 only grow.
+        //      UB <= best_v: no strict improvement; UB < v_thr: below the seed,
+        //      hence below the maximum.  Such a window is skipped, and the skip
+        //      is extended as far as the bound allows (bisection).
+        if (bb) {
+            long long d1, d2, dn;
+            if (prunable(ub_at(x, d1, d2, dn))) {
+                skip_to(farthest_prunable(x));
+                continue;
+            }
+        }
         int S = 1;
         while (S < W) S <<= 1;
         // gather
@@ -378,14 +510,17 @@ hipError_t launch_quantize(const float* rrot, int64_t n, int dp, int bits, const
     int cap = 1;
     while (cap < 2 * dp) cap <<= 1;
     if (cap < 4096) cap = 4096;
-    size_t sm = smem_bytes(SA, dp, cap);
+    // pruning pays off from B = 5 (15+ levels, many windows per vector) and
+    // needs its prefix sums to fit in LDS
+    int bb = (bits >= 5 && smem_bytes(SA, dp, cap, 1) <= 160 * 1024) ? 1 : 0;
+    size_t sm = smem_bytes(SA, dp, cap, bb);
     if (sm > 48 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void*)quantize_kernel,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(quantize_kernel, dim3((unsigned)n), dim3(kThreads), sm, st,
-                       rrot, n, dp, bits, SA, cap, norm2, codes, f_add, f_rescale, cos_oo, fac);
+                       rrot, n, dp, bits, SA, cap, norm2, codes, f_add, f_rescale, cos_oo, fac, bb);
     return hipGetLastError();
 }
 
