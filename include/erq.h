@@ -75,8 +75,12 @@ int erq_quantize(const float* rrot, int64_t n, int32_t dp, int32_t bits,
 
 /* ------------------------------------------------------------------------ */
 /* Coarse probe of IVF (Sec. 4.1): for every query the nprobe nearest list   */
-/* centroids by squared Euclidean distance (FP32 matrix cores), ascending   */
-/* by (distance, list id).  q: nq x dp raw queries, centroids: nlist x dp.  */
+/* centroids by squared Euclidean distance ||q||^2 + ||c||^2 - 2 q.c,        */
+/* ascending by (distance, list id).  q.c is taken on the BF16 matrix cores */
+/* from a hi/lo split of both FP32 operands (three products, FP32 sums):    */
+/* error <= 2^-14 sum|q_i c_i| plus FP32 accumulation, so only near-ties   */
+/* may order differently from exact arithmetic.                             */
+/* q: nq x dp raw queries, centroids: nlist x dp.                           */
 /* probes: nq x nprobe int32 (output), pdist: nq x nprobe FP32 or NULL.       */
 /* nprobe in [1, min(nlist, 1024)].  workspace: erq_probe_workspace_size.    */
 /* ------------------------------------------------------------------------ */

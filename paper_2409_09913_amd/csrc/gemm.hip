@@ -215,12 +215,111 @@ hipError_t launch_row_sqnorm(const float* X, int64_t n, int K, float* out, hipSt
 }
 
 // dist = ||a||^2 + ||b||^2 - 2 a.b, with norms an2 (n) and bn2 (N) precomputed
+// Squared distances ||a||^2 + ||b||^2 - 2 a.b of the coarse probe with the
+// products on the BF16 matrix cores: every FP32 operand is split into
+// hi = bf16(x) and lo = bf16(x - hi) (x - hi is exact, x = hi + lo to 2^-17
+// relative), and a.b = hi.hi + hi.lo + lo.hi in FP32 accumulation.  Each
+// product is off by at most 2^-15 |a_i b_i| (the dropped lo.lo and the two
+// split residuals), so a distance by at most 2^-14 sum|a_i b_i| plus FP32
+// accumulation: a few units in the 5th digit, enough to order centroids
+// except near-ties.  B is N x K
+// (row-major).  Tile 128 x 128, K staged 32 at a time in two LDS buffers; the
+// next K-tile is loaded into registers while the current one is multiplied.
+__global__ __launch_bounds__(256) void sqdist_bf16x3_kernel(
+    const float* __restrict__ A, int64_t n, int K, const float* __restrict__ B, int N,
+    float* __restrict__ out, int64_t ldo, const float* __restrict__ an2, const float* __restrict__ bn2)
+{
+    constexpr int BK = 32, LD = BK + 8;
+    __shared__ unsigned short Ah[2][BM][LD], Al[2][BM][LD], Bh[2][BN][LD], Bl[2][BN][LD];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int64_t row0 = (int64_t)blockIdx.y * BM;
+    const int col0 = blockIdx.x * BN;
+    const int wm = (wid >> 1) * 64, wn = (wid & 1) * 64;
+    v16f acc[2][2];
+    for (int a = 0; a < 2; ++a) for (int b = 0; b < 2; ++b) for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
+    // 128 rows x 32 k per operand = 4 float4 per thread
+    float4 ra[4], rb[4];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int e = tid + 256 * i;
+            const int m = e >> 3, kq = (e & 7) * 4;
+            const int64_t gr = row0 + m;
+            ra[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (gr < n && k0 + kq < K) ra[i] = *(const float4*)(A + gr * (int64_t)K + k0 + kq);
+            const int gc = col0 + m;
+            rb[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (gc < N && k0 + kq < K) rb[i] = *(const float4*)(B + (int64_t)gc * K + k0 + kq);
+        }
+    };
+    auto split = [&](float x, unsigned short& h, unsigned short& l) {
+        h = f2bf(x);
+        const float xh = __uint_as_float((unsigned)h << 16);
+        l = f2bf(x - xh);
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int e = tid + 256 * i;
+            const int m = e >> 3, kq = (e & 7) * 4;
+            const float av[4] = {ra[i].x, ra[i].y, ra[i].z, ra[i].w};
+            const float bv[4] = {rb[i].x, rb[i].y, rb[i].z, rb[i].w};
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                split(av[c], Ah[buf][m][kq + c], Al[buf][m][kq + c]);
+                split(bv[c], Bh[buf][m][kq + c], Bl[buf][m][kq + c]);
+            }
+        }
+    };
+    load(0);
+    store(0);
+    __syncthreads();
+    int cur = 0;
+    for (int k0 = 0; k0 < K; k0 += BK) {
+        const bool more = k0 + BK < K;
+        if (more) load(k0 + BK);
+#pragma unroll
+        for (int ks = 0; ks < BK; ks += 16) {
+            const int kk = ks + 8 * (lane >> 5);
+            v8bf ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                __builtin_memcpy(&ah[t], &Ah[cur][wm + 32 * t + (lane & 31)][kk], 16);
+                __builtin_memcpy(&al[t], &Al[cur][wm + 32 * t + (lane & 31)][kk], 16);
+                __builtin_memcpy(&bh[t], &Bh[cur][wn + 32 * t + (lane & 31)][kk], 16);
+                __builtin_memcpy(&bl[t], &Bl[cur][wn + 32 * t + (lane & 31)][kk], 16);
+            }
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
+                }
+        }
+        if (more) store(cur ^ 1);
+        __syncthreads();
+        cur ^= 1;
+    }
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+            const int gc = col0 + wn + 32 * b + (lane & 31);
+            if (gc >= N) continue;
+            for (int r = 0; r < 16; ++r) {
+                const int64_t gr = row0 + wm + 32 * a + out_row(lane, r);
+                if (gr >= n) continue;
+                out[gr * ldo + gc] = (an2[gr] + bn2[gc]) - 2.0f * acc[a][b][r];
+            }
+        }
+}
+
 hipError_t launch_sqdist_pre(const float* A, int64_t n, const float* Bm, int64_t N, int K,
                              const float* an2, const float* bn2, float* out, hipStream_t st)
 {
     if (n <= 0 || N <= 0) return hipSuccess;
     dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((n + BM - 1) / BM));
-    hipLaunchKernelGGL(gemm_f32_kernel<1>, grid, dim3(256), 0, st, A, n, K, Bm, (int)N, 1, out, N, an2, bn2);
+    hipLaunchKernelGGL(sqdist_bf16x3_kernel, grid, dim3(256), 0, st, A, n, K, Bm, (int)N, out, (int64_t)N, an2, bn2);
     return hipGetLastError();
 }
 
