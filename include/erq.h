@@ -138,11 +138,15 @@ int erq_index_export(erq_index idx, int64_t* list_off, int64_t* ids, uint8_t* co
 /* Scan (Sec. 3.3, Sec. 4.1): estimated squared distances of every member of */
 /* the probed lists, kept as the kk smallest per query.                     */
 /* qrot: nq x dp rotated queries q' = P^T q_r; probes: nq x nprobe list ids  */
-/* (entries < 0 are skipped, so queries may probe fewer lists).  Per (query, */
-/* list): s' = q' - c' (FP32), symmetric int8 quantisation of s' with        */
-/* delta = max|s'|/127, s_i = rint(s'_i * 127/max|s'|); <y_u, s_int> exact    */
-/* in int32 on the matrix cores; est = f_add + ||s'||^2 + f_rescale * delta/2 */
-/* * (2 <y_u, s_int> - (2^B - 1) sum s_int) in FP32.                          */
+/* (entries < 0 are skipped, so queries may probe fewer lists).  Every query */
+/* is quantised to int8 once, symmetrically: delta = max|q'|/127,           */
+/* q_i = rint(q'_i * 127/max|q'|).  For a probed list with rotated centroid */
+/* c', s' = q' - c' and <y_bar, s'> = <y_bar, q'> - <y_bar, c'> (linear), so  */
+/* est = f_add + ||s'||^2 + f_rescale * (delta/2 * (2 <y_u, q_int> -        */
+/*       (2^B - 1) sum q_int) - <y_bar, c'>)                                 */
+/* with <y_u, q_int> exact in int32 on the matrix cores, <y_bar, c'> held  */
+/* per member in the index (FP64 accumulate), ||s'||^2 per pair in FP32,     */
+/* the rest in FP32.                                                         */
 /* Output: out_ids, out_est nq x kk ascending by (est, id); missing entries  */
 /* are (-1, +inf).  kk in [1, 32].  workspace: erq_scan_workspace_size.      */
 /* ------------------------------------------------------------------------ */
@@ -176,9 +180,10 @@ int erq_search(erq_index idx, const float* q, int64_t nq, int32_t nprobe, int32_
 /* Kernel timing (measurement support, not part of the method).  While       */
 /* enabled, every launch of the named kernels is bracketed by two HIP events */
 /* recorded on the stream it is launched on.  Names: "scan" (the int8 matrix- */
-/* core scan, all passes), "scan_a", "scan_b", "scan_c" (its passes),         */
+/* core scan, all passes), "scan_a" (its first bound), "scan_b" (each launch */
+/* of the bounded scan), "scan_c" (final selection and exact fallback),     */
 /* "quantize", "rotate", "probe", "merge", "rerank".  "scan_redo_pairs"      */
-/* returns in total_ms the number of pairs re-scanned exactly in pass C;    */
+/* returns in total_ms the number of pairs re-scanned by the exact fallback;*/
 /* it is counted only with on == 2, which synchronises after each scan.     */
 /* erq_profile_read waits for the recorded events and returns the summed     */
 /* duration (ms) and launch count of one kernel (host outputs); reset != 0   */
