@@ -369,7 +369,7 @@ __global__ __launch_bounds__(kThreads, 2) void scanA_kernel(
 // with one compare; survivors go to the query's candidate buffer in HBM
 // (staged in LDS; straight to HBM once the LDS stage is full).
 // ---------------------------------------------------------------------------
-template <int BITS, int NQT, int PD>
+template <int BITS, int NQT, int PD, bool DENSE>
 __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
     const uint8_t* __restrict__ codes, const int64_t* __restrict__ tile_off,
     const int64_t* __restrict__ list_off, const float2* __restrict__ fac,
@@ -378,9 +378,10 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
     const int32_t* __restrict__ item_off, const int32_t* __restrict__ list_order, int nlist,
     int kk, unsigned* __restrict__ tau_key, int32_t* __restrict__ gcnt,
     float* __restrict__ gbuf_e, int32_t* __restrict__ gbuf_i, int32_t* __restrict__ work,
-    int vch, int dense, int nprobe)
+    int vch, int nprobe)
 {
-    // dense != 0 (first bound): only the first kDenseV members of each list,
+    constexpr bool dense = DENSE;
+    // DENSE (first bound): only the first kDenseV members of each list,
     // no bound test, every estimate written to slot rank*kDenseV + member of
     // the query's buffer (rank = probe rank of the pair, < kDenseR)
     constexpr int QPI = kQT * NQT;
@@ -390,7 +391,7 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
     __shared__ float s_be[QPI][kCapB];
     __shared__ int s_bi[QPI][kCapB];
     __shared__ unsigned s_tau[QPI];
-    __shared__ float2 s_fac[kVch];
+    __shared__ float2 s_fac[kVch + 64];      // + NaN padding up to the group end
     __shared__ int s_item[5];
 
     const int tid = threadIdx.x, lane = tid & 63;
@@ -420,10 +421,12 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
     int8_t* qs = (int8_t*)smem;
     const int qstride = dp + 16;
     load_queries<NQT>(qs, qstride, s_s2, s_hd, s_ss, s_slot, s_q, qa, dp, pair_q + p0, pair_slot + p0, mq, tid);
-    {   // factors of the item's members
+    {   // factors of the item's members; past the end NaN, which never passes
         const int64_t fb = list_off[l] + v0;
         const int nf = min((int)(list_off[l + 1] - list_off[l]) - v0, dense ? kDenseV : kVch);
-        for (int t = tid; t < nf; t += kThreads) s_fac[t] = fac[fb + t];
+        const int nfp = (nf + 63) & ~63;
+        for (int t = tid; t < nfp; t += kThreads)
+            s_fac[t] = (t < nf) ? fac[fb + t] : make_float2(__builtin_nanf(""), 0.0f);
     }
     __syncthreads();
     if (tid < QPI) s_tau[tid] = (tid < mq) ? tau_key[s_q[tid]] : 0u;
@@ -553,9 +556,8 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     const int v = tt * 32 + out_row(lane, r);
-                    const bool ok = v < nl;
-                    const float2 f = s_fac[ok ? v : 0];
-                    const float gv = ok ? f.x : __builtin_nanf("");   // NaN never passes
+                    const float2 f = s_fac[v];                     // NaN past the end
+                    const float gv = f.x;
                     float e[NQT];
                     bool pass[NQT], anyp = false;
 #pragma unroll
@@ -565,7 +567,8 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
                         pass[qt] = e[qt] <= cAQ[qt];
                         anyp = anyp || pass[qt];
                     }
-                    if (dense) {                            // first bound: keep every estimate
+                    if constexpr (DENSE) {                  // first bound: keep every estimate
+                        const bool ok = v < nl;
 #pragma unroll
                         for (int qt = 0; qt < NQT; ++qt) {
                             if (ok && qok[qt]) {
@@ -1136,10 +1139,10 @@ hipError_t launchA_b(const Index* ix, const ScanArgs& a, hipStream_t st)
 struct BArgs { unsigned* tau_key; int32_t* gcnt; float* gbuf_e; int32_t* gbuf_i; int32_t* work;
                int vch, dense, nprobe; };
 
-template <int BITS, int NQT, int PD>
-hipError_t launchB_t(const Index* ix, const ScanArgs& a, const BArgs& b, hipStream_t st)
+template <int BITS, int NQT, int PD, bool DENSE>
+hipError_t launchB_d(const Index* ix, const ScanArgs& a, const BArgs& b, hipStream_t st)
 {
-    const void* kern = (const void*)scanB_kernel<BITS, NQT, PD>;
+    const void* kern = (const void*)scanB_kernel<BITS, NQT, PD, DENSE>;
     const size_t sm = (size_t)(ix->dp + 16) * kQT * NQT;
     if (sm > 48 * 1024) {
         hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
@@ -1152,11 +1155,18 @@ hipError_t launchB_t(const Index* ix, const ScanArgs& a, const BArgs& b, hipStre
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
     const int64_t grid = std::min<int64_t>(a.grid, (int64_t)std::max(per_cu, 1) * std::max(ncu, 1));
-    hipLaunchKernelGGL((scanB_kernel<BITS, NQT, PD>), dim3((unsigned)grid), dim3(kThreads), sm, st,
+    hipLaunchKernelGGL((scanB_kernel<BITS, NQT, PD, DENSE>), dim3((unsigned)grid), dim3(kThreads), sm, st,
                        ix->codes, ix->tile_off, ix->list_off, ix->sfac, ix->ids, ix->dp,
                        a.qa, a.pair_off, a.pair_q, a.pair_slot, a.item_off, ix->list_order, (int)ix->nlist,
-                       a.kk, b.tau_key, b.gcnt, b.gbuf_e, b.gbuf_i, b.work, b.vch, b.dense, b.nprobe);
+                       a.kk, b.tau_key, b.gcnt, b.gbuf_e, b.gbuf_i, b.work, b.vch, b.nprobe);
     return hipGetLastError();
+}
+
+template <int BITS, int NQT, int PD>
+hipError_t launchB_t(const Index* ix, const ScanArgs& a, const BArgs& b, hipStream_t st)
+{
+    if (b.dense) return launchB_d<BITS, NQT, PD, true>(ix, a, b, st);
+    return launchB_d<BITS, NQT, PD, false>(ix, a, b, st);
 }
 
 // ring depth: 6 when it divides the K-steps per group and the raw words are
