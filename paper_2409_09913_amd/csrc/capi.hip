@@ -430,7 +430,7 @@ int erq_index_export(erq_index ix, int64_t* list_off, int64_t* ids, uint8_t* cod
 int erq_scan_workspace_size(erq_index ix, int64_t nq, int32_t nprobe, int32_t kk, size_t* bytes)
 {
     if (!ix || !bytes || nq < 0 || nprobe < 1 || kk < 1) return fail(ERQ_EINVAL, "erq_scan_workspace_size: bad arguments");
-    *bytes = scan_workspace_bytes(nq, nprobe, ix->nlist, kk, ix->dp);
+    *bytes = scan_workspace_bytes(nq, nprobe, ix->nlist, kk, ix->dp, ix->max_list);
     return ERQ_OK;
 }
 
@@ -467,7 +467,7 @@ static size_t search_ws(Index* ix, int64_t nq, int nprobe, int k, int rerank_k) 
     b += align256(sizeof(float) * nq * nprobe);           // probe distances ||q - c||^2
     b += align256(sizeof(int64_t) * nq * kk);             // candidate ids
     b += align256(sizeof(float) * nq * kk);               // candidate estimates
-    b += std::max(probe_ws(nq, ix->nlist), scan_workspace_bytes(nq, nprobe, ix->nlist, kk, ix->dp));
+    b += std::max(probe_ws(nq, ix->nlist), scan_workspace_bytes(nq, nprobe, ix->nlist, kk, ix->dp, ix->max_list));
     return b;
 }
 

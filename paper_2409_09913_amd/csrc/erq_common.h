@@ -102,7 +102,7 @@ hipError_t launch_quantize(const float* rrot, int64_t n, int dp, int bits, const
                            float2* fac, hipStream_t st);
 
 // scan pipeline
-size_t scan_workspace_bytes(int64_t nq, int nprobe, int64_t nlist, int kk, int dp);
+size_t scan_workspace_bytes(int64_t nq, int nprobe, int64_t nlist, int kk, int dp, int64_t max_list);
 // pdist: ||q' - c'||^2 per (query, probe) (nq x nprobe) or null to compute it
 int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, const float* pdist, int nprobe,
              int kk, int64_t* out_ids, float* out_est, void* ws, size_t ws_bytes, hipStream_t st);

@@ -182,7 +182,8 @@ struct QArgs {
 // 32 columns over all LDS banks.  Per-query scalars go to s_*.
 template <int NQT>
 __device__ inline void load_queries(int8_t* qs, int qstride, float* s_s2, float* s_hd, int* s_ss, int* s_slot,
-                                    int* s_q, const QArgs& qa, int dp, const int32_t* __restrict__ pq,
+                                    int* s_q, unsigned* s_tau, const unsigned* __restrict__ tau_key,
+                                    const QArgs& qa, int dp, const int32_t* __restrict__ pq,
                                     const int32_t* __restrict__ pslot, int mq, int tid)
 {
     constexpr int QPI = kQT * NQT;
@@ -204,6 +205,7 @@ __device__ inline void load_queries(int8_t* qs, int qstride, float* s_s2, float*
         s_ss[tid] = qa.qss[q];
         s_slot[tid] = slot;
         s_q[tid] = q;
+        if (s_tau) s_tau[tid] = tau_key[q];
     }
 }
 
@@ -254,7 +256,8 @@ __global__ __launch_bounds__(kThreads, 2) void scanA_kernel(
         if (tid < kQT) s_thr[tid] = 0xFFFFFFFFu;
         __syncthreads();
         const int l = s_item[0], p0 = s_item[1], mq = s_item[2];
-        load_queries<1>(qs, qstride, s_s2, s_hd, s_ss, s_slot, s_q, qa, dp, pair_q + p0, pair_slot + p0, mq, tid);
+        load_queries<1>(qs, qstride, s_s2, s_hd, s_ss, s_slot, s_q, nullptr, nullptr, qa, dp, pair_q + p0,
+                        pair_slot + p0, mq, tid);
         __syncthreads();
 
         const int j = lane & 31;
@@ -375,7 +378,7 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
     const int64_t* __restrict__ list_off, const float2* __restrict__ fac,
     const int64_t* __restrict__ ids, int dp, QArgs qa, const int32_t* __restrict__ pair_off,
     const int32_t* __restrict__ pair_q, const int32_t* __restrict__ pair_slot,
-    const int32_t* __restrict__ item_off, const int32_t* __restrict__ list_order, int nlist,
+    const int32_t* __restrict__ item_off, const int4* __restrict__ desc, int nlist,
     int kk, unsigned* __restrict__ tau_key, int32_t* __restrict__ gcnt,
     float* __restrict__ gbuf_e, int32_t* __restrict__ gbuf_i, int32_t* __restrict__ work,
     int vch, int nprobe)
@@ -397,30 +400,25 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
     const int tid = threadIdx.x, lane = tid & 63;
     const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform: scalar
     const int n_items = item_off[nlist];
-    // items are taken from a shared counter until it passes n_items
+    // Items are taken from a shared counter until it passes n_items; the id of
+    // the next item is fetched while the current one is scanned.
+    if (tid == 0) s_item[4] = atomicAdd(work, 1);
+    __syncthreads();
     for (;;) {
-    __syncthreads();                               // LDS of the previous item is free
+    const int item = s_item[4];
+    if (item >= n_items) break;
     if (tid == 0) {
-        const int item = atomicAdd(work, 1);
-        s_item[4] = item;
-        if (item < n_items) {
-            int l, t;
-            decode_item(item, item_off, list_order, nlist, &l, &t);
-            const int nv = (int)(list_off[l + 1] - list_off[l]);
-            const int nvc = (vch > 0) ? max(1, (nv + vch - 1) / vch) : 1;
-            const int qtile = t / nvc, vc = t - qtile * nvc;
-            const int p0 = pair_off[l] + qtile * QPI;
-            s_item[0] = l; s_item[1] = p0; s_item[2] = min(QPI, pair_off[l + 1] - p0);
-            s_item[3] = vc * vch;
-        }
+        const int4 d = desc[item];
+        s_item[0] = d.x; s_item[1] = d.y; s_item[2] = d.z; s_item[3] = d.w;
     }
     if (tid < QPI) s_cnt[tid] = 0;
     __syncthreads();
-    if (s_item[4] >= n_items) break;
+    if (tid == 0) s_item[4] = atomicAdd(work, 1);  // read again only after the item's last barrier
     const int l = s_item[0], p0 = s_item[1], mq = s_item[2], v0 = s_item[3];
     int8_t* qs = (int8_t*)smem;
     const int qstride = dp + 16;
-    load_queries<NQT>(qs, qstride, s_s2, s_hd, s_ss, s_slot, s_q, qa, dp, pair_q + p0, pair_slot + p0, mq, tid);
+    load_queries<NQT>(qs, qstride, s_s2, s_hd, s_ss, s_slot, s_q, s_tau, tau_key, qa, dp, pair_q + p0,
+                      pair_slot + p0, mq, tid);
     {   // factors of the item's members; past the end NaN, which never passes
         const int64_t fb = list_off[l] + v0;
         const int nf = min((int)(list_off[l + 1] - list_off[l]) - v0, dense ? kDenseV : kVch);
@@ -428,8 +426,6 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
         for (int t = tid; t < nfp; t += kThreads)
             s_fac[t] = (t < nf) ? fac[fb + t] : make_float2(__builtin_nanf(""), 0.0f);
     }
-    __syncthreads();
-    if (tid < QPI) s_tau[tid] = (tid < mq) ? tau_key[s_q[tid]] : 0u;
     __syncthreads();
 
     const int nkb = dp / 64;
@@ -620,6 +616,7 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
             }
         }
     }
+    __syncthreads();                               // LDS of this item is free; s_item[4] is the next id
     }
 }
 
@@ -1030,6 +1027,23 @@ __global__ __launch_bounds__(1024) void pair_scan_kernel(const int32_t* __restri
     if (tid == 1023) { pair_off[nlist] = part_a[1023]; item_off[nlist] = part_b[1023]; }
 }
 
+// descriptor of every item, (list, first pair, queries, first member), so
+// that a scan kernel reads one int4 per item; one thread per item
+__global__ void item_desc_kernel(const int32_t* __restrict__ item_off, const int32_t* __restrict__ list_order,
+                                 const int64_t* __restrict__ list_off, const int32_t* __restrict__ pair_off,
+                                 int nlist, int qpi, int vch, int64_t cap, int4* __restrict__ desc)
+{
+    const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (item >= cap || item >= item_off[nlist]) return;
+    int l, t;
+    decode_item((int)item, item_off, list_order, nlist, &l, &t);
+    const int nv = (int)(list_off[l + 1] - list_off[l]);
+    const int nvc = (vch > 0) ? max(1, (nv + vch - 1) / vch) : 1;
+    const int qtile = t / nvc, vc = t - qtile * nvc;
+    const int p0 = pair_off[l] + qtile * qpi;
+    desc[item] = make_int4(l, p0, min(qpi, pair_off[l + 1] - p0), vc * vch);
+}
+
 // one wave per query: the kk best of its probed lists' top-kk lists (pairs
 // with probe rank >= rlim are left out; with qmask only flagged queries)
 __global__ __launch_bounds__(256) void merge_kernel(const int32_t* __restrict__ probes, int64_t nq, int nprobe,
@@ -1103,6 +1117,7 @@ __global__ __launch_bounds__(256) void merge_kernel(const int32_t* __restrict__ 
 struct ScanArgs {
     QArgs qa;
     const int32_t *pair_off, *pair_q, *pair_slot, *item_off;
+    const int4* desc;
     int64_t grid;
     int vmax;
     int kk;
@@ -1157,7 +1172,7 @@ hipError_t launchB_d(const Index* ix, const ScanArgs& a, const BArgs& b, hipStre
     const int64_t grid = std::min<int64_t>(a.grid, (int64_t)std::max(per_cu, 1) * std::max(ncu, 1));
     hipLaunchKernelGGL((scanB_kernel<BITS, NQT, PD, DENSE>), dim3((unsigned)grid), dim3(kThreads), sm, st,
                        ix->codes, ix->tile_off, ix->list_off, ix->sfac, ix->ids, ix->dp,
-                       a.qa, a.pair_off, a.pair_q, a.pair_slot, a.item_off, ix->list_order, (int)ix->nlist,
+                       a.qa, a.pair_off, a.pair_q, a.pair_slot, a.item_off, a.desc, (int)ix->nlist,
                        a.kk, b.tau_key, b.gcnt, b.gbuf_e, b.gbuf_i, b.work, b.vch, b.nprobe);
     return hipGetLastError();
 }
@@ -1232,10 +1247,18 @@ hipError_t launch_scan_fac(const uint8_t* codes_u, const int64_t* list_off, int6
     return hipGetLastError();
 }
 
-size_t scan_workspace_bytes(int64_t nq, int nprobe, int64_t nlist, int kk, int dp)
+// items of one pair build: sum over lists of ceil(cnt/qpi) * ceil(n_l/kVch) <=
+// ceil(max_list/kVch) * (P/kQT + nlist) for any qpi >= kQT
+static int64_t desc_capacity(int64_t P, int64_t nlist, int64_t max_list) {
+    const int64_t chunks = std::max<int64_t>(1, (max_list + kVch - 1) / kVch);
+    return chunks * (P / kQT + 1 + nlist);
+}
+
+size_t scan_workspace_bytes(int64_t nq, int nprobe, int64_t nlist, int kk, int dp, int64_t max_list)
 {
     const int64_t P = nq * nprobe;
     size_t b = 0;
+    b += align256(sizeof(int4) * desc_capacity(P, nlist, max_list));   // item descriptors
     b += 2 * align256(sizeof(int32_t) * nlist);            // cnt, fill
     b += align256(sizeof(int32_t) * kPairBlocks * nlist);  // per-block list counts
     b += 2 * align256(sizeof(int32_t) * (nlist + 1));      // pair / item offsets
@@ -1259,11 +1282,13 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, co
     const int64_t P = nq * nprobe;
     const int64_t nlist = ix->nlist;
     const int dp = ix->dp;
-    if (ws_bytes < scan_workspace_bytes(nq, nprobe, nlist, kk, dp))
+    if (ws_bytes < scan_workspace_bytes(nq, nprobe, nlist, kk, dp, ix->max_list))
         return fail(ERQ_ENOMEM, "erq_scan: workspace too small");
     if (nq == 0) return ERQ_OK;
     char* w = (char*)ws;
     auto take = [&](size_t bytes) { char* p = w; w += align256(bytes); return p; };
+    const int64_t dcap = desc_capacity(P, nlist, ix->max_list);
+    int4* desc = (int4*)take(sizeof(int4) * dcap);
     int32_t* cnt = (int32_t*)take(sizeof(int32_t) * nlist);
     int32_t* fill = (int32_t*)take(sizeof(int32_t) * nlist);
     int32_t* cnt2 = (int32_t*)take(sizeof(int32_t) * kPairBlocks * nlist);
@@ -1308,6 +1333,8 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, co
         }
         hipLaunchKernelGGL(pair_scan_kernel, dim3(1), dim3(1024), 0, st, cnt, (int)nlist, ix->list_order,
                            ix->list_off, qpi, vch, poff, ioff);
+        hipLaunchKernelGGL(item_desc_kernel, dim3((unsigned)((dcap + th - 1) / th)), dim3(th), 0, st, ioff,
+                           ix->list_order, ix->list_off, poff, (int)nlist, qpi, vch, dcap, desc);
         if (lds_sort) {
             hipLaunchKernelGGL(pair_place_kernel, dim3(kPairBlocks), dim3(1024), 0, st, probes, P, nprobe,
                                (int)nlist, rlo, rhi, qmask, cnt2, poff, pq, ps);
@@ -1342,7 +1369,7 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, co
         hipError_t er = build_pairs(rlo, rhi, qmask, qpiB, dense ? 0 : kVch);
         if (er != hipSuccess) return er;
         zero(work, 1);
-        ScanArgs b{qa, poff, pq, ps, ioff, gridB, 0, kk, nullptr, nullptr};
+        ScanArgs b{qa, poff, pq, ps, ioff, desc, gridB, 0, kk, nullptr, nullptr};
         BArgs bb{tkey, gcnt, gbe, gbi, work, dense ? 0 : kVch, dense, nprobe};
         const int rec = prof_begin(dense ? PK_SCAN_A : PK_SCAN_B, st);   // one record per launch
         er = launchB(ix, b, bb, st);
@@ -1375,7 +1402,7 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, co
     if (e == hipSuccess) e = select(1, out_ids, out_est);
     if (e == hipSuccess) e = build_pairs(0, nprobe, ovf, kQT, 0);
     if (e == hipSuccess) {
-        ScanArgs c{qa, poff, pq, ps, ioff, std::min<int64_t>((P + kQT - 1) / kQT + nlist, 4096), 0x7FFFFFFF, kk,
+        ScanArgs c{qa, poff, pq, ps, ioff, desc, std::min<int64_t>((P + kQT - 1) / kQT + nlist, 4096), 0x7FFFFFFF, kk,
                    res_est, res_id};
         e = launchA(ix, c, st);
     }
