@@ -658,7 +658,8 @@ __global__ __launch_bounds__(256) void buf_select_kernel(int32_t* __restrict__ g
                                                          const float* __restrict__ gbuf_e,
                                                          const int32_t* __restrict__ gbuf_i, int kk, int mode,
                                                          unsigned* __restrict__ tau_key, int32_t* __restrict__ ovf,
-                                                         int64_t* __restrict__ out_ids, float* __restrict__ out_est)
+                                                         int64_t* __restrict__ out_ids, float* __restrict__ out_est,
+                                                         int32_t* __restrict__ any_over)
 {
     __shared__ unsigned hist[256];
     __shared__ unsigned s_digit, s_kr, s_wsum[4];
@@ -672,6 +673,7 @@ __global__ __launch_bounds__(256) void buf_select_kernel(int32_t* __restrict__ g
     const int tid = threadIdx.x;
     const int craw = gcnt[q];
     const bool over = craw > kCapQ;
+    if (mode != 0 && over && tid == 0) atomicOr(any_over, 1);   // gate of the rescans / fallback
     if (mode == 1 && over) {
         if (tid == 0) ovf[q] = 1;
         return;
@@ -926,11 +928,14 @@ __device__ inline int items_of(const int32_t* cnt, const int64_t* list_off, int 
 constexpr int kPairBlocks = 128;
 constexpr int kHistMax = 16384;
 
+// gate (all the kernels of a pair build and of a scan launch): when non-null
+// and zero, the launch has nothing to do and returns at once
 __global__ __launch_bounds__(1024) void pair_hist_kernel(const int32_t* __restrict__ probes, int64_t np, int nprobe,
                                                          int nlist, int rlo, int rhi,
                                                          const int32_t* __restrict__ qmask,
-                                                         int32_t* __restrict__ cnt2)
+                                                         int32_t* __restrict__ cnt2, const int32_t* __restrict__ gate)
 {
+    if (gate && *gate == 0) return;
     __shared__ int hist[kHistMax];
     const int b = blockIdx.x;
     for (int l = threadIdx.x; l < nlist; l += blockDim.x) hist[l] = 0;
@@ -949,8 +954,9 @@ __global__ __launch_bounds__(1024) void pair_hist_kernel(const int32_t* __restri
 // 64 lists per workgroup; thread (list, quarter) loads its quarter of the
 // blocks at once, quarter sums are combined in LDS
 __global__ __launch_bounds__(256) void pair_colsum_kernel(int32_t* __restrict__ cnt2, int nlist,
-                                                          int32_t* __restrict__ cnt)
+                                                          int32_t* __restrict__ cnt, const int32_t* __restrict__ gate)
 {
+    if (gate && *gate == 0) return;
     constexpr int BQ = kPairBlocks / 4;
     __shared__ int part[4][64];
     const int lq = threadIdx.x & 63, bq = threadIdx.x >> 6;
@@ -980,8 +986,10 @@ __global__ __launch_bounds__(1024) void pair_place_kernel(const int32_t* __restr
                                                           const int32_t* __restrict__ qmask,
                                                           const int32_t* __restrict__ cnt2,
                                                           const int32_t* __restrict__ off,
-                                                          int32_t* __restrict__ pq, int32_t* __restrict__ pslot)
+                                                          int32_t* __restrict__ pq, int32_t* __restrict__ pslot,
+                                                          const int32_t* __restrict__ gate)
 {
+    if (gate && *gate == 0) return;
     __shared__ int base[kHistMax];
     const int b = blockIdx.x;
     for (int l = threadIdx.x; l < nlist; l += blockDim.x) base[l] = off[l] + cnt2[(int64_t)b * nlist + l];
@@ -1002,8 +1010,14 @@ __global__ __launch_bounds__(1024) void pair_scan_kernel(const int32_t* __restri
                                                          const int32_t* __restrict__ list_order,
                                                          const int64_t* __restrict__ list_off, int qpi, int vch,
                                                          int32_t* __restrict__ pair_off,
-                                                         int32_t* __restrict__ item_off)
+                                                         int32_t* __restrict__ item_off,
+                                                         const int32_t* __restrict__ gate)
 {
+    // a gated-off build publishes zero items, so the scan after it is empty
+    if (gate && *gate == 0) {
+        if (threadIdx.x == 0) { item_off[nlist] = 0; pair_off[nlist] = 0; }
+        return;
+    }
     __shared__ int part_a[1024], part_b[1024];
     const int tid = threadIdx.x;
     const int chunk = (nlist + 1023) / 1024;
@@ -1033,7 +1047,7 @@ __global__ void item_desc_kernel(const int32_t* __restrict__ item_off, const int
                                  const int64_t* __restrict__ list_off, const int32_t* __restrict__ pair_off,
                                  int nlist, int qpi, int vch, int64_t cap, int4* __restrict__ desc)
 {
-    const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // empty build: item_off[nlist] == 0
     if (item >= cap || item >= item_off[nlist]) return;
     int l, t;
     decode_item((int)item, item_off, list_order, nlist, &l, &t);
@@ -1265,7 +1279,7 @@ size_t scan_workspace_bytes(int64_t nq, int nprobe, int64_t nlist, int kk, int d
     b += 2 * align256(sizeof(int32_t) * P);                // pair table (query, slot)
     b += align256(sizeof(unsigned) * nq);                  // bound per query
     b += 3 * align256(sizeof(int32_t) * nq);               // candidate counts, counts before a round, flags
-    b += align256(sizeof(int32_t));                        // pass-B work counter
+    b += 2 * align256(sizeof(int32_t));                    // pass-B work counter, overflow flag
     b += align256(sizeof(float) * nq * kCapQ);             // candidate buffers
     b += align256(sizeof(int32_t) * nq * kCapQ);
     b += align256(sizeof(float) * P * kk);                 // per-pair top-kk (pass A, fallback)
@@ -1301,6 +1315,7 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, co
     int32_t* gprev = (int32_t*)take(sizeof(int32_t) * nq);
     int32_t* ovf = (int32_t*)take(sizeof(int32_t) * nq);
     int32_t* work = (int32_t*)take(sizeof(int32_t));
+    int32_t* anyf = (int32_t*)take(sizeof(int32_t));       // some query's buffer overflowed
     float* gbe = (float*)take(sizeof(float) * nq * kCapQ);
     int32_t* gbi = (int32_t*)take(sizeof(int32_t) * nq * kCapQ);
     float* res_est = (float*)take(sizeof(float) * P * kk);
@@ -1319,12 +1334,12 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, co
     // pair table of the probes with rank in [rlo, rhi) (of flagged queries with
     // qmask), grouped by list; items split lists into chunks of vch members when vch > 0
     const bool lds_sort = nlist <= kHistMax;
-    auto build_pairs = [&](int rlo, int rhi, const int32_t* qmask, int qpi, int vch) {
+    auto build_pairs = [&](int rlo, int rhi, const int32_t* qmask, int qpi, int vch, const int32_t* gate) {
         if (lds_sort) {
             hipLaunchKernelGGL(pair_hist_kernel, dim3(kPairBlocks), dim3(1024), 0, st, probes, P, nprobe,
-                               (int)nlist, rlo, rhi, qmask, cnt2);
+                               (int)nlist, rlo, rhi, qmask, cnt2, gate);
             hipLaunchKernelGGL(pair_colsum_kernel, dim3((unsigned)((nlist + 63) / 64)), dim3(256), 0, st, cnt2,
-                               (int)nlist, cnt);
+                               (int)nlist, cnt, gate);
         } else {
             zero(cnt, nlist); zero(fill, nlist);
             if (P > 0)
@@ -1332,12 +1347,12 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, co
                                    rlo, rhi, qmask, cnt);
         }
         hipLaunchKernelGGL(pair_scan_kernel, dim3(1), dim3(1024), 0, st, cnt, (int)nlist, ix->list_order,
-                           ix->list_off, qpi, vch, poff, ioff);
+                           ix->list_off, qpi, vch, poff, ioff, lds_sort ? gate : nullptr);
         hipLaunchKernelGGL(item_desc_kernel, dim3((unsigned)((dcap + th - 1) / th)), dim3(th), 0, st, ioff,
                            ix->list_order, ix->list_off, poff, (int)nlist, qpi, vch, dcap, desc);
         if (lds_sort) {
             hipLaunchKernelGGL(pair_place_kernel, dim3(kPairBlocks), dim3(1024), 0, st, probes, P, nprobe,
-                               (int)nlist, rlo, rhi, qmask, cnt2, poff, pq, ps);
+                               (int)nlist, rlo, rhi, qmask, cnt2, poff, pq, ps, gate);
         } else if (P > 0) {
             hipLaunchKernelGGL(pair_scatter_kernel, dim3(pblocks), dim3(th), 0, st, probes, P, nprobe, (int)nlist,
                                rlo, rhi, qmask, poff, fill, pq, ps);
@@ -1347,7 +1362,7 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, co
     auto select = [&](int mode, int64_t* oi, float* oe) {
         const size_t sm = (mode == 1) ? (sizeof(float) + sizeof(int)) * kCapQ : 0;
         hipLaunchKernelGGL(buf_select_kernel, dim3((unsigned)nq), dim3(256), sm, st, gcnt, gprev, gbe, gbi, kk,
-                           mode, tkey, ovf, oi, oe);
+                           mode, tkey, ovf, oi, oe, anyf);
         return hipGetLastError();
     };
     const int qpiB = (ix->dp <= 768) ? 2 * kQT : kQT;
@@ -1365,8 +1380,8 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, co
     const int64_t gridB = 1 << 20;                    // capped at the resident blocks
     // a pass-B launch over the pairs of probe ranks [rlo, rhi) (of flagged
     // queries with qmask); dense = the first-bound mode
-    auto scan_round = [&](int rlo, int rhi, const int32_t* qmask, int dense) {
-        hipError_t er = build_pairs(rlo, rhi, qmask, qpiB, dense ? 0 : kVch);
+    auto scan_round = [&](int rlo, int rhi, const int32_t* qmask, int dense, const int32_t* gate) {
+        hipError_t er = build_pairs(rlo, rhi, qmask, qpiB, dense ? 0 : kVch, gate);
         if (er != hipSuccess) return er;
         zero(work, 1);
         ScanArgs b{qa, poff, pq, ps, ioff, desc, gridB, 0, kk, nullptr, nullptr};
@@ -1382,7 +1397,7 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, co
     hipLaunchKernelGGL(fill_dense_kernel, dim3((unsigned)((nq * kDenseR * kDenseV + th - 1) / th)), dim3(th), 0, st,
                        gbe, nq, gcnt, tkey);
     e = hipGetLastError();
-    if (e == hipSuccess) e = scan_round(0, r0, nullptr, 1);
+    if (e == hipSuccess) e = scan_round(0, r0, nullptr, 1, nullptr);
     if (e == hipSuccess) e = select(0, nullptr, nullptr);
     zero(gcnt, nq);                                  // the dense entries are found again by the rounds
     // pass B in rounds of increasing probe rank
@@ -1391,16 +1406,19 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, co
         const int rlo = bounds[r], rhi = bounds[r + 1];
         if (rhi <= rlo) continue;
         hipLaunchKernelGGL(copy_i32_kernel, dim3(qblocks), dim3(th), 0, st, gcnt, gprev, nq);
-        e = scan_round(rlo, rhi, nullptr, 0);
-        // queries that overflowed: back to their count before the round, tighter bound, rescan the round
+        e = scan_round(rlo, rhi, nullptr, 0, nullptr);
+        // queries that overflowed: back to their count before the round, tighter bound, rescan the
+        // round (skipped on the device when no query overflowed)
+        zero(anyf, 1);
         if (e == hipSuccess) e = select(2, nullptr, nullptr);
-        if (e == hipSuccess) e = scan_round(rlo, rhi, ovf, 0);
+        if (e == hipSuccess) e = scan_round(rlo, rhi, ovf, 0, anyf);
         if (e == hipSuccess && rhi < nprobe) e = select(0, nullptr, nullptr);
     }
     // exact top-kk per query; queries whose buffer still overflowed: pair by pair
     const int pc = prof_begin(PK_SCAN_C, st);
+    zero(anyf, 1);
     if (e == hipSuccess) e = select(1, out_ids, out_est);
-    if (e == hipSuccess) e = build_pairs(0, nprobe, ovf, kQT, 0);
+    if (e == hipSuccess) e = build_pairs(0, nprobe, ovf, kQT, 0, anyf);
     if (e == hipSuccess) {
         ScanArgs c{qa, poff, pq, ps, ioff, desc, std::min<int64_t>((P + kQT - 1) / kQT + nlist, 4096), 0x7FFFFFFF, kk,
                    res_est, res_id};
