@@ -63,6 +63,10 @@ def main():
     ap.add_argument("--cpu-sample-queries", type=int, default=32)
     ap.add_argument("--nprobe", type=int, default=0, help="fixed operating point (skips the sweep)")
     ap.add_argument("--rerank", type=int, default=-1, help="fixed re-rank depth (with --nprobe)")
+    ap.add_argument("--graph", type=int, default=1,
+                    help="1: the timed steps replay the search captured in a HIP graph; 0: eager calls")
+    ap.add_argument("--serve", type=int, default=0,
+                    help="N > 0: also run N Poisson-arrival requests through the batching server (p50/p99)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -75,7 +79,7 @@ def main():
         return
 
     import torch
-    from paper_2409_09913_amd import erq, ivf, synth
+    from paper_2409_09913_amd import erq, ivf, serve, synth
 
     dev = torch.device("cuda:0")
     erq.load()
@@ -183,6 +187,25 @@ def main():
     for _ in range(args.warmup):
         ix.search(q, nprobe, args.k, rr, ws=ws, out=out)
     torch.cuda.synchronize()
+    graph_dt, graph_rec = None, None
+    if args.graph:
+        # the whole search (rotation, probe, scan rounds, selects, re-rank) as one
+        # graph; queries already sit in its static input when the clock starts
+        g = serve.SearchGraph(ix, args.nq, nprobe, args.k, rr)
+        with torch.cuda.stream(g.stream):
+            g.q.copy_(q)
+            for _ in range(args.warmup):
+                g.graph.replay()
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        with torch.cuda.stream(g.stream):
+            for _ in range(args.steps):
+                g.graph.replay()
+        torch.cuda.synchronize()
+        graph_dt = time.perf_counter() - ts
+        graph_rec = recall_at(g.ids.cpu().numpy(), truth_np, args.k)
+        log("graph replay: %.3f ms/step, recall %.4f" % (1000 * graph_dt / args.steps, graph_rec))
+    # eager steps with the library's HIP events around every kernel (per-launch durations)
     erq.profile_enable(True)
     erq.profile_read("scan", reset=True)
     torch.cuda.synchronize()
@@ -206,10 +229,16 @@ def main():
     tot["redo_pairs"] = redo
     erq.profile_read("scan", reset=True)
     erq.profile_enable(False)
+    eager_ms = 1000 * dt / args.steps
+    rec_final = recall_at(out[0].cpu().numpy(), truth_np, args.k)
+    if graph_dt is not None:
+        if graph_rec != rec_final:
+            log("WARNING: graph replay recall %.4f differs from the eager call's %.4f" % (graph_rec, rec_final))
+        dt = graph_dt
     qps = args.steps * args.nq / dt
     ms_per_step = 1000 * dt / args.steps
-    rec_final = recall_at(out[0].cpu().numpy(), truth_np, args.k)
-    log("timed: %.0f QPS, %.3f ms/step, recall %.4f; per-launch ms %s" % (qps, ms_per_step, rec_final, tot))
+    log("timed: %.0f QPS, %.3f ms/step (eager %.3f), recall %.4f; per-launch ms %s" % (qps, ms_per_step, eager_ms,
+                                                                                   rec_final, tot))
 
     # ---- roofline of the scan kernel ------------------------------------------------------
     probes = erq.coarse_probe(q, cent, nprobe).cpu().numpy()
@@ -250,6 +279,20 @@ def main():
                  "hbm_frac": bytes_alg / avg_s / 1e9 / HBM_PEAK_GBS, "scan_hip_sha256_16": sha})
     log("roofline", roof)
 
+    # ---- serving: Poisson arrivals through the continuous-batching server ----------------
+    serving = None
+    if args.serve:
+        srv = serve.Server(ix, max_batch=1024, max_nprobe=max(nprobe, 64), max_k=args.k, max_rerank=max(rr, 20),
+                           slots=4)
+        res_s = {}
+        for rate in (1000.0, 10000.0, 50000.0):
+            reqs, p50, p99, sq = serve.poisson_run(srv, q, rate=rate, n_requests=args.serve, per_request=1,
+                                                   k=args.k, nprobes=(16, 64), rerank_k=rr, seed=7)
+            res_s["%d_rps" % rate] = {"p50_ms": p50, "p99_ms": p99, "qps": sq}
+            log("serving at %d req/s: p50 %.3f ms p99 %.3f ms, %.0f QPS" % (rate, p50, p99, sq))
+        serving = {"slots": srv.slots_admitted, "request": "1 query, nprobe 16 or 64, k=%d, rerank %d" % (args.k, rr),
+                   "by_rate": res_s}
+
     # ---- CPU baseline: the oracle on a bounded sample ------------------------------------
     cpu = None
     if not args.no_cpu_baseline:
@@ -268,6 +311,9 @@ def main():
         "encode_codes_per_s": enc_rate,
         "fp32_bruteforce_qps": flat_qps,
         "per_launch_ms": tot,
+        "timed_mode": "hip_graph_replay" if graph_dt is not None else "eager",
+        "eager_ms_per_step": eager_ms,
+        "serving": serving,
         "roofline": roof,
         "cpu_baseline": cpu,
         "sweep": [{"nprobe": a, "rerank_k": b, "recall@10": c, "qps": d} for a, b, c, d in rows],

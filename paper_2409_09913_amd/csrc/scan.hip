@@ -395,6 +395,7 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
     __shared__ int s_bi[QPI][kCapB];
     __shared__ unsigned s_tau[QPI];
     __shared__ float2 s_fac[kVch + 64];      // + NaN padding up to the group end
+    __shared__ int s_id[kVch + 64];          // ids of the item's members (no global load in the epilogue)
     __shared__ int s_item[5];
 
     const int tid = threadIdx.x, lane = tid & 63;
@@ -419,12 +420,15 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
     const int qstride = dp + 16;
     load_queries<NQT>(qs, qstride, s_s2, s_hd, s_ss, s_slot, s_q, s_tau, tau_key, qa, dp, pair_q + p0,
                       pair_slot + p0, mq, tid);
-    {   // factors of the item's members; past the end NaN, which never passes
+    {   // factors and ids of the item's members; past the end NaN, which never passes
         const int64_t fb = list_off[l] + v0;
         const int nf = min((int)(list_off[l + 1] - list_off[l]) - v0, dense ? kDenseV : kVch);
         const int nfp = (nf + 63) & ~63;
-        for (int t = tid; t < nfp; t += kThreads)
-            s_fac[t] = (t < nf) ? fac[fb + t] : make_float2(__builtin_nanf(""), 0.0f);
+        for (int t = tid; t < nfp; t += kThreads) {
+            const bool in = t < nf;
+            s_fac[t] = in ? fac[fb + t] : make_float2(__builtin_nanf(""), 0.0f);
+            s_id[t] = in ? (int)ids[fb + t] : -1;
+        }
     }
     __syncthreads();
 
@@ -434,7 +438,6 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
     const int8_t* qrow = qs + (lane & 31) * qstride + 16 * (lane >> 5);
     const int64_t tile_bytes = (int64_t)4 * dp * BITS;
     // members [v0, v0 + nl) of list l (v0 is a multiple of 64: whole tile pairs)
-    const int64_t lbase = list_off[l] + v0;
     const int nl = min((int)(list_off[l + 1] - list_off[l]) - v0, dense ? kDenseV : kVch);
     const int ntile = (nl + 31) >> 5;
     const int ngroup = (ntile + 1) >> 1;
@@ -544,15 +547,22 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
             kb0 = 0;
             const int g = wid + 4 * gi;
             ++gi;
-            // epilogue of group g: estimates, bound test, survivors to the stage
+            // epilogue of group g: estimates, bound test, survivors to the stage.
+            // The tile's 16 factor pairs are read from LDS before any is used,
+            // and nothing here touches global memory except the rare overflow
+            // of the stage, so the code loads in flight for the next group are
+            // not waited for.
 #pragma unroll
             for (int a = 0; a < 2; ++a) {
                 const int tt = 2 * g + a;
                 if (tt >= ntile) break;
+                float2 fr[16];
+#pragma unroll
+                for (int r = 0; r < 16; ++r) fr[r] = s_fac[tt * 32 + out_row(lane, r)];   // NaN past the end
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     const int v = tt * 32 + out_row(lane, r);
-                    const float2 f = s_fac[v];                     // NaN past the end
+                    const float2 f = fr[r];
                     const float gv = f.x;
                     float e[NQT];
                     bool pass[NQT], anyp = false;
@@ -569,7 +579,7 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
                         for (int qt = 0; qt < NQT; ++qt) {
                             if (ok && qok[qt]) {
                                 gbuf_e[qslot0[qt] + v] = e[qt] + qs2[qt];
-                                gbuf_i[qslot0[qt] + v] = (int)ids[lbase + v];
+                                gbuf_i[qslot0[qt] + v] = s_id[v];
                             }
                         }
                         continue;
@@ -580,7 +590,7 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
                         if (!pass[qt]) continue;
                         const float est = e[qt] + qs2[qt];
                         const int qi = qt * kQT + j;
-                        const int id = (int)ids[lbase + v];
+                        const int id = s_id[v];
                         const int pos = atomicAdd(&s_cnt[qi], 1);
                         if (pos < kCapB) {
                             s_be[qi][pos] = est; s_bi[qi][pos] = id;
