@@ -176,28 +176,19 @@ struct QArgs {
     const float* sdist;
 };
 
-// Prologue shared by the scan kernels: the int8 queries of one item into LDS,
-// row-major with a row stride of dp + 16 bytes (query qi at qs + qi*qstride).
-// Rows past mq are zero.  The 16-byte pad spreads the B-fragment reads of the
-// 32 columns over all LDS banks.  Per-query scalars go to s_*.
-template <int NQT>
-__device__ inline void load_queries(int8_t* qs, int qstride, float* s_s2, float* s_hd, int* s_ss, int* s_slot,
-                                    int* s_q, unsigned* s_tau, const unsigned* __restrict__ tau_key,
-                                    const QArgs& qa, int dp, const int32_t* __restrict__ pq,
-                                    const int32_t* __restrict__ pslot, int mq, int tid)
+// Prologue shared by the scan kernels, in two steps with a barrier between
+// them.  Step 1 (threads < mq): per-query scalars of the item's pairs into
+// s_* (query id, slot, ||s||^2, delta/2, sum of q_int, bound).  Step 2 (all
+// threads): the int8 query rows into LDS, row-major with a row stride of
+// dp + 16 bytes (query qi at qs + qi*qstride), rows past mq zero; every
+// thread issues all of its 16-byte loads (up to kRowLoads) before it stores
+// any, so a batch costs one memory latency.  The 16-byte pad spreads the
+// B-fragment reads of the 32 columns over all LDS banks.
+__device__ inline void load_query_scalars(float* s_s2, float* s_hd, int* s_ss, int* s_slot, int* s_q,
+                                          unsigned* s_tau, const unsigned* __restrict__ tau_key, const QArgs& qa,
+                                          const int32_t* __restrict__ pq, const int32_t* __restrict__ pslot,
+                                          int mq, int tid)
 {
-    constexpr int QPI = kQT * NQT;
-    const int nch = dp >> 4;                       // 16-byte chunks per row
-    const float rnch = 1.0f / (float)nch;          // u / nch below is exact: u < 2^16, gap >= 0.5/nch
-    const int units = QPI * nch;
-#pragma unroll 4
-    for (int u = tid; u < units; u += kThreads) {
-        const int qi = (int)(((float)u + 0.5f) * rnch);
-        const int c = u - qi * nch;
-        uint4 w = make_uint4(0, 0, 0, 0);
-        if (qi < mq) w = *(const uint4*)(qa.qint + (int64_t)pq[qi] * dp + 16 * c);
-        *(uint4*)(qs + qi * qstride + 16 * c) = w;
-    }
     if (tid < mq) {
         const int q = pq[tid], slot = pslot[tid];
         s_s2[tid] = qa.sdist[slot];
@@ -206,6 +197,36 @@ __device__ inline void load_queries(int8_t* qs, int qstride, float* s_s2, float*
         s_slot[tid] = slot;
         s_q[tid] = q;
         if (s_tau) s_tau[tid] = tau_key[q];
+    }
+}
+
+constexpr int kRowLoads = 12;
+
+template <int NQT>
+__device__ inline void load_query_rows(int8_t* qs, int qstride, const int* s_q, const int8_t* __restrict__ qint,
+                                       int dp, int mq, int tid)
+{
+    constexpr int QPI = kQT * NQT;
+    const int nch = dp >> 4;                       // 16-byte chunks per row
+    const float rnch = 1.0f / (float)nch;          // u / nch below is exact: u < 2^16, gap >= 0.5/nch
+    const int units = QPI * nch;
+    for (int base = 0; base < units; base += kRowLoads * kThreads) {
+        uint4 w[kRowLoads];
+#pragma unroll
+        for (int k = 0; k < kRowLoads; ++k) {
+            const int u = base + k * kThreads + tid;
+            const int qi = (int)(((float)u + 0.5f) * rnch);
+            const int c = u - qi * nch;
+            w[k] = make_uint4(0, 0, 0, 0);
+            if (u < units && qi < mq) w[k] = *(const uint4*)(qint + (int64_t)s_q[qi] * dp + 16 * c);
+        }
+#pragma unroll
+        for (int k = 0; k < kRowLoads; ++k) {
+            const int u = base + k * kThreads + tid;
+            const int qi = (int)(((float)u + 0.5f) * rnch);
+            const int c = u - qi * nch;
+            if (u < units) *(uint4*)(qs + qi * qstride + 16 * c) = w[k];
+        }
     }
 }
 
@@ -256,8 +277,9 @@ __global__ __launch_bounds__(kThreads, 2) void scanA_kernel(
         if (tid < kQT) s_thr[tid] = 0xFFFFFFFFu;
         __syncthreads();
         const int l = s_item[0], p0 = s_item[1], mq = s_item[2];
-        load_queries<1>(qs, qstride, s_s2, s_hd, s_ss, s_slot, s_q, nullptr, nullptr, qa, dp, pair_q + p0,
-                        pair_slot + p0, mq, tid);
+        load_query_scalars(s_s2, s_hd, s_ss, s_slot, s_q, nullptr, nullptr, qa, pair_q + p0, pair_slot + p0, mq, tid);
+        __syncthreads();
+        load_query_rows<1>(qs, qstride, s_q, qa.qint, dp, mq, tid);
         __syncthreads();
 
         const int j = lane & 31;
@@ -418,18 +440,30 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
     const int l = s_item[0], p0 = s_item[1], mq = s_item[2], v0 = s_item[3];
     int8_t* qs = (int8_t*)smem;
     const int qstride = dp + 16;
-    load_queries<NQT>(qs, qstride, s_s2, s_hd, s_ss, s_slot, s_q, s_tau, tau_key, qa, dp, pair_q + p0,
-                      pair_slot + p0, mq, tid);
-    {   // factors and ids of the item's members; past the end NaN, which never passes
+    load_query_scalars(s_s2, s_hd, s_ss, s_slot, s_q, s_tau, tau_key, qa, pair_q + p0, pair_slot + p0, mq, tid);
+    {   // factors and ids of the item's members, all loads of a thread in
+        // flight at once; past the end NaN, which never passes
+        constexpr int KF = (kVch + 64 + kThreads - 1) / kThreads;
         const int64_t fb = list_off[l] + v0;
         const int nf = min((int)(list_off[l + 1] - list_off[l]) - v0, dense ? kDenseV : kVch);
         const int nfp = (nf + 63) & ~63;
-        for (int t = tid; t < nfp; t += kThreads) {
+        float2 fv[KF];
+        int iv[KF];
+#pragma unroll
+        for (int k = 0; k < KF; ++k) {
+            const int t = tid + k * kThreads;
             const bool in = t < nf;
-            s_fac[t] = in ? fac[fb + t] : make_float2(__builtin_nanf(""), 0.0f);
-            s_id[t] = in ? (int)ids[fb + t] : -1;
+            fv[k] = in ? fac[fb + t] : make_float2(__builtin_nanf(""), 0.0f);
+            iv[k] = in ? (int)ids[fb + t] : -1;
+        }
+#pragma unroll
+        for (int k = 0; k < KF; ++k) {
+            const int t = tid + k * kThreads;
+            if (t < nfp) { s_fac[t] = fv[k]; s_id[t] = iv[k]; }
         }
     }
+    __syncthreads();
+    load_query_rows<NQT>(qs, qstride, s_q, qa.qint, dp, mq, tid);
     __syncthreads();
 
     const int nkb = dp / 64;
