@@ -474,7 +474,6 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
     // members [v0, v0 + nl) of list l (v0 is a multiple of 64: whole tile pairs)
     const int nl = min((int)(list_off[l + 1] - list_off[l]) - v0, dense ? kDenseV : kVch);
     const int ntile = (nl + 31) >> 5;
-    const int ngroup = (ntile + 1) >> 1;
     const int64_t tbase = tile_off[l] + (v0 >> 5);
     const int j = lane & 31;
     // Columns without a query (qi >= mq) have no LDS terms: they take zeros
@@ -515,22 +514,26 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
         cAQ[qt] = qok[qt] ? aq + (fabsf(qtau[qt]) + fabsf(qs2[qt])) * 0x1p-20f : -__builtin_huge_valf();
     }
 
-    // The wave's groups g = wid + 4 i (two tiles each) are walked as one
-    // sequence of K-steps (group, kb).  The packed codes of step s + PD are
-    // loaded while step s runs: a ring of PD slots of raw words in registers,
-    // unrolled by PD so that each slot is consumed and refilled in place (no
-    // copy of a register whose load is in flight).  PD divides nkb, so a group
-    // always ends with the last slot.  Past the end the last step is loaded
-    // again, so no load is conditional.
-    const int ngw = (ngroup > wid) ? (ngroup - 1 - wid) / 4 + 1 : 0;
+    // Wave wid takes the tiles [ta, tb) of the item (a contiguous quarter,
+    // so the waves differ by at most one tile) and walks them in groups of
+    // two tiles as one sequence of K-steps (group, kb); a group with one tile
+    // (the last of an odd range) skips the second tile's unpacking and
+    // MFMAs behind a wave-uniform branch.
+    // The packed codes of step s + PD are loaded while step s runs: a ring
+    // of PD slots of raw words in registers, unrolled by PD so that each slot
+    // is consumed and refilled in place (no copy of a register whose load is
+    // in flight).  PD divides nkb, so a group always ends with the last slot.
+    // Past the end the last step is loaded again, so no load is conditional.
+    const int ta = (wid * ntile) >> 2, tb = ((wid + 1) * ntile) >> 2;
+    const int ngw = (tb - ta + 1) >> 1;
     const int total = ngw * nkb;
     if (total > 0) {
         uint32_t ring[PD][2 * BITS];
         // next step to load: group tile t0 at p0 (second tile p0 + d1, or p0
-        // itself for an odd last tile), K-block offset koff
-        int t0 = 2 * wid, pleft = total;
+        // itself for a single-tile group), K-block offset koff
+        int t0 = ta, pleft = total;
         const uint8_t* p0 = codes + (tbase + t0) * tile_bytes;
-        int64_t d1 = (t0 + 1 < ntile) ? tile_bytes : 0;
+        int64_t d1 = (t0 + 1 < tb) ? tile_bytes : 0;
         int64_t koff = 0;
         auto load_step = [&](uint32_t* d) {
             load_raw<BITS>(p0 + koff, lane, d);
@@ -540,9 +543,9 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
                 koff += 256 * BITS;
                 if (koff == tile_bytes) {
                     koff = 0;
-                    t0 += 8;
-                    p0 += 8 * tile_bytes;
-                    d1 = (t0 + 1 < ntile) ? tile_bytes : 0;
+                    t0 += 2;
+                    p0 += 2 * tile_bytes;
+                    d1 = (t0 + 1 < tb) ? tile_bytes : 0;
                 }
             }
         };
@@ -559,11 +562,13 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
 #pragma unroll
                         for (int r = 0; r < 16; ++r) acc[a][qt][r] = 0;
             }
+            const int gt0 = ta + 2 * gi;                // first tile of the current group
+            const bool two = gt0 + 1 < tb;              // wave-uniform
 #pragma unroll
             for (int p = 0; p < PD; ++p) {
                 v4i a00, a01, a10, a11;
                 unpack_raw<BITS>(ring[p], a00, a01);
-                unpack_raw<BITS>(ring[p] + BITS, a10, a11);
+                if (two) unpack_raw<BITS>(ring[p] + BITS, a10, a11);
                 load_step(ring[p]);
                 const int kb = kb0 + p;
 #pragma unroll
@@ -571,15 +576,14 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
                     const v4i b0 = *(const v4i*)(qrow + qt * kQT * qstride + 64 * kb);
                     const v4i b1 = *(const v4i*)(qrow + qt * kQT * qstride + 64 * kb + 32);
                     acc[0][qt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a00, b0, acc[0][qt], 0, 0, 0);
-                    acc[1][qt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a10, b0, acc[1][qt], 0, 0, 0);
+                    if (two) acc[1][qt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a10, b0, acc[1][qt], 0, 0, 0);
                     acc[0][qt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a01, b1, acc[0][qt], 0, 0, 0);
-                    acc[1][qt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a11, b1, acc[1][qt], 0, 0, 0);
+                    if (two) acc[1][qt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a11, b1, acc[1][qt], 0, 0, 0);
                 }
             }
             kb0 += PD;
             if (kb0 < nkb) continue;                // next K-steps of the same group
             kb0 = 0;
-            const int g = wid + 4 * gi;
             ++gi;
             // epilogue of group g: estimates, bound test, survivors to the stage.
             // The tile's 16 factor pairs are read from LDS before any is used,
@@ -588,8 +592,8 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
             // not waited for.
 #pragma unroll
             for (int a = 0; a < 2; ++a) {
-                const int tt = 2 * g + a;
-                if (tt >= ntile) break;
+                const int tt = gt0 + a;
+                if (tt >= tb) break;
                 float2 fr[16];
 #pragma unroll
                 for (int r = 0; r < 16; ++r) fr[r] = s_fac[tt * 32 + out_row(lane, r)];   // NaN past the end
