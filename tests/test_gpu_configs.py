@@ -1,0 +1,182 @@
+"""GPU checks at the shapes of the evaluated workloads.
+
+* embed768 at full size (1,000,000 members, 4096 Zipf-skewed lists, D = 768,
+  B = 4, 10,000 queries, nprobe 128, kk = 20: the configuration the benchmark
+  times): the scan through the C ABI against the oracle on a sample of
+  queries, every query of the batch scanned in the same launches.
+* D = 960, lists of 20 to 5,000 members, B in {3, 5, 7}, per-query nprobe
+  mixed by -1 padding of the probe rows, and batches of 1 to 256 queries
+  (a query's result does not depend on its batch).
+* D = 1536, unit-norm clustered vectors, B = 2..8, rotation in FP32 and in
+  BF16 matrix-core precision: estimated-distance error against exact FP64
+  distances and recall@10 against exact k-NN, per bit width.
+* D = 3072, B = 4: scan parity, and served requests with nprobe 16 and 64
+  identical alone and in a mixed batch.
+
+Codes and factors that feed the oracle are synthetic (never produced by the
+GPU path); the D = 1536 check compares GPU results with exact distances.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2409_09913_amd import erq, ivf, serve, synth
+from parity_util import compare_topk, term_scale
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+DEV = torch.device("cuda:0")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _import(off, ids, codes, fa, fr, crot, dp, B):
+    P = synth.haar_orthogonal(dp, seed=2).astype(np.float32)
+    ix = erq.Index(dp, B, len(off) - 1, dev(P))
+    ix.import_(dev(off), dev(ids), dev(codes), dev(fa), dev(fr),
+               dev(np.zeros((len(off) - 1, dp), np.float32)), dev(crot))
+    return ix
+
+
+def _check_sample(gi, ge, off, ids, codes, fa, fr, crot, qrot, probes, B, kk, sample):
+    oi, oe = oracle.search(off, ids, codes, fa, fr, crot, qrot[sample], probes[sample], B, kk, est_mode=0)
+    scale = term_scale(codes, fa, fr, crot, qrot[sample], off, ids, None, probes[sample], B)
+    compare_topk(gi[sample], ge[sample], oi, oe, scale)
+
+
+def test_embed768_full_size_sampled():
+    n, nl, dp, B, nq, nprobe, kk = 1_000_000, 4096, 768, 4, 10_000, 128, 20
+    say("embed768 full size: scan of", nq, "queries, nprobe", nprobe)
+    off, ids, codes, fa, fr, crot = synth.random_index(n, nl, dp, B, seed=901)
+    qrot = synth.random_rotated(nq, dp, seed=902)
+    probes = synth.random_probes(nq, nl, nprobe, seed=903)
+    ix = _import(off, ids, codes, fa, fr, crot, dp, B)
+    gi, ge = ix.scan(dev(qrot), dev(probes), kk)
+    torch.cuda.synchronize()
+    gi, ge = gi.cpu().numpy(), ge.cpu().numpy()
+    ix.close()
+    sample = np.random.default_rng(5).choice(nq, 16, replace=False)
+    _check_sample(gi, ge, off, ids, codes, fa, fr, crot, qrot, probes, B, kk, sample)
+    assert (gi >= 0).all()
+    say("  16 sampled queries match the oracle")
+
+
+def _power_law_sizes(nlist, lo, hi, alpha, seed):
+    g = np.random.default_rng(seed)
+    u = g.random(nlist)
+    s = np.floor(lo * (1.0 - u) ** (-1.0 / alpha)).astype(np.int64)
+    return np.clip(s, lo, hi)
+
+
+@pytest.mark.parametrize("B", [3, 5, 7])
+def test_d960_uneven_lists_mixed_nprobe(B):
+    dp, nl, kk = 960, 96, 10
+    sizes = _power_law_sizes(nl, 20, 5000, 1.1, seed=B)
+    n = int(sizes.sum())
+    say("d960 B", B, "lists", nl, "members", n, "sizes", int(sizes.min()), "-", int(sizes.max()))
+    off, ids, codes, fa, fr, crot = synth.random_index(n, nl, dp, B, seed=910 + B, sizes=sizes)
+    nq, pmax = 256, 64
+    qrot = synth.random_rotated(nq, dp, seed=920 + B)
+    probes = synth.random_probes(nq, nl, pmax, seed=930 + B)
+    own = np.random.default_rng(B).choice([8, 16, 32, 64], nq)
+    for i in range(nq):
+        probes[i, own[i]:] = -1                      # per-query nprobe
+    ix = _import(off, ids, codes, fa, fr, crot, dp, B)
+    gi, ge = ix.scan(dev(qrot), dev(probes), kk)
+    torch.cuda.synchronize()
+    gi, ge = gi.cpu().numpy(), ge.cpu().numpy()
+    _check_sample(gi, ge, off, ids, codes, fa, fr, crot, qrot, probes, B, kk, np.arange(0, nq, 4))
+    # batches of 1 .. 256: the rows of a query are identical in every batch
+    for bs in (1, 4, 16, 64):
+        for lo in (0, 37):
+            bi, be = ix.scan(dev(qrot[lo:lo + bs]), dev(probes[lo:lo + bs]), kk)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(bi.cpu().numpy(), gi[lo:lo + bs])
+            np.testing.assert_array_equal(be.cpu().numpy().view(np.uint32), ge[lo:lo + bs].view(np.uint32))
+    ix.close()
+
+
+def test_d1536_precision_per_bit_width():
+    d, n, nq, k = 1536, 20000, 64, 10
+    x = synth.spherical_clusters(n, d, 256, seed=940)
+    q = synth.spherical_clusters(nq, d, 256, seed=940, stream=synth.S_QUERY)
+    truth, _ = oracle.knn(x, q, k)
+    xd = torch.from_numpy(x).to(DEV)
+    qd = torch.from_numpy(q).to(DEV)
+    P = dev(synth.haar_orthogonal(d, seed=941).astype(np.float32))
+    c = x.astype(np.float64).mean(0, keepdims=True).astype(np.float32)
+    x64, q64 = x.astype(np.float64), q.astype(np.float64)
+    res = {}
+    for prec in (0, 1):
+        for B in range(2, 9):
+            ix = erq.Index(d, B, 1, P)
+            ix.build(xd, dev(c), precision=prec)
+            ids, est = ix.search(qd, 1, 32, 0)
+            torch.cuda.synchronize()
+            ids, est = ids.cpu().numpy(), est.cpu().numpy().astype(np.float64)
+            ix.close()
+            exact = np.stack([((x64[ids[i]] - q64[i]) ** 2).sum(1) for i in range(nq)])
+            rel = np.abs(est - exact) / exact
+            rec = np.mean([len(set(ids[i, :k]) & set(truth[i])) / k for i in range(nq)])
+            res[prec, B] = (float(rel.mean()), float(rel.max()), rec)
+            say("  %s B=%d est rel err avg %.4f max %.4f recall@10 %.3f" %
+                ("bf16" if prec else "fp32", B, rel.mean(), rel.max(), rec))
+    for prec in (0, 1):
+        errs = [res[prec, B][0] for B in range(2, 9)]
+        # one more bit roughly halves the error (Sec. 3): it falls at every
+        # step, and by more than 10x from B = 2 to B = 8 (the int8 query and
+        # FP32 arithmetic put a floor under it at the top)
+        assert all(errs[i + 1] < errs[i] for i in range(len(errs) - 1)), errs
+        assert errs[-1] < 0.1 * errs[0], errs
+        assert res[prec, 8][2] >= 0.9
+    for B in range(2, 9):
+        # BF16 rotation (inputs rounded to 8 mantissa bits) moves the codes a
+        # little; its error stays within 1.5x of the FP32 rotation's plus an offset
+        assert res[1, B][0] <= 1.5 * res[0, B][0] + 2e-3, (B, res[0, B], res[1, B])
+        assert res[1, B][2] >= res[0, B][2] - 0.05
+
+
+def test_d3072_scan_and_serving():
+    dp, B = 3072, 4
+    off, ids, codes, fa, fr, crot = synth.random_index(6000, 24, dp, B, seed=950)
+    qrot = synth.random_rotated(40, dp, seed=951)
+    probes = synth.random_probes(40, 24, 16, seed=952)
+    ix = _import(off, ids, codes, fa, fr, crot, dp, B)
+    gi, ge = ix.scan(dev(qrot), dev(probes), 10)
+    torch.cuda.synchronize()
+    _check_sample(gi.cpu().numpy(), ge.cpu().numpy(), off, ids, codes, fa, fr, crot, qrot, probes, B, 10,
+                  np.arange(40))
+    ix.close()
+    say("d3072 scan parity ok; serving")
+    n, nl = 12000, 64
+    x = torch.from_numpy(synth.gmm(n, dp, 64, 0.3, seed=953)).to(DEV)
+    q = torch.from_numpy(synth.gmm(96, dp, 64, 0.3, seed=953, stream=synth.S_QUERY)).to(DEV)
+    P = dev(synth.haar_orthogonal(dp, seed=954).astype(np.float32))
+    cent, assign = ivf.kmeans(x, nl, iters=3)
+    ix = erq.Index(dp, B, nl, P)
+    ix.build(x, cent, assign, keep_raw=True)
+    srv = serve.Server(ix, max_batch=64, max_nprobe=64, max_k=10, max_rerank=20, slots=2)
+    reqs = [serve.Request(i, q[i * 3:i * 3 + 3], 10, (16, 64)[i % 2], 20) for i in range(32)]
+    for r in reqs:
+        srv.submit(r)
+    srv.drain()
+    torch.cuda.synchronize()
+    for r in reqs:
+        for j in range(3):
+            ai, ad = ix.search(r.q[j:j + 1].contiguous(), r.nprobe, r.k, r.rerank_k)
+            np.testing.assert_array_equal(ai.cpu().numpy(), r.ids[j:j + 1].cpu().numpy())
+            np.testing.assert_array_equal(ad.cpu().numpy().view(np.uint32), r.dist[j:j + 1].cpu().numpy().view(np.uint32))
+    ix.close()

@@ -15,6 +15,7 @@ import torch
 
 import oracle
 from paper_2409_09913_amd import erq, synth
+from parity_util import compare_topk as _compare_topk, term_scale as _term_scale
 
 pytestmark = pytest.mark.gpu
 
@@ -144,41 +145,6 @@ def test_pack_roundtrip(B):
 # ---------------------------------------------------------------------------
 # scan (int8 matrix cores + estimator + top-k)
 # ---------------------------------------------------------------------------
-def _term_scale(codes, fa, fr, crot, qrot, off, ids_o, q_ids, probes, B):
-    """Per query: the largest |f_add| + ||s||^2 + |f_rescale <y,s'>| over its candidates."""
-    out = np.zeros(qrot.shape[0])
-    yb = codes.astype(np.float64) - ((1 << B) - 1) / 2.0
-    for iq in range(qrot.shape[0]):
-        m = 0.0
-        for l in probes[iq]:
-            if l < 0:
-                continue
-            s = qrot[iq].astype(np.float64) - crot[l].astype(np.float64)
-            lo, hi = off[l], off[l + 1]
-            if hi > lo:
-                t = np.abs(fa[lo:hi]) + s @ s + np.abs(fr[lo:hi] * (yb[lo:hi] @ s))
-                m = max(m, float(t.max()))
-        out[iq] = m
-    return out
-
-
-def _compare_topk(gi, ge, oi, oe, scale, rel=1e-4):
-    for q in range(gi.shape[0]):
-        tol = rel * scale[q] + 1e-30
-        valid_o = oi[q] >= 0
-        valid_g = gi[q] >= 0
-        np.testing.assert_array_equal(valid_g, valid_o)
-        assert np.all(np.abs(ge[q][valid_g] - oe[q][valid_o]) <= tol), (q, ge[q], oe[q])
-        sg, so = set(gi[q][valid_g].tolist()), set(oi[q][valid_o].tolist())
-        if sg != so:
-            kth = oe[q][valid_o][-1]
-            for i in sg ^ so:
-                # an id that is in one list only must sit at the boundary (near-tie)
-                pos = np.nonzero(gi[q] == i)[0]
-                val = ge[q][pos[0]] if pos.size else oe[q][np.nonzero(oi[q] == i)[0][0]]
-                assert abs(val - kth) <= 2 * tol, (q, i, val, kth)
-
-
 def _scan_case(n, nl, dp, B, nq, nprobe, kk, seed, sizes=None, empty_lists=0, pad_probes=0, q_at_centroid=0):
     off, ids, codes, fa, fr, crot = synth.random_index(n, nl, dp, B, seed=seed, sizes=sizes,
                                                        empty_lists=empty_lists)
