@@ -63,6 +63,7 @@ def main():
     ap.add_argument("--cpu-sample-queries", type=int, default=32)
     ap.add_argument("--nprobe", type=int, default=0, help="fixed operating point (skips the sweep)")
     ap.add_argument("--rerank", type=int, default=-1, help="fixed re-rank depth (with --nprobe)")
+    ap.add_argument("--tune", type=int, default=1, help="1: run the scan-schedule autotuner before timing")
     ap.add_argument("--graph", type=int, default=1,
                     help="1: the timed steps replay the search captured in a HIP graph; 0: eager calls")
     ap.add_argument("--serve", type=int, default=0,
@@ -179,6 +180,13 @@ def main():
     best2 = None
     if args.bits2:
         best2, _ = sweep(ix2, "B=%d" % args.bits2)
+
+    # ---- scan schedule: the library's autotuner at the operating point ------------------
+    tuned = None
+    if args.tune:
+        tuned = ix.tune(q, nprobe, args.k, rr, reps=2)
+        log("autotune: nqt %d, ring depth %d, round-1 ranks %d (%.3f ms per search)" %
+            (tuned["nqt"], tuned["pd"], tuned["round1"], tuned["ms"]))
 
     # ---- timed region -----------------------------------------------------------------
     ws = torch.empty(ix.search_workspace_size(args.nq, nprobe, args.k, rr), dtype=torch.uint8, device=dev)
@@ -312,6 +320,7 @@ def main():
         "fp32_bruteforce_qps": flat_qps,
         "per_launch_ms": tot,
         "timed_mode": "hip_graph_replay" if graph_dt is not None else "eager",
+        "autotune": tuned,
         "eager_ms_per_step": eager_ms,
         "serving": serving,
         "roofline": roof,

@@ -17,6 +17,7 @@ typedef float v16f __attribute__((ext_vector_type(16)));
 constexpr int kWave = 64;
 constexpr int kTileV = 32;      // vectors per packed code tile (rows of one 32x32 MFMA tile)
 constexpr int kMaxDp = 4096;
+constexpr int kMaxDpNqt2 = 1536;  // largest dp whose two-tile query block fits the LDS
 
 // ---- status plumbing -------------------------------------------------------
 void set_error(const std::string& msg);
@@ -68,6 +69,7 @@ struct Index {
     int64_t* list_off = nullptr;   // nlist + 1 (device)
     int64_t* tile_off = nullptr;   // nlist + 1, offset of each list's first tile (device)
     int32_t* list_order = nullptr; // lists by decreasing size (device)
+    int tune_nqt = 0, tune_pd = 0, tune_round1 = 0;   // scan schedule; 0 = built-in rule
     int64_t* ids = nullptr;        // n, list order
     float2* fac = nullptr;         // n, (f_add, f_rescale), list order
     float2* sfac = nullptr;        // n, (f_add - f_rescale <y_bar, c'>, f_rescale): the scan's factors
@@ -103,6 +105,11 @@ hipError_t launch_quantize(const float* rrot, int64_t n, int dp, int bits, const
 
 // scan pipeline
 size_t scan_workspace_bytes(int64_t nq, int nprobe, int64_t nlist, int kk, int dp, int64_t max_list);
+// scan schedule in effect for an index (stored value if valid, else the rule)
+int scan_nqt(const Index* ix);
+int scan_pd(const Index* ix);
+int scan_round1(const Index* ix);
+bool scan_pd_valid(int pd, int dp, int bits);
 // pdist: ||q' - c'||^2 per (query, probe) (nq x nprobe) or null to compute it
 int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, const float* pdist, int nprobe,
              int kk, int64_t* out_ids, float* out_est, void* ws, size_t ws_bytes, hipStream_t st);

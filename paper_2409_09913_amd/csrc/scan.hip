@@ -1246,25 +1246,25 @@ hipError_t launchB_t(const Index* ix, const ScanArgs& a, const BArgs& b, hipStre
     return launchB_d<BITS, NQT, PD, false>(ix, a, b, st);
 }
 
-// ring depth: 6 when it divides the K-steps per group and the raw words are
-// small (B <= 4), else the largest of 4, 3, 2, 1 that divides them
 template <int BITS, int NQT>
 hipError_t launchB_n(const Index* ix, const ScanArgs& a, const BArgs& b, hipStream_t st)
 {
-    const int nkb = ix->dp / 64;
-    if constexpr (BITS <= 4) {
-        if (nkb % 6 == 0) return launchB_t<BITS, NQT, 6>(ix, a, b, st);
+    switch (scan_pd(ix)) {
+        case 6:
+            if constexpr (BITS <= 4) return launchB_t<BITS, NQT, 6>(ix, a, b, st);
+            break;
+        case 4: return launchB_t<BITS, NQT, 4>(ix, a, b, st);
+        case 3: return launchB_t<BITS, NQT, 3>(ix, a, b, st);
+        case 2: return launchB_t<BITS, NQT, 2>(ix, a, b, st);
+        default: break;
     }
-    if (nkb % 4 == 0) return launchB_t<BITS, NQT, 4>(ix, a, b, st);
-    if (nkb % 3 == 0) return launchB_t<BITS, NQT, 3>(ix, a, b, st);
-    if (nkb % 2 == 0) return launchB_t<BITS, NQT, 2>(ix, a, b, st);
     return launchB_t<BITS, NQT, 1>(ix, a, b, st);
 }
 
 template <int BITS>
 hipError_t launchB_b(const Index* ix, const ScanArgs& a, const BArgs& b, hipStream_t st)
 {
-    if (ix->dp <= 768) return launchB_n<BITS, 2>(ix, a, b, st);
+    if (scan_nqt(ix) == 2) return launchB_n<BITS, 2>(ix, a, b, st);
     return launchB_n<BITS, 1>(ix, a, b, st);
 }
 
@@ -1299,6 +1299,33 @@ hipError_t launchB(const Index* ix, const ScanArgs& a, const BArgs& b, hipStream
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
+
+// Scan schedule: the stored value when it is valid for the index, else the
+// built-in rule (two query tiles per item up to dp = 768; ring depth 6 when
+// it divides the K-steps per group and the raw words are small (B <= 4),
+// else the largest of 4, 3, 2, 1 that divides them; 8 ranks in round 1).
+int scan_nqt(const Index* ix)
+{
+    if (ix->tune_nqt == 1) return 1;
+    if (ix->tune_nqt == 2 && ix->dp <= kMaxDpNqt2) return 2;
+    return ix->dp <= 768 ? 2 : 1;
+}
+
+bool scan_pd_valid(int pd, int dp, int bits)
+{
+    const int nkb = dp / 64;
+    return (pd == 1 || pd == 2 || pd == 3 || pd == 4 || (pd == 6 && bits <= 4)) && nkb % pd == 0;
+}
+
+int scan_pd(const Index* ix)
+{
+    if (ix->tune_pd > 0 && scan_pd_valid(ix->tune_pd, ix->dp, ix->bits)) return ix->tune_pd;
+    for (int pd : {6, 4, 3, 2})
+        if (scan_pd_valid(pd, ix->dp, ix->bits)) return pd;
+    return 1;
+}
+
+int scan_round1(const Index* ix) { return ix->tune_round1 > 0 ? ix->tune_round1 : kRound1; }
 
 hipError_t launch_scan_fac(const uint8_t* codes_u, const int64_t* list_off, int64_t nlist, const float* cent_rot,
                            const float2* fac, int64_t n, int dp, int bits, float2* sfac, hipStream_t st)
@@ -1413,7 +1440,7 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, co
                            mode, tkey, ovf, oi, oe, anyf);
         return hipGetLastError();
     };
-    const int qpiB = (ix->dp <= 768) ? 2 * kQT : kQT;
+    const int qpiB = scan_nqt(ix) * kQT;            // queries per item of the launched kernel
     const int pr = prof_begin(PK_SCAN, st);
     hipError_t e = hipSuccess;
     // queries to int8 once; ||s||^2 per pair from the probe distances, else computed
@@ -1449,7 +1476,7 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, co
     if (e == hipSuccess) e = select(0, nullptr, nullptr);
     zero(gcnt, nq);                                  // the dense entries are found again by the rounds
     // pass B in rounds of increasing probe rank
-    const int bounds[3] = {0, std::min(nprobe, kRound1), nprobe};
+    const int bounds[3] = {0, std::min(nprobe, scan_round1(ix)), nprobe};
     for (int r = 0; r < 2 && e == hipSuccess; ++r) {
         const int rlo = bounds[r], rhi = bounds[r + 1];
         if (rhi <= rlo) continue;

@@ -180,3 +180,51 @@ def test_d3072_scan_and_serving():
             np.testing.assert_array_equal(ai.cpu().numpy(), r.ids[j:j + 1].cpu().numpy())
             np.testing.assert_array_equal(ad.cpu().numpy().view(np.uint32), r.dist[j:j + 1].cpu().numpy().view(np.uint32))
     ix.close()
+
+
+@pytest.mark.parametrize("B", [4, 5])
+def test_scan_schedules_identical_results(B):
+    """Every scan schedule (query tiles per item, codes in flight, first
+    round size) gives bit-identical results; the tuner keeps a valid one."""
+    dp, nl, kk = 768, 48, 20
+    off, ids, codes, fa, fr, crot = synth.random_index(30000, nl, dp, B, seed=960 + B)
+    qrot = synth.random_rotated(150, dp, seed=961)
+    probes = synth.random_probes(150, nl, 24, seed=962)
+    ix = _import(off, ids, codes, fa, fr, crot, dp, B)
+    ri, re = ix.scan(dev(qrot), dev(probes), kk)
+    ri, re = ri.cpu().numpy(), re.cpu().numpy()
+    pds = [p for p in (1, 2, 3, 4, 6) if (dp // 64) % p == 0 and (p != 6 or B <= 4)]
+    for nqt in (1, 2):
+        for pd in pds:
+            for r1 in (1, 8, 30):
+                ix.set_tune(nqt, pd, r1)
+                gi, ge = ix.scan(dev(qrot), dev(probes), kk)
+                torch.cuda.synchronize()
+                np.testing.assert_array_equal(gi.cpu().numpy(), ri, err_msg=str((nqt, pd, r1)))
+                np.testing.assert_array_equal(ge.cpu().numpy().view(np.uint32), re.view(np.uint32))
+    say("  B=%d: %d schedules identical" % (B, 2 * len(pds) * 3))
+    for bad in ((3, 0, 0), (0, 5, 0), (0, 0, 2000), (-1, 0, 0)) + (((0, 6, 0),) if B > 4 else ()):
+        with pytest.raises(erq.ErqError):
+            ix.set_tune(*bad)
+    ix.set_tune(0, 0, 0)
+    ix.close()
+
+
+def test_autotune_search():
+    n, d, nl = 40000, 768, 64
+    x = torch.from_numpy(synth.gmm(n, d, 32, 0.3, seed=970)).to(DEV)
+    q = torch.from_numpy(synth.gmm(500, d, 32, 0.3, seed=970, stream=synth.S_QUERY)).to(DEV)
+    P = dev(synth.haar_orthogonal(d, seed=971).astype(np.float32))
+    cent, assign = ivf.kmeans(x, nl, iters=4)
+    ix = erq.Index(d, 4, nl, P)
+    ix.build(x, cent, assign, keep_raw=True)
+    ri, rd = ix.search(q, 16, 10, 20)
+    ch = ix.tune(q, 16, 10, 20, reps=1)
+    say("  tuned", ch)
+    assert ch["nqt"] in (1, 2) and ch["pd"] in (1, 2, 3, 4, 6) and 1 <= ch["round1"] <= 1024 and ch["ms"] > 0
+    assert ix.get_tune() == {"nqt": ch["nqt"], "pd": ch["pd"], "round1": ch["round1"]}
+    gi, gd = ix.search(q, 16, 10, 20)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(gi.cpu().numpy(), ri.cpu().numpy())
+    np.testing.assert_array_equal(gd.cpu().numpy().view(np.uint32), rd.cpu().numpy().view(np.uint32))
+    ix.close()
