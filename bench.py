@@ -64,6 +64,8 @@ def main():
     ap.add_argument("--nprobe", type=int, default=0, help="fixed operating point (skips the sweep)")
     ap.add_argument("--rerank", type=int, default=-1, help="fixed re-rank depth (with --nprobe)")
     ap.add_argument("--tune", type=int, default=1, help="1: run the scan-schedule autotuner before timing")
+    ap.add_argument("--schedule", type=str, default="",
+                    help="nqt,pd,round1: fixed scan schedule (with --tune 0), e.g. the tuner's choice")
     ap.add_argument("--graph", type=int, default=1,
                     help="1: the timed steps replay the search captured in a HIP graph; 0: eager calls")
     ap.add_argument("--serve", type=int, default=0,
@@ -183,7 +185,12 @@ def main():
 
     # ---- scan schedule: the library's autotuner at the operating point ------------------
     tuned = None
-    if args.tune:
+    if args.schedule:
+        nqt_, pd_, r1_ = (int(v) for v in args.schedule.split(","))
+        ix.set_tune(nqt_, pd_, r1_)
+        tuned = dict(ix.get_tune(), ms=None, fixed=True)
+        log("fixed scan schedule", tuned)
+    if args.tune and not args.schedule:
         tuned = ix.tune(q, nprobe, args.k, rr, reps=2)
         log("autotune: nqt %d, ring depth %d, round-1 ranks %d (%.3f ms per search)" %
             (tuned["nqt"], tuned["pd"], tuned["round1"], tuned["ms"]))
