@@ -82,9 +82,11 @@ int erq_quantize(const float* rrot, int64_t n, int32_t dp, int32_t bits,
 /* may order differently from exact arithmetic.                             */
 /* q: nq x dp raw queries, centroids: nlist x dp.                           */
 /* probes: nq x nprobe int32 (output), pdist: nq x nprobe FP32 or NULL.       */
-/* nprobe in [1, min(nlist, 1024)].  workspace: erq_probe_workspace_size.    */
+/* nprobe in [1, min(nlist, 1024)].  workspace: erq_probe_workspace_size     */
+/* (it holds the nq x nlist distances and the BF16 hi/lo planes of q and    */
+/* the centroids, so it depends on dp).                                      */
 /* ------------------------------------------------------------------------ */
-int erq_probe_workspace_size(int64_t nq, int64_t nlist, int32_t nprobe, size_t* bytes);
+int erq_probe_workspace_size(int64_t nq, int64_t nlist, int32_t dp, int32_t nprobe, size_t* bytes);
 int erq_coarse_probe(const float* q, int64_t nq, const float* centroids, int64_t nlist,
                      int32_t dp, int32_t nprobe, int32_t* probes, float* pdist,
                      void* workspace, size_t ws_bytes, void* stream);

@@ -11,7 +11,9 @@ namespace erq {
 
 // launchers defined in the other translation units
 hipError_t launch_row_sqnorm(const float* X, int64_t n, int K, float* out, hipStream_t st);
-hipError_t launch_sqdist_pre(const float* A, int64_t n, const float* Bm, int64_t N, int K,
+hipError_t launch_split_bf16(const float* x, int64_t n, unsigned short* hi, unsigned short* lo, hipStream_t st);
+hipError_t launch_sqdist_pre(const unsigned short* Ah, const unsigned short* Al, int64_t n,
+                             const unsigned short* Bh, const unsigned short* Bl, int64_t N, int K,
                              const float* an2, const float* bn2, float* out, hipStream_t st);
 hipError_t launch_pack_n(const uint8_t* codes, const int64_t* list_off, const int64_t* tile_off,
                          int64_t nlist, int dp, int bits, int64_t ntiles, uint8_t* packed, hipStream_t st);
@@ -147,22 +149,30 @@ int set_list_meta(Index* ix, const std::vector<int64_t>& off, hipStream_t st) {
 int probe_impl(const float* q, int64_t nq, const float* cent, int64_t nlist, int dp, int nprobe,
                int32_t* probes, float* pdist, void* ws, size_t ws_bytes, hipStream_t st);
 
-size_t probe_ws(int64_t nq, int64_t nlist) {
-    return align256(sizeof(float) * nq * nlist) + align256(sizeof(float) * nq) + align256(sizeof(float) * nlist);
+// distances nq x nlist, norms, and the BF16 hi/lo planes of both operands
+size_t probe_ws(int64_t nq, int64_t nlist, int dp) {
+    return align256(sizeof(float) * nq * nlist) + align256(sizeof(float) * nq) + align256(sizeof(float) * nlist) +
+           2 * align256(sizeof(unsigned short) * nq * dp) + 2 * align256(sizeof(unsigned short) * nlist * dp);
 }
 
 int probe_impl(const float* q, int64_t nq, const float* cent, int64_t nlist, int dp, int nprobe,
                int32_t* probes, float* pdist, void* ws, size_t ws_bytes, hipStream_t st)
 {
-    if (ws_bytes < probe_ws(nq, nlist)) return fail(ERQ_ENOMEM, "coarse probe: workspace too small");
+    if (ws_bytes < probe_ws(nq, nlist, dp)) return fail(ERQ_ENOMEM, "coarse probe: workspace too small");
     char* w = (char*)ws;
     float* D = (float*)w; w += align256(sizeof(float) * nq * nlist);
     float* qn = (float*)w; w += align256(sizeof(float) * nq);
-    float* cn = (float*)w;
+    float* cn = (float*)w; w += align256(sizeof(float) * nlist);
+    unsigned short* qh = (unsigned short*)w; w += align256(sizeof(unsigned short) * nq * dp);
+    unsigned short* ql = (unsigned short*)w; w += align256(sizeof(unsigned short) * nq * dp);
+    unsigned short* ch = (unsigned short*)w; w += align256(sizeof(unsigned short) * nlist * dp);
+    unsigned short* cl = (unsigned short*)w;
     ERQ_HIP(launch_row_sqnorm(q, nq, dp, qn, st));
     ERQ_HIP(launch_row_sqnorm(cent, nlist, dp, cn, st));
     int pr = prof_begin(PK_PROBE, st);
-    ERQ_HIP(launch_sqdist_pre(q, nq, cent, nlist, dp, qn, cn, D, st));
+    ERQ_HIP(launch_split_bf16(q, nq * dp, qh, ql, st));
+    ERQ_HIP(launch_split_bf16(cent, nlist * dp, ch, cl, st));
+    ERQ_HIP(launch_sqdist_pre(qh, ql, nq, ch, cl, nlist, dp, qn, cn, D, st));
     ERQ_HIP(launch_row_topk(D, nq, nlist, nprobe, probes, pdist, st));
     prof_end(pr, st);
     return ERQ_OK;
@@ -205,10 +215,11 @@ int erq_quantize(const float* rrot, int64_t n, int32_t dp, int32_t bits, const f
     return ERQ_OK;
 }
 
-int erq_probe_workspace_size(int64_t nq, int64_t nlist, int32_t nprobe, size_t* bytes)
+int erq_probe_workspace_size(int64_t nq, int64_t nlist, int32_t dp, int32_t nprobe, size_t* bytes)
 {
-    if (!bytes || nq < 0 || nlist < 1 || nprobe < 1) return fail(ERQ_EINVAL, "erq_probe_workspace_size: bad arguments");
-    *bytes = probe_ws(nq, nlist);
+    if (!bytes || nq < 0 || nlist < 1 || nprobe < 1 || dp < 64 || dp % 64 != 0)
+        return fail(ERQ_EINVAL, "erq_probe_workspace_size: bad arguments");
+    *bytes = probe_ws(nq, nlist, dp);
     return ERQ_OK;
 }
 
@@ -334,7 +345,7 @@ int erq_index_build(erq_index ix, const float* x, int64_t n, const float* centro
     } else if (n > 0) {
         const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(n, (int64_t)(1LL << 28) / C));
         void* pws = nullptr;
-        size_t pb = probe_ws(chunk, C);
+        size_t pb = probe_ws(chunk, C, dp);
         ERQ_HIP(hipMalloc(&pws, pb));
         guard.p.push_back(pws);
         for (int64_t r0 = 0; r0 < n; r0 += chunk) {
@@ -467,7 +478,7 @@ static size_t search_ws(Index* ix, int64_t nq, int nprobe, int k, int rerank_k) 
     b += align256(sizeof(float) * nq * nprobe);           // probe distances ||q - c||^2
     b += align256(sizeof(int64_t) * nq * kk);             // candidate ids
     b += align256(sizeof(float) * nq * kk);               // candidate estimates
-    b += std::max(probe_ws(nq, ix->nlist), scan_workspace_bytes(nq, nprobe, ix->nlist, kk, ix->dp, ix->max_list));
+    b += std::max(probe_ws(nq, ix->nlist, ix->dp), scan_workspace_bytes(nq, nprobe, ix->nlist, kk, ix->dp, ix->max_list));
     return b;
 }
 

@@ -215,79 +215,91 @@ hipError_t launch_row_sqnorm(const float* X, int64_t n, int K, float* out, hipSt
 }
 
 // dist = ||a||^2 + ||b||^2 - 2 a.b, with norms an2 (n) and bn2 (N) precomputed
+// FP32 -> two BF16 planes: hi = bf16(x) and lo = bf16(x - hi) (x - hi is
+// exact, so x = hi + lo to 2^-17 relative); bit patterns, 4 elements per
+// thread, n a multiple of 4.
+__global__ __launch_bounds__(256) void split_bf16_kernel(const float* __restrict__ x, int64_t n,
+                                                         unsigned short* __restrict__ hi,
+                                                         unsigned short* __restrict__ lo)
+{
+    const int64_t i = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+    if (i >= n) return;
+    const float4 v = *(const float4*)(x + i);
+    const float xv[4] = {v.x, v.y, v.z, v.w};
+    unsigned h[4], l[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        h[c] = f2bf(xv[c]);
+        l[c] = f2bf(xv[c] - __uint_as_float(h[c] << 16));
+    }
+    *(uint2*)(hi + i) = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+    *(uint2*)(lo + i) = make_uint2(l[0] | (l[1] << 16), l[2] | (l[3] << 16));
+}
+
+__device__ inline uint4 ld16(const unsigned short* p, bool ok) {
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (ok) v = *(const uint4*)p;
+    return v;
+}
+
 // Squared distances ||a||^2 + ||b||^2 - 2 a.b of the coarse probe with the
-// products on the BF16 matrix cores: every FP32 operand is split into
-// hi = bf16(x) and lo = bf16(x - hi) (x - hi is exact, x = hi + lo to 2^-17
-// relative), and a.b = hi.hi + hi.lo + lo.hi in FP32 accumulation.  Each
-// product is off by at most 2^-15 |a_i b_i| (the dropped lo.lo and the two
-// split residuals), so a distance by at most 2^-14 sum|a_i b_i| plus FP32
-// accumulation: a few units in the 5th digit, enough to order centroids
-// except near-ties.  B is N x K
-// (row-major).  Tile 128 x 128, K staged 32 at a time in two LDS buffers; the
-// next K-tile is loaded into registers while the current one is multiplied.
-__global__ __launch_bounds__(256) void sqdist_bf16x3_kernel(
-    const float* __restrict__ A, int64_t n, int K, const float* __restrict__ B, int N,
+// products on the BF16 matrix cores, from operands split beforehand into hi
+// and lo BF16 planes (split_bf16_kernel): a.b = lo.hi + hi.lo + hi.hi per
+// 16-wide K chunk, FP32 accumulation.  Each product is off by at most
+// 2^-15 |a_i b_i| (the dropped lo.lo and the two split residuals), so a
+// distance by at most 2^-14 sum|a_i b_i| plus FP32 accumulation: a few units
+// in the 5th digit, enough to order centroids except near-ties.  A is n x K,
+// B is N x K (row-major planes), K a multiple of 32.  Tile 128 x 128, K
+// staged 32 at a time in one LDS buffer (40 KB, so several blocks share a
+// CU); the next K-tile is loaded into registers while the current one is
+// multiplied.
+__global__ __launch_bounds__(256, 3) void sqdist_bf16x3_kernel(
+    const unsigned short* __restrict__ Ahg, const unsigned short* __restrict__ Alg, int64_t n, int K,
+    const unsigned short* __restrict__ Bhg, const unsigned short* __restrict__ Blg, int N,
     float* __restrict__ out, int64_t ldo, const float* __restrict__ an2, const float* __restrict__ bn2)
 {
     constexpr int BK = 32, LD = BK + 8;
-    __shared__ unsigned short Ah[2][BM][LD], Al[2][BM][LD], Bh[2][BN][LD], Bl[2][BN][LD];
+    __shared__ __align__(16) unsigned short Ah[BM][LD], Al[BM][LD], Bh[BN][LD], Bl[BN][LD];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int64_t row0 = (int64_t)blockIdx.y * BM;
     const int col0 = blockIdx.x * BN;
     const int wm = (wid >> 1) * 64, wn = (wid & 1) * 64;
     v16f acc[2][2];
     for (int a = 0; a < 2; ++a) for (int b = 0; b < 2; ++b) for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
-    // 128 rows x 32 k per operand = 4 float4 per thread
-    float4 ra[4], rb[4];
-    auto load = [&](int k0) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int e = tid + 256 * i;
-            const int m = e >> 3, kq = (e & 7) * 4;
-            const int64_t gr = row0 + m;
-            ra[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (gr < n && k0 + kq < K) ra[i] = *(const float4*)(A + gr * (int64_t)K + k0 + kq);
-            const int gc = col0 + m;
-            rb[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (gc < N && k0 + kq < K) rb[i] = *(const float4*)(B + (int64_t)gc * K + k0 + kq);
-        }
-    };
-    auto split = [&](float x, unsigned short& h, unsigned short& l) {
-        h = f2bf(x);
-        const float xh = __uint_as_float((unsigned)h << 16);
-        l = f2bf(x - xh);
-    };
-    auto store = [&](int buf) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int e = tid + 256 * i;
-            const int m = e >> 3, kq = (e & 7) * 4;
-            const float av[4] = {ra[i].x, ra[i].y, ra[i].z, ra[i].w};
-            const float bv[4] = {rb[i].x, rb[i].y, rb[i].z, rb[i].w};
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                split(av[c], Ah[buf][m][kq + c], Al[buf][m][kq + c]);
-                split(bv[c], Bh[buf][m][kq + c], Bl[buf][m][kq + c]);
-            }
-        }
-    };
-    load(0);
-    store(0);
+    // per K-tile and plane: 128 rows x 32 k = 512 chunks of 16 bytes; thread
+    // tid moves chunks tid and tid + 256 (row m = e/4, k offset 8*(e%4))
+    const int m0 = tid >> 2, m1 = m0 + 64, kq = (tid & 3) * 8;
+    const bool a0 = row0 + m0 < n, a1 = row0 + m1 < n, b0 = col0 + m0 < N, b1 = col0 + m1 < N;
+    const unsigned short* pa0h = Ahg + (row0 + m0) * K + kq;
+    const unsigned short* pa1h = Ahg + (row0 + m1) * K + kq;
+    const unsigned short* pa0l = Alg + (row0 + m0) * K + kq;
+    const unsigned short* pa1l = Alg + (row0 + m1) * K + kq;
+    const unsigned short* pb0h = Bhg + (int64_t)(col0 + m0) * K + kq;
+    const unsigned short* pb1h = Bhg + (int64_t)(col0 + m1) * K + kq;
+    const unsigned short* pb0l = Blg + (int64_t)(col0 + m0) * K + kq;
+    const unsigned short* pb1l = Blg + (int64_t)(col0 + m1) * K + kq;
+    uint4 r0 = ld16(pa0h, a0), r1 = ld16(pa1h, a1), r2 = ld16(pa0l, a0), r3 = ld16(pa1l, a1);
+    uint4 r4 = ld16(pb0h, b0), r5 = ld16(pb1h, b1), r6 = ld16(pb0l, b0), r7 = ld16(pb1l, b1);
+    *(uint4*)&Ah[m0][kq] = r0; *(uint4*)&Ah[m1][kq] = r1; *(uint4*)&Al[m0][kq] = r2; *(uint4*)&Al[m1][kq] = r3;
+    *(uint4*)&Bh[m0][kq] = r4; *(uint4*)&Bh[m1][kq] = r5; *(uint4*)&Bl[m0][kq] = r6; *(uint4*)&Bl[m1][kq] = r7;
     __syncthreads();
-    int cur = 0;
     for (int k0 = 0; k0 < K; k0 += BK) {
         const bool more = k0 + BK < K;
-        if (more) load(k0 + BK);
+        if (more) {                                 // next K-tile into registers while this one is multiplied
+            const int k1 = k0 + BK;
+            r0 = ld16(pa0h + k1, a0); r1 = ld16(pa1h + k1, a1); r2 = ld16(pa0l + k1, a0); r3 = ld16(pa1l + k1, a1);
+            r4 = ld16(pb0h + k1, b0); r5 = ld16(pb1h + k1, b1); r6 = ld16(pb0l + k1, b0); r7 = ld16(pb1l + k1, b1);
+        }
 #pragma unroll
         for (int ks = 0; ks < BK; ks += 16) {
             const int kk = ks + 8 * (lane >> 5);
             v8bf ah[2], al[2], bh[2], bl[2];
 #pragma unroll
             for (int t = 0; t < 2; ++t) {
-                __builtin_memcpy(&ah[t], &Ah[cur][wm + 32 * t + (lane & 31)][kk], 16);
-                __builtin_memcpy(&al[t], &Al[cur][wm + 32 * t + (lane & 31)][kk], 16);
-                __builtin_memcpy(&bh[t], &Bh[cur][wn + 32 * t + (lane & 31)][kk], 16);
-                __builtin_memcpy(&bl[t], &Bl[cur][wn + 32 * t + (lane & 31)][kk], 16);
+                __builtin_memcpy(&ah[t], &Ah[wm + 32 * t + (lane & 31)][kk], 16);
+                __builtin_memcpy(&al[t], &Al[wm + 32 * t + (lane & 31)][kk], 16);
+                __builtin_memcpy(&bh[t], &Bh[wn + 32 * t + (lane & 31)][kk], 16);
+                __builtin_memcpy(&bl[t], &Bl[wn + 32 * t + (lane & 31)][kk], 16);
             }
 #pragma unroll
             for (int a = 0; a < 2; ++a)
@@ -298,9 +310,12 @@ __global__ __launch_bounds__(256) void sqdist_bf16x3_kernel(
                     acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
                 }
         }
-        if (more) store(cur ^ 1);
-        __syncthreads();
-        cur ^= 1;
+        __syncthreads();                        // every read of this K-tile is done
+        if (more) {
+            *(uint4*)&Ah[m0][kq] = r0; *(uint4*)&Ah[m1][kq] = r1; *(uint4*)&Al[m0][kq] = r2; *(uint4*)&Al[m1][kq] = r3;
+            *(uint4*)&Bh[m0][kq] = r4; *(uint4*)&Bh[m1][kq] = r5; *(uint4*)&Bl[m0][kq] = r6; *(uint4*)&Bl[m1][kq] = r7;
+            __syncthreads();
+        }
     }
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b) {
@@ -314,12 +329,21 @@ __global__ __launch_bounds__(256) void sqdist_bf16x3_kernel(
         }
 }
 
-hipError_t launch_sqdist_pre(const float* A, int64_t n, const float* Bm, int64_t N, int K,
+hipError_t launch_split_bf16(const float* x, int64_t n, unsigned short* hi, unsigned short* lo, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(split_bf16_kernel, dim3((unsigned)((n / 4 + 255) / 256)), dim3(256), 0, st, x, n, hi, lo);
+    return hipGetLastError();
+}
+
+hipError_t launch_sqdist_pre(const unsigned short* Ah, const unsigned short* Al, int64_t n,
+                             const unsigned short* Bh, const unsigned short* Bl, int64_t N, int K,
                              const float* an2, const float* bn2, float* out, hipStream_t st)
 {
     if (n <= 0 || N <= 0) return hipSuccess;
     dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((n + BM - 1) / BM));
-    hipLaunchKernelGGL(sqdist_bf16x3_kernel, grid, dim3(256), 0, st, A, n, K, Bm, (int)N, out, (int64_t)N, an2, bn2);
+    hipLaunchKernelGGL(sqdist_bf16x3_kernel, grid, dim3(256), 0, st, Ah, Al, n, K, Bh, Bl, (int)N, out,
+                       (int64_t)N, an2, bn2);
     return hipGetLastError();
 }
 

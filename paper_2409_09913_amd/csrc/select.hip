@@ -31,7 +31,7 @@ __global__ __launch_bounds__(kSelThreads) void row_topk_kernel(
     __shared__ unsigned hist[256];
     __shared__ unsigned skey[kSelMaxK];
     __shared__ int sidx[kSelMaxK];
-    __shared__ unsigned scan_l[kSelThreads], scan_e[kSelThreads];
+    __shared__ unsigned scan_l[kSelThreads / 64], scan_e[kSelThreads / 64];
     __shared__ unsigned s_digit, s_kr, s_wsum[kSelThreads / 64];
     const int tid = threadIdx.x;
     const int64_t row = blockIdx.x;
@@ -110,19 +110,23 @@ __global__ __launch_bounds__(kSelThreads) void row_topk_kernel(
             if (R > 0) break;
         }
     }
-    scan_l[tid] = nl; scan_e[tid] = ne;
-    __syncthreads();
-    if (tid == 0) {
-        unsigned a = 0, b = 0;
-        for (int t = 0; t < kSelThreads; ++t) {
-            unsigned x = scan_l[t], y = scan_e[t];
-            scan_l[t] = a; scan_e[t] = b;
-            a += x; b += y;
+    // exclusive prefix sums of both counts over the threads (chunk order)
+    unsigned pl, pe;
+    {
+        const int lane = tid & 63, wid = tid >> 6;
+        unsigned x = nl, y = ne;
+        for (int o = 1; o < 64; o <<= 1) {
+            const unsigned xu = __shfl_up(x, o), yu = __shfl_up(y, o);
+            if (lane >= o) { x += xu; y += yu; }
         }
+        if (lane == 63) { scan_l[wid] = x; scan_e[wid] = y; }
+        __syncthreads();
+        unsigned bl = 0, be = 0;
+        for (int w = 0; w < wid; ++w) { bl += scan_l[w]; be += scan_e[w]; }
+        pl = bl + x - nl;
+        pe = be + y - ne;
     }
-    __syncthreads();
     const unsigned nless = (unsigned)kk - need_eq;
-    unsigned pl = scan_l[tid], pe = scan_e[tid];
     if (kk > 0) {
 #pragma unroll
         for (int u = 0; u < RR; ++u) {

@@ -24,7 +24,7 @@ SIGNATURES = {
     "erq_version": (C.c_int, []),
     "erq_rotate": (C.c_int, [_p, _i64, _i32, _p, _i32, _p, _p]),
     "erq_quantize": (C.c_int, [_p, _i64, _i32, _i32, _p, _p, _p, _p, _p, _p]),
-    "erq_probe_workspace_size": (C.c_int, [_i64, _i64, _i32, C.POINTER(_sz)]),
+    "erq_probe_workspace_size": (C.c_int, [_i64, _i64, _i32, _i32, C.POINTER(_sz)]),
     "erq_coarse_probe": (C.c_int, [_p, _i64, _p, _i64, _i32, _i32, _p, _p, _p, _sz, _p]),
     "erq_index_create": (C.c_int, [_i32, _i32, _i64, _p, _p, C.POINTER(_p)]),
     "erq_index_destroy": (C.c_int, [_p]),
@@ -126,7 +126,7 @@ def coarse_probe(q, centroids, nprobe: int, with_dist: bool = False):
     nq, dp = q.shape
     nl = centroids.shape[0]
     sz = C.c_size_t()
-    _check(load().erq_probe_workspace_size(nq, nl, nprobe, C.byref(sz)))
+    _check(load().erq_probe_workspace_size(nq, nl, q.shape[1], nprobe, C.byref(sz)))
     ws = _ws(sz.value, q.device)
     probes = torch.empty((nq, nprobe), dtype=torch.int32, device=q.device)
     pd = torch.empty((nq, nprobe), dtype=torch.float32, device=q.device) if with_dist else None

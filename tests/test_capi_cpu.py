@@ -55,6 +55,7 @@ def test_argument_validation_without_device_work():
     assert lib.erq_index_create(64, 0, 4, nul, nul, C.byref(h)) == erq.ERQ_EUNSUPPORTED
     assert lib.erq_index_create(64, 4, 0, nul, nul, C.byref(h)) == erq.ERQ_EINVAL
     sz = C.c_size_t()
-    assert lib.erq_probe_workspace_size(10, 0, 1, C.byref(sz)) == erq.ERQ_EINVAL
-    assert lib.erq_probe_workspace_size(10, 16, 4, C.byref(sz)) == erq.ERQ_OK and sz.value >= 10 * 16 * 4
+    assert lib.erq_probe_workspace_size(10, 0, 64, 1, C.byref(sz)) == erq.ERQ_EINVAL
+    assert lib.erq_probe_workspace_size(10, 16, 100, 4, C.byref(sz)) == erq.ERQ_EINVAL   # dp not a multiple of 64
+    assert lib.erq_probe_workspace_size(10, 16, 64, 4, C.byref(sz)) == erq.ERQ_OK and sz.value >= 10 * 16 * 4 + 26 * 64 * 4
     assert lib.erq_index_destroy(nul) == erq.ERQ_OK
