@@ -168,8 +168,11 @@ int erq_rerank(erq_index idx, const float* q, int64_t nq, const int64_t* cand, i
 
 /* ------------------------------------------------------------------------ */
 /* Whole query path: rotate, coarse probe, scan, and (rerank_k > 0) exact    */
-/* re-rank of the rerank_k best estimates.  Output nq x k: estimated squared */
-/* distances without re-rank, exact ones with it.  k <= 32, rerank_k <= 32.  */
+/* re-rank of the rerank_k best estimates.  The rotation q' = q P uses the   */
+/* probe's BF16 hi/lo products (error <= 2^-14 sum_k |q_k P_kj| per output,  */
+/* about the FP32 accumulation bound at dp = 768); erq_rotate keeps the FP32 */
+/* and BF16 modes.  Output nq x k: estimated squared distances without       */
+/* re-rank, exact ones with it.  k <= 32, rerank_k <= 32.                    */
 /* workspace: erq_search_workspace_size.                                     */
 /* ------------------------------------------------------------------------ */
 int erq_search_workspace_size(erq_index idx, int64_t nq, int32_t nprobe, int32_t k,

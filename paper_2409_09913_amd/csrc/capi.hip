@@ -12,6 +12,10 @@ namespace erq {
 // launchers defined in the other translation units
 hipError_t launch_row_sqnorm(const float* X, int64_t n, int K, float* out, hipStream_t st);
 hipError_t launch_split_bf16(const float* x, int64_t n, unsigned short* hi, unsigned short* lo, hipStream_t st);
+hipError_t launch_split_bf16_t(const float* x, int K, int N, unsigned short* hi, unsigned short* lo, hipStream_t st);
+hipError_t launch_gemm_bf16x3(const unsigned short* Ah, const unsigned short* Al, int64_t n,
+                              const unsigned short* Bh, const unsigned short* Bl, int64_t N, int K,
+                              float* out, int64_t ldo, hipStream_t st);
 hipError_t launch_sqdist_pre(const unsigned short* Ah, const unsigned short* Al, int64_t n,
                              const unsigned short* Bh, const unsigned short* Bl, int64_t N, int K,
                              const float* an2, const float* bn2, float* out, hipStream_t st);
@@ -147,7 +151,8 @@ int set_list_meta(Index* ix, const std::vector<int64_t>& off, hipStream_t st) {
 }
 
 int probe_impl(const float* q, int64_t nq, const float* cent, int64_t nlist, int dp, int nprobe,
-               int32_t* probes, float* pdist, void* ws, size_t ws_bytes, hipStream_t st);
+               int32_t* probes, float* pdist, void* ws, size_t ws_bytes, hipStream_t st,
+               const unsigned short* qh_pre = nullptr, const unsigned short* ql_pre = nullptr);
 
 // distances nq x nlist, norms, and the BF16 hi/lo planes of both operands
 size_t probe_ws(int64_t nq, int64_t nlist, int dp) {
@@ -155,8 +160,10 @@ size_t probe_ws(int64_t nq, int64_t nlist, int dp) {
            2 * align256(sizeof(unsigned short) * nq * dp) + 2 * align256(sizeof(unsigned short) * nlist * dp);
 }
 
+// qh_pre / ql_pre: the queries' BF16 planes when the caller has them (else split here)
 int probe_impl(const float* q, int64_t nq, const float* cent, int64_t nlist, int dp, int nprobe,
-               int32_t* probes, float* pdist, void* ws, size_t ws_bytes, hipStream_t st)
+               int32_t* probes, float* pdist, void* ws, size_t ws_bytes, hipStream_t st,
+               const unsigned short* qh_pre, const unsigned short* ql_pre)
 {
     if (ws_bytes < probe_ws(nq, nlist, dp)) return fail(ERQ_ENOMEM, "coarse probe: workspace too small");
     char* w = (char*)ws;
@@ -170,7 +177,8 @@ int probe_impl(const float* q, int64_t nq, const float* cent, int64_t nlist, int
     ERQ_HIP(launch_row_sqnorm(q, nq, dp, qn, st));
     ERQ_HIP(launch_row_sqnorm(cent, nlist, dp, cn, st));
     int pr = prof_begin(PK_PROBE, st);
-    ERQ_HIP(launch_split_bf16(q, nq * dp, qh, ql, st));
+    if (qh_pre && ql_pre) { qh = (unsigned short*)qh_pre; ql = (unsigned short*)ql_pre; }
+    else ERQ_HIP(launch_split_bf16(q, nq * dp, qh, ql, st));
     ERQ_HIP(launch_split_bf16(cent, nlist * dp, ch, cl, st));
     ERQ_HIP(launch_sqdist_pre(qh, ql, nq, ch, cl, nlist, dp, qn, cn, D, st));
     ERQ_HIP(launch_row_topk(D, nq, nlist, nprobe, probes, pdist, st));
@@ -245,8 +253,14 @@ int erq_index_create(int32_t dp, int32_t bits, int64_t nlist, const float* P, vo
     hipGetDevice(&ix->device);
     if (hipMalloc(&ix->P, sizeof(float) * dp * dp) != hipSuccess) { delete ix; return fail(ERQ_ENOMEM, "erq_index_create: hipMalloc failed"); }
     hipError_t e = hipMemcpyAsync(ix->P, P, sizeof(float) * dp * dp, hipMemcpyDeviceToDevice, (hipStream_t)stream);
+    if (e == hipSuccess) e = hipMalloc(&ix->pt_hi, sizeof(unsigned short) * dp * dp);
+    if (e == hipSuccess) e = hipMalloc(&ix->pt_lo, sizeof(unsigned short) * dp * dp);
+    if (e == hipSuccess) e = launch_split_bf16_t(ix->P, dp, dp, ix->pt_hi, ix->pt_lo, (hipStream_t)stream);
     if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
-    if (e != hipSuccess) { hipFree(ix->P); delete ix; return fail(ERQ_EDEVICE, std::string("erq_index_create: ") + hipGetErrorString(e)); }
+    if (e != hipSuccess) {
+        hipFree(ix->P); hipFree(ix->pt_hi); hipFree(ix->pt_lo); delete ix;
+        return fail(ERQ_EDEVICE, std::string("erq_index_create: ") + hipGetErrorString(e));
+    }
     *out = ix;
     return ERQ_OK;
 }
@@ -257,6 +271,8 @@ int erq_index_destroy(erq_index ix)
     hipDeviceSynchronize();
     free_index_storage(ix);
     hipFree(ix->P);
+    hipFree(ix->pt_hi);
+    hipFree(ix->pt_lo);
     hipFree(ix->raw);
     delete ix;
     return ERQ_OK;
@@ -478,6 +494,7 @@ static size_t search_ws(Index* ix, int64_t nq, int nprobe, int k, int rerank_k) 
     b += align256(sizeof(float) * nq * nprobe);           // probe distances ||q - c||^2
     b += align256(sizeof(int64_t) * nq * kk);             // candidate ids
     b += align256(sizeof(float) * nq * kk);               // candidate estimates
+    b += 2 * align256(sizeof(unsigned short) * nq * ix->dp);   // BF16 hi/lo planes of the queries
     b += std::max(probe_ws(nq, ix->nlist, ix->dp), scan_workspace_bytes(nq, nprobe, ix->nlist, kk, ix->dp, ix->max_list));
     return b;
 }
@@ -509,12 +526,17 @@ int erq_search(erq_index ix, const float* q, int64_t nq, int32_t nprobe, int32_t
     float* pdist = (float*)w; w += align256(sizeof(float) * nq * nprobe);
     int64_t* cid = (int64_t*)w; w += align256(sizeof(int64_t) * nq * kk);
     float* cest = (float*)w; w += align256(sizeof(float) * nq * kk);
+    unsigned short* qh = (unsigned short*)w; w += align256(sizeof(unsigned short) * nq * ix->dp);
+    unsigned short* ql = (unsigned short*)w; w += align256(sizeof(unsigned short) * nq * ix->dp);
     size_t rest = ws_bytes - (size_t)(w - (char*)workspace);
+    // q' = q P on the BF16 matrix cores from hi/lo planes (the probe's
+    // products and error bound); the planes serve the probe too
     int pr = prof_begin(PK_ROTATE, st);
-    ERQ_HIP(launch_gemm(q, nq, ix->dp, ix->P, ix->dp, 0, 0, qrot, ix->dp, st));
+    ERQ_HIP(launch_split_bf16(q, nq * ix->dp, qh, ql, st));
+    ERQ_HIP(launch_gemm_bf16x3(qh, ql, nq, ix->pt_hi, ix->pt_lo, ix->dp, ix->dp, qrot, ix->dp, st));
     prof_end(pr, st);
     // the probe's ||q - c||^2 = ||q' - c'||^2 (P orthogonal) is the scan's ||s||^2
-    if (int rc = probe_impl(q, nq, ix->cent, ix->nlist, ix->dp, nprobe, probes, pdist, w, rest, st)) return rc;
+    if (int rc = probe_impl(q, nq, ix->cent, ix->nlist, ix->dp, nprobe, probes, pdist, w, rest, st, qh, ql)) return rc;
     if (int rc = run_scan(ix, qrot, nq, probes, pdist, nprobe, kk, cid, cest, w, rest, st)) return rc;
     if (rerank_k > 0) {
         int pr2 = prof_begin(PK_RERANK, st);

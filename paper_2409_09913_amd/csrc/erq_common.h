@@ -64,6 +64,8 @@ struct Index {
     int64_t nlist = 0, n = 0;
     int device = 0;
     float* P = nullptr;            // dp x dp
+    unsigned short* pt_hi = nullptr;   // BF16 hi/lo planes of P^T (dp x dp each): the search's rotation
+    unsigned short* pt_lo = nullptr;
     float* cent = nullptr;         // nlist x dp raw centroids
     float* cent_rot = nullptr;     // nlist x dp rotated centroids
     int64_t* list_off = nullptr;   // nlist + 1 (device)

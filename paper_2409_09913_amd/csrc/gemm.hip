@@ -242,8 +242,9 @@ __device__ inline uint4 ld16(const unsigned short* p, bool ok) {
     return v;
 }
 
-// Squared distances ||a||^2 + ||b||^2 - 2 a.b of the coarse probe with the
-// products on the BF16 matrix cores, from operands split beforehand into hi
+// EPI 1: squared distances ||a||^2 + ||b||^2 - 2 a.b of the coarse probe;
+// EPI 0: a.b (the query rotation).  Products on the BF16 matrix cores, from
+// operands split beforehand into hi
 // and lo BF16 planes (split_bf16_kernel): a.b = lo.hi + hi.lo + hi.hi per
 // 16-wide K chunk, FP32 accumulation.  Each product is off by at most
 // 2^-15 |a_i b_i| (the dropped lo.lo and the two split residuals), so a
@@ -253,6 +254,7 @@ __device__ inline uint4 ld16(const unsigned short* p, bool ok) {
 // staged 32 at a time in one LDS buffer (40 KB, so several blocks share a
 // CU); the next K-tile is loaded into registers while the current one is
 // multiplied.
+template <int EPI>
 __global__ __launch_bounds__(256, 3) void sqdist_bf16x3_kernel(
     const unsigned short* __restrict__ Ahg, const unsigned short* __restrict__ Alg, int64_t n, int K,
     const unsigned short* __restrict__ Bhg, const unsigned short* __restrict__ Blg, int N,
@@ -324,9 +326,46 @@ __global__ __launch_bounds__(256, 3) void sqdist_bf16x3_kernel(
             for (int r = 0; r < 16; ++r) {
                 const int64_t gr = row0 + wm + 32 * a + out_row(lane, r);
                 if (gr >= n) continue;
-                out[gr * ldo + gc] = (an2[gr] + bn2[gc]) - 2.0f * acc[a][b][r];
+                if constexpr (EPI == 1) out[gr * ldo + gc] = (an2[gr] + bn2[gc]) - 2.0f * acc[a][b][r];
+                else out[gr * ldo + gc] = acc[a][b][r];
             }
         }
+}
+
+// Transposed split of a K x N row-major matrix: hi/lo planes of its
+// transpose (N x K), for the B operand of sqdist_bf16x3_kernel.
+__global__ __launch_bounds__(256) void split_bf16_t_kernel(const float* __restrict__ x, int K, int N,
+                                                           unsigned short* __restrict__ hi,
+                                                           unsigned short* __restrict__ lo)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;   // output index: row j of N, column k of K
+    if (i >= (int64_t)K * N) return;
+    const int64_t j = i / K, k = i - j * K;
+    const float v = x[k * N + j];
+    const unsigned h = f2bf(v);
+    hi[i] = (unsigned short)h;
+    lo[i] = f2bf(v - __uint_as_float(h << 16));
+}
+
+hipError_t launch_split_bf16_t(const float* x, int K, int N, unsigned short* hi, unsigned short* lo, hipStream_t st)
+{
+    const int64_t n = (int64_t)K * N;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(split_bf16_t_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, K, N, hi, lo);
+    return hipGetLastError();
+}
+
+// out = A.B^T (n x N, leading dimension ldo) from the BF16 hi/lo planes of A
+// (n x K) and B (N x K); same products and error as the probe's distances
+hipError_t launch_gemm_bf16x3(const unsigned short* Ah, const unsigned short* Al, int64_t n,
+                              const unsigned short* Bh, const unsigned short* Bl, int64_t N, int K,
+                              float* out, int64_t ldo, hipStream_t st)
+{
+    if (n <= 0 || N <= 0) return hipSuccess;
+    dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((n + BM - 1) / BM));
+    hipLaunchKernelGGL(sqdist_bf16x3_kernel<0>, grid, dim3(256), 0, st, Ah, Al, n, K, Bh, Bl, (int)N, out, ldo,
+                       (const float*)nullptr, (const float*)nullptr);
+    return hipGetLastError();
 }
 
 hipError_t launch_split_bf16(const float* x, int64_t n, unsigned short* hi, unsigned short* lo, hipStream_t st)
@@ -342,7 +381,7 @@ hipError_t launch_sqdist_pre(const unsigned short* Ah, const unsigned short* Al,
 {
     if (n <= 0 || N <= 0) return hipSuccess;
     dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((n + BM - 1) / BM));
-    hipLaunchKernelGGL(sqdist_bf16x3_kernel, grid, dim3(256), 0, st, Ah, Al, n, K, Bh, Bl, (int)N, out,
+    hipLaunchKernelGGL(sqdist_bf16x3_kernel<1>, grid, dim3(256), 0, st, Ah, Al, n, K, Bh, Bl, (int)N, out,
                        (int64_t)N, an2, bn2);
     return hipGetLastError();
 }

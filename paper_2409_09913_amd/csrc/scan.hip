@@ -668,155 +668,199 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
     }
 }
 
-// 256 threads, one histogram bin each: the digit d whose bin holds the kr-th
-// smallest entry (exclusive prefix < kr <= inclusive prefix) and the rank
-// kr - exclusive prefix within that bin.  Ends with a barrier.
-__device__ inline void digit_of_rank(const unsigned* hist, unsigned kr, unsigned* s_digit, unsigned* s_kr,
-                                     unsigned* s_wsum) {
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const unsigned v = hist[tid];
-    unsigned x = v;
-    for (int o = 1; o < 64; o <<= 1) {
-        const unsigned y = __shfl_up(x, o);
-        if (lane >= o) x += y;
-    }
-    if (lane == 63) s_wsum[wid] = x;
-    __syncthreads();
-    unsigned base = 0;
-    for (int w = 0; w < wid; ++w) base += s_wsum[w];
-    const unsigned incl = base + x, excl = incl - v;
-    if (excl < kr && kr <= incl) { *s_digit = (unsigned)tid; *s_kr = kr - excl; }
-    __syncthreads();
-}
 
 // ---------------------------------------------------------------------------
 // Per query, over its candidate buffer (count c): radix select of the key of
-// the kk-th smallest estimate (4 passes of 8 bits).
+// the kk-th smallest estimate (4 passes of 8 bits).  One wave per query (4
+// per block); each pass re-reads the buffer (lane l: entries l, l + 64, ...,
+// just written, so from L2) into a wave-private LDS histogram; no block
+// barrier.
 //   mode 0: lowers the query's bound to it (the kk-th best candidate so far).
-//   mode 1: writes the exact top-kk ascending by (est, id): the candidates
-//           with key <= that of the kk-th are compacted and sorted.  A buffer
-//           that overflowed raises the query's flag for the fallback.
+//   mode 1: writes the exact top-kk ascending by (est, id): every candidate
+//           with a smaller key, and of those whose key equals the kk-th the
+//           ones with the smallest ids (a second radix select, over ids,
+//           when they are more than needed); at most kk entries are then
+//           ranked by (est, id).  A buffer that overflowed raises the
+//           query's flag for the fallback.
 //   mode 2: after a round; a buffer that overflowed raises the flag, gets back
 //           the count gprev it had before the round, and the bound drops to
 //           the kk-th best of its kCapQ stored candidates (all of them real
 //           estimates of distinct members, so still a valid bound).
 // ---------------------------------------------------------------------------
+constexpr int kSelQ = 4;               // queries (waves) per block
+
+// LDS written by some lanes of a wave and read by others: wait for the
+// wave's LDS operations and keep the compiler from moving accesses across
+__device__ inline void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Rank kr (1-based) among the values val(t) (t < c) with (v & mask) ==
+// prefix: the next 8-bit digit at `shift` and the rank within that digit.
+// Lane l reads entries l, l + 64, ...; hist: the wave's 256 bins.
+template <class F>
+__device__ __attribute__((always_inline)) inline void wave_digit(F val, int c, int lane, unsigned prefix,
+                                                                  unsigned mask, int shift, unsigned* hist,
+                                                                  unsigned& kr, unsigned& digit)
+{
+#pragma unroll
+    for (int b = 0; b < 4; ++b) hist[lane * 4 + b] = 0;
+    wave_lds_sync();
+    unsigned run_d = 0xFFFFFFFFu, run_n = 0;
+    for (int t = lane; t < c; t += 64) {
+        const unsigned x = val(t);
+        if ((x & mask) == prefix) {
+            const unsigned dg = (x >> shift) & 0xFF;
+            if (dg != run_d) {
+                if (run_n) atomicAdd(&hist[run_d], run_n);
+                run_d = dg; run_n = 0;
+            }
+            ++run_n;
+        }
+    }
+    if (run_n) atomicAdd(&hist[run_d], run_n);
+    wave_lds_sync();
+    unsigned h[4], s = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) { h[b] = hist[lane * 4 + b]; s += h[b]; }
+    unsigned incl = s;
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+    }
+    unsigned run = incl - s, my_d = 0, my_kr = 0;
+    bool found = false;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        if (!found && run < kr && kr <= run + h[b]) { found = true; my_d = lane * 4 + b; my_kr = kr - run; }
+        run += h[b];
+    }
+    const int src = __ffsll((unsigned long long)__ballot(found)) - 1;
+    digit = __shfl(my_d, src);
+    kr = __shfl(my_kr, src);
+    wave_lds_sync();                        // the bins are read before the next pass clears them
+}
+
 __global__ __launch_bounds__(256) void buf_select_kernel(int32_t* __restrict__ gcnt,
                                                          const int32_t* __restrict__ gprev,
                                                          const float* __restrict__ gbuf_e,
-                                                         const int32_t* __restrict__ gbuf_i, int kk, int mode,
-                                                         unsigned* __restrict__ tau_key, int32_t* __restrict__ ovf,
-                                                         int64_t* __restrict__ out_ids, float* __restrict__ out_est,
-                                                         int32_t* __restrict__ any_over)
+                                                         const int32_t* __restrict__ gbuf_i, int64_t nq, int kk,
+                                                         int mode, unsigned* __restrict__ tau_key,
+                                                         int32_t* __restrict__ ovf, int64_t* __restrict__ out_ids,
+                                                         float* __restrict__ out_est, int32_t* __restrict__ any_over)
 {
-    __shared__ unsigned hist[256];
-    __shared__ unsigned s_digit, s_kr, s_wsum[4];
-    __shared__ int s_m;
-    // sort arrays (kCapQ estimates and ids) only for mode 1: dynamic LDS, so
-    // that the bound modes keep many blocks per CU
-    extern __shared__ __align__(16) char sort_lds[];
-    float* se = (float*)sort_lds;
-    int* si = (int*)(sort_lds + sizeof(float) * kCapQ);
-    const int64_t q = blockIdx.x;
-    const int tid = threadIdx.x;
+    __shared__ unsigned hist[kSelQ][256];
+    __shared__ float s_e[kSelQ][32];
+    __shared__ int s_i[kSelQ][32];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t q = (int64_t)blockIdx.x * kSelQ + w;
+    if (q >= nq) return;                                // the whole wave
     const int craw = gcnt[q];
     const bool over = craw > kCapQ;
-    if (mode != 0 && over && tid == 0) atomicOr(any_over, 1);   // gate of the rescans / fallback
+    if (mode != 0 && over && lane == 0) atomicOr(any_over, 1);   // gate of the rescans / fallback
     if (mode == 1 && over) {
-        if (tid == 0) ovf[q] = 1;
+        if (lane == 0) ovf[q] = 1;
         return;
     }
     if (mode != 0 && !over) {
-        if (tid == 0) ovf[q] = 0;
+        if (lane == 0) ovf[q] = 0;
         if (mode == 2) return;
     }
-    if (mode == 0 && (over || craw < kk)) return;    // no (new) bound from this buffer
+    if (mode == 0 && (over || craw < kk)) return;       // no (new) bound from this buffer
     const int c = over ? kCapQ : craw;
     const float* be = gbuf_e + q * kCapQ;
     const int* bi = gbuf_i + q * kCapQ;
-    // the buffer is read once: thread t keeps the keys of entries t + 256 u
-    constexpr int RK = kCapQ / 256;
-    unsigned kreg[RK];
-#pragma unroll
-    for (int u = 0; u < RK; ++u) {
-        const int t = tid + 256 * u;
-        kreg[u] = (t < c) ? f2key(be[t]) : 0u;
-    }
-    unsigned kth = 0xFFFFFFFFu;
+    auto key_at = [&](int t) -> unsigned { return f2key(be[t]); };
+    unsigned kth = 0xFFFFFFFFu, need_eq = 0;
     if (c >= kk) {
         unsigned prefix = 0, mask = 0, kr = (unsigned)kk;
         for (int pass = 0; pass < 4; ++pass) {
             const int shift = 24 - 8 * pass;
-            hist[tid] = 0;
-            __syncthreads();
-            unsigned run_d = 0xFFFFFFFFu, run_n = 0;     // runs of equal digits counted in a register
-#pragma unroll
-            for (int u = 0; u < RK; ++u) {
-                const unsigned key = kreg[u];
-                if (tid + 256 * u < c && (key & mask) == prefix) {
-                    const unsigned dg = (key >> shift) & 0xFF;
-                    if (dg != run_d) {
-                        if (run_n) atomicAdd(&hist[run_d], run_n);
-                        run_d = dg; run_n = 0;
-                    }
-                    ++run_n;
-                }
-            }
-            if (run_n) atomicAdd(&hist[run_d], run_n);
-            __syncthreads();
-            digit_of_rank(hist, kr, &s_digit, &s_kr, s_wsum);
-            prefix |= s_digit << shift;
-            kr = s_kr;
+            unsigned dg;
+            wave_digit(key_at, c, lane, prefix, mask, shift, hist[w], kr, dg);
+            prefix |= dg << shift;
             mask |= 0xFFu << shift;
         }
         kth = prefix;
+        need_eq = kr;                                    // entries equal to kth that belong to the top-kk
     }
     if (mode == 0) {
-        if (tid == 0) atomicMin(&tau_key[q], kth);
+        if (lane == 0) atomicMin(&tau_key[q], kth);
         return;
     }
-    if (mode == 2) {                                  // over: kCapQ >= kk entries were ranked
-        if (tid == 0) {
+    if (mode == 2) {                                     // over: kCapQ >= kk entries were ranked
+        if (lane == 0) {
             atomicMin(&tau_key[q], kth);
             gcnt[q] = gprev[q];
             ovf[q] = 1;
         }
         return;
     }
-    // compaction of the candidates with key <= kth, then an exact sort
-    if (tid == 0) s_m = 0;
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < RK; ++u) {
-        const int t = tid + 256 * u;
-        if (t < c && kreg[u] <= kth) {
-            const int pos = atomicAdd(&s_m, 1);
-            se[pos] = key2f(kreg[u]);
-            si[pos] = bi[t];
+    // mode 1: the selected entries.  c < kk: all of them.  Else every key
+    // below kth, and of the keys equal to kth the need_eq smallest ids.
+    unsigned idth = 0xFFFFFFFFu;                         // ids <= idth are taken among the equal keys
+    if (c >= kk) {
+        unsigned neq = 0;
+        for (int t = lane; t < c; t += 64) neq += (key_at(t) == kth) ? 1u : 0u;
+        for (int o = 32; o > 0; o >>= 1) neq += __shfl_xor(neq, o);
+        if (neq > need_eq) {                             // ties at the boundary: smallest ids win
+            // entries outside the tie read as 0xFFFFFFFF, above any id taken
+            auto id_at = [&](int t) -> unsigned { return key_at(t) == kth ? (unsigned)bi[t] : 0xFFFFFFFFu; };
+            unsigned prefix = 0, mask = 0, kr = need_eq;
+            for (int pass = 0; pass < 4; ++pass) {
+                const int shift = 24 - 8 * pass;
+                unsigned dg;
+                wave_digit(id_at, c, lane, prefix, mask, shift, hist[w], kr, dg);
+                prefix |= dg << shift;
+                mask |= 0xFFu << shift;
+            }
+            idth = prefix;
         }
     }
-    __syncthreads();
-    const int m = s_m;
-    int S = 1;
-    while (S < m) S <<= 1;
-    for (int t = m + tid; t < S; t += 256) { se[t] = __builtin_huge_valf(); si[t] = 0x7FFFFFFF; }
-    for (int kb = 2; kb <= S; kb <<= 1)
-        for (int jj = kb >> 1; jj > 0; jj >>= 1) {
-            __syncthreads();
-            for (int t = tid; t < S / 2; t += 256) {
-                int i = 2 * t - (t & (jj - 1)), p = i + jj;
-                bool up = (i & kb) == 0;
-                float e0 = se[i], e1 = se[p];
-                int i0 = si[i], i1 = si[p];
-                bool first0 = lt(e0, i0, e1, i1);
-                if (first0 != up) { se[i] = e1; se[p] = e0; si[i] = i1; si[p] = i0; }
+    // compaction of the selected entries (at most kk, in lane order)
+    auto selected = [&](int t) -> bool {
+        if (c < kk) return true;
+        const unsigned k = key_at(t);
+        return k < kth || (k == kth && (idth == 0xFFFFFFFFu || (unsigned)bi[t] <= idth));
+    };
+    unsigned cnt = 0;
+    for (int t = lane; t < c; t += 64) cnt += selected(t) ? 1u : 0u;
+    unsigned pos = cnt;
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned y = __shfl_up(pos, o);
+        if (lane >= o) pos += y;
+    }
+    const unsigned m_all = __shfl(pos, 63);
+    pos -= cnt;                                          // exclusive prefix
+    for (int t = lane; t < c && cnt > 0; t += 64) {
+        if (selected(t)) {
+            if (pos < (unsigned)kk) {
+                s_e[w][pos] = be[t];
+                s_i[w][pos] = bi[t];
             }
+            ++pos;
+            --cnt;
         }
-    __syncthreads();
-    for (int t = tid; t < kk; t += 256) {
-        const bool valid = t < m;
-        out_ids[q * kk + t] = valid ? (int64_t)si[t] : -1;
-        out_est[q * kk + t] = valid ? se[t] : __builtin_huge_valf();
+    }
+    wave_lds_sync();
+    const int m = (int)min(m_all, (unsigned)kk);
+    // rank of entry `lane` by (est, id) among the m selected; equal pairs by position
+    if (lane < m) {
+        const float e = s_e[w][lane];
+        const int id = s_i[w][lane];
+        int r = 0;
+        for (int j = 0; j < m; ++j) {
+            const float ej = s_e[w][j];
+            const int ij = s_i[w][j];
+            r += (lt(ej, ij, e, id) || (j < lane && ej == e && ij == id)) ? 1 : 0;
+        }
+        out_ids[q * kk + r] = id;
+        out_est[q * kk + r] = e;
+    }
+    for (int t = m + lane; t < kk; t += 64) {
+        out_ids[q * kk + t] = -1;
+        out_est[q * kk + t] = __builtin_huge_valf();
     }
 }
 
@@ -1435,9 +1479,8 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, co
         return hipGetLastError();
     };
     auto select = [&](int mode, int64_t* oi, float* oe) {
-        const size_t sm = (mode == 1) ? (sizeof(float) + sizeof(int)) * kCapQ : 0;
-        hipLaunchKernelGGL(buf_select_kernel, dim3((unsigned)nq), dim3(256), sm, st, gcnt, gprev, gbe, gbi, kk,
-                           mode, tkey, ovf, oi, oe, anyf);
+        hipLaunchKernelGGL(buf_select_kernel, dim3((unsigned)((nq + kSelQ - 1) / kSelQ)), dim3(256), 0, st, gcnt,
+                           gprev, gbe, gbi, nq, kk, mode, tkey, ovf, oi, oe, anyf);
         return hipGetLastError();
     };
     const int qpiB = scan_nqt(ix) * kQT;            // queries per item of the launched kernel

@@ -214,6 +214,35 @@ def test_scan_edge_cases():
     assert (gi == -1).any()
 
 
+@pytest.mark.parametrize("kk", [16, 32])
+def test_scan_exact_ties_by_id(kk):
+    """Every member of a list is a copy of one code row with the same factors,
+    so all its estimates tie exactly (in FP32 and FP64): the top-kk must take
+    the smallest ids of a tied group, in id order (reading C-16)."""
+    say("scan exact ties kk", kk)
+    dp, B, nl = 64, 4, 3
+    sizes = np.array([300, 500, 40])
+    off, ids, codes, fa, fr, crot = synth.random_index(int(sizes.sum()), nl, dp, B, seed=40 + kk, sizes=sizes)
+    for l in range(nl):
+        lo, hi = off[l], off[l + 1]
+        codes[lo:hi] = codes[lo]
+        fa[lo:hi] = fa[lo]
+        fr[lo:hi] = fr[lo]
+    qrot = synth.random_rotated(12, dp, seed=41)
+    probes = np.tile(np.arange(nl, dtype=np.int32), (12, 1))
+    P = synth.haar_orthogonal(dp, seed=2).astype(np.float32)
+    ix = erq.Index(dp, B, nl, dev(P))
+    ix.import_(dev(off), dev(ids), dev(codes), dev(fa), dev(fr), dev(np.zeros((nl, dp), np.float32)), dev(crot))
+    gi, ge = ix.scan(dev(qrot), dev(probes), kk)
+    torch.cuda.synchronize()
+    gi, ge = gi.cpu().numpy(), ge.cpu().numpy()
+    oi, oe = oracle.search(off, ids, codes, fa, fr, crot, qrot, probes, B, kk, est_mode=0)
+    np.testing.assert_array_equal(gi, oi)
+    scale = _term_scale(codes, fa, fr, crot, qrot, off, ids, None, probes, B)
+    _compare_topk(gi, ge, oi, oe, scale)
+    ix.close()
+
+
 def test_scan_many_queries_per_list():
     """More than 32 queries per list (several query tiles per list)."""
     say("scan many queries")
