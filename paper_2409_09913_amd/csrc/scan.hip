@@ -688,6 +688,7 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
 //           estimates of distinct members, so still a valid bound).
 // ---------------------------------------------------------------------------
 constexpr int kSelQ = 4;               // queries (waves) per block
+constexpr int kSelB = 16;              // entries per lane loaded together (1024 per wave)
 
 // LDS written by some lanes of a wave and read by others: wait for the
 // wave's LDS operations and keep the compiler from moving accesses across
@@ -700,23 +701,34 @@ __device__ inline void wave_lds_sync() {
 // prefix: the next 8-bit digit at `shift` and the rank within that digit.
 // Lane l reads entries l, l + 64, ...; hist: the wave's 256 bins.
 template <class F>
-__device__ __attribute__((always_inline)) inline void wave_digit(F val, int c, int lane, unsigned prefix,
-                                                                  unsigned mask, int shift, unsigned* hist,
-                                                                  unsigned& kr, unsigned& digit)
+__device__ __attribute__((always_inline)) inline void wave_digit(const unsigned (&v0)[kSelB], F val, int c, int lane,
+                                                                  unsigned prefix, unsigned mask, int shift,
+                                                                  unsigned* hist, unsigned& kr, unsigned& digit)
 {
 #pragma unroll
     for (int b = 0; b < 4; ++b) hist[lane * 4 + b] = 0;
     wave_lds_sync();
     unsigned run_d = 0xFFFFFFFFu, run_n = 0;
-    for (int t = lane; t < c; t += 64) {
-        const unsigned x = val(t);
-        if ((x & mask) == prefix) {
-            const unsigned dg = (x >> shift) & 0xFF;
-            if (dg != run_d) {
-                if (run_n) atomicAdd(&hist[run_d], run_n);
-                run_d = dg; run_n = 0;
+    // the first 64 * kSelB entries come from registers (v0), the rest in
+    // batches with kSelB loads in flight
+    for (int base = 0; base < c; base += 64 * kSelB) {
+        unsigned v[kSelB];
+#pragma unroll
+        for (int k = 0; k < kSelB; ++k) {
+            const int t = base + lane + 64 * k;
+            v[k] = (base == 0) ? v0[k] : ((t < c) ? val(t) : 0u);
+        }
+#pragma unroll
+        for (int k = 0; k < kSelB; ++k) {
+            const int t = base + lane + 64 * k;
+            if (t < c && (v[k] & mask) == prefix) {
+                const unsigned dg = (v[k] >> shift) & 0xFF;
+                if (dg != run_d) {
+                    if (run_n) atomicAdd(&hist[run_d], run_n);
+                    run_d = dg; run_n = 0;
+                }
+                ++run_n;
             }
-            ++run_n;
         }
     }
     if (run_n) atomicAdd(&hist[run_d], run_n);
@@ -772,13 +784,19 @@ __global__ __launch_bounds__(256) void buf_select_kernel(int32_t* __restrict__ g
     const float* be = gbuf_e + q * kCapQ;
     const int* bi = gbuf_i + q * kCapQ;
     auto key_at = [&](int t) -> unsigned { return f2key(be[t]); };
+    unsigned key0[kSelB];                                // keys of entries lane + 64 k (k < kSelB)
+#pragma unroll
+    for (int k = 0; k < kSelB; ++k) {
+        const int t = lane + 64 * k;
+        key0[k] = (t < c) ? key_at(t) : 0u;
+    }
     unsigned kth = 0xFFFFFFFFu, need_eq = 0;
     if (c >= kk) {
         unsigned prefix = 0, mask = 0, kr = (unsigned)kk;
         for (int pass = 0; pass < 4; ++pass) {
             const int shift = 24 - 8 * pass;
             unsigned dg;
-            wave_digit(key_at, c, lane, prefix, mask, shift, hist[w], kr, dg);
+            wave_digit(key0, key_at, c, lane, prefix, mask, shift, hist[w], kr, dg);
             prefix |= dg << shift;
             mask |= 0xFFu << shift;
         }
@@ -802,16 +820,31 @@ __global__ __launch_bounds__(256) void buf_select_kernel(int32_t* __restrict__ g
     unsigned idth = 0xFFFFFFFFu;                         // ids <= idth are taken among the equal keys
     if (c >= kk) {
         unsigned neq = 0;
-        for (int t = lane; t < c; t += 64) neq += (key_at(t) == kth) ? 1u : 0u;
+        for (int base = 0; base < c; base += 64 * kSelB) {
+            unsigned v[kSelB];
+#pragma unroll
+            for (int k = 0; k < kSelB; ++k) {
+                const int t = base + lane + 64 * k;
+                v[k] = (base == 0) ? key0[k] : ((t < c) ? key_at(t) : 0u);
+            }
+#pragma unroll
+            for (int k = 0; k < kSelB; ++k) neq += (base + lane + 64 * k < c && v[k] == kth) ? 1u : 0u;
+        }
         for (int o = 32; o > 0; o >>= 1) neq += __shfl_xor(neq, o);
         if (neq > need_eq) {                             // ties at the boundary: smallest ids win
             // entries outside the tie read as 0xFFFFFFFF, above any id taken
             auto id_at = [&](int t) -> unsigned { return key_at(t) == kth ? (unsigned)bi[t] : 0xFFFFFFFFu; };
+            unsigned id0[kSelB];
+#pragma unroll
+            for (int k = 0; k < kSelB; ++k) {
+                const int t = lane + 64 * k;
+                id0[k] = (t < c && key0[k] == kth) ? (unsigned)bi[t] : 0xFFFFFFFFu;
+            }
             unsigned prefix = 0, mask = 0, kr = need_eq;
             for (int pass = 0; pass < 4; ++pass) {
                 const int shift = 24 - 8 * pass;
                 unsigned dg;
-                wave_digit(id_at, c, lane, prefix, mask, shift, hist[w], kr, dg);
+                wave_digit(id0, id_at, c, lane, prefix, mask, shift, hist[w], kr, dg);
                 prefix |= dg << shift;
                 mask |= 0xFFu << shift;
             }
@@ -819,13 +852,25 @@ __global__ __launch_bounds__(256) void buf_select_kernel(int32_t* __restrict__ g
         }
     }
     // compaction of the selected entries (at most kk, in lane order)
-    auto selected = [&](int t) -> bool {
+    auto sel_key = [&](int t, unsigned k) -> bool {
         if (c < kk) return true;
-        const unsigned k = key_at(t);
         return k < kth || (k == kth && (idth == 0xFFFFFFFFu || (unsigned)bi[t] <= idth));
     };
+    auto selected = [&](int base, int k) -> bool {
+        const int t = base + lane + 64 * k;
+        return sel_key(t, base == 0 ? key0[k] : key_at(t));
+    };
     unsigned cnt = 0;
-    for (int t = lane; t < c; t += 64) cnt += selected(t) ? 1u : 0u;
+    for (int base = 0; base < c; base += 64 * kSelB) {
+        bool v[kSelB];
+#pragma unroll
+        for (int k = 0; k < kSelB; ++k) {
+            const int t = base + lane + 64 * k;
+            v[k] = (t < c) && selected(base, k);
+        }
+#pragma unroll
+        for (int k = 0; k < kSelB; ++k) cnt += v[k] ? 1u : 0u;
+    }
     unsigned pos = cnt;
     for (int o = 1; o < 64; o <<= 1) {
         const unsigned y = __shfl_up(pos, o);
@@ -833,14 +878,24 @@ __global__ __launch_bounds__(256) void buf_select_kernel(int32_t* __restrict__ g
     }
     const unsigned m_all = __shfl(pos, 63);
     pos -= cnt;                                          // exclusive prefix
-    for (int t = lane; t < c && cnt > 0; t += 64) {
-        if (selected(t)) {
-            if (pos < (unsigned)kk) {
-                s_e[w][pos] = be[t];
-                s_i[w][pos] = bi[t];
+    for (int base = 0; base < c && __any(cnt > 0); base += 64 * kSelB) {
+        bool v[kSelB];
+#pragma unroll
+        for (int k = 0; k < kSelB; ++k) {
+            const int t = base + lane + 64 * k;
+            v[k] = cnt > 0 && (t < c) && selected(base, k);
+        }
+#pragma unroll
+        for (int k = 0; k < kSelB; ++k) {
+            if (v[k]) {
+                const int t = base + lane + 64 * k;
+                if (pos < (unsigned)kk) {
+                    s_e[w][pos] = be[t];
+                    s_i[w][pos] = bi[t];
+                }
+                ++pos;
+                --cnt;
             }
-            ++pos;
-            --cnt;
         }
     }
     wave_lds_sync();
