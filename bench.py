@@ -166,7 +166,7 @@ def main():
     def sweep(index, label):
         rows = []
         grid = [(args.nprobe, max(args.rerank, 0))] if args.nprobe > 0 else \
-            [(n_, r_) for n_ in (16, 32, 64, 80, 96, 112, 128, 160, 256) for r_ in (0, 10, 20, 32)]
+            [(n_, r_) for n_ in (16, 32, 64, 72, 80, 88, 96, 112, 128, 160, 256) for r_ in (0, 16, 20, 24, 32)]
         for nprobe, rr in grid:
             if True:
                 ids, qps = timed_search(index, nprobe, rr, 3)
