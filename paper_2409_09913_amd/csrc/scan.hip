@@ -754,11 +754,14 @@ __device__ __attribute__((always_inline)) inline void wave_digit(const unsigned 
     wave_lds_sync();                        // the bins are read before the next pass clears them
 }
 
+// post (mode 0 only), applied on entry after the count is read: 1 empties the
+// buffer (count and count-before-round 0), 2 records the count as the
+// count before the next round
 __global__ __launch_bounds__(256) void buf_select_kernel(int32_t* __restrict__ gcnt,
-                                                         const int32_t* __restrict__ gprev,
+                                                         int32_t* __restrict__ gprev,
                                                          const float* __restrict__ gbuf_e,
                                                          const int32_t* __restrict__ gbuf_i, int64_t nq, int kk,
-                                                         int mode, unsigned* __restrict__ tau_key,
+                                                         int mode, int post, unsigned* __restrict__ tau_key,
                                                          int32_t* __restrict__ ovf, int64_t* __restrict__ out_ids,
                                                          float* __restrict__ out_est, int32_t* __restrict__ any_over)
 {
@@ -770,6 +773,10 @@ __global__ __launch_bounds__(256) void buf_select_kernel(int32_t* __restrict__ g
     if (q >= nq) return;                                // the whole wave
     const int craw = gcnt[q];
     const bool over = craw > kCapQ;
+    if (mode == 0 && post != 0 && lane == 0) {
+        if (post == 1) { gcnt[q] = 0; gprev[q] = 0; }
+        else gprev[q] = craw;
+    }
     if (mode != 0 && over && lane == 0) atomicOr(any_over, 1);   // gate of the rescans / fallback
     if (mode == 1 && over) {
         if (lane == 0) ovf[q] = 1;
@@ -1011,11 +1018,6 @@ __global__ void fill_dense_kernel(float* __restrict__ gbuf_e, int64_t nq, int32_
 
 
 // ---------------------------------------------------------------------------
-__global__ void copy_i32_kernel(const int32_t* __restrict__ src, int32_t* __restrict__ dst, int64_t n) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) dst[i] = src[i];
-}
-
 __global__ void fill_i32_kernel(int32_t* p, int64_t n, int32_t v) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -1152,14 +1154,22 @@ __global__ __launch_bounds__(1024) void pair_place_kernel(const int32_t* __restr
     }
 }
 
-// single workgroup: pair_off (by list id) and item_off (by rank of list_order)
+// single workgroup: pair_off (by list id) and item_off (by rank of list_order).
+// Thread 0 also zeroes the work counter of the scan launch that follows and,
+// when given, two flags (zf0, zf1), so that they need no launches of their own.
 __global__ __launch_bounds__(1024) void pair_scan_kernel(const int32_t* __restrict__ cnt, int nlist,
                                                          const int32_t* __restrict__ list_order,
                                                          const int64_t* __restrict__ list_off, int qpi, int vch,
                                                          int32_t* __restrict__ pair_off,
                                                          int32_t* __restrict__ item_off,
-                                                         const int32_t* __restrict__ gate)
+                                                         const int32_t* __restrict__ gate, int32_t* __restrict__ work,
+                                                         int32_t* __restrict__ zf0, int32_t* __restrict__ zf1)
 {
+    if (threadIdx.x == 0) {
+        *work = 0;
+        if (zf0) *zf0 = 0;
+        if (zf1) *zf1 = 0;
+    }
     // a gated-off build publishes zero items, so the scan after it is empty
     if (gate && *gate == 0) {
         if (threadIdx.x == 0) { item_off[nlist] = 0; pair_off[nlist] = 0; }
@@ -1453,7 +1463,7 @@ size_t scan_workspace_bytes(int64_t nq, int nprobe, int64_t nlist, int kk, int d
     b += 2 * align256(sizeof(int32_t) * P);                // pair table (query, slot)
     b += align256(sizeof(unsigned) * nq);                  // bound per query
     b += 3 * align256(sizeof(int32_t) * nq);               // candidate counts, counts before a round, flags
-    b += 2 * align256(sizeof(int32_t));                    // pass-B work counter, overflow flag
+    b += 3 * align256(sizeof(int32_t));                    // pass-B work counter, two overflow flags
     b += align256(sizeof(float) * nq * kCapQ);             // candidate buffers
     b += align256(sizeof(int32_t) * nq * kCapQ);
     b += align256(sizeof(float) * P * kk);                 // per-pair top-kk (pass A, fallback)
@@ -1489,7 +1499,8 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, co
     int32_t* gprev = (int32_t*)take(sizeof(int32_t) * nq);
     int32_t* ovf = (int32_t*)take(sizeof(int32_t) * nq);
     int32_t* work = (int32_t*)take(sizeof(int32_t));
-    int32_t* anyf = (int32_t*)take(sizeof(int32_t));       // some query's buffer overflowed
+    int32_t* anyf = (int32_t*)take(sizeof(int32_t));       // some query's buffer overflowed in a round
+    int32_t* anyf2 = (int32_t*)take(sizeof(int32_t));      // ... at the final selection
     float* gbe = (float*)take(sizeof(float) * nq * kCapQ);
     int32_t* gbi = (int32_t*)take(sizeof(int32_t) * nq * kCapQ);
     float* res_est = (float*)take(sizeof(float) * P * kk);
@@ -1500,7 +1511,6 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, co
     float* sdist_ws = (float*)take(sizeof(float) * P);
 
     const int th = 256;
-    const unsigned qblocks = (unsigned)((nq + th - 1) / th);
     auto zero = [&](int32_t* p, int64_t n) {
         if (n > 0) hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)((n + th - 1) / th)), dim3(th), 0, st, p, n, 0);
     };
@@ -1508,6 +1518,8 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, co
     // pair table of the probes with rank in [rlo, rhi) (of flagged queries with
     // qmask), grouped by list; items split lists into chunks of vch members when vch > 0
     const bool lds_sort = nlist <= kHistMax;
+    // the pair scan also zeroes the work counter and, for a build that is not
+    // gated, both overflow flags
     auto build_pairs = [&](int rlo, int rhi, const int32_t* qmask, int qpi, int vch, const int32_t* gate) {
         if (lds_sort) {
             hipLaunchKernelGGL(pair_hist_kernel, dim3(kPairBlocks), dim3(1024), 0, st, probes, P, nprobe,
@@ -1521,7 +1533,8 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, co
                                    rlo, rhi, qmask, cnt);
         }
         hipLaunchKernelGGL(pair_scan_kernel, dim3(1), dim3(1024), 0, st, cnt, (int)nlist, ix->list_order,
-                           ix->list_off, qpi, vch, poff, ioff, lds_sort ? gate : nullptr);
+                           ix->list_off, qpi, vch, poff, ioff, lds_sort ? gate : nullptr, work,
+                           gate ? nullptr : anyf, gate ? nullptr : anyf2);
         hipLaunchKernelGGL(item_desc_kernel, dim3((unsigned)((dcap + th - 1) / th)), dim3(th), 0, st, ioff,
                            ix->list_order, ix->list_off, poff, (int)nlist, qpi, vch, dcap, desc);
         if (lds_sort) {
@@ -1533,9 +1546,9 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, co
         }
         return hipGetLastError();
     };
-    auto select = [&](int mode, int64_t* oi, float* oe) {
+    auto select = [&](int mode, int post, int64_t* oi, float* oe) {
         hipLaunchKernelGGL(buf_select_kernel, dim3((unsigned)((nq + kSelQ - 1) / kSelQ)), dim3(256), 0, st, gcnt,
-                           gprev, gbe, gbi, nq, kk, mode, tkey, ovf, oi, oe, anyf);
+                           gprev, gbe, gbi, nq, kk, mode, post, tkey, ovf, oi, oe, mode == 1 ? anyf2 : anyf);
         return hipGetLastError();
     };
     const int qpiB = scan_nqt(ix) * kQT;            // queries per item of the launched kernel
@@ -1556,7 +1569,6 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, co
     auto scan_round = [&](int rlo, int rhi, const int32_t* qmask, int dense, const int32_t* gate) {
         hipError_t er = build_pairs(rlo, rhi, qmask, qpiB, dense ? 0 : kVch, gate);
         if (er != hipSuccess) return er;
-        zero(work, 1);
         ScanArgs b{qa, poff, pq, ps, ioff, desc, gridB, 0, kk, nullptr, nullptr};
         BArgs bb{tkey, gcnt, gbe, gbi, work, dense ? 0 : kVch, dense, nprobe};
         const int rec = prof_begin(dense ? PK_SCAN_A : PK_SCAN_B, st);   // one record per launch
@@ -1571,27 +1583,25 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, co
                        gbe, nq, gcnt, tkey);
     e = hipGetLastError();
     if (e == hipSuccess) e = scan_round(0, r0, nullptr, 1, nullptr);
-    if (e == hipSuccess) e = select(0, nullptr, nullptr);
-    zero(gcnt, nq);                                  // the dense entries are found again by the rounds
-    // pass B in rounds of increasing probe rank
+    // bound, then the buffer is emptied (the dense entries are found again by the rounds)
+    if (e == hipSuccess) e = select(0, 1, nullptr, nullptr);
+    // pass B in rounds of increasing probe rank; the count before each round is
+    // recorded by the select before it (0 after the dense bound)
     const int bounds[3] = {0, std::min(nprobe, scan_round1(ix)), nprobe};
     for (int r = 0; r < 2 && e == hipSuccess; ++r) {
         const int rlo = bounds[r], rhi = bounds[r + 1];
         if (rhi <= rlo) continue;
-        hipLaunchKernelGGL(copy_i32_kernel, dim3(qblocks), dim3(th), 0, st, gcnt, gprev, nq);
-        e = scan_round(rlo, rhi, nullptr, 0, nullptr);
+        e = scan_round(rlo, rhi, nullptr, 0, nullptr);        // its pair scan zeroes both flags
         // queries that overflowed: back to their count before the round, tighter bound, rescan the
         // round (skipped on the device when no query overflowed)
-        zero(anyf, 1);
-        if (e == hipSuccess) e = select(2, nullptr, nullptr);
+        if (e == hipSuccess) e = select(2, 0, nullptr, nullptr);
         if (e == hipSuccess) e = scan_round(rlo, rhi, ovf, 0, anyf);
-        if (e == hipSuccess && rhi < nprobe) e = select(0, nullptr, nullptr);
+        if (e == hipSuccess && rhi < nprobe) e = select(0, 2, nullptr, nullptr);
     }
     // exact top-kk per query; queries whose buffer still overflowed: pair by pair
     const int pc = prof_begin(PK_SCAN_C, st);
-    zero(anyf, 1);
-    if (e == hipSuccess) e = select(1, out_ids, out_est);
-    if (e == hipSuccess) e = build_pairs(0, nprobe, ovf, kQT, 0, anyf);
+    if (e == hipSuccess) e = select(1, 0, out_ids, out_est);
+    if (e == hipSuccess) e = build_pairs(0, nprobe, ovf, kQT, 0, anyf2);
     if (e == hipSuccess) {
         ScanArgs c{qa, poff, pq, ps, ioff, desc, std::min<int64_t>((P + kQT - 1) / kQT + nlist, 4096), 0x7FFFFFFF, kk,
                    res_est, res_id};
