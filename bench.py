@@ -68,8 +68,9 @@ def main():
                     help="nqt,pd,round1: fixed scan schedule (with --tune 0), e.g. the tuner's choice")
     ap.add_argument("--graph", type=int, default=1,
                     help="1: the timed steps replay the search captured in a HIP graph; 0: eager calls")
-    ap.add_argument("--serve", type=int, default=0,
-                    help="N > 0: also run N Poisson-arrival requests through the batching server (p50/p99)")
+    ap.add_argument("--serve", type=int, default=2000,
+                    help="N > 0: also run N Poisson-arrival requests per rate through the batching server "
+                         "(p50/p99); 0 skips it")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (scale for HBM byte counters)")
     args = ap.parse_args()
