@@ -1154,6 +1154,10 @@ __global__ __launch_bounds__(1024) void pair_place_kernel(const int32_t* __restr
     }
 }
 
+__device__ inline void list_scan(const int32_t* __restrict__ cnt, int nlist, const int32_t* __restrict__ list_order,
+                                 const int64_t* __restrict__ list_off, int qpi, int vch,
+                                 int32_t* __restrict__ pair_off, int32_t* __restrict__ item_off);
+
 // single workgroup: pair_off (by list id) and item_off (by rank of list_order).
 // Thread 0 also zeroes the work counter of the scan launch that follows and,
 // when given, two flags (zf0, zf1), so that they need no launches of their own.
@@ -1175,6 +1179,15 @@ __global__ __launch_bounds__(1024) void pair_scan_kernel(const int32_t* __restri
         if (threadIdx.x == 0) { item_off[nlist] = 0; pair_off[nlist] = 0; }
         return;
     }
+    list_scan(cnt, nlist, list_order, list_off, qpi, vch, pair_off, item_off);
+}
+
+// One workgroup of 1024: exclusive prefix of the pair counts (pair_off, by
+// list id) and of the item counts (item_off, by rank of list_order).
+__device__ inline void list_scan(const int32_t* __restrict__ cnt, int nlist, const int32_t* __restrict__ list_order,
+                                 const int64_t* __restrict__ list_off, int qpi, int vch,
+                                 int32_t* __restrict__ pair_off, int32_t* __restrict__ item_off)
+{
     __shared__ int part_a[1024], part_b[1024];
     const int tid = threadIdx.x;
     const int chunk = (nlist + 1023) / 1024;
@@ -1200,12 +1213,11 @@ __global__ __launch_bounds__(1024) void pair_scan_kernel(const int32_t* __restri
 
 // descriptor of every item, (list, first pair, queries, first member), so
 // that a scan kernel reads one int4 per item; one thread per item
-__global__ void item_desc_kernel(const int32_t* __restrict__ item_off, const int32_t* __restrict__ list_order,
-                                 const int64_t* __restrict__ list_off, const int32_t* __restrict__ pair_off,
-                                 int nlist, int qpi, int vch, int64_t cap, int4* __restrict__ desc)
+__device__ inline void item_desc_one(int64_t item, const int32_t* __restrict__ item_off,
+                                     const int32_t* __restrict__ list_order, const int64_t* __restrict__ list_off,
+                                     const int32_t* __restrict__ pair_off, int nlist, int qpi, int vch,
+                                     int4* __restrict__ desc)
 {
-    const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // empty build: item_off[nlist] == 0
-    if (item >= cap || item >= item_off[nlist]) return;
     int l, t;
     decode_item((int)item, item_off, list_order, nlist, &l, &t);
     const int nv = (int)(list_off[l + 1] - list_off[l]);
@@ -1213,6 +1225,58 @@ __global__ void item_desc_kernel(const int32_t* __restrict__ item_off, const int
     const int qtile = t / nvc, vc = t - qtile * nvc;
     const int p0 = pair_off[l] + qtile * qpi;
     desc[item] = make_int4(l, p0, min(qpi, pair_off[l + 1] - p0), vc * vch);
+}
+
+__global__ void item_desc_kernel(const int32_t* __restrict__ item_off, const int32_t* __restrict__ list_order,
+                                 const int64_t* __restrict__ list_off, const int32_t* __restrict__ pair_off,
+                                 int nlist, int qpi, int vch, int64_t cap, int4* __restrict__ desc)
+{
+    const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // empty build: item_off[nlist] == 0
+    if (item >= cap || item >= item_off[nlist]) return;
+    item_desc_one(item, item_off, list_order, list_off, pair_off, nlist, qpi, vch, desc);
+}
+
+// A gated pair build (the rescan of overflowed queries, the exact fallback)
+// in one launch of one workgroup: nothing but the published empty build when
+// the gate is off (the usual case); else count per list (global atomics),
+// the list scan, placement and the item descriptors.  The pairs of flagged
+// queries only, so few; their order within a list is free (every query's
+// result is its exact top-kk whatever the grouping).  cnt: nlist counters.
+__global__ __launch_bounds__(1024) void pair_build_gated_kernel(
+    const int32_t* __restrict__ probes, int64_t np, int nprobe, int nlist, int rlo, int rhi,
+    const int32_t* __restrict__ qmask, const int32_t* __restrict__ list_order,
+    const int64_t* __restrict__ list_off, int qpi, int vch, int32_t* __restrict__ cnt,
+    int32_t* __restrict__ pair_off, int32_t* __restrict__ item_off, int32_t* __restrict__ pq,
+    int32_t* __restrict__ pslot, int4* __restrict__ desc, int64_t cap, int32_t* __restrict__ work,
+    const int32_t* __restrict__ gate)
+{
+    const int tid = threadIdx.x;
+    if (tid == 0) *work = 0;
+    if (*gate == 0) {
+        if (tid == 0) { item_off[nlist] = 0; pair_off[nlist] = 0; }
+        return;
+    }
+    for (int l = tid; l < nlist; l += 1024) cnt[l] = 0;
+    __syncthreads();
+    for (int64_t i = tid; i < np; i += 1024) {
+        int l; int64_t q;
+        if (pair_sel(probes, i, nprobe, nlist, rlo, rhi, qmask, &l, &q)) atomicAdd(&cnt[l], 1);
+    }
+    __syncthreads();
+    list_scan(cnt, nlist, list_order, list_off, qpi, vch, pair_off, item_off);
+    __syncthreads();
+    for (int l = tid; l < nlist; l += 1024) cnt[l] = 0;     // placement counters
+    __syncthreads();
+    for (int64_t i = tid; i < np; i += 1024) {
+        int l; int64_t q;
+        if (!pair_sel(probes, i, nprobe, nlist, rlo, rhi, qmask, &l, &q)) continue;
+        const int pos = pair_off[l] + atomicAdd(&cnt[l], 1);
+        pq[pos] = (int32_t)q;
+        pslot[pos] = (int32_t)i;
+    }
+    const int64_t n_items = min<int64_t>(item_off[nlist], cap);
+    for (int64_t item = tid; item < n_items; item += 1024)
+        item_desc_one(item, item_off, list_order, list_off, pair_off, nlist, qpi, vch, desc);
 }
 
 // one wave per query: the kk best of its probed lists' top-kk lists (pairs
@@ -1521,6 +1585,12 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, co
     // the pair scan also zeroes the work counter and, for a build that is not
     // gated, both overflow flags
     auto build_pairs = [&](int rlo, int rhi, const int32_t* qmask, int qpi, int vch, const int32_t* gate) {
+        if (gate) {                                      // usually empty: one launch
+            hipLaunchKernelGGL(pair_build_gated_kernel, dim3(1), dim3(1024), 0, st, probes, P, nprobe, (int)nlist,
+                               rlo, rhi, qmask, ix->list_order, ix->list_off, qpi, vch, cnt, poff, ioff, pq, ps,
+                               desc, dcap, work, gate);
+            return hipGetLastError();
+        }
         if (lds_sort) {
             hipLaunchKernelGGL(pair_hist_kernel, dim3(kPairBlocks), dim3(1024), 0, st, probes, P, nprobe,
                                (int)nlist, rlo, rhi, qmask, cnt2, gate);
