@@ -10,8 +10,9 @@
 namespace erq {
 
 // launchers defined in the other translation units
-hipError_t launch_row_sqnorm(const float* X, int64_t n, int K, float* out, hipStream_t st);
 hipError_t launch_split_bf16(const float* x, int64_t n, unsigned short* hi, unsigned short* lo, hipStream_t st);
+hipError_t launch_split_norm(const float* X, int64_t n, int K, unsigned short* hi, unsigned short* lo, float* n2,
+                             hipStream_t st);
 hipError_t launch_split_bf16_t(const float* x, int K, int N, unsigned short* hi, unsigned short* lo, hipStream_t st);
 hipError_t launch_gemm_bf16x3(const unsigned short* Ah, const unsigned short* Al, int64_t n,
                               const unsigned short* Bh, const unsigned short* Bl, int64_t N, int K,
@@ -80,6 +81,8 @@ void prof_end(int rec, hipStream_t st)
 void free_index_storage(Index* ix)
 {
     hipFree(ix->cent); hipFree(ix->cent_rot); hipFree(ix->list_off); hipFree(ix->tile_off);
+    hipFree(ix->cent_hi); hipFree(ix->cent_lo); hipFree(ix->cent_n2);
+    ix->cent_hi = ix->cent_lo = nullptr; ix->cent_n2 = nullptr;
     hipFree(ix->list_order); hipFree(ix->ids); hipFree(ix->fac); hipFree(ix->sfac); hipFree(ix->codes);
     ix->cent = ix->cent_rot = nullptr; ix->list_off = ix->tile_off = nullptr; ix->list_order = nullptr;
     ix->ids = nullptr; ix->fac = nullptr; ix->sfac = nullptr; ix->codes = nullptr;
@@ -150,9 +153,25 @@ int set_list_meta(Index* ix, const std::vector<int64_t>& off, hipStream_t st) {
     return ERQ_OK;
 }
 
+// BF16 hi/lo planes and squared norms of the index's raw centroids (the
+// probe's fixed operand), from ix->cent
+hipError_t alloc_cent_planes(Index* ix, hipStream_t st)
+{
+    const int64_t C = ix->nlist, dp = ix->dp;
+    hipError_t e = hipMalloc(&ix->cent_hi, sizeof(unsigned short) * C * dp);
+    if (e == hipSuccess) e = hipMalloc(&ix->cent_lo, sizeof(unsigned short) * C * dp);
+    if (e == hipSuccess) e = hipMalloc(&ix->cent_n2, sizeof(float) * C);
+    if (e == hipSuccess) e = launch_split_norm(ix->cent, C, (int)dp, ix->cent_hi, ix->cent_lo, ix->cent_n2, st);
+    return e;
+}
+
+struct ProbePre {           // operands already split (and their norms), or null
+    const unsigned short *qh = nullptr, *ql = nullptr; const float* qn = nullptr;
+    const unsigned short *ch = nullptr, *cl = nullptr; const float* cn = nullptr;
+};
 int probe_impl(const float* q, int64_t nq, const float* cent, int64_t nlist, int dp, int nprobe,
                int32_t* probes, float* pdist, void* ws, size_t ws_bytes, hipStream_t st,
-               const unsigned short* qh_pre = nullptr, const unsigned short* ql_pre = nullptr);
+               const ProbePre& pre = ProbePre());
 
 // distances nq x nlist, norms, and the BF16 hi/lo planes of both operands
 size_t probe_ws(int64_t nq, int64_t nlist, int dp) {
@@ -160,10 +179,10 @@ size_t probe_ws(int64_t nq, int64_t nlist, int dp) {
            2 * align256(sizeof(unsigned short) * nq * dp) + 2 * align256(sizeof(unsigned short) * nlist * dp);
 }
 
-// qh_pre / ql_pre: the queries' BF16 planes when the caller has them (else split here)
+// pre: the BF16 planes and norms of the queries and / or centroids when the
+// caller has them (else computed here)
 int probe_impl(const float* q, int64_t nq, const float* cent, int64_t nlist, int dp, int nprobe,
-               int32_t* probes, float* pdist, void* ws, size_t ws_bytes, hipStream_t st,
-               const unsigned short* qh_pre, const unsigned short* ql_pre)
+               int32_t* probes, float* pdist, void* ws, size_t ws_bytes, hipStream_t st, const ProbePre& pre)
 {
     if (ws_bytes < probe_ws(nq, nlist, dp)) return fail(ERQ_ENOMEM, "coarse probe: workspace too small");
     char* w = (char*)ws;
@@ -174,13 +193,14 @@ int probe_impl(const float* q, int64_t nq, const float* cent, int64_t nlist, int
     unsigned short* ql = (unsigned short*)w; w += align256(sizeof(unsigned short) * nq * dp);
     unsigned short* ch = (unsigned short*)w; w += align256(sizeof(unsigned short) * nlist * dp);
     unsigned short* cl = (unsigned short*)w;
-    ERQ_HIP(launch_row_sqnorm(q, nq, dp, qn, st));
-    ERQ_HIP(launch_row_sqnorm(cent, nlist, dp, cn, st));
     int pr = prof_begin(PK_PROBE, st);
-    if (qh_pre && ql_pre) { qh = (unsigned short*)qh_pre; ql = (unsigned short*)ql_pre; }
-    else ERQ_HIP(launch_split_bf16(q, nq * dp, qh, ql, st));
-    ERQ_HIP(launch_split_bf16(cent, nlist * dp, ch, cl, st));
-    ERQ_HIP(launch_sqdist_pre(qh, ql, nq, ch, cl, nlist, dp, qn, cn, D, st));
+    const unsigned short *uqh = qh, *uql = ql, *uch = ch, *ucl = cl;
+    const float *uqn = qn, *ucn = cn;
+    if (pre.qh && pre.ql && pre.qn) { uqh = pre.qh; uql = pre.ql; uqn = pre.qn; }
+    else ERQ_HIP(launch_split_norm(q, nq, dp, qh, ql, qn, st));
+    if (pre.ch && pre.cl && pre.cn) { uch = pre.ch; ucl = pre.cl; ucn = pre.cn; }
+    else ERQ_HIP(launch_split_norm(cent, nlist, dp, ch, cl, cn, st));
+    ERQ_HIP(launch_sqdist_pre(uqh, uql, nq, uch, ucl, nlist, dp, uqn, ucn, D, st));
     ERQ_HIP(launch_row_topk(D, nq, nlist, nprobe, probes, pdist, st));
     prof_end(pr, st);
     return ERQ_OK;
@@ -303,6 +323,7 @@ int erq_index_import(erq_index ix, int64_t n, const int64_t* list_off, const int
     ERQ_HIP(hipMalloc(&ix->cent, sizeof(float) * C * dp));
     ERQ_HIP(hipMalloc(&ix->cent_rot, sizeof(float) * C * dp));
     ERQ_HIP(hipMemcpyAsync(ix->cent, centroids, sizeof(float) * C * dp, hipMemcpyDeviceToDevice, st));
+    ERQ_HIP(alloc_cent_planes(ix, st));
     if (centroids_rot)
         ERQ_HIP(hipMemcpyAsync(ix->cent_rot, centroids_rot, sizeof(float) * C * dp, hipMemcpyDeviceToDevice, st));
     else
@@ -347,6 +368,7 @@ int erq_index_build(erq_index ix, const float* x, int64_t n, const float* centro
     ERQ_HIP(hipMalloc(&ix->cent, sizeof(float) * C * dp));
     ERQ_HIP(hipMalloc(&ix->cent_rot, sizeof(float) * C * dp));
     ERQ_HIP(hipMemcpyAsync(ix->cent, centroids, sizeof(float) * C * dp, hipMemcpyDeviceToDevice, st));
+    ERQ_HIP(alloc_cent_planes(ix, st));
     ERQ_HIP(launch_gemm(ix->cent, C, dp, ix->P, dp, 0, 0, ix->cent_rot, dp, st));
 
     // assignment (nearest centroid when not given)
@@ -495,6 +517,7 @@ static size_t search_ws(Index* ix, int64_t nq, int nprobe, int k, int rerank_k) 
     b += align256(sizeof(int64_t) * nq * kk);             // candidate ids
     b += align256(sizeof(float) * nq * kk);               // candidate estimates
     b += 2 * align256(sizeof(unsigned short) * nq * ix->dp);   // BF16 hi/lo planes of the queries
+    b += align256(sizeof(float) * nq);                          // ||q||^2
     b += std::max(probe_ws(nq, ix->nlist, ix->dp), scan_workspace_bytes(nq, nprobe, ix->nlist, kk, ix->dp, ix->max_list));
     return b;
 }
@@ -528,15 +551,19 @@ int erq_search(erq_index ix, const float* q, int64_t nq, int32_t nprobe, int32_t
     float* cest = (float*)w; w += align256(sizeof(float) * nq * kk);
     unsigned short* qh = (unsigned short*)w; w += align256(sizeof(unsigned short) * nq * ix->dp);
     unsigned short* ql = (unsigned short*)w; w += align256(sizeof(unsigned short) * nq * ix->dp);
+    float* qn = (float*)w; w += align256(sizeof(float) * nq);
     size_t rest = ws_bytes - (size_t)(w - (char*)workspace);
     // q' = q P on the BF16 matrix cores from hi/lo planes (the probe's
     // products and error bound); the planes serve the probe too
     int pr = prof_begin(PK_ROTATE, st);
-    ERQ_HIP(launch_split_bf16(q, nq * ix->dp, qh, ql, st));
+    ERQ_HIP(launch_split_norm(q, nq, ix->dp, qh, ql, qn, st));
     ERQ_HIP(launch_gemm_bf16x3(qh, ql, nq, ix->pt_hi, ix->pt_lo, ix->dp, ix->dp, qrot, ix->dp, st));
     prof_end(pr, st);
     // the probe's ||q - c||^2 = ||q' - c'||^2 (P orthogonal) is the scan's ||s||^2
-    if (int rc = probe_impl(q, nq, ix->cent, ix->nlist, ix->dp, nprobe, probes, pdist, w, rest, st, qh, ql)) return rc;
+    ProbePre pre;
+    pre.qh = qh; pre.ql = ql; pre.qn = qn;
+    pre.ch = ix->cent_hi; pre.cl = ix->cent_lo; pre.cn = ix->cent_n2;
+    if (int rc = probe_impl(q, nq, ix->cent, ix->nlist, ix->dp, nprobe, probes, pdist, w, rest, st, pre)) return rc;
     if (int rc = run_scan(ix, qrot, nq, probes, pdist, nprobe, kk, cid, cest, w, rest, st)) return rc;
     if (rerank_k > 0) {
         int pr2 = prof_begin(PK_RERANK, st);

@@ -68,6 +68,9 @@ struct Index {
     unsigned short* pt_lo = nullptr;
     float* cent = nullptr;         // nlist x dp raw centroids
     float* cent_rot = nullptr;     // nlist x dp rotated centroids
+    unsigned short* cent_hi = nullptr;   // BF16 hi/lo planes of the raw centroids and their squared
+    unsigned short* cent_lo = nullptr;   // norms: the probe's B operand, fixed per index
+    float* cent_n2 = nullptr;
     int64_t* list_off = nullptr;   // nlist + 1 (device)
     int64_t* tile_off = nullptr;   // nlist + 1, offset of each list's first tile (device)
     int32_t* list_order = nullptr; // lists by decreasing size (device)

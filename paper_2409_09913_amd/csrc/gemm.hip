@@ -181,17 +181,6 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(
         }
 }
 
-__global__ void row_sqnorm_kernel(const float* __restrict__ X, int64_t n, int K, float* __restrict__ out)
-{
-    int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    int lane = threadIdx.x & 63;
-    if (r >= n) return;
-    float s = 0.0f;
-    for (int k = lane; k < K; k += 64) { float v = X[r * (int64_t)K + k]; s += v * v; }
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    if (lane == 0) out[r] = s;
-}
-
 }  // namespace
 
 hipError_t launch_gemm(const float* A, int64_t n, int K, const float* B, int N, int b_trans,
@@ -204,13 +193,6 @@ hipError_t launch_gemm(const float* A, int64_t n, int K, const float* B, int N, 
     else
         hipLaunchKernelGGL(gemm_f32_kernel<0>, grid, dim3(256), 0, st, A, n, K, B, N, b_trans, out, ldo,
                            (const float*)nullptr, (const float*)nullptr);
-    return hipGetLastError();
-}
-
-hipError_t launch_row_sqnorm(const float* X, int64_t n, int K, float* out, hipStream_t st)
-{
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(row_sqnorm_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, X, n, K, out);
     return hipGetLastError();
 }
 
@@ -365,6 +347,43 @@ hipError_t launch_gemm_bf16x3(const unsigned short* Ah, const unsigned short* Al
     dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((n + BM - 1) / BM));
     hipLaunchKernelGGL(sqdist_bf16x3_kernel<0>, grid, dim3(256), 0, st, Ah, Al, n, K, Bh, Bl, (int)N, out, ldo,
                        (const float*)nullptr, (const float*)nullptr);
+    return hipGetLastError();
+}
+
+// Rows of X (n x K, K a multiple of 4) -> their BF16 hi/lo planes (as
+// split_bf16_kernel) and squared norms ||x||^2 (FP32); one wave per row,
+// 4 consecutive elements per lane
+__global__ __launch_bounds__(256) void split_norm_kernel(const float* __restrict__ X, int64_t n, int K,
+                                                         unsigned short* __restrict__ hi,
+                                                         unsigned short* __restrict__ lo, float* __restrict__ n2)
+{
+    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (r >= n) return;
+    float s = 0.0f;
+    for (int k = 4 * lane; k < K; k += 256) {
+        const int64_t i = r * (int64_t)K + k;
+        const float4 v = *(const float4*)(X + i);
+        const float xv[4] = {v.x, v.y, v.z, v.w};
+        unsigned h[4], l[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            s += xv[c] * xv[c];
+            h[c] = f2bf(xv[c]);
+            l[c] = f2bf(xv[c] - __uint_as_float(h[c] << 16));
+        }
+        *(uint2*)(hi + i) = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+        *(uint2*)(lo + i) = make_uint2(l[0] | (l[1] << 16), l[2] | (l[3] << 16));
+    }
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) n2[r] = s;
+}
+
+hipError_t launch_split_norm(const float* X, int64_t n, int K, unsigned short* hi, unsigned short* lo, float* n2,
+                             hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(split_norm_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, X, n, K, hi, lo, n2);
     return hipGetLastError();
 }
 
