@@ -273,13 +273,16 @@ def main():
     mma_t = ops_alg / (INT8_PEAK_TOPS * 1e12)
     src = open(os.path.join(ROOT, "paper_2409_09913_amd", "csrc", "scan.hip"), "rb").read()
     sha = hashlib.sha256(src).hexdigest()[:16]
+    # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE counters
+    # (profiles/scan_traffic.json, one entry per operating point), used only
+    # when the entry was taken on this scan source at this nprobe and B
     traffic = None
     tf = os.path.join(ROOT, "profiles", "scan_traffic.json")
     if os.path.exists(tf):
         try:
-            t = json.load(open(tf))
-            if t.get("scan_hip_sha256_16") == sha and t.get("nprobe") == nprobe and t.get("bits") == args.bits:
-                traffic = t.get("hbm_bytes_per_launch")
+            for t in json.load(open(tf)).get("entries", []):
+                if t.get("scan_hip_sha256_16") == sha and t.get("nprobe") == nprobe and t.get("bits") == args.bits:
+                    traffic = t.get("hbm_bytes_per_launch")
         except Exception:
             traffic = None
     if hbm_t >= mma_t:
