@@ -1238,38 +1238,50 @@ __global__ void item_desc_kernel(const int32_t* __restrict__ item_off, const int
 
 // A gated pair build (the rescan of overflowed queries, the exact fallback)
 // in one launch of one workgroup: nothing but the published empty build when
-// the gate is off (the usual case); else count per list (global atomics),
-// the list scan, placement and the item descriptors.  The pairs of flagged
-// queries only, so few; their order within a list is free (every query's
-// result is its exact top-kk whatever the grouping).  cnt: nlist counters.
+// the gate is off (the usual case); else the flagged queries are gathered into
+// qlist (nq slots), and only their pairs of rank [rlo, rhi) are visited: count
+// per list (global atomics), the list scan, placement and the item
+// descriptors, in time proportional to the flagged pairs, not to all pairs.
+// Their order within a list is free (every query's result is its exact top-kk
+// whatever the grouping).  cnt: nlist counters.
 __global__ __launch_bounds__(1024) void pair_build_gated_kernel(
-    const int32_t* __restrict__ probes, int64_t np, int nprobe, int nlist, int rlo, int rhi,
+    const int32_t* __restrict__ probes, int64_t nq, int nprobe, int nlist, int rlo, int rhi,
     const int32_t* __restrict__ qmask, const int32_t* __restrict__ list_order,
     const int64_t* __restrict__ list_off, int qpi, int vch, int32_t* __restrict__ cnt,
     int32_t* __restrict__ pair_off, int32_t* __restrict__ item_off, int32_t* __restrict__ pq,
     int32_t* __restrict__ pslot, int4* __restrict__ desc, int64_t cap, int32_t* __restrict__ work,
-    const int32_t* __restrict__ gate)
+    const int32_t* __restrict__ gate, int32_t* __restrict__ qlist)
 {
+    __shared__ int nflag;
     const int tid = threadIdx.x;
     if (tid == 0) *work = 0;
     if (*gate == 0) {
         if (tid == 0) { item_off[nlist] = 0; pair_off[nlist] = 0; }
         return;
     }
+    if (tid == 0) nflag = 0;
     for (int l = tid; l < nlist; l += 1024) cnt[l] = 0;
     __syncthreads();
-    for (int64_t i = tid; i < np; i += 1024) {
-        int l; int64_t q;
-        if (pair_sel(probes, i, nprobe, nlist, rlo, rhi, qmask, &l, &q)) atomicAdd(&cnt[l], 1);
+    for (int64_t q = tid; q < nq; q += 1024)
+        if (!qmask || qmask[q]) qlist[atomicAdd(&nflag, 1)] = (int32_t)q;
+    __syncthreads();
+    const int nr = rhi - rlo;
+    const int64_t nsel = (int64_t)nflag * nr;     // flagged pairs, visited as (query of qlist, rank)
+    for (int64_t j = tid; j < nsel; j += 1024) {
+        const int64_t q = qlist[j / nr];
+        const int l = probes[q * nprobe + rlo + (int)(j % nr)];
+        if (l >= 0 && l < nlist) atomicAdd(&cnt[l], 1);
     }
     __syncthreads();
     list_scan(cnt, nlist, list_order, list_off, qpi, vch, pair_off, item_off);
     __syncthreads();
     for (int l = tid; l < nlist; l += 1024) cnt[l] = 0;     // placement counters
     __syncthreads();
-    for (int64_t i = tid; i < np; i += 1024) {
-        int l; int64_t q;
-        if (!pair_sel(probes, i, nprobe, nlist, rlo, rhi, qmask, &l, &q)) continue;
+    for (int64_t j = tid; j < nsel; j += 1024) {
+        const int64_t q = qlist[j / nr];
+        const int64_t i = q * nprobe + rlo + (int)(j % nr);
+        const int l = probes[i];
+        if (l < 0 || l >= nlist) continue;
         const int pos = pair_off[l] + atomicAdd(&cnt[l], 1);
         pq[pos] = (int32_t)q;
         pslot[pos] = (int32_t)i;
@@ -1535,6 +1547,7 @@ size_t scan_workspace_bytes(int64_t nq, int nprobe, int64_t nlist, int kk, int d
     b += align256((size_t)nq * dp);                        // int8 queries
     b += 2 * align256(sizeof(float) * nq);                 // delta/2, sum of int8 values
     b += align256(sizeof(float) * P);                      // ||s||^2 per pair
+    b += align256(sizeof(int32_t) * nq);                   // flagged queries of a gated pair build
     return b;
 }
 
@@ -1573,6 +1586,7 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, co
     float* qhd = (float*)take(sizeof(float) * nq);
     int32_t* qss = (int32_t*)take(sizeof(int32_t) * nq);
     float* sdist_ws = (float*)take(sizeof(float) * P);
+    int32_t* qlist = (int32_t*)take(sizeof(int32_t) * nq);
 
     const int th = 256;
     auto zero = [&](int32_t* p, int64_t n) {
@@ -1586,9 +1600,9 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, co
     // gated, both overflow flags
     auto build_pairs = [&](int rlo, int rhi, const int32_t* qmask, int qpi, int vch, const int32_t* gate) {
         if (gate) {                                      // usually empty: one launch
-            hipLaunchKernelGGL(pair_build_gated_kernel, dim3(1), dim3(1024), 0, st, probes, P, nprobe, (int)nlist,
+            hipLaunchKernelGGL(pair_build_gated_kernel, dim3(1), dim3(1024), 0, st, probes, nq, nprobe, (int)nlist,
                                rlo, rhi, qmask, ix->list_order, ix->list_off, qpi, vch, cnt, poff, ioff, pq, ps,
-                               desc, dcap, work, gate);
+                               desc, dcap, work, gate, qlist);
             return hipGetLastError();
         }
         if (lds_sort) {

@@ -6,7 +6,9 @@ centroids and the row -> list assignment that both the HIP library
 (erq_index_build) and the CPU oracle receive as inputs.  Readings: seeded
 random initial centroids (distinct rows), a fixed number of Lloyd iterations,
 ties to the lowest centroid id (torch.argmin), an empty cluster keeps its
-previous centroid.
+previous centroid.  The per-list sums are accumulated in a fixed order
+(torch's deterministic index_add_, which sorts by list before summing), so
+the same input and seed give the same centroids and lists on every run.
 """
 from __future__ import annotations
 
@@ -23,6 +25,15 @@ def _assign(x, cent, chunk=65536):
     return out
 
 
+def _list_sums(x, a, nlist):
+    prev = torch.are_deterministic_algorithms_enabled()
+    torch.use_deterministic_algorithms(True)
+    try:
+        return torch.zeros((nlist, x.shape[1]), dtype=x.dtype, device=x.device).index_add_(0, a, x)
+    finally:
+        torch.use_deterministic_algorithms(prev)
+
+
 def kmeans(x: torch.Tensor, nlist: int, iters: int = 10, seed: int = 240909913):
     """Returns (centroids nlist x dp float32, assign int32) on x's device."""
     g = torch.Generator(device="cpu").manual_seed(seed)
@@ -30,7 +41,7 @@ def kmeans(x: torch.Tensor, nlist: int, iters: int = 10, seed: int = 240909913):
     cent = x[idx].clone()
     for _ in range(iters):
         a = _assign(x, cent)
-        sums = torch.zeros_like(cent).index_add_(0, a, x)
+        sums = _list_sums(x, a, nlist)
         cnt = torch.bincount(a, minlength=nlist).to(x.dtype)
         nz = cnt > 0
         cent[nz] = sums[nz] / cnt[nz, None]
