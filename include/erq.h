@@ -182,31 +182,35 @@ int erq_search(erq_index idx, const float* q, int64_t nq, int32_t nprobe, int32_
                void* workspace, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------ */
-/* Scan schedule (tuning, not part of the method).  Three knobs of the       */
+/* Scan schedule (tuning, not part of the method).  Four knobs of the        */
 /* bounded scan; 0 selects the built-in rule:                                */
 /*   nqt    query tiles of 32 per work item, 1 or 2 (2 needs dp <= 1536;     */
 /*          rule: 2 for dp <= 768);                                          */
 /*   pd     K-steps of packed codes in flight per wave, one of 1, 2, 3, 4, 6 */
 /*          dividing dp/64 (6 only for bits <= 4; rule: the largest);        */
 /*   round1 probe ranks of the first bounded round, in [1, 1024]            */
-/*          (rule: 8).                                                       */
+/*          (rule: 8);                                                       */
+/*   round2 end of a middle round [round1, round2), in [0, 1024]; it takes  */
+/*          effect only when round1 < round2 < nprobe (rule: no middle      */
+/*          round).  Each round ends with a select that lowers the bound.   */
 /* No value changes a result: estimates are computed pair by pair in the    */
 /* same arithmetic and the output is the exact top-kk by (estimate, id)      */
 /* under every schedule.  set_tune rejects invalid values (ERQ_EINVAL) and   */
-/* leaves the schedule unchanged; get_tune writes the three stored values.  */
+/* leaves the schedule unchanged; get_tune writes the four stored values.   */
 /* erq_index_tune searches the schedule on the caller's queries and         */
 /* erq_search arguments (outputs and workspace as for erq_search; they hold */
 /* the last call's result on return): first (nqt, pd) over every valid pair */
-/* with round1 fixed, then round1 in {2, 4, 8, 16, 32} (< nprobe); each      */
+/* with round1 and round2 fixed, then round1 in {2, 4, 8, 16, 32}          */
+/* (< nprobe), then round2 in {0, 2, 4, 8, 16} x round1 (< nprobe); each     */
 /* candidate is timed with HIP events over `reps` calls after one untimed   */
-/* call, on `stream`.  It keeps the fastest, writes it to choice[0..2]       */
+/* call, on `stream`.  It keeps the fastest, writes it to choice[0..3]       */
 /* (host) and its mean milliseconds per call to *best_ms (host, may be      */
 /* NULL).  It synchronises the stream and must not run concurrently with    */
 /* other calls on the same index.  reps in [1, 100].  On an error the       */
 /* previous schedule is restored.                                            */
 /* ------------------------------------------------------------------------ */
-int erq_index_set_tune(erq_index idx, int32_t nqt, int32_t pd, int32_t round1);
-int erq_index_get_tune(erq_index idx, int32_t* nqt, int32_t* pd, int32_t* round1);
+int erq_index_set_tune(erq_index idx, int32_t nqt, int32_t pd, int32_t round1, int32_t round2);
+int erq_index_get_tune(erq_index idx, int32_t* nqt, int32_t* pd, int32_t* round1, int32_t* round2);
 int erq_index_tune(erq_index idx, const float* q, int64_t nq, int32_t nprobe, int32_t k,
                    int32_t rerank_k, int32_t reps, int64_t* out_ids, float* out_dist,
                    void* workspace, size_t ws_bytes, void* stream, int32_t* choice, double* best_ms);

@@ -576,7 +576,7 @@ int erq_search(erq_index ix, const float* q, int64_t nq, int32_t nprobe, int32_t
     return ERQ_OK;
 }
 
-int erq_index_set_tune(erq_index ix, int32_t nqt, int32_t pd, int32_t round1)
+int erq_index_set_tune(erq_index ix, int32_t nqt, int32_t pd, int32_t round1, int32_t round2)
 {
     if (!ix) return fail(ERQ_EINVAL, "erq_index_set_tune: null index");
     if (nqt < 0 || nqt > 2 || (nqt == 2 && ix->dp > kMaxDpNqt2))
@@ -584,19 +584,21 @@ int erq_index_set_tune(erq_index ix, int32_t nqt, int32_t pd, int32_t round1)
     if (pd < 0 || (pd > 0 && !scan_pd_valid(pd, ix->dp, ix->bits)))
         return fail(ERQ_EINVAL, "erq_index_set_tune: pd must be 0 or one of 1, 2, 3, 4, 6 dividing dp/64 (6 for bits <= 4)");
     if (round1 < 0 || round1 > 1024) return fail(ERQ_EINVAL, "erq_index_set_tune: round1 must be in [0, 1024]");
-    ix->tune_nqt = nqt; ix->tune_pd = pd; ix->tune_round1 = round1;
+    if (round2 < 0 || round2 > 1024) return fail(ERQ_EINVAL, "erq_index_set_tune: round2 must be in [0, 1024]");
+    ix->tune_nqt = nqt; ix->tune_pd = pd; ix->tune_round1 = round1; ix->tune_round2 = round2;
     return ERQ_OK;
 }
 
-int erq_index_get_tune(erq_index ix, int32_t* nqt, int32_t* pd, int32_t* round1)
+int erq_index_get_tune(erq_index ix, int32_t* nqt, int32_t* pd, int32_t* round1, int32_t* round2)
 {
-    if (!ix || !nqt || !pd || !round1) return fail(ERQ_EINVAL, "erq_index_get_tune: null pointer");
-    *nqt = ix->tune_nqt; *pd = ix->tune_pd; *round1 = ix->tune_round1;
+    if (!ix || !nqt || !pd || !round1 || !round2) return fail(ERQ_EINVAL, "erq_index_get_tune: null pointer");
+    *nqt = ix->tune_nqt; *pd = ix->tune_pd; *round1 = ix->tune_round1; *round2 = ix->tune_round2;
     return ERQ_OK;
 }
 
 // Coordinate search over the scan schedule: first (nqt, pd) with the stored
-// round1, then round1 with the best (nqt, pd); each candidate is timed with
+// round1 and round2, then round1, then round2 (none or a multiple of round1);
+// each candidate is timed with
 // HIP events over `reps` calls of erq_search after one untimed call.
 int erq_index_tune(erq_index ix, const float* q, int64_t nq, int32_t nprobe, int32_t k, int32_t rerank_k,
                    int32_t reps, int64_t* out_ids, float* out_dist, void* workspace, size_t ws_bytes, void* stream,
@@ -611,12 +613,12 @@ int erq_index_tune(erq_index ix, const float* q, int64_t nq, int32_t nprobe, int
         if (ea) hipEventDestroy(ea);
         return fail(ERQ_EDEVICE, "erq_index_tune: hipEventCreate failed");
     }
-    const int saved[3] = {ix->tune_nqt, ix->tune_pd, ix->tune_round1};
+    const int saved[4] = {ix->tune_nqt, ix->tune_pd, ix->tune_round1, ix->tune_round2};
     int rc = ERQ_OK;
     double best = -1.0;
-    int bq = scan_nqt(ix), bp = scan_pd(ix), br = scan_round1(ix);
-    auto time_one = [&](int nqt, int pd, int r1, double* ms) -> int {
-        ix->tune_nqt = nqt; ix->tune_pd = pd; ix->tune_round1 = r1;
+    int bq = scan_nqt(ix), bp = scan_pd(ix), br = scan_round1(ix), b2 = scan_round2(ix);
+    auto time_one = [&](int nqt, int pd, int r1, int r2, double* ms) -> int {
+        ix->tune_nqt = nqt; ix->tune_pd = pd; ix->tune_round1 = r1; ix->tune_round2 = r2;
         if (int r = erq_search(ix, q, nq, nprobe, k, rerank_k, out_ids, out_dist, workspace, ws_bytes, stream)) return r;
         if (hipEventRecord(ea, st) != hipSuccess) return fail(ERQ_EDEVICE, "erq_index_tune: event record failed");
         for (int i = 0; i < reps; ++i)
@@ -634,7 +636,7 @@ int erq_index_tune(erq_index ix, const float* q, int64_t nq, int32_t nprobe, int
         for (int pd : {6, 4, 3, 2, 1}) {
             if (!scan_pd_valid(pd, ix->dp, ix->bits)) continue;
             double ms = 0.0;
-            rc = time_one(nqt, pd, br, &ms);
+            rc = time_one(nqt, pd, br, b2, &ms);
             if (rc != ERQ_OK) break;
             if (best < 0.0 || ms < best) { best = ms; bq = nqt; bp = pd; }
         }
@@ -643,17 +645,25 @@ int erq_index_tune(erq_index ix, const float* q, int64_t nq, int32_t nprobe, int
         if (rc != ERQ_OK) break;
         if (r1 >= nprobe || r1 == br) continue;
         double ms = 0.0;
-        rc = time_one(bq, bp, r1, &ms);
+        rc = time_one(bq, bp, r1, b2, &ms);
         if (rc == ERQ_OK && ms < best) { best = ms; br = r1; }
+    }
+    for (int f : {0, 2, 4, 8, 16}) {
+        if (rc != ERQ_OK) break;
+        const int r2 = f * br;
+        if ((f > 0 && r2 >= nprobe) || r2 == b2) continue;
+        double ms = 0.0;
+        rc = time_one(bq, bp, br, r2, &ms);
+        if (rc == ERQ_OK && ms < best) { best = ms; b2 = r2; }
     }
     hipEventDestroy(ea);
     hipEventDestroy(eb);
     if (rc != ERQ_OK) {
-        ix->tune_nqt = saved[0]; ix->tune_pd = saved[1]; ix->tune_round1 = saved[2];
+        ix->tune_nqt = saved[0]; ix->tune_pd = saved[1]; ix->tune_round1 = saved[2]; ix->tune_round2 = saved[3];
         return rc;
     }
-    ix->tune_nqt = bq; ix->tune_pd = bp; ix->tune_round1 = br;
-    choice[0] = bq; choice[1] = bp; choice[2] = br;
+    ix->tune_nqt = bq; ix->tune_pd = bp; ix->tune_round1 = br; ix->tune_round2 = b2;
+    choice[0] = bq; choice[1] = bp; choice[2] = br; choice[3] = b2;
     if (best_ms) *best_ms = best;
     return ERQ_OK;
 }

@@ -75,6 +75,7 @@ struct Index {
     int64_t* tile_off = nullptr;   // nlist + 1, offset of each list's first tile (device)
     int32_t* list_order = nullptr; // lists by decreasing size (device)
     int tune_nqt = 0, tune_pd = 0, tune_round1 = 0;   // scan schedule; 0 = built-in rule
+    int tune_round2 = 0;                               // end of a middle round of probe ranks; 0 = none
     int64_t* ids = nullptr;        // n, list order
     float2* fac = nullptr;         // n, (f_add, f_rescale), list order
     float2* sfac = nullptr;        // n, (f_add - f_rescale <y_bar, c'>, f_rescale): the scan's factors
@@ -114,6 +115,7 @@ size_t scan_workspace_bytes(int64_t nq, int nprobe, int64_t nlist, int kk, int d
 int scan_nqt(const Index* ix);
 int scan_pd(const Index* ix);
 int scan_round1(const Index* ix);
+int scan_round2(const Index* ix);
 bool scan_pd_valid(int pd, int dp, int bits);
 // pdist: ||q' - c'||^2 per (query, probe) (nq x nprobe) or null to compute it
 int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, const float* pdist, int nprobe,

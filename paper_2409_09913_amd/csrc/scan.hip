@@ -39,7 +39,7 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kQT = 32;        // queries per MFMA column tile
 constexpr int kCapB = 32;      // per-query survivor buffer of a pass-B item (LDS)
-constexpr int kDenseR = 2;     // first bound: nearest probes per query ...
+constexpr int kDenseR = 4;     // first bound: nearest probes per query ...
 constexpr int kDenseV = 256;   // ... and members per list (all estimates kept)
 constexpr int kRound1 = 8;     // pass B, round 1: probe ranks [0, kRound1)
 constexpr int kCapQ = 4096;    // candidate buffer per query (HBM)
@@ -1511,6 +1511,7 @@ int scan_pd(const Index* ix)
 }
 
 int scan_round1(const Index* ix) { return ix->tune_round1 > 0 ? ix->tune_round1 : kRound1; }
+int scan_round2(const Index* ix) { return ix->tune_round2; }
 
 hipError_t launch_scan_fac(const uint8_t* codes_u, const int64_t* list_off, int64_t nlist, const float* cent_rot,
                            const float2* fac, int64_t n, int dp, int bits, float2* sfac, hipStream_t st)
@@ -1669,10 +1670,14 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, co
     if (e == hipSuccess) e = scan_round(0, r0, nullptr, 1, nullptr);
     // bound, then the buffer is emptied (the dense entries are found again by the rounds)
     if (e == hipSuccess) e = select(0, 1, nullptr, nullptr);
-    // pass B in rounds of increasing probe rank; the count before each round is
-    // recorded by the select before it (0 after the dense bound)
-    const int bounds[3] = {0, std::min(nprobe, scan_round1(ix)), nprobe};
-    for (int r = 0; r < 2 && e == hipSuccess; ++r) {
+    // pass B in rounds of increasing probe rank, [0, round1), [round1, round2)
+    // when round2 lies between round1 and nprobe, and the rest; the count
+    // before each round is recorded by the select before it (0 after the
+    // dense bound)
+    const int r1 = std::min(nprobe, scan_round1(ix)), r2 = scan_round2(ix);
+    int bounds[4] = {0, r1, nprobe, nprobe}, nround = 2;
+    if (r2 > r1 && r2 < nprobe) { bounds[2] = r2; nround = 3; }
+    for (int r = 0; r < nround && e == hipSuccess; ++r) {
         const int rlo = bounds[r], rhi = bounds[r + 1];
         if (rhi <= rlo) continue;
         e = scan_round(rlo, rhi, nullptr, 0, nullptr);        // its pair scan zeroes both flags

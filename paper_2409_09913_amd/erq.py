@@ -39,8 +39,8 @@ SIGNATURES = {
     "erq_rerank": (C.c_int, [_p, _p, _i64, _p, _i32, _i32, _p, _p, _p]),
     "erq_search_workspace_size": (C.c_int, [_p, _i64, _i32, _i32, _i32, C.POINTER(_sz)]),
     "erq_search": (C.c_int, [_p, _p, _i64, _i32, _i32, _i32, _p, _p, _p, _sz, _p]),
-    "erq_index_set_tune": (C.c_int, [_p, _i32, _i32, _i32]),
-    "erq_index_get_tune": (C.c_int, [_p, C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i32)]),
+    "erq_index_set_tune": (C.c_int, [_p, _i32, _i32, _i32, _i32]),
+    "erq_index_get_tune": (C.c_int, [_p, C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i32)]),
     "erq_index_tune": (C.c_int, [_p, _p, _i64, _i32, _i32, _i32, _i32, _p, _p, _p, _sz, _p,
                                  C.POINTER(_i32), C.POINTER(C.c_double)]),
     "erq_profile_enable": (C.c_int, [_i32]),
@@ -233,29 +233,29 @@ class Index:
         return ids, d
 
 
-    def set_tune(self, nqt: int = 0, pd: int = 0, round1: int = 0):
+    def set_tune(self, nqt: int = 0, pd: int = 0, round1: int = 0, round2: int = 0):
         """Scan schedule (0 = built-in rule for that knob)."""
-        _check(load().erq_index_set_tune(self.h, nqt, pd, round1))
+        _check(load().erq_index_set_tune(self.h, nqt, pd, round1, round2))
 
     def get_tune(self):
-        a, b, c = _i32(), _i32(), _i32()
-        _check(load().erq_index_get_tune(self.h, C.byref(a), C.byref(b), C.byref(c)))
-        return {"nqt": a.value, "pd": b.value, "round1": c.value}
+        a, b, c, d = _i32(), _i32(), _i32(), _i32()
+        _check(load().erq_index_get_tune(self.h, C.byref(a), C.byref(b), C.byref(c), C.byref(d)))
+        return {"nqt": a.value, "pd": b.value, "round1": c.value, "round2": d.value}
 
     def tune(self, q, nprobe: int, k: int, rerank_k: int = 0, reps: int = 2, ws=None, out=None):
         """Times every valid scan schedule on these queries and keeps the fastest;
-        returns {"nqt", "pd", "round1", "ms"}."""
+        returns {"nqt", "pd", "round1", "round2", "ms"}."""
         nq = q.shape[0]
         if ws is None:
             ws = _ws(self.search_workspace_size(nq, nprobe, k, rerank_k), q.device)
         if out is None:
             out = (torch.empty((nq, k), dtype=torch.int64, device=q.device),
                    torch.empty((nq, k), dtype=torch.float32, device=q.device))
-        ch = (_i32 * 3)()
+        ch = (_i32 * 4)()
         ms = C.c_double()
         _check(load().erq_index_tune(self.h, _ptr(q, torch.float32, "q"), nq, nprobe, k, rerank_k, reps,
                                      _ptr(out[0]), _ptr(out[1]), _ptr(ws), ws.numel(), _stream(), ch, C.byref(ms)))
-        return {"nqt": ch[0], "pd": ch[1], "round1": ch[2], "ms": ms.value}
+        return {"nqt": ch[0], "pd": ch[1], "round1": ch[2], "round2": ch[3], "ms": ms.value}
 
 
 def profile_enable(on=True):

@@ -196,17 +196,18 @@ def test_scan_schedules_identical_results(B):
     pds = [p for p in (1, 2, 3, 4, 6) if (dp // 64) % p == 0 and (p != 6 or B <= 4)]
     for nqt in (1, 2):
         for pd in pds:
-            for r1 in (1, 8, 30):
-                ix.set_tune(nqt, pd, r1)
+            for r1, r2 in ((1, 0), (8, 0), (30, 0), (1, 4), (2, 12), (8, 20), (8, 24), (8, 3)):
+                ix.set_tune(nqt, pd, r1, r2)
                 gi, ge = ix.scan(dev(qrot), dev(probes), kk)
                 torch.cuda.synchronize()
-                np.testing.assert_array_equal(gi.cpu().numpy(), ri, err_msg=str((nqt, pd, r1)))
+                np.testing.assert_array_equal(gi.cpu().numpy(), ri, err_msg=str((nqt, pd, r1, r2)))
                 np.testing.assert_array_equal(ge.cpu().numpy().view(np.uint32), re.view(np.uint32))
-    say("  B=%d: %d schedules identical" % (B, 2 * len(pds) * 3))
-    for bad in ((3, 0, 0), (0, 5, 0), (0, 0, 2000), (-1, 0, 0)) + (((0, 6, 0),) if B > 4 else ()):
+    say("  B=%d: %d schedules identical" % (B, 2 * len(pds) * 8))
+    for bad in ((3, 0, 0, 0), (0, 5, 0, 0), (0, 0, 2000, 0), (-1, 0, 0, 0), (0, 0, 0, 1025), (0, 0, 0, -1)) + \
+            (((0, 6, 0, 0),) if B > 4 else ()):
         with pytest.raises(erq.ErqError):
             ix.set_tune(*bad)
-    ix.set_tune(0, 0, 0)
+    ix.set_tune(0, 0, 0, 0)
     ix.close()
 
 
@@ -222,7 +223,8 @@ def test_autotune_search():
     ch = ix.tune(q, 16, 10, 20, reps=1)
     say("  tuned", ch)
     assert ch["nqt"] in (1, 2) and ch["pd"] in (1, 2, 3, 4, 6) and 1 <= ch["round1"] <= 1024 and ch["ms"] > 0
-    assert ix.get_tune() == {"nqt": ch["nqt"], "pd": ch["pd"], "round1": ch["round1"]}
+    assert ch["round2"] == 0 or ch["round1"] < ch["round2"] < 16
+    assert ix.get_tune() == {k: ch[k] for k in ("nqt", "pd", "round1", "round2")}
     gi, gd = ix.search(q, 16, 10, 20)
     torch.cuda.synchronize()
     np.testing.assert_array_equal(gi.cpu().numpy(), ri.cpu().numpy())

@@ -292,6 +292,34 @@ def test_coarse_probe_parity():
             np.testing.assert_array_equal(np.sort(pg[i]), np.sort(po[i]))
 
 
+@pytest.mark.parametrize("nl,nprobe", [(1, 1), (63, 7), (64, 64), (65, 10), (300, 17), (1000, 88), (1024, 256),
+                                       (1025, 100), (2048, 1), (3000, 128), (4096, 88), (4096, 256), (4096, 300),
+                                       (5000, 96), (9000, 40)])
+def test_probe_selection_exact_ties(nl, nprobe):
+    """The nprobe nearest centroids, ascending by (distance, column), where the
+    distances are small integers (exact in FP32 and in the BF16 planes) with
+    many ties, so the rows decide ties among equal distances by column.
+    Covers each register-tile width of the selection kernel (rows of up to
+    1024, 2048, 4096 and 8192 entries, and longer rows read from memory) and
+    ragged row lengths."""
+    say("probe ties", nl, nprobe)
+    g = np.random.default_rng(nl * 7 + nprobe)
+    dp, nq = 64, 37
+    cent = np.zeros((nl, dp), np.float32)
+    cent[:, :6] = g.integers(-2, 3, (nl, 6))
+    q = np.zeros((nq, dp), np.float32)
+    q[:, :6] = g.integers(-2, 3, (nq, 6))
+    q[0] = 0.0
+    pg, dg = erq.coarse_probe(dev(q), dev(cent), nprobe, with_dist=True)
+    pg, dg = pg.cpu().numpy(), dg.cpu().numpy()
+    exact = ((q[:, None, :6].astype(np.int64) - cent[None, :, :6].astype(np.int64)) ** 2).sum(-1)
+    cols = np.arange(nl)
+    for i in range(nq):
+        order = np.lexsort((cols, exact[i]))[:nprobe]
+        np.testing.assert_array_equal(pg[i], order)
+        np.testing.assert_array_equal(dg[i], exact[i][order].astype(np.float32))
+
+
 def test_rerank_parity():
     say("rerank")
     dp, n, nq, kc, k = 192, 2000, 30, 50, 10
