@@ -167,7 +167,7 @@ def main():
     def sweep(index, label):
         rows = []
         grid = [(args.nprobe, max(args.rerank, 0))] if args.nprobe > 0 else \
-            [(n_, r_) for n_ in (16, 32, 64, 72, 80, 88, 96, 112, 128, 160, 256) for r_ in (0, 16, 20, 24, 32)]
+            [(n_, r_) for n_ in (16, 32, 64, 72, 80, 84, 88, 92, 96, 104, 112, 128, 160, 256) for r_ in (0, 16, 18, 20, 22, 24, 32)]
         for nprobe, rr in grid:
             if True:
                 ids, qps = timed_search(index, nprobe, rr, 3)
@@ -312,6 +312,9 @@ def main():
     if args.serve:
         srv = serve.Server(ix, max_batch=1024, max_nprobe=max(nprobe, 64), max_k=args.k, max_rerank=max(rr, 20),
                            slots=4)
+        # untimed pass first: the slots' streams and output blocks are set up on first use
+        serve.poisson_run(srv, q, rate=10000.0, n_requests=200, per_request=1, k=args.k, nprobes=(16, 64),
+                          rerank_k=rr, seed=1)
         res_s = {}
         for rate in (1000.0, 10000.0, 50000.0):
             reqs, p50, p99, sq = serve.poisson_run(srv, q, rate=rate, n_requests=args.serve, per_request=1,
