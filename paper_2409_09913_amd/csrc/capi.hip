@@ -5,6 +5,8 @@
 #include <cstring>
 #include <numeric>
 
+#include <hipcub/hipcub.hpp>
+
 #include "erq_common.h"
 
 namespace erq {
@@ -25,9 +27,6 @@ hipError_t launch_pack_n(const uint8_t* codes, const int64_t* list_off, const in
 hipError_t launch_unpack_n(const uint8_t* packed, const int64_t* list_off, const int64_t* tile_off,
                            int64_t nlist, int dp, int bits, int64_t ntiles, uint8_t* codes, hipStream_t st);
 hipError_t launch_count(const int32_t* assign, int64_t n, int64_t nlist, int32_t* cnt, int32_t* bad, hipStream_t st);
-hipError_t launch_scatter(const int32_t* assign, int64_t n, const int64_t* off, int32_t* fill, int32_t* ids32,
-                          hipStream_t st);
-hipError_t launch_sort_lists(const int64_t* off, int64_t nlist, int32_t* ids32, int64_t* ids64, hipStream_t st);
 
 static thread_local std::string g_err;
 
@@ -102,6 +101,14 @@ __global__ void split_fac_kernel(const float2* f, int64_t n, float* a, float* b)
 __global__ void fill_i32(int32_t* p, int64_t n, int32_t v) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
+}
+__global__ void iota_i32(int32_t* p, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = (int32_t)i;
+}
+__global__ void widen_i32(const int32_t* a, int64_t n, int64_t* b) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = a[i];
 }
 __global__ void gather_topk_kernel(const int32_t* idx, int64_t n, int k, int32_t* out) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -373,7 +380,7 @@ int erq_index_build(erq_index ix, const float* x, int64_t n, const float* centro
 
     // assignment (nearest centroid when not given)
     int32_t* asg = nullptr;
-    int32_t* aux = nullptr;     // cnt | fill | bad
+    int32_t* aux = nullptr;     // cnt | (unused) | bad
     ERQ_HIP(hipMalloc(&asg, sizeof(int32_t) * std::max<int64_t>(n, 1)));
     ERQ_HIP(hipMalloc(&aux, sizeof(int32_t) * (2 * C + 1)));
     struct Guard { std::vector<void*> p; ~Guard() { for (void* q : p) hipFree(q); } } guard;
@@ -392,7 +399,6 @@ int erq_index_build(erq_index ix, const float* x, int64_t n, const float* centro
         }
     }
     int32_t* cnt = aux;
-    int32_t* fillc = aux + C;
     int32_t* bad = aux + 2 * C;
     hipLaunchKernelGGL(fill_i32, dim3(blocks(2 * C + 1)), dim3(256), 0, st, aux, 2 * C + 1, 0);
     ERQ_HIP(launch_count(asg, n, C, cnt, bad, st));
@@ -413,8 +419,27 @@ int erq_index_build(erq_index ix, const float* x, int64_t n, const float* centro
     ERQ_HIP(hipMalloc(&ix->fac, sizeof(float2) * std::max<int64_t>(n, 1)));
     ERQ_HIP(hipMalloc(&ix->sfac, sizeof(float2) * std::max<int64_t>(n, 1)));
     ERQ_HIP(hipMalloc(&ix->codes, std::max<int64_t>((int64_t)4 * dp * ix->bits * ix->ntiles, 256)));
-    ERQ_HIP(launch_scatter(asg, n, ix->list_off, fillc, ids32, st));
-    ERQ_HIP(launch_sort_lists(ix->list_off, C, ids32, ix->ids, st));
+    // members in list order, ids ascending within each list: a stable radix
+    // sort of (list, id) pairs by list, so the layout is the same on every build
+    if (n > 0) {
+        int32_t *iota = nullptr, *keys = nullptr;
+        ERQ_HIP(hipMalloc(&iota, sizeof(int32_t) * n));
+        guard.p.push_back(iota);
+        ERQ_HIP(hipMalloc(&keys, sizeof(int32_t) * n));
+        guard.p.push_back(keys);
+        hipLaunchKernelGGL(iota_i32, dim3(blocks(n)), dim3(256), 0, st, iota, n);
+        ERQ_HIP(hipGetLastError());
+        int end_bit = 1;
+        while ((1LL << end_bit) < C) ++end_bit;
+        size_t tb = 0;
+        ERQ_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, asg, keys, iota, ids32, (int)n, 0, end_bit, st));
+        void* tmp = nullptr;
+        ERQ_HIP(hipMalloc(&tmp, std::max<size_t>(tb, 1)));
+        guard.p.push_back(tmp);
+        ERQ_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tb, asg, keys, iota, ids32, (int)n, 0, end_bit, st));
+        hipLaunchKernelGGL(widen_i32, dim3(blocks(n)), dim3(256), 0, st, ids32, n, ix->ids);
+        ERQ_HIP(hipGetLastError());
+    }
 
     // residual -> rotate -> quantise, in batches, list order
     uint8_t* codes_u = nullptr;

@@ -4,7 +4,7 @@
 //    probe (Sec. 4.1) and the nearest centroid of a k-means assignment.
 //    Exact radix select on the order-preserving integer image of the floats
 //    (4 passes of 8 bits), then a stable compaction and a bitonic sort.
-//  * IVF list construction: count, scan, scatter, per-list sort of ids.
+//  * IVF list construction: the member count of every list.
 //  * residuals r = x - c and ||r||^2 (FP64 accumulate) in list order.
 #include "erq_common.h"
 
@@ -179,45 +179,6 @@ __global__ void count_kernel(const int32_t* __restrict__ assign, int64_t n, int6
     atomicAdd(&cnt[l], 1);
 }
 
-__global__ void scatter_kernel(const int32_t* __restrict__ assign, int64_t n, const int64_t* __restrict__ off,
-                               int32_t* __restrict__ fill, int32_t* __restrict__ ids32)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int32_t l = assign[i];
-    int32_t p = atomicAdd(&fill[l], 1);
-    ids32[off[l] + p] = (int32_t)i;
-}
-
-// per-list ascending sort of the ids (one workgroup per list, lists <= 16384)
-__global__ __launch_bounds__(1024) void sort_lists_kernel(const int64_t* __restrict__ off, int32_t* __restrict__ ids32,
-                                                          int64_t* __restrict__ ids64)
-{
-    __shared__ int s[16384];
-    const int l = blockIdx.x;
-    const int64_t lo = off[l];
-    const int n = (int)(off[l + 1] - lo);
-    if (n > 16384) {            // too long for one LDS sort: keep the scatter order
-        for (int t = threadIdx.x; t < n; t += blockDim.x) ids64[lo + t] = ids32[lo + t];
-        return;
-    }
-    int S = 1;
-    while (S < n) S <<= 1;
-    for (int t = threadIdx.x; t < S; t += blockDim.x) s[t] = (t < n) ? ids32[lo + t] : 0x7FFFFFFF;
-    for (int kb = 2; kb <= S; kb <<= 1)
-        for (int j = kb >> 1; j > 0; j >>= 1) {
-            __syncthreads();
-            for (int t = threadIdx.x; t < S / 2; t += blockDim.x) {
-                int i = 2 * t - (t & (j - 1)), p = i + j;
-                bool up = (i & kb) == 0;
-                int a = s[i], b = s[p];
-                if ((a < b) != up) { s[i] = b; s[p] = a; }
-            }
-        }
-    __syncthreads();
-    for (int t = threadIdx.x; t < n; t += blockDim.x) ids64[lo + t] = s[t];
-}
-
 // residual rows in list order: res[v] = x[ids[v]] - cent[assign[ids[v]]]; norm2 in FP64
 __global__ void residual_kernel(const float* __restrict__ x, const int64_t* __restrict__ ids,
                                 const int32_t* __restrict__ assign, const float* __restrict__ cent,
@@ -259,21 +220,6 @@ hipError_t launch_count(const int32_t* assign, int64_t n, int64_t nlist, int32_t
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(count_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, assign, n, nlist, cnt, bad);
-    return hipGetLastError();
-}
-
-hipError_t launch_scatter(const int32_t* assign, int64_t n, const int64_t* off, int32_t* fill, int32_t* ids32,
-                          hipStream_t st)
-{
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, assign, n, off, fill, ids32);
-    return hipGetLastError();
-}
-
-hipError_t launch_sort_lists(const int64_t* off, int64_t nlist, int32_t* ids32, int64_t* ids64, hipStream_t st)
-{
-    if (nlist <= 0) return hipSuccess;
-    hipLaunchKernelGGL(sort_lists_kernel, dim3((unsigned)nlist), dim3(1024), 0, st, off, ids32, ids64);
     return hipGetLastError();
 }
 

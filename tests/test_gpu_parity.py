@@ -345,6 +345,33 @@ def test_rerank_parity():
 # ---------------------------------------------------------------------------
 # end to end on the tiny GMM workload (10,000 x 128, B = 4)
 # ---------------------------------------------------------------------------
+def test_build_list_order_deterministic():
+    """Members are laid out by list with ids ascending within each list, one
+    list longer than 16,384 members included, and two builds of the same
+    input export the same index bit for bit."""
+    say("build list order")
+    dp, nl, n = 64, 8, 60000
+    g = np.random.default_rng(91)
+    x = synth.gmm(n, dp, 8, 0.5, seed=92, dp=dp)
+    assign = g.integers(1, nl, n).astype(np.int32)
+    assign[g.choice(n, 20000, replace=False)] = 0
+    cent = np.stack([x[assign == l].astype(np.float64).mean(0) for l in range(nl)]).astype(np.float32)
+    P = synth.haar_orthogonal(dp, seed=93).astype(np.float32)
+    outs = []
+    for _ in range(2):
+        ix = erq.Index(dp, 4, nl, dev(P))
+        ix.build(dev(x), dev(cent), dev(assign))
+        outs.append([t.cpu().numpy() for t in ix.export()])
+        ix.close()
+    for a, b in zip(*outs):
+        assert a.tobytes() == b.tobytes()
+    off, ids = outs[0][0], outs[0][1]
+    np.testing.assert_array_equal(np.diff(off), np.bincount(assign, minlength=nl))
+    for l in range(nl):
+        seg = ids[off[l]:off[l + 1]]
+        np.testing.assert_array_equal(seg, np.nonzero(assign == l)[0])
+
+
 def test_end_to_end_tiny():
     say("end to end tiny")
     x, q = synth.tiny_gmm()
