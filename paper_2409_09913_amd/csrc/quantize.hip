@@ -11,8 +11,11 @@
 //      pattern of the double x, counting events with one binary search per
 //      level; a window holds at most CAP events (CAP >= 2 dp, and an exact
 //      tie group has at most dp events, so bisection always succeeds);
-//   3. the window's events are gathered, bitonic-sorted by (d desc, dim asc),
-//      and prefix-summed in integers: 2<y,r'> as int64 fixed point (a scaled
+//   3. the window's events are ordered by (d desc, dim asc): for B <= 4
+//      each goes to its rank (every level's events are already in order; the
+//      rank adds, per other level, a binary search on exact products), for
+//      larger B they are gathered and bitonic-sorted; then prefix-summed in
+//      integers: 2<y,r'> as int64 fixed point (a scaled
 //      by the power of two that puts max a in [1,2), 40 fractional bits) and
 //      4||y||^2 exactly; the objective double(2S1)/sqrt(double(4S2)) of every
 //      event is compared, keeping the first strict maximum;
@@ -359,36 +362,72 @@ __global__ __launch_bounds__(kThreads) void quantize_kernel(
         }
         int S = 1;
         while (S < W) S <<= 1;
-        // gather
-        for (int t = tid; t < S; t += kThreads) {
-            if (t < W) {
+        if (K <= 7) {
+            // few levels (B <= 4): ranks, no sort stages
+            // every event of the window goes straight to its rank by (d desc, dim
+            // asc): its rank in its own level's run (sorted by a descending, dim
+            // ascending, so by d descending) plus, for every other level, the
+            // number of that run's window events before it, by binary search.
+            // a'/m' > a/m is decided as a'*m > a*m', exact in double (24-bit
+            // magnitudes times levels below 2^7), which orders the events as
+            // their keys do (distinct ratios give distinct keys in the same order)
+            for (int t = tid; t < W; t += kThreads) {
                 int lo = 0, hi = K;            // largest m with loff[m] <= t
                 while (hi - lo > 1) { int mid = (lo + hi) >> 1; if (s.loff[mid] <= t) lo = mid; else hi = mid; }
-                int m = lo + 1;
-                int j = s.cprev[lo] + (t - s.loff[lo]);
-                s.key[t] = (double)s.A[j] / (double)m;
-                s.pay[t] = ((unsigned)m << 12) | (unsigned)s.I[j];
-            } else {
-                s.key[t] = -1.0;
-                s.pay[t] = 0xFFFFFu;
+                const int m = lo + 1;
+                const int j = s.cprev[lo] + (t - s.loff[lo]);
+                const float a = s.A[j];
+                const int dim = s.I[j];
+                int rank = t - s.loff[lo];
+                for (int l2 = 0; l2 < K; ++l2) {
+                    if (l2 == lo) continue;
+                    const double am2 = (double)a * (double)(l2 + 1);
+                    int b = s.cprev[l2], e = s.cnext[l2];
+                    while (b < e) {                // first event of run l2 that does not come before
+                        const int mid = (b + e) >> 1;
+                        const double pm = (double)s.A[mid] * (double)m;
+                        if (pm > am2 || (pm == am2 && s.I[mid] < dim)) b = mid + 1;
+                        else e = mid;
+                    }
+                    rank += b - s.cprev[l2];
+                }
+                s.key[rank] = (double)a / (double)m;
+                s.pay[rank] = ((unsigned)m << 12) | (unsigned)dim;
             }
-        }
-        // bitonic sort of the window by (d desc, dim asc)
-        for (int k = 2; k <= S; k <<= 1) {
-            for (int j = k >> 1; j > 0; j >>= 1) {
-                __syncthreads();
-                for (int t = tid; t < S / 2; t += kThreads) {
-                    int i = 2 * t - (t & (j - 1));
-                    int p = i + j;
-                    bool up = ((i & k) == 0);
-                    double k0 = s.key[i], k1 = s.key[p];
-                    unsigned p0 = s.pay[i], p1 = s.pay[p];
-                    bool first0 = key_before(k0, (int)(p0 & 0xFFFu), k1, (int)(p1 & 0xFFFu));
-                    if (first0 != up) { s.key[i] = k1; s.key[p] = k0; s.pay[i] = p1; s.pay[p] = p0; }
+            __syncthreads();
+        } else {
+            // many levels: gather, then a bitonic sort of the window
+            // gather
+            for (int t = tid; t < S; t += kThreads) {
+                if (t < W) {
+                    int lo = 0, hi = K;            // largest m with loff[m] <= t
+                    while (hi - lo > 1) { int mid = (lo + hi) >> 1; if (s.loff[mid] <= t) lo = mid; else hi = mid; }
+                    int m = lo + 1;
+                    int j = s.cprev[lo] + (t - s.loff[lo]);
+                    s.key[t] = (double)s.A[j] / (double)m;
+                    s.pay[t] = ((unsigned)m << 12) | (unsigned)s.I[j];
+                } else {
+                    s.key[t] = -1.0;
+                    s.pay[t] = 0xFFFFFu;
                 }
             }
+            // bitonic sort of the window by (d desc, dim asc)
+            for (int k = 2; k <= S; k <<= 1) {
+                for (int j = k >> 1; j > 0; j >>= 1) {
+                    __syncthreads();
+                    for (int t = tid; t < S / 2; t += kThreads) {
+                        int i = 2 * t - (t & (j - 1));
+                        int p = i + j;
+                        bool up = ((i & k) == 0);
+                        double k0 = s.key[i], k1 = s.key[p];
+                        unsigned p0 = s.pay[i], p1 = s.pay[p];
+                        bool first0 = key_before(k0, (int)(p0 & 0xFFFu), k1, (int)(p1 & 0xFFFu));
+                        if (first0 != up) { s.key[i] = k1; s.key[p] = k0; s.pay[i] = p1; s.pay[p] = p0; }
+                    }
+                }
+            }
+            __syncthreads();
         }
-        __syncthreads();
         // integer prefix sums over the window; each thread owns a contiguous chunk
         const int L = (S + kThreads - 1) / kThreads;
         const int beg = tid * L, end = min(W, beg + L);
