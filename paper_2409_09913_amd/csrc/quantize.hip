@@ -99,10 +99,12 @@ struct Smem {
     long long* red_ll; double* red_d; float* red_f; int* misc;
 };
 
-__device__ inline Smem carve(char* base, int SA, int dp, int cap, int bb) {
+// The window's keys are stored only for the sort (B >= 5, keyed = 1); ranks
+// (B <= 4) need only the (level, dimension) payload.
+__device__ inline Smem carve(char* base, int SA, int dp, int cap, int bb, int keyed) {
     Smem s;
     size_t o = 0;
-    s.key = (double*)(base + o); o += sizeof(double) * cap;
+    s.key = keyed ? (double*)(base + o) : nullptr; o += keyed ? sizeof(double) * cap : 0;
     s.afx = (long long*)(base + o); o += sizeof(long long) * dp;
     s.ps = (long long*)(base + o); o += bb ? sizeof(long long) * (SA + 1) : 0;
     s.red_ll = (long long*)(base + o); o += sizeof(long long) * 2 * (kThreads + 8);
@@ -118,8 +120,8 @@ __device__ inline Smem carve(char* base, int SA, int dp, int cap, int bb) {
     return s;
 }
 
-__host__ __device__ inline size_t smem_bytes(int SA, int dp, int cap, int bb) {
-    return sizeof(double) * cap + sizeof(long long) * dp + (bb ? sizeof(long long) * (SA + 1) : 0) +
+__host__ __device__ inline size_t smem_bytes(int SA, int dp, int cap, int bb, int keyed) {
+    return (keyed ? sizeof(double) * cap : 0) + sizeof(long long) * dp + (bb ? sizeof(long long) * (SA + 1) : 0) +
            sizeof(long long) * 2 * (kThreads + 8) +
            sizeof(double) * 8 + sizeof(float) * SA + sizeof(int) * SA + sizeof(unsigned) * cap +
            sizeof(int) * (128 + 128 + 132) + sizeof(float) * 8 + sizeof(int) * 16;
@@ -138,7 +140,7 @@ __global__ __launch_bounds__(kThreads) void quantize_kernel(
     const int lane = tid & 63, wid = tid >> 6;
     const int64_t row = blockIdx.x;
     if (row >= n_vec) return;
-    Smem s = carve(smem_raw, SA, dp, cap, bb);
+    Smem s = carve(smem_raw, SA, dp, cap, bb, bits >= 5);
     const float* r = rrot + row * (int64_t)dp;
     const int K = (1 << (bits - 1)) - 1;
     const int half = 1 << (bits - 1);
@@ -391,7 +393,6 @@ __global__ __launch_bounds__(kThreads) void quantize_kernel(
                     }
                     rank += b - s.cprev[l2];
                 }
-                s.key[rank] = (double)a / (double)m;
                 s.pay[rank] = ((unsigned)m << 12) | (unsigned)dim;
             }
             __syncthreads();
@@ -480,8 +481,9 @@ __global__ __launch_bounds__(kThreads) void quantize_kernel(
             }
             if (bp != 0x7FFFFFFF && bv > best_v) {
                 best_v = bv;
-                best_d = s.key[bp];
                 best_i = (int)(s.pay[bp] & 0xFFFu);
+                // the key of the best event, as the sort would have stored it
+                best_d = s.key ? s.key[bp] : (double)fabsf(r[best_i]) / (double)(s.pay[bp] >> 12);
                 best_s2 = bs2;
             }
         }
@@ -551,8 +553,17 @@ hipError_t launch_quantize(const float* rrot, int64_t n, int dp, int bits, const
     if (cap < 4096) cap = 4096;
     // pruning pays off from B = 5 (15+ levels, many windows per vector) and
     // needs its prefix sums to fit in LDS
-    int bb = (bits >= 5 && smem_bytes(SA, dp, cap, 1) <= 160 * 1024) ? 1 : 0;
-    size_t sm = smem_bytes(SA, dp, cap, bb);
+    const int keyed = bits >= 5;
+    int bb = (bits >= 5 && smem_bytes(SA, dp, cap, 1, keyed) <= 160 * 1024) ? 1 : 0;
+    // ranks (B <= 4): one window for all of a vector's events when the
+    // payloads fit in a third of the LDS (three blocks per CU): no bisection
+    if (!keyed) {
+        const int K = (1 << (bits - 1)) - 1;
+        int call = cap;
+        while (call < K * dp) call <<= 1;
+        if (call > cap && smem_bytes(SA, dp, call, 0, 0) <= 53 * 1024) cap = call;
+    }
+    size_t sm = smem_bytes(SA, dp, cap, bb, keyed);
     if (sm > 48 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void*)quantize_kernel,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
