@@ -37,6 +37,7 @@ namespace erq {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr int kRedLL = 64;           // int64 reduction slots (block_sum3 uses 32..43)
 
 __device__ inline double wave_sum_d(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -107,7 +108,7 @@ __device__ inline Smem carve(char* base, int SA, int dp, int cap, int bb, int ke
     s.key = keyed ? (double*)(base + o) : nullptr; o += keyed ? sizeof(double) * cap : 0;
     s.afx = (long long*)(base + o); o += sizeof(long long) * dp;
     s.ps = (long long*)(base + o); o += bb ? sizeof(long long) * (SA + 1) : 0;
-    s.red_ll = (long long*)(base + o); o += sizeof(long long) * 2 * (kThreads + 8);
+    s.red_ll = (long long*)(base + o); o += sizeof(long long) * kRedLL;
     s.red_d = (double*)(base + o); o += sizeof(double) * 8;
     s.A = (float*)(base + o); o += sizeof(float) * SA;
     s.I = (int*)(base + o); o += sizeof(int) * SA;
@@ -122,7 +123,7 @@ __device__ inline Smem carve(char* base, int SA, int dp, int cap, int bb, int ke
 
 __host__ __device__ inline size_t smem_bytes(int SA, int dp, int cap, int bb, int keyed) {
     return (keyed ? sizeof(double) * cap : 0) + sizeof(long long) * dp + (bb ? sizeof(long long) * (SA + 1) : 0) +
-           sizeof(long long) * 2 * (kThreads + 8) +
+           sizeof(long long) * kRedLL +
            sizeof(double) * 8 + sizeof(float) * SA + sizeof(int) * SA + sizeof(unsigned) * cap +
            sizeof(int) * (128 + 128 + 132) + sizeof(float) * 8 + sizeof(int) * 16;
 }
@@ -555,12 +556,12 @@ hipError_t launch_quantize(const float* rrot, int64_t n, int dp, int bits, const
     // needs its prefix sums to fit in LDS
     const int keyed = bits >= 5;
     int bb = (bits >= 5 && smem_bytes(SA, dp, cap, 1, keyed) <= 160 * 1024) ? 1 : 0;
-    // ranks (B <= 4): one window for all of a vector's events when the
-    // payloads fit in a third of the LDS (three blocks per CU): no bisection
+    // ranks (B <= 4): one window for all of a vector's events when their
+    // payloads fit in a third of the LDS (at least three blocks per CU): no
+    // bisection for the window ends
     if (!keyed) {
         const int K = (1 << (bits - 1)) - 1;
-        int call = cap;
-        while (call < K * dp) call <<= 1;
+        const int call = (K * dp + 63) & ~63;
         if (call > cap && smem_bytes(SA, dp, call, 0, 0) <= 53 * 1024) cap = call;
     }
     size_t sm = smem_bytes(SA, dp, cap, bb, keyed);
