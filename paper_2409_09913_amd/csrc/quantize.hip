@@ -551,7 +551,10 @@ hipError_t launch_quantize(const float* rrot, int64_t n, int dp, int bits, const
     while (SA < dp) SA <<= 1;
     int cap = 1;
     while (cap < 2 * dp) cap <<= 1;
-    if (cap < 4096) cap = 4096;
+    // B >= 5 (sorted windows, pruned or bisected): 2048 keeps three blocks
+    // per CU at dp 768; the window must stay a power of two >= 2 dp
+    const int cap_floor = bits >= 5 ? 2048 : 4096;
+    if (cap < cap_floor) cap = cap_floor;
     // pruning pays off from B = 5 (15+ levels, many windows per vector) and
     // needs its prefix sums to fit in LDS
     const int keyed = bits >= 5;
