@@ -96,6 +96,7 @@ __device__ inline void block_sum3(long long* red, long long& a, long long& b, lo
 
 struct Smem {
     float* A; int* I; long long* afx; long long* ps; double* key; unsigned* pay;
+    unsigned short* pay16;     // the same payloads in 16 bits when not keyed (level <= 7, dim < 4096)
     int* cprev; int* cnext; int* loff;
     long long* red_ll; double* red_d; float* red_f; int* misc;
 };
@@ -112,7 +113,9 @@ __device__ inline Smem carve(char* base, int SA, int dp, int cap, int bb, int ke
     s.red_d = (double*)(base + o); o += sizeof(double) * 8;
     s.A = (float*)(base + o); o += sizeof(float) * SA;
     s.I = (int*)(base + o); o += sizeof(int) * SA;
-    s.pay = (unsigned*)(base + o); o += sizeof(unsigned) * cap;
+    s.pay = (unsigned*)(base + o);
+    s.pay16 = (unsigned short*)(base + o);
+    o += (keyed ? sizeof(unsigned) : sizeof(unsigned short)) * cap;
     s.cprev = (int*)(base + o); o += sizeof(int) * 128;
     s.cnext = (int*)(base + o); o += sizeof(int) * 128;
     s.loff = (int*)(base + o); o += sizeof(int) * 132;
@@ -124,7 +127,8 @@ __device__ inline Smem carve(char* base, int SA, int dp, int cap, int bb, int ke
 __host__ __device__ inline size_t smem_bytes(int SA, int dp, int cap, int bb, int keyed) {
     return (keyed ? sizeof(double) * cap : 0) + sizeof(long long) * dp + (bb ? sizeof(long long) * (SA + 1) : 0) +
            sizeof(long long) * kRedLL +
-           sizeof(double) * 8 + sizeof(float) * SA + sizeof(int) * SA + sizeof(unsigned) * cap +
+           sizeof(double) * 8 + sizeof(float) * SA + sizeof(int) * SA +
+           (keyed ? sizeof(unsigned) : sizeof(unsigned short)) * cap +
            sizeof(int) * (128 + 128 + 132) + sizeof(float) * 8 + sizeof(int) * 16;
 }
 
@@ -394,7 +398,7 @@ __global__ __launch_bounds__(kThreads) void quantize_kernel(
                     }
                     rank += b - s.cprev[l2];
                 }
-                s.pay[rank] = ((unsigned)m << 12) | (unsigned)dim;
+                s.pay16[rank] = (unsigned short)((m << 12) | dim);
             }
             __syncthreads();
         } else {
@@ -435,7 +439,7 @@ __global__ __launch_bounds__(kThreads) void quantize_kernel(
         const int beg = tid * L, end = min(W, beg + L);
         long long ls1 = 0, ls2 = 0;
         for (int t = beg; t < end; ++t) {
-            unsigned pp = s.pay[t];
+            unsigned pp = s.key ? s.pay[t] : (unsigned)s.pay16[t];
             ls1 += 2 * s.afx[pp & 0xFFFu];
             ls2 += 8 * (long long)(pp >> 12);
         }
@@ -455,7 +459,7 @@ __global__ __launch_bounds__(kThreads) void quantize_kernel(
         long long c2 = s2base + w2 + i2 - ls2;
         double tb = 0.0; int tpos = -1; long long ts2 = 0;
         for (int t = beg; t < end; ++t) {
-            unsigned pp = s.pay[t];
+            unsigned pp = s.key ? s.pay[t] : (unsigned)s.pay16[t];
             c1 += 2 * s.afx[pp & 0xFFFu];
             c2 += 8 * (long long)(pp >> 12);
             double v = (double)c1 / sqrt((double)c2);
@@ -482,9 +486,10 @@ __global__ __launch_bounds__(kThreads) void quantize_kernel(
             }
             if (bp != 0x7FFFFFFF && bv > best_v) {
                 best_v = bv;
-                best_i = (int)(s.pay[bp] & 0xFFFu);
+                const unsigned bpay = s.key ? s.pay[bp] : (unsigned)s.pay16[bp];
+                best_i = (int)(bpay & 0xFFFu);
                 // the key of the best event, as the sort would have stored it
-                best_d = s.key ? s.key[bp] : (double)fabsf(r[best_i]) / (double)(s.pay[bp] >> 12);
+                best_d = s.key ? s.key[bp] : (double)fabsf(r[best_i]) / (double)(bpay >> 12);
                 best_s2 = bs2;
             }
         }
