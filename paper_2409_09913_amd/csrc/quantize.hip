@@ -37,7 +37,7 @@ namespace erq {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kRedLL = 64;           // int64 reduction slots (block_sum3 uses 32..43)
+constexpr int kRedLL = 48;           // int64 reduction slots (block_sum3 uses 32..43)
 
 __device__ inline double wave_sum_d(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -134,7 +134,11 @@ __host__ __device__ inline size_t smem_bytes(int SA, int dp, int cap, int bb, in
 
 }  // namespace
 
-__global__ __launch_bounds__(kThreads) void quantize_kernel(
+// KEYED (B >= 5): windows are sorted, and may be pruned (bb); else (B <= 4)
+// events are placed by rank with 16-bit payloads.  Each instantiation keeps
+// only its own path, so the rank one fits six blocks per CU.
+template <bool KEYED>
+__global__ __launch_bounds__(kThreads, KEYED ? 5 : 6) void quantize_kernel(
     const float* __restrict__ rrot, int64_t n_vec, int dp, int bits, int SA, int cap,
     const float* __restrict__ norm2, uint8_t* __restrict__ codes, float* __restrict__ f_add,
     float* __restrict__ f_rescale, float* __restrict__ cos_oo, float2* __restrict__ fac, int bb)
@@ -145,7 +149,8 @@ __global__ __launch_bounds__(kThreads) void quantize_kernel(
     const int lane = tid & 63, wid = tid >> 6;
     const int64_t row = blockIdx.x;
     if (row >= n_vec) return;
-    Smem s = carve(smem_raw, SA, dp, cap, bb, bits >= 5);
+    bb = KEYED ? bb : 0;
+    Smem s = carve(smem_raw, SA, dp, cap, bb, KEYED);
     const float* r = rrot + row * (int64_t)dp;
     const int K = (1 << (bits - 1)) - 1;
     const int half = 1 << (bits - 1);
@@ -369,7 +374,7 @@ __global__ __launch_bounds__(kThreads) void quantize_kernel(
         }
         int S = 1;
         while (S < W) S <<= 1;
-        if (K <= 7) {
+        if (!KEYED) {
             // few levels (B <= 4): ranks, no sort stages
             // every event of the window goes straight to its rank by (d desc, dim
             // asc): its rank in its own level's run (sorted by a descending, dim
@@ -439,7 +444,7 @@ __global__ __launch_bounds__(kThreads) void quantize_kernel(
         const int beg = tid * L, end = min(W, beg + L);
         long long ls1 = 0, ls2 = 0;
         for (int t = beg; t < end; ++t) {
-            unsigned pp = s.key ? s.pay[t] : (unsigned)s.pay16[t];
+            unsigned pp = KEYED ? s.pay[t] : (unsigned)s.pay16[t];
             ls1 += 2 * s.afx[pp & 0xFFFu];
             ls2 += 8 * (long long)(pp >> 12);
         }
@@ -459,7 +464,7 @@ __global__ __launch_bounds__(kThreads) void quantize_kernel(
         long long c2 = s2base + w2 + i2 - ls2;
         double tb = 0.0; int tpos = -1; long long ts2 = 0;
         for (int t = beg; t < end; ++t) {
-            unsigned pp = s.key ? s.pay[t] : (unsigned)s.pay16[t];
+            unsigned pp = KEYED ? s.pay[t] : (unsigned)s.pay16[t];
             c1 += 2 * s.afx[pp & 0xFFFu];
             c2 += 8 * (long long)(pp >> 12);
             double v = (double)c1 / sqrt((double)c2);
@@ -486,10 +491,10 @@ __global__ __launch_bounds__(kThreads) void quantize_kernel(
             }
             if (bp != 0x7FFFFFFF && bv > best_v) {
                 best_v = bv;
-                const unsigned bpay = s.key ? s.pay[bp] : (unsigned)s.pay16[bp];
+                const unsigned bpay = KEYED ? s.pay[bp] : (unsigned)s.pay16[bp];
                 best_i = (int)(bpay & 0xFFFu);
                 // the key of the best event, as the sort would have stored it
-                best_d = s.key ? s.key[bp] : (double)fabsf(r[best_i]) / (double)(bpay >> 12);
+                best_d = KEYED ? s.key[bp] : (double)fabsf(r[best_i]) / (double)(bpay >> 12);
                 best_s2 = bs2;
             }
         }
@@ -573,13 +578,17 @@ hipError_t launch_quantize(const float* rrot, int64_t n, int dp, int bits, const
         if (call > cap && smem_bytes(SA, dp, call, 0, 0) <= 53 * 1024) cap = call;
     }
     size_t sm = smem_bytes(SA, dp, cap, bb, keyed);
+    const void* fn = keyed ? (const void*)quantize_kernel<true> : (const void*)quantize_kernel<false>;
     if (sm > 48 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void*)quantize_kernel,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(quantize_kernel, dim3((unsigned)n), dim3(kThreads), sm, st,
-                       rrot, n, dp, bits, SA, cap, norm2, codes, f_add, f_rescale, cos_oo, fac, bb);
+    if (keyed)
+        hipLaunchKernelGGL(quantize_kernel<true>, dim3((unsigned)n), dim3(kThreads), sm, st,
+                           rrot, n, dp, bits, SA, cap, norm2, codes, f_add, f_rescale, cos_oo, fac, bb);
+    else
+        hipLaunchKernelGGL(quantize_kernel<false>, dim3((unsigned)n), dim3(kThreads), sm, st,
+                           rrot, n, dp, bits, SA, cap, norm2, codes, f_add, f_rescale, cos_oo, fac, bb);
     return hipGetLastError();
 }
 
