@@ -52,9 +52,17 @@ __device__ inline float wave_max_f(float v) {
     return v;
 }
 
-// events before x in key order: d = a/m with the larger d first.
-__device__ inline bool key_before(double d1, int i1, double d2, int i2) {
-    return d1 > d2 || (d1 == d2 && i1 < i2);
+// event p0 = (level m0, dim d0) before p1 in key order (d = a/m descending,
+// dim ascending): a0/m0 > a1/m1 decided as a0*m1 > a1*m0, exact in double
+// (24-bit magnitudes times levels below 2^7); distinct ratios give distinct
+// keys in the same order, so this is the order of the rounded keys.
+// 0xFFFFFFFF is padding, after every event.
+__device__ inline bool ev_before(const float* adim, unsigned p0, unsigned p1) {
+    if (p1 == 0xFFFFFFFFu) return p0 != 0xFFFFFFFFu;
+    if (p0 == 0xFFFFFFFFu) return false;
+    const unsigned d0 = p0 & 0xFFFu, d1 = p1 & 0xFFFu;
+    const double x0 = (double)adim[d0] * (double)(p1 >> 12), x1 = (double)adim[d1] * (double)(p0 >> 12);
+    return x0 > x1 || (x0 == x1 && d0 < d1);
 }
 
 // number of j in [0, n) with fl(A[j]/m) >= x  (A sorted descending)
@@ -95,18 +103,19 @@ __device__ inline void block_sum3(long long* red, long long& a, long long& b, lo
 }
 
 struct Smem {
-    float* A; int* I; long long* afx; long long* ps; double* key; unsigned* pay;
+    float* A; int* I; long long* afx; long long* ps; float* adim; unsigned* pay;
     unsigned short* pay16;     // the same payloads in 16 bits when not keyed (level <= 7, dim < 4096)
     int* cprev; int* cnext; int* loff;
     long long* red_ll; double* red_d; float* red_f; int* misc;
 };
 
-// The window's keys are stored only for the sort (B >= 5, keyed = 1); ranks
-// (B <= 4) need only the (level, dimension) payload.
+// A window holds (level, dimension) payloads only: 32-bit for the sort
+// (B >= 5, keyed = 1), which compares events through the magnitudes by
+// dimension (adim), 16-bit for ranks (B <= 4).
 __device__ inline Smem carve(char* base, int SA, int dp, int cap, int bb, int keyed) {
     Smem s;
     size_t o = 0;
-    s.key = keyed ? (double*)(base + o) : nullptr; o += keyed ? sizeof(double) * cap : 0;
+    s.adim = keyed ? (float*)(base + o) : nullptr; o += keyed ? sizeof(float) * dp : 0;
     s.afx = (long long*)(base + o); o += sizeof(long long) * dp;
     s.ps = (long long*)(base + o); o += bb ? sizeof(long long) * (SA + 1) : 0;
     s.red_ll = (long long*)(base + o); o += sizeof(long long) * kRedLL;
@@ -125,7 +134,7 @@ __device__ inline Smem carve(char* base, int SA, int dp, int cap, int bb, int ke
 }
 
 __host__ __device__ inline size_t smem_bytes(int SA, int dp, int cap, int bb, int keyed) {
-    return (keyed ? sizeof(double) * cap : 0) + sizeof(long long) * dp + (bb ? sizeof(long long) * (SA + 1) : 0) +
+    return (keyed ? sizeof(float) * dp : 0) + sizeof(long long) * dp + (bb ? sizeof(long long) * (SA + 1) : 0) +
            sizeof(long long) * kRedLL +
            sizeof(double) * 8 + sizeof(float) * SA + sizeof(int) * SA +
            (keyed ? sizeof(unsigned) : sizeof(unsigned short)) * cap +
@@ -160,6 +169,7 @@ __global__ __launch_bounds__(kThreads, KEYED ? 5 : 6) void quantize_kernel(
     for (int i = tid; i < SA; i += kThreads) {
         float a = (i < dp) ? fabsf(r[i]) : -1.0f;
         s.A[i] = a; s.I[i] = i;
+        if (KEYED && i < dp) s.adim[i] = a;
         lmax = fmaxf(lmax, a);
     }
     lmax = wave_max_f(lmax);
@@ -415,11 +425,9 @@ __global__ __launch_bounds__(kThreads, KEYED ? 5 : 6) void quantize_kernel(
                     while (hi - lo > 1) { int mid = (lo + hi) >> 1; if (s.loff[mid] <= t) lo = mid; else hi = mid; }
                     int m = lo + 1;
                     int j = s.cprev[lo] + (t - s.loff[lo]);
-                    s.key[t] = (double)s.A[j] / (double)m;
                     s.pay[t] = ((unsigned)m << 12) | (unsigned)s.I[j];
                 } else {
-                    s.key[t] = -1.0;
-                    s.pay[t] = 0xFFFFFu;
+                    s.pay[t] = 0xFFFFFFFFu;
                 }
             }
             // bitonic sort of the window by (d desc, dim asc)
@@ -430,10 +438,9 @@ __global__ __launch_bounds__(kThreads, KEYED ? 5 : 6) void quantize_kernel(
                         int i = 2 * t - (t & (j - 1));
                         int p = i + j;
                         bool up = ((i & k) == 0);
-                        double k0 = s.key[i], k1 = s.key[p];
                         unsigned p0 = s.pay[i], p1 = s.pay[p];
-                        bool first0 = key_before(k0, (int)(p0 & 0xFFFu), k1, (int)(p1 & 0xFFFu));
-                        if (first0 != up) { s.key[i] = k1; s.key[p] = k0; s.pay[i] = p1; s.pay[p] = p0; }
+                        bool first0 = ev_before(s.adim, p0, p1);
+                        if (first0 != up) { s.pay[i] = p1; s.pay[p] = p0; }
                     }
                 }
             }
@@ -494,7 +501,7 @@ __global__ __launch_bounds__(kThreads, KEYED ? 5 : 6) void quantize_kernel(
                 const unsigned bpay = KEYED ? s.pay[bp] : (unsigned)s.pay16[bp];
                 best_i = (int)(bpay & 0xFFFu);
                 // the key of the best event, as the sort would have stored it
-                best_d = KEYED ? s.key[bp] : (double)fabsf(r[best_i]) / (double)(bpay >> 12);
+                best_d = (double)(KEYED ? s.adim[best_i] : fabsf(r[best_i])) / (double)(bpay >> 12);
                 best_s2 = bs2;
             }
         }
