@@ -77,7 +77,7 @@ __device__ inline int count_ge(const float* A, int n, int m, double x) {
 }
 
 // number of j with (fl(A[j]/m), I[j]) at or before (d, i) in key order
-__device__ inline int count_upto(const float* A, const int* I, int n, int m, double d, int i) {
+__device__ inline int count_upto(const float* A, const unsigned short* I, int n, int m, double d, int i) {
     int lo = 0, hi = n;
     const double dm = (double)m;
     while (lo < hi) {
@@ -103,7 +103,7 @@ __device__ inline void block_sum3(long long* red, long long& a, long long& b, lo
 }
 
 struct Smem {
-    float* A; int* I; long long* afx; long long* ps; float* adim; unsigned* pay;
+    float* A; unsigned short* I; long long* afx; long long* ps; float* adim; unsigned* pay;   // I: dims < 4096
     unsigned short* pay16;     // the same payloads in 16 bits when not keyed (level <= 7, dim < 4096)
     int* cprev; int* cnext; int* loff;
     long long* red_ll; double* red_d; float* red_f; int* misc;
@@ -117,11 +117,11 @@ __device__ inline Smem carve(char* base, int SA, int dp, int cap, int bb, int ke
     size_t o = 0;
     s.adim = keyed ? (float*)(base + o) : nullptr; o += keyed ? sizeof(float) * dp : 0;
     s.afx = (long long*)(base + o); o += sizeof(long long) * dp;
-    s.ps = (long long*)(base + o); o += bb ? sizeof(long long) * (SA + 1) : 0;
+    s.ps = (long long*)(base + o); o += bb ? sizeof(long long) * (dp + 1) : 0;
     s.red_ll = (long long*)(base + o); o += sizeof(long long) * kRedLL;
     s.red_d = (double*)(base + o); o += sizeof(double) * 8;
     s.A = (float*)(base + o); o += sizeof(float) * SA;
-    s.I = (int*)(base + o); o += sizeof(int) * SA;
+    s.I = (unsigned short*)(base + o); o += sizeof(unsigned short) * SA;
     s.pay = (unsigned*)(base + o);
     s.pay16 = (unsigned short*)(base + o);
     o += (keyed ? sizeof(unsigned) : sizeof(unsigned short)) * cap;
@@ -134,9 +134,9 @@ __device__ inline Smem carve(char* base, int SA, int dp, int cap, int bb, int ke
 }
 
 __host__ __device__ inline size_t smem_bytes(int SA, int dp, int cap, int bb, int keyed) {
-    return (keyed ? sizeof(float) * dp : 0) + sizeof(long long) * dp + (bb ? sizeof(long long) * (SA + 1) : 0) +
+    return (keyed ? sizeof(float) * dp : 0) + sizeof(long long) * dp + (bb ? sizeof(long long) * (dp + 1) : 0) +
            sizeof(long long) * kRedLL +
-           sizeof(double) * 8 + sizeof(float) * SA + sizeof(int) * SA +
+           sizeof(double) * 8 + sizeof(float) * SA + sizeof(unsigned short) * SA +
            (keyed ? sizeof(unsigned) : sizeof(unsigned short)) * cap +
            sizeof(int) * (128 + 128 + 132) + sizeof(float) * 8 + sizeof(int) * 16;
 }
@@ -168,7 +168,7 @@ __global__ __launch_bounds__(kThreads, KEYED ? 5 : 6) void quantize_kernel(
     float lmax = 0.0f;
     for (int i = tid; i < SA; i += kThreads) {
         float a = (i < dp) ? fabsf(r[i]) : -1.0f;
-        s.A[i] = a; s.I[i] = i;
+        s.A[i] = a; s.I[i] = (unsigned short)i;
         if (KEYED && i < dp) s.adim[i] = a;
         lmax = fmaxf(lmax, a);
     }
@@ -203,7 +203,7 @@ __global__ __launch_bounds__(kThreads, KEYED ? 5 : 6) void quantize_kernel(
                 int i0 = s.I[i], i1 = s.I[p];
                 bool first0 = (a0 > a1) || (a0 == a1 && i0 < i1);   // element i before p
                 if (first0 != up) {
-                    s.A[i] = a1; s.A[p] = a0; s.I[i] = i1; s.I[p] = i0;
+                    s.A[i] = a1; s.A[p] = a0; s.I[i] = (unsigned short)i1; s.I[p] = (unsigned short)i0;
                 }
             }
         }
@@ -238,10 +238,10 @@ __global__ __launch_bounds__(kThreads, KEYED ? 5 : 6) void quantize_kernel(
         for (int w = 0; w < wid; ++w) run += s.red_ll[24 + w];
         for (int t = 0; t < L; ++t) {
             const int j = b0 + t;
-            if (j < SA) s.ps[j] = run;
+            if (j <= dp) s.ps[j] = run;
             if (j < nnz) run += s.afx[s.I[j]];
         }
-        if (tid == kThreads - 1) s.ps[SA] = run;     // the last thread's run is the total
+        if (tid == kThreads - 1 && SA == dp) s.ps[dp] = run;     // the total (else written at j = dp)
         __syncthreads();
     }
     // ---- seed: the best of a few grid points k_i = min(K, floor(t a_i)) ------
