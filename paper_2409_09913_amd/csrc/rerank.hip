@@ -20,22 +20,39 @@ __global__ __launch_bounds__(256) void rerank_kernel(const float* __restrict__ r
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int64_t iq = blockIdx.x;
     const float* qv = q + iq * (int64_t)dp;
-    for (int c = wid; c < kc; c += 4) {
-        const long long id = cand[iq * kc + c];
-        float s = 0.0f;
-        if (id >= 0) {
-            const float* xv = raw + id * (int64_t)dp;
-            for (int i = lane * 4; i < dp; i += 256) {
-                float4 a = *(const float4*)(xv + i);
-                float4 b = *(const float4*)(qv + i);
-                float d0 = a.x - b.x, d1 = a.y - b.y, d2 = a.z - b.z, d3 = a.w - b.w;
-                s += d0 * d0 + d1 * d1 + d2 * d2 + d3 * d3;
-            }
-            for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    // wave wid takes candidates wid, wid + 4, ... in batches of CB, whose row
+    // loads are issued together; each distance is summed in the same order
+    // as one candidate at a time
+    constexpr int CB = 8;
+    for (int c0 = wid; c0 < kc; c0 += 4 * CB) {
+        long long id[CB];
+        float s[CB];
+#pragma unroll
+        for (int b = 0; b < CB; ++b) {
+            const int c = c0 + 4 * b;
+            id[b] = (c < kc) ? cand[iq * kc + c] : -1;
+            s[b] = 0.0f;
         }
-        if (lane == 0) {
-            sd[c] = (id >= 0) ? s : __builtin_huge_valf();
-            si[c] = (id >= 0) ? id : 0x7FFFFFFFFFFFFFFFLL;
+        for (int i = lane * 4; i < dp; i += 256) {
+            const float4 qq = *(const float4*)(qv + i);
+            float4 a[CB];
+#pragma unroll
+            for (int b = 0; b < CB; ++b)
+                a[b] = (id[b] >= 0) ? *(const float4*)(raw + id[b] * (int64_t)dp + i) : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+            for (int b = 0; b < CB; ++b) {
+                const float d0 = a[b].x - qq.x, d1 = a[b].y - qq.y, d2 = a[b].z - qq.z, d3 = a[b].w - qq.w;
+                s[b] += d0 * d0 + d1 * d1 + d2 * d2 + d3 * d3;
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < CB; ++b) {
+            for (int o = 32; o > 0; o >>= 1) s[b] += __shfl_xor(s[b], o);
+            const int c = c0 + 4 * b;
+            if (lane == 0 && c < kc) {
+                sd[c] = (id[b] >= 0) ? s[b] : __builtin_huge_valf();
+                si[c] = (id[b] >= 0) ? id[b] : 0x7FFFFFFFFFFFFFFFLL;
+            }
         }
     }
     int S = 1;
