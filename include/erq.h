@@ -118,7 +118,9 @@ int erq_index_import(erq_index idx, int64_t n, const int64_t* list_off, const in
    x: n x dp raw vectors (row i has id i); centroids: nlist x dp; assign: n
    list ids, or NULL to assign every row to its nearest centroid.  Per row:
    r = x - c, ||r||^2, r' = P^T r (precision as in erq_rotate), Algorithm 1,
-   factors, packing.  keep_raw != 0 keeps a copy of x for erq_rerank.
+   factors, packing.  Members are stored list by list, ids ascending
+   within each list, so the same input always gives the same index.
+   keep_raw != 0 keeps a copy of x for erq_rerank.
    Synchronises `stream` before returning. */
 int erq_index_build(erq_index idx, const float* x, int64_t n, const float* centroids,
                     const int32_t* assign, int32_t precision, int32_t keep_raw, void* stream);
