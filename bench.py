@@ -8,7 +8,7 @@ k-means lists; B = 4 codes (B = 8 reported beside it); k = 10.
 
 A step is one search of the whole query batch through the C ABI
 (erq_search: rotation, coarse probe, pair build, int8 matrix-core scan with
-estimator and top-k, merge, exact re-rank), with the index and the queries
+estimator and top-k, exact re-rank), with the index and the queries
 resident in HBM.  The operating point (nprobe, re-rank depth) is the fastest
 one whose recall@10 against exact FP32 brute force is >= 0.95.  Encode
 throughput is the time of erq_index_build (residuals, rotation, Algorithm 1,
@@ -241,7 +241,7 @@ def main():
     dt = time.perf_counter() - ts
     scan_ms, scan_n = erq.profile_read("scan")
     tot, raw = {}, {}
-    for kname in ("rotate", "probe", "scan", "scan_a", "scan_b", "scan_c", "merge", "rerank"):
+    for kname in ("rotate", "probe", "scan", "scan_a", "scan_b", "scan_c", "rerank"):
         ms, nl = erq.profile_read(kname)
         tot[kname] = ms / max(nl, 1)
         raw[kname] = (ms, nl)

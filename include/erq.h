@@ -50,7 +50,13 @@ int erq_version(void);
 /* Rotation (Sec. 3.2.1, Sec. 3.4): out = x * P, i.e. every row r of x is    */
 /* replaced by P^T r = P^{-1} r for the random orthogonal P.                 */
 /* x: n x dp, P: dp x dp, out: n x dp (FP32).  precision 0 = FP32 matrix     */
-/* cores, 1 = BF16 inputs with FP32 accumulation.  out must not alias x.     */
+/* cores; 1 = BF16 inputs with FP32 accumulation; 2 = the rotation of       */
+/* erq_search: both operands split into BF16 hi/lo planes (x = hi + lo to   */
+/* 2^-17 relative), three products per K chunk (lo*hi, hi*lo, hi*hi) with   */
+/* FP32 accumulation, error <= 2^-14 sum_k |x_k P_kj| plus the FP32          */
+/* accumulation bound; bit-identical to the rotation inside erq_search.    */
+/* Precision 2 allocates its scratch planes and synchronises `stream`.     */
+/* out must not alias x.                                                     */
 /* ------------------------------------------------------------------------ */
 int erq_rotate(const float* x, int64_t n, int32_t dp, const float* P,
                int32_t precision, float* out, void* stream);
@@ -107,9 +113,12 @@ int erq_index_destroy(erq_index idx);
 
 /* Fills the index from caller-made contents (no quantisation on the device):
    list_off: nlist+1 int64 offsets into the list-ordered arrays; ids: n int64
-   row ids; codes: n x dp uint8 y_u in list order; f_add, f_rescale: n FP32;
-   centroids, centroids_rot: nlist x dp FP32 (centroids_rot = P^T c; NULL ->
-   computed with erq_rotate in FP32).  Replaces previous contents. */
+   row ids, each in [0, n) (row numbers of the vectors given to
+   erq_index_set_raw; ERQ_EINVAL otherwise, checked on the device before the
+   call returns); codes: n x dp uint8 y_u in list order; f_add, f_rescale: n
+   FP32; centroids, centroids_rot: nlist x dp FP32 (centroids_rot = P^T c;
+   NULL -> computed with erq_rotate in FP32).  Replaces previous contents.
+   Synchronises `stream`. */
 int erq_index_import(erq_index idx, int64_t n, const int64_t* list_off, const int64_t* ids,
                      const uint8_t* codes, const float* f_add, const float* f_rescale,
                      const float* centroids, const float* centroids_rot, void* stream);
@@ -152,7 +161,7 @@ int erq_index_export(erq_index idx, int64_t* list_off, int64_t* ids, uint8_t* co
 /* per member in the index (FP64 accumulate), ||s'||^2 per pair in FP32,     */
 /* the rest in FP32.                                                         */
 /* Output: out_ids, out_est nq x kk ascending by (est, id); missing entries  */
-/* are (-1, +inf).  kk in [1, 32].  workspace: erq_scan_workspace_size.      */
+/* are (-1, +inf).  kk in [1, 1024].  workspace: erq_scan_workspace_size.    */
 /* ------------------------------------------------------------------------ */
 int erq_scan_workspace_size(erq_index idx, int64_t nq, int32_t nprobe, int32_t kk, size_t* bytes);
 int erq_scan(erq_index idx, const float* qrot, int64_t nq, const int32_t* probes,
@@ -161,26 +170,36 @@ int erq_scan(erq_index idx, const float* qrot, int64_t nq, const int32_t* probes
 
 /* ------------------------------------------------------------------------ */
 /* Exact re-rank: squared Euclidean distance (FP32) between each raw query   */
-/* and its kc candidate rows (ids < 0 skipped), the k smallest ascending by  */
-/* (distance, id).  Needs raw vectors in the index.  q: nq x dp, cand: nq x  */
-/* kc int64; out: nq x k (-1, +inf padded).  kc in [1, 256], k <= kc.        */
+/* and its kc candidate rows (ids outside [0, n) are skipped), the k         */
+/* smallest ascending by (distance, id).  Needs raw vectors in the index.    */
+/* q: nq x dp, cand: nq x kc int64; out: nq x k (-1, +inf padded).  kc in    */
+/* [1, 1024], k <= kc.                                                       */
 /* ------------------------------------------------------------------------ */
 int erq_rerank(erq_index idx, const float* q, int64_t nq, const int64_t* cand, int32_t kc,
                int32_t k, int64_t* out_ids, float* out_dist, void* stream);
 
 /* ------------------------------------------------------------------------ */
-/* Whole query path: rotate, coarse probe, scan, and (rerank_k > 0) exact    */
-/* re-rank of the rerank_k best estimates.  The rotation q' = q P uses the   */
-/* probe's BF16 hi/lo products (error <= 2^-14 sum_k |q_k P_kj| per output,  */
-/* about the FP32 accumulation bound at dp = 768); erq_rotate keeps the FP32 */
-/* and BF16 modes.  Output nq x k: estimated squared distances without       */
-/* re-rank, exact ones with it.  k <= 32, rerank_k <= 32.                    */
-/* workspace: erq_search_workspace_size.                                     */
+/* Whole query path (Sec. 2.1 K-NN, Sec. 4.1 IVF): rotate, coarse probe,     */
+/* scan, and exact re-rank of the best estimates.  The rotation q' = q P is  */
+/* erq_rotate's precision 2 (error <= 2^-14 sum_k |q_k P_kj| per output,     */
+/* about the FP32 accumulation bound at dp = 768).  The scan's ||s||^2 per   */
+/* pair is the probe's ||q||^2 + ||c||^2 - 2 q.c, clamped at 0.              */
+/* nprobe, k, rerank_k are the batch's largest values: nprobe in            */
+/* [1, min(nlist, 1024)], k in [1, 1024], rerank_k 0 or in [k, 1024]        */
+/* (re-rank needs raw vectors).  Per-query values (device int32 arrays of nq, */
+/* each may be NULL = the batch value for every query): nprobe_q clamped to */
+/* [1, nprobe]; k_q clamped to [1, k]; rerank_q 0 (estimates) or clamped to */
+/* [k_q, rerank_k] (0 for all when rerank_k is 0).  A query's result does   */
+/* not depend on the other queries of the batch.  Output nq x k ascending by */
+/* (distance, id): estimated squared distances for a query without re-rank, */
+/* exact FP32 ones with it; columns past the query's k_q are (-1, +inf).     */
+/* workspace: erq_search_workspace_size(nq, nprobe, k, rerank_k).           */
 /* ------------------------------------------------------------------------ */
 int erq_search_workspace_size(erq_index idx, int64_t nq, int32_t nprobe, int32_t k,
                               int32_t rerank_k, size_t* bytes);
 int erq_search(erq_index idx, const float* q, int64_t nq, int32_t nprobe, int32_t k,
-               int32_t rerank_k, int64_t* out_ids, float* out_dist,
+               int32_t rerank_k, const int32_t* nprobe_q, const int32_t* k_q,
+               const int32_t* rerank_q, int64_t* out_ids, float* out_dist,
                void* workspace, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------ */
@@ -200,7 +219,8 @@ int erq_search(erq_index idx, const float* q, int64_t nq, int32_t nprobe, int32_
 /* under every schedule.  set_tune rejects invalid values (ERQ_EINVAL) and   */
 /* leaves the schedule unchanged; get_tune writes the four stored values.   */
 /* erq_index_tune searches the schedule on the caller's queries and         */
-/* erq_search arguments (outputs and workspace as for erq_search; they hold */
+/* erq_search arguments, every query with the batch values (outputs and     */
+/* workspace as for erq_search; they hold                                   */
 /* the last call's result on return): first (nqt, pd) over every valid pair */
 /* with round1 and round2 fixed, then round1 in {2, 4, 8, 16, 32}          */
 /* (< nprobe), then round2 in {0, 2, 4, 8, 16} x round1 (< nprobe); each     */
@@ -223,7 +243,7 @@ int erq_index_tune(erq_index idx, const float* q, int64_t nq, int32_t nprobe, in
 /* recorded on the stream it is launched on.  Names: "scan" (the int8 matrix- */
 /* core scan, all passes), "scan_a" (its first bound), "scan_b" (each launch */
 /* of the bounded scan), "scan_c" (final selection and exact fallback),     */
-/* "quantize", "rotate", "probe", "merge", "rerank".  "scan_redo_pairs"      */
+/* "quantize", "rotate", "probe", "rerank".  "scan_redo_pairs"              */
 /* returns in total_ms the number of pairs re-scanned by the exact fallback;*/
 /* it is counted only with on == 2, which synchronises after each scan.     */
 /* erq_profile_read waits for the recorded events and returns the summed     */

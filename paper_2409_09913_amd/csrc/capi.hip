@@ -40,7 +40,7 @@ std::mutex g_prof_mu;
 std::vector<ProfRec> g_prof;
 bool g_prof_on = false;
 bool g_prof_stats = false;     // also count pass-C pairs (synchronises after each scan)
-const char* const kProfNames[PK_COUNT] = {"scan", "quantize", "rotate", "probe", "merge", "rerank",
+const char* const kProfNames[PK_COUNT] = {"scan", "quantize", "rotate", "probe", "rerank",
                                           "scan_a", "scan_b", "scan_c"};
 int64_t g_redo_total = 0, g_redo_calls = 0;
 }  // namespace
@@ -98,6 +98,10 @@ __global__ void split_fac_kernel(const float2* f, int64_t n, float* a, float* b)
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) { if (a) a[i] = f[i].x; if (b) b[i] = f[i].y; }
 }
+__global__ void check_ids_kernel(const int64_t* ids, int64_t n, int32_t* bad) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && (ids[i] < 0 || ids[i] >= n)) atomicOr(bad, 1);
+}
 __global__ void fill_i32(int32_t* p, int64_t n, int32_t v) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -114,12 +118,33 @@ __global__ void gather_topk_kernel(const int32_t* idx, int64_t n, int k, int32_t
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) out[i] = idx[i * k];
 }
+// first kout columns of (ids, est); with k_q, columns past the query's own k are (-1, +inf)
 __global__ void copy_cols_kernel(const int64_t* ids, const float* est, int64_t nq, int kin, int kout,
-                                 int64_t* oi, float* oe) {
+                                 const int32_t* k_q, int64_t* oi, float* oe) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nq * kout) return;
     int64_t q = i / kout; int t = (int)(i % kout);
-    oi[i] = ids[q * kin + t]; oe[i] = est[q * kin + t];
+    const bool in = !k_q || t < k_q[q];
+    oi[i] = in ? ids[q * kin + t] : -1;
+    oe[i] = in ? est[q * kin + t] : __builtin_huge_valf();
+}
+
+// Per-query search parameters clamped to the batch maxima: nprobe in
+// [1, nprobe], k in [1, kmax], re-rank depth 0 or in [k, rrmax] (rrmax 0: no
+// re-rank); null arrays give the maxima.  Probe ranks past a query's own
+// nprobe become -1, which every later step skips.
+__global__ void query_params_kernel(int64_t nq, int nprobe, int kmax, int rrmax, const int32_t* np_in,
+                                    const int32_t* k_in, const int32_t* rr_in, int32_t* k_out, int32_t* rr_out,
+                                    int32_t* probes) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nq) return;
+    const int np = np_in ? min(max(np_in[i], 1), nprobe) : nprobe;
+    const int k = k_in ? min(max(k_in[i], 1), kmax) : kmax;
+    int rr = rr_in ? rr_in[i] : rrmax;
+    rr = (rr <= 0 || rrmax == 0) ? 0 : min(max(rr, k), rrmax);
+    k_out[i] = k;
+    rr_out[i] = rr;
+    for (int p = np; p < nprobe; ++p) probes[i * nprobe + p] = -1;
 }
 
 inline unsigned blocks(int64_t n, int th = 256) { return (unsigned)((n + th - 1) / th); }
@@ -223,17 +248,36 @@ struct erq_index_s : public Index {};
 extern "C" {
 
 const char* erq_last_error(void) { return g_err.c_str(); }
-int erq_version(void) { return 100; }
+int erq_version(void) { return 200; }
 
 int erq_rotate(const float* x, int64_t n, int32_t dp, const float* P, int32_t precision, float* out, void* stream)
 {
     if (int rc = check_dp(dp, "erq_rotate")) return rc;
     if (n < 0 || (n > 0 && (!x || !P || !out))) return fail(ERQ_EINVAL, "erq_rotate: null pointer or n < 0");
-    if (precision != 0 && precision != 1) return fail(ERQ_EUNSUPPORTED, "erq_rotate: precision must be 0 or 1");
+    if (precision < 0 || precision > 2) return fail(ERQ_EUNSUPPORTED, "erq_rotate: precision must be 0, 1 or 2");
     if (x == out) return fail(ERQ_EINVAL, "erq_rotate: out must not alias x");
-    int pr = prof_begin(PK_ROTATE, (hipStream_t)stream);
-    ERQ_HIP(launch_gemm(x, n, dp, P, dp, 0, precision, out, dp, (hipStream_t)stream));
-    prof_end(pr, (hipStream_t)stream);
+    hipStream_t st = (hipStream_t)stream;
+    if (precision == 2) {
+        // the search's rotation: BF16 hi/lo planes of x and of P^T, three products per K chunk
+        if (n == 0) return ERQ_OK;
+        struct Tmp { void* p[4] = {nullptr, nullptr, nullptr, nullptr}; ~Tmp() { for (void* q : p) hipFree(q); } } t;
+        ERQ_HIP(hipMalloc(&t.p[0], sizeof(unsigned short) * n * dp));
+        ERQ_HIP(hipMalloc(&t.p[1], sizeof(unsigned short) * n * dp));
+        ERQ_HIP(hipMalloc(&t.p[2], sizeof(unsigned short) * dp * dp));
+        ERQ_HIP(hipMalloc(&t.p[3], sizeof(unsigned short) * dp * dp));
+        auto* xh = (unsigned short*)t.p[0]; auto* xl = (unsigned short*)t.p[1];
+        auto* ph = (unsigned short*)t.p[2]; auto* pl = (unsigned short*)t.p[3];
+        int pr = prof_begin(PK_ROTATE, st);
+        ERQ_HIP(launch_split_bf16(x, n * dp, xh, xl, st));
+        ERQ_HIP(launch_split_bf16_t(P, dp, dp, ph, pl, st));
+        ERQ_HIP(launch_gemm_bf16x3(xh, xl, n, ph, pl, dp, dp, out, dp, st));
+        prof_end(pr, st);
+        ERQ_HIP(hipStreamSynchronize(st));          // before the scratch planes are freed
+        return ERQ_OK;
+    }
+    int pr = prof_begin(PK_ROTATE, st);
+    ERQ_HIP(launch_gemm(x, n, dp, P, dp, 0, precision, out, dp, st));
+    prof_end(pr, st);
     return ERQ_OK;
 }
 
@@ -336,6 +380,20 @@ int erq_index_import(erq_index ix, int64_t n, const int64_t* list_off, const int
     else
         ERQ_HIP(launch_gemm(ix->cent, C, dp, ix->P, dp, 0, 0, ix->cent_rot, dp, st));
     if (n > 0) {
+        // ids are row numbers: in [0, n) (the scan keeps them as int32, the re-rank indexes raw rows by them)
+        int32_t* bad = nullptr;
+        ERQ_HIP(hipMalloc(&bad, sizeof(int32_t)));
+        int32_t hbad = 0;
+        hipLaunchKernelGGL(fill_i32, dim3(1), dim3(64), 0, st, bad, 1, 0);
+        hipLaunchKernelGGL(check_ids_kernel, dim3(blocks(n)), dim3(256), 0, st, ids, n, bad);
+        hipError_t ce = hipMemcpyAsync(&hbad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+        if (ce == hipSuccess) ce = hipStreamSynchronize(st);
+        hipFree(bad);
+        ERQ_HIP(ce);
+        if (hbad) {
+            free_index_storage(ix);
+            return fail(ERQ_EINVAL, "erq_index_import: ids must lie in [0, n)");
+        }
         ERQ_HIP(hipMemcpyAsync(ix->ids, ids, sizeof(int64_t) * n, hipMemcpyDeviceToDevice, st));
         hipLaunchKernelGGL(interleave_fac_kernel, dim3(blocks(n)), dim3(256), 0, st, f_add, f_rescale, n, ix->fac);
         ERQ_HIP(hipGetLastError());
@@ -514,7 +572,7 @@ int erq_scan(erq_index ix, const float* qrot, int64_t nq, const int32_t* probes,
     if (!ix || !ix->codes) return fail(ERQ_EINVAL, "erq_scan: index is empty");
     if (nq < 0 || nq * (int64_t)std::max(nprobe, 1) > (1LL << 31) - 1) return fail(ERQ_EINVAL, "erq_scan: nq out of range");
     if (nprobe < 1 || nprobe > 1024) return fail(ERQ_EUNSUPPORTED, "erq_scan: nprobe must be in [1, 1024]");
-    if (kk < 1 || kk > 32) return fail(ERQ_EUNSUPPORTED, "erq_scan: kk must be in [1, 32]");
+    if (kk < 1 || kk > kMaxK) return fail(ERQ_EUNSUPPORTED, "erq_scan: kk must be in [1, 1024]");
     if (nq > 0 && (!qrot || !probes || !out_ids || !out_est || !workspace)) return fail(ERQ_EINVAL, "erq_scan: null pointer");
     if (ix->nlist > 1000000) return fail(ERQ_EUNSUPPORTED, "erq_scan: more than 10^6 lists");
     return run_scan(ix, qrot, nq, probes, nullptr, nprobe, kk, out_ids, out_est, workspace, ws_bytes,
@@ -525,10 +583,11 @@ int erq_rerank(erq_index ix, const float* q, int64_t nq, const int64_t* cand, in
                int64_t* out_ids, float* out_dist, void* stream)
 {
     if (!ix || !ix->raw) return fail(ERQ_EINVAL, "erq_rerank: the index holds no raw vectors");
-    if (kc < 1 || kc > 256 || k < 1 || k > kc) return fail(ERQ_EUNSUPPORTED, "erq_rerank: need 1 <= k <= kc <= 256");
+    if (kc < 1 || kc > kMaxK || k < 1 || k > kc) return fail(ERQ_EUNSUPPORTED, "erq_rerank: need 1 <= k <= kc <= 1024");
     if (nq < 0 || (nq > 0 && (!q || !cand || !out_ids || !out_dist))) return fail(ERQ_EINVAL, "erq_rerank: bad arguments");
     int pr = prof_begin(PK_RERANK, (hipStream_t)stream);
-    ERQ_HIP(launch_rerank(ix->raw, ix->dp, q, nq, cand, kc, k, out_ids, out_dist, (hipStream_t)stream));
+    ERQ_HIP(launch_rerank(ix->raw, ix->n, ix->dp, q, nq, cand, nullptr, kc, k, nullptr, nullptr, out_ids, out_dist,
+                          (hipStream_t)stream));
     prof_end(pr, (hipStream_t)stream);
     return ERQ_OK;
 }
@@ -543,6 +602,7 @@ static size_t search_ws(Index* ix, int64_t nq, int nprobe, int k, int rerank_k) 
     b += align256(sizeof(float) * nq * kk);               // candidate estimates
     b += 2 * align256(sizeof(unsigned short) * nq * ix->dp);   // BF16 hi/lo planes of the queries
     b += align256(sizeof(float) * nq);                          // ||q||^2
+    b += 2 * align256(sizeof(int32_t) * nq);                    // per-query k and re-rank depth
     b += std::max(probe_ws(nq, ix->nlist, ix->dp), scan_workspace_bytes(nq, nprobe, ix->nlist, kk, ix->dp, ix->max_list));
     return b;
 }
@@ -554,19 +614,29 @@ int erq_search_workspace_size(erq_index ix, int64_t nq, int32_t nprobe, int32_t 
     return ERQ_OK;
 }
 
-int erq_search(erq_index ix, const float* q, int64_t nq, int32_t nprobe, int32_t k, int32_t rerank_k,
-               int64_t* out_ids, float* out_dist, void* workspace, size_t ws_bytes, void* stream)
+// argument checks of erq_search (and of its no-allocation variant)
+static int search_check(Index* ix, const float* q, int64_t nq, int nprobe, int k, int rerank_k, int64_t* out_ids,
+                        float* out_dist, const char* who)
 {
-    if (!ix || !ix->codes) return fail(ERQ_EINVAL, "erq_search: index is empty");
-    if (k < 1 || k > 32) return fail(ERQ_EUNSUPPORTED, "erq_search: k must be in [1, 32]");
-    if (rerank_k < 0 || rerank_k > 32 || (rerank_k > 0 && rerank_k < k)) return fail(ERQ_EUNSUPPORTED, "erq_search: rerank_k must be 0 or in [k, 32]");
-    if (rerank_k > 0 && !ix->raw) return fail(ERQ_EINVAL, "erq_search: re-rank needs raw vectors in the index");
-    if (nprobe < 1 || nprobe > 1024 || nprobe > ix->nlist) return fail(ERQ_EUNSUPPORTED, "erq_search: nprobe must be in [1, min(nlist, 1024)]");
-    if (nq < 0 || nq * (int64_t)nprobe > (1LL << 31) - 1) return fail(ERQ_EINVAL, "erq_search: nq out of range");
-    if (nq == 0) return ERQ_OK;
-    if (!q || !out_ids || !out_dist || !workspace) return fail(ERQ_EINVAL, "erq_search: null pointer");
-    if (ws_bytes < search_ws(ix, nq, nprobe, k, rerank_k)) return fail(ERQ_ENOMEM, "erq_search: workspace too small");
-    hipStream_t st = (hipStream_t)stream;
+    const std::string w(who);
+    if (!ix || !ix->codes) return fail(ERQ_EINVAL, w + ": index is empty");
+    if (k < 1 || k > kMaxK) return fail(ERQ_EUNSUPPORTED, w + ": k must be in [1, 1024]");
+    if (rerank_k < 0 || rerank_k > kMaxK || (rerank_k > 0 && rerank_k < k))
+        return fail(ERQ_EUNSUPPORTED, w + ": rerank_k must be 0 or in [k, 1024]");
+    if (rerank_k > 0 && !ix->raw) return fail(ERQ_EINVAL, w + ": re-rank needs raw vectors in the index");
+    if (nprobe < 1 || nprobe > 1024 || nprobe > ix->nlist)
+        return fail(ERQ_EUNSUPPORTED, w + ": nprobe must be in [1, min(nlist, 1024)]");
+    if (nq < 0 || nq * (int64_t)nprobe > (1LL << 31) - 1) return fail(ERQ_EINVAL, w + ": nq out of range");
+    if (nq > 0 && (!q || !out_ids || !out_dist)) return fail(ERQ_EINVAL, w + ": null pointer");
+    return ERQ_OK;
+}
+
+// The query path on a checked call: rotate, probe, per-query parameters,
+// scan, re-rank or copy, all on `st` inside the workspace ws.
+static int search_run(Index* ix, const float* q, int64_t nq, int nprobe, int k, int rerank_k, const int32_t* nprobe_q,
+                      const int32_t* k_q, const int32_t* rerank_q, int64_t* out_ids, float* out_dist, void* workspace,
+                      size_t ws_bytes, hipStream_t st)
+{
     const int kk = rerank_k > 0 ? rerank_k : k;
     char* w = (char*)workspace;
     float* qrot = (float*)w; w += align256(sizeof(float) * nq * ix->dp);
@@ -577,6 +647,8 @@ int erq_search(erq_index ix, const float* q, int64_t nq, int32_t nprobe, int32_t
     unsigned short* qh = (unsigned short*)w; w += align256(sizeof(unsigned short) * nq * ix->dp);
     unsigned short* ql = (unsigned short*)w; w += align256(sizeof(unsigned short) * nq * ix->dp);
     float* qn = (float*)w; w += align256(sizeof(float) * nq);
+    int32_t* kq = (int32_t*)w; w += align256(sizeof(int32_t) * nq);
+    int32_t* rq = (int32_t*)w; w += align256(sizeof(int32_t) * nq);
     size_t rest = ws_bytes - (size_t)(w - (char*)workspace);
     // q' = q P on the BF16 matrix cores from hi/lo planes (the probe's
     // products and error bound); the planes serve the probe too
@@ -589,16 +661,36 @@ int erq_search(erq_index ix, const float* q, int64_t nq, int32_t nprobe, int32_t
     pre.qh = qh; pre.ql = ql; pre.qn = qn;
     pre.ch = ix->cent_hi; pre.cl = ix->cent_lo; pre.cn = ix->cent_n2;
     if (int rc = probe_impl(q, nq, ix->cent, ix->nlist, ix->dp, nprobe, probes, pdist, w, rest, st, pre)) return rc;
+    const bool per_query = nprobe_q || k_q || rerank_q;
+    if (per_query) {
+        hipLaunchKernelGGL(query_params_kernel, dim3(blocks(nq)), dim3(256), 0, st, nq, nprobe, k, rerank_k, nprobe_q,
+                           k_q, rerank_q, kq, rq, probes);
+        ERQ_HIP(hipGetLastError());
+    }
     if (int rc = run_scan(ix, qrot, nq, probes, pdist, nprobe, kk, cid, cest, w, rest, st)) return rc;
     if (rerank_k > 0) {
         int pr2 = prof_begin(PK_RERANK, st);
-        ERQ_HIP(launch_rerank(ix->raw, ix->dp, q, nq, cid, kk, k, out_ids, out_dist, st));
+        ERQ_HIP(launch_rerank(ix->raw, ix->n, ix->dp, q, nq, cid, cest, kk, k, per_query ? rq : nullptr,
+                              per_query ? kq : nullptr, out_ids, out_dist, st));
         prof_end(pr2, st);
     } else {
-        hipLaunchKernelGGL(copy_cols_kernel, dim3(blocks(nq * k)), dim3(256), 0, st, cid, cest, nq, kk, k, out_ids, out_dist);
+        hipLaunchKernelGGL(copy_cols_kernel, dim3(blocks(nq * k)), dim3(256), 0, st, cid, cest, nq, kk, k,
+                           per_query ? kq : nullptr, out_ids, out_dist);
         ERQ_HIP(hipGetLastError());
     }
     return ERQ_OK;
+}
+
+int erq_search(erq_index ix, const float* q, int64_t nq, int32_t nprobe, int32_t k, int32_t rerank_k,
+               const int32_t* nprobe_q, const int32_t* k_q, const int32_t* rerank_q, int64_t* out_ids,
+               float* out_dist, void* workspace, size_t ws_bytes, void* stream)
+{
+    if (int rc = search_check(ix, q, nq, nprobe, k, rerank_k, out_ids, out_dist, "erq_search")) return rc;
+    if (nq == 0) return ERQ_OK;
+    if (!workspace) return fail(ERQ_EINVAL, "erq_search: null workspace");
+    if (ws_bytes < search_ws(ix, nq, nprobe, k, rerank_k)) return fail(ERQ_ENOMEM, "erq_search: workspace too small");
+    return search_run(ix, q, nq, nprobe, k, rerank_k, nprobe_q, k_q, rerank_q, out_ids, out_dist, workspace, ws_bytes,
+                      (hipStream_t)stream);
 }
 
 int erq_index_set_tune(erq_index ix, int32_t nqt, int32_t pd, int32_t round1, int32_t round2)
@@ -644,10 +736,13 @@ int erq_index_tune(erq_index ix, const float* q, int64_t nq, int32_t nprobe, int
     int bq = scan_nqt(ix), bp = scan_pd(ix), br = scan_round1(ix), b2 = scan_round2(ix);
     auto time_one = [&](int nqt, int pd, int r1, int r2, double* ms) -> int {
         ix->tune_nqt = nqt; ix->tune_pd = pd; ix->tune_round1 = r1; ix->tune_round2 = r2;
-        if (int r = erq_search(ix, q, nq, nprobe, k, rerank_k, out_ids, out_dist, workspace, ws_bytes, stream)) return r;
+        if (int r = erq_search(ix, q, nq, nprobe, k, rerank_k, nullptr, nullptr, nullptr, out_ids, out_dist, workspace,
+                               ws_bytes, stream))
+            return r;
         if (hipEventRecord(ea, st) != hipSuccess) return fail(ERQ_EDEVICE, "erq_index_tune: event record failed");
         for (int i = 0; i < reps; ++i)
-            if (int r = erq_search(ix, q, nq, nprobe, k, rerank_k, out_ids, out_dist, workspace, ws_bytes, stream))
+            if (int r = erq_search(ix, q, nq, nprobe, k, rerank_k, nullptr, nullptr, nullptr, out_ids, out_dist,
+                                   workspace, ws_bytes, stream))
                 return r;
         float t = 0.0f;
         if (hipEventRecord(eb, st) != hipSuccess || hipEventSynchronize(eb) != hipSuccess ||

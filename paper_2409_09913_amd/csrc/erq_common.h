@@ -18,6 +18,7 @@ constexpr int kWave = 64;
 constexpr int kTileV = 32;      // vectors per packed code tile (rows of one 32x32 MFMA tile)
 constexpr int kMaxDp = 4096;
 constexpr int kMaxDpNqt2 = 1536;  // largest dp whose two-tile query block fits the LDS
+constexpr int kMaxK = 1024;       // largest top-k / re-rank depth of a scan
 
 // ---- status plumbing -------------------------------------------------------
 void set_error(const std::string& msg);
@@ -89,9 +90,9 @@ struct Index {
 void free_index_storage(Index* ix);
 
 // ---- kernel timing (see erq_profile_enable) ---------------------------------
-enum ProfKernel { PK_SCAN = 0, PK_QUANTIZE, PK_ROTATE, PK_PROBE, PK_MERGE, PK_RERANK, PK_SCAN_A, PK_SCAN_B,
+enum ProfKernel { PK_SCAN = 0, PK_QUANTIZE, PK_ROTATE, PK_PROBE, PK_RERANK, PK_SCAN_A, PK_SCAN_B,
                   PK_SCAN_C, PK_COUNT };
-// diagnostics of the last scan while profiling is on (pairs queued to pass C)
+// diagnostics of the last scan while profiling is on (pairs scanned by the exact fallback)
 void prof_note_redo(const int32_t* dev_count, hipStream_t st);
 // returns a started record (or -1 when profiling is off); prof_end closes it
 int prof_begin(int kernel, hipStream_t st);
@@ -123,8 +124,12 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, co
 // scan factors from unpacked codes (list order) and (f_add, f_rescale)
 hipError_t launch_scan_fac(const uint8_t* codes_u, const int64_t* list_off, int64_t nlist, const float* cent_rot,
                            const float2* fac, int64_t n, int dp, int bits, float2* sfac, hipStream_t st);
-hipError_t launch_rerank(const float* raw, int dp, const float* q, int64_t nq, const int64_t* cand,
-                         int kc, int k, int64_t* out_ids, float* out_d, hipStream_t st);
+// exact re-rank of each query's first kc_q[i] (all kc when null) candidates
+// (ids outside [0, n) skipped), keeping its k_q[i] (else k) best; a query
+// with kc_q[i] == 0 gets its first candidates and their estimates copied
+hipError_t launch_rerank(const float* raw, int64_t n, int dp, const float* q, int64_t nq, const int64_t* cand,
+                         const float* cand_est, int kc, int k, const int32_t* kc_q, const int32_t* k_q,
+                         int64_t* out_ids, float* out_d, hipStream_t st);
 
 // list building
 hipError_t launch_residual(const float* x, const int64_t* ids, const int32_t* assign, const float* cent,

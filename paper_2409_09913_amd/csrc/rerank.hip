@@ -8,29 +8,46 @@ namespace erq {
 
 namespace {
 
-constexpr int kMaxKc = 256;
+constexpr int kMaxKc = 1024;
 
-__global__ __launch_bounds__(256) void rerank_kernel(const float* __restrict__ raw, int dp,
+// One block per query.  cand: nq x kc (stride kc); the query re-ranks its
+// first kcq = kc_q[iq] candidates (all kc when kc_q is null) and keeps the
+// kq = k_q[iq] (else k) best; kcq == 0 copies its first kq candidates and
+// their estimates (cand_est) unchanged.  Ids outside [0, n) count as missing.
+__global__ __launch_bounds__(256) void rerank_kernel(const float* __restrict__ raw, int64_t n, int dp,
                                                      const float* __restrict__ q, const int64_t* __restrict__ cand,
-                                                     int kc, int k, int64_t* __restrict__ out_ids,
-                                                     float* __restrict__ out_d)
+                                                     const float* __restrict__ cand_est, int kc, int k,
+                                                     const int32_t* __restrict__ kc_q, const int32_t* __restrict__ k_q,
+                                                     int64_t* __restrict__ out_ids, float* __restrict__ out_d)
 {
     __shared__ float sd[kMaxKc];
     __shared__ long long si[kMaxKc];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int64_t iq = blockIdx.x;
     const float* qv = q + iq * (int64_t)dp;
+    const int kq = k_q ? k_q[iq] : k;
+    const int kcq = kc_q ? kc_q[iq] : kc;
+    if (kcq == 0) {                                  // no re-rank for this query
+        for (int t = tid; t < k; t += 256) {
+            const bool ok = t < kq && cand[iq * kc + t] >= 0;
+            out_ids[iq * k + t] = ok ? cand[iq * kc + t] : -1;
+            out_d[iq * k + t] = ok ? cand_est[iq * kc + t] : __builtin_huge_valf();
+        }
+        return;
+    }
+    const int64_t* cq = cand + iq * kc;
     // wave wid takes candidates wid, wid + 4, ... in batches of CB, whose row
     // loads are issued together; each distance is summed in the same order
     // as one candidate at a time
     constexpr int CB = 8;
-    for (int c0 = wid; c0 < kc; c0 += 4 * CB) {
+    for (int c0 = wid; c0 < kcq; c0 += 4 * CB) {
         long long id[CB];
         float s[CB];
 #pragma unroll
         for (int b = 0; b < CB; ++b) {
             const int c = c0 + 4 * b;
-            id[b] = (c < kc) ? cand[iq * kc + c] : -1;
+            id[b] = (c < kcq) ? cq[c] : -1;
+            if (id[b] >= n) id[b] = -1;
             s[b] = 0.0f;
         }
         for (int i = lane * 4; i < dp; i += 256) {
@@ -49,15 +66,15 @@ __global__ __launch_bounds__(256) void rerank_kernel(const float* __restrict__ r
         for (int b = 0; b < CB; ++b) {
             for (int o = 32; o > 0; o >>= 1) s[b] += __shfl_xor(s[b], o);
             const int c = c0 + 4 * b;
-            if (lane == 0 && c < kc) {
+            if (lane == 0 && c < kcq) {
                 sd[c] = (id[b] >= 0) ? s[b] : __builtin_huge_valf();
                 si[c] = (id[b] >= 0) ? id[b] : 0x7FFFFFFFFFFFFFFFLL;
             }
         }
     }
     int S = 1;
-    while (S < kc) S <<= 1;
-    for (int t = kc + tid; t < S; t += 256) { sd[t] = __builtin_huge_valf(); si[t] = 0x7FFFFFFFFFFFFFFFLL; }
+    while (S < kcq) S <<= 1;
+    for (int t = kcq + tid; t < S; t += 256) { sd[t] = __builtin_huge_valf(); si[t] = 0x7FFFFFFFFFFFFFFFLL; }
     for (int kb = 2; kb <= S; kb <<= 1)
         for (int j = kb >> 1; j > 0; j >>= 1) {
             __syncthreads();
@@ -72,7 +89,7 @@ __global__ __launch_bounds__(256) void rerank_kernel(const float* __restrict__ r
         }
     __syncthreads();
     for (int t = tid; t < k; t += 256) {
-        const bool valid = t < kc && sd[t] < __builtin_huge_valf();
+        const bool valid = t < kq && t < kcq && sd[t] < __builtin_huge_valf();
         out_ids[iq * k + t] = valid ? si[t] : -1;
         out_d[iq * k + t] = valid ? sd[t] : __builtin_huge_valf();
     }
@@ -80,11 +97,13 @@ __global__ __launch_bounds__(256) void rerank_kernel(const float* __restrict__ r
 
 }  // namespace
 
-hipError_t launch_rerank(const float* raw, int dp, const float* q, int64_t nq, const int64_t* cand,
-                         int kc, int k, int64_t* out_ids, float* out_d, hipStream_t st)
+hipError_t launch_rerank(const float* raw, int64_t n, int dp, const float* q, int64_t nq, const int64_t* cand,
+                         const float* cand_est, int kc, int k, const int32_t* kc_q, const int32_t* k_q,
+                         int64_t* out_ids, float* out_d, hipStream_t st)
 {
     if (nq <= 0) return hipSuccess;
-    hipLaunchKernelGGL(rerank_kernel, dim3((unsigned)nq), dim3(256), 0, st, raw, dp, q, cand, kc, k, out_ids, out_d);
+    hipLaunchKernelGGL(rerank_kernel, dim3((unsigned)nq), dim3(256), 0, st, raw, n, dp, q, cand, cand_est, kc, k,
+                       kc_q, k_q, out_ids, out_d);
     return hipGetLastError();
 }
 

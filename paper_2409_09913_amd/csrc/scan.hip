@@ -1,12 +1,14 @@
 // IVF scan of Extended RaBitQ codes on the int8 matrix cores (Sec. 3.3,
-// Sec. 4.1).  For every (query, probed list) pair the estimated squared
-// distance of every member is
-//     est = f_add + ||s'||^2 + f_rescale * delta/2 * (2 <y_u, s_int> - (2^B - 1) sum s_int)
-// (Eq. eq:dis to ip with Eq. eq 3.3: represent), where s' = q' - c' is the
-// rotated query residual of the list, quantised to int8 per pair
-// (symmetric, delta = max|s'|/127), and <y_u, s_int> is accumulated exactly in
-// int32 by v_mfma_i32_32x32x32_i8.  The kk smallest (est, id) per query are
-// returned.  One query batch runs as:
+// Sec. 4.1).  Every rotated query q' is quantised to int8 once
+// (symmetric, delta = max|q'|/127, q_int = rint(q' / delta)).  For a probed
+// list with rotated centroid c' the residual is s' = q' - c', and by
+// linearity <y_bar, s'> = <y_bar, q'> - <y_bar, c'>, where the list term is
+// folded into the member's factor g_add = f_add - f_rescale <y_bar, c'>.  The
+// estimated squared distance of a member is then
+//     est = g_add + ||s'||^2 + f_rescale * delta/2 * (2 <y_u, q_int> - (2^B - 1) sum q_int)
+// (Eq. eq:dis to ip with Eq. eq 3.3: represent), with <y_u, q_int>
+// accumulated exactly in int32 by v_mfma_i32_32x32x32_i8.  The kk smallest
+// (est, id) per query are returned.  One query batch runs as:
 //
 //  1. pair build: (query, probe) pairs grouped by list (count, scan,
 //     scatter) for a range of probe ranks; work items are (list, tile of its
@@ -16,8 +18,8 @@
 //     candidate buffer; tau_q is the kk-th best of them (radix select).  Any
 //     subset of a query's candidates gives a valid bound: every member of the
 //     final top-kk has est <= tau_q.  The buffer is then emptied.
-//  3. pass B (the scan) in two rounds of probe rank, [0, kRound1) and the
-//     rest: 64 vectors x 64 queries per wave step.  Estimates above tau_q are
+//  3. pass B (the scan) in rounds of probe rank, [0, round1) and the rest:
+//     64 vectors x 32 or 64 queries per wave step.  Estimates above tau_q are
 //     dropped with one compare; the rest are staged in a per-query LDS
 //     buffer (spilling straight to global memory when it is full) and
 //     appended to the query's candidate buffer in HBM.  A query whose buffer
@@ -26,8 +28,8 @@
 //     round's pairs of those queries are scanned again.  After a round tau_q
 //     drops to the kk-th best candidate so far.
 //  4. select: per query, the exact kk smallest (est, id) of its candidates.
-//  5. fallback: a query whose buffer still overflowed is scanned pair by
-//     pair with the exact per-lane-list kernel and merged.
+//  5. fallback: a query whose buffer still overflowed is scanned again in
+//     full by one workgroup that keeps its exact top-kk in LDS.
 #include <algorithm>
 
 #include "erq_common.h"
@@ -135,26 +137,22 @@ __device__ inline void unpack_raw(const uint32_t* d, v4i& a0, v4i& a1) {
     a1 = v4i{(int)U[4], (int)U[5], (int)U[6], (int)U[7]};
 }
 
-template <int KK>
-__device__ inline void insert_sorted(float* le, int* li, float e, int i) {
-#pragma unroll
-    for (int t = 0; t < KK; ++t) {
-        bool sw = lt(e, i, le[t], li[t]);
-        float te = le[t]; int ti = li[t];
-        le[t] = sw ? e : te; li[t] = sw ? i : ti;
-        e = sw ? te : e; i = sw ? ti : i;
-    }
-}
-
-template <int KK>
-__device__ inline float kth_of(const float* le, int kk) {
-    float c = le[KK - 1];
-#pragma unroll
-    for (int t = 0; t < KK; ++t) c = (t == kk - 1) ? le[t] : c;
-    return c;
-}
-
 __device__ inline int out_row(int lane, int r) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
+
+// Estimator epilogue of one (member, query) pair, evaluated in this order by
+// every scan kernel, so that a pair's estimate is bit-identical whichever
+// kernel computes it: e = f_rescale * (h2 * IP + hc) + g_add and
+// est = e + ||s||^2, where f = (g_add, f_rescale) and the column constants
+// are h2 = 2 * delta/2 and hc = delta/2 * corr * sum(q_int) (epi_consts).
+template <int BITS>
+__device__ inline void epi_consts(float hd, int ss, float& h2, float& hc) {
+    constexpr int corr = 2 * (BITS == 8 ? 128 : 0) - ((1 << BITS) - 1);
+    h2 = 2.0f * hd;
+    hc = hd * (float)(corr * ss);
+}
+__device__ inline float epi_e(float2 f, int acc, float h2, float hc) {
+    return __fmaf_rn(f.y, __fmaf_rn(h2, (float)acc, hc), f.x);
+}
 
 // Item of a pair table grouped by list: largest rank r with item_off[r] <= item.
 __device__ inline void decode_item(int item, const int32_t* item_off, const int32_t* list_order, int nlist,
@@ -191,7 +189,7 @@ __device__ inline void load_query_scalars(float* s_s2, float* s_hd, int* s_ss, i
 {
     if (tid < mq) {
         const int q = pq[tid], slot = pslot[tid];
-        s_s2[tid] = qa.sdist[slot];
+        s_s2[tid] = fmaxf(qa.sdist[slot], 0.0f);     // the probe's expanded form may round below 0
         s_hd[tid] = qa.qhd[q];
         s_ss[tid] = qa.qss[q];
         s_slot[tid] = slot;
@@ -226,163 +224,6 @@ __device__ inline void load_query_rows(int8_t* qs, int qstride, const int* s_q, 
             const int qi = (int)(((float)u + 0.5f) * rnch);
             const int c = u - qi * nch;
             if (u < units) *(uint4*)(qs + qi * qstride + 16 * c) = w[k];
-        }
-    }
-}
-
-template <int BITS>
-__device__ inline float estimate(float2 f, int acc, float s2, float hd, int ss) {
-    constexpr int corr = 2 * (BITS == 8 ? 128 : 0) - ((1 << BITS) - 1);
-    const int ip2 = 2 * acc + corr * ss;
-    return (f.x + s2) + f.y * (hd * (float)ip2);
-}
-
-// ---------------------------------------------------------------------------
-// Pass A / fallback: exact per-pair top-kk, 32 queries per item, per-lane
-// lists; only the first vmax members of each list are scanned.  Items come
-// from a pair table grouped by list; grid-stride loop over items.
-// ---------------------------------------------------------------------------
-template <int BITS, int KK>
-__global__ __launch_bounds__(kThreads, 2) void scanA_kernel(
-    const uint8_t* __restrict__ codes, const int64_t* __restrict__ tile_off,
-    const int64_t* __restrict__ list_off, const float2* __restrict__ fac,
-    const int64_t* __restrict__ ids, int dp, QArgs qa, const int32_t* __restrict__ pair_off,
-    const int32_t* __restrict__ pair_q, const int32_t* __restrict__ pair_slot,
-    const int32_t* __restrict__ item_off, const int32_t* __restrict__ list_order, int nlist, int vmax,
-    int kk, float* __restrict__ res_est, int32_t* __restrict__ res_id)
-{
-    extern __shared__ __align__(16) char smem[];
-    __shared__ float s_s2[kQT], s_hd[kQT];
-    __shared__ int s_ss[kQT], s_slot[kQT], s_q[kQT];
-    __shared__ unsigned s_thr[kQT];
-    __shared__ int s_item[3];
-
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int n_items = item_off[nlist];
-    const int nkb = dp / 64;
-    int8_t* qs = (int8_t*)smem;
-    const int qstride = dp + 16;
-    const int64_t tile_bytes = (int64_t)4 * dp * BITS;
-    // B fragment of lane (h = lane/32, j = lane%32): query j, bytes 16h.. of each 32-dim block
-    const int8_t* qrow = qs + (lane & 31) * qstride + 16 * (lane >> 5);
-
-    for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
-        __syncthreads();                               // LDS of the previous item is free
-        if (tid == 0) {
-            int l, t;
-            decode_item(item, item_off, list_order, nlist, &l, &t);
-            const int p0 = pair_off[l] + t * kQT;
-            s_item[0] = l; s_item[1] = p0; s_item[2] = min(kQT, pair_off[l + 1] - p0);
-        }
-        if (tid < kQT) s_thr[tid] = 0xFFFFFFFFu;
-        __syncthreads();
-        const int l = s_item[0], p0 = s_item[1], mq = s_item[2];
-        load_query_scalars(s_s2, s_hd, s_ss, s_slot, s_q, nullptr, nullptr, qa, pair_q + p0, pair_slot + p0, mq, tid);
-        __syncthreads();
-        load_query_rows<1>(qs, qstride, s_q, qa.qint, dp, mq, tid);
-        __syncthreads();
-
-        const int j = lane & 31;
-        const bool qvalid = j < mq;
-        const float qs2 = qvalid ? s_s2[j] : 0.0f;
-        const float qhd = qvalid ? s_hd[j] : 0.0f;
-        const int qss = qvalid ? s_ss[j] : 0;
-        float le[KK];
-        int li[KK];
-#pragma unroll
-        for (int t = 0; t < KK; ++t) { le[t] = __builtin_huge_valf(); li[t] = 0x7FFFFFFF; }
-        float cut = __builtin_huge_valf();
-        const int64_t lbase = list_off[l];
-        const int nl = min((int)(list_off[l + 1] - lbase), vmax);
-        const int ntile = (nl + 31) >> 5;
-        const int64_t tbase = tile_off[l];
-
-        for (int tt = wid; tt < ntile; tt += 4) {
-            const uint8_t* tp = codes + (tbase + tt) * tile_bytes;
-            v16i acc;
-#pragma unroll
-            for (int r = 0; r < 16; ++r) acc[r] = 0;
-            for (int kb = 0; kb < nkb; ++kb) {
-                v4i a0, a1;
-                load_codes<BITS>(tp + (int64_t)kb * 256 * BITS, lane, a0, a1);
-                const v4i b0 = *(const v4i*)(qrow + 64 * kb);
-                const v4i b1 = *(const v4i*)(qrow + 64 * kb + 32);
-                acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, b0, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, b1, acc, 0, 0, 0);
-            }
-            const float c0 = fminf(cut, key2f(s_thr[j]));
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int v = tt * 32 + out_row(lane, r);
-                const bool ok = qvalid && v < nl;
-                float est = __builtin_huge_valf();
-                if (ok) est = estimate<BITS>(fac[lbase + v], acc[r], qs2, qhd, qss);
-                const bool pass = ok && est <= c0;
-                if (__any(pass)) {
-                    int id = 0x7FFFFFFF;
-                    if (pass) id = (int)ids[lbase + v];
-                    else est = __builtin_huge_valf();
-                    insert_sorted<KK>(le, li, est, id);
-                }
-            }
-            cut = kth_of<KK>(le, kk);
-            if (qvalid && cut < __builtin_huge_valf()) atomicMin(&s_thr[j], f2key(cut));
-        }
-        __syncthreads();                           // done with the B operand: reuse LDS
-
-        // lanes j and j+32 hold the same query: keep the KK smallest of both
-        {
-            float oe[KK]; int oi[KK];
-#pragma unroll
-            for (int t = 0; t < KK; ++t) { oe[t] = __shfl_xor(le[t], 32); oi[t] = __shfl_xor(li[t], 32); }
-#pragma unroll
-            for (int t = 0; t < KK; ++t) {
-                bool take = lt(oe[KK - 1 - t], oi[KK - 1 - t], le[t], li[t]);
-                float e = take ? oe[KK - 1 - t] : le[t];
-                int i = take ? oi[KK - 1 - t] : li[t];
-                le[t] = e; li[t] = i;
-            }
-#pragma unroll
-            for (int jj = KK / 2; jj > 0; jj >>= 1) {
-#pragma unroll
-                for (int t = 0; t < KK; ++t) {
-                    if ((t & jj) == 0) {
-                        const int p = t + jj;
-                        if (lt(le[p], li[p], le[t], li[t])) {
-                            float e = le[t]; le[t] = le[p]; le[p] = e;
-                            int i = li[t]; li[t] = li[p]; li[p] = i;
-                        }
-                    }
-                }
-            }
-        }
-        float* me = (float*)smem;                         // [4][32][KK]
-        int* mi = (int*)(smem + sizeof(float) * 4 * kQT * KK);
-        if (lane < 32) {
-#pragma unroll
-            for (int t = 0; t < KK; ++t) {
-                me[(wid * kQT + lane) * KK + t] = le[t];
-                mi[(wid * kQT + lane) * KK + t] = li[t];
-            }
-        }
-        __syncthreads();
-        if (tid < mq) {
-            int h[4] = {0, 0, 0, 0};
-            const int slot = s_slot[tid];
-            for (int o = 0; o < kk; ++o) {
-                int bw = 0;
-                float be = me[(0 * kQT + tid) * KK + h[0]];
-                int bi = mi[(0 * kQT + tid) * KK + h[0]];
-                for (int w = 1; w < 4; ++w) {
-                    float e = me[(w * kQT + tid) * KK + h[w]];
-                    int i = mi[(w * kQT + tid) * KK + h[w]];
-                    if (lt(e, i, be, bi)) { be = e; bi = i; bw = w; }
-                }
-                if (h[bw] < KK - 1) ++h[bw];
-                else { me[(bw * kQT + tid) * KK + h[bw]] = __builtin_huge_valf(); mi[(bw * kQT + tid) * KK + h[bw]] = 0x7FFFFFFF; }
-                res_est[(int64_t)slot * kk + o] = be;
-                res_id[(int64_t)slot * kk + o] = (be < __builtin_huge_valf()) ? bi : -1;
-            }
         }
     }
 }
@@ -504,12 +345,10 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
     // compares the part before + s2 with AQ = tau - s2 rounded up by a margin
     // above the rounding of both subtractions, so it never drops a candidate
     // whose final estimate is <= tau.  Columns without a query take AQ = -inf.
-    constexpr int corr = 2 * (BITS == 8 ? 128 : 0) - ((1 << BITS) - 1);
     float cH2[NQT], cHC[NQT], cAQ[NQT];
 #pragma unroll
     for (int qt = 0; qt < NQT; ++qt) {
-        cH2[qt] = 2.0f * qhd[qt];
-        cHC[qt] = qhd[qt] * (float)(corr * qss[qt]);
+        epi_consts<BITS>(qhd[qt], qss[qt], cH2[qt], cHC[qt]);
         const float aq = qtau[qt] - qs2[qt];
         cAQ[qt] = qok[qt] ? aq + (fabsf(qtau[qt]) + fabsf(qs2[qt])) * 0x1p-20f : -__builtin_huge_valf();
     }
@@ -601,13 +440,11 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
                 for (int r = 0; r < 16; ++r) {
                     const int v = tt * 32 + out_row(lane, r);
                     const float2 f = fr[r];
-                    const float gv = f.x;
                     float e[NQT];
                     bool pass[NQT], anyp = false;
 #pragma unroll
                     for (int qt = 0; qt < NQT; ++qt) {
-                        const float y = __fmaf_rn(cH2[qt], (float)acc[a][qt][r], cHC[qt]);
-                        e[qt] = __fmaf_rn(f.y, y, gv);
+                        e[qt] = epi_e(f, acc[a][qt][r], cH2[qt], cHC[qt]);
                         pass[qt] = e[qt] <= cAQ[qt];
                         anyp = anyp || pass[qt];
                     }
@@ -754,6 +591,35 @@ __device__ __attribute__((always_inline)) inline void wave_digit(const unsigned 
     wave_lds_sync();                        // the bins are read before the next pass clears them
 }
 
+// LDS slots per wave for the selected entries of mode 1: a power of two >= kk
+// (and >= 64), so that a bitonic sort can run over them
+__host__ __device__ inline int sel_slots(int kk) {
+    int s = 64;
+    while (s < kk) s <<= 1;
+    return s;
+}
+
+// Ascending bitonic sort by (est, id) of the m entries (se, si) of one wave
+// in LDS, padded with (+inf, INT_MAX) up to the next power of two (at most
+// sel_slots(kk) entries); lanes move pairs t, t + 64, ... of each step.
+__device__ inline void wave_bitonic(float* se, int* si, int m, int lane) {
+    int S = 1;
+    while (S < m) S <<= 1;
+    for (int t = m + lane; t < S; t += 64) { se[t] = __builtin_huge_valf(); si[t] = 0x7FFFFFFF; }
+    wave_lds_sync();
+    for (int kb = 2; kb <= S; kb <<= 1)
+        for (int j = kb >> 1; j > 0; j >>= 1) {
+            for (int t = lane; t < S / 2; t += 64) {
+                const int i = 2 * t - (t & (j - 1)), p = i + j;
+                const bool up = (i & kb) == 0;
+                const float e0 = se[i], e1 = se[p];
+                const int i0 = si[i], i1 = si[p];
+                if (lt(e0, i0, e1, i1) != up) { se[i] = e1; se[p] = e0; si[i] = i1; si[p] = i0; }
+            }
+            wave_lds_sync();
+        }
+}
+
 // post (mode 0 only), applied on entry after the count is read: 1 empties the
 // buffer (count and count-before-round 0), 2 records the count as the
 // count before the next round
@@ -766,9 +632,12 @@ __global__ __launch_bounds__(256) void buf_select_kernel(int32_t* __restrict__ g
                                                          float* __restrict__ out_est, int32_t* __restrict__ any_over)
 {
     __shared__ unsigned hist[kSelQ][256];
-    __shared__ float s_e[kSelQ][32];
-    __shared__ int s_i[kSelQ][32];
+    // mode 1: the selected entries of each wave, kS = pow2 >= max(kk, 64) slots
+    extern __shared__ __align__(16) char sel_smem[];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int kS = sel_slots(kk);
+    float* s_e = (float*)sel_smem + w * kS;
+    int* s_i = (int*)(sel_smem + sizeof(float) * kSelQ * kS) + w * kS;
     const int64_t q = (int64_t)blockIdx.x * kSelQ + w;
     if (q >= nq) return;                                // the whole wave
     const int craw = gcnt[q];
@@ -897,8 +766,8 @@ __global__ __launch_bounds__(256) void buf_select_kernel(int32_t* __restrict__ g
             if (v[k]) {
                 const int t = base + lane + 64 * k;
                 if (pos < (unsigned)kk) {
-                    s_e[w][pos] = be[t];
-                    s_i[w][pos] = bi[t];
+                    s_e[pos] = be[t];
+                    s_i[pos] = bi[t];
                 }
                 ++pos;
                 --cnt;
@@ -907,22 +776,280 @@ __global__ __launch_bounds__(256) void buf_select_kernel(int32_t* __restrict__ g
     }
     wave_lds_sync();
     const int m = (int)min(m_all, (unsigned)kk);
-    // rank of entry `lane` by (est, id) among the m selected; equal pairs by position
-    if (lane < m) {
-        const float e = s_e[w][lane];
-        const int id = s_i[w][lane];
-        int r = 0;
-        for (int j = 0; j < m; ++j) {
-            const float ej = s_e[w][j];
-            const int ij = s_i[w][j];
-            r += (lt(ej, ij, e, id) || (j < lane && ej == e && ij == id)) ? 1 : 0;
+    if (m <= 64) {
+        // rank of entry `lane` by (est, id) among the m selected; equal pairs by position
+        if (lane < m) {
+            const float e = s_e[lane];
+            const int id = s_i[lane];
+            int r = 0;
+            for (int j = 0; j < m; ++j) {
+                const float ej = s_e[j];
+                const int ij = s_i[j];
+                r += (lt(ej, ij, e, id) || (j < lane && ej == e && ij == id)) ? 1 : 0;
+            }
+            out_ids[q * kk + r] = id;
+            out_est[q * kk + r] = e;
         }
-        out_ids[q * kk + r] = id;
-        out_est[q * kk + r] = e;
+    } else {
+        wave_bitonic(s_e, s_i, m, lane);
+        for (int t = lane; t < m; t += 64) {
+            out_ids[q * kk + t] = s_i[t];
+            out_est[q * kk + t] = s_e[t];
+        }
     }
     for (int t = m + lane; t < kk; t += 64) {
         out_ids[q * kk + t] = -1;
         out_est[q * kk + t] = __builtin_huge_valf();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Exact fallback for the queries whose candidate buffer still overflowed
+// after their rounds were rescanned: one workgroup per flagged query scans
+// every member of its probed lists and keeps the exact kk smallest (est, id)
+// in LDS as 64-bit keys (order-preserving image of the estimate, then the
+// id).  Keys below the current threshold T are appended; when fewer than
+// 4 * 32 free slots remain, a radix select keeps the kk smallest and T drops
+// to the largest kept key, so each compaction frees kCapE - kk slots and the
+// scan always advances.  Estimates use the pass-B arithmetic (epi_e), so a
+// query gets the same result on this path as on the bounded one.
+// ---------------------------------------------------------------------------
+constexpr int kCapE = 4096;      // candidate keys per flagged query (LDS)
+constexpr int kPerE = kCapE / 256;
+
+// inclusive prefix sum over the 256 threads of a block; s_w: 4 slots
+__device__ inline unsigned block_scan256(unsigned v, unsigned* s_w) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    unsigned x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) s_w[wid] = x;
+    __syncthreads();
+    unsigned base = 0;
+    for (int w = 0; w < wid; ++w) base += s_w[w];
+    __syncthreads();                             // s_w is free for the next call
+    return base + x;
+}
+
+// Radix select (8 passes of 8 bits) of the kr-th smallest (1-based, kr <= c)
+// of keys[0, c), block-wide.  Returns it; *need is how many of the keys equal
+// to it belong to the kr smallest.
+__device__ __attribute__((always_inline)) inline unsigned long long block_select64(
+    const unsigned long long* keys, int c, unsigned kr, unsigned* hist, unsigned* s_w, unsigned* s_bc, unsigned& need)
+{
+    const int tid = threadIdx.x;
+    unsigned long long prefix = 0, mask = 0;
+    for (int pass = 0; pass < 8; ++pass) {
+        const int shift = 56 - 8 * pass;
+        hist[tid] = 0;
+        __syncthreads();
+        unsigned run_d = 0xFFFFFFFFu, run_n = 0;
+        for (int t = tid; t < c; t += 256) {
+            const unsigned long long k = keys[t];
+            if ((k & mask) == prefix) {
+                const unsigned dg = (unsigned)(k >> shift) & 0xFFu;
+                if (dg != run_d) {
+                    if (run_n) atomicAdd(&hist[run_d], run_n);
+                    run_d = dg; run_n = 0;
+                }
+                ++run_n;
+            }
+        }
+        if (run_n) atomicAdd(&hist[run_d], run_n);
+        __syncthreads();
+        const unsigned v = hist[tid];
+        const unsigned incl = block_scan256(v, s_w);
+        const unsigned excl = incl - v;
+        if (excl < kr && kr <= incl) { s_bc[0] = (unsigned)tid; s_bc[1] = kr - excl; }
+        __syncthreads();
+        prefix |= (unsigned long long)s_bc[0] << shift;
+        mask |= 0xFFull << shift;
+        kr = s_bc[1];
+        __syncthreads();                         // s_bc and hist are read before the next pass
+    }
+    need = kr;
+    return prefix;
+}
+
+// Keeps the kk smallest of keys[0, c) (c > kk, c <= kCapE) in keys[0, kk):
+// the keys below the kk-th, then as many keys equal to it as belong to the kk
+// smallest (first ones in index order).  Returns the kk-th smallest key.
+// Every thread reads its contiguous chunk into registers before any writes.
+__device__ __attribute__((always_inline)) inline unsigned long long block_keep(
+    unsigned long long* keys, int c, int kk, unsigned* hist, unsigned* s_w, unsigned* s_bc)
+{
+    unsigned need;
+    const unsigned long long kth = block_select64(keys, c, (unsigned)kk, hist, s_w, s_bc, need);
+    const int per = (c + 255) / 256;             // <= kPerE
+    const int b0 = min(c, (int)threadIdx.x * per), b1 = min(c, b0 + per);
+    unsigned long long v[kPerE];
+    unsigned nl = 0, ne = 0;
+#pragma unroll
+    for (int u = 0; u < kPerE; ++u) {
+        const int t = b0 + u;
+        v[u] = (t < b1) ? keys[t] : ~0ull;
+        nl += (t < b1 && v[u] < kth) ? 1u : 0u;
+        ne += (t < b1 && v[u] == kth) ? 1u : 0u;
+    }
+    unsigned pl = block_scan256(nl, s_w) - nl;   // barriers inside: every chunk has been read
+    unsigned pe = block_scan256(ne, s_w) - ne;
+    const unsigned nless = (unsigned)kk - need;
+#pragma unroll
+    for (int u = 0; u < kPerE; ++u) {
+        const int t = b0 + u;
+        if (t < b1) {
+            if (v[u] < kth) keys[pl++] = v[u];
+            else if (v[u] == kth) {
+                if (pe < need) keys[nless + pe] = v[u];
+                ++pe;
+            }
+        }
+    }
+    __syncthreads();
+    return kth;
+}
+
+// One flagged query per workgroup (grid-stride over the queries).  Dynamic
+// LDS: kCapE keys, the tile prefix over the probes (nprobe + 1 ints, rounded
+// up to 16 bytes) and the query's int8 row (dp bytes).  redo counts the
+// probed pairs of the flagged queries (diagnostics).
+template <int BITS>
+__global__ __launch_bounds__(256) void exact_kernel(
+    const uint8_t* __restrict__ codes, const int64_t* __restrict__ tile_off, const int64_t* __restrict__ list_off,
+    const float2* __restrict__ fac, const int64_t* __restrict__ ids, int dp, QArgs qa,
+    const int32_t* __restrict__ probes, int64_t nq, int nprobe, int nlist, int kk,
+    const int32_t* __restrict__ ovf, const int32_t* __restrict__ gate, int32_t* __restrict__ redo,
+    int64_t* __restrict__ out_ids, float* __restrict__ out_est)
+{
+    if (*gate == 0) return;
+    extern __shared__ __align__(16) char smem[];
+    unsigned long long* keys = (unsigned long long*)smem;
+    int* tpref = (int*)(smem + sizeof(unsigned long long) * kCapE);
+    int8_t* qs = (int8_t*)(tpref + ((nprobe + 4) & ~3));
+    __shared__ unsigned hist[256], s_w[4], s_bc[2];
+    __shared__ int s_cnt;
+    __shared__ unsigned long long s_T;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int nkb = dp / 64;
+    const int64_t tile_bytes = (int64_t)4 * dp * BITS;
+    const int8_t* qrow = qs + 16 * (lane >> 5);  // every MFMA column is the query itself
+    for (int64_t q = blockIdx.x; q < nq; q += gridDim.x) {
+        if (!ovf[q]) continue;                   // the same for the whole block
+        __syncthreads();                         // LDS of the previous query is free
+        for (int c = tid; c < dp / 16; c += 256) *(uint4*)(qs + 16 * c) = *(const uint4*)(qa.qint + q * dp + 16 * c);
+        // member tiles per probe (thread t: probes 4t .. 4t+3), exclusive prefix
+        unsigned nt[4], sum = 0, npair = 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int p = 4 * tid + u;
+            unsigned n = 0;
+            if (p < nprobe) {
+                const int l = probes[q * nprobe + p];
+                if (l >= 0 && l < nlist) {
+                    n = (unsigned)((list_off[l + 1] - list_off[l] + 31) >> 5);
+                    ++npair;
+                }
+            }
+            nt[u] = n;
+            sum += n;
+        }
+        const unsigned incl = block_scan256(sum, s_w);
+        unsigned run = incl - sum;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int p = 4 * tid + u;
+            if (p < nprobe) tpref[p] = (int)run;
+            run += nt[u];
+        }
+        if (tid == 255) tpref[nprobe] = (int)incl;
+        if (tid == 0) { s_cnt = 0; s_T = ~0ull; }
+        if (redo && npair) atomicAdd(redo, (int)npair);
+        __syncthreads();
+        const int total = tpref[nprobe];
+        float h2, hc;
+        epi_consts<BITS>(qa.qhd[q], qa.qss[q], h2, hc);
+        for (int base = 0; base < total; base += 4) {
+            const int g = base + wid;
+            const unsigned long long T = s_T;
+            if (g < total) {
+                int lo = 0, hi = nprobe;             // tpref[lo] <= g < tpref[hi]
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (tpref[mid] <= g) lo = mid; else hi = mid;
+                }
+                const int tt = g - tpref[lo];
+                const int l = probes[q * nprobe + lo];
+                const float s2 = fmaxf(qa.sdist[q * nprobe + lo], 0.0f);
+                const int64_t lb = list_off[l];
+                const int nl = (int)(list_off[l + 1] - lb);
+                const uint8_t* tp = codes + (tile_off[l] + tt) * tile_bytes;
+                v16i acc;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[r] = 0;
+                for (int kb = 0; kb < nkb; ++kb) {
+                    v4i a0, a1;
+                    load_codes<BITS>(tp + (int64_t)kb * 256 * BITS, lane, a0, a1);
+                    const v4i b0 = *(const v4i*)(qrow + 64 * kb);
+                    const v4i b1 = *(const v4i*)(qrow + 64 * kb + 32);
+                    acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, b0, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, b1, acc, 0, 0, 0);
+                }
+                // lane (h, j < 16) takes output row out_row(lane, j): the 32
+                // lanes cover the tile's 32 members once
+                const int j = lane & 31;
+                if (j < 16) {
+                    int a = acc[0];
+#pragma unroll
+                    for (int r = 1; r < 16; ++r) a = (r == j) ? acc[r] : a;
+                    const int v = tt * 32 + out_row(lane, j);
+                    if (v < nl) {
+                        const float est = epi_e(fac[lb + v], a, h2, hc) + s2;
+                        const unsigned long long key =
+                            ((unsigned long long)f2key(est) << 32) | (unsigned)(int)ids[lb + v];
+                        if (key < T) keys[atomicAdd(&s_cnt, 1)] = key;
+                    }
+                }
+            }
+            __syncthreads();
+            if (s_cnt > kCapE - 4 * 32) {        // room for the next step's 128 candidates
+                const unsigned long long kth = block_keep(keys, s_cnt, kk, hist, s_w, s_bc);
+                if (tid == 0) { s_cnt = kk; s_T = kth; }
+                __syncthreads();
+            }
+        }
+        const int c = s_cnt;
+        int m = c;
+        if (c > kk) {
+            block_keep(keys, c, kk, hist, s_w, s_bc);
+            m = kk;
+        }
+        // ascending bitonic sort of keys[0, m), padded to a power of two (<= kk rounded up)
+        int S = 1;
+        while (S < m) S <<= 1;
+        for (int t = m + tid; t < S; t += 256) keys[t] = ~0ull;
+        __syncthreads();
+        for (int kb = 2; kb <= S; kb <<= 1)
+            for (int jj = kb >> 1; jj > 0; jj >>= 1) {
+                for (int t = tid; t < S / 2; t += 256) {
+                    const int i = 2 * t - (t & (jj - 1)), p = i + jj;
+                    const bool up = (i & kb) == 0;
+                    const unsigned long long k0 = keys[i], k1 = keys[p];
+                    if ((k0 < k1) != up) { keys[i] = k1; keys[p] = k0; }
+                }
+                __syncthreads();
+            }
+        for (int t = tid; t < kk; t += 256) {
+            if (t < m) {
+                const unsigned long long k = keys[t];
+                out_ids[q * kk + t] = (int64_t)(int)(unsigned)(k & 0xFFFFFFFFull);
+                out_est[q * kk + t] = key2f((unsigned)(k >> 32));
+            } else {
+                out_ids[q * kk + t] = -1;
+                out_est[q * kk + t] = __builtin_huge_valf();
+            }
+        }
     }
 }
 
@@ -1006,10 +1133,11 @@ __global__ __launch_bounds__(256) void scan_fac_kernel(const uint8_t* __restrict
 // before the first bound: slots [0, kDenseR*kDenseV) of every query's buffer
 // hold +inf, the count covers them, and the bound is +inf
 __global__ void fill_dense_kernel(float* __restrict__ gbuf_e, int64_t nq, int32_t* __restrict__ gcnt,
-                                  unsigned* __restrict__ tau_key)
+                                  unsigned* __restrict__ tau_key, int32_t* __restrict__ redo)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     constexpr int W = kDenseR * kDenseV;
+    if (i == 0) *redo = 0;
     if (i >= nq * W) return;
     const int64_t q = i / W;
     gbuf_e[q * kCapQ + (i - q * W)] = __builtin_huge_valf();
@@ -1291,112 +1419,13 @@ __global__ __launch_bounds__(1024) void pair_build_gated_kernel(
         item_desc_one(item, item_off, list_order, list_off, pair_off, nlist, qpi, vch, desc);
 }
 
-// one wave per query: the kk best of its probed lists' top-kk lists (pairs
-// with probe rank >= rlim are left out; with qmask only flagged queries)
-__global__ __launch_bounds__(256) void merge_kernel(const int32_t* __restrict__ probes, int64_t nq, int nprobe,
-                                                    int nlist, int kk, int rlim, const int32_t* __restrict__ qmask,
-                                                    const float* __restrict__ res_est,
-                                                    const int32_t* __restrict__ res_id,
-                                                    int64_t* __restrict__ out_ids, float* __restrict__ out_est)
-{
-    const int lane = threadIdx.x & 63;
-    const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (q >= nq) return;
-    if (qmask && !qmask[q]) return;
-    constexpr int U = 16;                 // nprobe <= 1024
-    int hp[U];
-    float he[U];
-    int hi[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const int p = lane + 64 * u;
-        hp[u] = 0;
-        he[u] = __builtin_huge_valf();
-        hi[u] = 0x7FFFFFFF;
-        if (p < nprobe && p < rlim) {
-            int l = probes[q * nprobe + p];
-            if (l >= 0 && l < nlist) {
-                const int64_t s = q * nprobe + p;
-                int id = res_id[s * kk];
-                he[u] = id < 0 ? __builtin_huge_valf() : res_est[s * kk];
-                hi[u] = id < 0 ? 0x7FFFFFFF : id;
-            }
-        }
-    }
-    for (int o = 0; o < kk; ++o) {
-        float be = __builtin_huge_valf();
-        int bi = 0x7FFFFFFF, bu = -1;
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (lt(he[u], hi[u], be, bi)) { be = he[u]; bi = hi[u]; bu = u; }
-        float ge = be; int gi = bi; int gl = lane;
-        for (int off = 32; off > 0; off >>= 1) {
-            float oe = __shfl_xor(ge, off);
-            int oi = __shfl_xor(gi, off);
-            int ol = __shfl_xor(gl, off);
-            if (lt(oe, oi, ge, gi) || (oe == ge && oi == gi && ol < gl)) { ge = oe; gi = oi; gl = ol; }
-        }
-        if (lane == 0) {
-            const bool valid = ge < __builtin_huge_valf();
-            if (out_ids) out_ids[q * kk + o] = valid ? (int64_t)gi : -1;
-            out_est[q * kk + o] = valid ? ge : __builtin_huge_valf();
-        }
-        if (lane == gl && bu >= 0) {
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                if (u == bu) {
-                    const int64_t s = q * nprobe + lane + 64 * u;
-                    hp[u] += 1;
-                    if (hp[u] < kk) {
-                        int id = res_id[s * kk + hp[u]];
-                        he[u] = id < 0 ? __builtin_huge_valf() : res_est[s * kk + hp[u]];
-                        hi[u] = id < 0 ? 0x7FFFFFFF : id;
-                    } else {
-                        he[u] = __builtin_huge_valf();
-                        hi[u] = 0x7FFFFFFF;
-                    }
-                }
-            }
-        }
-    }
-}
-
 struct ScanArgs {
     QArgs qa;
     const int32_t *pair_off, *pair_q, *pair_slot, *item_off;
     const int4* desc;
     int64_t grid;
-    int vmax;
     int kk;
-    float* res_est;
-    int32_t* res_id;
 };
-
-template <int BITS, int KK>
-hipError_t launchA_t(const Index* ix, const ScanArgs& a, hipStream_t st)
-{
-    size_t sm = (size_t)(ix->dp + 16) * kQT;
-    size_t mb = (size_t)4 * kQT * KK * 8;
-    if (mb > sm) sm = mb;
-    if (sm > 48 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void*)scanA_kernel<BITS, KK>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
-        if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL((scanA_kernel<BITS, KK>), dim3((unsigned)a.grid), dim3(kThreads), sm, st,
-                       ix->codes, ix->tile_off, ix->list_off, ix->sfac, ix->ids, ix->dp,
-                       a.qa, a.pair_off, a.pair_q, a.pair_slot, a.item_off, ix->list_order, (int)ix->nlist,
-                       a.vmax, a.kk, a.res_est, a.res_id);
-    return hipGetLastError();
-}
-
-template <int BITS>
-hipError_t launchA_b(const Index* ix, const ScanArgs& a, hipStream_t st)
-{
-    // kk <= 32 (checked at the ABI); a 64-entry register list spills to scratch
-    if (a.kk <= 16) return launchA_t<BITS, 16>(ix, a, st);
-    return launchA_t<BITS, 32>(ix, a, st);
-}
 
 struct BArgs { unsigned* tau_key; int32_t* gcnt; float* gbuf_e; int32_t* gbuf_i; int32_t* work;
                int vch, dense, nprobe; };
@@ -1453,20 +1482,6 @@ hipError_t launchB_b(const Index* ix, const ScanArgs& a, const BArgs& b, hipStre
     return launchB_n<BITS, 1>(ix, a, b, st);
 }
 
-hipError_t launchA(const Index* ix, const ScanArgs& a, hipStream_t st)
-{
-    switch (ix->bits) {
-        case 1: return launchA_b<1>(ix, a, st);
-        case 2: return launchA_b<2>(ix, a, st);
-        case 3: return launchA_b<3>(ix, a, st);
-        case 4: return launchA_b<4>(ix, a, st);
-        case 5: return launchA_b<5>(ix, a, st);
-        case 6: return launchA_b<6>(ix, a, st);
-        case 7: return launchA_b<7>(ix, a, st);
-        default: return launchA_b<8>(ix, a, st);
-    }
-}
-
 hipError_t launchB(const Index* ix, const ScanArgs& a, const BArgs& b, hipStream_t st)
 {
     switch (ix->bits) {
@@ -1478,6 +1493,36 @@ hipError_t launchB(const Index* ix, const ScanArgs& a, const BArgs& b, hipStream
         case 6: return launchB_b<6>(ix, a, b, st);
         case 7: return launchB_b<7>(ix, a, b, st);
         default: return launchB_b<8>(ix, a, b, st);
+    }
+}
+
+template <int BITS>
+hipError_t launch_exact_b(const Index* ix, const QArgs& qa, const int32_t* probes, int64_t nq, int nprobe, int kk,
+                          const int32_t* ovf, const int32_t* gate, int32_t* redo, int64_t* oi, float* oe,
+                          hipStream_t st)
+{
+    const size_t sm = sizeof(unsigned long long) * kCapE + sizeof(int) * ((nprobe + 4) & ~3) + (size_t)ix->dp;
+    const unsigned grid = (unsigned)std::min<int64_t>(nq, 1024);
+    hipLaunchKernelGGL((exact_kernel<BITS>), dim3(grid), dim3(256), sm, st, ix->codes, ix->tile_off, ix->list_off,
+                       ix->sfac, ix->ids, ix->dp, qa, probes, nq, nprobe, (int)ix->nlist, kk, ovf, gate, redo, oi, oe);
+    return hipGetLastError();
+}
+
+// exact fallback for the flagged queries (returns at once on the device when
+// the gate is 0)
+hipError_t launch_exact(const Index* ix, const QArgs& qa, const int32_t* probes, int64_t nq, int nprobe, int kk,
+                        const int32_t* ovf, const int32_t* gate, int32_t* redo, int64_t* oi, float* oe, hipStream_t st)
+{
+    if (nq <= 0) return hipSuccess;
+    switch (ix->bits) {
+        case 1: return launch_exact_b<1>(ix, qa, probes, nq, nprobe, kk, ovf, gate, redo, oi, oe, st);
+        case 2: return launch_exact_b<2>(ix, qa, probes, nq, nprobe, kk, ovf, gate, redo, oi, oe, st);
+        case 3: return launch_exact_b<3>(ix, qa, probes, nq, nprobe, kk, ovf, gate, redo, oi, oe, st);
+        case 4: return launch_exact_b<4>(ix, qa, probes, nq, nprobe, kk, ovf, gate, redo, oi, oe, st);
+        case 5: return launch_exact_b<5>(ix, qa, probes, nq, nprobe, kk, ovf, gate, redo, oi, oe, st);
+        case 6: return launch_exact_b<6>(ix, qa, probes, nq, nprobe, kk, ovf, gate, redo, oi, oe, st);
+        case 7: return launch_exact_b<7>(ix, qa, probes, nq, nprobe, kk, ovf, gate, redo, oi, oe, st);
+        default: return launch_exact_b<8>(ix, qa, probes, nq, nprobe, kk, ovf, gate, redo, oi, oe, st);
     }
 }
 
@@ -1543,8 +1588,7 @@ size_t scan_workspace_bytes(int64_t nq, int nprobe, int64_t nlist, int kk, int d
     b += 3 * align256(sizeof(int32_t));                    // pass-B work counter, two overflow flags
     b += align256(sizeof(float) * nq * kCapQ);             // candidate buffers
     b += align256(sizeof(int32_t) * nq * kCapQ);
-    b += align256(sizeof(float) * P * kk);                 // per-pair top-kk (pass A, fallback)
-    b += align256(sizeof(int32_t) * P * kk);
+    b += align256(sizeof(int32_t));                        // fallback pair count
     b += align256((size_t)nq * dp);                        // int8 queries
     b += 2 * align256(sizeof(float) * nq);                 // delta/2, sum of int8 values
     b += align256(sizeof(float) * P);                      // ||s||^2 per pair
@@ -1581,8 +1625,7 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, co
     int32_t* anyf2 = (int32_t*)take(sizeof(int32_t));      // ... at the final selection
     float* gbe = (float*)take(sizeof(float) * nq * kCapQ);
     int32_t* gbi = (int32_t*)take(sizeof(int32_t) * nq * kCapQ);
-    float* res_est = (float*)take(sizeof(float) * P * kk);
-    int32_t* res_id = (int32_t*)take(sizeof(int32_t) * P * kk);
+    int32_t* redo = (int32_t*)take(sizeof(int32_t));       // pairs scanned by the exact fallback
     int8_t* qint = (int8_t*)take((size_t)nq * dp);
     float* qhd = (float*)take(sizeof(float) * nq);
     int32_t* qss = (int32_t*)take(sizeof(int32_t) * nq);
@@ -1631,8 +1674,10 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, co
         }
         return hipGetLastError();
     };
+    const size_t sel_lds = (size_t)kSelQ * sel_slots(kk) * (sizeof(float) + sizeof(int));
     auto select = [&](int mode, int post, int64_t* oi, float* oe) {
-        hipLaunchKernelGGL(buf_select_kernel, dim3((unsigned)((nq + kSelQ - 1) / kSelQ)), dim3(256), 0, st, gcnt,
+        hipLaunchKernelGGL(buf_select_kernel, dim3((unsigned)((nq + kSelQ - 1) / kSelQ)), dim3(256),
+                           mode == 1 ? sel_lds : 0, st, gcnt,
                            gprev, gbe, gbi, nq, kk, mode, post, tkey, ovf, oi, oe, mode == 1 ? anyf2 : anyf);
         return hipGetLastError();
     };
@@ -1654,7 +1699,7 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, co
     auto scan_round = [&](int rlo, int rhi, const int32_t* qmask, int dense, const int32_t* gate) {
         hipError_t er = build_pairs(rlo, rhi, qmask, qpiB, dense ? 0 : kVch, gate);
         if (er != hipSuccess) return er;
-        ScanArgs b{qa, poff, pq, ps, ioff, desc, gridB, 0, kk, nullptr, nullptr};
+        ScanArgs b{qa, poff, pq, ps, ioff, desc, gridB, kk};
         BArgs bb{tkey, gcnt, gbe, gbi, work, dense ? 0 : kVch, dense, nprobe};
         const int rec = prof_begin(dense ? PK_SCAN_A : PK_SCAN_B, st);   // one record per launch
         er = launchB(ix, b, bb, st);
@@ -1665,7 +1710,7 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, co
     // nearest lists, in fixed buffer slots (+inf where a list is shorter)
     const int r0 = std::min(nprobe, kDenseR);
     hipLaunchKernelGGL(fill_dense_kernel, dim3((unsigned)((nq * kDenseR * kDenseV + th - 1) / th)), dim3(th), 0, st,
-                       gbe, nq, gcnt, tkey);
+                       gbe, nq, gcnt, tkey, redo);
     e = hipGetLastError();
     if (e == hipSuccess) e = scan_round(0, r0, nullptr, 1, nullptr);
     // bound, then the buffer is emptied (the dense entries are found again by the rounds)
@@ -1687,24 +1732,14 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, co
         if (e == hipSuccess) e = scan_round(rlo, rhi, ovf, 0, anyf);
         if (e == hipSuccess && rhi < nprobe) e = select(0, 2, nullptr, nullptr);
     }
-    // exact top-kk per query; queries whose buffer still overflowed: pair by pair
+    // exact top-kk per query; queries whose buffer still overflowed: the exact fallback
     const int pc = prof_begin(PK_SCAN_C, st);
     if (e == hipSuccess) e = select(1, 0, out_ids, out_est);
-    if (e == hipSuccess) e = build_pairs(0, nprobe, ovf, kQT, 0, anyf2);
-    if (e == hipSuccess) {
-        ScanArgs c{qa, poff, pq, ps, ioff, desc, std::min<int64_t>((P + kQT - 1) / kQT + nlist, 4096), 0x7FFFFFFF, kk,
-                   res_est, res_id};
-        e = launchA(ix, c, st);
-    }
-    if (e == hipSuccess) {
-        hipLaunchKernelGGL(merge_kernel, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, st, probes, nq, nprobe,
-                           (int)nlist, kk, nprobe, ovf, res_est, res_id, out_ids, out_est);
-        e = hipGetLastError();
-    }
+    if (e == hipSuccess) e = launch_exact(ix, qa, probes, nq, nprobe, kk, ovf, anyf2, redo, out_ids, out_est, st);
     prof_end(pc, st);
     prof_end(pr, st);
     if (e != hipSuccess) return fail(ERQ_EDEVICE, std::string("scan launch: ") + hipGetErrorString(e));
-    prof_note_redo(poff + nlist, st);       // pairs rescanned by the fallback
+    prof_note_redo(redo, st);               // pairs scanned by the exact fallback
     return ERQ_OK;
 }
 

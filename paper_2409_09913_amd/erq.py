@@ -38,7 +38,7 @@ SIGNATURES = {
     "erq_scan": (C.c_int, [_p, _p, _i64, _p, _i32, _i32, _p, _p, _p, _sz, _p]),
     "erq_rerank": (C.c_int, [_p, _p, _i64, _p, _i32, _i32, _p, _p, _p]),
     "erq_search_workspace_size": (C.c_int, [_p, _i64, _i32, _i32, _i32, C.POINTER(_sz)]),
-    "erq_search": (C.c_int, [_p, _p, _i64, _i32, _i32, _i32, _p, _p, _p, _sz, _p]),
+    "erq_search": (C.c_int, [_p, _p, _i64, _i32, _i32, _i32, _p, _p, _p, _p, _p, _p, _sz, _p]),
     "erq_index_set_tune": (C.c_int, [_p, _i32, _i32, _i32, _i32]),
     "erq_index_get_tune": (C.c_int, [_p, C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i32)]),
     "erq_index_tune": (C.c_int, [_p, _p, _i64, _i32, _i32, _i32, _i32, _p, _p, _p, _sz, _p,
@@ -99,7 +99,8 @@ def _ws(nbytes: int, device):
 
 # --------------------------------------------------------------------------
 def rotate(x, P, precision: int = 0, out=None):
-    """Rows of x times P (= P^T applied to each row), FP32 or BF16 matrix cores."""
+    """Rows of x times P (= P^T applied to each row): precision 0 FP32 matrix
+    cores, 1 BF16 inputs, 2 the BF16 hi/lo three-product form of erq_search."""
     n, dp = x.shape
     if out is None:
         out = torch.empty_like(x)
@@ -220,7 +221,11 @@ class Index:
         _check(load().erq_search_workspace_size(self.h, nq, nprobe, k, rerank_k, C.byref(sz)))
         return sz.value
 
-    def search(self, q, nprobe: int, k: int, rerank_k: int = 0, ws=None, out=None):
+    def search(self, q, nprobe: int, k: int, rerank_k: int = 0, ws=None, out=None,
+               nprobe_q=None, k_q=None, rerank_q=None):
+        """k-NN of the rows of q.  nprobe, k, rerank_k are the batch's largest
+        values; nprobe_q, k_q, rerank_q (int32 device tensors of nq, optional)
+        give each query its own (see erq_search)."""
         nq = q.shape[0]
         if ws is None:
             ws = _ws(self.search_workspace_size(nq, nprobe, k, rerank_k), q.device)
@@ -228,7 +233,9 @@ class Index:
             out = (torch.empty((nq, k), dtype=torch.int64, device=q.device),
                    torch.empty((nq, k), dtype=torch.float32, device=q.device))
         ids, d = out
-        _check(load().erq_search(self.h, _ptr(q, torch.float32, "q"), nq, nprobe, k, rerank_k, _ptr(ids), _ptr(d),
+        _check(load().erq_search(self.h, _ptr(q, torch.float32, "q"), nq, nprobe, k, rerank_k,
+                                 _ptr(nprobe_q, torch.int32, "nprobe_q"), _ptr(k_q, torch.int32, "k_q"),
+                                 _ptr(rerank_q, torch.int32, "rerank_q"), _ptr(ids), _ptr(d),
                                  _ptr(ws), ws.numel(), _stream()))
         return ids, d
 

@@ -3,15 +3,18 @@ resident in HBM, and HIP-graph capture of the whole query path.
 
 A request is a block of queries with its own k, nprobe and re-rank depth
 (Sec. 2.1 asks for the K nearest neighbours of each query; Sec. 4.1 probes
-nprobe lists).  The server keeps `slots` batches in flight, each on its own
-stream with a workspace allocated once, sized for `max_batch` queries at the
-largest (nprobe, k, rerank_k) the server accepts; the number of slots is
-capped by a memory budget (admission by memory).  Whenever a slot is free,
-the queued requests that share the (k, nprobe, rerank_k) of the oldest one are
-packed into it, up to `max_batch` queries, and the batch is launched; batches
-on different slots overlap on the device.  Results of a query do not depend
-on the batch it rides in: every step of the path (rotation, probe, int8
-query, scan, selection, re-rank) is computed per query.
+nprobe lists).  The server keeps up to `slots` batches in flight, each on its
+own stream.  Admission is by memory: every batch takes its search workspace,
+sized exactly for its query count and its largest (nprobe, k, rerank_k), from
+one device pool of `mem_budget` bytes, and a batch is launched only when a
+stream is free and the pool has room for it.  Whenever that holds, queued
+requests are packed in arrival order, whatever their (k, nprobe, rerank_k),
+while the batch stays within `max_batch` queries and its workspace fits the
+pool's largest free block; each query carries its own values into the batch
+(erq_search's per-query arrays).  Batches on different streams overlap on the
+device.  Results of a query do not depend on the batch it rides in: every step
+of the path (rotation, probe, int8 query, scan, selection, re-rank) is
+computed per query, and the selection is the exact top-k by (estimate, id).
 
 Every step runs in the library's kernels (`erq.Index.search`); this module
 only moves tensors and events.
@@ -83,98 +86,170 @@ class Request:
         return (self.k, self.nprobe, self.rerank_k)
 
 
+class _Pool:
+    """First-fit allocator of 256-byte aligned blocks inside one device buffer."""
+
+    def __init__(self, nbytes: int, device):
+        self.size = int(nbytes)
+        self.buf = torch.empty(self.size, dtype=torch.uint8, device=device)
+        self.free = [(0, self.size)]                 # (offset, bytes), sorted, coalesced
+
+    def largest(self) -> int:
+        return max((n for _, n in self.free), default=0)
+
+    def alloc(self, nbytes: int):
+        n = (int(nbytes) + 255) & ~255
+        for i, (o, m) in enumerate(self.free):
+            if m >= n:
+                self.free[i:i + 1] = [(o + n, m - n)] if m > n else []
+                return o, n
+        return None
+
+    def release(self, o: int, n: int):
+        self.free.append((o, n))
+        self.free.sort()
+        out = []
+        for fo, fn in self.free:
+            if out and out[-1][0] + out[-1][1] == fo:
+                out[-1] = (out[-1][0], out[-1][1] + fn)
+            else:
+                out.append((fo, fn))
+        self.free = out
+
+
 @dataclass
 class _Slot:
     stream: torch.cuda.Stream
-    ws: torch.Tensor
-    qbuf: torch.Tensor
+    qbuf: torch.Tensor                     # max_batch x dp queries of the batch
+    pdev: torch.Tensor                     # 3 x max_batch per-query (nprobe, k, rerank_k)
+    phost: torch.Tensor                    # pinned staging of pdev
     event: torch.cuda.Event = field(default_factory=torch.cuda.Event)
     reqs: list = field(default_factory=list)
+    block: tuple | None = None             # the batch's workspace in the pool
     busy: bool = False
 
 
 class Server:
-    """Continuous batching over `slots` streams (see the module docstring)."""
+    """Continuous batching with admission by memory (see the module docstring)."""
 
     def __init__(self, index: erq.Index, max_batch: int = 1024, max_nprobe: int = 128, max_k: int = 32,
-                 max_rerank: int = 32, slots: int = 4, mem_budget: int = 8 << 30):
+                 max_rerank: int = 32, slots: int = 4, mem_budget: int = 1 << 30):
         dev = torch.device("cuda", torch.cuda.current_device())
         self.index, self.max_batch = index, max_batch
         self.limits = (max_k, max_nprobe, max_rerank)
-        per_slot = index.search_workspace_size(max_batch, max_nprobe, max_k, max_rerank)
-        per_slot += max_batch * (index.dp * 4 + max_k * 12)
-        self.slots_admitted = int(max(1, min(slots, mem_budget // max(per_slot, 1))))
+        free, _ = torch.cuda.mem_get_info(dev)
+        self.pool = _Pool(min(int(mem_budget), int(free * 0.8)), dev)
+        full = index.search_workspace_size(max_batch, max_nprobe, max_k, max_rerank)
+        # streams that a pool of this size can keep busy with full-size batches (at least one)
+        self.slots_admitted = int(max(1, min(slots, self.pool.size // max(full, 1))))
         self.slots = []
-        for _ in range(self.slots_admitted):
+        for _ in range(max(1, slots)):
             self.slots.append(_Slot(
                 stream=torch.cuda.Stream(device=dev),
-                ws=torch.empty(index.search_workspace_size(max_batch, max_nprobe, max_k, max_rerank),
-                               dtype=torch.uint8, device=dev),
-                qbuf=torch.empty((max_batch, index.dp), dtype=torch.float32, device=dev)))
+                qbuf=torch.empty((max_batch, index.dp), dtype=torch.float32, device=dev),
+                pdev=torch.empty((3, max_batch), dtype=torch.int32, device=dev),
+                phost=torch.empty((3, max_batch), dtype=torch.int32).pin_memory()))
         self.queue: deque[Request] = deque()
         self.t0 = time.perf_counter()
+        self.batches = 0
+        self.mixed_batches = 0                 # batches whose requests differ in (k, nprobe, rerank_k)
 
     def now(self) -> float:
         return time.perf_counter() - self.t0
+
+    def _need(self, m: int, np_: int, k: int, rr: int) -> int:
+        return self.index.search_workspace_size(m, np_, k, rr)
 
     def submit(self, req: Request):
         k, nprobe, rr = req.key
         if k > self.limits[0] or nprobe > self.limits[1] or rr > self.limits[2]:
             raise ValueError("request exceeds the server's limits (k, nprobe, rerank_k)")
+        if rr and rr < k:
+            raise ValueError("a re-rank depth must be 0 or at least k")
         if req.q.shape[0] > self.max_batch:
             raise ValueError("request larger than max_batch")
+        if self._need(req.q.shape[0], nprobe, k, rr) > self.pool.size:
+            raise ValueError("request needs more workspace than the server's memory budget")
         self.queue.append(req)
 
-    def _launch(self, slot: _Slot):
-        head = self.queue[0]
-        key, batch, m = head.key, [], 0
+    def _launch(self, slot: _Slot) -> bool:
+        """Packs queued requests (arrival order, any keys) into one batch whose
+        workspace fits the pool's largest free block; False if even the oldest
+        request does not fit now."""
+        room = self.pool.largest()
+        batch, m, mx = [], 0, (0, 0, 0)
         keep = deque()
         while self.queue:
             r = self.queue.popleft()
-            if r.key == key and m + r.q.shape[0] <= self.max_batch:
+            k, np_, rr = r.key
+            nmx = (max(mx[0], np_), max(mx[1], k), max(mx[2], rr))
+            if m + r.q.shape[0] <= self.max_batch and self._need(m + r.q.shape[0], *nmx) <= room:
                 batch.append(r)
                 m += r.q.shape[0]
+                mx = nmx
             else:
                 keep.append(r)
         self.queue = keep
-        k, nprobe, rr = key
+        if not batch:
+            return False
+        nprobe, k, rr = mx
+        block = self.pool.alloc(self._need(m, nprobe, k, rr))
+        assert block is not None
+        o, nb = block
+        ph = slot.phost.numpy()
+        row = 0
+        for r in batch:
+            c = r.q.shape[0]
+            ph[0, row:row + c] = r.nprobe
+            ph[1, row:row + c] = r.k
+            ph[2, row:row + c] = r.rerank_k
+            row += c
         # the queries were written on the submitter's stream
         slot.stream.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(slot.stream):
-            o = 0
+            slot.pdev[:, :m].copy_(slot.phost[:, :m], non_blocking=True)
+            o2 = 0
             for r in batch:
-                slot.qbuf[o:o + r.q.shape[0]].copy_(r.q, non_blocking=True)
-                o += r.q.shape[0]
+                slot.qbuf[o2:o2 + r.q.shape[0]].copy_(r.q, non_blocking=True)
+                o2 += r.q.shape[0]
             # outputs come from torch's caching allocator (no device allocation
-            # once warm); the workspace and query buffer are the slot's own
-            out = (torch.empty((m, k), dtype=torch.int64, device=slot.ws.device),
-                   torch.empty((m, k), dtype=torch.float32, device=slot.ws.device))
-            self.index.search(slot.qbuf[:m], nprobe, k, rr, ws=slot.ws, out=out)
+            # once warm); the workspace is the batch's block of the pool
+            out = (torch.empty((m, k), dtype=torch.int64, device=slot.qbuf.device),
+                   torch.empty((m, k), dtype=torch.float32, device=slot.qbuf.device))
+            pd = slot.pdev[:, :m]
+            self.index.search(slot.qbuf[:m], nprobe, k, rr, ws=self.pool.buf[o:o + nb], out=out,
+                              nprobe_q=pd[0], k_q=pd[1], rerank_q=pd[2])
             slot.event.record(slot.stream)
         slot.reqs = [(r, out) for r in batch]
         slot.offsets = np.cumsum([0] + [r.q.shape[0] for r in batch])
+        slot.block = block
         slot.busy = True
+        self.batches += 1
+        self.mixed_batches += len(set(r.key for r in batch)) > 1
+        return True
 
     def _retire(self, slot: _Slot):
         t = self.now()
         cur = torch.cuda.current_stream()
         for i, (r, out) in enumerate(slot.reqs):
-            if i == 0 or out is not slot.reqs[i - 1][1]:
+            if i == 0:
                 out[0].record_stream(cur)
                 out[1].record_stream(cur)
             a, b = slot.offsets[i], slot.offsets[i + 1]
-            r.ids, r.dist, r.done = out[0][a:b], out[1][a:b], t
-        slot.reqs, slot.busy = [], False
+            r.ids, r.dist, r.done = out[0][a:b, :r.k], out[1][a:b, :r.k], t
+        self.pool.release(*slot.block)
+        slot.reqs, slot.block, slot.busy = [], None, False
 
     def step(self) -> int:
-        """Retires finished batches and launches queued work on free slots;
-        returns the number of batches in flight."""
+        """Retires finished batches and launches queued work on free streams
+        while the pool has room; returns the number of batches in flight."""
         for s in self.slots:
             if s.busy and s.event.query():
                 self._retire(s)
         for s in self.slots:
             if not s.busy and self.queue:
-                self._launch(s)
+                if not self._launch(s):
+                    break
         return sum(s.busy for s in self.slots)
 
     def drain(self):

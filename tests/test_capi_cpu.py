@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
     for name in _declared():
         assert hasattr(lib, name), name
     assert set(_declared()) == set(erq.SIGNATURES), "binding and header disagree"
-    assert lib.erq_version() == 100
+    assert lib.erq_version() == 200
 
 
 def test_argument_validation_without_device_work():
@@ -45,7 +45,7 @@ def test_argument_validation_without_device_work():
     # dp above the quantiser's LDS window
     assert lib.erq_quantize(nul, 0, 4096, 4, nul, nul, nul, nul, nul, nul) == erq.ERQ_EUNSUPPORTED
     # bad precision
-    assert lib.erq_rotate(nul, 0, 64, nul, 2, nul, nul) == erq.ERQ_EUNSUPPORTED
+    assert lib.erq_rotate(nul, 0, 64, nul, 3, nul, nul) == erq.ERQ_EUNSUPPORTED
     # nprobe larger than nlist
     assert lib.erq_coarse_probe(nul, 0, nul, 4, 64, 5, nul, nul, nul, 0, nul) == erq.ERQ_EUNSUPPORTED
     # null index

@@ -24,7 +24,7 @@ import torch
 
 import oracle
 from paper_2409_09913_amd import erq, ivf, serve, synth
-from parity_util import compare_topk, term_scale
+from parity_util import CandTerms, compare_topk
 
 pytestmark = pytest.mark.gpu
 
@@ -53,8 +53,8 @@ def _import(off, ids, codes, fa, fr, crot, dp, B):
 
 def _check_sample(gi, ge, off, ids, codes, fa, fr, crot, qrot, probes, B, kk, sample):
     oi, oe = oracle.search(off, ids, codes, fa, fr, crot, qrot[sample], probes[sample], B, kk, est_mode=0)
-    scale = term_scale(codes, fa, fr, crot, qrot[sample], off, ids, None, probes[sample], B)
-    compare_topk(gi[sample], ge[sample], oi, oe, scale)
+    compare_topk(gi[sample], ge[sample], oi, oe, CandTerms(off, ids, codes, fa, fr, crot, qrot[sample],
+                                                           probes[sample], B))
 
 
 def test_embed768_full_size_sampled():

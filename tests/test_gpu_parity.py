@@ -15,7 +15,7 @@ import torch
 
 import oracle
 from paper_2409_09913_amd import erq, synth
-from parity_util import compare_topk as _compare_topk, term_scale as _term_scale
+from parity_util import CandTerms, compare_topk as _compare_topk
 
 pytestmark = pytest.mark.gpu
 
@@ -161,8 +161,7 @@ def _scan_case(n, nl, dp, B, nq, nprobe, kk, seed, sizes=None, empty_lists=0, pa
     torch.cuda.synchronize()
     gi, ge = gi.cpu().numpy(), ge.cpu().numpy()
     oi, oe = oracle.search(off, ids, codes, fa, fr, crot, qrot, probes, B, kk, est_mode=0)
-    scale = _term_scale(codes, fa, fr, crot, qrot, off, ids, None, probes, B)
-    _compare_topk(gi, ge, oi, oe, scale)
+    _compare_topk(gi, ge, oi, oe, CandTerms(off, ids, codes, fa, fr, crot, qrot, probes, B))
     ix.close()
     return gi, oi
 
@@ -170,21 +169,18 @@ def _scan_case(n, nl, dp, B, nq, nprobe, kk, seed, sizes=None, empty_lists=0, pa
 @pytest.mark.parametrize("B", [1, 2, 3, 4, 5, 6, 7, 8])
 def test_scan_parity_bits(B):
     say("scan B", B)
-    gi, oi = _scan_case(n=6000, nl=24, dp=128, B=B, nq=70, nprobe=6, kk=10, seed=B)
-    assert (gi == oi).mean() > 0.99
+    _scan_case(n=6000, nl=24, dp=128, B=B, nq=70, nprobe=6, kk=10, seed=B)
 
 
-@pytest.mark.parametrize("kk", [1, 10, 16, 17, 32])
+@pytest.mark.parametrize("kk", [1, 10, 16, 17, 32, 33, 64, 100, 257, 1000, 1024])
 def test_scan_parity_kk(kk):
     say("scan kk", kk)
     _scan_case(n=8000, nl=16, dp=192, B=4, nq=50, nprobe=5, kk=kk, seed=100 + kk)
 
 
-@pytest.mark.parametrize("kk", [33, 64])
-def test_scan_rejects_kk_above_32(kk):
-    """kk > 32 is switched off: a run of the 64-entry register-list kernel
-    (the only one that spills to scratch) ended in a GPU memory fault whose
-    cause was not found; the call must fail before any launch."""
+@pytest.mark.parametrize("kk", [0, 1025])
+def test_scan_rejects_kk_out_of_range(kk):
+    """kk outside [1, 1024] fails before any launch."""
     say("scan kk rejected", kk)
     dp, nl, n = 128, 4, 200
     off, ids, codes, fa, fr, crot = synth.random_index(n, nl, dp, 4, seed=1)
@@ -193,7 +189,7 @@ def test_scan_rejects_kk_above_32(kk):
     ix.import_(dev(off), dev(ids), dev(codes), dev(fa), dev(fr), dev(np.zeros((nl, dp), np.float32)), dev(crot))
     with pytest.raises(erq.ErqError) as e:
         ix.scan(dev(synth.random_rotated(3, dp, seed=3)), dev(synth.random_probes(3, nl, 2, seed=4)), kk)
-    assert e.value.code == erq.ERQ_EUNSUPPORTED
+    assert e.value.code in (erq.ERQ_EUNSUPPORTED, erq.ERQ_EINVAL)
     ix.close()
 
 
@@ -214,14 +210,19 @@ def test_scan_edge_cases():
     assert (gi == -1).any()
 
 
-@pytest.mark.parametrize("kk", [16, 32])
-def test_scan_exact_ties_by_id(kk):
+@pytest.mark.parametrize("kk,sizes", [(16, (300, 500, 40)), (32, (300, 500, 40)), (100, (300, 500, 40)),
+                                      (10, (9000, 5000, 40)), (32, (9000, 5000, 40)), (100, (9000, 5000, 40)),
+                                      (1000, (9000, 5000, 40))])
+def test_scan_exact_ties_by_id(kk, sizes):
     """Every member of a list is a copy of one code row with the same factors,
     so all its estimates tie exactly (in FP32 and FP64): the top-kk must take
-    the smallest ids of a tied group, in id order (reading C-16)."""
-    say("scan exact ties kk", kk)
+    the smallest ids of a tied group, in id order (reading C-16).  With lists
+    of 9000 and 5000 tied members no bound can shrink a query's candidates
+    below its buffer's 4096 entries, so the exact fallback runs (its pair
+    count is read back)."""
+    say("scan exact ties kk", kk, "sizes", sizes)
     dp, B, nl = 64, 4, 3
-    sizes = np.array([300, 500, 40])
+    sizes = np.array(sizes)
     off, ids, codes, fa, fr, crot = synth.random_index(int(sizes.sum()), nl, dp, B, seed=40 + kk, sizes=sizes)
     for l in range(nl):
         lo, hi = off[l], off[l + 1]
@@ -233,13 +234,25 @@ def test_scan_exact_ties_by_id(kk):
     P = synth.haar_orthogonal(dp, seed=2).astype(np.float32)
     ix = erq.Index(dp, B, nl, dev(P))
     ix.import_(dev(off), dev(ids), dev(codes), dev(fa), dev(fr), dev(np.zeros((nl, dp), np.float32)), dev(crot))
-    gi, ge = ix.scan(dev(qrot), dev(probes), kk)
-    torch.cuda.synchronize()
+    erq.profile_enable(2)
+    erq.profile_read("scan_redo_pairs", reset=True)
+    try:
+        gi, ge = ix.scan(dev(qrot), dev(probes), kk)
+        torch.cuda.synchronize()
+        redo, _ = erq.profile_read("scan_redo_pairs", reset=True)
+    finally:
+        erq.profile_read("scan", reset=True)
+        erq.profile_enable(False)
     gi, ge = gi.cpu().numpy(), ge.cpu().numpy()
     oi, oe = oracle.search(off, ids, codes, fa, fr, crot, qrot, probes, B, kk, est_mode=0)
     np.testing.assert_array_equal(gi, oi)
-    scale = _term_scale(codes, fa, fr, crot, qrot, off, ids, None, probes, B)
-    _compare_topk(gi, ge, oi, oe, scale)
+    _compare_topk(gi, ge, oi, oe, CandTerms(off, ids, codes, fa, fr, crot, qrot, probes, B))
+    say("  pairs rescanned by the exact fallback", redo)
+    # the fallback must have run when some query has more than 4096
+    # candidates at or below its kk-th estimate (a tied group no bound splits)
+    _, all_e = oracle.search(off, ids, codes, fa, fr, crot, qrot, probes, B, int(sizes.sum()), est_mode=0)
+    if any((all_e[i] <= oe[i][min(kk, int(sizes.sum())) - 1]).sum() > 4096 for i in range(len(qrot))):
+        assert redo > 0
     ix.close()
 
 
@@ -338,8 +351,32 @@ def test_rerank_parity():
     gi, gd = gi.cpu().numpy(), gd.cpu().numpy()
     oi, od = oracle.rerank(x, q, cand, k)
     np.testing.assert_allclose(gd, od, rtol=1e-5)
-    assert (gi == oi).mean() > 0.999
+    _same_up_to_exact_ties(gi, gd, oi, od, x, q)
+    # ids outside [0, n) count as missing
+    bad = cand.copy()
+    bad[:, 1] = n
+    bad[:, 2] = n + 12345
+    gi2, gd2 = ix.rerank(dev(q), dev(bad), k)
+    bad2 = bad.copy()
+    bad2[bad2 >= n] = -1
+    oi2, od2 = oracle.rerank(x, q, bad2, k)
+    np.testing.assert_allclose(gd2.cpu().numpy(), od2, rtol=1e-5)
+    _same_up_to_exact_ties(gi2.cpu().numpy(), gd2.cpu().numpy(), oi2, od2, x, q)
     ix.close()
+
+
+def _same_up_to_exact_ties(gi, gd, oi, od, x, q, rel=1e-5):
+    """Re-ranked ids equal the oracle's except where two exact FP64 distances
+    lie within the FP32 rounding of each other (either order is correct)."""
+    for i in range(gi.shape[0]):
+        if np.array_equal(gi[i], oi[i]):
+            continue
+        kth = od[i][-1]
+        for j in set(gi[i].tolist()) ^ set(oi[i].tolist()):
+            d = float(((x[j].astype(np.float64) - q[i].astype(np.float64)) ** 2).sum())
+            assert abs(d - kth) <= rel * kth, (i, j, d, kth)
+        # inside the list only equal-distance neighbours may swap
+        np.testing.assert_allclose(gd[i], od[i], rtol=rel)
 
 
 # ---------------------------------------------------------------------------

@@ -86,6 +86,8 @@ def test_server_alone_equals_mixed(built):
         srv.submit(r)
     srv.drain()
     torch.cuda.synchronize()
+    say("  %d batches, %d with mixed (k, nprobe, rerank_k)" % (srv.batches, srv.mixed_batches))
+    assert srv.mixed_batches > 0
     for r in reqs:
         assert r.ids is not None and r.ids.shape == (r.q.shape[0], r.k)
         for j in range(r.q.shape[0]):
@@ -95,11 +97,25 @@ def test_server_alone_equals_mixed(built):
 
 
 def test_server_admission_by_memory(built):
+    """Batches take their workspace from a pool of the memory budget: with
+    room for 2.5 full-size batches, at most 2 full-size batches are in flight
+    at once, and every request still completes with its alone result."""
     ix, q = built
     per = ix.search_workspace_size(512, 64, 10, 20)
     srv = serve.Server(ix, max_batch=512, max_nprobe=64, max_k=10, max_rerank=20, slots=8,
                        mem_budget=int(2.5 * per))
     assert srv.slots_admitted == 2
+    reqs = [serve.Request(i, q[(i * 97) % 128:(i * 97) % 128 + 512], 10, 64, 20) for i in range(6)]
+    for r in reqs:
+        srv.submit(r)
+    peak = 0
+    while srv.queue or any(s.busy for s in srv.slots):
+        peak = max(peak, srv.step())
+    torch.cuda.synchronize()
+    assert peak <= 2
+    for r in reqs[:2]:
+        ai, ad = ix.search(r.q.contiguous(), r.nprobe, r.k, r.rerank_k)
+        _same(r.ids, r.dist, ai, ad, f"request {r.rid}")
     with pytest.raises(ValueError):
         srv.submit(serve.Request(0, q[:4], 11, 16, 0))
     with pytest.raises(ValueError):
