@@ -203,6 +203,24 @@ int erq_search(erq_index idx, const float* q, int64_t nq, int32_t nprobe, int32_
                void* workspace, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------ */
+/* erq_search without a workspace argument, for callers that cannot         */
+/* allocate device memory (code under HIP graph capture, tight serving      */
+/* loops, harnesses that forbid hipMalloc).  Same arguments, checks and     */
+/* results as erq_search; the workspace is the library's own static device  */
+/* scratch of 64 MiB (erq_static_scratch_bytes), one copy per GPU, held from */
+/* the library's load until the process ends; its address is looked up on   */
+/* the first call on each device.  The call makes no allocation.  Calls     */
+/* whose workspace (erq_search_workspace_size) exceeds the scratch return   */
+/* ERQ_ENOMEM before any device work.  Every call on a GPU uses that GPU's   */
+/* one scratch: calls that may overlap on the same GPU (other streams, other */
+/* host threads) race and must be serialised by the caller.                */
+/* ------------------------------------------------------------------------ */
+int erq_search_static(erq_index idx, const float* q, int64_t nq, int32_t nprobe, int32_t k,
+                      int32_t rerank_k, const int32_t* nprobe_q, const int32_t* k_q,
+                      const int32_t* rerank_q, int64_t* out_ids, float* out_dist, void* stream);
+int erq_static_scratch_bytes(size_t* bytes);
+
+/* ------------------------------------------------------------------------ */
 /* Scan schedule (tuning, not part of the method).  Four knobs of the        */
 /* bounded scan; 0 selects the built-in rule:                                */
 /*   nqt    query tiles of 32 per work item, 1 or 2 (2 needs dp <= 1536;     */

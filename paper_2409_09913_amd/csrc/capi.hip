@@ -681,6 +681,61 @@ static int search_run(Index* ix, const float* q, int64_t nq, int nprobe, int k, 
     return ERQ_OK;
 }
 
+// ---- erq_search_static: the search with the library's own device scratch ----
+// A file-scope device array, one copy per GPU, used as the search workspace
+// by callers that cannot allocate.  Host code never passes the array's name
+// to a kernel: its device address is looked up once per device with
+// hipGetSymbolAddress and kept in g_scratch_ptr.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// device address of `scratch` on the current device (looked up on the first call there)
+int scratch_ptr(void** out)
+{
+    int d = 0;
+    ERQ_HIP(hipGetDevice(&d));
+    if (d < 0 || d >= kMaxDevices) return fail(ERQ_EUNSUPPORTED, "erq_search_static: device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[d]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(ERQ_EDEVICE, std::string("erq_search_static: hipGetSymbolAddress: ") + hipGetErrorString(e));
+        g_scratch_ptr[d] = p;
+    }
+    *out = g_scratch_ptr[d];
+    return ERQ_OK;
+}
+}  // namespace
+
+int erq_search_static(erq_index ix, const float* q, int64_t nq, int32_t nprobe, int32_t k, int32_t rerank_k,
+                      const int32_t* nprobe_q, const int32_t* k_q, const int32_t* rerank_q, int64_t* out_ids,
+                      float* out_dist, void* stream)
+{
+    if (int rc = search_check(ix, q, nq, nprobe, k, rerank_k, out_ids, out_dist, "erq_search_static")) return rc;
+    if (nq == 0) return ERQ_OK;
+    const size_t need = search_ws(ix, nq, nprobe, k, rerank_k);
+    if (need > kScratchBytes)
+        return fail(ERQ_ENOMEM, "erq_search_static: the call needs " + std::to_string(need) +
+                                    " bytes of workspace, more than the library's 64 MiB scratch");
+    void* ws = nullptr;
+    if (int rc = scratch_ptr(&ws)) return rc;
+    return search_run(ix, q, nq, nprobe, k, rerank_k, nprobe_q, k_q, rerank_q, out_ids, out_dist, ws, kScratchBytes,
+                      (hipStream_t)stream);
+}
+
+int erq_static_scratch_bytes(size_t* bytes)
+{
+    if (!bytes) return fail(ERQ_EINVAL, "erq_static_scratch_bytes: null pointer");
+    *bytes = kScratchBytes;
+    return ERQ_OK;
+}
+
 int erq_search(erq_index ix, const float* q, int64_t nq, int32_t nprobe, int32_t k, int32_t rerank_k,
                const int32_t* nprobe_q, const int32_t* k_q, const int32_t* rerank_q, int64_t* out_ids,
                float* out_dist, void* workspace, size_t ws_bytes, void* stream)

@@ -39,6 +39,8 @@ SIGNATURES = {
     "erq_rerank": (C.c_int, [_p, _p, _i64, _p, _i32, _i32, _p, _p, _p]),
     "erq_search_workspace_size": (C.c_int, [_p, _i64, _i32, _i32, _i32, C.POINTER(_sz)]),
     "erq_search": (C.c_int, [_p, _p, _i64, _i32, _i32, _i32, _p, _p, _p, _p, _p, _p, _sz, _p]),
+    "erq_search_static": (C.c_int, [_p, _p, _i64, _i32, _i32, _i32, _p, _p, _p, _p, _p, _p]),
+    "erq_static_scratch_bytes": (C.c_int, [C.POINTER(_sz)]),
     "erq_index_set_tune": (C.c_int, [_p, _i32, _i32, _i32, _i32]),
     "erq_index_get_tune": (C.c_int, [_p, C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i32)]),
     "erq_index_tune": (C.c_int, [_p, _p, _i64, _i32, _i32, _i32, _i32, _p, _p, _p, _sz, _p,
@@ -240,6 +242,20 @@ class Index:
         return ids, d
 
 
+    def search_static(self, q, nprobe: int, k: int, rerank_k: int = 0, out=None, nprobe_q=None, k_q=None,
+                      rerank_q=None):
+        """erq_search on the library's static device scratch (no workspace, no
+        allocation in the library; the outputs are allocated here unless given)."""
+        nq = q.shape[0]
+        if out is None:
+            out = (torch.empty((nq, k), dtype=torch.int64, device=q.device),
+                   torch.empty((nq, k), dtype=torch.float32, device=q.device))
+        ids, d = out
+        _check(load().erq_search_static(self.h, _ptr(q, torch.float32, "q"), nq, nprobe, k, rerank_k,
+                                        _ptr(nprobe_q, torch.int32, "nprobe_q"), _ptr(k_q, torch.int32, "k_q"),
+                                        _ptr(rerank_q, torch.int32, "rerank_q"), _ptr(ids), _ptr(d), _stream()))
+        return ids, d
+
     def set_tune(self, nqt: int = 0, pd: int = 0, round1: int = 0, round2: int = 0):
         """Scan schedule (0 = built-in rule for that knob)."""
         _check(load().erq_index_set_tune(self.h, nqt, pd, round1, round2))
@@ -263,6 +279,13 @@ class Index:
         _check(load().erq_index_tune(self.h, _ptr(q, torch.float32, "q"), nq, nprobe, k, rerank_k, reps,
                                      _ptr(out[0]), _ptr(out[1]), _ptr(ws), ws.numel(), _stream(), ch, C.byref(ms)))
         return {"nqt": ch[0], "pd": ch[1], "round1": ch[2], "round2": ch[3], "ms": ms.value}
+
+
+def static_scratch_bytes() -> int:
+    """Size of the library's static device scratch used by erq_search_static."""
+    sz = C.c_size_t()
+    _check(load().erq_static_scratch_bytes(C.byref(sz)))
+    return sz.value
 
 
 def profile_enable(on=True):
