@@ -105,11 +105,38 @@ int erq_coarse_probe(const float* q, int64_t nq, const float* centroids, int64_t
 /* ------------------------------------------------------------------------ */
 typedef struct erq_index_s* erq_index;
 
+/* The random orthogonal matrix of Sec. 3.2.1 (the codebook is fixed by P
+   alone), sampled from the seed: Haar-distributed, the Q factor of the QR
+   decomposition of a dp x dp standard-normal matrix with the signs of R's
+   diagonal folded into Q.  Normals from Philox4x32-10 (counter-based, keyed
+   by the seed) and Box-Muller; QR by Householder reflections in FP64 on the
+   host.  P_host: dp x dp FP32, row-major, HOST memory.  Deterministic in
+   (dp, seed).  No device work. */
+int erq_sample_rotation(int32_t dp, uint64_t seed, float* P_host);
+
 /* Empty index for dp-dimensional vectors, B = bits, nlist lists.  P (device,
-   dp x dp FP32) is copied. */
+   dp x dp FP32) is copied; P = NULL samples it with erq_sample_rotation(dp,
+   seed).  Synchronises `stream`. */
 int erq_index_create(int32_t dp, int32_t bits, int64_t nlist, const float* P,
-                     void* stream, erq_index* out);
+                     uint64_t seed, void* stream, erq_index* out);
+/* Frees everything the index owns.  No work that uses the index may still be
+   in flight (freeing device memory waits for the device). */
 int erq_index_destroy(erq_index idx);
+
+/* Copies the index's rotation P (dp x dp FP32, row-major) to P_out (device). */
+int erq_index_get_rotation(erq_index idx, float* P_out, void* stream);
+
+/* Writes the whole index to a file (host path): a versioned header (magic
+   "ERQIDX", version 1, dp, bits, nlist, n, tiles, scan schedule, seed),
+   then P, raw and rotated centroids, list offsets, ids, factors, scan
+   factors, packed codes and, when kept, the raw vectors, in native byte
+   order.  Synchronises `stream`. */
+int erq_index_save(erq_index idx, const char* path, void* stream);
+/* Reads a file of erq_index_save into a new index on the current device.
+   ERQ_EINVAL for a file that is not an index, whose size does not match its
+   header, or whose lists are inconsistent (checked before any device work);
+   ERQ_EUNSUPPORTED for another file version.  Synchronises `stream`. */
+int erq_index_load(const char* path, void* stream, erq_index* out);
 
 /* Fills the index from caller-made contents (no quantisation on the device):
    list_off: nlist+1 int64 offsets into the list-ordered arrays; ids: n int64

@@ -2,6 +2,7 @@
 // in which the kernels of each call are enqueued.
 #include <algorithm>
 #include <mutex>
+#include <cstdio>
 #include <cstring>
 #include <numeric>
 
@@ -238,6 +239,52 @@ int probe_impl(const float* q, int64_t nq, const float* cent, int64_t nlist, int
     return ERQ_OK;
 }
 
+// ---- index files --------------------------------------------------------------
+constexpr char kMagic[8] = {'E', 'R', 'Q', 'I', 'D', 'X', '\0', '\0'};
+constexpr uint32_t kFileVersion = 1;
+struct FileHeader {
+    char magic[8];
+    uint32_t version;
+    int32_t dp, bits, has_raw;
+    int64_t nlist, n, ntiles;
+    int32_t tune[4];
+    uint64_t seed;
+};
+
+// bytes of every array of an index file after the header, in file order
+std::vector<size_t> file_arrays(const FileHeader& h) {
+    const size_t dp = (size_t)h.dp, C = (size_t)h.nlist, n = (size_t)h.n;
+    return {sizeof(float) * dp * dp,              // P
+            sizeof(float) * C * dp,               // raw centroids
+            sizeof(float) * C * dp,               // rotated centroids
+            sizeof(int64_t) * (C + 1),            // list offsets
+            sizeof(int64_t) * n,                  // ids
+            sizeof(float2) * n,                   // (f_add, f_rescale)
+            sizeof(float2) * n,                   // scan factors
+            (size_t)4 * dp * h.bits * (size_t)h.ntiles,   // packed codes
+            h.has_raw ? sizeof(float) * n * dp : 0};      // raw vectors
+}
+
+// device <-> file through a host staging buffer, in chunks
+int dev_to_file(FILE* f, const void* d, size_t bytes, std::vector<char>& buf, hipStream_t st) {
+    for (size_t o = 0; o < bytes; o += buf.size()) {
+        const size_t m = std::min(buf.size(), bytes - o);
+        ERQ_HIP(hipMemcpyAsync(buf.data(), (const char*)d + o, m, hipMemcpyDeviceToHost, st));
+        ERQ_HIP(hipStreamSynchronize(st));
+        if (fwrite(buf.data(), 1, m, f) != m) return fail(ERQ_EINVAL, "erq_index_save: write failed");
+    }
+    return ERQ_OK;
+}
+int file_to_dev(FILE* f, void* d, size_t bytes, std::vector<char>& buf, hipStream_t st) {
+    for (size_t o = 0; o < bytes; o += buf.size()) {
+        const size_t m = std::min(buf.size(), bytes - o);
+        if (fread(buf.data(), 1, m, f) != m) return fail(ERQ_EINVAL, "erq_index_load: file is truncated");
+        ERQ_HIP(hipMemcpyAsync((char*)d + o, buf.data(), m, hipMemcpyHostToDevice, st));
+        ERQ_HIP(hipStreamSynchronize(st));
+    }
+    return ERQ_OK;
+}
+
 }  // namespace
 }  // namespace erq
 
@@ -312,18 +359,35 @@ int erq_coarse_probe(const float* q, int64_t nq, const float* centroids, int64_t
     return probe_impl(q, nq, centroids, nlist, dp, nprobe, probes, pdist, workspace, ws_bytes, (hipStream_t)stream);
 }
 
-int erq_index_create(int32_t dp, int32_t bits, int64_t nlist, const float* P, void* stream, erq_index* out)
+int erq_sample_rotation(int32_t dp, uint64_t seed, float* P_host)
+{
+    if (int rc = check_dp(dp, "erq_sample_rotation")) return rc;
+    if (!P_host) return fail(ERQ_EINVAL, "erq_sample_rotation: null pointer");
+    sample_rotation(dp, seed, P_host);
+    return ERQ_OK;
+}
+
+int erq_index_create(int32_t dp, int32_t bits, int64_t nlist, const float* P, uint64_t seed, void* stream,
+                     erq_index* out)
 {
     if (int rc = check_dp(dp, "erq_index_create")) return rc;
     if (bits < 1 || bits > 8) return fail(ERQ_EUNSUPPORTED, "erq_index_create: bits must be in [1, 8]");
     if (nlist < 1 || nlist > (1 << 24)) return fail(ERQ_EINVAL, "erq_index_create: nlist must be in [1, 2^24]");
-    if (!P || !out) return fail(ERQ_EINVAL, "erq_index_create: null pointer");
+    if (!out) return fail(ERQ_EINVAL, "erq_index_create: null pointer");
+    std::vector<float> hP;
+    if (!P) {                                       // sample P (Haar) on the host
+        hP.resize((size_t)dp * dp);
+        sample_rotation(dp, seed, hP.data());
+    }
     erq_index_s* ix = new (std::nothrow) erq_index_s();
     if (!ix) return fail(ERQ_ENOMEM, "erq_index_create: out of host memory");
     ix->dp = dp; ix->bits = bits; ix->nlist = nlist;
+    ix->seed = P ? 0 : seed;
     hipGetDevice(&ix->device);
     if (hipMalloc(&ix->P, sizeof(float) * dp * dp) != hipSuccess) { delete ix; return fail(ERQ_ENOMEM, "erq_index_create: hipMalloc failed"); }
-    hipError_t e = hipMemcpyAsync(ix->P, P, sizeof(float) * dp * dp, hipMemcpyDeviceToDevice, (hipStream_t)stream);
+    hipError_t e = P ? hipMemcpyAsync(ix->P, P, sizeof(float) * dp * dp, hipMemcpyDeviceToDevice, (hipStream_t)stream)
+                     : hipMemcpyAsync(ix->P, hP.data(), sizeof(float) * dp * dp, hipMemcpyHostToDevice,
+                                      (hipStream_t)stream);
     if (e == hipSuccess) e = hipMalloc(&ix->pt_hi, sizeof(unsigned short) * dp * dp);
     if (e == hipSuccess) e = hipMalloc(&ix->pt_lo, sizeof(unsigned short) * dp * dp);
     if (e == hipSuccess) e = launch_split_bf16_t(ix->P, dp, dp, ix->pt_hi, ix->pt_lo, (hipStream_t)stream);
@@ -333,6 +397,104 @@ int erq_index_create(int32_t dp, int32_t bits, int64_t nlist, const float* P, vo
         return fail(ERQ_EDEVICE, std::string("erq_index_create: ") + hipGetErrorString(e));
     }
     *out = ix;
+    return ERQ_OK;
+}
+
+int erq_index_save(erq_index ix, const char* path, void* stream)
+{
+    if (!ix || !path) return fail(ERQ_EINVAL, "erq_index_save: null pointer");
+    if (!ix->list_off) return fail(ERQ_EINVAL, "erq_index_save: the index is empty");
+    hipStream_t st = (hipStream_t)stream;
+    FileHeader h{};
+    std::memcpy(h.magic, kMagic, 8);
+    h.version = kFileVersion;
+    h.dp = ix->dp; h.bits = ix->bits; h.has_raw = ix->raw ? 1 : 0;
+    h.nlist = ix->nlist; h.n = ix->n; h.ntiles = ix->ntiles;
+    h.tune[0] = ix->tune_nqt; h.tune[1] = ix->tune_pd; h.tune[2] = ix->tune_round1; h.tune[3] = ix->tune_round2;
+    h.seed = ix->seed;
+    FILE* f = std::fopen(path, "wb");
+    if (!f) return fail(ERQ_EINVAL, std::string("erq_index_save: cannot open ") + path);
+    struct Closer { FILE* f; ~Closer() { if (f) std::fclose(f); } } closer{f};
+    if (fwrite(&h, sizeof(h), 1, f) != 1) return fail(ERQ_EINVAL, "erq_index_save: write failed");
+    std::vector<char> buf((size_t)64 << 20);
+    const void* src[9] = {ix->P, ix->cent, ix->cent_rot, ix->list_off, ix->ids, ix->fac, ix->sfac, ix->codes, ix->raw};
+    const std::vector<size_t> sz = file_arrays(h);
+    for (int a = 0; a < 9; ++a)
+        if (sz[a]) { if (int rc = dev_to_file(f, src[a], sz[a], buf, st)) return rc; }
+    if (std::fclose(f) != 0) { closer.f = nullptr; return fail(ERQ_EINVAL, "erq_index_save: close failed"); }
+    closer.f = nullptr;
+    return ERQ_OK;
+}
+
+int erq_index_load(const char* path, void* stream, erq_index* out)
+{
+    if (!path || !out) return fail(ERQ_EINVAL, "erq_index_load: null pointer");
+    hipStream_t st = (hipStream_t)stream;
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return fail(ERQ_EINVAL, std::string("erq_index_load: cannot open ") + path);
+    struct Closer { FILE* f; ~Closer() { std::fclose(f); } } closer{f};
+    FileHeader h{};
+    if (fread(&h, sizeof(h), 1, f) != 1 || std::memcmp(h.magic, kMagic, 8) != 0)
+        return fail(ERQ_EINVAL, "erq_index_load: not an index file");
+    if (h.version != kFileVersion) return fail(ERQ_EUNSUPPORTED, "erq_index_load: unknown file version");
+    if (h.dp < 64 || h.dp > kMaxDp || h.dp % 64 || h.bits < 1 || h.bits > 8 || h.nlist < 1 ||
+        h.nlist > (1 << 24) || h.n < 0 || h.n > (1LL << 31) - 1 || h.ntiles < 0 || (h.has_raw != 0 && h.has_raw != 1))
+        return fail(ERQ_EINVAL, "erq_index_load: bad header");
+    const std::vector<size_t> sz = file_arrays(h);
+    size_t total = sizeof(h);
+    for (size_t b : sz) total += b;
+    if (std::fseek(f, 0, SEEK_END) != 0 || (size_t)std::ftell(f) != total)
+        return fail(ERQ_EINVAL, "erq_index_load: file size does not match its header");
+    std::fseek(f, (long)sizeof(h), SEEK_SET);
+    // list offsets first (host): they fix the tiles and the list order
+    const int64_t C = h.nlist, n = h.n;
+    const int dp = h.dp;
+    std::vector<int64_t> off(C + 1);
+    {
+        size_t skip = sz[0] + sz[1] + sz[2];
+        std::fseek(f, (long)(sizeof(h) + skip), SEEK_SET);
+        if (fread(off.data(), sizeof(int64_t), C + 1, f) != (size_t)(C + 1))
+            return fail(ERQ_EINVAL, "erq_index_load: file is truncated");
+        std::fseek(f, (long)sizeof(h), SEEK_SET);
+    }
+    if (off[0] != 0 || off[C] != n) return fail(ERQ_EINVAL, "erq_index_load: bad list offsets");
+    erq_index_s* ix = new (std::nothrow) erq_index_s();
+    if (!ix) return fail(ERQ_ENOMEM, "erq_index_load: out of host memory");
+    struct Owner { erq_index_s* p; ~Owner() { if (p) erq_index_destroy(p); } } owner{ix};
+    ix->dp = dp; ix->bits = h.bits; ix->nlist = C; ix->seed = h.seed;
+    ix->tune_nqt = h.tune[0]; ix->tune_pd = h.tune[1]; ix->tune_round1 = h.tune[2]; ix->tune_round2 = h.tune[3];
+    hipGetDevice(&ix->device);
+    if (int rc = set_list_meta(ix, off, st)) return rc;
+    if (ix->ntiles != h.ntiles) return fail(ERQ_EINVAL, "erq_index_load: tile count does not match the lists");
+    ix->n = n;
+    ERQ_HIP(hipMalloc(&ix->P, sz[0]));
+    ERQ_HIP(hipMalloc(&ix->cent, sz[1]));
+    ERQ_HIP(hipMalloc(&ix->cent_rot, sz[2]));
+    ERQ_HIP(hipMalloc(&ix->ids, std::max<size_t>(sz[4], 8)));
+    ERQ_HIP(hipMalloc(&ix->fac, std::max<size_t>(sz[5], 8)));
+    ERQ_HIP(hipMalloc(&ix->sfac, std::max<size_t>(sz[6], 8)));
+    ERQ_HIP(hipMalloc(&ix->codes, std::max<size_t>(sz[7], 256)));
+    if (h.has_raw) ERQ_HIP(hipMalloc(&ix->raw, std::max<size_t>(sz[8], 4)));
+    void* dst[9] = {ix->P, ix->cent, ix->cent_rot, nullptr, ix->ids, ix->fac, ix->sfac, ix->codes, ix->raw};
+    std::vector<char> buf((size_t)64 << 20);
+    for (int a = 0; a < 9; ++a) {
+        if (a == 3) { std::fseek(f, (long)sz[3], SEEK_CUR); continue; }   // list offsets: already uploaded
+        if (sz[a]) { if (int rc = file_to_dev(f, dst[a], sz[a], buf, st)) return rc; }
+    }
+    ERQ_HIP(hipMalloc(&ix->pt_hi, sizeof(unsigned short) * dp * dp));
+    ERQ_HIP(hipMalloc(&ix->pt_lo, sizeof(unsigned short) * dp * dp));
+    ERQ_HIP(launch_split_bf16_t(ix->P, dp, dp, ix->pt_hi, ix->pt_lo, st));
+    ERQ_HIP(alloc_cent_planes(ix, st));
+    ERQ_HIP(hipStreamSynchronize(st));
+    owner.p = nullptr;
+    *out = ix;
+    return ERQ_OK;
+}
+
+int erq_index_get_rotation(erq_index ix, float* P_out, void* stream)
+{
+    if (!ix || !P_out) return fail(ERQ_EINVAL, "erq_index_get_rotation: null pointer");
+    ERQ_HIP(hipMemcpyAsync(P_out, ix->P, sizeof(float) * ix->dp * ix->dp, hipMemcpyDeviceToDevice, (hipStream_t)stream));
     return ERQ_OK;
 }
 

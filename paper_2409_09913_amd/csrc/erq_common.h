@@ -64,6 +64,7 @@ struct Index {
     int dp = 0, bits = 0;
     int64_t nlist = 0, n = 0;
     int device = 0;
+    uint64_t seed = 0;             // seed P was sampled from (0 when the caller gave P)
     float* P = nullptr;            // dp x dp
     unsigned short* pt_hi = nullptr;   // BF16 hi/lo planes of P^T (dp x dp each): the search's rotation
     unsigned short* pt_lo = nullptr;
@@ -130,6 +131,9 @@ hipError_t launch_scan_fac(const uint8_t* codes_u, const int64_t* list_off, int6
 hipError_t launch_rerank(const float* raw, int64_t n, int dp, const float* q, int64_t nq, const int64_t* cand,
                          const float* cand_est, int kc, int k, const int32_t* kc_q, const int32_t* k_q,
                          int64_t* out_ids, float* out_d, hipStream_t st);
+
+// Haar orthogonal dp x dp matrix of the seed, row-major FP32, host memory (host code)
+void sample_rotation(int dp, uint64_t seed, float* P);
 
 // list building
 hipError_t launch_residual(const float* x, const int64_t* ids, const int32_t* assign, const float* cent,

@@ -26,8 +26,12 @@ SIGNATURES = {
     "erq_quantize": (C.c_int, [_p, _i64, _i32, _i32, _p, _p, _p, _p, _p, _p]),
     "erq_probe_workspace_size": (C.c_int, [_i64, _i64, _i32, _i32, C.POINTER(_sz)]),
     "erq_coarse_probe": (C.c_int, [_p, _i64, _p, _i64, _i32, _i32, _p, _p, _p, _sz, _p]),
-    "erq_index_create": (C.c_int, [_i32, _i32, _i64, _p, _p, C.POINTER(_p)]),
+    "erq_sample_rotation": (C.c_int, [_i32, C.c_uint64, _p]),
+    "erq_index_create": (C.c_int, [_i32, _i32, _i64, _p, C.c_uint64, _p, C.POINTER(_p)]),
     "erq_index_destroy": (C.c_int, [_p]),
+    "erq_index_get_rotation": (C.c_int, [_p, _p, _p]),
+    "erq_index_save": (C.c_int, [_p, C.c_char_p, _p]),
+    "erq_index_load": (C.c_int, [C.c_char_p, _p, C.POINTER(_p)]),
     "erq_index_import": (C.c_int, [_p, _i64, _p, _p, _p, _p, _p, _p, _p, _p]),
     "erq_index_build": (C.c_int, [_p, _p, _i64, _p, _p, _i32, _i32, _p]),
     "erq_index_set_raw": (C.c_int, [_p, _p, _i64, _p]),
@@ -138,15 +142,45 @@ def coarse_probe(q, centroids, nprobe: int, with_dist: bool = False):
     return (probes, pd) if with_dist else probes
 
 
-class Index:
-    """Owner of an erq_index handle (lists, packed codes, factors, P, centroids)."""
+def sample_rotation(dp: int, seed: int):
+    """The library's Haar rotation for (dp, seed) as a host numpy array (no device work)."""
+    import numpy as np
+    out = np.empty((dp, dp), np.float32)
+    _check(load().erq_sample_rotation(dp, seed, out.ctypes.data_as(C.c_void_p)))
+    return out
 
-    def __init__(self, dp: int, bits: int, nlist: int, P):
+
+class Index:
+    """Owner of an erq_index handle (lists, packed codes, factors, P, centroids).
+    P: the dp x dp rotation (device tensor), or None to have the library
+    sample it from `seed`."""
+
+    def __init__(self, dp: int, bits: int, nlist: int, P=None, seed: int = 0, _handle=None):
         self.dp, self.bits, self.nlist = dp, bits, nlist
+        self.device = P.device if P is not None else torch.device("cuda", torch.cuda.current_device())
+        if _handle is not None:
+            self.h = _handle
+            return
         h = C.c_void_p()
-        _check(load().erq_index_create(dp, bits, nlist, _ptr(P, torch.float32, "P"), _stream(), C.byref(h)))
+        _check(load().erq_index_create(dp, bits, nlist, _ptr(P, torch.float32, "P"), seed, _stream(), C.byref(h)))
         self.h = h
-        self.device = P.device
+
+    @classmethod
+    def load_file(cls, path: str):
+        """An index read from a file of save()."""
+        h = C.c_void_p()
+        _check(load().erq_index_load(os.fsencode(path), _stream(), C.byref(h)))
+        n, dp, b, nl, cb = C.c_int64(), C.c_int32(), C.c_int32(), C.c_int64(), C.c_int64()
+        _check(load().erq_index_info(h, C.byref(n), C.byref(dp), C.byref(b), C.byref(nl), C.byref(cb)))
+        return cls(dp.value, b.value, nl.value, _handle=h)
+
+    def save(self, path: str):
+        _check(load().erq_index_save(self.h, os.fsencode(path), _stream()))
+
+    def rotation(self):
+        P = torch.empty((self.dp, self.dp), dtype=torch.float32, device=self.device)
+        _check(load().erq_index_get_rotation(self.h, _ptr(P), _stream()))
+        return P
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:

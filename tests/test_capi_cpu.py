@@ -52,8 +52,11 @@ def test_argument_validation_without_device_work():
     assert lib.erq_scan(nul, nul, 0, nul, 1, 1, nul, nul, nul, 0, nul) == erq.ERQ_EINVAL
     assert lib.erq_rerank(nul, nul, 0, nul, 1, 1, nul, nul, nul) == erq.ERQ_EINVAL
     h = C.c_void_p()
-    assert lib.erq_index_create(64, 0, 4, nul, nul, C.byref(h)) == erq.ERQ_EUNSUPPORTED
-    assert lib.erq_index_create(64, 4, 0, nul, nul, C.byref(h)) == erq.ERQ_EINVAL
+    assert lib.erq_index_create(64, 0, 4, nul, 0, nul, C.byref(h)) == erq.ERQ_EUNSUPPORTED
+    assert lib.erq_index_create(64, 4, 0, nul, 0, nul, C.byref(h)) == erq.ERQ_EINVAL
+    # the no-allocation search checks its arguments like erq_search
+    assert lib.erq_search_static(nul, nul, 1, 4, 10, 0, nul, nul, nul, nul, nul, nul) == erq.ERQ_EINVAL
+    assert lib.erq_sample_rotation(65, 1, nul) == erq.ERQ_ESHAPE
     sz = C.c_size_t()
     assert lib.erq_probe_workspace_size(10, 0, 64, 1, C.byref(sz)) == erq.ERQ_EINVAL
     assert lib.erq_probe_workspace_size(10, 16, 100, 4, C.byref(sz)) == erq.ERQ_EINVAL   # dp not a multiple of 64
