@@ -83,7 +83,7 @@ def main():
         return
 
     import torch
-    from paper_2409_09913_amd import erq, ivf, serve, synth
+    from paper_2409_09913_amd import erq, serve, synth
 
     dev = torch.device("cuda:0")
     erq.load()
@@ -98,7 +98,7 @@ def main():
     log("data ready %.1fs" % (time.time() - t0))
 
     log("k-means", args.nlist, "lists,", args.kmeans_iters, "iterations")
-    cent, assign = ivf.kmeans(x, args.nlist, iters=args.kmeans_iters)
+    cent, assign = erq.kmeans(x, args.nlist, iters=args.kmeans_iters)
     torch.cuda.synchronize()
     sizes = torch.bincount(assign.long(), minlength=args.nlist).cpu().numpy()
     log("k-means done %.1fs; list sizes min %d mean %.1f max %d" % (time.time() - t0, sizes.min(), sizes.mean(),

@@ -150,9 +150,25 @@ int erq_index_import(erq_index idx, int64_t n, const int64_t* list_off, const in
                      const uint8_t* codes, const float* f_add, const float* f_rescale,
                      const float* centroids, const float* centroids_rot, void* stream);
 
+/* k-means for the IVF lists (Sec. 4.1 partitions the data with KMeans),
+   Lloyd's algorithm on the device.  Readings of what the paper leaves open:
+   the initial centroids are nlist distinct rows picked by Floyd's sampling
+   with Philox4x32-10 numbers of the seed (in ascending row order); each of
+   `iters` rounds assigns every row to its nearest centroid (the coarse
+   probe's distances, ties to the lower id) and replaces each centroid by its
+   list's mean (FP64 sums in ascending row order); an empty list keeps its
+   centroid.  x: n x dp; centroids: nlist x dp output; assign: n int32 output
+   (the nearest final centroid of each row) or NULL.  Every sum has a fixed
+   order, so a seed gives the same result on every run.  1 <= nlist <= n,
+   iters in [0, 1000].  Allocates its scratch; synchronises `stream`. */
+int erq_kmeans(const float* x, int64_t n, int32_t dp, int64_t nlist, int32_t iters, uint64_t seed,
+               float* centroids, int32_t* assign, void* stream);
+
 /* Index phase on the device (Sec. 3.4 with IVF centring, Sec. 4.1, 5.1):
-   x: n x dp raw vectors (row i has id i); centroids: nlist x dp; assign: n
-   list ids, or NULL to assign every row to its nearest centroid.  Per row:
+   x: n x dp raw vectors (row i has id i); centroids: nlist x dp, or NULL to
+   build the lists with erq_kmeans (10 rounds, seeded from the index's
+   seed); assign: n list ids, or NULL to assign every row to its nearest
+   centroid (must be NULL when centroids is).  Per row:
    r = x - c, ||r||^2, r' = P^T r (precision as in erq_rotate), Algorithm 1,
    factors, packing.  Members are stored list by list, ids ascending
    within each list, so the same input always gives the same index.

@@ -6,7 +6,7 @@
 #include <cstring>
 #include <numeric>
 
-#include <hipcub/hipcub.hpp>
+#include <unordered_set>
 
 #include "erq_common.h"
 
@@ -149,6 +149,7 @@ __global__ void query_params_kernel(int64_t nq, int nprobe, int kmax, int rrmax,
 }
 
 inline unsigned blocks(int64_t n, int th = 256) { return (unsigned)((n + th - 1) / th); }
+constexpr int kBuildKmeansIters = 10;          // Lloyd rounds of erq_index_build without centroids
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 int check_dp(int dp, const char* who) {
@@ -236,6 +237,94 @@ int probe_impl(const float* q, int64_t nq, const float* cent, int64_t nlist, int
     ERQ_HIP(launch_sqdist_pre(uqh, uql, nq, uch, ucl, nlist, dp, uqn, ucn, D, st));
     ERQ_HIP(launch_row_topk(D, nq, nlist, nprobe, probes, pdist, st));
     prof_end(pr, st);
+    return ERQ_OK;
+}
+
+// ---- k-means (Sec. 4.1 builds the IVF lists with KMeans) -------------------------
+// nearest centroid of every row (the probe with nprobe = 1: ties to the lower
+// centroid id), in row chunks that keep the n x C distances small
+int assign_rows(const float* x, int64_t n, int dp, const float* cent, int64_t C, int32_t* asg, hipStream_t st)
+{
+    if (n <= 0) return ERQ_OK;
+    const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(n, (int64_t)(1LL << 28) / C));
+    void* pws = nullptr;
+    const size_t pb = probe_ws(chunk, C, dp);
+    ERQ_HIP(hipMalloc(&pws, pb));
+    struct Free { void* p; ~Free() { hipFree(p); } } fr{pws};
+    for (int64_t r0 = 0; r0 < n; r0 += chunk) {
+        const int64_t m = std::min(chunk, n - r0);
+        if (int rc = probe_impl(x + r0 * dp, m, cent, C, dp, 1, asg + r0, nullptr, pws, pb, st)) return rc;
+    }
+    return ERQ_OK;
+}
+
+// per-list counts of an assignment -> host list offsets (ERQ_EINVAL for ids outside [0, C))
+int list_offsets(const int32_t* asg, int64_t n, int64_t C, std::vector<int64_t>& off, hipStream_t st)
+{
+    int32_t* aux = nullptr;
+    ERQ_HIP(hipMalloc(&aux, sizeof(int32_t) * (C + 1)));
+    struct Free { void* p; ~Free() { hipFree(p); } } fr{aux};
+    hipLaunchKernelGGL(fill_i32, dim3(blocks(C + 1)), dim3(256), 0, st, aux, C + 1, 0);
+    ERQ_HIP(launch_count(asg, n, C, aux, aux + C, st));
+    std::vector<int32_t> hc(C + 1);
+    ERQ_HIP(hipMemcpyAsync(hc.data(), aux, sizeof(int32_t) * (C + 1), hipMemcpyDeviceToHost, st));
+    ERQ_HIP(hipStreamSynchronize(st));
+    if (hc[C] != 0) return fail(ERQ_EINVAL, "assignment outside [0, nlist)");
+    off.assign(C + 1, 0);
+    for (int64_t l = 0; l < C; ++l) off[l + 1] = off[l] + hc[l];
+    return ERQ_OK;
+}
+
+// Lloyd's algorithm.  Readings: the initial centroids are C distinct rows
+// chosen by Floyd's sampling with Philox random numbers of the seed (taken in
+// ascending row order); `iters` rounds of assignment then per-list means; an
+// empty list keeps its centroid; the returned assignment is to the final
+// centroids.  Every sum has a fixed order, so a seed gives the same lists on
+// every run.
+int kmeans_impl(const float* x, int64_t n, int dp, int64_t C, int iters, uint64_t seed, float* cent, int32_t* asg_out,
+                hipStream_t st)
+{
+    if (n < C) return fail(ERQ_EINVAL, "k-means: fewer rows than lists");
+    std::unordered_set<int64_t> pick;
+    pick.reserve((size_t)C * 2);
+    for (int64_t j = n - C; j < n; ++j) {                 // Floyd: C distinct values of [0, n)
+        const int64_t t = (int64_t)(philox_u64(seed, 0x4B4D4541u, (uint64_t)j) % (uint64_t)(j + 1));
+        pick.insert(pick.count(t) ? j : t);
+    }
+    std::vector<int64_t> rows(pick.begin(), pick.end());
+    std::sort(rows.begin(), rows.end());
+    struct Bufs { std::vector<void*> p; ~Bufs() { for (void* q : p) hipFree(q); } } bufs;
+    auto dalloc = [&](size_t b, void** out) -> int {
+        ERQ_HIP(hipMalloc(out, std::max<size_t>(b, 256)));
+        bufs.p.push_back(*out);
+        return ERQ_OK;
+    };
+    int64_t* drows = nullptr; int32_t* asg = asg_out; int32_t* ids32 = nullptr; int64_t* doff = nullptr;
+    void* bscr = nullptr;
+    if (int rc = dalloc(sizeof(int64_t) * C, (void**)&drows)) return rc;
+    if (!asg) {
+        if (int rc = dalloc(sizeof(int32_t) * n, (void**)&asg)) return rc;
+    }
+    if (int rc = dalloc(sizeof(int32_t) * n, (void**)&ids32)) return rc;
+    if (int rc = dalloc(sizeof(int64_t) * (C + 1), (void**)&doff)) return rc;
+    if (int rc = dalloc(bucket_scratch_bytes(n, C), &bscr)) return rc;
+    ERQ_HIP(hipMemcpyAsync(drows, rows.data(), sizeof(int64_t) * C, hipMemcpyHostToDevice, st));
+    ERQ_HIP(launch_gather_rows(x, dp, drows, C, cent, st));
+    ERQ_HIP(hipStreamSynchronize(st));                   // rows goes out of scope
+    std::vector<int64_t> off;
+    for (int it = 0; it < iters; ++it) {
+        if (int rc = assign_rows(x, n, dp, cent, C, asg, st)) return rc;
+        if (int rc = list_offsets(asg, n, C, off, st)) return rc;
+        ERQ_HIP(hipMemcpyAsync(doff, off.data(), sizeof(int64_t) * (C + 1), hipMemcpyHostToDevice, st));
+        ERQ_HIP(launch_bucket_sort(asg, n, C, doff, ids32, bscr, st));
+        void* mscr = nullptr;
+        ERQ_HIP(hipMalloc(&mscr, list_mean_scratch_bytes(off, dp)));
+        const hipError_t e = launch_list_mean(x, dp, ids32, off, doff, cent, mscr, st);   // synchronises
+        hipFree(mscr);
+        ERQ_HIP(e);
+    }
+    if (int rc = assign_rows(x, n, dp, cent, C, asg, st)) return rc;
+    ERQ_HIP(hipStreamSynchronize(st));
     return ERQ_OK;
 }
 
@@ -578,12 +667,34 @@ int erq_index_set_raw(erq_index ix, const float* x, int64_t n, void* stream)
     return ERQ_OK;
 }
 
+int erq_kmeans(const float* x, int64_t n, int32_t dp, int64_t nlist, int32_t iters, uint64_t seed,
+               float* centroids, int32_t* assign, void* stream)
+{
+    if (int rc = check_dp(dp, "erq_kmeans")) return rc;
+    if (nlist < 1 || nlist > (1 << 24) || n < nlist || n > (1LL << 31) - 1)
+        return fail(ERQ_EINVAL, "erq_kmeans: need 1 <= nlist <= n < 2^31");
+    if (iters < 0 || iters > 1000) return fail(ERQ_EINVAL, "erq_kmeans: iters must be in [0, 1000]");
+    if (!x || !centroids) return fail(ERQ_EINVAL, "erq_kmeans: null pointer");
+    return kmeans_impl(x, n, dp, nlist, iters, seed, centroids, assign, (hipStream_t)stream);
+}
+
 int erq_index_build(erq_index ix, const float* x, int64_t n, const float* centroids, const int32_t* assign,
                     int32_t precision, int32_t keep_raw, void* stream)
 {
     if (!ix) return fail(ERQ_EINVAL, "erq_index_build: null index");
     if (n < 0 || n > (1LL << 31) - 1) return fail(ERQ_EINVAL, "erq_index_build: n out of range");
-    if (!centroids || (n > 0 && !x)) return fail(ERQ_EINVAL, "erq_index_build: null pointer");
+    if (n > 0 && !x) return fail(ERQ_EINVAL, "erq_index_build: null pointer");
+    float* own_cent = nullptr;                      // centroids of the library's k-means
+    struct FreeC { float** p; ~FreeC() { hipFree(*p); } } free_cent{&own_cent};
+    if (!centroids) {
+        if (assign) return fail(ERQ_EINVAL, "erq_index_build: an assignment needs its centroids");
+        if (n < ix->nlist) return fail(ERQ_EINVAL, "erq_index_build: k-means needs at least nlist rows");
+        ERQ_HIP(hipMalloc(&own_cent, sizeof(float) * ix->nlist * ix->dp));
+        if (int rc = kmeans_impl(x, n, ix->dp, ix->nlist, kBuildKmeansIters, ix->seed ^ 0x6B6D65616E73ull, own_cent,
+                                 nullptr, (hipStream_t)stream))
+            return rc;
+        centroids = own_cent;
+    }
     if (precision != 0 && precision != 1) return fail(ERQ_EUNSUPPORTED, "erq_index_build: precision must be 0 or 1");
     if (ix->dp > 3072) return fail(ERQ_EUNSUPPORTED, "erq_index_build: dp > 3072 exceeds the LDS window");
     hipStream_t st = (hipStream_t)stream;
@@ -639,24 +750,13 @@ int erq_index_build(erq_index ix, const float* x, int64_t n, const float* centro
     ERQ_HIP(hipMalloc(&ix->fac, sizeof(float2) * std::max<int64_t>(n, 1)));
     ERQ_HIP(hipMalloc(&ix->sfac, sizeof(float2) * std::max<int64_t>(n, 1)));
     ERQ_HIP(hipMalloc(&ix->codes, std::max<int64_t>((int64_t)4 * dp * ix->bits * ix->ntiles, 256)));
-    // members in list order, ids ascending within each list: a stable radix
-    // sort of (list, id) pairs by list, so the layout is the same on every build
+    // members in list order, ids ascending within each list: a stable bucket
+    // sort of the rows by list, so the layout is the same on every build
     if (n > 0) {
-        int32_t *iota = nullptr, *keys = nullptr;
-        ERQ_HIP(hipMalloc(&iota, sizeof(int32_t) * n));
-        guard.p.push_back(iota);
-        ERQ_HIP(hipMalloc(&keys, sizeof(int32_t) * n));
-        guard.p.push_back(keys);
-        hipLaunchKernelGGL(iota_i32, dim3(blocks(n)), dim3(256), 0, st, iota, n);
-        ERQ_HIP(hipGetLastError());
-        int end_bit = 1;
-        while ((1LL << end_bit) < C) ++end_bit;
-        size_t tb = 0;
-        ERQ_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, asg, keys, iota, ids32, (int)n, 0, end_bit, st));
-        void* tmp = nullptr;
-        ERQ_HIP(hipMalloc(&tmp, std::max<size_t>(tb, 1)));
-        guard.p.push_back(tmp);
-        ERQ_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tb, asg, keys, iota, ids32, (int)n, 0, end_bit, st));
+        void* bs = nullptr;
+        ERQ_HIP(hipMalloc(&bs, bucket_scratch_bytes(n, C)));
+        guard.p.push_back(bs);
+        ERQ_HIP(launch_bucket_sort(asg, n, C, ix->list_off, ids32, bs, st));
         hipLaunchKernelGGL(widen_i32, dim3(blocks(n)), dim3(256), 0, st, ids32, n, ix->ids);
         ERQ_HIP(hipGetLastError());
     }

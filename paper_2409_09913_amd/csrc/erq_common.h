@@ -134,6 +134,22 @@ hipError_t launch_rerank(const float* raw, int64_t n, int dp, const float* q, in
 
 // Haar orthogonal dp x dp matrix of the seed, row-major FP32, host memory (host code)
 void sample_rotation(int dp, uint64_t seed, float* P);
+// 64 random bits of Philox4x32-10 for (seed, stream tag, counter) (host code)
+uint64_t philox_u64(uint64_t seed, uint32_t tag, uint64_t counter);
+
+// Stable bucket sort of row ids by list: ids32[list_off[l] + j] = the j-th
+// row (ascending) with assign[row] == l.  list_off (device, nlist + 1) must
+// hold the exclusive prefix of the per-list counts.  Scratch: bucket_scratch_bytes.
+size_t bucket_scratch_bytes(int64_t n, int64_t nlist);
+hipError_t launch_bucket_sort(const int32_t* assign, int64_t n, int64_t nlist, const int64_t* list_off,
+                              int32_t* ids32, void* scratch, hipStream_t st);
+// Per-list means of x over the members of each list (rows ids32 in list
+// order, FP64 sums in member order), into cent (FP32); empty lists keep
+// their row of cent.  Scratch: list_mean_scratch_bytes.
+size_t list_mean_scratch_bytes(const std::vector<int64_t>& off, int dp);
+hipError_t launch_list_mean(const float* x, int dp, const int32_t* ids32, const std::vector<int64_t>& off,
+                            const int64_t* list_off, float* cent, void* scratch, hipStream_t st);
+hipError_t launch_gather_rows(const float* x, int dp, const int64_t* rows, int64_t m, float* out, hipStream_t st);
 
 // list building
 hipError_t launch_residual(const float* x, const int64_t* ids, const int32_t* assign, const float* cent,

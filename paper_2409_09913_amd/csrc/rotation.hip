@@ -87,6 +87,14 @@ void for_columns(int lo, int hi, int nthr, F f) {
 
 }  // namespace
 
+// 64 random bits for (seed, stream tag, counter): one Philox4x32-10 block
+uint64_t philox_u64(uint64_t seed, uint32_t tag, uint64_t counter)
+{
+    Philox x{{(uint32_t)counter, (uint32_t)(counter >> 32), tag, 0u}};
+    const Philox r = philox10(x, (uint32_t)seed, (uint32_t)(seed >> 32));
+    return ((uint64_t)r.c[0] << 32) | r.c[1];
+}
+
 // P (row-major dp x dp, FP32) <- Haar orthogonal matrix of the seed
 void sample_rotation(int dp, uint64_t seed, float* P)
 {

@@ -33,6 +33,7 @@ SIGNATURES = {
     "erq_index_save": (C.c_int, [_p, C.c_char_p, _p]),
     "erq_index_load": (C.c_int, [C.c_char_p, _p, C.POINTER(_p)]),
     "erq_index_import": (C.c_int, [_p, _i64, _p, _p, _p, _p, _p, _p, _p, _p]),
+    "erq_kmeans": (C.c_int, [_p, _i64, _i32, _i64, _i32, C.c_uint64, _p, _p, _p]),
     "erq_index_build": (C.c_int, [_p, _p, _i64, _p, _p, _i32, _i32, _p]),
     "erq_index_set_raw": (C.c_int, [_p, _p, _i64, _p]),
     "erq_index_info": (C.c_int, [_p, C.POINTER(_i64), C.POINTER(_i32), C.POINTER(_i32),
@@ -150,6 +151,17 @@ def sample_rotation(dp: int, seed: int):
     return out
 
 
+def kmeans(x, nlist: int, iters: int = 10, seed: int = 240909913):
+    """Lloyd k-means of the rows of x in the library (erq_kmeans); returns
+    (centroids nlist x dp float32, assign int32) on x's device."""
+    n, dp = x.shape
+    cent = torch.empty((nlist, dp), dtype=torch.float32, device=x.device)
+    asg = torch.empty(n, dtype=torch.int32, device=x.device)
+    _check(load().erq_kmeans(_ptr(x, torch.float32, "x"), n, dp, nlist, iters, seed, _ptr(cent), _ptr(asg),
+                             _stream()))
+    return cent, asg
+
+
 class Index:
     """Owner of an erq_index handle (lists, packed codes, factors, P, centroids).
     P: the dp x dp rotation (device tensor), or None to have the library
@@ -201,7 +213,8 @@ class Index:
                                        _ptr(centroids, torch.float32, "centroids"),
                                        _ptr(centroids_rot, torch.float32, "centroids_rot"), _stream()))
 
-    def build(self, x, centroids, assign=None, precision: int = 0, keep_raw: bool = False):
+    def build(self, x, centroids=None, assign=None, precision: int = 0, keep_raw: bool = False):
+        """Index phase on the device; centroids None: the library's k-means."""
         _check(load().erq_index_build(self.h, _ptr(x, torch.float32, "x"), x.shape[0],
                                       _ptr(centroids, torch.float32, "centroids"),
                                       _ptr(assign, torch.int32, "assign"), precision, int(keep_raw), _stream()))

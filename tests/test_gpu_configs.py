@@ -23,7 +23,7 @@ import pytest
 import torch
 
 import oracle
-from paper_2409_09913_amd import erq, ivf, serve, synth
+from paper_2409_09913_amd import erq, serve, synth
 from parity_util import CandTerms, compare_topk
 
 pytestmark = pytest.mark.gpu
@@ -165,7 +165,7 @@ def test_d3072_scan_and_serving():
     x = torch.from_numpy(synth.gmm(n, dp, 64, 0.3, seed=953)).to(DEV)
     q = torch.from_numpy(synth.gmm(96, dp, 64, 0.3, seed=953, stream=synth.S_QUERY)).to(DEV)
     P = dev(synth.haar_orthogonal(dp, seed=954).astype(np.float32))
-    cent, assign = ivf.kmeans(x, nl, iters=3)
+    cent, assign = erq.kmeans(x, nl, iters=3)
     ix = erq.Index(dp, B, nl, P)
     ix.build(x, cent, assign, keep_raw=True)
     srv = serve.Server(ix, max_batch=64, max_nprobe=64, max_k=10, max_rerank=20, slots=2)
@@ -216,7 +216,7 @@ def test_autotune_search():
     x = torch.from_numpy(synth.gmm(n, d, 32, 0.3, seed=970)).to(DEV)
     q = torch.from_numpy(synth.gmm(500, d, 32, 0.3, seed=970, stream=synth.S_QUERY)).to(DEV)
     P = dev(synth.haar_orthogonal(d, seed=971).astype(np.float32))
-    cent, assign = ivf.kmeans(x, nl, iters=4)
+    cent, assign = erq.kmeans(x, nl, iters=4)
     ix = erq.Index(d, 4, nl, P)
     ix.build(x, cent, assign, keep_raw=True)
     ri, rd = ix.search(q, 16, 10, 20)

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 import torch
 
-from paper_2409_09913_amd import erq, ivf, synth
+from paper_2409_09913_amd import erq, synth
 
 pytestmark = pytest.mark.gpu
 
@@ -34,7 +34,7 @@ def test_save_load_roundtrip(tmp_path, keep_raw):
     n, d, nl = 30000, 192, 48
     x = torch.from_numpy(synth.gmm(n, d, 16, 0.3, seed=71, dp=d)).to(DEV)
     q = torch.from_numpy(synth.gmm(200, d, 16, 0.3, seed=71, stream=synth.S_QUERY, dp=d)).to(DEV)
-    cent, assign = ivf.kmeans(x, nl, iters=3)
+    cent, assign = erq.kmeans(x, nl, iters=3)
     ix = erq.Index(d, 5, nl, None, seed=9)
     ix.build(x, cent, assign, keep_raw=keep_raw)
     ix.set_tune(1, 3, 4, 0)

@@ -25,7 +25,7 @@ import pytest
 import torch
 
 import oracle
-from paper_2409_09913_amd import erq, ivf, synth
+from paper_2409_09913_amd import erq, synth
 from parity_util import CandTerms, compare_topk
 
 pytestmark = pytest.mark.gpu
@@ -111,7 +111,7 @@ def built768():
     q = synth.gmm(nq, d, 256, 0.3, zipf=True, lognormal_norm=0.2, seed=777, stream=synth.S_QUERY)
     P = synth.haar_orthogonal(d, seed=778).astype(np.float32)
     xd = dev(x)
-    cent, assign = ivf.kmeans(xd, nl, iters=5)
+    cent, assign = erq.kmeans(xd, nl, iters=5)
     ix = erq.Index(d, 4, nl, dev(P))
     ix.build(xd, cent, assign, keep_raw=True)
     torch.cuda.synchronize()

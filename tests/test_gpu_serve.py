@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 import torch
 
-from paper_2409_09913_amd import erq, ivf, serve, synth
+from paper_2409_09913_amd import erq, serve, synth
 
 pytestmark = pytest.mark.gpu
 
@@ -32,7 +32,7 @@ def built():
     x = torch.from_numpy(synth.gmm(n, d, 16, 0.3, seed=21, stream=synth.S_BASE)).to(DEV)
     q = torch.from_numpy(synth.gmm(640, d, 16, 0.3, seed=21, stream=synth.S_QUERY)).to(DEV)
     P = torch.from_numpy(synth.haar_orthogonal(d, seed=22).astype(np.float32)).to(DEV)
-    cent, assign = ivf.kmeans(x, nl, iters=5)
+    cent, assign = erq.kmeans(x, nl, iters=5)
     ix = erq.Index(d, 4, nl, P)
     ix.build(x, cent, assign, keep_raw=True)
     torch.cuda.synchronize()

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 import torch
 
-from paper_2409_09913_amd import erq, ivf, synth
+from paper_2409_09913_amd import erq, synth
 
 pytestmark = pytest.mark.gpu
 
@@ -36,7 +36,7 @@ def test_search_static_matches_search():
     x = torch.from_numpy(synth.gmm(n, d, 16, 0.3, seed=61, stream=synth.S_BASE)).to(DEV)
     q = torch.from_numpy(synth.gmm(400, d, 16, 0.3, seed=61, stream=synth.S_QUERY)).to(DEV)
     P = torch.from_numpy(synth.haar_orthogonal(d, seed=62).astype(np.float32)).to(DEV)
-    cent, assign = ivf.kmeans(x, nl, iters=4)
+    cent, assign = erq.kmeans(x, nl, iters=4)
     ix = erq.Index(d, 4, nl, P)
     ix.build(x, cent, assign, keep_raw=True)
     assert erq.static_scratch_bytes() == 64 << 20
