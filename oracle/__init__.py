@@ -61,6 +61,7 @@ def _load():
         lib.orc_rerank.argtypes = [p, i32, p, i64, p, i32, i32, p, p]
         lib.orc_knn.argtypes = [p, i64, i32, p, i64, i32, p, p]
         lib.orc_num_threads.restype = i32
+        lib.orc_set_threads.argtypes = [i32]
         _lib = lib
     return _lib
 
@@ -75,6 +76,11 @@ def _c(a, dtype):
 
 def num_threads() -> int:
     return int(_load().orc_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the following oracle calls."""
+    _load().orc_set_threads(int(n))
 
 
 def rotate(x, P):
@@ -172,7 +178,8 @@ def probe(q, cent, nprobe):
 
 def search(list_off, ids, codes, f_add, f_rescale, crot, qrot, probes, B, kk,
            cos_oo=None, est_mode=0):
-    """IVF scan + top-kk by (est, id); est_mode 0 = int8 query, 1 = float query."""
+    """IVF scan + top-kk by (est, id); est_mode 0 = int8 query (factor form),
+    1 = float query (paper form, needs cos_oo), 2 = float query (factor form)."""
     list_off = _c(list_off, np.int64)
     ids = _c(ids, np.int64)
     codes = _c(codes, np.uint8)

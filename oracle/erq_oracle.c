@@ -399,7 +399,9 @@ void orc_probe(const float* q, int64_t nq, const float* cent, int64_t C, int dp,
    Queries: qrot[nq x dp] rotated (FP32), probes[nq x nprobe].  Every query
    is quantised to int8 once; for every probed list s' = q' - c' and ||s||^2
    in FP64 (exact differences of the FP32 inputs); every member gets an
-   estimate; the kk smallest (est, id) are returned.  est_mode 0 = int8 query
+   estimate; the kk smallest (est, id) are returned.  est_mode 2 = float
+   query with the stored factors (f_add + ||s||^2 + f_rescale <y, s'>, FP64);
+   est_mode 0 = int8 query
    (factor form), 1 = float query (paper form, uses cos_oo). */
 int orc_search(const int64_t* list_off, const int64_t* ids, const uint8_t* codes,
                const float* f_add, const float* f_rescale, const double* cos_oo,
@@ -437,7 +439,12 @@ int orc_search(const int64_t* list_off, const int64_t* ids, const uint8_t* codes
                 for (int64_t v = lo; v < hi; ++v) {
                     const uint8_t* cd = codes + v * (int64_t)dp;
                     double est;
-                    if (est_mode == 0) {
+                    if (est_mode == 2) {
+                        /* float query, factor form (reading C-11): f_add + ||s||^2 + f_rescale <y, s'> */
+                        double ys = 0.0;
+                        for (int i = 0; i < dp; ++i) ys += ((double)cd[i] - half) * sd[i];
+                        est = (double)f_add[v] + ns2 + (double)f_rescale[v] * ys;
+                    } else if (est_mode == 0) {
                         int64_t ip = 0;
                         double ybc = 0.0;
                         for (int i = 0; i < dp; ++i) {
@@ -505,6 +512,15 @@ void orc_knn(const float* x, int64_t n, int dp, const float* q, int64_t nq, int 
         }
         free(c);
     }
+}
+
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
 }
 
 int orc_num_threads(void)
