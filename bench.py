@@ -60,7 +60,13 @@ def main():
     ap.add_argument("--kmeans-iters", type=int, default=10)
     ap.add_argument("--target-recall", type=float, default=0.95)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-queries", type=int, default=32)
+    ap.add_argument("--cpu-sample-queries", type=int, default=1000,
+                    help="queries of the oracle's all-core run (the first ones)")
+    ap.add_argument("--cpu-single-queries", type=int, default=40,
+                    help="queries of the oracle's single-thread run")
+    ap.add_argument("--est-queries", type=int, default=400,
+                    help="queries of the float- vs int8-query recall table (0 = skip)")
+    ap.add_argument("--flat", type=int, default=1, help="1: FP32 IVF-Flat comparator sweep on the same lists")
     ap.add_argument("--nprobe", type=int, default=0, help="fixed operating point (skips the sweep)")
     ap.add_argument("--rerank", type=int, default=-1, help="fixed re-rank depth (with --nprobe)")
     ap.add_argument("--tune", type=int, default=1, help="1: run the scan-schedule autotuner before timing")
@@ -324,6 +330,35 @@ def main():
         serving = {"slots": srv.slots_admitted, "request": "1 query, nprobe 16 or 64, k=%d, rerank %d" % (args.k, rr),
                    "by_rate": res_s}
 
+    # ---- FP32 IVF-Flat on the same lists and probes: the metric's FP32 scan ---------------
+    flat = None
+    if args.flat:
+        rows_f = []
+        for npf in (16, 32, 64, 88, 128, 192):
+            run = ivf_flat_fp32(x, q, cent, assign.cpu().numpy(), npf, args.k)
+            ids_f = run()
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            ids_f = run()
+            torch.cuda.synchronize()
+            dtf = time.perf_counter() - ts
+            rec_f = recall_at(ids_f.cpu().numpy(), truth_np, args.k)
+            rows_f.append({"nprobe": npf, "recall@10": rec_f, "qps": args.nq / dtf})
+            log("IVF-Flat FP32 nprobe %3d recall@10 %.4f QPS %.0f" % (npf, rec_f, args.nq / dtf))
+            del run
+        ok_f = [r for r in rows_f if r["recall@10"] >= args.target_recall]
+        flat = {"kind": "FP32 IVF-Flat, same lists and probe lists, exact distances by torch.bmm (library GEMM)",
+                "best": max(ok_f, key=lambda r: r["qps"]) if ok_f else None, "sweep": rows_f}
+
+    # ---- accuracy of the int8 query (reading C-13): float- vs int8-query recall ------------
+    est_tab = []
+    if args.est_queries:
+        for index, B, npr in ((ix, args.bits, nprobe),) + (((ix2, args.bits2, best2[0]),) if args.bits2 else ()):
+            r = estimator_recall(index, cent, q_np, P_np, truth_np, npr, args.k, B, args.est_queries)
+            est_tab.append(r)
+            log("estimator recall B=%d nprobe %d (%d queries, no re-rank): int8 query %.4f, float query %.4f" %
+                (B, npr, r["queries"], r["recall_int8_query"], r["recall_float_query"]))
+
     # ---- CPU baseline: the oracle on a bounded sample ------------------------------------
     cpu = None
     if not args.no_cpu_baseline:
@@ -341,6 +376,8 @@ def main():
                    "parallelism": "single GPU"},
         "encode_codes_per_s": enc_rate,
         "fp32_bruteforce_qps": flat_qps,
+        "fp32_ivf_flat": flat,
+        "estimator_recall": est_tab,
         "per_launch_ms": tot,
         "timed_mode": "hip_graph_replay" if graph_dt is not None else "eager",
         "autotune": tuned,
@@ -372,28 +409,35 @@ def calib_copy():
     print(json.dumps({"copy_bytes": 4 * n, "copies": 5}), flush=True)
 
 
+def host_cores() -> int:
+    """Cores this process may run on (the affinity mask, as nproc reports)."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
 def cpu_baseline(args, x_np, q_np, P_np, cent_np, assign_np, nprobe, rr):
-    """The oracle as it stands on a bounded sample: the first S queries are
-    probed over all centroids (FP64), their probed lists are encoded by the
-    oracle, scanned with the int8 estimator and re-ranked exactly."""
+    """The oracle as it stands, on the host cores: the first S queries
+    (default 1,000) are probed over all centroids (FP64), the lists they probe
+    are encoded by the oracle (untimed: the search needs codes), scanned with
+    the int8 estimator and re-ranked exactly; the whole query path is timed
+    with every core and again with one thread (the paper's single-thread
+    convention) on the first S1 queries.  The oracle's encode rate is timed on
+    the first 100,000 rows."""
     import oracle
-    S = args.cpu_sample_queries
+    cores = host_cores()
+    oracle.set_threads(cores)
+    S, S1 = min(args.cpu_sample_queries, len(q_np)), min(args.cpu_single_queries, len(q_np))
     sizes = np.bincount(assign_np, minlength=cent_np.shape[0])
+    # encode rate: the first 100k rows, each centred on its own list
+    ne = min(100_000, len(x_np))
+    t1 = time.perf_counter()
+    oracle.encode(x_np[:ne], cent_np.astype(np.float64), assign_np[:ne], P_np.astype(np.float64), args.bits)
+    enc_rate = ne / (time.perf_counter() - t1)
+    log("cpu baseline: oracle encode %.0f codes/s on %d threads (first %d rows)" % (enc_rate, cores, ne))
     probes_all, _ = oracle.probe(q_np[:S], cent_np, nprobe)
-    # bound the oracle's encoding work: keep the first queries whose lists hold <= 100k rows
-    seen, rows_needed, keep = set(), 0, 0
-    for i in range(S):
-        new = set(probes_all[i].tolist()) - seen
-        add = int(sizes[list(new)].sum()) if new else 0
-        if keep >= 4 and rows_needed + add > 100_000:
-            break
-        seen |= new
-        rows_needed += add
-        keep += 1
-    S = keep
-    qs = q_np[:S]
-    probes = probes_all[:S]
-    lists = np.unique(probes)
+    lists = np.unique(probes_all)
     remap = -np.ones(cent_np.shape[0], np.int64)
     remap[lists] = np.arange(len(lists))
     members = [np.nonzero(assign_np == l)[0] for l in lists]
@@ -401,34 +445,135 @@ def cpu_baseline(args, x_np, q_np, P_np, cent_np, assign_np, nprobe, rr):
     off = np.zeros(len(lists) + 1, np.int64)
     off[1:] = np.cumsum([len(m) for m in members])
     asg_local = np.repeat(np.arange(len(lists), dtype=np.int32), [len(m) for m in members])
-    log("cpu baseline: encoding %d rows of %d lists with the oracle" % (len(ids), len(lists)))
-    t1 = time.perf_counter()
+    log("cpu baseline: encoding %d rows of the %d lists the first %d queries probe" % (len(ids), len(lists), S))
     codes, fa, fr, co, _ = oracle.encode(x_np[ids], cent_np[lists].astype(np.float64), asg_local,
                                          P_np.astype(np.float64), args.bits)
-    t_enc = time.perf_counter() - t1
     crot = oracle.rotate(cent_np[lists], P_np).astype(np.float32)
     kk = rr if rr > 0 else args.k
     fa32, fr32 = fa.astype(np.float32), fr.astype(np.float32)
-    reps, t_search = 0, 0.0
-    while t_search < 10.0 or reps < 2:         # the whole query path, repeated for about 10 s
-        t2 = time.perf_counter()
+
+    def path(qs):
         pr, _ = oracle.probe(qs, cent_np, nprobe)
         qrot = oracle.rotate(qs, P_np).astype(np.float32)
         oi, od = oracle.search(off, ids, codes, fa32, fr32, crot, qrot, remap[pr].astype(np.int32), args.bits, kk)
         if rr > 0:
             oi, od = oracle.rerank(x_np, qs, oi, args.k)
-        t_search += time.perf_counter() - t2
-        reps += 1
-    cores = oracle.num_threads()
-    qps = S * reps / t_search
-    log("cpu baseline: %.1f QPS (%d queries x %d passes, %.2fs), encode %.0f codes/s, %d threads" %
-        (qps, S, reps, t_search, len(ids) / t_enc, cores))
+        return oi
+
+    t2 = time.perf_counter()
+    path(q_np[:S])
+    t_all = time.perf_counter() - t2
+    oracle.set_threads(1)
+    t3 = time.perf_counter()
+    path(q_np[:S1])
+    t_one = time.perf_counter() - t3
+    oracle.set_threads(cores)
+    qps, qps1 = S / t_all, S1 / t_one
+    log("cpu baseline: %.1f QPS on %d threads (%d queries, %.1f s); %.2f QPS on 1 thread (%d queries, %.1f s)" %
+        (qps, cores, S, t_all, qps1, S1, t_one))
     return {"value": qps, "unit": "QPS", "cores": cores, "kind": "oracle",
-            "sample": "%d queries, whole path repeated %d times (%.1f s): FP64 probe over %d centroids, "
-                      "int8-estimator scan of nprobe=%d lists, re-rank %d; the probed lists encoded by the "
-                      "oracle first (%d rows, %.1f s, not in the rate)" % (S, reps, t_search, cent_np.shape[0],
-                                                                          nprobe, rr, len(ids), t_enc),
-            "encode_codes_per_s": len(ids) / t_enc}
+            "sample": "first %d queries, whole query path once (%.1f s): FP64 probe over %d centroids, rotation, "
+                      "int8-estimator scan of nprobe=%d lists, re-rank %d; lists encoded by the oracle first "
+                      "(%d rows, untimed)" % (S, t_all, cent_np.shape[0], nprobe, rr, len(ids)),
+            "single_thread": {"value": qps1, "unit": "QPS", "cores": 1, "queries": S1, "seconds": t_one},
+            "encode_codes_per_s": enc_rate, "encode_sample_rows": ne}
+
+
+def ivf_flat_fp32(x, q, cent, assign_np, nprobe, k, budget=1 << 27, xbudget=1 << 28):
+    """FP32 IVF-Flat on the same lists and the same probe lists (erq's coarse
+    probe): exact squared distances ||q||^2 + ||x||^2 - 2 q.x of every member
+    of the probed lists as batched FP32 products (torch.bmm, the library
+    GEMM), padded groups of lists, top-k per (query, list), then per query.
+    Returns a function running the search (timed by the caller) and the
+    host-side group tables (built once, outside the timing)."""
+    import torch
+    from paper_2409_09913_amd import erq
+    dev = q.device
+    nq, dp = q.shape
+    nl = cent.shape[0]
+    probes = erq.coarse_probe(q, cent, nprobe).cpu().numpy().astype(np.int64)
+    order = np.argsort(assign_np, kind="stable")
+    sizes = np.bincount(assign_np, minlength=nl)
+    loff = np.zeros(nl + 1, np.int64)
+    loff[1:] = np.cumsum(sizes)
+    pl = probes.reshape(-1)
+    pslot = np.arange(nq * nprobe)
+    po = np.argsort(pl, kind="stable")
+    pcnt = np.bincount(pl, minlength=nl)
+    poff = np.zeros(nl + 1, np.int64)
+    poff[1:] = np.cumsum(pcnt)
+    lists = [l for l in np.argsort(-sizes, kind="stable") if pcnt[l] > 0 and sizes[l] > 0]
+    groups, cur, mq, mm = [], [], 0, 0
+    for l in lists:
+        nmq, nmm = max(mq, pcnt[l]), max(mm, sizes[l])
+        if cur and ((len(cur) + 1) * nmq * nmm > budget or (len(cur) + 1) * nmm * dp > xbudget):
+            groups.append(cur)
+            cur, nmq, nmm = [], pcnt[l], sizes[l]
+        cur.append(l)
+        mq, mm = nmq, nmm
+    if cur:
+        groups.append(cur)
+    tabs = []
+    for gl in groups:
+        G = len(gl)
+        mq = int(max(pcnt[l] for l in gl))
+        mm = int(max(sizes[l] for l in gl))
+        mem = np.zeros((G, mm), np.int64)
+        mval = np.zeros((G, mm), bool)
+        qs = np.zeros((G, mq), np.int64)
+        sl = np.full((G, mq), -1, np.int64)
+        for i, l in enumerate(gl):
+            m = order[loff[l]:loff[l + 1]]
+            mem[i, :len(m)] = m
+            mval[i, :len(m)] = True
+            ps = pslot[po[poff[l]:poff[l + 1]]]
+            qs[i, :len(ps)] = ps // nprobe
+            sl[i, :len(ps)] = ps
+        tabs.append(tuple(torch.from_numpy(a).to(dev) for a in (mem, mval, qs, sl)))
+    xn = (x * x).sum(1)
+    qn = (q * q).sum(1)
+    kk = k
+
+    def run():
+        best_d = torch.full((nq * nprobe, kk), float("inf"), device=dev)
+        best_i = torch.full((nq * nprobe, kk), -1, dtype=torch.int64, device=dev)
+        for mem, mval, qs, sl in tabs:
+            X = x[mem]                                       # G x mm x dp
+            Q = q[qs]                                        # G x mq x dp
+            d = qn[qs][:, :, None] + xn[mem][:, None, :] - 2.0 * torch.bmm(Q, X.transpose(1, 2).contiguous())
+            d = d.masked_fill(~mval[:, None, :], float("inf"))
+            kt = min(kk, d.shape[2])
+            tv, ti = torch.topk(d, kt, dim=2, largest=False)
+            ids = torch.gather(mem[:, None, :].expand(-1, d.shape[1], -1), 2, ti)
+            ok = sl >= 0
+            best_d[sl[ok], :kt] = tv[ok]
+            best_i[sl[ok], :kt] = ids[ok]
+        bd = best_d.view(nq, nprobe * kk)
+        bi = best_i.view(nq, nprobe * kk)
+        tv, ti = torch.topk(bd, kk, dim=1, largest=False)
+        return torch.gather(bi, 1, ti)
+
+    return run
+
+
+def estimator_recall(ix, cent, q_np, P_np, truth_np, nprobe, k, B, S):
+    """Recall@k without re-rank of the paper's float-query estimator (the
+    oracle in FP64, factor form with the index's stored codes and factors)
+    beside the int8-query estimator of the GPU scan, on the first S queries
+    with the same probe lists."""
+    import torch
+    import oracle
+    from paper_2409_09913_amd import erq
+    dev = torch.device("cuda:0")
+    off, ids, codes, fa, fr, crot = [t.cpu().numpy() for t in ix.export()]
+    qs = torch.from_numpy(np.ascontiguousarray(q_np[:S])).to(dev)
+    probes = erq.coarse_probe(qs, cent, nprobe).cpu().numpy()
+    gi, _ = ix.search(qs, nprobe, k, 0)
+    gi = gi.cpu().numpy()
+    qrot = oracle.rotate(q_np[:S], P_np).astype(np.float32)
+    fi, _ = oracle.search(off, ids, codes, fa, fr, crot, qrot, probes, B, k, est_mode=2)
+    return {"bits": B, "nprobe": nprobe, "queries": S, "recall_int8_query": recall_at(gi, truth_np[:S], k),
+            "recall_float_query": recall_at(fi, truth_np[:S], k)}
 
 
 if __name__ == "__main__":
