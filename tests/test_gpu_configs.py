@@ -12,6 +12,12 @@
   distances and recall@10 against exact k-NN, per bit width.
 * D = 3072, B = 4: scan parity, and served requests with nprobe 16 and 64
   identical alone and in a mixed batch.
+* Full sizes with random codes generated on the device (seeded): the
+  batching workload (2,000,000 x 960, 8192 lists of 20 to 5000 members,
+  B = 3, 5, 7, per-query nprobe in 8..256, batches of 1 to 4096 queries) and
+  the serving workload's index (5,000,000 x 3072, 16,384 lists, B = 4,
+  nprobe 16 or 64 per query, k = 10 and 100): sampled queries against the
+  oracle on their probed lists, and every query's row the same in every batch.
 
 Codes and factors that feed the oracle are synthetic (never produced by the
 GPU path); the D = 1536 check compares GPU results with exact distances.
@@ -230,3 +236,101 @@ def test_autotune_search():
     np.testing.assert_array_equal(gi.cpu().numpy(), ri.cpu().numpy())
     np.testing.assert_array_equal(gd.cpu().numpy().view(np.uint32), rd.cpu().numpy().view(np.uint32))
     ix.close()
+
+
+def _device_index(sizes, dp, B, seed):
+    """Random index contents made on the device from a seeded torch generator
+    (codes uniform in [0, 2^B), f_add > 0, f_rescale < 0, ids a permutation)."""
+    g = torch.Generator(device=DEV).manual_seed(seed)
+    n = int(sizes.sum())
+    codes = torch.randint(0, 1 << B, (n, dp), dtype=torch.uint8, device=DEV, generator=g)
+    fa = torch.rand(n, device=DEV, generator=g) * 2 + 0.1
+    fr = -(torch.rand(n, device=DEV, generator=g) * 0.5 + 0.05)
+    ids = torch.randperm(n, device=DEV, generator=g)
+    crot = torch.randn((len(sizes), dp), device=DEV, generator=g)
+    off = np.zeros(len(sizes) + 1, np.int64)
+    off[1:] = np.cumsum(sizes)
+    return off, ids, codes, fa, fr, crot
+
+
+def _sub_index(off, ids, codes, fa, fr, crot, probes):
+    """Host copy of just the lists that `probes` name, with the probe rows
+    renumbered to them (the oracle's input for sampled queries)."""
+    lists = np.unique(probes[probes >= 0])
+    rows = np.concatenate([np.arange(off[l], off[l + 1]) for l in lists])
+    ridx = torch.from_numpy(rows).to(DEV)
+    soff = np.zeros(len(lists) + 1, np.int64)
+    soff[1:] = np.cumsum([off[l + 1] - off[l] for l in lists])
+    remap = -np.ones(len(off) - 1, np.int64)
+    remap[lists] = np.arange(len(lists))
+    sp = np.where(probes >= 0, remap[np.maximum(probes, 0)], -1).astype(np.int32)
+    return (soff, ids[ridx].cpu().numpy().astype(np.int64), codes[ridx].cpu().numpy(), fa[ridx].cpu().numpy(),
+            fr[ridx].cpu().numpy(), crot[torch.from_numpy(lists).to(DEV)].cpu().numpy(), sp)
+
+
+def _sampled_parity(gi, ge, sample, dev_index, qrot, probes, B, kk):
+    off, ids, codes, fa, fr, crot = dev_index
+    soff, sids, scodes, sfa, sfr, scrot, sp = _sub_index(off, ids, codes, fa, fr, crot, probes[sample])
+    oi, oe = oracle.search(soff, sids, scodes, sfa, sfr, scrot, qrot[sample], sp, B, kk, est_mode=0)
+    compare_topk(gi[sample], ge[sample], oi, oe, CandTerms(soff, sids, scodes, sfa, sfr, scrot, qrot[sample], sp, B))
+
+
+@pytest.mark.parametrize("B", [3, 5, 7])
+def test_batching_full_size(B):
+    dp, nl, kk, nq = 960, 8192, 10, 4096
+    sizes = _power_law_sizes(nl, 20, 5000, 1.1, seed=40 + B)
+    say("batching full size B", B, "members", int(sizes.sum()), "lists", nl)
+    dix = _device_index(sizes, dp, B, seed=41 + B)
+    off, ids, codes, fa, fr, crot = dix
+    P = dev(synth.haar_orthogonal(dp, seed=2).astype(np.float32))
+    ix = erq.Index(dp, B, nl, P)
+    ix.import_(dev(off), ids, codes, fa, fr, torch.zeros((nl, dp), device=DEV), crot)
+    qrot = synth.random_rotated(nq, dp, seed=42 + B)
+    g = np.random.default_rng(43 + B)
+    own = g.choice([8, 16, 32, 64, 128, 256], nq)
+    probes = np.full((nq, 256), -1, np.int32)
+    for i in range(nq):
+        probes[i, :own[i]] = g.choice(nl, own[i], replace=False)
+    qd, pd = dev(qrot), dev(probes)
+    gi, ge = ix.scan(qd, pd, kk)
+    torch.cuda.synchronize()
+    gi, ge = gi.cpu().numpy(), ge.cpu().numpy()
+    for bs in (1, 4, 16, 64, 256, 1024):
+        lo = (bs * 37) % (nq - bs)
+        bi, be = ix.scan(qd[lo:lo + bs].contiguous(), pd[lo:lo + bs].contiguous(), kk)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(bi.cpu().numpy(), gi[lo:lo + bs])
+        np.testing.assert_array_equal(be.cpu().numpy().view(np.uint32), ge[lo:lo + bs].view(np.uint32))
+    sample = np.random.default_rng(B).choice(nq, 6, replace=False)
+    _sampled_parity(gi, ge, sample, dix, qrot, probes, B, kk)
+    say("  6 sampled queries match the oracle; batches 1..1024 identical to the 4096 batch")
+    ix.close()
+    del dix, codes
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("kk", [10, 100])
+def test_serving_index_full_size(kk):
+    dp, nl, B, n, nq = 3072, 16384, 4, 5_000_000, 512
+    sizes = synth.zipf_list_sizes(n, nl, seed=50)
+    say("serving index full size: %d x %d, %d lists, kk %d" % (n, dp, nl, kk))
+    dix = _device_index(sizes, dp, B, seed=51)
+    off, ids, codes, fa, fr, crot = dix
+    P = dev(synth.haar_orthogonal(dp, seed=2).astype(np.float32))
+    ix = erq.Index(dp, B, nl, P)
+    ix.import_(dev(off), ids, codes, fa, fr, torch.zeros((nl, dp), device=DEV), crot)
+    qrot = synth.random_rotated(nq, dp, seed=52)
+    g = np.random.default_rng(53)
+    probes = np.full((nq, 64), -1, np.int32)
+    for i in range(nq):
+        npq = int(g.choice([16, 64]))
+        probes[i, :npq] = g.choice(nl, npq, replace=False)
+    gi, ge = ix.scan(dev(qrot), dev(probes), kk)
+    torch.cuda.synchronize()
+    gi, ge = gi.cpu().numpy(), ge.cpu().numpy()
+    sample = np.random.default_rng(54).choice(nq, 4, replace=False)
+    _sampled_parity(gi, ge, sample, dix, qrot, probes, B, kk)
+    say("  4 sampled queries match the oracle")
+    ix.close()
+    del dix, codes
+    torch.cuda.empty_cache()
