@@ -67,6 +67,8 @@ def main():
     ap.add_argument("--est-queries", type=int, default=400,
                     help="queries of the float- vs int8-query recall table (0 = skip)")
     ap.add_argument("--flat", type=int, default=1, help="1: FP32 IVF-Flat comparator sweep on the same lists")
+    ap.add_argument("--serve-n", type=int, default=5_000_000, help="rows of the serving workload")
+    ap.add_argument("--serve-kmeans-iters", type=int, default=6, help="k-means rounds of the serving workload")
     ap.add_argument("--nprobe", type=int, default=0, help="fixed operating point (skips the sweep)")
     ap.add_argument("--rerank", type=int, default=-1, help="fixed re-rank depth (with --nprobe)")
     ap.add_argument("--tune", type=int, default=1, help="1: run the scan-schedule autotuner before timing")
@@ -77,6 +79,9 @@ def main():
     ap.add_argument("--serve", type=int, default=2000,
                     help="N > 0: also run N Poisson-arrival requests per rate through the batching server "
                          "(p50/p99); 0 skips it")
+    ap.add_argument("--workload", type=str, default="embed768", choices=("embed768", "batching", "serving"),
+                    help="embed768 (the default line); batching: 2M x 960, 8192 uneven lists, B=3/5/7, batches "
+                         "1..4096 with mixed nprobe; serving: 5M x 3072, 16384 lists, B=4, Poisson arrivals")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -86,6 +91,12 @@ def main():
         sys.exit(2)
     if args.calib_copy:
         calib_copy()
+        return
+    if args.workload == "batching":
+        run_batching(args)
+        return
+    if args.workload == "serving":
+        run_serving(args)
         return
 
     import torch
@@ -392,6 +403,196 @@ def main():
                         "best": {"nprobe": best2[0], "rerank_k": best2[1], "recall@10": best2[2], "qps": best2[3]}}
     log("total %.1fs" % (time.time() - t0))
     print(json.dumps(res), flush=True)
+
+
+def brute_topk(x, qb, k, chunk=256):
+    """Exact FP32 k-NN (library GEMM + top-k), the ground truth of a workload."""
+    import torch
+    xn = (x * x).sum(1)
+    out = torch.empty((qb.shape[0], k), dtype=torch.int64, device=qb.device)
+    for i in range(0, qb.shape[0], chunk):
+        d = xn[None, :] - 2.0 * (qb[i:i + chunk] @ x.T)
+        out[i:i + chunk] = torch.topk(d, k, dim=1, largest=False).indices
+    return out
+
+
+def scan_roofline(ix, nq, dp, B, sizes, probes_np, launches_ms):
+    """Algorithmic int8 ops and code bytes of one search over the probed pairs,
+    against the pass-B launch time."""
+    lists, cnt = np.unique(probes_np[probes_np >= 0], return_counts=True)
+    ops = float((sizes[lists] * cnt).sum()) * 2 * dp
+    byt = float(sizes[lists].sum()) * (B * dp / 8 + 8)
+    ms, nl = launches_ms
+    t = ms / 1000.0
+    return {"int8_tops": ops / t / 1e12, "mfma_frac": ops / t / 1e12 / INT8_PEAK_TOPS,
+            "code_gbs": byt / t / 1e9, "hbm_frac": byt / t / 1e9 / HBM_PEAK_GBS, "scan_b_ms_per_search": ms,
+            "launches": nl}
+
+
+def run_batching(args):
+    """Batching workload: N = 2,000,000 x D = 960 clusters of an anisotropic
+    Gaussian (variance i^-0.5), 8192 lists of 20..5000 members (power law,
+    mean about 244), B = 3, 5, 7; 4096 queries with per-query nprobe uniform in
+    {8, ..., 256}; each batch size of 1..4096 captured as one HIP graph with
+    per-query parameters, scan schedule autotuned at the full batch."""
+    import torch
+    from paper_2409_09913_amd import erq, serve, synth
+    dev = torch.device("cuda:0")
+    erq.load()
+    t0 = time.time()
+    nl, dp, nq, k = 8192, 960, 4096, args.k
+    sizes = synth.power_law_sizes(nl, 20, 5000, 0.76)
+    x, lab, cent = synth.clustered_anisotropic_device(sizes, dp, device=dev)
+    n = x.shape[0]
+    g = np.random.default_rng(7)
+    qsz = np.zeros(nl, np.int64)
+    qlab = g.integers(0, nl, nq)
+    sd = torch.from_numpy((np.arange(1, dp + 1, dtype=np.float64) ** -0.25).astype(np.float32)).to(dev)
+    gq = torch.Generator(device=dev).manual_seed(11)
+    q = (cent[torch.from_numpy(qlab).to(dev)] + 0.5 * torch.randn((nq, dp), device=dev, generator=gq) * sd).contiguous()
+    own = g.choice([8, 16, 32, 64, 128, 256], nq).astype(np.int32)
+    npq = torch.from_numpy(own).to(dev)
+    truth = brute_topk(x, q, k).cpu().numpy()
+    log("batching workload: %d x %d, %d lists (%d..%d), data %.1fs" % (n, dp, nl, sizes.min(), sizes.max(),
+                                                                      time.time() - t0))
+    out = {"metric": "QPS per batch size, per-query nprobe 8..256 (batching workload)", "unit": "QPS",
+           "config": {"workload": "batching: N=%d x D=960 anisotropic clusters, 8192 lists 20..5000, %d queries, "
+                                  "nprobe uniform in {8..256} per query, k=%d" % (n, nq, k)}, "by_bits": []}
+    for B in (3, 5, 7):
+        ix = erq.Index(dp, B, nl, None, seed=240909913)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        ix.build(x, cent, lab, keep_raw=False)
+        torch.cuda.synchronize()
+        enc = n / (time.perf_counter() - ts)
+        ix.set_raw(x)
+        tuned = ix.tune(q, 128, k, 2 * k, reps=2)
+        rows = []
+        for rr in (0, 2 * k):
+            ids, _ = ix.search(q, 256, k, rr, nprobe_q=npq)
+            rec = recall_at(ids.cpu().numpy(), truth, k)
+            for bs in (1, 4, 16, 64, 256, 1024, 4096):
+                gph = serve.SearchGraph(ix, bs, 256, k, rr, per_query=True)
+                gph.q.copy_(q[:bs])
+                gph.params[0].copy_(npq[:bs])
+                with torch.cuda.stream(gph.stream):
+                    gph.graph.replay()
+                torch.cuda.synchronize()
+                reps = max(3, min(200, 8192 // bs))
+                ts = time.perf_counter()
+                with torch.cuda.stream(gph.stream):
+                    for _ in range(reps):
+                        gph.graph.replay()
+                torch.cuda.synchronize()
+                dt = (time.perf_counter() - ts) / reps
+                rows.append({"rerank_k": rr, "batch": bs, "qps": bs / dt, "ms_per_batch": dt * 1e3,
+                             "recall@10_full_batch": rec})
+                del gph
+            log("batching B=%d rerank %d recall@10 %.4f; QPS by batch %s" %
+                (B, rr, rec, {r["batch"]: round(r["qps"]) for r in rows if r["rerank_k"] == rr}))
+        # pass-B launch time of the full batch for the roofline
+        erq.profile_enable(True)
+        erq.profile_read("scan_b", reset=True)
+        ix.search(q, 256, k, 0, nprobe_q=npq)
+        torch.cuda.synchronize()
+        sb = erq.profile_read("scan_b", reset=True)
+        erq.profile_read("scan", reset=True)
+        erq.profile_enable(False)
+        probes = erq.coarse_probe(q, cent, 256).cpu().numpy()
+        probes[np.arange(256)[None, :] >= own[:, None]] = -1
+        roof = scan_roofline(ix, nq, dp, B, sizes, probes, sb)
+        out["by_bits"].append({"bits": B, "encode_codes_per_s": enc, "autotune": tuned, "rows": rows,
+                               "scan_full_batch": roof})
+        log("batching B=%d encode %.3g codes/s, scan %s" % (B, enc, roof))
+        ix.close()
+        torch.cuda.empty_cache()
+    log("total %.1fs" % (time.time() - t0))
+    print(json.dumps(out), flush=True)
+
+
+def run_serving(args):
+    """Serving workload: N = 5,000,000 x D = 3072 Gaussian mixture (2048
+    components, Zipf weights, sigma 0.3), 16384 k-means lists, B = 4 codes
+    and raw vectors resident in HBM; requests of one query with k in {10, 100}
+    and nprobe in {16, 64}, Poisson arrivals, admitted by memory."""
+    import torch
+    from paper_2409_09913_amd import erq, serve, synth
+    dev = torch.device("cuda:0")
+    erq.load()
+    t0 = time.time()
+    n, dp, nl, nq = args.serve_n, 3072, 16384, 2000
+    x, _ = synth.gmm_device(n, dp, 2048, 0.3, zipf=True, device=dev)
+    q = torch.from_numpy(synth.gmm(nq, dp, 2048, 0.3, zipf=True, stream=synth.S_QUERY)).to(dev)
+    log("serving workload: %d x %d data in %.1fs" % (n, dp, time.time() - t0))
+    ts = time.perf_counter()
+    cent, assign = erq.kmeans(x, nl, iters=args.serve_kmeans_iters)
+    torch.cuda.synchronize()
+    t_km = time.perf_counter() - ts
+    sizes = torch.bincount(assign.long(), minlength=nl).cpu().numpy()
+    log("k-means %d lists, %d rounds: %.1fs; sizes %d..%d" % (nl, args.serve_kmeans_iters, t_km, sizes.min(),
+                                                            sizes.max()))
+    ix = erq.Index(dp, 4, nl, None, seed=240909913)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    ix.build(x, cent, assign, keep_raw=False)
+    torch.cuda.synchronize()
+    enc = n / (time.perf_counter() - ts)
+    ix.set_raw(x)
+    truth = brute_topk(x, q, 100).cpu().numpy()
+    log("encode %.3g codes/s; ground truth done %.1fs" % (enc, time.time() - t0))
+    sweep = []
+    for kq, rrs in ((10, (0, 20, 50, 100)), (100, (0, 100, 200, 300))):
+        for npr in (16, 32, 64):
+            for rr in rrs:
+                ids, _ = ix.search(q, npr, kq, rr)
+                torch.cuda.synchronize()
+                tt = time.perf_counter()
+                for _ in range(3):
+                    ids, _ = ix.search(q, npr, kq, rr)
+                torch.cuda.synchronize()
+                qps = 3 * nq / (time.perf_counter() - tt)
+                rec = recall_at(ids.cpu().numpy(), truth, kq)
+                sweep.append({"k": kq, "nprobe": npr, "rerank_k": rr, "recall": rec, "qps": qps})
+                log("serving sweep k=%d nprobe %d rerank %d recall@%d %.4f QPS %.0f" % (kq, npr, rr, kq, rec, qps))
+    # re-rank depth per k: the smallest reaching the target at nprobe 64
+    rr_of = {}
+    for kq in (10, 100):
+        ok = [r for r in sweep if r["k"] == kq and r["nprobe"] == 64 and r["recall"] >= args.target_recall]
+        rr_of[kq] = min((r["rerank_k"] for r in ok), default=max(r["rerank_k"] for r in sweep if r["k"] == kq))
+    srv = serve.Server(ix, max_batch=256, max_nprobe=64, max_k=100, max_rerank=max(rr_of.values()), slots=4,
+                       mem_budget=2 << 30)
+    serve.poisson_run(srv, q, rate=5000.0, n_requests=300, per_request=1, k=(10, 100), nprobes=(16, 64),
+                      rerank_k=rr_of, seed=1)
+    by_rate = {}
+    for rate in (1000.0, 2000.0, 5000.0, 10000.0, 20000.0, 50000.0):
+        reqs, p50, p99, sq = serve.poisson_run(srv, q, rate=rate, n_requests=args.serve, per_request=1,
+                                               k=(10, 100), nprobes=(16, 64), rerank_k=rr_of, seed=7)
+        hit = [len(set(r.ids[0].cpu().numpy().tolist()) & set(truth[(r.rid * 1) % (nq - 1)][:r.k].tolist())) / r.k
+               for r in reqs[:400]]
+        by_rate["%d_rps" % rate] = {"p50_ms": p50, "p99_ms": p99, "qps": sq, "recall_mixed_k": float(np.mean(hit)),
+                                    "batches": srv.batches}
+        log("serving %d req/s: p50 %.3f ms p99 %.3f ms, %.0f QPS, recall (k 10/100 mix) %.4f" %
+            (rate, p50, p99, sq, np.mean(hit)))
+    # scan roofline of a 256-query batch at nprobe 64 (lists rarely shared: the HBM-bound regime)
+    erq.profile_enable(True)
+    erq.profile_read("scan_b", reset=True)
+    ix.search(q[:256].contiguous(), 64, 10, 0)
+    torch.cuda.synchronize()
+    sb = erq.profile_read("scan_b", reset=True)
+    erq.profile_read("scan", reset=True)
+    erq.profile_enable(False)
+    probes = erq.coarse_probe(q[:256].contiguous(), cent, 64).cpu().numpy()
+    roof = scan_roofline(ix, 256, dp, 4, sizes, probes, sb)
+    log("scan at batch 256, nprobe 64: %s" % roof)
+    out = {"metric": "serving: p50/p99 latency and sustained QPS under Poisson arrivals; QPS at recall@10>=0.95",
+           "unit": "QPS", "config": {"workload": "serving: N=%d x D=3072 GMM(2048, Zipf, sigma 0.3), IVF 16384, B=4, "
+                                                  "raw resident; requests: 1 query, k in {10,100}, nprobe in "
+                                                  "{16,64}" % n},
+           "encode_codes_per_s": enc, "kmeans_s": t_km, "sweep": sweep, "rerank_by_k": rr_of,
+           "serving": {"slots": srv.slots_admitted, "pool_bytes": srv.pool.size, "by_rate": by_rate},
+           "scan_batch256_np64": roof}
+    log("total %.1fs" % (time.time() - t0))
+    print(json.dumps(out), flush=True)
 
 
 def calib_copy():

@@ -40,7 +40,7 @@ class SearchGraph:
     launches of the library (it clears memory with its own fill kernels)."""
 
     def __init__(self, index: erq.Index, nq: int, nprobe: int, k: int, rerank_k: int = 0,
-                 stream: torch.cuda.Stream | None = None):
+                 stream: torch.cuda.Stream | None = None, per_query: bool = False):
         dev = torch.device("cuda", torch.cuda.current_device())
         self.index, self.nq, self.nprobe, self.k, self.rerank_k = index, nq, nprobe, k, rerank_k
         self.stream = stream or torch.cuda.Stream(device=dev)
@@ -48,13 +48,17 @@ class SearchGraph:
         self.ws = torch.empty(index.search_workspace_size(nq, nprobe, k, rerank_k), dtype=torch.uint8, device=dev)
         self.ids = torch.empty((nq, k), dtype=torch.int64, device=dev)
         self.dist = torch.empty((nq, k), dtype=torch.float32, device=dev)
+        # per_query: static per-query (nprobe, k, rerank_k) rows the caller fills before a replay
+        self.params = torch.stack([torch.full((nq,), v, dtype=torch.int32, device=dev)
+                                   for v in (nprobe, k, rerank_k)]) if per_query else None
+        pq = dict(nprobe_q=self.params[0], k_q=self.params[1], rerank_q=self.params[2]) if per_query else {}
         with torch.cuda.stream(self.stream):
             # one eager run first: the library's one-time kernel attributes are set outside capture
-            self.index.search(self.q, nprobe, k, rerank_k, ws=self.ws, out=(self.ids, self.dist))
+            self.index.search(self.q, nprobe, k, rerank_k, ws=self.ws, out=(self.ids, self.dist), **pq)
         self.stream.synchronize()
         self.graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(self.graph, stream=self.stream, capture_error_mode="thread_local"):
-            self.index.search(self.q, nprobe, k, rerank_k, ws=self.ws, out=(self.ids, self.dist))
+            self.index.search(self.q, nprobe, k, rerank_k, ws=self.ws, out=(self.ids, self.dist), **pq)
         self.stream.synchronize()
 
     def run(self, q: torch.Tensor):
@@ -259,18 +263,23 @@ class Server:
 
 
 def poisson_run(server: Server, queries: torch.Tensor, rate: float, n_requests: int, per_request: int,
-                k: int, nprobes, rerank_k: int = 0, seed: int = 0):
+                k, nprobes, rerank_k=0, seed: int = 0):
     """Requests of `per_request` queries arrive as a Poisson process of `rate`
-    requests per second, each with an nprobe drawn from `nprobes`; returns the
-    finished requests and (p50, p99) latency in ms and the sustained QPS."""
+    requests per second, each with an nprobe drawn from `nprobes` and a k
+    drawn from `k` (an int or a tuple); `rerank_k` is an int or a dict k ->
+    re-rank depth.  Returns the finished requests, (p50, p99) latency in ms
+    and the sustained QPS."""
     g = np.random.default_rng(seed)
     gaps = g.exponential(1.0 / rate, n_requests)
     arrivals = np.cumsum(gaps)
     nq = queries.shape[0]
+    ks = (k,) if isinstance(k, int) else tuple(k)
     reqs = []
     for i in range(n_requests):
         lo = (i * per_request) % max(nq - per_request, 1)
-        reqs.append(Request(i, queries[lo:lo + per_request], k, int(g.choice(nprobes)), rerank_k,
+        kr = int(g.choice(ks))
+        rr = rerank_k.get(kr, 0) if isinstance(rerank_k, dict) else rerank_k
+        reqs.append(Request(i, queries[lo:lo + per_request], kr, int(g.choice(nprobes)), rr,
                             arrival=float(arrivals[i])))
     torch.cuda.synchronize()
     server.t0 = time.perf_counter()

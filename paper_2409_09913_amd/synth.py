@@ -13,6 +13,9 @@ Recipes (named by what they are, with their sizes):
   * anisotropic(...) Gaussian with per-dimension variance i^-0.5.
   * spherical_clusters(...) unit vectors around uniform directions
                      (embedding-like).
+  * gmm_device(...), clustered_anisotropic_device(...): the same kinds of
+                     rows drawn on the GPU with a seeded torch generator, for
+                     workloads too large to draw on the host (5M x 3072).
 """
 from __future__ import annotations
 
@@ -234,3 +237,53 @@ def edge_rows(dp: int, seed: int = SEED) -> np.ndarray:
     mix = g.standard_normal(dp); mix[g.random(dp) < 0.5] = 0.0; rows.append(mix)
     q = np.round(g.standard_normal(dp) * 4) / 4; rows.append(q)
     return np.asarray(rows, dtype=np.float32)
+
+
+# --------------------------------------------------------------------------
+# Device-side draws for the largest workloads (seeded torch generators).
+# --------------------------------------------------------------------------
+def gmm_device(n: int, d: int, ncomp: int, sigma: float = 0.3, zipf: bool = False, seed: int = SEED,
+               stream: int = S_BASE, device="cuda", chunk: int = 1 << 18):
+    """n x d rows of the Gaussian mixture of gmm() (same component means),
+    drawn on `device` in chunks; returns (rows float32, labels int64)."""
+    import torch
+    means = torch.from_numpy(rng(seed, S_MEANS).standard_normal((ncomp, d)).astype(np.float32)).to(device)
+    w = _zipf_weights(ncomp) if zipf else np.full(ncomp, 1.0 / ncomp)
+    wt = torch.from_numpy(w).to(device)
+    g = torch.Generator(device=device).manual_seed(int(seed) * 16 + stream)
+    x = torch.empty((n, d), dtype=torch.float32, device=device)
+    lab = torch.empty(n, dtype=torch.int64, device=device)
+    for lo in range(0, n, chunk):
+        m = min(chunk, n - lo)
+        lb = torch.multinomial(wt, m, replacement=True, generator=g)
+        x[lo:lo + m] = means[lb] + sigma * torch.randn((m, d), device=device, generator=g)
+        lab[lo:lo + m] = lb
+    return x, lab
+
+
+def clustered_anisotropic_device(sizes, d: int, noise: float = 0.5, seed: int = SEED, device="cuda",
+                                 chunk: int = 1 << 18):
+    """Clusters of the given sizes around centres drawn from the Gaussian with
+    variance i^-0.5 in dimension i; members = centre + noise * (a draw of the
+    same Gaussian).  Returns (rows float32 on device, labels int32, centres
+    float32 on device); rows are ordered by cluster."""
+    import torch
+    sizes = np.asarray(sizes, np.int64)
+    sd = torch.from_numpy((np.arange(1, d + 1, dtype=np.float64) ** -0.25).astype(np.float32)).to(device)
+    g = torch.Generator(device=device).manual_seed(int(seed) * 16 + S_MEANS)
+    cent = torch.randn((len(sizes), d), device=device, generator=g) * sd
+    lab = torch.from_numpy(np.repeat(np.arange(len(sizes), dtype=np.int32), sizes)).to(device)
+    n = int(sizes.sum())
+    x = torch.empty((n, d), dtype=torch.float32, device=device)
+    g2 = torch.Generator(device=device).manual_seed(int(seed) * 16 + S_BASE)
+    for lo in range(0, n, chunk):
+        m = min(chunk, n - lo)
+        x[lo:lo + m] = cent[lab[lo:lo + m].long()] + noise * torch.randn((m, d), device=device, generator=g2) * sd
+    return x, lab, cent
+
+
+def power_law_sizes(nlist: int, lo: int, hi: int, alpha: float, seed: int = SEED) -> np.ndarray:
+    """nlist sizes from a Pareto law of exponent alpha truncated to [lo, hi]."""
+    g = rng(seed, S_AUX, 7)
+    u = g.random(nlist)
+    return np.clip(np.floor(lo * (1.0 - u) ** (-1.0 / alpha)), lo, hi).astype(np.int64)

@@ -278,7 +278,7 @@ def _sampled_parity(gi, ge, sample, dev_index, qrot, probes, B, kk):
 @pytest.mark.parametrize("B", [3, 5, 7])
 def test_batching_full_size(B):
     dp, nl, kk, nq = 960, 8192, 10, 4096
-    sizes = _power_law_sizes(nl, 20, 5000, 1.1, seed=40 + B)
+    sizes = synth.power_law_sizes(nl, 20, 5000, 0.76, seed=40 + B)     # mean about 244: about 2M members
     say("batching full size B", B, "members", int(sizes.sum()), "lists", nl)
     dix = _device_index(sizes, dp, B, seed=41 + B)
     off, ids, codes, fa, fr, crot = dix
