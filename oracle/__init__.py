@@ -59,6 +59,12 @@ def _load():
                                    p, i64, p, i32, i32, i32, p, p]
         lib.orc_search.restype = i32
         lib.orc_rerank.argtypes = [p, i32, p, i64, p, i32, i32, p, p]
+        lib.orc_search_ip.argtypes = [p, p, p, p, p, p, p, i64, i32, i32,
+                                      p, i64, p, i32, i32, i32, p, p]
+        lib.orc_search_ip.restype = i32
+        lib.orc_probe_ip.argtypes = [p, i64, p, i64, i32, i32, p, p]
+        lib.orc_rerank_ip.argtypes = [p, i32, p, i64, p, i32, i32, p, p]
+        lib.orc_knn_ip.argtypes = [p, i64, i32, p, i64, i32, p, p]
         lib.orc_knn.argtypes = [p, i64, i32, p, i64, i32, p, p]
         lib.orc_num_threads.restype = i32
         lib.orc_set_threads.argtypes = [i32]
@@ -220,4 +226,61 @@ def knn(x, q, k):
     oi = np.empty((q.shape[0], k), np.int64)
     od = np.empty((q.shape[0], k), np.float64)
     _load().orc_knn(_p(x), x.shape[0], x.shape[1], _p(q), q.shape[0], k, _p(oi), _p(od))
+    return oi, od
+
+
+# --------------------------------------------------------------------------
+# Inner-product metric: values are negated inner products, ascending.
+# --------------------------------------------------------------------------
+def search_ip(list_off, ids, codes, f_add, f_rescale, crot, qrot, probes, B, kk, cos_oo=None, est_mode=0):
+    """IVF scan by largest estimated inner product (erq_oracle.c, orc_search_ip)."""
+    list_off = _c(list_off, np.int64)
+    ids = _c(ids, np.int64)
+    codes = _c(codes, np.uint8)
+    fa = _c(f_add, np.float32)
+    fr = _c(f_rescale, np.float32)
+    crot = _c(crot, np.float32)
+    qrot = _c(qrot, np.float32)
+    probes = _c(probes, np.int32)
+    co = _c(cos_oo if cos_oo is not None else np.ones(ids.shape[0]), np.float64)
+    nq, dp = qrot.shape
+    nprobe = probes.shape[1]
+    oi = np.empty((nq, kk), np.int64)
+    od = np.empty((nq, kk), np.float64)
+    rc = _load().orc_search_ip(_p(list_off), _p(ids), _p(codes), _p(fa), _p(fr), _p(co),
+                               _p(crot), crot.shape[0], dp, B, _p(qrot), nq, _p(probes),
+                               nprobe, kk, est_mode, _p(oi), _p(od))
+    if rc != 0:
+        raise ValueError("bad arguments to search_ip")
+    return oi, od
+
+
+def probe_ip(q, cent, nprobe):
+    """nprobe centroids of largest inner product (FP64), ties by id."""
+    q = _c(q, np.float32)
+    cent = _c(cent, np.float32)
+    nq, dp = q.shape
+    pr = np.empty((nq, nprobe), np.int32)
+    pd = np.empty((nq, nprobe), np.float64)
+    _load().orc_probe_ip(_p(q), nq, _p(cent), cent.shape[0], dp, nprobe, _p(pr), _p(pd))
+    return pr, pd
+
+
+def rerank_ip(x, q, cand, k):
+    x = _c(x, np.float32)
+    q = _c(q, np.float32)
+    cand = _c(cand, np.int64)
+    nq = q.shape[0]
+    oi = np.empty((nq, k), np.int64)
+    od = np.empty((nq, k), np.float64)
+    _load().orc_rerank_ip(_p(x), x.shape[1], _p(q), nq, _p(cand), cand.shape[1], k, _p(oi), _p(od))
+    return oi, od
+
+
+def knn_ip(x, q, k):
+    x = _c(x, np.float32)
+    q = _c(q, np.float32)
+    oi = np.empty((q.shape[0], k), np.int64)
+    od = np.empty((q.shape[0], k), np.float64)
+    _load().orc_knn_ip(_p(x), x.shape[0], x.shape[1], _p(q), q.shape[0], k, _p(oi), _p(od))
     return oi, od

@@ -523,6 +523,163 @@ void orc_set_threads(int n)
 #endif
 }
 
+/* ------------------------------------------------------------------------ */
+/* Inner-product metric (the paper's conclusion: the method adapts to inner  */
+/* product and cosine).  With c the list centroid and r = o_r - c:          */
+/*   <o_r, q_r> = <c, q_r> + <r, q_r>,   <r, q_r> = ||r|| <o, q'>,           */
+/* and <o, q'> is estimated as <o_bar, q'>/<o_bar, o> (Lemma 2.1, unbiased  */
+/* for any q' by linearity), which with the stored factors is               */
+/*   <r, q_r> ~ ||r||^2 <y, q'> / <y, r'> = -(f_rescale / 2) <y, q'>.       */
+/* Results are ordered by the NEGATED inner product (smallest first), so   */
+/* the top-k are the largest inner products.  <c, q_r> = <c', q'> (the     */
+/* rotation preserves inner products), in FP64 from the rotated inputs.    */
+/* est_mode 0: int8 query (decided in FP32 like the L2 scan); 2: float     */
+/* query with the stored factors; 1: float query, paper form with          */
+/* <o_bar, o> (cos_oo) and ||r|| = sqrt(f_add).                            */
+/* ------------------------------------------------------------------------ */
+int orc_search_ip(const int64_t* list_off, const int64_t* ids, const uint8_t* codes,
+                  const float* f_add, const float* f_rescale, const double* cos_oo,
+                  const float* crot, int64_t C, int dp, int B,
+                  const float* qrot, int64_t nq, const int32_t* probes, int nprobe,
+                  int kk, int est_mode, int64_t* out_ids, double* out_d)
+{
+    if (dp <= 0 || B < 1 || B > 8 || kk < 1) return -1;
+    int bad = 0;
+    #pragma omp parallel reduction(|:bad)
+    {
+        int8_t* qq = (int8_t*)malloc((size_t)dp);
+        const double half = ((double)((1 << B) - 1)) / 2.0;
+        int64_t cap = 1024;
+        orc_cand* cand = (orc_cand*)malloc(sizeof(orc_cand) * (size_t)cap);
+        #pragma omp for schedule(dynamic, 1)
+        for (int64_t iq = 0; iq < nq; ++iq) {
+            int64_t nc = 0;
+            float delta; int32_t qsum;
+            const float* qv = qrot + iq * (int64_t)dp;
+            orc_query_quant(qv, dp, qq, &delta, &qsum);
+            double qs = 0.0, qn = 0.0;
+            for (int i = 0; i < dp; ++i) { qs += (double)qv[i]; qn += (double)qv[i] * qv[i]; }
+            for (int p = 0; p < nprobe; ++p) {
+                int32_t l = probes[iq * nprobe + p];
+                if (l < 0) continue;
+                if (l >= C) { bad = 1; continue; }
+                const float* cv = crot + (int64_t)l * dp;
+                double cq = 0.0;
+                for (int i = 0; i < dp; ++i) cq += (double)cv[i] * (double)qv[i];
+                int64_t lo = list_off[l], hi = list_off[l + 1];
+                if (nc + (hi - lo) > cap) {
+                    while (nc + (hi - lo) > cap) cap *= 2;
+                    cand = (orc_cand*)realloc(cand, sizeof(orc_cand) * (size_t)cap);
+                }
+                for (int64_t v = lo; v < hi; ++v) {
+                    const uint8_t* cd = codes + v * (int64_t)dp;
+                    double rq;                                  /* estimate of <r, q_r> */
+                    if (est_mode == 0) {
+                        int64_t ip = 0;
+                        for (int i = 0; i < dp; ++i) ip += (int64_t)cd[i] * (int64_t)qq[i];
+                        const double yq = 0.5 * (double)delta * (double)(2 * ip - (int64_t)((1 << B) - 1) * qsum);
+                        rq = -0.5 * (double)f_rescale[v] * yq;
+                    } else if (est_mode == 2) {
+                        double yq = 0.0;
+                        for (int i = 0; i < dp; ++i) yq += ((double)cd[i] - half) * (double)qv[i];
+                        rq = -0.5 * (double)f_rescale[v] * yq;
+                    } else {
+                        /* ||r|| <o_bar, q'> / <o_bar, o>, <o_bar, q'> = (<y_u, q'> - half sum q') / ||y|| */
+                        double yu = 0.0, ny = 0.0;
+                        for (int i = 0; i < dp; ++i) {
+                            yu += (double)cd[i] * (double)qv[i];
+                            const double y = (double)cd[i] - half;
+                            ny += y * y;
+                        }
+                        rq = (f_add[v] > 0.0f) ? sqrt((double)f_add[v]) * ((yu - half * qs) / sqrt(ny)) / cos_oo[v] : 0.0;
+                    }
+                    cand[nc].d = -(cq + rq); cand[nc].id = ids[v]; ++nc;
+                }
+            }
+            (void)qn;
+            orc_take_k(cand, nc, kk, out_ids + iq * kk, out_d + iq * kk);
+        }
+        free(qq); free(cand);
+    }
+    return bad ? -1 : 0;
+}
+
+/* The nprobe centroids of largest inner product with q (FP64), ties by id;
+   pdist receives the negated inner products. */
+void orc_probe_ip(const float* q, int64_t nq, const float* cent, int64_t C, int dp,
+                  int nprobe, int32_t* probes, double* pdist)
+{
+    #pragma omp parallel
+    {
+        orc_cand* c = (orc_cand*)malloc(sizeof(orc_cand) * (size_t)C);
+        int64_t* tid = (int64_t*)malloc(sizeof(int64_t) * (size_t)nprobe);
+        double* td = (double*)malloc(sizeof(double) * (size_t)nprobe);
+        #pragma omp for schedule(dynamic, 4)
+        for (int64_t iq = 0; iq < nq; ++iq) {
+            const float* qv = q + iq * (int64_t)dp;
+            for (int64_t j = 0; j < C; ++j) {
+                const float* cv = cent + j * (int64_t)dp;
+                double s = 0.0;
+                for (int i = 0; i < dp; ++i) s += (double)qv[i] * (double)cv[i];
+                c[j].d = -s; c[j].id = j;
+            }
+            orc_take_k(c, C, nprobe, tid, td);
+            for (int j = 0; j < nprobe; ++j) {
+                probes[iq * nprobe + j] = (int32_t)tid[j];
+                if (pdist) pdist[iq * nprobe + j] = td[j];
+            }
+        }
+        free(c); free(tid); free(td);
+    }
+}
+
+/* Exact re-rank / k-NN by largest inner product (values: negated inner
+   products, ascending; cand ids < 0 skipped). */
+void orc_rerank_ip(const float* x, int dp, const float* q, int64_t nq,
+                   const int64_t* cand, int kc, int k, int64_t* out_ids, double* out_d)
+{
+    #pragma omp parallel
+    {
+        orc_cand* c = (orc_cand*)malloc(sizeof(orc_cand) * (size_t)(kc > 0 ? kc : 1));
+        #pragma omp for schedule(dynamic, 4)
+        for (int64_t iq = 0; iq < nq; ++iq) {
+            int64_t n = 0;
+            for (int j = 0; j < kc; ++j) {
+                int64_t id = cand[iq * kc + j];
+                if (id < 0) continue;
+                const float* xv = x + id * (int64_t)dp;
+                const float* qv = q + iq * (int64_t)dp;
+                double s = 0.0;
+                for (int i = 0; i < dp; ++i) s += (double)xv[i] * (double)qv[i];
+                c[n].d = -s; c[n].id = id; ++n;
+            }
+            orc_take_k(c, n, k, out_ids + iq * k, out_d + iq * k);
+        }
+        free(c);
+    }
+}
+
+void orc_knn_ip(const float* x, int64_t n, int dp, const float* q, int64_t nq, int k,
+                int64_t* out_ids, double* out_d)
+{
+    #pragma omp parallel
+    {
+        orc_cand* c = (orc_cand*)malloc(sizeof(orc_cand) * (size_t)(n > 0 ? n : 1));
+        #pragma omp for schedule(dynamic, 1)
+        for (int64_t iq = 0; iq < nq; ++iq) {
+            const float* qv = q + iq * (int64_t)dp;
+            for (int64_t r = 0; r < n; ++r) {
+                const float* xv = x + r * (int64_t)dp;
+                double s = 0.0;
+                for (int i = 0; i < dp; ++i) s += (double)xv[i] * (double)qv[i];
+                c[r].d = -s; c[r].id = r;
+            }
+            orc_take_k(c, n, k, out_ids + iq * k, out_d + iq * k);
+        }
+        free(c);
+    }
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP
