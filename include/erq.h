@@ -40,6 +40,15 @@ typedef enum {
     ERQ_EDEVICE = 5        /* HIP runtime error (message has the HIP text) */
 } erq_status;
 
+/* Distance of an index.  L2: squared Euclidean distance (the paper's
+   setting).  IP: inner product, results ordered by the negated inner
+   product (largest first); the estimate is <c, q> + <r, q> with
+   <r, q> = ||r|| <o, q'> estimated as <o_bar, q'>/<o_bar, o> (Lemma 2.1),
+   which the stored factors give as -(f_rescale / 2) <y_bar, q'>.  COSINE:
+   the inner product of rows and queries normalised to unit length by the
+   library (the paper's conclusion names both adaptations). */
+typedef enum { ERQ_METRIC_L2 = 0, ERQ_METRIC_IP = 1, ERQ_METRIC_COSINE = 2 } erq_metric;
+
 /* Thread-local description of the last non-zero status of this thread. */
 const char* erq_last_error(void);
 
@@ -82,7 +91,9 @@ int erq_quantize(const float* rrot, int64_t n, int32_t dp, int32_t bits,
 /* ------------------------------------------------------------------------ */
 /* Coarse probe of IVF (Sec. 4.1): for every query the nprobe nearest list   */
 /* centroids by squared Euclidean distance ||q||^2 + ||c||^2 - 2 q.c,        */
-/* ascending by (distance, list id).  q.c is taken on the BF16 matrix cores */
+/* ascending by (distance, list id); metric IP or COSINE: by the negated     */
+/* inner product -q.c (largest inner products first; the caller normalises  */
+/* for cosine).  q.c is taken on the BF16 matrix cores */
 /* from a hi/lo split of both FP32 operands (three products, FP32 sums):    */
 /* error <= 2^-14 sum|q_i c_i| plus FP32 accumulation, so only near-ties   */
 /* may order differently from exact arithmetic.                             */
@@ -94,7 +105,7 @@ int erq_quantize(const float* rrot, int64_t n, int32_t dp, int32_t bits,
 /* ------------------------------------------------------------------------ */
 int erq_probe_workspace_size(int64_t nq, int64_t nlist, int32_t dp, int32_t nprobe, size_t* bytes);
 int erq_coarse_probe(const float* q, int64_t nq, const float* centroids, int64_t nlist,
-                     int32_t dp, int32_t nprobe, int32_t* probes, float* pdist,
+                     int32_t dp, int32_t nprobe, int32_t metric, int32_t* probes, float* pdist,
                      void* workspace, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------ */
@@ -114,11 +125,11 @@ typedef struct erq_index_s* erq_index;
    (dp, seed).  No device work. */
 int erq_sample_rotation(int32_t dp, uint64_t seed, float* P_host);
 
-/* Empty index for dp-dimensional vectors, B = bits, nlist lists.  P (device,
-   dp x dp FP32) is copied; P = NULL samples it with erq_sample_rotation(dp,
-   seed).  Synchronises `stream`. */
+/* Empty index for dp-dimensional vectors, B = bits, nlist lists, distance
+   `metric` (erq_metric).  P (device, dp x dp FP32) is copied; P = NULL
+   samples it with erq_sample_rotation(dp, seed).  Synchronises `stream`. */
 int erq_index_create(int32_t dp, int32_t bits, int64_t nlist, const float* P,
-                     uint64_t seed, void* stream, erq_index* out);
+                     uint64_t seed, int32_t metric, void* stream, erq_index* out);
 /* Frees everything the index owns.  No work that uses the index may still be
    in flight (freeing device memory waits for the device). */
 int erq_index_destroy(erq_index idx);
@@ -127,7 +138,8 @@ int erq_index_destroy(erq_index idx);
 int erq_index_get_rotation(erq_index idx, float* P_out, void* stream);
 
 /* Writes the whole index to a file (host path): a versioned header (magic
-   "ERQIDX", version 1, dp, bits, nlist, n, tiles, scan schedule, seed),
+   "ERQIDX", version 1, dp, bits, raw kept, metric, nlist, n, tiles, scan
+   schedule, seed),
    then P, raw and rotated centroids, list offsets, ids, factors, scan
    factors, packed codes and, when kept, the raw vectors, in native byte
    order.  Synchronises `stream`. */
@@ -222,6 +234,10 @@ int erq_rerank(erq_index idx, const float* q, int64_t nq, const int64_t* cand, i
                int32_t k, int64_t* out_ids, float* out_dist, void* stream);
 
 /* ------------------------------------------------------------------------ */
+/* With the inner-product metrics (erq_metric) the per-pair term is -<c', q'> */
+/* (from the probe in erq_search, computed per pair in erq_scan), the member */
+/* factors are (0, f_rescale / 2), and the results are the negated estimated */
+/* inner products; the rest is the same.                                     */
 /* Whole query path (Sec. 2.1 K-NN, Sec. 4.1 IVF): rotate, coarse probe,     */
 /* scan, and exact re-rank of the best estimates.  The rotation q' = q P is  */
 /* erq_rotate's precision 2 (error <= 2^-14 sum_k |q_k P_kj| per output,     */
@@ -236,6 +252,9 @@ int erq_rerank(erq_index idx, const float* q, int64_t nq, const int64_t* cand, i
 /* not depend on the other queries of the batch.  Output nq x k ascending by */
 /* (distance, id): estimated squared distances for a query without re-rank, */
 /* exact FP32 ones with it; columns past the query's k_q are (-1, +inf).     */
+/* Inner-product metrics: negated (estimated or exact) inner products; the   */
+/* cosine metric normalises the queries first (rows were normalised at      */
+/* build, and raw rows kept for re-rank are stored normalised).             */
 /* workspace: erq_search_workspace_size(nq, nprobe, k, rerank_k).           */
 /* ------------------------------------------------------------------------ */
 int erq_search_workspace_size(erq_index idx, int64_t nq, int32_t nprobe, int32_t k,

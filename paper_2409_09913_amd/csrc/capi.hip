@@ -22,7 +22,7 @@ hipError_t launch_gemm_bf16x3(const unsigned short* Ah, const unsigned short* Al
                               float* out, int64_t ldo, hipStream_t st);
 hipError_t launch_sqdist_pre(const unsigned short* Ah, const unsigned short* Al, int64_t n,
                              const unsigned short* Bh, const unsigned short* Bl, int64_t N, int K,
-                             const float* an2, const float* bn2, float* out, hipStream_t st);
+                             const float* an2, const float* bn2, float* out, hipStream_t st, int neg_ip);
 hipError_t launch_pack_n(const uint8_t* codes, const int64_t* list_off, const int64_t* tile_off,
                          int64_t nlist, int dp, int bits, int64_t ntiles, uint8_t* packed, hipStream_t st);
 hipError_t launch_unpack_n(const uint8_t* packed, const int64_t* list_off, const int64_t* tile_off,
@@ -205,7 +205,7 @@ struct ProbePre {           // operands already split (and their norms), or null
 };
 int probe_impl(const float* q, int64_t nq, const float* cent, int64_t nlist, int dp, int nprobe,
                int32_t* probes, float* pdist, void* ws, size_t ws_bytes, hipStream_t st,
-               const ProbePre& pre = ProbePre());
+               const ProbePre& pre = ProbePre(), int metric = ERQ_METRIC_L2);
 
 // distances nq x nlist, norms, and the BF16 hi/lo planes of both operands
 size_t probe_ws(int64_t nq, int64_t nlist, int dp) {
@@ -214,9 +214,11 @@ size_t probe_ws(int64_t nq, int64_t nlist, int dp) {
 }
 
 // pre: the BF16 planes and norms of the queries and / or centroids when the
-// caller has them (else computed here)
+// caller has them (else computed here).  metric L2: ascending squared
+// distances; inner product / cosine: ascending negated inner products.
 int probe_impl(const float* q, int64_t nq, const float* cent, int64_t nlist, int dp, int nprobe,
-               int32_t* probes, float* pdist, void* ws, size_t ws_bytes, hipStream_t st, const ProbePre& pre)
+               int32_t* probes, float* pdist, void* ws, size_t ws_bytes, hipStream_t st, const ProbePre& pre,
+               int metric)
 {
     if (ws_bytes < probe_ws(nq, nlist, dp)) return fail(ERQ_ENOMEM, "coarse probe: workspace too small");
     char* w = (char*)ws;
@@ -234,7 +236,7 @@ int probe_impl(const float* q, int64_t nq, const float* cent, int64_t nlist, int
     else ERQ_HIP(launch_split_norm(q, nq, dp, qh, ql, qn, st));
     if (pre.ch && pre.cl && pre.cn) { uch = pre.ch; ucl = pre.cl; ucn = pre.cn; }
     else ERQ_HIP(launch_split_norm(cent, nlist, dp, ch, cl, cn, st));
-    ERQ_HIP(launch_sqdist_pre(uqh, uql, nq, uch, ucl, nlist, dp, uqn, ucn, D, st));
+    ERQ_HIP(launch_sqdist_pre(uqh, uql, nq, uch, ucl, nlist, dp, uqn, ucn, D, st, metric != ERQ_METRIC_L2));
     ERQ_HIP(launch_row_topk(D, nq, nlist, nprobe, probes, pdist, st));
     prof_end(pr, st);
     return ERQ_OK;
@@ -334,7 +336,7 @@ constexpr uint32_t kFileVersion = 1;
 struct FileHeader {
     char magic[8];
     uint32_t version;
-    int32_t dp, bits, has_raw;
+    int32_t dp, bits, has_raw, metric, reserved;     // reserved = 0 (keeps the int64 fields aligned)
     int64_t nlist, n, ntiles;
     int32_t tune[4];
     uint64_t seed;
@@ -439,13 +441,16 @@ int erq_probe_workspace_size(int64_t nq, int64_t nlist, int32_t dp, int32_t npro
 }
 
 int erq_coarse_probe(const float* q, int64_t nq, const float* centroids, int64_t nlist, int32_t dp,
-                     int32_t nprobe, int32_t* probes, float* pdist, void* workspace, size_t ws_bytes, void* stream)
+                     int32_t nprobe, int32_t metric, int32_t* probes, float* pdist, void* workspace, size_t ws_bytes,
+                     void* stream)
 {
+    if (metric < ERQ_METRIC_L2 || metric > ERQ_METRIC_COSINE) return fail(ERQ_EINVAL, "erq_coarse_probe: bad metric");
     if (int rc = check_dp(dp, "erq_coarse_probe")) return rc;
     if (nq < 0 || nlist < 1 || nlist > (1LL << 31) - 1) return fail(ERQ_EINVAL, "erq_coarse_probe: bad sizes");
     if (nprobe < 1 || nprobe > 1024 || nprobe > nlist) return fail(ERQ_EUNSUPPORTED, "erq_coarse_probe: nprobe must be in [1, min(nlist, 1024)]");
     if (nq > 0 && (!q || !centroids || !probes || !workspace)) return fail(ERQ_EINVAL, "erq_coarse_probe: null pointer");
-    return probe_impl(q, nq, centroids, nlist, dp, nprobe, probes, pdist, workspace, ws_bytes, (hipStream_t)stream);
+    return probe_impl(q, nq, centroids, nlist, dp, nprobe, probes, pdist, workspace, ws_bytes, (hipStream_t)stream,
+                      ProbePre(), metric);
 }
 
 int erq_sample_rotation(int32_t dp, uint64_t seed, float* P_host)
@@ -456,10 +461,11 @@ int erq_sample_rotation(int32_t dp, uint64_t seed, float* P_host)
     return ERQ_OK;
 }
 
-int erq_index_create(int32_t dp, int32_t bits, int64_t nlist, const float* P, uint64_t seed, void* stream,
-                     erq_index* out)
+int erq_index_create(int32_t dp, int32_t bits, int64_t nlist, const float* P, uint64_t seed, int32_t metric,
+                     void* stream, erq_index* out)
 {
     if (int rc = check_dp(dp, "erq_index_create")) return rc;
+    if (metric < ERQ_METRIC_L2 || metric > ERQ_METRIC_COSINE) return fail(ERQ_EINVAL, "erq_index_create: bad metric");
     if (bits < 1 || bits > 8) return fail(ERQ_EUNSUPPORTED, "erq_index_create: bits must be in [1, 8]");
     if (nlist < 1 || nlist > (1 << 24)) return fail(ERQ_EINVAL, "erq_index_create: nlist must be in [1, 2^24]");
     if (!out) return fail(ERQ_EINVAL, "erq_index_create: null pointer");
@@ -470,7 +476,7 @@ int erq_index_create(int32_t dp, int32_t bits, int64_t nlist, const float* P, ui
     }
     erq_index_s* ix = new (std::nothrow) erq_index_s();
     if (!ix) return fail(ERQ_ENOMEM, "erq_index_create: out of host memory");
-    ix->dp = dp; ix->bits = bits; ix->nlist = nlist;
+    ix->dp = dp; ix->bits = bits; ix->nlist = nlist; ix->metric = metric;
     ix->seed = P ? 0 : seed;
     hipGetDevice(&ix->device);
     if (hipMalloc(&ix->P, sizeof(float) * dp * dp) != hipSuccess) { delete ix; return fail(ERQ_ENOMEM, "erq_index_create: hipMalloc failed"); }
@@ -497,7 +503,7 @@ int erq_index_save(erq_index ix, const char* path, void* stream)
     FileHeader h{};
     std::memcpy(h.magic, kMagic, 8);
     h.version = kFileVersion;
-    h.dp = ix->dp; h.bits = ix->bits; h.has_raw = ix->raw ? 1 : 0;
+    h.dp = ix->dp; h.bits = ix->bits; h.has_raw = ix->raw ? 1 : 0; h.metric = ix->metric;
     h.nlist = ix->nlist; h.n = ix->n; h.ntiles = ix->ntiles;
     h.tune[0] = ix->tune_nqt; h.tune[1] = ix->tune_pd; h.tune[2] = ix->tune_round1; h.tune[3] = ix->tune_round2;
     h.seed = ix->seed;
@@ -527,7 +533,8 @@ int erq_index_load(const char* path, void* stream, erq_index* out)
         return fail(ERQ_EINVAL, "erq_index_load: not an index file");
     if (h.version != kFileVersion) return fail(ERQ_EUNSUPPORTED, "erq_index_load: unknown file version");
     if (h.dp < 64 || h.dp > kMaxDp || h.dp % 64 || h.bits < 1 || h.bits > 8 || h.nlist < 1 ||
-        h.nlist > (1 << 24) || h.n < 0 || h.n > (1LL << 31) - 1 || h.ntiles < 0 || (h.has_raw != 0 && h.has_raw != 1))
+        h.nlist > (1 << 24) || h.n < 0 || h.n > (1LL << 31) - 1 || h.ntiles < 0 || (h.has_raw != 0 && h.has_raw != 1) ||
+        h.metric < ERQ_METRIC_L2 || h.metric > ERQ_METRIC_COSINE)
         return fail(ERQ_EINVAL, "erq_index_load: bad header");
     const std::vector<size_t> sz = file_arrays(h);
     size_t total = sizeof(h);
@@ -550,7 +557,7 @@ int erq_index_load(const char* path, void* stream, erq_index* out)
     erq_index_s* ix = new (std::nothrow) erq_index_s();
     if (!ix) return fail(ERQ_ENOMEM, "erq_index_load: out of host memory");
     struct Owner { erq_index_s* p; ~Owner() { if (p) erq_index_destroy(p); } } owner{ix};
-    ix->dp = dp; ix->bits = h.bits; ix->nlist = C; ix->seed = h.seed;
+    ix->dp = dp; ix->bits = h.bits; ix->nlist = C; ix->seed = h.seed; ix->metric = h.metric;
     ix->tune_nqt = h.tune[0]; ix->tune_pd = h.tune[1]; ix->tune_round1 = h.tune[2]; ix->tune_round2 = h.tune[3];
     hipGetDevice(&ix->device);
     if (int rc = set_list_meta(ix, off, st)) return rc;
@@ -649,7 +656,8 @@ int erq_index_import(erq_index ix, int64_t n, const int64_t* list_off, const int
         hipLaunchKernelGGL(interleave_fac_kernel, dim3(blocks(n)), dim3(256), 0, st, f_add, f_rescale, n, ix->fac);
         ERQ_HIP(hipGetLastError());
         ERQ_HIP(launch_pack_n(codes, ix->list_off, ix->tile_off, C, dp, ix->bits, ix->ntiles, ix->codes, st));
-        ERQ_HIP(launch_scan_fac(codes, ix->list_off, C, ix->cent_rot, ix->fac, n, dp, ix->bits, ix->sfac, st));
+        ERQ_HIP(launch_scan_fac(codes, ix->list_off, C, ix->cent_rot, ix->fac, n, dp, ix->bits, ix->metric, ix->sfac,
+                                st));
     }
     ERQ_HIP(hipStreamSynchronize(st));
     return ERQ_OK;
@@ -662,7 +670,10 @@ int erq_index_set_raw(erq_index ix, const float* x, int64_t n, void* stream)
     hipFree(ix->raw);
     ix->raw = nullptr;
     ERQ_HIP(hipMalloc(&ix->raw, sizeof(float) * std::max<int64_t>(n, 1) * ix->dp));
-    ERQ_HIP(hipMemcpyAsync(ix->raw, x, sizeof(float) * n * ix->dp, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    if (ix->metric == ERQ_METRIC_COSINE)
+        ERQ_HIP(launch_normalize(x, n, ix->dp, ix->raw, (hipStream_t)stream));
+    else
+        ERQ_HIP(hipMemcpyAsync(ix->raw, x, sizeof(float) * n * ix->dp, hipMemcpyDeviceToDevice, (hipStream_t)stream));
     ERQ_HIP(hipStreamSynchronize((hipStream_t)stream));
     return ERQ_OK;
 }
@@ -685,7 +696,13 @@ int erq_index_build(erq_index ix, const float* x, int64_t n, const float* centro
     if (n < 0 || n > (1LL << 31) - 1) return fail(ERQ_EINVAL, "erq_index_build: n out of range");
     if (n > 0 && !x) return fail(ERQ_EINVAL, "erq_index_build: null pointer");
     float* own_cent = nullptr;                      // centroids of the library's k-means
-    struct FreeC { float** p; ~FreeC() { hipFree(*p); } } free_cent{&own_cent};
+    float* xnorm = nullptr;                         // cosine: the rows scaled to unit length
+    struct FreeC { float** p; float** q; ~FreeC() { hipFree(*p); hipFree(*q); } } free_cent{&own_cent, &xnorm};
+    if (ix->metric == ERQ_METRIC_COSINE && n > 0) {
+        ERQ_HIP(hipMalloc(&xnorm, sizeof(float) * n * ix->dp));
+        ERQ_HIP(launch_normalize(x, n, ix->dp, xnorm, (hipStream_t)stream));
+        x = xnorm;
+    }
     if (!centroids) {
         if (assign) return fail(ERQ_EINVAL, "erq_index_build: an assignment needs its centroids");
         if (n < ix->nlist) return fail(ERQ_EINVAL, "erq_index_build: k-means needs at least nlist rows");
@@ -726,7 +743,9 @@ int erq_index_build(erq_index ix, const float* x, int64_t n, const float* centro
         guard.p.push_back(pws);
         for (int64_t r0 = 0; r0 < n; r0 += chunk) {
             int64_t m = std::min(chunk, n - r0);
-            if (int rc = probe_impl(x + r0 * dp, m, ix->cent, C, dp, 1, asg + r0, nullptr, pws, pb, st)) return rc;
+            if (int rc = probe_impl(x + r0 * dp, m, ix->cent, C, dp, 1, asg + r0, nullptr, pws, pb, st, ProbePre(),
+                                    ix->metric))
+                return rc;
         }
     }
     int32_t* cnt = aux;
@@ -783,7 +802,8 @@ int erq_index_build(erq_index ix, const float* x, int64_t n, const float* centro
         prof_end(pr, st);
     }
     ERQ_HIP(launch_pack_n(codes_u, ix->list_off, ix->tile_off, C, dp, ix->bits, ix->ntiles, ix->codes, st));
-    ERQ_HIP(launch_scan_fac(codes_u, ix->list_off, C, ix->cent_rot, ix->fac, n, dp, ix->bits, ix->sfac, st));
+    ERQ_HIP(launch_scan_fac(codes_u, ix->list_off, C, ix->cent_rot, ix->fac, n, dp, ix->bits, ix->metric, ix->sfac,
+                            st));
     if (keep_raw && n > 0) {
         ERQ_HIP(hipMalloc(&ix->raw, sizeof(float) * n * dp));
         ERQ_HIP(hipMemcpyAsync(ix->raw, x, sizeof(float) * n * dp, hipMemcpyDeviceToDevice, st));
@@ -848,8 +868,20 @@ int erq_rerank(erq_index ix, const float* q, int64_t nq, const int64_t* cand, in
     if (kc < 1 || kc > kMaxK || k < 1 || k > kc) return fail(ERQ_EUNSUPPORTED, "erq_rerank: need 1 <= k <= kc <= 1024");
     if (nq < 0 || (nq > 0 && (!q || !cand || !out_ids || !out_dist))) return fail(ERQ_EINVAL, "erq_rerank: bad arguments");
     int pr = prof_begin(PK_RERANK, (hipStream_t)stream);
-    ERQ_HIP(launch_rerank(ix->raw, ix->n, ix->dp, q, nq, cand, nullptr, kc, k, nullptr, nullptr, out_ids, out_dist,
-                          (hipStream_t)stream));
+    const float* qq = q;
+    float* qnorm = nullptr;
+    if (ix->metric == ERQ_METRIC_COSINE && nq > 0) {      // the rows are stored normalised; so is the query
+        ERQ_HIP(hipMalloc(&qnorm, sizeof(float) * nq * ix->dp));
+        ERQ_HIP(launch_normalize(q, nq, ix->dp, qnorm, (hipStream_t)stream));
+        qq = qnorm;
+    }
+    hipError_t re = launch_rerank(ix->raw, ix->n, ix->dp, qq, nq, cand, nullptr, kc, k, nullptr, nullptr, out_ids,
+                                  out_dist, (hipStream_t)stream, ix->metric);
+    if (qnorm) {
+        if (re == hipSuccess) re = hipStreamSynchronize((hipStream_t)stream);
+        hipFree(qnorm);
+    }
+    ERQ_HIP(re);
     prof_end(pr, (hipStream_t)stream);
     return ERQ_OK;
 }
@@ -865,6 +897,7 @@ static size_t search_ws(Index* ix, int64_t nq, int nprobe, int k, int rerank_k) 
     b += 2 * align256(sizeof(unsigned short) * nq * ix->dp);   // BF16 hi/lo planes of the queries
     b += align256(sizeof(float) * nq);                          // ||q||^2
     b += 2 * align256(sizeof(int32_t) * nq);                    // per-query k and re-rank depth
+    if (ix->metric == ERQ_METRIC_COSINE) b += align256(sizeof(float) * nq * ix->dp);   // unit-length queries
     b += std::max(probe_ws(nq, ix->nlist, ix->dp), scan_workspace_bytes(nq, nprobe, ix->nlist, kk, ix->dp, ix->max_list));
     return b;
 }
@@ -911,6 +944,11 @@ static int search_run(Index* ix, const float* q, int64_t nq, int nprobe, int k, 
     float* qn = (float*)w; w += align256(sizeof(float) * nq);
     int32_t* kq = (int32_t*)w; w += align256(sizeof(int32_t) * nq);
     int32_t* rq = (int32_t*)w; w += align256(sizeof(int32_t) * nq);
+    if (ix->metric == ERQ_METRIC_COSINE) {          // unit-length queries for every later step
+        float* qn_rows = (float*)w; w += align256(sizeof(float) * nq * ix->dp);
+        ERQ_HIP(launch_normalize(q, nq, ix->dp, qn_rows, st));
+        q = qn_rows;
+    }
     size_t rest = ws_bytes - (size_t)(w - (char*)workspace);
     // q' = q P on the BF16 matrix cores from hi/lo planes (the probe's
     // products and error bound); the planes serve the probe too
@@ -918,11 +956,13 @@ static int search_run(Index* ix, const float* q, int64_t nq, int nprobe, int k, 
     ERQ_HIP(launch_split_norm(q, nq, ix->dp, qh, ql, qn, st));
     ERQ_HIP(launch_gemm_bf16x3(qh, ql, nq, ix->pt_hi, ix->pt_lo, ix->dp, ix->dp, qrot, ix->dp, st));
     prof_end(pr, st);
-    // the probe's ||q - c||^2 = ||q' - c'||^2 (P orthogonal) is the scan's ||s||^2
+    // the probe's ||q - c||^2 = ||q' - c'||^2 (P orthogonal) is the scan's ||s||^2 (L2), its
+    // -<q, c> = -<q', c'> the scan's per-pair term (inner-product metrics)
     ProbePre pre;
     pre.qh = qh; pre.ql = ql; pre.qn = qn;
     pre.ch = ix->cent_hi; pre.cl = ix->cent_lo; pre.cn = ix->cent_n2;
-    if (int rc = probe_impl(q, nq, ix->cent, ix->nlist, ix->dp, nprobe, probes, pdist, w, rest, st, pre)) return rc;
+    if (int rc = probe_impl(q, nq, ix->cent, ix->nlist, ix->dp, nprobe, probes, pdist, w, rest, st, pre, ix->metric))
+        return rc;
     const bool per_query = nprobe_q || k_q || rerank_q;
     if (per_query) {
         hipLaunchKernelGGL(query_params_kernel, dim3(blocks(nq)), dim3(256), 0, st, nq, nprobe, k, rerank_k, nprobe_q,
@@ -933,7 +973,7 @@ static int search_run(Index* ix, const float* q, int64_t nq, int nprobe, int k, 
     if (rerank_k > 0) {
         int pr2 = prof_begin(PK_RERANK, st);
         ERQ_HIP(launch_rerank(ix->raw, ix->n, ix->dp, q, nq, cid, cest, kk, k, per_query ? rq : nullptr,
-                              per_query ? kq : nullptr, out_ids, out_dist, st));
+                              per_query ? kq : nullptr, out_ids, out_dist, st, ix->metric));
         prof_end(pr2, st);
     } else {
         hipLaunchKernelGGL(copy_cols_kernel, dim3(blocks(nq * k)), dim3(256), 0, st, cid, cest, nq, kk, k,

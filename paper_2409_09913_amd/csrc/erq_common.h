@@ -62,6 +62,7 @@ __host__ __device__ inline int stored_offset(int bits) { return bits == 8 ? 128 
 // ---- the index ---------------------------------------------------------------
 struct Index {
     int dp = 0, bits = 0;
+    int metric = ERQ_METRIC_L2;    // erq_metric
     int64_t nlist = 0, n = 0;
     int device = 0;
     uint64_t seed = 0;             // seed P was sampled from (0 when the caller gave P)
@@ -119,18 +120,23 @@ int scan_pd(const Index* ix);
 int scan_round1(const Index* ix);
 int scan_round2(const Index* ix);
 bool scan_pd_valid(int pd, int dp, int bits);
-// pdist: ||q' - c'||^2 per (query, probe) (nq x nprobe) or null to compute it
+// pdist: the per-pair term (nq x nprobe) or null to compute it: ||q' - c'||^2
+// for L2, -<q', c'> for the inner-product metrics (ix->metric)
 int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, const float* pdist, int nprobe,
              int kk, int64_t* out_ids, float* out_est, void* ws, size_t ws_bytes, hipStream_t st);
-// scan factors from unpacked codes (list order) and (f_add, f_rescale)
+// scan factors from unpacked codes (list order) and (f_add, f_rescale):
+// L2 (g_add, f_rescale) with g_add = f_add - f_rescale <y_bar, c'>; the
+// inner-product metrics (0, f_rescale / 2)
 hipError_t launch_scan_fac(const uint8_t* codes_u, const int64_t* list_off, int64_t nlist, const float* cent_rot,
-                           const float2* fac, int64_t n, int dp, int bits, float2* sfac, hipStream_t st);
+                           const float2* fac, int64_t n, int dp, int bits, int metric, float2* sfac, hipStream_t st);
+// rows scaled to unit length (FP32, IEEE sqrt and division; zero rows stay zero)
+hipError_t launch_normalize(const float* x, int64_t n, int dp, float* out, hipStream_t st);
 // exact re-rank of each query's first kc_q[i] (all kc when null) candidates
 // (ids outside [0, n) skipped), keeping its k_q[i] (else k) best; a query
 // with kc_q[i] == 0 gets its first candidates and their estimates copied
 hipError_t launch_rerank(const float* raw, int64_t n, int dp, const float* q, int64_t nq, const int64_t* cand,
                          const float* cand_est, int kc, int k, const int32_t* kc_q, const int32_t* k_q,
-                         int64_t* out_ids, float* out_d, hipStream_t st);
+                         int64_t* out_ids, float* out_d, hipStream_t st, int metric = ERQ_METRIC_L2);
 
 // Haar orthogonal dp x dp matrix of the seed, row-major FP32, host memory (host code)
 void sample_rotation(int dp, uint64_t seed, float* P);

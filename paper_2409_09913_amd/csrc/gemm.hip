@@ -225,7 +225,8 @@ __device__ inline uint4 ld16(const unsigned short* p, bool ok) {
 }
 
 // EPI 1: squared distances ||a||^2 + ||b||^2 - 2 a.b of the coarse probe;
-// EPI 0: a.b (the query rotation).  Products on the BF16 matrix cores, from
+// EPI 2: negated inner products -a.b (the probe of the inner-product
+// metrics); EPI 0: a.b (the query rotation).  Products on the BF16 matrix cores, from
 // operands split beforehand into hi
 // and lo BF16 planes (split_bf16_kernel): a.b = lo.hi + hi.lo + hi.hi per
 // 16-wide K chunk, FP32 accumulation.  Each product is off by at most
@@ -309,6 +310,7 @@ __global__ __launch_bounds__(256, 3) void sqdist_bf16x3_kernel(
                 const int64_t gr = row0 + wm + 32 * a + out_row(lane, r);
                 if (gr >= n) continue;
                 if constexpr (EPI == 1) out[gr * ldo + gc] = (an2[gr] + bn2[gc]) - 2.0f * acc[a][b][r];
+                else if constexpr (EPI == 2) out[gr * ldo + gc] = -acc[a][b][r];
                 else out[gr * ldo + gc] = acc[a][b][r];
             }
         }
@@ -396,12 +398,16 @@ hipError_t launch_split_bf16(const float* x, int64_t n, unsigned short* hi, unsi
 
 hipError_t launch_sqdist_pre(const unsigned short* Ah, const unsigned short* Al, int64_t n,
                              const unsigned short* Bh, const unsigned short* Bl, int64_t N, int K,
-                             const float* an2, const float* bn2, float* out, hipStream_t st)
+                             const float* an2, const float* bn2, float* out, hipStream_t st, int neg_ip)
 {
     if (n <= 0 || N <= 0) return hipSuccess;
     dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((n + BM - 1) / BM));
-    hipLaunchKernelGGL(sqdist_bf16x3_kernel<1>, grid, dim3(256), 0, st, Ah, Al, n, K, Bh, Bl, (int)N, out,
-                       (int64_t)N, an2, bn2);
+    if (neg_ip)
+        hipLaunchKernelGGL(sqdist_bf16x3_kernel<2>, grid, dim3(256), 0, st, Ah, Al, n, K, Bh, Bl, (int)N, out,
+                           (int64_t)N, an2, bn2);
+    else
+        hipLaunchKernelGGL(sqdist_bf16x3_kernel<1>, grid, dim3(256), 0, st, Ah, Al, n, K, Bh, Bl, (int)N, out,
+                           (int64_t)N, an2, bn2);
     return hipGetLastError();
 }
 

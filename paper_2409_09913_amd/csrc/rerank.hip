@@ -1,7 +1,8 @@
 // Exact re-rank of the best estimated candidates with the raw vectors.  The
 // paper's own setting keeps no raw vectors (Sec. 2.1, Sec. 4.1); this step
 // is the optional exact pass on top of it: squared Euclidean distances in
-// FP32 of kc gathered rows, then the k smallest by (distance, id).
+// FP32 of kc gathered rows, then the k smallest by (distance, id); for the
+// inner-product metrics the distance is the negated inner product.
 #include "erq_common.h"
 
 namespace erq {
@@ -14,6 +15,7 @@ constexpr int kMaxKc = 1024;
 // first kcq = kc_q[iq] candidates (all kc when kc_q is null) and keeps the
 // kq = k_q[iq] (else k) best; kcq == 0 copies its first kq candidates and
 // their estimates (cand_est) unchanged.  Ids outside [0, n) count as missing.
+template <bool IP>
 __global__ __launch_bounds__(256) void rerank_kernel(const float* __restrict__ raw, int64_t n, int dp,
                                                      const float* __restrict__ q, const int64_t* __restrict__ cand,
                                                      const float* __restrict__ cand_est, int kc, int k,
@@ -58,8 +60,12 @@ __global__ __launch_bounds__(256) void rerank_kernel(const float* __restrict__ r
                 a[b] = (id[b] >= 0) ? *(const float4*)(raw + id[b] * (int64_t)dp + i) : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
             for (int b = 0; b < CB; ++b) {
-                const float d0 = a[b].x - qq.x, d1 = a[b].y - qq.y, d2 = a[b].z - qq.z, d3 = a[b].w - qq.w;
-                s[b] += d0 * d0 + d1 * d1 + d2 * d2 + d3 * d3;
+                if constexpr (IP) {
+                    s[b] -= a[b].x * qq.x + a[b].y * qq.y + a[b].z * qq.z + a[b].w * qq.w;
+                } else {
+                    const float d0 = a[b].x - qq.x, d1 = a[b].y - qq.y, d2 = a[b].z - qq.z, d3 = a[b].w - qq.w;
+                    s[b] += d0 * d0 + d1 * d1 + d2 * d2 + d3 * d3;
+                }
             }
         }
 #pragma unroll
@@ -99,11 +105,39 @@ __global__ __launch_bounds__(256) void rerank_kernel(const float* __restrict__ r
 
 hipError_t launch_rerank(const float* raw, int64_t n, int dp, const float* q, int64_t nq, const int64_t* cand,
                          const float* cand_est, int kc, int k, const int32_t* kc_q, const int32_t* k_q,
-                         int64_t* out_ids, float* out_d, hipStream_t st)
+                         int64_t* out_ids, float* out_d, hipStream_t st, int metric)
 {
     if (nq <= 0) return hipSuccess;
-    hipLaunchKernelGGL(rerank_kernel, dim3((unsigned)nq), dim3(256), 0, st, raw, n, dp, q, cand, cand_est, kc, k,
-                       kc_q, k_q, out_ids, out_d);
+    if (metric != ERQ_METRIC_L2)
+        hipLaunchKernelGGL(rerank_kernel<true>, dim3((unsigned)nq), dim3(256), 0, st, raw, n, dp, q, cand, cand_est,
+                           kc, k, kc_q, k_q, out_ids, out_d);
+    else
+        hipLaunchKernelGGL(rerank_kernel<false>, dim3((unsigned)nq), dim3(256), 0, st, raw, n, dp, q, cand, cand_est,
+                           kc, k, kc_q, k_q, out_ids, out_d);
+    return hipGetLastError();
+}
+
+namespace {
+// one wave per row: s = sum of squares (FP32, fixed order), row / sqrt(s)
+__global__ __launch_bounds__(256) void normalize_kernel(const float* __restrict__ x, int64_t n, int dp,
+                                                        float* __restrict__ out)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= n) return;
+    const float* xr = x + r * dp;
+    float s = 0.0f;
+    for (int i = lane; i < dp; i += 64) s += xr[i] * xr[i];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    const float nrm = __fsqrt_rn(s);
+    for (int i = lane; i < dp; i += 64) out[r * dp + i] = (nrm > 0.0f) ? __fdiv_rn(xr[i], nrm) : 0.0f;
+}
+}  // namespace
+
+hipError_t launch_normalize(const float* x, int64_t n, int dp, float* out, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(normalize_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, x, n, dp, out);
     return hipGetLastError();
 }
 

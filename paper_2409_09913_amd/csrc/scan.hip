@@ -172,6 +172,7 @@ struct QArgs {
     const float* qhd;
     const int32_t* qss;
     const float* sdist;
+    float s2_floor;          // 0 for L2 (a squared distance rounded below 0 is clamped), -inf otherwise
 };
 
 // Prologue shared by the scan kernels, in two steps with a barrier between
@@ -189,7 +190,7 @@ __device__ inline void load_query_scalars(float* s_s2, float* s_hd, int* s_ss, i
 {
     if (tid < mq) {
         const int q = pq[tid], slot = pslot[tid];
-        s_s2[tid] = fmaxf(qa.sdist[slot], 0.0f);     // the probe's expanded form may round below 0
+        s_s2[tid] = fmaxf(qa.sdist[slot], qa.s2_floor);   // L2: the probe's expanded form may round below 0
         s_hd[tid] = qa.qhd[q];
         s_ss[tid] = qa.qss[q];
         s_slot[tid] = slot;
@@ -981,7 +982,7 @@ __global__ __launch_bounds__(256) void exact_kernel(
                 }
                 const int tt = g - tpref[lo];
                 const int l = probes[q * nprobe + lo];
-                const float s2 = fmaxf(qa.sdist[q * nprobe + lo], 0.0f);
+                const float s2 = fmaxf(qa.sdist[q * nprobe + lo], qa.s2_floor);
                 const int64_t lb = list_off[l];
                 const int nl = (int)(list_off[l + 1] - lb);
                 const uint8_t* tp = codes + (tile_off[l] + tt) * tile_bytes;
@@ -1081,8 +1082,10 @@ __global__ __launch_bounds__(256) void qprep_kernel(const float* __restrict__ qr
     }
 }
 
-// ||q' - c'||^2 of every (query, probe) pair in FP32; one wave per pair
-// (used when the caller has no probe distances)
+// The per-pair term of every (query, probe) pair in FP32, one wave per pair
+// (used when the caller has no probe distances): ||q' - c'||^2 for L2,
+// -<q', c'> for the inner-product metrics (IP)
+template <bool IP>
 __global__ __launch_bounds__(256) void pair_s2_kernel(const float* __restrict__ qrot,
                                                       const float* __restrict__ cent_rot,
                                                       const int32_t* __restrict__ probes, int64_t np, int nprobe,
@@ -1096,7 +1099,11 @@ __global__ __launch_bounds__(256) void pair_s2_kernel(const float* __restrict__ 
     if (l >= 0 && l < nlist) {
         const float* qv = qrot + (i / nprobe) * dp;
         const float* cv = cent_rot + (int64_t)l * dp;
-        for (int d = lane; d < dp; d += 64) { const float t = qv[d] - cv[d]; s += t * t; }
+        if constexpr (IP) {
+            for (int d = lane; d < dp; d += 64) s -= qv[d] * cv[d];
+        } else {
+            for (int d = lane; d < dp; d += 64) { const float t = qv[d] - cv[d]; s += t * t; }
+        }
     }
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
     if (lane == 0) sdist[i] = s;
@@ -1107,15 +1114,21 @@ __global__ __launch_bounds__(256) void pair_s2_kernel(const float* __restrict__ 
 // rotated centroid of the member's list, <y_bar, c'> accumulated in FP64.
 // Then est = g_add + ||s||^2 + f_rescale * <y_bar, q'> for s' = q' - c'.
 // codes_u: n x dp unpacked y_u in list order; one wave per member.
+// Inner-product metrics: (0, f_rescale / 2), so that the same epilogue gives
+// -<c, q> + (f_rescale / 2) <y_bar, q'> with the per-pair term -<c', q'>.
 __global__ __launch_bounds__(256) void scan_fac_kernel(const uint8_t* __restrict__ codes_u,
                                                        const int64_t* __restrict__ list_off, int nlist,
                                                        const float* __restrict__ cent_rot,
                                                        const float2* __restrict__ fac, int64_t n, int dp,
-                                                       int bits, float2* __restrict__ sfac)
+                                                       int bits, int ip, float2* __restrict__ sfac)
 {
     const int lane = threadIdx.x & 63;
     const int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (v >= n) return;
+    if (ip) {
+        if (lane == 0) sfac[v] = make_float2(0.0f, 0.5f * fac[v].y);
+        return;
+    }
     int lo = 0, hi = nlist;                        // list of member v: last l with list_off[l] <= v
     while (hi - lo > 1) { const int mid = (lo + hi) >> 1; if (list_off[mid] <= v) lo = mid; else hi = mid; }
     const uint8_t* y = codes_u + v * dp;
@@ -1559,11 +1572,11 @@ int scan_round1(const Index* ix) { return ix->tune_round1 > 0 ? ix->tune_round1 
 int scan_round2(const Index* ix) { return ix->tune_round2; }
 
 hipError_t launch_scan_fac(const uint8_t* codes_u, const int64_t* list_off, int64_t nlist, const float* cent_rot,
-                           const float2* fac, int64_t n, int dp, int bits, float2* sfac, hipStream_t st)
+                           const float2* fac, int64_t n, int dp, int bits, int metric, float2* sfac, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(scan_fac_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, codes_u, list_off,
-                       (int)nlist, cent_rot, fac, n, dp, bits, sfac);
+                       (int)nlist, cent_rot, fac, n, dp, bits, metric != ERQ_METRIC_L2 ? 1 : 0, sfac);
     return hipGetLastError();
 }
 
@@ -1687,12 +1700,17 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, co
     // queries to int8 once; ||s||^2 per pair from the probe distances, else computed
     hipLaunchKernelGGL(qprep_kernel, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, st, qrot, nq, dp, qint, qhd, qss);
     const float* sdist = pdist;
+    const bool ip = ix->metric != ERQ_METRIC_L2;
     if (!sdist && P > 0) {
-        hipLaunchKernelGGL(pair_s2_kernel, dim3((unsigned)((P + 3) / 4)), dim3(256), 0, st, qrot, ix->cent_rot,
-                           probes, P, nprobe, (int)nlist, dp, sdist_ws);
+        if (ip)
+            hipLaunchKernelGGL(pair_s2_kernel<true>, dim3((unsigned)((P + 3) / 4)), dim3(256), 0, st, qrot,
+                               ix->cent_rot, probes, P, nprobe, (int)nlist, dp, sdist_ws);
+        else
+            hipLaunchKernelGGL(pair_s2_kernel<false>, dim3((unsigned)((P + 3) / 4)), dim3(256), 0, st, qrot,
+                               ix->cent_rot, probes, P, nprobe, (int)nlist, dp, sdist_ws);
         sdist = sdist_ws;
     }
-    const QArgs qa{qint, qhd, qss, sdist};
+    const QArgs qa{qint, qhd, qss, sdist, ip ? -__builtin_huge_valf() : 0.0f};
     const int64_t gridB = 1 << 20;                    // capped at the resident blocks
     // a pass-B launch over the pairs of probe ranks [rlo, rhi) (of flagged
     // queries with qmask); dense = the first-bound mode

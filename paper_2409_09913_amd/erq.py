@@ -16,6 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liberq.so")
 
 ERQ_OK, ERQ_EINVAL, ERQ_ESHAPE, ERQ_ENOMEM, ERQ_EUNSUPPORTED, ERQ_EDEVICE = range(6)
+METRICS = {"l2": 0, "ip": 1, "cosine": 2}
 
 # name -> (restype, argtypes) for every symbol of include/erq.h
 _p, _i32, _i64, _sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
@@ -25,9 +26,9 @@ SIGNATURES = {
     "erq_rotate": (C.c_int, [_p, _i64, _i32, _p, _i32, _p, _p]),
     "erq_quantize": (C.c_int, [_p, _i64, _i32, _i32, _p, _p, _p, _p, _p, _p]),
     "erq_probe_workspace_size": (C.c_int, [_i64, _i64, _i32, _i32, C.POINTER(_sz)]),
-    "erq_coarse_probe": (C.c_int, [_p, _i64, _p, _i64, _i32, _i32, _p, _p, _p, _sz, _p]),
+    "erq_coarse_probe": (C.c_int, [_p, _i64, _p, _i64, _i32, _i32, _i32, _p, _p, _p, _sz, _p]),
     "erq_sample_rotation": (C.c_int, [_i32, C.c_uint64, _p]),
-    "erq_index_create": (C.c_int, [_i32, _i32, _i64, _p, C.c_uint64, _p, C.POINTER(_p)]),
+    "erq_index_create": (C.c_int, [_i32, _i32, _i64, _p, C.c_uint64, _i32, _p, C.POINTER(_p)]),
     "erq_index_destroy": (C.c_int, [_p]),
     "erq_index_get_rotation": (C.c_int, [_p, _p, _p]),
     "erq_index_save": (C.c_int, [_p, C.c_char_p, _p]),
@@ -130,7 +131,7 @@ def quantize(rrot, bits: int, norm2=None):
     return codes, fa, fr, co
 
 
-def coarse_probe(q, centroids, nprobe: int, with_dist: bool = False):
+def coarse_probe(q, centroids, nprobe: int, with_dist: bool = False, metric: str = "l2"):
     nq, dp = q.shape
     nl = centroids.shape[0]
     sz = C.c_size_t()
@@ -139,7 +140,8 @@ def coarse_probe(q, centroids, nprobe: int, with_dist: bool = False):
     probes = torch.empty((nq, nprobe), dtype=torch.int32, device=q.device)
     pd = torch.empty((nq, nprobe), dtype=torch.float32, device=q.device) if with_dist else None
     _check(load().erq_coarse_probe(_ptr(q, torch.float32, "q"), nq, _ptr(centroids, torch.float32, "centroids"),
-                                   nl, dp, nprobe, _ptr(probes), _ptr(pd), _ptr(ws), ws.numel(), _stream()))
+                                   nl, dp, nprobe, METRICS[metric], _ptr(probes), _ptr(pd), _ptr(ws), ws.numel(),
+                                   _stream()))
     return (probes, pd) if with_dist else probes
 
 
@@ -167,14 +169,15 @@ class Index:
     P: the dp x dp rotation (device tensor), or None to have the library
     sample it from `seed`."""
 
-    def __init__(self, dp: int, bits: int, nlist: int, P=None, seed: int = 0, _handle=None):
-        self.dp, self.bits, self.nlist = dp, bits, nlist
+    def __init__(self, dp: int, bits: int, nlist: int, P=None, seed: int = 0, metric: str = "l2", _handle=None):
+        self.dp, self.bits, self.nlist, self.metric = dp, bits, nlist, metric
         self.device = P.device if P is not None else torch.device("cuda", torch.cuda.current_device())
         if _handle is not None:
             self.h = _handle
             return
         h = C.c_void_p()
-        _check(load().erq_index_create(dp, bits, nlist, _ptr(P, torch.float32, "P"), seed, _stream(), C.byref(h)))
+        _check(load().erq_index_create(dp, bits, nlist, _ptr(P, torch.float32, "P"), seed, METRICS[metric], _stream(),
+                                       C.byref(h)))
         self.h = h
 
     @classmethod

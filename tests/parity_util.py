@@ -12,21 +12,26 @@ import numpy as np
 class CandTerms:
     """Per-candidate term magnitude of reading C-15 for (query, member id)."""
 
-    def __init__(self, off, ids, codes, fa, fr, crot, qrot, probes, B):
+    def __init__(self, off, ids, codes, fa, fr, crot, qrot, probes, B, metric="l2"):
         self.off = np.asarray(off, np.int64)
         self.pos = np.empty(int(np.max(ids)) + 1 if len(ids) else 0, np.int64)
         self.pos[np.asarray(ids, np.int64)] = np.arange(len(ids))
         self.codes, self.fa, self.fr = codes, fa, fr
         self.crot, self.qrot, self.probes = crot, qrot, probes
         self.half = ((1 << B) - 1) / 2.0
+        self.metric = metric
 
     def __call__(self, iq, mid):
         """f_add + ||s||^2 + |f_rescale <y_bar, s'>| of member `mid` for query iq."""
         p = int(self.pos[mid])
         l = int(np.searchsorted(self.off, p, side="right") - 1)
         assert l in set(int(v) for v in self.probes[iq]), (iq, mid, l)
-        s = self.qrot[iq].astype(np.float64) - self.crot[l].astype(np.float64)
         yb = self.codes[p].astype(np.float64) - self.half
+        if self.metric != "l2":
+            # negated inner product -<c', q'> + (f_rescale / 2) <y_bar, q'>: its two terms
+            q = self.qrot[iq].astype(np.float64)
+            return abs(float(self.crot[l].astype(np.float64) @ q)) + abs(0.5 * float(self.fr[p]) * float(yb @ q))
+        s = self.qrot[iq].astype(np.float64) - self.crot[l].astype(np.float64)
         return abs(float(self.fa[p])) + float(s @ s) + abs(float(self.fr[p]) * float(yb @ s))
 
 

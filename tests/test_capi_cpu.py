@@ -47,13 +47,14 @@ def test_argument_validation_without_device_work():
     # bad precision
     assert lib.erq_rotate(nul, 0, 64, nul, 3, nul, nul) == erq.ERQ_EUNSUPPORTED
     # nprobe larger than nlist
-    assert lib.erq_coarse_probe(nul, 0, nul, 4, 64, 5, nul, nul, nul, 0, nul) == erq.ERQ_EUNSUPPORTED
+    assert lib.erq_coarse_probe(nul, 0, nul, 4, 64, 5, 0, nul, nul, nul, 0, nul) == erq.ERQ_EUNSUPPORTED
     # null index
     assert lib.erq_scan(nul, nul, 0, nul, 1, 1, nul, nul, nul, 0, nul) == erq.ERQ_EINVAL
     assert lib.erq_rerank(nul, nul, 0, nul, 1, 1, nul, nul, nul) == erq.ERQ_EINVAL
     h = C.c_void_p()
-    assert lib.erq_index_create(64, 0, 4, nul, 0, nul, C.byref(h)) == erq.ERQ_EUNSUPPORTED
-    assert lib.erq_index_create(64, 4, 0, nul, 0, nul, C.byref(h)) == erq.ERQ_EINVAL
+    assert lib.erq_index_create(64, 0, 4, nul, 0, 0, nul, C.byref(h)) == erq.ERQ_EUNSUPPORTED
+    assert lib.erq_index_create(64, 4, 0, nul, 0, 0, nul, C.byref(h)) == erq.ERQ_EINVAL
+    assert lib.erq_index_create(64, 4, 4, nul, 0, 7, nul, C.byref(h)) == erq.ERQ_EINVAL
     # the no-allocation search checks its arguments like erq_search
     assert lib.erq_search_static(nul, nul, 1, 4, 10, 0, nul, nul, nul, nul, nul, nul) == erq.ERQ_EINVAL
     assert lib.erq_sample_rotation(65, 1, nul) == erq.ERQ_ESHAPE

@@ -60,12 +60,12 @@ def test_load_rejects_bad_files(tmp_path):
     p.write_bytes(b"not an index file at all" * 10)
     assert lib.erq_index_load(os.fsencode(str(p)), None, C.byref(h)) == erq.ERQ_EINVAL
     # a well-formed header of version 1 whose arrays are missing: size mismatch
-    hdr = b"ERQIDX\0\0" + struct.pack("<Iiii", 1, 64, 4, 0) + struct.pack("<qqq", 2, 10, 2) + \
+    hdr = b"ERQIDX\0\0" + struct.pack("<Iiiiii", 1, 64, 4, 0, 0, 0) + struct.pack("<qqq", 2, 10, 2) + \
         struct.pack("<iiii", 0, 0, 0, 0) + struct.pack("<Q", 0)
     p2 = tmp_path / "short.idx"
     p2.write_bytes(hdr)
     assert lib.erq_index_load(os.fsencode(str(p2)), None, C.byref(h)) == erq.ERQ_EINVAL
     assert b"size" in lib.erq_last_error()
     p3 = tmp_path / "v9.idx"
-    p3.write_bytes(b"ERQIDX\0\0" + struct.pack("<Iiii", 9, 64, 4, 0) + hdr[24:])
+    p3.write_bytes(b"ERQIDX\0\0" + struct.pack("<Iiiiii", 9, 64, 4, 0, 0, 0) + hdr[32:])
     assert lib.erq_index_load(os.fsencode(str(p3)), None, C.byref(h)) == erq.ERQ_EUNSUPPORTED
