@@ -58,6 +58,11 @@ def _load():
         lib.orc_search.argtypes = [p, p, p, p, p, p, p, i64, i32, i32,
                                    p, i64, p, i32, i32, i32, p, p]
         lib.orc_search.restype = i32
+        lib.orc_search_ld.argtypes = [p, p, p, p, p, p, p, i64, i32, i32, i32,
+                                      p, i64, p, i32, i32, i32, p, p]
+        lib.orc_search_ld.restype = i32
+        lib.orc_encode_proj.argtypes = [p, i64, i32, i32, p, p, p, i32, p, p, p]
+        lib.orc_encode_proj.restype = i32
         lib.orc_rerank.argtypes = [p, i32, p, i64, p, i32, i32, p, p]
         lib.orc_search_ip.argtypes = [p, p, p, p, p, p, p, i64, i32, i32,
                                       p, i64, p, i32, i32, i32, p, p]
@@ -182,10 +187,29 @@ def probe(q, cent, nprobe):
     return pr, pd
 
 
+def encode_proj(x, cent, assign, P, B, dc):
+    """Index phase with a random projection to dc < dp dimensions (App. C):
+    codes (n x dc), f_add = ||r||^2, f_rescale = -(2 dp/dc) ||r'_d||^2/<y, r'_d>."""
+    x = _c(x, np.float64)
+    cent = _c(cent, np.float64)
+    assign = _c(assign, np.int32)
+    P = _c(P, np.float64)
+    n, dp = x.shape
+    codes = np.empty((n, dc), np.uint8)
+    fa = np.empty(n, np.float64)
+    fr = np.empty(n, np.float64)
+    rc = _load().orc_encode_proj(_p(x), n, dp, dc, _p(cent), _p(assign), _p(P), B, _p(codes), _p(fa), _p(fr))
+    if rc != 0:
+        raise ValueError("bad arguments to encode_proj")
+    return codes, fa, fr
+
+
 def search(list_off, ids, codes, f_add, f_rescale, crot, qrot, probes, B, kk,
            cos_oo=None, est_mode=0):
     """IVF scan + top-kk by (est, id); est_mode 0 = int8 query (factor form),
-    1 = float query (paper form, needs cos_oo), 2 = float query (factor form)."""
+    1 = float query (paper form, needs cos_oo), 2 = float query (factor form).
+    With codes narrower than qrot / crot (the projection of App. C) the codes
+    use the first coordinates and ||s||^2 all of them."""
     list_off = _c(list_off, np.int64)
     ids = _c(ids, np.int64)
     codes = _c(codes, np.uint8)
@@ -195,13 +219,14 @@ def search(list_off, ids, codes, f_add, f_rescale, crot, qrot, probes, B, kk,
     qrot = _c(qrot, np.float32)
     probes = _c(probes, np.int32)
     co = _c(cos_oo if cos_oo is not None else np.ones(ids.shape[0]), np.float64)
-    nq, dp = qrot.shape
+    nq, ld = qrot.shape
+    dp = codes.shape[1] if codes.ndim == 2 and codes.shape[0] else ld
     nprobe = probes.shape[1]
     oi = np.empty((nq, kk), np.int64)
     od = np.empty((nq, kk), np.float64)
-    rc = _load().orc_search(_p(list_off), _p(ids), _p(codes), _p(fa), _p(fr), _p(co),
-                            _p(crot), crot.shape[0], dp, B, _p(qrot), nq, _p(probes),
-                            nprobe, kk, est_mode, _p(oi), _p(od))
+    rc = _load().orc_search_ld(_p(list_off), _p(ids), _p(codes), _p(fa), _p(fr), _p(co),
+                               _p(crot), crot.shape[0], dp, ld, B, _p(qrot), nq, _p(probes),
+                               nprobe, kk, est_mode, _p(oi), _p(od))
     if rc != 0:
         raise ValueError("bad arguments to search")
     return oi, od

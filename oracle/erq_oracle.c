@@ -267,6 +267,48 @@ int orc_encode(const double* x, int64_t n, int dp, const double* cent,
     return rc;
 }
 
+/* Encoding with a random projection to d < D dimensions before quantising
+   (App. C): the estimate of <r, s> is (D/d) <P_d r, P_d s> (Johnson-
+   Lindenstrauss), and the inner product of the d-dimensional projections is
+   estimated by the extended codes.  With r'_d = the first d coordinates of
+   P^T r (P^T r rotated by the full P, then cut to d rows = a d x D random
+   orthogonal projection), the two stored floats are
+     f_add = ||r||^2 (all D coordinates),
+     f_rescale = -(2 D / d) ||r'_d||^2 / <y, r'_d>,
+   so est = f_add + ||s||^2 + f_rescale <y, s'_d> with ||s||^2 over all D
+   coordinates.  d == D is orc_encode. */
+int orc_encode_proj(const double* x, int64_t n, int dp, int dc, const double* cent,
+                    const int32_t* assign, const double* P, int B,
+                    uint8_t* codes, double* f_add, double* f_rescale)
+{
+    if (dp <= 0 || dc <= 0 || dc > dp || B < 1 || B > 8 || n < 0) return -1;
+    double* res = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1) * dp);
+    double* rr = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1) * dp);
+    double* rd = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1) * dc);
+    double* nr2 = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double* co = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    for (int64_t r = 0; r < n; ++r) {
+        const double* c = cent + (int64_t)assign[r] * dp;
+        double s = 0.0;
+        for (int i = 0; i < dp; ++i) {
+            const double v = x[r * (int64_t)dp + i] - c[i];
+            res[r * (int64_t)dp + i] = v;
+            s += v * v;
+        }
+        nr2[r] = s;
+    }
+    orc_rotate(res, n, dp, P, rr);
+    for (int64_t r = 0; r < n; ++r)
+        for (int i = 0; i < dc; ++i) rd[r * (int64_t)dc + i] = rr[r * (int64_t)dp + i];
+    int rc = orc_quantize(rd, n, dc, B, NULL, codes, f_add, f_rescale, co);    /* norm2 = ||r'_d||^2 */
+    for (int64_t r = 0; r < n; ++r) {
+        f_rescale[r] *= (double)dp / (double)dc;
+        f_add[r] = nr2[r];
+    }
+    free(res); free(rr); free(rd); free(nr2); free(co);
+    return rc;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Query side.                                                               */
 /* ------------------------------------------------------------------------ */
@@ -393,6 +435,12 @@ void orc_probe(const float* q, int64_t nq, const float* cent, int64_t C, int dp,
     }
 }
 
+int orc_search_ld(const int64_t* list_off, const int64_t* ids, const uint8_t* codes,
+                  const float* f_add, const float* f_rescale, const double* cos_oo,
+                  const float* crot, int64_t C, int dp, int ld, int B,
+                  const float* qrot, int64_t nq, const int32_t* probes, int nprobe,
+                  int kk, int est_mode, int64_t* out_ids, double* out_d);
+
 /* IVF search with the int8 estimator (Sec. 4.1 with Sec. 3.3).  Index:
    list_off[C+1], ids[N] (row ids), codes[N x dp] (y_u, list order),
    f_add/f_rescale[N] (FP32 as stored), crot[C x dp] rotated centroids (FP32).
@@ -409,6 +457,20 @@ int orc_search(const int64_t* list_off, const int64_t* ids, const uint8_t* codes
                const float* qrot, int64_t nq, const int32_t* probes, int nprobe,
                int kk, int est_mode, int64_t* out_ids, double* out_d)
 {
+    return orc_search_ld(list_off, ids, codes, f_add, f_rescale, cos_oo, crot, C, dp, dp, B, qrot, nq, probes,
+                         nprobe, kk, est_mode, out_ids, out_d);
+}
+
+/* The scan of orc_search when the codes cover only the first dp of the ld
+   coordinates of the rotated queries and centroids (the projection of
+   App. C): ||s||^2 is taken over all ld coordinates, everything else over the
+   first dp.  ld == dp is orc_search. */
+int orc_search_ld(const int64_t* list_off, const int64_t* ids, const uint8_t* codes,
+                  const float* f_add, const float* f_rescale, const double* cos_oo,
+                  const float* crot, int64_t C, int dp, int ld, int B,
+                  const float* qrot, int64_t nq, const int32_t* probes, int nprobe,
+                  int kk, int est_mode, int64_t* out_ids, double* out_d)
+{
     if (dp <= 0 || B < 1 || B > 8 || kk < 1) return -1;
     int bad = 0;
     #pragma omp parallel reduction(|:bad)
@@ -422,15 +484,16 @@ int orc_search(const int64_t* list_off, const int64_t* ids, const uint8_t* codes
         for (int64_t iq = 0; iq < nq; ++iq) {
             int64_t nc = 0;
             float delta; int32_t qsum;
-            orc_query_quant(qrot + iq * (int64_t)dp, dp, qq, &delta, &qsum);
+            orc_query_quant(qrot + iq * (int64_t)ld, dp, qq, &delta, &qsum);
             for (int p = 0; p < nprobe; ++p) {
                 int32_t l = probes[iq * nprobe + p];
                 if (l < 0) continue;                 /* padding: the query probes fewer lists */
                 if (l >= C) { bad = 1; continue; }
-                const float* qv = qrot + iq * (int64_t)dp;
-                const float* cv = crot + (int64_t)l * dp;
+                const float* qv = qrot + iq * (int64_t)ld;
+                const float* cv = crot + (int64_t)l * ld;
                 double ns2 = 0.0;
                 for (int i = 0; i < dp; ++i) { sd[i] = (double)qv[i] - (double)cv[i]; ns2 += sd[i] * sd[i]; }
+                for (int i = dp; i < ld; ++i) { const double t = (double)qv[i] - (double)cv[i]; ns2 += t * t; }
                 int64_t lo = list_off[l], hi = list_off[l + 1];
                 if (nc + (hi - lo) > cap) {
                     while (nc + (hi - lo) > cap) cap *= 2;
