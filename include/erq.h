@@ -134,12 +134,26 @@ int erq_index_create(int32_t dp, int32_t bits, int64_t nlist, const float* P,
    in flight (freeing device memory waits for the device). */
 int erq_index_destroy(erq_index idx);
 
+/* Random projection to dc < dp dimensions before quantising (App. C): the
+   codes keep the first dc coordinates of the rotated residual r' (a random
+   dc-dimensional projection, P being Haar), with f_add = ||r||^2 over all dp
+   coordinates and f_rescale = -(2 dp/dc) ||r'_d||^2 / <y_bar, r'_d> from the
+   kept ones, so that <y_bar, s'_d> f_rescale estimates -2 <r, s>; ||s||^2
+   stays exact over all dp.  Queries are rotated to their first dc
+   coordinates only.  dc: a multiple of 64 in [64, dp] (dp = no projection,
+   the default).  Only on an empty index (ERQ_EINVAL after a build or
+   import) with the L2 metric (ERQ_EUNSUPPORTED otherwise).  Synchronises
+   `stream`. */
+int erq_index_set_projection(erq_index idx, int32_t dc, void* stream);
+/* The code dimension dc (dp without a projection). */
+int erq_index_code_dim(erq_index idx, int32_t* dc);
+
 /* Copies the index's rotation P (dp x dp FP32, row-major) to P_out (device). */
 int erq_index_get_rotation(erq_index idx, float* P_out, void* stream);
 
 /* Writes the whole index to a file (host path): a versioned header (magic
-   "ERQIDX", version 1, dp, bits, raw kept, metric, nlist, n, tiles, scan
-   schedule, seed),
+   "ERQIDX", version 1, dp, bits, raw kept, metric, code dimension, nlist,
+   n, tiles, scan schedule, seed),
    then P, raw and rotated centroids, list offsets, ids, factors, scan
    factors, packed codes and, when kept, the raw vectors, in native byte
    order.  Synchronises `stream`. */
@@ -154,8 +168,9 @@ int erq_index_load(const char* path, void* stream, erq_index* out);
    list_off: nlist+1 int64 offsets into the list-ordered arrays; ids: n int64
    row ids, each in [0, n) (row numbers of the vectors given to
    erq_index_set_raw; ERQ_EINVAL otherwise, checked on the device before the
-   call returns); codes: n x dp uint8 y_u in list order; f_add, f_rescale: n
-   FP32; centroids, centroids_rot: nlist x dp FP32 (centroids_rot = P^T c;
+   call returns); codes: n x dc uint8 y_u in list order (dc = the code
+   dimension, dp without a projection); f_add, f_rescale: n FP32;
+   centroids, centroids_rot: nlist x dp FP32 (centroids_rot = P^T c;
    NULL -> computed with erq_rotate in FP32).  Replaces previous contents.
    Synchronises `stream`. */
 int erq_index_import(erq_index idx, int64_t n, const int64_t* list_off, const int64_t* ids,
@@ -197,7 +212,7 @@ int erq_index_info(erq_index idx, int64_t* n, int32_t* dp, int32_t* bits, int64_
                    int64_t* code_bytes);
 
 /* Reads the contents back in list order: list_off (nlist+1), ids (n),
-   codes (n x dp, y_u unpacked from the packed layout), f_add, f_rescale (n),
+   codes (n x dc, y_u unpacked from the packed layout), f_add, f_rescale (n),
    centroids_rot (nlist x dp).  Any output may be NULL. */
 int erq_index_export(erq_index idx, int64_t* list_off, int64_t* ids, uint8_t* codes,
                      float* f_add, float* f_rescale, float* centroids_rot, void* stream);
@@ -205,7 +220,8 @@ int erq_index_export(erq_index idx, int64_t* list_off, int64_t* ids, uint8_t* co
 /* ------------------------------------------------------------------------ */
 /* Scan (Sec. 3.3, Sec. 4.1): estimated squared distances of every member of */
 /* the probed lists, kept as the kk smallest per query.                     */
-/* qrot: nq x dp rotated queries q' = P^T q_r; probes: nq x nprobe list ids  */
+/* qrot: nq x dp rotated queries q' = P^T q_r (with a projection the codes */
+/* use the first dc coordinates, ||s'||^2 all dp); probes: nq x nprobe ids    */
 /* (entries < 0 are skipped, so queries may probe fewer lists).  Every query */
 /* is quantised to int8 once, symmetrically: delta = max|q'|/127,           */
 /* q_i = rint(q'_i * 127/max|q'|).  For a probed list with rotated centroid */

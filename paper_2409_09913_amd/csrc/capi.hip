@@ -130,6 +130,14 @@ __global__ void copy_cols_kernel(const int64_t* ids, const float* est, int64_t n
     oe[i] = in ? est[q * kin + t] : __builtin_huge_valf();
 }
 
+// projection fix-up: f_add = ||r||^2 over all dp coordinates, f_rescale
+// scaled by dp / dc (App. C)
+__global__ void proj_fac_kernel(const float* nrm, int64_t n, float scale, float2* fac) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    fac[i] = make_float2(nrm[i], fac[i].y * scale);
+}
+
 // Per-query search parameters clamped to the batch maxima: nprobe in
 // [1, nprobe], k in [1, kmax], re-rank depth 0 or in [k, rrmax] (rrmax 0: no
 // re-rank); null arrays give the maxima.  Probe ranks past a query's own
@@ -197,6 +205,19 @@ hipError_t alloc_cent_planes(Index* ix, hipStream_t st)
     if (e == hipSuccess) e = hipMalloc(&ix->cent_n2, sizeof(float) * C);
     if (e == hipSuccess) e = launch_split_norm(ix->cent, C, (int)dp, ix->cent_hi, ix->cent_lo, ix->cent_n2, st);
     return e;
+}
+
+// Pd = the first dc columns of P (dp x dc, row-major) when dc < dp: the
+// build's rotation then yields only the coordinates the codes keep
+int set_projection_matrix(Index* ix, hipStream_t st)
+{
+    hipFree(ix->Pd);
+    ix->Pd = nullptr;
+    if (ix->dc == ix->dp) return ERQ_OK;
+    ERQ_HIP(hipMalloc(&ix->Pd, sizeof(float) * ix->dp * ix->dc));
+    ERQ_HIP(hipMemcpy2DAsync(ix->Pd, sizeof(float) * ix->dc, ix->P, sizeof(float) * ix->dp, sizeof(float) * ix->dc,
+                             ix->dp, hipMemcpyDeviceToDevice, st));
+    return ERQ_OK;
 }
 
 struct ProbePre {           // operands already split (and their norms), or null
@@ -336,7 +357,7 @@ constexpr uint32_t kFileVersion = 1;
 struct FileHeader {
     char magic[8];
     uint32_t version;
-    int32_t dp, bits, has_raw, metric, reserved;     // reserved = 0 (keeps the int64 fields aligned)
+    int32_t dp, bits, has_raw, metric, dc;           // dc: code dimension (App. C projection when < dp)
     int64_t nlist, n, ntiles;
     int32_t tune[4];
     uint64_t seed;
@@ -352,7 +373,7 @@ std::vector<size_t> file_arrays(const FileHeader& h) {
             sizeof(int64_t) * n,                  // ids
             sizeof(float2) * n,                   // (f_add, f_rescale)
             sizeof(float2) * n,                   // scan factors
-            (size_t)4 * dp * h.bits * (size_t)h.ntiles,   // packed codes
+            (size_t)4 * (size_t)h.dc * h.bits * (size_t)h.ntiles,   // packed codes
             h.has_raw ? sizeof(float) * n * dp : 0};      // raw vectors
 }
 
@@ -476,7 +497,7 @@ int erq_index_create(int32_t dp, int32_t bits, int64_t nlist, const float* P, ui
     }
     erq_index_s* ix = new (std::nothrow) erq_index_s();
     if (!ix) return fail(ERQ_ENOMEM, "erq_index_create: out of host memory");
-    ix->dp = dp; ix->bits = bits; ix->nlist = nlist; ix->metric = metric;
+    ix->dp = dp; ix->bits = bits; ix->nlist = nlist; ix->metric = metric; ix->dc = dp;
     ix->seed = P ? 0 : seed;
     hipGetDevice(&ix->device);
     if (hipMalloc(&ix->P, sizeof(float) * dp * dp) != hipSuccess) { delete ix; return fail(ERQ_ENOMEM, "erq_index_create: hipMalloc failed"); }
@@ -503,7 +524,7 @@ int erq_index_save(erq_index ix, const char* path, void* stream)
     FileHeader h{};
     std::memcpy(h.magic, kMagic, 8);
     h.version = kFileVersion;
-    h.dp = ix->dp; h.bits = ix->bits; h.has_raw = ix->raw ? 1 : 0; h.metric = ix->metric;
+    h.dp = ix->dp; h.bits = ix->bits; h.has_raw = ix->raw ? 1 : 0; h.metric = ix->metric; h.dc = ix->dc;
     h.nlist = ix->nlist; h.n = ix->n; h.ntiles = ix->ntiles;
     h.tune[0] = ix->tune_nqt; h.tune[1] = ix->tune_pd; h.tune[2] = ix->tune_round1; h.tune[3] = ix->tune_round2;
     h.seed = ix->seed;
@@ -534,7 +555,7 @@ int erq_index_load(const char* path, void* stream, erq_index* out)
     if (h.version != kFileVersion) return fail(ERQ_EUNSUPPORTED, "erq_index_load: unknown file version");
     if (h.dp < 64 || h.dp > kMaxDp || h.dp % 64 || h.bits < 1 || h.bits > 8 || h.nlist < 1 ||
         h.nlist > (1 << 24) || h.n < 0 || h.n > (1LL << 31) - 1 || h.ntiles < 0 || (h.has_raw != 0 && h.has_raw != 1) ||
-        h.metric < ERQ_METRIC_L2 || h.metric > ERQ_METRIC_COSINE)
+        h.metric < ERQ_METRIC_L2 || h.metric > ERQ_METRIC_COSINE || h.dc < 64 || h.dc > h.dp || h.dc % 64)
         return fail(ERQ_EINVAL, "erq_index_load: bad header");
     const std::vector<size_t> sz = file_arrays(h);
     size_t total = sizeof(h);
@@ -557,7 +578,7 @@ int erq_index_load(const char* path, void* stream, erq_index* out)
     erq_index_s* ix = new (std::nothrow) erq_index_s();
     if (!ix) return fail(ERQ_ENOMEM, "erq_index_load: out of host memory");
     struct Owner { erq_index_s* p; ~Owner() { if (p) erq_index_destroy(p); } } owner{ix};
-    ix->dp = dp; ix->bits = h.bits; ix->nlist = C; ix->seed = h.seed; ix->metric = h.metric;
+    ix->dp = dp; ix->bits = h.bits; ix->nlist = C; ix->seed = h.seed; ix->metric = h.metric; ix->dc = h.dc;
     ix->tune_nqt = h.tune[0]; ix->tune_pd = h.tune[1]; ix->tune_round1 = h.tune[2]; ix->tune_round2 = h.tune[3];
     hipGetDevice(&ix->device);
     if (int rc = set_list_meta(ix, off, st)) return rc;
@@ -580,10 +601,31 @@ int erq_index_load(const char* path, void* stream, erq_index* out)
     ERQ_HIP(hipMalloc(&ix->pt_hi, sizeof(unsigned short) * dp * dp));
     ERQ_HIP(hipMalloc(&ix->pt_lo, sizeof(unsigned short) * dp * dp));
     ERQ_HIP(launch_split_bf16_t(ix->P, dp, dp, ix->pt_hi, ix->pt_lo, st));
+    if (int rc = set_projection_matrix(ix, st)) return rc;
     ERQ_HIP(alloc_cent_planes(ix, st));
     ERQ_HIP(hipStreamSynchronize(st));
     owner.p = nullptr;
     *out = ix;
+    return ERQ_OK;
+}
+
+int erq_index_set_projection(erq_index ix, int32_t dc, void* stream)
+{
+    if (!ix) return fail(ERQ_EINVAL, "erq_index_set_projection: null index");
+    if (ix->list_off) return fail(ERQ_EINVAL, "erq_index_set_projection: the index already holds vectors");
+    if (ix->metric != ERQ_METRIC_L2) return fail(ERQ_EUNSUPPORTED, "erq_index_set_projection: L2 metric only");
+    if (dc < 64 || dc > ix->dp || dc % 64 != 0)
+        return fail(ERQ_ESHAPE, "erq_index_set_projection: dc must be a multiple of 64 in [64, dp]");
+    ix->dc = dc;
+    if (int rc = set_projection_matrix(ix, (hipStream_t)stream)) return rc;
+    ERQ_HIP(hipStreamSynchronize((hipStream_t)stream));
+    return ERQ_OK;
+}
+
+int erq_index_code_dim(erq_index ix, int32_t* dc)
+{
+    if (!ix || !dc) return fail(ERQ_EINVAL, "erq_index_code_dim: null pointer");
+    *dc = ix->dc;
     return ERQ_OK;
 }
 
@@ -600,6 +642,7 @@ int erq_index_destroy(erq_index ix)
     hipDeviceSynchronize();
     free_index_storage(ix);
     hipFree(ix->P);
+    hipFree(ix->Pd);
     hipFree(ix->pt_hi);
     hipFree(ix->pt_lo);
     hipFree(ix->raw);
@@ -628,7 +671,7 @@ int erq_index_import(erq_index ix, int64_t n, const int64_t* list_off, const int
     ERQ_HIP(hipMalloc(&ix->ids, sizeof(int64_t) * std::max<int64_t>(n, 1)));
     ERQ_HIP(hipMalloc(&ix->fac, sizeof(float2) * std::max<int64_t>(n, 1)));
     ERQ_HIP(hipMalloc(&ix->sfac, sizeof(float2) * std::max<int64_t>(n, 1)));
-    ERQ_HIP(hipMalloc(&ix->codes, std::max<int64_t>((int64_t)4 * dp * ix->bits * ix->ntiles, 256)));
+    ERQ_HIP(hipMalloc(&ix->codes, std::max<int64_t>((int64_t)4 * ix->dc * ix->bits * ix->ntiles, 256)));
     ERQ_HIP(hipMalloc(&ix->cent, sizeof(float) * C * dp));
     ERQ_HIP(hipMalloc(&ix->cent_rot, sizeof(float) * C * dp));
     ERQ_HIP(hipMemcpyAsync(ix->cent, centroids, sizeof(float) * C * dp, hipMemcpyDeviceToDevice, st));
@@ -655,9 +698,9 @@ int erq_index_import(erq_index ix, int64_t n, const int64_t* list_off, const int
         ERQ_HIP(hipMemcpyAsync(ix->ids, ids, sizeof(int64_t) * n, hipMemcpyDeviceToDevice, st));
         hipLaunchKernelGGL(interleave_fac_kernel, dim3(blocks(n)), dim3(256), 0, st, f_add, f_rescale, n, ix->fac);
         ERQ_HIP(hipGetLastError());
-        ERQ_HIP(launch_pack_n(codes, ix->list_off, ix->tile_off, C, dp, ix->bits, ix->ntiles, ix->codes, st));
-        ERQ_HIP(launch_scan_fac(codes, ix->list_off, C, ix->cent_rot, ix->fac, n, dp, ix->bits, ix->metric, ix->sfac,
-                                st));
+        ERQ_HIP(launch_pack_n(codes, ix->list_off, ix->tile_off, C, ix->dc, ix->bits, ix->ntiles, ix->codes, st));
+        ERQ_HIP(launch_scan_fac(codes, ix->list_off, C, ix->cent_rot, ix->fac, n, ix->dc, dp, ix->bits, ix->metric,
+                                ix->sfac, st));
     }
     ERQ_HIP(hipStreamSynchronize(st));
     return ERQ_OK;
@@ -716,7 +759,7 @@ int erq_index_build(erq_index ix, const float* x, int64_t n, const float* centro
     if (ix->dp > 3072) return fail(ERQ_EUNSUPPORTED, "erq_index_build: dp > 3072 exceeds the LDS window");
     hipStream_t st = (hipStream_t)stream;
     const int64_t C = ix->nlist;
-    const int dp = ix->dp;
+    const int dp = ix->dp, dc = ix->dc;
     free_index_storage(ix);
     hipFree(ix->raw);
     ix->raw = nullptr;
@@ -768,7 +811,7 @@ int erq_index_build(erq_index ix, const float* x, int64_t n, const float* centro
     ERQ_HIP(hipMalloc(&ix->ids, sizeof(int64_t) * std::max<int64_t>(n, 1)));
     ERQ_HIP(hipMalloc(&ix->fac, sizeof(float2) * std::max<int64_t>(n, 1)));
     ERQ_HIP(hipMalloc(&ix->sfac, sizeof(float2) * std::max<int64_t>(n, 1)));
-    ERQ_HIP(hipMalloc(&ix->codes, std::max<int64_t>((int64_t)4 * dp * ix->bits * ix->ntiles, 256)));
+    ERQ_HIP(hipMalloc(&ix->codes, std::max<int64_t>((int64_t)4 * dc * ix->bits * ix->ntiles, 256)));
     // members in list order, ids ascending within each list: a stable bucket
     // sort of the rows by list, so the layout is the same on every build
     if (n > 0) {
@@ -782,28 +825,36 @@ int erq_index_build(erq_index ix, const float* x, int64_t n, const float* centro
 
     // residual -> rotate -> quantise, in batches, list order
     uint8_t* codes_u = nullptr;
-    ERQ_HIP(hipMalloc(&codes_u, std::max<int64_t>(n, 1) * dp));
+    ERQ_HIP(hipMalloc(&codes_u, std::max<int64_t>(n, 1) * dc));
     guard.p.push_back(codes_u);
     const int64_t bt = std::max<int64_t>(1, std::min<int64_t>(n, 131072));
     float *res = nullptr, *rot = nullptr, *nrm = nullptr;
     ERQ_HIP(hipMalloc(&res, sizeof(float) * bt * dp));
-    ERQ_HIP(hipMalloc(&rot, sizeof(float) * bt * dp));
+    ERQ_HIP(hipMalloc(&rot, sizeof(float) * bt * dc));
     ERQ_HIP(hipMalloc(&nrm, sizeof(float) * bt));
     guard.p.push_back(res); guard.p.push_back(rot); guard.p.push_back(nrm);
     for (int64_t v0 = 0; v0 < n; v0 += bt) {
         int64_t m = std::min(bt, n - v0);
         ERQ_HIP(launch_residual(x, ix->ids + v0, asg, ix->cent, m, dp, res, nrm, st));
         int pr = prof_begin(PK_ROTATE, st);
-        ERQ_HIP(launch_gemm(res, m, dp, ix->P, dp, 0, precision, rot, dp, st));
+        ERQ_HIP(launch_gemm(res, m, dp, dc < dp ? ix->Pd : ix->P, dc, 0, precision, rot, dc, st));
         prof_end(pr, st);
         pr = prof_begin(PK_QUANTIZE, st);
-        ERQ_HIP(launch_quantize(rot, m, dp, ix->bits, nrm, codes_u + v0 * dp, nullptr, nullptr, nullptr,
-                                ix->fac + v0, st));
+        // projection (App. C): the codes and <y, r'_d> from the first dc
+        // coordinates, ||r'_d||^2 from them too; the fix-up then takes
+        // f_add = ||r||^2 and scales f_rescale by dp / dc
+        ERQ_HIP(launch_quantize(rot, m, dc, ix->bits, dc < dp ? nullptr : nrm, codes_u + v0 * dc, nullptr, nullptr,
+                                nullptr, ix->fac + v0, st));
+        if (dc < dp) {
+            hipLaunchKernelGGL(proj_fac_kernel, dim3(blocks(m)), dim3(256), 0, st, nrm, m, (float)dp / (float)dc,
+                               ix->fac + v0);
+            ERQ_HIP(hipGetLastError());
+        }
         prof_end(pr, st);
     }
-    ERQ_HIP(launch_pack_n(codes_u, ix->list_off, ix->tile_off, C, dp, ix->bits, ix->ntiles, ix->codes, st));
-    ERQ_HIP(launch_scan_fac(codes_u, ix->list_off, C, ix->cent_rot, ix->fac, n, dp, ix->bits, ix->metric, ix->sfac,
-                            st));
+    ERQ_HIP(launch_pack_n(codes_u, ix->list_off, ix->tile_off, C, dc, ix->bits, ix->ntiles, ix->codes, st));
+    ERQ_HIP(launch_scan_fac(codes_u, ix->list_off, C, ix->cent_rot, ix->fac, n, dc, dp, ix->bits, ix->metric,
+                            ix->sfac, st));
     if (keep_raw && n > 0) {
         ERQ_HIP(hipMalloc(&ix->raw, sizeof(float) * n * dp));
         ERQ_HIP(hipMemcpyAsync(ix->raw, x, sizeof(float) * n * dp, hipMemcpyDeviceToDevice, st));
@@ -819,7 +870,7 @@ int erq_index_info(erq_index ix, int64_t* n, int32_t* dp, int32_t* bits, int64_t
     if (dp) *dp = ix->dp;
     if (bits) *bits = ix->bits;
     if (nlist) *nlist = ix->nlist;
-    if (code_bytes) *code_bytes = (int64_t)4 * ix->dp * ix->bits * ix->ntiles;
+    if (code_bytes) *code_bytes = (int64_t)4 * ix->dc * ix->bits * ix->ntiles;
     return ERQ_OK;
 }
 
@@ -832,7 +883,7 @@ int erq_index_export(erq_index ix, int64_t* list_off, int64_t* ids, uint8_t* cod
     const int64_t n = ix->n, C = ix->nlist;
     if (list_off) ERQ_HIP(hipMemcpyAsync(list_off, ix->list_off, sizeof(int64_t) * (C + 1), hipMemcpyDeviceToDevice, st));
     if (ids && n) ERQ_HIP(hipMemcpyAsync(ids, ix->ids, sizeof(int64_t) * n, hipMemcpyDeviceToDevice, st));
-    if (codes && n) ERQ_HIP(launch_unpack_n(ix->codes, ix->list_off, ix->tile_off, C, ix->dp, ix->bits, ix->ntiles, codes, st));
+    if (codes && n) ERQ_HIP(launch_unpack_n(ix->codes, ix->list_off, ix->tile_off, C, ix->dc, ix->bits, ix->ntiles, codes, st));
     if ((f_add || f_rescale) && n) {
         hipLaunchKernelGGL(split_fac_kernel, dim3(blocks(n)), dim3(256), 0, st, ix->fac, n, f_add, f_rescale);
         ERQ_HIP(hipGetLastError());
@@ -844,7 +895,7 @@ int erq_index_export(erq_index ix, int64_t* list_off, int64_t* ids, uint8_t* cod
 int erq_scan_workspace_size(erq_index ix, int64_t nq, int32_t nprobe, int32_t kk, size_t* bytes)
 {
     if (!ix || !bytes || nq < 0 || nprobe < 1 || kk < 1) return fail(ERQ_EINVAL, "erq_scan_workspace_size: bad arguments");
-    *bytes = scan_workspace_bytes(nq, nprobe, ix->nlist, kk, ix->dp, ix->max_list);
+    *bytes = scan_workspace_bytes(nq, nprobe, ix->nlist, kk, ix->dc, ix->max_list);
     return ERQ_OK;
 }
 
@@ -857,7 +908,7 @@ int erq_scan(erq_index ix, const float* qrot, int64_t nq, const int32_t* probes,
     if (kk < 1 || kk > kMaxK) return fail(ERQ_EUNSUPPORTED, "erq_scan: kk must be in [1, 1024]");
     if (nq > 0 && (!qrot || !probes || !out_ids || !out_est || !workspace)) return fail(ERQ_EINVAL, "erq_scan: null pointer");
     if (ix->nlist > 1000000) return fail(ERQ_EUNSUPPORTED, "erq_scan: more than 10^6 lists");
-    return run_scan(ix, qrot, nq, probes, nullptr, nprobe, kk, out_ids, out_est, workspace, ws_bytes,
+    return run_scan(ix, qrot, ix->dp, nq, probes, nullptr, nprobe, kk, out_ids, out_est, workspace, ws_bytes,
                     (hipStream_t)stream);
 }
 
@@ -889,7 +940,7 @@ int erq_rerank(erq_index ix, const float* q, int64_t nq, const int64_t* cand, in
 static size_t search_ws(Index* ix, int64_t nq, int nprobe, int k, int rerank_k) {
     const int kk = rerank_k > 0 ? rerank_k : k;
     size_t b = 0;
-    b += align256(sizeof(float) * nq * ix->dp);           // qrot
+    b += align256(sizeof(float) * nq * ix->dc);           // qrot (the coordinates the codes use)
     b += align256(sizeof(int32_t) * nq * nprobe);         // probes
     b += align256(sizeof(float) * nq * nprobe);           // probe distances ||q - c||^2
     b += align256(sizeof(int64_t) * nq * kk);             // candidate ids
@@ -898,7 +949,7 @@ static size_t search_ws(Index* ix, int64_t nq, int nprobe, int k, int rerank_k) 
     b += align256(sizeof(float) * nq);                          // ||q||^2
     b += 2 * align256(sizeof(int32_t) * nq);                    // per-query k and re-rank depth
     if (ix->metric == ERQ_METRIC_COSINE) b += align256(sizeof(float) * nq * ix->dp);   // unit-length queries
-    b += std::max(probe_ws(nq, ix->nlist, ix->dp), scan_workspace_bytes(nq, nprobe, ix->nlist, kk, ix->dp, ix->max_list));
+    b += std::max(probe_ws(nq, ix->nlist, ix->dp), scan_workspace_bytes(nq, nprobe, ix->nlist, kk, ix->dc, ix->max_list));
     return b;
 }
 
@@ -934,7 +985,7 @@ static int search_run(Index* ix, const float* q, int64_t nq, int nprobe, int k, 
 {
     const int kk = rerank_k > 0 ? rerank_k : k;
     char* w = (char*)workspace;
-    float* qrot = (float*)w; w += align256(sizeof(float) * nq * ix->dp);
+    float* qrot = (float*)w; w += align256(sizeof(float) * nq * ix->dc);
     int32_t* probes = (int32_t*)w; w += align256(sizeof(int32_t) * nq * nprobe);
     float* pdist = (float*)w; w += align256(sizeof(float) * nq * nprobe);
     int64_t* cid = (int64_t*)w; w += align256(sizeof(int64_t) * nq * kk);
@@ -954,7 +1005,8 @@ static int search_run(Index* ix, const float* q, int64_t nq, int nprobe, int k, 
     // products and error bound); the planes serve the probe too
     int pr = prof_begin(PK_ROTATE, st);
     ERQ_HIP(launch_split_norm(q, nq, ix->dp, qh, ql, qn, st));
-    ERQ_HIP(launch_gemm_bf16x3(qh, ql, nq, ix->pt_hi, ix->pt_lo, ix->dp, ix->dp, qrot, ix->dp, st));
+    // (with the projection, the first dc coordinates of q' only)
+    ERQ_HIP(launch_gemm_bf16x3(qh, ql, nq, ix->pt_hi, ix->pt_lo, ix->dc, ix->dp, qrot, ix->dc, st));
     prof_end(pr, st);
     // the probe's ||q - c||^2 = ||q' - c'||^2 (P orthogonal) is the scan's ||s||^2 (L2), its
     // -<q, c> = -<q', c'> the scan's per-pair term (inner-product metrics)
@@ -969,7 +1021,7 @@ static int search_run(Index* ix, const float* q, int64_t nq, int nprobe, int k, 
                            k_q, rerank_q, kq, rq, probes);
         ERQ_HIP(hipGetLastError());
     }
-    if (int rc = run_scan(ix, qrot, nq, probes, pdist, nprobe, kk, cid, cest, w, rest, st)) return rc;
+    if (int rc = run_scan(ix, qrot, ix->dc, nq, probes, pdist, nprobe, kk, cid, cest, w, rest, st)) return rc;
     if (rerank_k > 0) {
         int pr2 = prof_begin(PK_RERANK, st);
         ERQ_HIP(launch_rerank(ix->raw, ix->n, ix->dp, q, nq, cid, cest, kk, k, per_query ? rq : nullptr,
@@ -1053,9 +1105,9 @@ int erq_search(erq_index ix, const float* q, int64_t nq, int32_t nprobe, int32_t
 int erq_index_set_tune(erq_index ix, int32_t nqt, int32_t pd, int32_t round1, int32_t round2)
 {
     if (!ix) return fail(ERQ_EINVAL, "erq_index_set_tune: null index");
-    if (nqt < 0 || nqt > 2 || (nqt == 2 && ix->dp > kMaxDpNqt2))
+    if (nqt < 0 || nqt > 2 || (nqt == 2 && ix->dc > kMaxDpNqt2))
         return fail(ERQ_EINVAL, "erq_index_set_tune: nqt must be 0, 1 or 2 (2 needs dp <= 1536)");
-    if (pd < 0 || (pd > 0 && !scan_pd_valid(pd, ix->dp, ix->bits)))
+    if (pd < 0 || (pd > 0 && !scan_pd_valid(pd, ix->dc, ix->bits)))
         return fail(ERQ_EINVAL, "erq_index_set_tune: pd must be 0 or one of 1, 2, 3, 4, 6 dividing dp/64 (6 for bits <= 4)");
     if (round1 < 0 || round1 > 1024) return fail(ERQ_EINVAL, "erq_index_set_tune: round1 must be in [0, 1024]");
     if (round2 < 0 || round2 > 1024) return fail(ERQ_EINVAL, "erq_index_set_tune: round2 must be in [0, 1024]");
@@ -1109,9 +1161,9 @@ int erq_index_tune(erq_index ix, const float* q, int64_t nq, int32_t nprobe, int
         return ERQ_OK;
     };
     for (int nqt = 1; nqt <= 2 && rc == ERQ_OK; ++nqt) {
-        if (nqt == 2 && ix->dp > kMaxDpNqt2) continue;
+        if (nqt == 2 && ix->dc > kMaxDpNqt2) continue;
         for (int pd : {6, 4, 3, 2, 1}) {
-            if (!scan_pd_valid(pd, ix->dp, ix->bits)) continue;
+            if (!scan_pd_valid(pd, ix->dc, ix->bits)) continue;
             double ms = 0.0;
             rc = time_one(nqt, pd, br, b2, &ms);
             if (rc != ERQ_OK) break;

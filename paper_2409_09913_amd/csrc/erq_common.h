@@ -62,11 +62,13 @@ __host__ __device__ inline int stored_offset(int bits) { return bits == 8 ? 128 
 // ---- the index ---------------------------------------------------------------
 struct Index {
     int dp = 0, bits = 0;
+    int dc = 0;                    // code dimension: dp, or d < dp with the projection of App. C
     int metric = ERQ_METRIC_L2;    // erq_metric
     int64_t nlist = 0, n = 0;
     int device = 0;
     uint64_t seed = 0;             // seed P was sampled from (0 when the caller gave P)
     float* P = nullptr;            // dp x dp
+    float* Pd = nullptr;           // dp x dc, the first dc columns of P (only when dc < dp)
     unsigned short* pt_hi = nullptr;   // BF16 hi/lo planes of P^T (dp x dp each): the search's rotation
     unsigned short* pt_lo = nullptr;
     float* cent = nullptr;         // nlist x dp raw centroids
@@ -82,7 +84,7 @@ struct Index {
     int64_t* ids = nullptr;        // n, list order
     float2* fac = nullptr;         // n, (f_add, f_rescale), list order
     float2* sfac = nullptr;        // n, (f_add - f_rescale <y_bar, c'>, f_rescale): the scan's factors
-    uint8_t* codes = nullptr;      // ntiles * 4 * dp * bits bytes
+    uint8_t* codes = nullptr;      // ntiles * 4 * dc * bits bytes
     float* raw = nullptr;          // n x dp raw vectors (id order) or null
     int64_t ntiles = 0;
     std::vector<int64_t> h_list_off;
@@ -122,13 +124,17 @@ int scan_round2(const Index* ix);
 bool scan_pd_valid(int pd, int dp, int bits);
 // pdist: the per-pair term (nq x nprobe) or null to compute it: ||q' - c'||^2
 // for L2, -<q', c'> for the inner-product metrics (ix->metric)
-int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, const float* pdist, int nprobe,
-             int kk, int64_t* out_ids, float* out_est, void* ws, size_t ws_bytes, hipStream_t st);
+// qrot: nq rows qld apart; the codes use their first dc coordinates; without
+// pdist the per-pair term is computed from all dp (then qld must be dp)
+int run_scan(Index* ix, const float* qrot, int64_t qld, int64_t nq, const int32_t* probes, const float* pdist,
+             int nprobe, int kk, int64_t* out_ids, float* out_est, void* ws, size_t ws_bytes, hipStream_t st);
 // scan factors from unpacked codes (list order) and (f_add, f_rescale):
 // L2 (g_add, f_rescale) with g_add = f_add - f_rescale <y_bar, c'>; the
 // inner-product metrics (0, f_rescale / 2)
+// codes_u: n x dc; cent_rot: nlist x ld (its first dc coordinates are used)
 hipError_t launch_scan_fac(const uint8_t* codes_u, const int64_t* list_off, int64_t nlist, const float* cent_rot,
-                           const float2* fac, int64_t n, int dp, int bits, int metric, float2* sfac, hipStream_t st);
+                           const float2* fac, int64_t n, int dc, int ld, int bits, int metric, float2* sfac,
+                           hipStream_t st);
 // rows scaled to unit length (FP32, IEEE sqrt and division; zero rows stay zero)
 hipError_t launch_normalize(const float* x, int64_t n, int dp, float* out, hipStream_t st);
 // exact re-rank of each query's first kc_q[i] (all kc when null) candidates

@@ -1056,14 +1056,15 @@ __global__ __launch_bounds__(256) void exact_kernel(
 
 // q' -> int8 once per query (symmetric: inv = 127/max|q'|, round half to
 // even, clamp to +-127), delta/2 and the sum of the int8 values; one wave per query
-__global__ __launch_bounds__(256) void qprep_kernel(const float* __restrict__ qrot, int64_t nq, int dp,
+// (the first dp coordinates of each row of qrot, rows ld apart)
+__global__ __launch_bounds__(256) void qprep_kernel(const float* __restrict__ qrot, int64_t nq, int dp, int ld,
                                                     int8_t* __restrict__ qint, float* __restrict__ qhd,
                                                     int32_t* __restrict__ qss)
 {
     const int lane = threadIdx.x & 63;
     const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (q >= nq) return;
-    const float* qv = qrot + q * dp;
+    const float* qv = qrot + q * ld;
     float amax = 0.0f;
     for (int i = lane; i < dp; i += 64) amax = fmaxf(amax, fabsf(qv[i]));
     for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o));
@@ -1085,6 +1086,8 @@ __global__ __launch_bounds__(256) void qprep_kernel(const float* __restrict__ qr
 // The per-pair term of every (query, probe) pair in FP32, one wave per pair
 // (used when the caller has no probe distances): ||q' - c'||^2 for L2,
 // -<q', c'> for the inner-product metrics (IP)
+// (over all dp coordinates of the rotated query and centroid, whatever the
+// code dimension)
 template <bool IP>
 __global__ __launch_bounds__(256) void pair_s2_kernel(const float* __restrict__ qrot,
                                                       const float* __restrict__ cent_rot,
@@ -1119,7 +1122,7 @@ __global__ __launch_bounds__(256) void pair_s2_kernel(const float* __restrict__ 
 __global__ __launch_bounds__(256) void scan_fac_kernel(const uint8_t* __restrict__ codes_u,
                                                        const int64_t* __restrict__ list_off, int nlist,
                                                        const float* __restrict__ cent_rot,
-                                                       const float2* __restrict__ fac, int64_t n, int dp,
+                                                       const float2* __restrict__ fac, int64_t n, int dp, int ld,
                                                        int bits, int ip, float2* __restrict__ sfac)
 {
     const int lane = threadIdx.x & 63;
@@ -1132,7 +1135,7 @@ __global__ __launch_bounds__(256) void scan_fac_kernel(const uint8_t* __restrict
     int lo = 0, hi = nlist;                        // list of member v: last l with list_off[l] <= v
     while (hi - lo > 1) { const int mid = (lo + hi) >> 1; if (list_off[mid] <= v) lo = mid; else hi = mid; }
     const uint8_t* y = codes_u + v * dp;
-    const float* c = cent_rot + (int64_t)lo * dp;
+    const float* c = cent_rot + (int64_t)lo * ld;      // the codes cover its first dp coordinates
     const double half = 0.5 * (double)((1 << bits) - 1);
     double acc = 0.0;
     for (int d = lane; d < dp; d += 64) acc += ((double)y[d] - half) * (double)c[d];
@@ -1447,7 +1450,7 @@ template <int BITS, int NQT, int PD, bool DENSE>
 hipError_t launchB_d(const Index* ix, const ScanArgs& a, const BArgs& b, hipStream_t st)
 {
     const void* kern = (const void*)scanB_kernel<BITS, NQT, PD, DENSE>;
-    const size_t sm = (size_t)(ix->dp + 16) * kQT * NQT;
+    const size_t sm = (size_t)(ix->dc + 16) * kQT * NQT;
     if (sm > 48 * 1024) {
         hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
         if (e != hipSuccess) return e;
@@ -1460,7 +1463,7 @@ hipError_t launchB_d(const Index* ix, const ScanArgs& a, const BArgs& b, hipStre
     if (e != hipSuccess) return e;
     const int64_t grid = std::min<int64_t>(a.grid, (int64_t)std::max(per_cu, 1) * std::max(ncu, 1));
     hipLaunchKernelGGL((scanB_kernel<BITS, NQT, PD, DENSE>), dim3((unsigned)grid), dim3(kThreads), sm, st,
-                       ix->codes, ix->tile_off, ix->list_off, ix->sfac, ix->ids, ix->dp,
+                       ix->codes, ix->tile_off, ix->list_off, ix->sfac, ix->ids, ix->dc,
                        a.qa, a.pair_off, a.pair_q, a.pair_slot, a.item_off, a.desc, (int)ix->nlist,
                        a.kk, b.tau_key, b.gcnt, b.gbuf_e, b.gbuf_i, b.work, b.vch, b.nprobe);
     return hipGetLastError();
@@ -1514,10 +1517,10 @@ hipError_t launch_exact_b(const Index* ix, const QArgs& qa, const int32_t* probe
                           const int32_t* ovf, const int32_t* gate, int32_t* redo, int64_t* oi, float* oe,
                           hipStream_t st)
 {
-    const size_t sm = sizeof(unsigned long long) * kCapE + sizeof(int) * ((nprobe + 4) & ~3) + (size_t)ix->dp;
+    const size_t sm = sizeof(unsigned long long) * kCapE + sizeof(int) * ((nprobe + 4) & ~3) + (size_t)ix->dc;
     const unsigned grid = (unsigned)std::min<int64_t>(nq, 1024);
     hipLaunchKernelGGL((exact_kernel<BITS>), dim3(grid), dim3(256), sm, st, ix->codes, ix->tile_off, ix->list_off,
-                       ix->sfac, ix->ids, ix->dp, qa, probes, nq, nprobe, (int)ix->nlist, kk, ovf, gate, redo, oi, oe);
+                       ix->sfac, ix->ids, ix->dc, qa, probes, nq, nprobe, (int)ix->nlist, kk, ovf, gate, redo, oi, oe);
     return hipGetLastError();
 }
 
@@ -1550,8 +1553,8 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 int scan_nqt(const Index* ix)
 {
     if (ix->tune_nqt == 1) return 1;
-    if (ix->tune_nqt == 2 && ix->dp <= kMaxDpNqt2) return 2;
-    return ix->dp <= 768 ? 2 : 1;
+    if (ix->tune_nqt == 2 && ix->dc <= kMaxDpNqt2) return 2;
+    return ix->dc <= 768 ? 2 : 1;
 }
 
 bool scan_pd_valid(int pd, int dp, int bits)
@@ -1562,9 +1565,9 @@ bool scan_pd_valid(int pd, int dp, int bits)
 
 int scan_pd(const Index* ix)
 {
-    if (ix->tune_pd > 0 && scan_pd_valid(ix->tune_pd, ix->dp, ix->bits)) return ix->tune_pd;
+    if (ix->tune_pd > 0 && scan_pd_valid(ix->tune_pd, ix->dc, ix->bits)) return ix->tune_pd;
     for (int pd : {6, 4, 3, 2})
-        if (scan_pd_valid(pd, ix->dp, ix->bits)) return pd;
+        if (scan_pd_valid(pd, ix->dc, ix->bits)) return pd;
     return 1;
 }
 
@@ -1572,11 +1575,12 @@ int scan_round1(const Index* ix) { return ix->tune_round1 > 0 ? ix->tune_round1 
 int scan_round2(const Index* ix) { return ix->tune_round2; }
 
 hipError_t launch_scan_fac(const uint8_t* codes_u, const int64_t* list_off, int64_t nlist, const float* cent_rot,
-                           const float2* fac, int64_t n, int dp, int bits, int metric, float2* sfac, hipStream_t st)
+                           const float2* fac, int64_t n, int dp, int ld, int bits, int metric, float2* sfac,
+                           hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(scan_fac_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, codes_u, list_off,
-                       (int)nlist, cent_rot, fac, n, dp, bits, metric != ERQ_METRIC_L2 ? 1 : 0, sfac);
+                       (int)nlist, cent_rot, fac, n, dp, ld, bits, metric != ERQ_METRIC_L2 ? 1 : 0, sfac);
     return hipGetLastError();
 }
 
@@ -1609,12 +1613,12 @@ size_t scan_workspace_bytes(int64_t nq, int nprobe, int64_t nlist, int kk, int d
     return b;
 }
 
-int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, const float* pdist, int nprobe,
-             int kk, int64_t* out_ids, float* out_est, void* ws, size_t ws_bytes, hipStream_t st)
+int run_scan(Index* ix, const float* qrot, int64_t qld, int64_t nq, const int32_t* probes, const float* pdist,
+             int nprobe, int kk, int64_t* out_ids, float* out_est, void* ws, size_t ws_bytes, hipStream_t st)
 {
     const int64_t P = nq * nprobe;
     const int64_t nlist = ix->nlist;
-    const int dp = ix->dp;
+    const int dp = ix->dc;                             // the code dimension
     if (ws_bytes < scan_workspace_bytes(nq, nprobe, nlist, kk, dp, ix->max_list))
         return fail(ERQ_ENOMEM, "erq_scan: workspace too small");
     if (nq == 0) return ERQ_OK;
@@ -1698,16 +1702,17 @@ int run_scan(Index* ix, const float* qrot, int64_t nq, const int32_t* probes, co
     const int pr = prof_begin(PK_SCAN, st);
     hipError_t e = hipSuccess;
     // queries to int8 once; ||s||^2 per pair from the probe distances, else computed
-    hipLaunchKernelGGL(qprep_kernel, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, st, qrot, nq, dp, qint, qhd, qss);
+    hipLaunchKernelGGL(qprep_kernel, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, st, qrot, nq, dp, (int)qld, qint,
+                       qhd, qss);
     const float* sdist = pdist;
     const bool ip = ix->metric != ERQ_METRIC_L2;
     if (!sdist && P > 0) {
         if (ip)
             hipLaunchKernelGGL(pair_s2_kernel<true>, dim3((unsigned)((P + 3) / 4)), dim3(256), 0, st, qrot,
-                               ix->cent_rot, probes, P, nprobe, (int)nlist, dp, sdist_ws);
+                               ix->cent_rot, probes, P, nprobe, (int)nlist, ix->dp, sdist_ws);
         else
             hipLaunchKernelGGL(pair_s2_kernel<false>, dim3((unsigned)((P + 3) / 4)), dim3(256), 0, st, qrot,
-                               ix->cent_rot, probes, P, nprobe, (int)nlist, dp, sdist_ws);
+                               ix->cent_rot, probes, P, nprobe, (int)nlist, ix->dp, sdist_ws);
         sdist = sdist_ws;
     }
     const QArgs qa{qint, qhd, qss, sdist, ip ? -__builtin_huge_valf() : 0.0f};

@@ -30,6 +30,8 @@ SIGNATURES = {
     "erq_sample_rotation": (C.c_int, [_i32, C.c_uint64, _p]),
     "erq_index_create": (C.c_int, [_i32, _i32, _i64, _p, C.c_uint64, _i32, _p, C.POINTER(_p)]),
     "erq_index_destroy": (C.c_int, [_p]),
+    "erq_index_set_projection": (C.c_int, [_p, _i32, _p]),
+    "erq_index_code_dim": (C.c_int, [_p, C.POINTER(_i32)]),
     "erq_index_get_rotation": (C.c_int, [_p, _p, _p]),
     "erq_index_save": (C.c_int, [_p, C.c_char_p, _p]),
     "erq_index_load": (C.c_int, [C.c_char_p, _p, C.POINTER(_p)]),
@@ -189,6 +191,16 @@ class Index:
         _check(load().erq_index_info(h, C.byref(n), C.byref(dp), C.byref(b), C.byref(nl), C.byref(cb)))
         return cls(dp.value, b.value, nl.value, _handle=h)
 
+    def set_projection(self, dc: int):
+        """Codes of dc < dp dimensions (App. C random projection); only on an
+        empty index."""
+        _check(load().erq_index_set_projection(self.h, dc, _stream()))
+
+    def code_dim(self) -> int:
+        dc = C.c_int32()
+        _check(load().erq_index_code_dim(self.h, C.byref(dc)))
+        return dc.value
+
     def save(self, path: str):
         _check(load().erq_index_save(self.h, os.fsencode(path), _stream()))
 
@@ -236,7 +248,7 @@ class Index:
         dev = self.device
         off = torch.empty(nl + 1, dtype=torch.int64, device=dev)
         ids = torch.empty(n, dtype=torch.int64, device=dev)
-        codes = torch.empty((n, dp), dtype=torch.uint8, device=dev)
+        codes = torch.empty((n, self.code_dim()), dtype=torch.uint8, device=dev)
         fa = torch.empty(n, dtype=torch.float32, device=dev)
         fr = torch.empty(n, dtype=torch.float32, device=dev)
         cr = torch.empty((nl, dp), dtype=torch.float32, device=dev)

@@ -32,7 +32,8 @@ class CandTerms:
             q = self.qrot[iq].astype(np.float64)
             return abs(float(self.crot[l].astype(np.float64) @ q)) + abs(0.5 * float(self.fr[p]) * float(yb @ q))
         s = self.qrot[iq].astype(np.float64) - self.crot[l].astype(np.float64)
-        return abs(float(self.fa[p])) + float(s @ s) + abs(float(self.fr[p]) * float(yb @ s))
+        # codes narrower than s (a projection): they meet its first coordinates
+        return abs(float(self.fa[p])) + float(s @ s) + abs(float(self.fr[p]) * float(yb @ s[:yb.shape[0]]))
 
 
 def compare_topk(gi, ge, oi, oe, terms, rel=1e-4):
