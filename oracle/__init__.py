@@ -71,6 +71,13 @@ def _load():
         lib.orc_rerank_ip.argtypes = [p, i32, p, i64, p, i32, i32, p, p]
         lib.orc_knn_ip.argtypes = [p, i64, i32, p, i64, i32, p, p]
         lib.orc_knn.argtypes = [p, i64, i32, p, i64, i32, p, p]
+        d = C.c_double
+        lib.orc_search_two_stage.argtypes = [p, p, p, p, p, p, p, i64, i32, i32,
+                                             p, i64, p, i32, i32, d, p, p, p]
+        lib.orc_search_two_stage.restype = i32
+        lib.orc_msb_bounds.argtypes = [p, p, i64, p, p, p, p, i64, i32, i32,
+                                       p, i64, p, i32, p, i32, d, p, p]
+        lib.orc_msb_bounds.restype = i32
         lib.orc_num_threads.restype = i32
         lib.orc_set_threads.argtypes = [i32]
         _lib = lib
@@ -257,6 +264,59 @@ def knn(x, q, k):
 # --------------------------------------------------------------------------
 # Inner-product metric: values are negated inner products, ascending.
 # --------------------------------------------------------------------------
+def search_two_stage(list_off, ids, codes, f_add, f_rescale, l1, crot, qrot, probes, B, kk, eps0):
+    """MSB-first two-stage IVF scan of Sec. 4.2 (erq_oracle.c, orc_search_two_stage):
+    the 1-bit estimate of the most significant bits with its Lemma 2.1 lower
+    bound prunes a candidate when it exceeds the kk-th best full estimate so
+    far; the rest get the full int8 estimate of search(est_mode=0), completed
+    by Eq. 4.2.  l1: ||r'||_1 per member (list order).  Returns (ids, est,
+    number of full estimates per query)."""
+    list_off = _c(list_off, np.int64)
+    ids = _c(ids, np.int64)
+    codes = _c(codes, np.uint8)
+    fa = _c(f_add, np.float32)
+    fr = _c(f_rescale, np.float32)
+    l1 = _c(l1, np.float64)
+    crot = _c(crot, np.float32)
+    qrot = _c(qrot, np.float32)
+    probes = _c(probes, np.int32)
+    nq, dp = qrot.shape
+    nprobe = probes.shape[1]
+    oi = np.empty((nq, kk), np.int64)
+    od = np.empty((nq, kk), np.float64)
+    nf = np.empty(nq, np.int64)
+    rc = _load().orc_search_two_stage(_p(list_off), _p(ids), _p(codes), _p(fa), _p(fr), _p(l1), _p(crot),
+                                      crot.shape[0], dp, B, _p(qrot), nq, _p(probes), nprobe, kk, float(eps0),
+                                      _p(oi), _p(od), _p(nf))
+    if rc != 0:
+        raise ValueError("bad arguments to search_two_stage")
+    return oi, od, nf
+
+
+def msb_bounds(list_off, ids, codes, f_add, l1, crot, qrot, probes, B, cand, eps0):
+    """(est1, lb) of the 1-bit stage for candidate ids cand[nq x m] (Sec. 4.2,
+    Lemma 2.1; erq_oracle.c, orc_msb_bounds); +inf for ids < 0."""
+    list_off = _c(list_off, np.int64)
+    ids = _c(ids, np.int64)
+    codes = _c(codes, np.uint8)
+    fa = _c(f_add, np.float32)
+    l1 = _c(l1, np.float64)
+    crot = _c(crot, np.float32)
+    qrot = _c(qrot, np.float32)
+    probes = _c(probes, np.int32)
+    cand = _c(cand, np.int64)
+    nq, dp = qrot.shape
+    m = cand.shape[1]
+    e1 = np.empty((nq, m), np.float64)
+    lb = np.empty((nq, m), np.float64)
+    rc = _load().orc_msb_bounds(_p(list_off), _p(ids), ids.shape[0], _p(codes), _p(fa), _p(l1), _p(crot),
+                                crot.shape[0], dp, B, _p(qrot), nq, _p(probes), probes.shape[1], _p(cand), m,
+                                float(eps0), _p(e1), _p(lb))
+    if rc != 0:
+        raise ValueError("bad arguments to msb_bounds")
+    return e1, lb
+
+
 def search_ip(list_off, ids, codes, f_add, f_rescale, crot, qrot, probes, B, kk, cos_oo=None, est_mode=0):
     """IVF scan by largest estimated inner product (erq_oracle.c, orc_search_ip)."""
     list_off = _c(list_off, np.int64)

@@ -743,6 +743,164 @@ void orc_knn_ip(const float* x, int64_t n, int dp, const float* q, int64_t nq, i
     }
 }
 
+/* ------------------------------------------------------------------------ */
+/* MSB-first two-stage scan (Sec. 4.2).                                      */
+/* ------------------------------------------------------------------------ */
+/* The most significant bit of every coordinate of y_u is RaBitQ's 1-bit code
+   x_b of the same residual (both are its orthant), so
+     y_u = 2^(B-1) x_b + y_last                       (Eq. 4.2, decomposition)
+   with y_last the B-1 low bits.  The 1-bit estimate is RaBitQ's (the B = 1
+   case of the method) with the factors of the same residual: for the
+   centred code x = x_b - 1/2, <x, r'> = ||r'||_1 / 2 =: l1 / 2, hence
+     f1 = -2 ||r||^2 / <x, r'> = -4 f_add / l1,
+     est1 = f_add + ||s||^2 + f1 <x, s'>,
+   and with the int8 query of orc_search, 2<x, q'> ~= delta (2<x_b, q_int> -
+   sum q_int).  Lemma 2.1 bounds the error of the unit-vector inner product
+   behind est1 by sqrt(1 - c^2)/c * eps0/sqrt(D - 1), where
+   c = <o_bar0, o> = <x, r'>/(||x|| ||r||) = l1/(sqrt(D) ||r||); scaled to
+   the squared distance (est = ||r||^2 + ||s||^2 - 2 ||r|| ||s|| <o, q>):
+     lb = est1 - 2 ||r|| ||s|| sqrt(1 - c^2)/c * eps0/sqrt(D - 1).
+   Members with r = 0 (f_add = 0) or l1 = 0 have an exact est1 = ||s||^2. */
+static void orc_msb_lb(const uint8_t* cd, int dp, int B, const int8_t* qq, double delta, int32_t qsum,
+                       const float* cv, double ns2, double f_add, double l1, double eps0,
+                       int64_t* ip_msb, double* est1, double* lb)
+{
+    int64_t ipm = 0;
+    double xc = 0.0;
+    for (int i = 0; i < dp; ++i) {
+        const int xb = cd[i] >> (B - 1);
+        ipm += (int64_t)xb * (int64_t)qq[i];
+        xc += ((double)xb - 0.5) * (double)cv[i];
+    }
+    *ip_msb = ipm;
+    if (!(f_add > 0.0) || !(l1 > 0.0)) { *est1 = ns2; *lb = ns2; return; }
+    const double f1 = -4.0 * f_add / l1;
+    const double xs = 0.5 * delta * (double)(2 * ipm - (int64_t)qsum) - xc;     /* <x, s'> */
+    *est1 = f_add + ns2 + f1 * xs;
+    const double nr = sqrt(f_add), c = l1 / (sqrt((double)dp) * nr);
+    const double cc = c < 1.0 ? c : 1.0;
+    *lb = *est1 - 2.0 * nr * sqrt(ns2) * sqrt(1.0 - cc * cc) / cc * eps0 / sqrt((double)dp - 1.0);
+}
+
+/* The paper's procedure for one query at a time, in a fixed order (probe
+   rank, then list order): a candidate whose lower bound lb exceeds the
+   kk-th best full estimate found so far is dropped; otherwise its full
+   estimate is completed from the reused <x_b, q_int>:
+     <y_u, q_int> = 2^(B-1) <x_b, q_int> + <y_last, q_int>   (Eq. 4.2, simplify)
+   and evaluated exactly as in orc_search (est_mode 0).  l1[N]: ||r'||_1 per
+   member (list order).  n_full[nq] (or NULL): full estimates computed. */
+int orc_search_two_stage(const int64_t* list_off, const int64_t* ids, const uint8_t* codes,
+                         const float* f_add, const float* f_rescale, const double* l1,
+                         const float* crot, int64_t C, int dp, int B,
+                         const float* qrot, int64_t nq, const int32_t* probes, int nprobe,
+                         int kk, double eps0, int64_t* out_ids, double* out_d, int64_t* n_full)
+{
+    if (dp <= 1 || B < 2 || B > 8 || kk < 1) return -1;
+    int bad = 0;
+    #pragma omp parallel reduction(|:bad)
+    {
+        double* sd = (double*)malloc(sizeof(double) * dp);
+        int8_t* qq = (int8_t*)malloc((size_t)dp);
+        orc_cand* top = (orc_cand*)malloc(sizeof(orc_cand) * (size_t)(kk + 1));
+        const double half = ((double)((1 << B) - 1)) / 2.0;
+        const int lowmask = (1 << (B - 1)) - 1;
+        #pragma omp for schedule(dynamic, 1)
+        for (int64_t iq = 0; iq < nq; ++iq) {
+            float delta; int32_t qsum;
+            const float* qv = qrot + iq * (int64_t)dp;
+            orc_query_quant(qv, dp, qq, &delta, &qsum);
+            int nt = 0;                               /* top[0..nt) ascending by (est, id) */
+            int64_t nf = 0;
+            for (int p = 0; p < nprobe; ++p) {
+                const int32_t l = probes[iq * nprobe + p];
+                if (l < 0) continue;
+                if (l >= C) { bad = 1; continue; }
+                const float* cv = crot + (int64_t)l * dp;
+                double ns2 = 0.0;
+                for (int i = 0; i < dp; ++i) { sd[i] = (double)qv[i] - (double)cv[i]; ns2 += sd[i] * sd[i]; }
+                for (int64_t v = list_off[l]; v < list_off[l + 1]; ++v) {
+                    const uint8_t* cd = codes + v * (int64_t)dp;
+                    int64_t ipm; double est1, lb;
+                    orc_msb_lb(cd, dp, B, qq, (double)delta, qsum, cv, ns2, (double)f_add[v], l1[v], eps0,
+                               &ipm, &est1, &lb);
+                    if (nt == kk && lb > top[kk - 1].d) continue;        /* pruned by the 1-bit bound */
+                    int64_t ipl = 0;
+                    double ybc = 0.0;
+                    for (int i = 0; i < dp; ++i) {
+                        ipl += (int64_t)(cd[i] & lowmask) * (int64_t)qq[i];
+                        ybc += ((double)cd[i] - half) * (double)cv[i];
+                    }
+                    const int64_t ipu = ipm * (int64_t)(1 << (B - 1)) + ipl;
+                    orc_cand c;
+                    c.d = orc_est_int8(ipu, qsum, B, (double)delta, ybc, ns2, (double)f_add[v],
+                                       (double)f_rescale[v]);
+                    c.id = ids[v];
+                    ++nf;
+                    /* insert into the sorted top list */
+                    int pos = nt;
+                    while (pos > 0 && orc_cand_cmp(&c, &top[pos - 1]) < 0) { top[pos] = top[pos - 1]; --pos; }
+                    top[pos] = c;
+                    if (nt < kk) ++nt;
+                }
+            }
+            for (int j = 0; j < kk; ++j) {
+                if (j < nt) { out_ids[iq * kk + j] = top[j].id; out_d[iq * kk + j] = top[j].d; }
+                else { out_ids[iq * kk + j] = -1; out_d[iq * kk + j] = INFINITY; }
+            }
+            if (n_full) n_full[iq] = nf;
+        }
+        free(sd); free(qq); free(top);
+    }
+    return bad ? -1 : 0;
+}
+
+/* est1 and lb (above) of given candidates: cand[nq x m] member ids (< 0
+   skipped, giving +inf), each looked up in the query's probed lists. */
+int orc_msb_bounds(const int64_t* list_off, const int64_t* ids, int64_t N, const uint8_t* codes,
+                   const float* f_add, const double* l1, const float* crot, int64_t C, int dp, int B,
+                   const float* qrot, int64_t nq, const int32_t* probes, int nprobe,
+                   const int64_t* cand, int m, double eps0, double* out_est1, double* out_lb)
+{
+    if (dp <= 1 || B < 2 || B > 8) return -1;
+    int64_t maxid = -1;
+    for (int64_t v = 0; v < N; ++v) if (ids[v] > maxid) maxid = ids[v];
+    int64_t* pos = (int64_t*)malloc(sizeof(int64_t) * (size_t)(maxid + 2));
+    for (int64_t i = 0; i <= maxid; ++i) pos[i] = -1;
+    for (int64_t v = 0; v < N; ++v) pos[ids[v]] = v;
+    int bad = 0;
+    #pragma omp parallel reduction(|:bad)
+    {
+        int8_t* qq = (int8_t*)malloc((size_t)dp);
+        #pragma omp for schedule(dynamic, 1)
+        for (int64_t iq = 0; iq < nq; ++iq) {
+            float delta; int32_t qsum;
+            const float* qv = qrot + iq * (int64_t)dp;
+            orc_query_quant(qv, dp, qq, &delta, &qsum);
+            for (int j = 0; j < m; ++j) {
+                out_est1[iq * m + j] = INFINITY; out_lb[iq * m + j] = INFINITY;
+                const int64_t id = cand[iq * m + j];
+                if (id < 0 || id > maxid || pos[id] < 0) continue;
+                const int64_t v = pos[id];
+                int l = -1;
+                for (int p = 0; p < nprobe; ++p) {
+                    const int32_t t = probes[iq * nprobe + p];
+                    if (t >= 0 && t < C && list_off[t] <= v && v < list_off[t + 1]) { l = t; break; }
+                }
+                if (l < 0) { bad = 1; continue; }
+                const float* cv = crot + (int64_t)l * dp;
+                double ns2 = 0.0;
+                for (int i = 0; i < dp; ++i) { const double d = (double)qv[i] - (double)cv[i]; ns2 += d * d; }
+                int64_t ipm;
+                orc_msb_lb(codes + v * (int64_t)dp, dp, B, qq, (double)delta, qsum, cv, ns2, (double)f_add[v],
+                           l1[v], eps0, &ipm, &out_est1[iq * m + j], &out_lb[iq * m + j]);
+            }
+        }
+        free(qq);
+    }
+    free(pos);
+    return bad ? -1 : 0;
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP
