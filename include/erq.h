@@ -145,6 +145,26 @@ int erq_index_destroy(erq_index idx);
    import) with the L2 metric (ERQ_EUNSUPPORTED otherwise).  Synchronises
    `stream`. */
 int erq_index_set_projection(erq_index idx, int32_t dc, void* stream);
+/* MSB-first two-stage scan (Sec. 4.2).  The most significant bit of every
+   coordinate of y_u is RaBitQ's 1-bit code of the same residual; the scan
+   first estimates every (member, query) pair from those bits alone,
+     est1 = f_add + ||s||^2 + f1 <x, s'>,  x = x_b - 1/2, f1 = -4 f_add / ||r'||_1,
+   drops a pair whose Lemma 2.1 lower bound
+     est1 - eps0 * 2 ||r|| ||s|| sqrt(1 - c^2) / c / sqrt(D - 1),
+     c = ||r'||_1 / (sqrt(D) ||r||),
+   exceeds the query's current bound (an upper bound of its kk-th estimate),
+   and reads the full codes only for groups of 64 members in which some pair
+   is left; those pairs get the one-stage estimate.  A member of the one-stage
+   top-kk is lost only when its 1-bit bound fails (probability decreasing
+   like exp(-eps0^2 / 2)).  On an empty index, eps0 > 0 makes erq_index_build
+   store the 1-bit data (bit planes: dp/8 bytes, factors: 16 bytes per
+   member); on a built index it sets eps0 (0 = the one-stage scan; ERQ_EINVAL
+   when the index has no 1-bit data).  ERQ_EUNSUPPORTED for the
+   inner-product metrics, B = 1 and a projection; erq_index_import refuses an
+   index that requested it.  The 1-bit data and eps0 are saved with the
+   index. */
+int erq_index_set_two_stage(erq_index idx, float eps0);
+
 /* The code dimension dc (dp without a projection). */
 int erq_index_code_dim(erq_index idx, int32_t* dc);
 
@@ -152,11 +172,12 @@ int erq_index_code_dim(erq_index idx, int32_t* dc);
 int erq_index_get_rotation(erq_index idx, float* P_out, void* stream);
 
 /* Writes the whole index to a file (host path): a versioned header (magic
-   "ERQIDX", version 1, dp, bits, raw kept, metric, code dimension, nlist,
-   n, tiles, scan schedule, seed),
+   "ERQIDX", version 2, dp, bits, raw kept, metric, code dimension, nlist,
+   n, tiles, scan schedule, seed, two-stage flag and eps0),
    then P, raw and rotated centroids, list offsets, ids, factors, scan
-   factors, packed codes and, when kept, the raw vectors, in native byte
-   order.  Synchronises `stream`. */
+   factors, packed codes, when kept the raw vectors, and with the two-stage
+   scan its bit planes and 1-bit factors, in native byte order.
+   Synchronises `stream`. */
 int erq_index_save(erq_index idx, const char* path, void* stream);
 /* Reads a file of erq_index_save into a new index on the current device.
    ERQ_EINVAL for a file that is not an index, whose size does not match its

@@ -84,8 +84,10 @@ void free_index_storage(Index* ix)
     hipFree(ix->cent_hi); hipFree(ix->cent_lo); hipFree(ix->cent_n2);
     ix->cent_hi = ix->cent_lo = nullptr; ix->cent_n2 = nullptr;
     hipFree(ix->list_order); hipFree(ix->ids); hipFree(ix->fac); hipFree(ix->sfac); hipFree(ix->codes);
+    hipFree(ix->msb); hipFree(ix->fac1);
     ix->cent = ix->cent_rot = nullptr; ix->list_off = ix->tile_off = nullptr; ix->list_order = nullptr;
     ix->ids = nullptr; ix->fac = nullptr; ix->sfac = nullptr; ix->codes = nullptr;
+    ix->msb = nullptr; ix->fac1 = nullptr;
     ix->n = 0; ix->ntiles = 0; ix->h_list_off.clear(); ix->max_list = 0;
 }
 
@@ -128,6 +130,23 @@ __global__ void copy_cols_kernel(const int64_t* ids, const float* est, int64_t n
     const bool in = !k_q || t < k_q[q];
     oi[i] = in ? ids[q * kin + t] : -1;
     oe[i] = in ? est[q * kin + t] : __builtin_huge_valf();
+}
+
+// ||r'||_1 of each row of a rotated batch (one wave per row, FP64 sum)
+__global__ void row_l1_kernel(const float* rot, int64_t m, int d, float* out) {
+    const int lane = threadIdx.x & 63;
+    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= m) return;
+    double s = 0.0;
+    for (int i = lane; i < d; i += 64) s += fabs((double)rot[r * d + i]);
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) out[r] = (float)s;
+}
+
+// the most significant bit of each B-bit code value (RaBitQ's 1-bit code)
+__global__ void msb_kernel(const uint8_t* in, int64_t count, int shift, uint8_t* out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) out[i] = (uint8_t)(in[i] >> shift);
 }
 
 // projection fix-up: f_add = ||r||^2 over all dp coordinates, f_rescale
@@ -353,7 +372,7 @@ int kmeans_impl(const float* x, int64_t n, int dp, int64_t C, int iters, uint64_
 
 // ---- index files --------------------------------------------------------------
 constexpr char kMagic[8] = {'E', 'R', 'Q', 'I', 'D', 'X', '\0', '\0'};
-constexpr uint32_t kFileVersion = 1;
+constexpr uint32_t kFileVersion = 2;
 struct FileHeader {
     char magic[8];
     uint32_t version;
@@ -361,6 +380,8 @@ struct FileHeader {
     int64_t nlist, n, ntiles;
     int32_t tune[4];
     uint64_t seed;
+    int32_t two_stage;                               // 1: the two-stage scan's data follow the codes
+    float eps0;
 };
 
 // bytes of every array of an index file after the header, in file order
@@ -374,7 +395,9 @@ std::vector<size_t> file_arrays(const FileHeader& h) {
             sizeof(float2) * n,                   // (f_add, f_rescale)
             sizeof(float2) * n,                   // scan factors
             (size_t)4 * (size_t)h.dc * h.bits * (size_t)h.ntiles,   // packed codes
-            h.has_raw ? sizeof(float) * n * dp : 0};      // raw vectors
+            h.has_raw ? sizeof(float) * n * dp : 0,       // raw vectors
+            h.two_stage ? (size_t)4 * (size_t)h.dc * (size_t)h.ntiles : 0,   // most significant bit planes
+            h.two_stage ? sizeof(float4) * n : 0};        // 1-bit factors
 }
 
 // device <-> file through a host staging buffer, in chunks
@@ -528,14 +551,17 @@ int erq_index_save(erq_index ix, const char* path, void* stream)
     h.nlist = ix->nlist; h.n = ix->n; h.ntiles = ix->ntiles;
     h.tune[0] = ix->tune_nqt; h.tune[1] = ix->tune_pd; h.tune[2] = ix->tune_round1; h.tune[3] = ix->tune_round2;
     h.seed = ix->seed;
+    h.two_stage = ix->msb ? 1 : 0;
+    h.eps0 = ix->eps0;
     FILE* f = std::fopen(path, "wb");
     if (!f) return fail(ERQ_EINVAL, std::string("erq_index_save: cannot open ") + path);
     struct Closer { FILE* f; ~Closer() { if (f) std::fclose(f); } } closer{f};
     if (fwrite(&h, sizeof(h), 1, f) != 1) return fail(ERQ_EINVAL, "erq_index_save: write failed");
     std::vector<char> buf((size_t)64 << 20);
-    const void* src[9] = {ix->P, ix->cent, ix->cent_rot, ix->list_off, ix->ids, ix->fac, ix->sfac, ix->codes, ix->raw};
+    const void* src[11] = {ix->P, ix->cent, ix->cent_rot, ix->list_off, ix->ids, ix->fac, ix->sfac, ix->codes,
+                           ix->raw, ix->msb, ix->fac1};
     const std::vector<size_t> sz = file_arrays(h);
-    for (int a = 0; a < 9; ++a)
+    for (int a = 0; a < 11; ++a)
         if (sz[a]) { if (int rc = dev_to_file(f, src[a], sz[a], buf, st)) return rc; }
     if (std::fclose(f) != 0) { closer.f = nullptr; return fail(ERQ_EINVAL, "erq_index_save: close failed"); }
     closer.f = nullptr;
@@ -555,7 +581,8 @@ int erq_index_load(const char* path, void* stream, erq_index* out)
     if (h.version != kFileVersion) return fail(ERQ_EUNSUPPORTED, "erq_index_load: unknown file version");
     if (h.dp < 64 || h.dp > kMaxDp || h.dp % 64 || h.bits < 1 || h.bits > 8 || h.nlist < 1 ||
         h.nlist > (1 << 24) || h.n < 0 || h.n > (1LL << 31) - 1 || h.ntiles < 0 || (h.has_raw != 0 && h.has_raw != 1) ||
-        h.metric < ERQ_METRIC_L2 || h.metric > ERQ_METRIC_COSINE || h.dc < 64 || h.dc > h.dp || h.dc % 64)
+        h.metric < ERQ_METRIC_L2 || h.metric > ERQ_METRIC_COSINE || h.dc < 64 || h.dc > h.dp || h.dc % 64 ||
+        (h.two_stage != 0 && h.two_stage != 1) || !(h.eps0 >= 0.0f) || !(h.eps0 < 1e30f))
         return fail(ERQ_EINVAL, "erq_index_load: bad header");
     const std::vector<size_t> sz = file_arrays(h);
     size_t total = sizeof(h);
@@ -579,6 +606,7 @@ int erq_index_load(const char* path, void* stream, erq_index* out)
     if (!ix) return fail(ERQ_ENOMEM, "erq_index_load: out of host memory");
     struct Owner { erq_index_s* p; ~Owner() { if (p) erq_index_destroy(p); } } owner{ix};
     ix->dp = dp; ix->bits = h.bits; ix->nlist = C; ix->seed = h.seed; ix->metric = h.metric; ix->dc = h.dc;
+    ix->two_stage = h.two_stage; ix->eps0 = h.eps0;
     ix->tune_nqt = h.tune[0]; ix->tune_pd = h.tune[1]; ix->tune_round1 = h.tune[2]; ix->tune_round2 = h.tune[3];
     hipGetDevice(&ix->device);
     if (int rc = set_list_meta(ix, off, st)) return rc;
@@ -592,9 +620,14 @@ int erq_index_load(const char* path, void* stream, erq_index* out)
     ERQ_HIP(hipMalloc(&ix->sfac, std::max<size_t>(sz[6], 8)));
     ERQ_HIP(hipMalloc(&ix->codes, std::max<size_t>(sz[7], 256)));
     if (h.has_raw) ERQ_HIP(hipMalloc(&ix->raw, std::max<size_t>(sz[8], 4)));
-    void* dst[9] = {ix->P, ix->cent, ix->cent_rot, nullptr, ix->ids, ix->fac, ix->sfac, ix->codes, ix->raw};
+    if (h.two_stage) {
+        ERQ_HIP(hipMalloc(&ix->msb, std::max<size_t>(sz[9], 256)));
+        ERQ_HIP(hipMalloc(&ix->fac1, std::max<size_t>(sz[10], 16)));
+    }
+    void* dst[11] = {ix->P, ix->cent, ix->cent_rot, nullptr, ix->ids, ix->fac, ix->sfac, ix->codes, ix->raw,
+                     ix->msb, ix->fac1};
     std::vector<char> buf((size_t)64 << 20);
-    for (int a = 0; a < 9; ++a) {
+    for (int a = 0; a < 11; ++a) {
         if (a == 3) { std::fseek(f, (long)sz[3], SEEK_CUR); continue; }   // list offsets: already uploaded
         if (sz[a]) { if (int rc = file_to_dev(f, dst[a], sz[a], buf, st)) return rc; }
     }
@@ -614,11 +647,30 @@ int erq_index_set_projection(erq_index ix, int32_t dc, void* stream)
     if (!ix) return fail(ERQ_EINVAL, "erq_index_set_projection: null index");
     if (ix->list_off) return fail(ERQ_EINVAL, "erq_index_set_projection: the index already holds vectors");
     if (ix->metric != ERQ_METRIC_L2) return fail(ERQ_EUNSUPPORTED, "erq_index_set_projection: L2 metric only");
+    if (ix->two_stage && dc != ix->dp)
+        return fail(ERQ_EUNSUPPORTED, "erq_index_set_projection: not with the two-stage scan");
     if (dc < 64 || dc > ix->dp || dc % 64 != 0)
         return fail(ERQ_ESHAPE, "erq_index_set_projection: dc must be a multiple of 64 in [64, dp]");
     ix->dc = dc;
     if (int rc = set_projection_matrix(ix, (hipStream_t)stream)) return rc;
     ERQ_HIP(hipStreamSynchronize((hipStream_t)stream));
+    return ERQ_OK;
+}
+
+int erq_index_set_two_stage(erq_index ix, float eps0)
+{
+    if (!ix) return fail(ERQ_EINVAL, "erq_index_set_two_stage: null index");
+    if (!(eps0 >= 0.0f) || !(eps0 < 1e30f)) return fail(ERQ_EINVAL, "erq_index_set_two_stage: eps0 must be >= 0");
+    if (eps0 > 0.0f && (ix->metric != ERQ_METRIC_L2 || ix->bits < 2 || ix->dc != ix->dp))
+        return fail(ERQ_EUNSUPPORTED, "erq_index_set_two_stage: needs the L2 metric, bits >= 2, no projection");
+    if (!ix->list_off) {                             // empty: the build computes the 1-bit data
+        ix->two_stage = eps0 > 0.0f ? 1 : 0;
+        ix->eps0 = eps0;
+        return ERQ_OK;
+    }
+    if (eps0 > 0.0f && !ix->msb)
+        return fail(ERQ_EINVAL, "erq_index_set_two_stage: the index holds no 1-bit data (request it before the build)");
+    ix->eps0 = eps0;
     return ERQ_OK;
 }
 
@@ -658,6 +710,7 @@ int erq_index_import(erq_index ix, int64_t n, const int64_t* list_off, const int
     if (n < 0 || n > (1LL << 31) - 1) return fail(ERQ_EINVAL, "erq_index_import: n out of range");
     if (!list_off || !centroids || (n > 0 && (!ids || !codes || !f_add || !f_rescale)))
         return fail(ERQ_EINVAL, "erq_index_import: null pointer");
+    if (ix->two_stage) return fail(ERQ_EUNSUPPORTED, "erq_index_import: the two-stage data need erq_index_build");
     hipStream_t st = (hipStream_t)stream;
     const int64_t C = ix->nlist;
     const int dp = ix->dp;
@@ -833,6 +886,11 @@ int erq_index_build(erq_index ix, const float* x, int64_t n, const float* centro
     ERQ_HIP(hipMalloc(&rot, sizeof(float) * bt * dc));
     ERQ_HIP(hipMalloc(&nrm, sizeof(float) * bt));
     guard.p.push_back(res); guard.p.push_back(rot); guard.p.push_back(nrm);
+    float* l1 = nullptr;                            // ||r'||_1 per member (two-stage scan)
+    if (ix->two_stage) {
+        ERQ_HIP(hipMalloc(&l1, sizeof(float) * std::max<int64_t>(n, 1)));
+        guard.p.push_back(l1);
+    }
     for (int64_t v0 = 0; v0 < n; v0 += bt) {
         int64_t m = std::min(bt, n - v0);
         ERQ_HIP(launch_residual(x, ix->ids + v0, asg, ix->cent, m, dp, res, nrm, st));
@@ -850,11 +908,30 @@ int erq_index_build(erq_index ix, const float* x, int64_t n, const float* centro
                                ix->fac + v0);
             ERQ_HIP(hipGetLastError());
         }
+        if (l1) {
+            hipLaunchKernelGGL(row_l1_kernel, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, st, rot, m, dc, l1 + v0);
+            ERQ_HIP(hipGetLastError());
+        }
         prof_end(pr, st);
     }
     ERQ_HIP(launch_pack_n(codes_u, ix->list_off, ix->tile_off, C, dc, ix->bits, ix->ntiles, ix->codes, st));
     ERQ_HIP(launch_scan_fac(codes_u, ix->list_off, C, ix->cent_rot, ix->fac, n, dc, dp, ix->bits, ix->metric,
                             ix->sfac, st));
+    if (ix->two_stage) {
+        // the most significant bit planes in the 1-bit tile layout, and the 1-bit factors
+        uint8_t* mu = nullptr;
+        ERQ_HIP(hipMalloc(&mu, std::max<int64_t>(n, 1) * dc));
+        guard.p.push_back(mu);
+        ERQ_HIP(hipMalloc(&ix->msb, std::max<int64_t>((int64_t)4 * dc * ix->ntiles, 256)));
+        ERQ_HIP(hipMalloc(&ix->fac1, sizeof(float4) * std::max<int64_t>(n, 1)));
+        if (n > 0) {
+            hipLaunchKernelGGL(msb_kernel, dim3(blocks(n * dc)), dim3(256), 0, st, codes_u, n * dc, ix->bits - 1, mu);
+            ERQ_HIP(hipGetLastError());
+        }
+        ERQ_HIP(launch_pack_n(mu, ix->list_off, ix->tile_off, C, dc, 1, ix->ntiles, ix->msb, st));
+        ERQ_HIP(launch_scan1_fac(codes_u, ix->list_off, C, ix->cent_rot, dp, ix->fac, l1, n, dc, ix->bits, ix->fac1,
+                                 st));
+    }
     if (keep_raw && n > 0) {
         ERQ_HIP(hipMalloc(&ix->raw, sizeof(float) * n * dp));
         ERQ_HIP(hipMemcpyAsync(ix->raw, x, sizeof(float) * n * dp, hipMemcpyDeviceToDevice, st));

@@ -85,6 +85,13 @@ struct Index {
     float2* fac = nullptr;         // n, (f_add, f_rescale), list order
     float2* sfac = nullptr;        // n, (f_add - f_rescale <y_bar, c'>, f_rescale): the scan's factors
     uint8_t* codes = nullptr;      // ntiles * 4 * dc * bits bytes
+    // two-stage scan (Sec. 4.2): requested before the build; its data are the
+    // most significant bit planes (ntiles * 4 * dc bytes, the 1-bit tile
+    // layout) and the 1-bit factors (g1, f1, e1, 0) per member
+    int two_stage = 0;
+    float eps0 = 0.0f;             // > 0: the scan prunes with the 1-bit bound at this eps0
+    uint8_t* msb = nullptr;
+    float4* fac1 = nullptr;
     float* raw = nullptr;          // n x dp raw vectors (id order) or null
     int64_t ntiles = 0;
     std::vector<int64_t> h_list_off;
@@ -132,6 +139,10 @@ int run_scan(Index* ix, const float* qrot, int64_t qld, int64_t nq, const int32_
 // L2 (g_add, f_rescale) with g_add = f_add - f_rescale <y_bar, c'>; the
 // inner-product metrics (0, f_rescale / 2)
 // codes_u: n x dc; cent_rot: nlist x ld (its first dc coordinates are used)
+// 1-bit factors of the two-stage scan (codes_u: n x dp; cent_rot rows ld apart)
+hipError_t launch_scan1_fac(const uint8_t* codes_u, const int64_t* list_off, int64_t nlist, const float* cent_rot,
+                            int ld, const float2* fac, const float* l1, int64_t n, int dp, int bits, float4* fac1,
+                            hipStream_t st);
 hipError_t launch_scan_fac(const uint8_t* codes_u, const int64_t* list_off, int64_t nlist, const float* cent_rot,
                            const float2* fac, int64_t n, int dc, int ld, int bits, int metric, float2* sfac,
                            hipStream_t st);

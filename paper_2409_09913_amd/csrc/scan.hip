@@ -508,6 +508,260 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
 
 
 // ---------------------------------------------------------------------------
+// Two-stage pass B (Sec. 4.2, most significant bits first).  For a group of
+// two code tiles, every (member, query) pair first gets the 1-bit estimate
+// of the most significant bit planes (RaBitQ's code of the same residual),
+//     est1 = g1 + f1 * delta/2 * (2 <x_b, q_int> - sum q_int) + ||s||^2,
+// g1 = f_add - f1 <x, c'> (x = x_b - 1/2, f1 = -4 f_add / ||r'||_1), and its
+// Lemma 2.1 lower bound est1 - eps0 ||s|| e1 (e1 = 2 ||r|| sqrt(1 - c^2) / c
+// / sqrt(D - 1), c = ||r'||_1 / (sqrt(D) ||r||), per member).  Pairs whose
+// bound is above the query's bound are dropped; when no pair of the group is
+// left, the group's full codes are never read.  Otherwise the full product
+// <y_u, q_int> of the group is taken from the full codes (on the matrix cores
+// it costs the same as the product of the remaining bits alone), and the
+// pairs kept by the first stage get the one-stage estimate and bound test.
+// ---------------------------------------------------------------------------
+constexpr int kVch2 = 384;     // members per item (the LDS also holds their 1-bit factors)
+
+template <int BITS, int NQT>
+__global__ __launch_bounds__(kThreads, 2) void scan2_kernel(
+    const uint8_t* __restrict__ codes, const uint8_t* __restrict__ msb, const int64_t* __restrict__ tile_off,
+    const int64_t* __restrict__ list_off, const float2* __restrict__ fac, const float4* __restrict__ fac1,
+    const int64_t* __restrict__ ids, int dp, QArgs qa, const int32_t* __restrict__ pair_q,
+    const int32_t* __restrict__ pair_slot, const int32_t* __restrict__ item_off, const int4* __restrict__ desc,
+    int nlist, unsigned* __restrict__ tau_key, int32_t* __restrict__ gcnt, float* __restrict__ gbuf_e,
+    int32_t* __restrict__ gbuf_i, int32_t* __restrict__ work, float eps0)
+{
+    constexpr int QPI = kQT * NQT;
+    constexpr int KC = 4;                          // K-blocks whose words are loaded together
+    extern __shared__ __align__(16) char smem[];
+    __shared__ float s_s2[QPI], s_hd[QPI];
+    __shared__ int s_ss[QPI], s_slot[QPI], s_q[QPI], s_cnt[QPI], s_base[QPI];
+    __shared__ float s_be[QPI][kCapB];
+    __shared__ int s_bi[QPI][kCapB];
+    __shared__ unsigned s_tau[QPI];
+    __shared__ float2 s_fac[kVch2 + 64];
+    __shared__ float4 s_f1[kVch2 + 64];
+    __shared__ int s_id[kVch2 + 64];
+    __shared__ int s_item[5];
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int n_items = item_off[nlist];
+    if (tid == 0) s_item[4] = atomicAdd(work, 1);
+    __syncthreads();
+    for (;;) {
+    const int item = s_item[4];
+    if (item >= n_items) break;
+    if (tid == 0) {
+        const int4 d = desc[item];
+        s_item[0] = d.x; s_item[1] = d.y; s_item[2] = d.z; s_item[3] = d.w;
+    }
+    if (tid < QPI) s_cnt[tid] = 0;
+    __syncthreads();
+    if (tid == 0) s_item[4] = atomicAdd(work, 1);  // read again only after the item's last barrier
+    const int l = s_item[0], p0 = s_item[1], mq = s_item[2], v0 = s_item[3];
+    int8_t* qs = (int8_t*)smem;
+    const int qstride = dp + 16;
+    load_query_scalars(s_s2, s_hd, s_ss, s_slot, s_q, s_tau, tau_key, qa, pair_q + p0, pair_slot + p0, mq, tid);
+    {   // factors (both stages) and ids of the item's members; past the end NaN, which never passes
+        constexpr int KF = (kVch2 + 64 + kThreads - 1) / kThreads;
+        const int64_t fb = list_off[l] + v0;
+        const int nf = min((int)(list_off[l + 1] - list_off[l]) - v0, kVch2);
+        const int nfp = (nf + 63) & ~63;
+        float2 fv[KF];
+        float4 gv[KF];
+        int iv[KF];
+#pragma unroll
+        for (int k = 0; k < KF; ++k) {
+            const int t = tid + k * kThreads;
+            const bool in = t < nf;
+            fv[k] = in ? fac[fb + t] : make_float2(__builtin_nanf(""), 0.0f);
+            gv[k] = in ? fac1[fb + t] : make_float4(__builtin_nanf(""), 0.0f, 0.0f, 0.0f);
+            iv[k] = in ? (int)ids[fb + t] : -1;
+        }
+#pragma unroll
+        for (int k = 0; k < KF; ++k) {
+            const int t = tid + k * kThreads;
+            if (t < nfp) { s_fac[t] = fv[k]; s_f1[t] = gv[k]; s_id[t] = iv[k]; }
+        }
+    }
+    __syncthreads();
+    load_query_rows<NQT>(qs, qstride, s_q, qa.qint, dp, mq, tid);
+    __syncthreads();
+
+    const int nkb = dp / 64;
+    const int8_t* qrow = qs + (lane & 31) * qstride + 16 * (lane >> 5);
+    const int64_t tile_bytes = (int64_t)4 * dp * BITS, tile1 = (int64_t)4 * dp;
+    const int nl = min((int)(list_off[l + 1] - list_off[l]) - v0, kVch2);
+    const int ntile = (nl + 31) >> 5;
+    const int64_t tbase = tile_off[l] + (v0 >> 5);
+    const int j = lane & 31;
+    // column constants as in scanB_kernel, for both code widths, and the
+    // bound's per-column factor eps0 * ||s||
+    float qs2[NQT], cH2[NQT], cHC[NQT], cH21[NQT], cHC1[NQT], cAQ[NQT], cEN[NQT];
+#pragma unroll
+    for (int qt = 0; qt < NQT; ++qt) {
+        const int qi = qt * kQT + j;
+        const bool ok = qi < mq;
+        qs2[qt] = ok ? s_s2[qi] : 0.0f;
+        const float hd = ok ? s_hd[qi] : 0.0f, tau = ok ? key2f(s_tau[qi]) : 0.0f;
+        const int ss = ok ? s_ss[qi] : 0;
+        epi_consts<BITS>(hd, ss, cH2[qt], cHC[qt]);
+        epi_consts<1>(hd, ss, cH21[qt], cHC1[qt]);
+        const float aq = tau - qs2[qt];
+        cAQ[qt] = ok ? aq + (fabsf(tau) + fabsf(qs2[qt])) * 0x1p-20f : -__builtin_huge_valf();
+        cEN[qt] = eps0 * sqrtf(fmaxf(qs2[qt], 0.0f));
+    }
+    const int ta = (wid * ntile) >> 2, tb = ((wid + 1) * ntile) >> 2;
+    for (int gt0 = ta; gt0 < tb; gt0 += 2) {
+        // a single-tile group (the last of an odd range) reads its tile twice
+        // and ignores the copy
+        const int64_t o0 = tbase + gt0, o1 = (gt0 + 1 < tb) ? o0 + 1 : o0;
+        v16i acc[2][NQT];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int qt = 0; qt < NQT; ++qt)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[a][qt][r] = 0;
+        // stage 1: the most significant bit planes
+        for (int kb0 = 0; kb0 < nkb; kb0 += KC) {
+            uint32_t w[KC][2];
+#pragma unroll
+            for (int p = 0; p < KC; ++p) {
+                const int kb = min(kb0 + p, nkb - 1);
+                w[p][0] = *(const uint32_t*)(msb + o0 * tile1 + kb * 256 + lane * 4);
+                w[p][1] = *(const uint32_t*)(msb + o1 * tile1 + kb * 256 + lane * 4);
+            }
+#pragma unroll
+            for (int p = 0; p < KC; ++p) {
+                const int kb = kb0 + p;
+                if (kb >= nkb) break;                   // wave-uniform
+                v4i a00, a01, a10, a11;
+                unpack_raw<1>(w[p], a00, a01);
+                unpack_raw<1>(w[p] + 1, a10, a11);
+#pragma unroll
+                for (int qt = 0; qt < NQT; ++qt) {
+                    const v4i b0 = *(const v4i*)(qrow + qt * kQT * qstride + 64 * kb);
+                    const v4i b1 = *(const v4i*)(qrow + qt * kQT * qstride + 64 * kb + 32);
+                    acc[0][qt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a00, b0, acc[0][qt], 0, 0, 0);
+                    acc[1][qt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a10, b0, acc[1][qt], 0, 0, 0);
+                    acc[0][qt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a01, b1, acc[0][qt], 0, 0, 0);
+                    acc[1][qt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a11, b1, acc[1][qt], 0, 0, 0);
+                }
+            }
+        }
+        // lower-bound test: bit a*16 + r of pm[qt] for every kept pair
+        uint32_t pm[NQT];
+#pragma unroll
+        for (int qt = 0; qt < NQT; ++qt) pm[qt] = 0;
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const int tt = gt0 + a;
+            if (tt >= tb) break;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const float4 g = s_f1[tt * 32 + out_row(lane, r)];
+#pragma unroll
+                for (int qt = 0; qt < NQT; ++qt) {
+                    const float e1 = epi_e(make_float2(g.x, g.y), acc[a][qt][r], cH21[qt], cHC1[qt]);
+                    if (__fmaf_rn(-cEN[qt], g.z, e1) <= cAQ[qt]) pm[qt] |= 1u << (a * 16 + r);
+                }
+            }
+        }
+        bool anyq = false;
+#pragma unroll
+        for (int qt = 0; qt < NQT; ++qt) anyq = anyq || pm[qt] != 0;
+        if (!__any(anyq)) continue;                     // the group's full codes are not read
+        // stage 2: the full codes
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int qt = 0; qt < NQT; ++qt)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[a][qt][r] = 0;
+        for (int kb0 = 0; kb0 < nkb; kb0 += KC) {
+            uint32_t w[KC][2 * BITS];
+#pragma unroll
+            for (int p = 0; p < KC; ++p) {
+                const int kb = min(kb0 + p, nkb - 1);
+                load_raw<BITS>(codes + o0 * tile_bytes + (int64_t)kb * 256 * BITS, lane, w[p]);
+                load_raw<BITS>(codes + o1 * tile_bytes + (int64_t)kb * 256 * BITS, lane, w[p] + BITS);
+            }
+#pragma unroll
+            for (int p = 0; p < KC; ++p) {
+                const int kb = kb0 + p;
+                if (kb >= nkb) break;
+                v4i a00, a01, a10, a11;
+                unpack_raw<BITS>(w[p], a00, a01);
+                unpack_raw<BITS>(w[p] + BITS, a10, a11);
+#pragma unroll
+                for (int qt = 0; qt < NQT; ++qt) {
+                    const v4i b0 = *(const v4i*)(qrow + qt * kQT * qstride + 64 * kb);
+                    const v4i b1 = *(const v4i*)(qrow + qt * kQT * qstride + 64 * kb + 32);
+                    acc[0][qt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a00, b0, acc[0][qt], 0, 0, 0);
+                    acc[1][qt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a10, b0, acc[1][qt], 0, 0, 0);
+                    acc[0][qt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a01, b1, acc[0][qt], 0, 0, 0);
+                    acc[1][qt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a11, b1, acc[1][qt], 0, 0, 0);
+                }
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const int tt = gt0 + a;
+            if (tt >= tb) break;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int v = tt * 32 + out_row(lane, r);
+                const uint32_t bit = 1u << (a * 16 + r);
+#pragma unroll
+                for (int qt = 0; qt < NQT; ++qt) {
+                    if (!(pm[qt] & bit)) continue;
+                    const float e = epi_e(s_fac[v], acc[a][qt][r], cH2[qt], cHC[qt]);
+                    if (!(e <= cAQ[qt])) continue;
+                    const float est = e + qs2[qt];
+                    const int qi = qt * kQT + j;
+                    const int id = s_id[v];
+                    const int pos = atomicAdd(&s_cnt[qi], 1);
+                    if (pos < kCapB) {
+                        s_be[qi][pos] = est; s_bi[qi][pos] = id;
+                    } else {                            // stage full: straight to HBM
+                        const int q = s_q[qi];
+                        const int gp = atomicAdd(&gcnt[q], 1);
+                        if (gp < kCapQ) {
+                            gbuf_e[(int64_t)q * kCapQ + gp] = est;
+                            gbuf_i[(int64_t)q * kCapQ + gp] = id;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // flush the LDS stage to the query's candidate buffer
+    const int qi = tid >> 2, sub = tid & 3;
+    if (qi < mq && sub == 0) {
+        const int m = min(s_cnt[qi], kCapB);
+        s_base[qi] = (m > 0) ? atomicAdd(&gcnt[s_q[qi]], m) : 0;
+    }
+    __syncthreads();
+    if (qi < mq) {
+        const int q = s_q[qi];
+        const int m = min(s_cnt[qi], kCapB);
+        const int base = s_base[qi];
+        for (int e = sub; e < m; e += 4) {
+            if (base + e < kCapQ) {
+                gbuf_e[(int64_t)q * kCapQ + base + e] = s_be[qi][e];
+                gbuf_i[(int64_t)q * kCapQ + base + e] = s_bi[qi][e];
+            }
+        }
+    }
+    __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Per query, over its candidate buffer (count c): radix select of the key of
 // the kk-th smallest estimate (4 passes of 8 bits).  One wave per query (4
 // per block); each pass re-reads the buffer (lane l: entries l, l + 64, ...,
@@ -1146,6 +1400,41 @@ __global__ __launch_bounds__(256) void scan_fac_kernel(const uint8_t* __restrict
     }
 }
 
+// 1-bit factors of the two-stage scan per member (list order), from the
+// most significant bits x_b of y_u and l1 = ||r'||_1:
+// (g1, f1, e1, 0) with f1 = -4 f_add / l1, g1 = f_add - f1 <x, c'> (x = x_b -
+// 1/2, FP64 accumulate) and e1 = 2 ||r|| sqrt(1 - c^2) / c / sqrt(D - 1),
+// c = l1 / (sqrt(D) ||r||); a member at its centroid gets (0, 0, 0, 0), whose
+// 1-bit estimate ||s||^2 is exact.  One wave per member.
+__global__ __launch_bounds__(256) void scan1_fac_kernel(const uint8_t* __restrict__ codes_u,
+                                                        const int64_t* __restrict__ list_off, int nlist,
+                                                        const float* __restrict__ cent_rot, int ld,
+                                                        const float2* __restrict__ fac, const float* __restrict__ l1,
+                                                        int64_t n, int dp, int bits, float4* __restrict__ fac1)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (v >= n) return;
+    int lo = 0, hi = nlist;
+    while (hi - lo > 1) { const int mid = (lo + hi) >> 1; if (list_off[mid] <= v) lo = mid; else hi = mid; }
+    const uint8_t* y = codes_u + v * dp;
+    const float* c = cent_rot + (int64_t)lo * ld;
+    double acc = 0.0;
+    for (int d = lane; d < dp; d += 64) acc += ((double)(y[d] >> (bits - 1)) - 0.5) * (double)c[d];
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if (lane == 0) {
+        const double fa = (double)fac[v].x, s1 = (double)l1[v];
+        float4 out = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (fa > 0.0 && s1 > 0.0) {
+            const double f1 = -4.0 * fa / s1, nr = sqrt(fa);
+            const double cc = fmin(s1 / (sqrt((double)dp) * nr), 1.0);
+            const double e1 = 2.0 * nr * sqrt(fmax(1.0 - cc * cc, 0.0)) / cc / sqrt((double)dp - 1.0);
+            out = make_float4((float)(fa - f1 * acc), (float)f1, (float)e1, 0.0f);
+        }
+        fac1[v] = out;
+    }
+}
+
 // before the first bound: slots [0, kDenseR*kDenseV) of every query's buffer
 // hold +inf, the count covers them, and the bound is +inf
 __global__ void fill_dense_kernel(float* __restrict__ gbuf_e, int64_t nq, int32_t* __restrict__ gcnt,
@@ -1512,6 +1801,50 @@ hipError_t launchB(const Index* ix, const ScanArgs& a, const BArgs& b, hipStream
     }
 }
 
+template <int BITS, int NQT>
+hipError_t launch2_n(const Index* ix, const ScanArgs& a, const BArgs& b, hipStream_t st)
+{
+    const void* kern = (const void*)scan2_kernel<BITS, NQT>;
+    const size_t sm = (size_t)(ix->dc + 16) * kQT * NQT;
+    if (sm > 48 * 1024) {
+        hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+        if (e != hipSuccess) return e;
+    }
+    int per_cu = 0, dev = 0, ncu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kThreads, sm);
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    const int64_t grid = std::min<int64_t>(a.grid, (int64_t)std::max(per_cu, 1) * std::max(ncu, 1));
+    hipLaunchKernelGGL((scan2_kernel<BITS, NQT>), dim3((unsigned)grid), dim3(kThreads), sm, st,
+                       ix->codes, ix->msb, ix->tile_off, ix->list_off, ix->sfac, ix->fac1, ix->ids, ix->dc,
+                       a.qa, a.pair_q, a.pair_slot, a.item_off, a.desc, (int)ix->nlist,
+                       b.tau_key, b.gcnt, b.gbuf_e, b.gbuf_i, b.work, ix->eps0);
+    return hipGetLastError();
+}
+
+template <int BITS>
+hipError_t launch2_b(const Index* ix, const ScanArgs& a, const BArgs& b, hipStream_t st)
+{
+    if (scan_nqt(ix) == 2) return launch2_n<BITS, 2>(ix, a, b, st);
+    return launch2_n<BITS, 1>(ix, a, b, st);
+}
+
+// two-stage pass B (B >= 2)
+hipError_t launch2(const Index* ix, const ScanArgs& a, const BArgs& b, hipStream_t st)
+{
+    switch (ix->bits) {
+        case 2: return launch2_b<2>(ix, a, b, st);
+        case 3: return launch2_b<3>(ix, a, b, st);
+        case 4: return launch2_b<4>(ix, a, b, st);
+        case 5: return launch2_b<5>(ix, a, b, st);
+        case 6: return launch2_b<6>(ix, a, b, st);
+        case 7: return launch2_b<7>(ix, a, b, st);
+        case 8: return launch2_b<8>(ix, a, b, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <int BITS>
 hipError_t launch_exact_b(const Index* ix, const QArgs& qa, const int32_t* probes, int64_t nq, int nprobe, int kk,
                           const int32_t* ovf, const int32_t* gate, int32_t* redo, int64_t* oi, float* oe,
@@ -1574,6 +1907,16 @@ int scan_pd(const Index* ix)
 int scan_round1(const Index* ix) { return ix->tune_round1 > 0 ? ix->tune_round1 : kRound1; }
 int scan_round2(const Index* ix) { return ix->tune_round2; }
 
+hipError_t launch_scan1_fac(const uint8_t* codes_u, const int64_t* list_off, int64_t nlist, const float* cent_rot,
+                            int ld, const float2* fac, const float* l1, int64_t n, int dp, int bits, float4* fac1,
+                            hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(scan1_fac_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, codes_u, list_off,
+                       (int)nlist, cent_rot, ld, fac, l1, n, dp, bits, fac1);
+    return hipGetLastError();
+}
+
 hipError_t launch_scan_fac(const uint8_t* codes_u, const int64_t* list_off, int64_t nlist, const float* cent_rot,
                            const float2* fac, int64_t n, int dp, int ld, int bits, int metric, float2* sfac,
                            hipStream_t st)
@@ -1584,10 +1927,10 @@ hipError_t launch_scan_fac(const uint8_t* codes_u, const int64_t* list_off, int6
     return hipGetLastError();
 }
 
-// items of one pair build: sum over lists of ceil(cnt/qpi) * ceil(n_l/kVch) <=
-// ceil(max_list/kVch) * (P/kQT + nlist) for any qpi >= kQT
+// items of one pair build: sum over lists of ceil(cnt/qpi) * ceil(n_l/vch) <=
+// ceil(max_list/vch) * (P/kQT + nlist) for any qpi >= kQT (vch >= kVch2)
 static int64_t desc_capacity(int64_t P, int64_t nlist, int64_t max_list) {
-    const int64_t chunks = std::max<int64_t>(1, (max_list + kVch - 1) / kVch);
+    const int64_t chunks = std::max<int64_t>(1, (max_list + kVch2 - 1) / kVch2);
     return chunks * (P / kQT + 1 + nlist);
 }
 
@@ -1719,13 +2062,16 @@ int run_scan(Index* ix, const float* qrot, int64_t qld, int64_t nq, const int32_
     const int64_t gridB = 1 << 20;                    // capped at the resident blocks
     // a pass-B launch over the pairs of probe ranks [rlo, rhi) (of flagged
     // queries with qmask); dense = the first-bound mode
+    // the two-stage scan (Sec. 4.2) replaces pass B when the index has its 1-bit data and eps0 > 0
+    const bool two = ix->eps0 > 0.0f && ix->msb && ix->fac1;
     auto scan_round = [&](int rlo, int rhi, const int32_t* qmask, int dense, const int32_t* gate) {
-        hipError_t er = build_pairs(rlo, rhi, qmask, qpiB, dense ? 0 : kVch, gate);
+        const int vch = dense ? 0 : (two ? kVch2 : kVch);
+        hipError_t er = build_pairs(rlo, rhi, qmask, qpiB, vch, gate);
         if (er != hipSuccess) return er;
         ScanArgs b{qa, poff, pq, ps, ioff, desc, gridB, kk};
-        BArgs bb{tkey, gcnt, gbe, gbi, work, dense ? 0 : kVch, dense, nprobe};
+        BArgs bb{tkey, gcnt, gbe, gbi, work, vch, dense, nprobe};
         const int rec = prof_begin(dense ? PK_SCAN_A : PK_SCAN_B, st);   // one record per launch
-        er = launchB(ix, b, bb, st);
+        er = (two && !dense) ? launch2(ix, b, bb, st) : launchB(ix, b, bb, st);
         prof_end(rec, st);
         return er;
     };

@@ -31,6 +31,7 @@ SIGNATURES = {
     "erq_index_create": (C.c_int, [_i32, _i32, _i64, _p, C.c_uint64, _i32, _p, C.POINTER(_p)]),
     "erq_index_destroy": (C.c_int, [_p]),
     "erq_index_set_projection": (C.c_int, [_p, _i32, _p]),
+    "erq_index_set_two_stage": (C.c_int, [_p, C.c_float]),
     "erq_index_code_dim": (C.c_int, [_p, C.POINTER(_i32)]),
     "erq_index_get_rotation": (C.c_int, [_p, _p, _p]),
     "erq_index_save": (C.c_int, [_p, C.c_char_p, _p]),
@@ -195,6 +196,12 @@ class Index:
         """Codes of dc < dp dimensions (App. C random projection); only on an
         empty index."""
         _check(load().erq_index_set_projection(self.h, dc, _stream()))
+
+    def set_two_stage(self, eps0: float):
+        """MSB-first two-stage scan (Sec. 4.2) with the Lemma 2.1 bound at eps0;
+        on an empty index it makes the build store the 1-bit data, on a
+        built one it sets eps0 (0 = the one-stage scan)."""
+        _check(load().erq_index_set_two_stage(self.h, float(eps0)))
 
     def code_dim(self) -> int:
         dc = C.c_int32()

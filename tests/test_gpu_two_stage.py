@@ -1,0 +1,174 @@
+"""MSB-first two-stage scan (Sec. 4.2) on the device against the oracle.
+
+The index is built on the device with the 1-bit data; the oracle takes its
+exported codes and factors, and ||r'||_1 of the oracle's own FP64 rotated
+residuals for the bounds.
+
+* eps0 = 8: no bound fails, so the scan equals the oracle's one-stage scan
+  per candidate (tolerance of reading C-15, swaps only at the boundary).
+* eps0 = 1.9: every returned pair carries its one-stage estimate; a member of
+  the oracle's one-stage top-kk may be missing only when its 1-bit lower
+  bound (oracle) exceeds the oracle's kk-th estimate (bound failure).
+* eps0 = 0 on the same index is the one-stage scan, bit for bit equal to an
+  index built without the 1-bit data.
+* The whole search path, save / load with the 1-bit data, and the refusals.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2409_09913_amd import erq, synth
+from parity_util import CandTerms, compare_topk
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+DEV = torch.device("cuda:0")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+@pytest.fixture(scope="module", params=[4, 7], ids=["B4", "B7"])
+def built(request):
+    B = request.param
+    n, d, nl, nq = 60000, 256, 48, 64
+    say("two-stage build B", B)
+    x = synth.gmm(n, d, 64, 0.3, seed=400 + B, dp=d)
+    q = synth.gmm(nq, d, 64, 0.3, seed=400 + B, stream=synth.S_QUERY, dp=d)
+    P = synth.haar_orthogonal(d, seed=401 + B).astype(np.float32)
+    cent = x[:nl].copy()
+    assign = oracle.probe(x, cent, 1)[0][:, 0].astype(np.int32)
+    ix = erq.Index(d, B, nl, dev(P))
+    ix.set_two_stage(8.0)
+    ix.build(dev(x), dev(cent), dev(assign), precision=0, keep_raw=True)
+    iy = erq.Index(d, B, nl, dev(P))                     # the same index without the 1-bit data
+    iy.build(dev(x), dev(cent), dev(assign), precision=0, keep_raw=True)
+    torch.cuda.synchronize()
+    off, ids, codes, fa, fr, _ = [t.cpu().numpy() for t in ix.export()]
+    rr = oracle.rotate(x.astype(np.float64) - cent[assign].astype(np.float64), P)
+    l1 = np.abs(rr).sum(1)[ids]                          # list order, from the oracle's rotation
+    crot = oracle.rotate(cent, P).astype(np.float32)
+    qrot = erq.rotate(dev(q), dev(P), precision=0)
+    yield dict(ix=ix, iy=iy, x=x, q=q, P=P, cent=cent, B=B, off=off, ids=ids, codes=codes, fa=fa, fr=fr, l1=l1,
+               crot=crot, qrot=qrot, qrot_np=qrot.cpu().numpy())
+    ix.close()
+    iy.close()
+
+
+def _scan(b, eps0, nprobe, kk):
+    b["ix"].set_two_stage(eps0)
+    probes = oracle.probe(b["q"], b["cent"], nprobe)[0].astype(np.int32)
+    gi, ge = b["ix"].scan(b["qrot"], dev(probes), kk)
+    return gi.cpu().numpy(), ge.cpu().numpy(), probes
+
+
+@pytest.mark.parametrize("nprobe,kk", [(6, 10), (12, 100)])
+def test_two_stage_large_eps0_equals_one_stage(built, nprobe, kk):
+    b = built
+    gi, ge, probes = _scan(b, 8.0, nprobe, kk)
+    oi, oe = oracle.search(b["off"], b["ids"], b["codes"], b["fa"], b["fr"], b["crot"], b["qrot_np"], probes, b["B"],
+                           kk, est_mode=0)
+    compare_topk(gi, ge, oi, oe, CandTerms(b["off"], b["ids"], b["codes"], b["fa"], b["fr"], b["crot"], b["qrot_np"],
+                                           probes, b["B"]))
+
+
+@pytest.mark.parametrize("nprobe,kk", [(6, 10), (12, 50)])
+def test_two_stage_drops_only_bound_failures(built, nprobe, kk):
+    b = built
+    eps0 = 1.9
+    gi, ge, probes = _scan(b, eps0, nprobe, kk)
+    big = 1500                                           # every candidate's one-stage estimate
+    oi, oe = oracle.search(b["off"], b["ids"], b["codes"], b["fa"], b["fr"], b["crot"], b["qrot_np"], probes, b["B"],
+                           big, est_mode=0)
+    terms = CandTerms(b["off"], b["ids"], b["codes"], b["fa"], b["fr"], b["crot"], b["qrot_np"], probes, b["B"])
+    _, lb = oracle.msb_bounds(b["off"], b["ids"], b["codes"], b["fa"], b["l1"], b["crot"], b["qrot_np"], probes,
+                              b["B"], oi[:, :kk], eps0)
+    lost = 0
+    for i in range(len(gi)):
+        est_of = dict(zip(oi[i].tolist(), oe[i].tolist()))
+        g = gi[i][gi[i] >= 0]
+        assert len(g) == min(kk, int((oi[i] >= 0).sum()))
+        for v, e in zip(g.tolist(), ge[i][: len(g)].tolist()):
+            assert v in est_of, (i, v)
+            assert abs(e - est_of[v]) <= 1e-4 * terms(i, v), (i, v, e, est_of[v])
+        kth = oe[i, kk - 1]
+        gs = set(g.tolist())
+        for j in range(kk):
+            v = int(oi[i, j])
+            if v in gs:
+                continue
+            tol = 1e-4 * (terms(i, v) + terms(i, int(oi[i, kk - 1])))
+            near_tie = abs(oe[i, j] - kth) <= tol
+            assert near_tie or lb[i, j] > kth - tol, (i, v, lb[i, j], kth)
+            lost += 0 if near_tie else 1
+    say("  one-stage top-%d members dropped by failed 1-bit bounds: %d of %d" % (kk, lost, kk * len(gi)))
+
+
+def test_two_stage_eps0_zero_is_one_stage(built):
+    b = built
+    b["ix"].set_two_stage(0.0)
+    probes = dev(oracle.probe(b["q"], b["cent"], 8)[0].astype(np.int32))
+    a = b["ix"].scan(b["qrot"], probes, 20)
+    c = b["iy"].scan(b["qrot"], probes, 20)
+    torch.cuda.synchronize()
+    assert torch.equal(a[0], c[0]) and torch.equal(a[1].view(torch.int32), c[1].view(torch.int32))
+
+
+def test_two_stage_search_path(built, tmp_path):
+    b = built
+    qd = dev(b["q"])
+    b["ix"].set_two_stage(4.0)
+    a = [t.cpu().numpy() for t in b["ix"].search(qd, 10, 10, 30)]
+    c = [t.cpu().numpy() for t in b["iy"].search(qd, 10, 10, 30)]
+    same = np.mean([set(u) == set(v) for u, v in zip(a[0], c[0])])
+    say("  search with re-rank: identical id sets for %.3f of queries" % same)
+    assert same >= 0.95
+    # saved and loaded with its 1-bit data and eps0: the same results
+    path = str(tmp_path / "two.erq")
+    b["ix"].save(path)
+    iz = erq.Index.load_file(path)
+    d = [t.cpu().numpy() for t in iz.search(qd, 10, 10, 30)]
+    np.testing.assert_array_equal(d[0], a[0])
+    np.testing.assert_array_equal(d[1].view(np.uint32), a[1].view(np.uint32))
+    iz.close()
+
+
+def test_two_stage_refusals(built):
+    with pytest.raises(erq.ErqError) as e:
+        built["iy"].set_two_stage(2.0)                   # built without the 1-bit data
+    assert e.value.code == erq.ERQ_EINVAL
+    built["iy"].set_two_stage(0.0)
+    for kw, bits in ((dict(metric="ip"), 4), (dict(), 1)):
+        ix = erq.Index(128, bits, 4, None, seed=1, **kw)
+        with pytest.raises(erq.ErqError) as e:
+            ix.set_two_stage(2.0)
+        assert e.value.code == erq.ERQ_EUNSUPPORTED
+        ix.close()
+    ix = erq.Index(128, 4, 4, None, seed=1)
+    ix.set_projection(64)
+    with pytest.raises(erq.ErqError) as e:
+        ix.set_two_stage(2.0)
+    assert e.value.code == erq.ERQ_EUNSUPPORTED
+    ix.close()
+    ix = erq.Index(128, 4, 2, None, seed=1)
+    ix.set_two_stage(2.0)
+    with pytest.raises(erq.ErqError) as e:
+        ix.set_projection(64)
+    assert e.value.code == erq.ERQ_EUNSUPPORTED
+    off, ids, codes, fa, fr, crot = synth.random_index(100, 2, 128, 4, seed=3)
+    with pytest.raises(erq.ErqError) as e:
+        ix.import_(dev(off), dev(ids), dev(codes), dev(fa), dev(fr), dev(np.zeros((2, 128), np.float32)))
+    assert e.value.code == erq.ERQ_EUNSUPPORTED
+    ix.close()

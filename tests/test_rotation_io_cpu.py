@@ -61,17 +61,23 @@ def test_load_rejects_bad_files(tmp_path):
     assert lib.erq_index_load(os.fsencode(str(p)), None, C.byref(h)) == erq.ERQ_EINVAL
     # a well-formed header of version 1 whose arrays are missing: size mismatch
     # (version, dp, bits, has_raw, metric, code dimension), (nlist, n, tiles), schedule, seed
-    hdr = b"ERQIDX\0\0" + struct.pack("<Iiiiii", 1, 64, 4, 0, 0, 64) + struct.pack("<qqq", 2, 10, 2) + \
-        struct.pack("<iiii", 0, 0, 0, 0) + struct.pack("<Q", 0)
+    # ..., schedule, seed, (two-stage flag, eps0)
+    hdr = b"ERQIDX\0\0" + struct.pack("<Iiiiii", 2, 64, 4, 0, 0, 64) + struct.pack("<qqq", 2, 10, 2) + \
+        struct.pack("<iiii", 0, 0, 0, 0) + struct.pack("<Q", 0) + struct.pack("<if", 0, 0.0)
     p2 = tmp_path / "short.idx"
     p2.write_bytes(hdr)
     assert lib.erq_index_load(os.fsencode(str(p2)), None, C.byref(h)) == erq.ERQ_EINVAL
     assert b"size" in lib.erq_last_error()
+    for tail in (struct.pack("<if", 2, 0.0), struct.pack("<if", 1, -1.0)):   # bad two-stage flag, eps0
+        pb = tmp_path / "ts.idx"
+        pb.write_bytes(hdr[:80] + tail)
+        assert lib.erq_index_load(os.fsencode(str(pb)), None, C.byref(h)) == erq.ERQ_EINVAL
+        assert b"bad header" in lib.erq_last_error()
     for dc in (0, 32, 96, 128):        # code dimension not a multiple of 64 in [64, dp]
         pb = tmp_path / f"dc{dc}.idx"
         pb.write_bytes(hdr[:28] + struct.pack("<i", dc) + hdr[32:])
         assert lib.erq_index_load(os.fsencode(str(pb)), None, C.byref(h)) == erq.ERQ_EINVAL
         assert b"bad header" in lib.erq_last_error()
     p3 = tmp_path / "v9.idx"
-    p3.write_bytes(b"ERQIDX\0\0" + struct.pack("<Iiiiii", 9, 64, 4, 0, 0, 0) + hdr[32:])
+    p3.write_bytes(b"ERQIDX\0\0" + struct.pack("<Iiiiii", 9, 64, 4, 0, 0, 64) + hdr[32:])
     assert lib.erq_index_load(os.fsencode(str(p3)), None, C.byref(h)) == erq.ERQ_EUNSUPPORTED
