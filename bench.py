@@ -79,9 +79,11 @@ def main():
     ap.add_argument("--serve", type=int, default=2000,
                     help="N > 0: also run N Poisson-arrival requests per rate through the batching server "
                          "(p50/p99); 0 skips it")
-    ap.add_argument("--workload", type=str, default="embed768", choices=("embed768", "batching", "serving"),
+    ap.add_argument("--workload", type=str, default="embed768",
+                    choices=("embed768", "batching", "serving", "two_stage"),
                     help="embed768 (the default line); batching: 2M x 960, 8192 uneven lists, B=3/5/7, batches "
-                         "1..4096 with mixed nprobe; serving: 5M x 3072, 16384 lists, B=4, Poisson arrivals")
+                         "1..4096 with mixed nprobe; serving: 5M x 3072, 16384 lists, B=4, Poisson arrivals; "
+                         "two_stage: embed768 with the MSB-first two-stage scan against the one-stage scan")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -97,6 +99,9 @@ def main():
         return
     if args.workload == "serving":
         run_serving(args)
+        return
+    if args.workload == "two_stage":
+        run_two_stage(args)
         return
 
     import torch
@@ -504,6 +509,112 @@ def run_batching(args):
         out["by_bits"].append({"bits": B, "encode_codes_per_s": enc, "autotune": tuned, "rows": rows,
                                "scan_full_batch": roof})
         log("batching B=%d encode %.3g codes/s, scan %s" % (B, enc, roof))
+        ix.close()
+        torch.cuda.empty_cache()
+    log("total %.1fs" % (time.time() - t0))
+    print(json.dumps(out), flush=True)
+
+
+def run_two_stage(args):
+    """MSB-first two-stage scan (Sec. 4.2) against the one-stage scan on the
+    embed768 workload (N = 1,000,000 x 768, 4096 k-means lists), B = 4 and 8:
+    QPS at recall@10 >= the target for eps0 in {0 (one-stage), 1.9, 3} at the
+    full 10,000-query batch, and QPS by batch size (1, 16, 256, 4096) at the
+    one-stage operating point, each batch size captured as a HIP graph."""
+    import torch
+    from paper_2409_09913_amd import erq, serve, synth
+    dev = torch.device("cuda:0")
+    erq.load()
+    t0 = time.time()
+    x_np, q_np = synth.embed768(args.n, args.nq)
+    dp = x_np.shape[1]
+    x = torch.from_numpy(x_np).to(dev)
+    q = torch.from_numpy(q_np).to(dev)
+    P = torch.from_numpy(synth.haar_orthogonal(dp).astype(np.float32)).to(dev)
+    cent, assign = erq.kmeans(x, args.nlist, iters=args.kmeans_iters)
+    truth = brute_topk(x, q, args.k).cpu().numpy()
+    log("two-stage workload ready %.1fs" % (time.time() - t0))
+    eps_list = (0.0, 1.9, 3.0)
+    out = {"metric": "QPS at recall@10>=%.2f, two-stage (MSB-first) vs one-stage scan" % args.target_recall,
+           "unit": "QPS", "config": {"workload": "embed768: N=%d x 768, %d lists, %d queries, k=%d" %
+                                     (args.n, args.nlist, args.nq, args.k)}, "by_bits": []}
+    for B in (4, 8):
+        ix = erq.Index(dp, B, args.nlist, P)
+        ix.set_two_stage(1.0)                      # the build stores the 1-bit data
+        ix.build(x, cent, assign, keep_raw=False)
+        ix.set_raw(x)
+        res = {"bits": B, "best": {}, "by_batch": {}}
+
+        def timed(nq_b, nprobe, rr, reps, qb):
+            ws = torch.empty(ix.search_workspace_size(nq_b, nprobe, args.k, rr), dtype=torch.uint8, device=dev)
+            o = (torch.empty((nq_b, args.k), dtype=torch.int64, device=dev),
+                 torch.empty((nq_b, args.k), dtype=torch.float32, device=dev))
+            ix.search(qb, nprobe, args.k, rr, ws=ws, out=o)
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            for _ in range(reps):
+                ix.search(qb, nprobe, args.k, rr, ws=ws, out=o)
+            torch.cuda.synchronize()
+            return o[0].cpu().numpy(), nq_b * reps / (time.perf_counter() - ts)
+
+        for eps in eps_list:
+            ix.set_two_stage(eps)
+            rows = []
+            for nprobe in (64, 80, 96, 112, 128):
+                for rr in (0, 16, 24, 32):
+                    ids, qps = timed(args.nq, nprobe, rr, 3, q)
+                    rows.append((nprobe, rr, recall_at(ids, truth, args.k), qps))
+            ok = [r for r in rows if r[2] >= args.target_recall] or [max(rows, key=lambda r: r[2])]
+            b = max(ok, key=lambda r: r[3])
+            res["best"][str(eps)] = {"nprobe": b[0], "rerank_k": b[1], "recall@10": b[2], "qps": b[3]}
+            if eps > 0:                                # share of 64-member groups whose full codes were skipped
+                erq.profile_enable(2)
+                erq.profile_read("scan2_groups", reset=True)
+                ix.search(q, b[0], args.k, b[1])
+                torch.cuda.synchronize()
+                sk, ng = erq.profile_read("scan2_groups", reset=True)
+                erq.profile_read("scan", reset=True)
+                erq.profile_enable(False)
+                res["best"][str(eps)]["groups_skipped_frac"] = sk / max(ng, 1)
+            log("two-stage B=%d eps0 %.1f: best nprobe %d rerank %d recall %.4f QPS %.0f, groups skipped %.3f" %
+                ((B, eps) + b + (res["best"][str(eps)].get("groups_skipped_frac", 0.0),)))
+        op = res["best"]["0.0"]
+        for bs in (1, 16, 256, 4096):
+            row = {}
+            for eps in eps_list:
+                ix.set_two_stage(eps)
+                gph = serve.SearchGraph(ix, bs, op["nprobe"], args.k, op["rerank_k"])
+                nb = max(1, min(256, 4096 // bs))
+                got = torch.empty((nb * bs, args.k), dtype=torch.int64, device=dev)
+                with torch.cuda.stream(gph.stream):       # warm-up replay
+                    gph.q.copy_(q[:bs])
+                    gph.graph.replay()
+                torch.cuda.synchronize()
+                ts = time.perf_counter()
+                with torch.cuda.stream(gph.stream):       # consecutive batches, results kept on the device
+                    for it in range(nb):
+                        gph.q.copy_(q[it * bs:(it + 1) * bs])
+                        gph.graph.replay()
+                        got[it * bs:(it + 1) * bs].copy_(gph.ids)
+                torch.cuda.synchronize()
+                dt = (time.perf_counter() - ts) / nb
+                rec = recall_at(got.cpu().numpy(), truth[:nb * bs], args.k)
+                row[str(eps)] = {"qps": bs / dt, "ms_per_batch": dt * 1e3, "recall@10": rec}
+                if eps > 0:
+                    erq.profile_enable(2)
+                    erq.profile_read("scan2_groups", reset=True)
+                    ix.search(q[:bs].contiguous(), op["nprobe"], args.k, op["rerank_k"])
+                    torch.cuda.synchronize()
+                    sk, ng = erq.profile_read("scan2_groups", reset=True)
+                    erq.profile_read("scan", reset=True)
+                    erq.profile_enable(False)
+                    row[str(eps)]["groups_skipped_frac"] = sk / max(ng, 1)
+                del gph
+            res["by_batch"][str(bs)] = row
+            log("two-stage B=%d batch %d: %s" % (B, bs, {e: (round(v["qps"]), round(v["recall@10"], 4),
+                                                            round(v.get("groups_skipped_frac", 0), 3))
+                                                        for e, v in row.items()}))
+        out["by_bits"].append(res)
         ix.close()
         torch.cuda.empty_cache()
     log("total %.1fs" % (time.time() - t0))

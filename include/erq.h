@@ -361,8 +361,10 @@ int erq_index_tune(erq_index idx, const float* q, int64_t nq, int32_t nprobe, in
 /* core scan, all passes), "scan_a" (its first bound), "scan_b" (each launch */
 /* of the bounded scan), "scan_c" (final selection and exact fallback),     */
 /* "quantize", "rotate", "probe", "rerank".  "scan_redo_pairs"              */
-/* returns in total_ms the number of pairs re-scanned by the exact fallback;*/
-/* it is counted only with on == 2, which synchronises after each scan.     */
+/* returns in total_ms the number of pairs re-scanned by the exact fallback,*/
+/* "scan2_groups" the groups of 64 members whose full codes the two-stage   */
+/* scan did not read (total_ms) and all its groups (launches); both are     */
+/* counted only with on == 2, which synchronises after each scan.           */
 /* erq_profile_read waits for the recorded events and returns the summed     */
 /* duration (ms) and launch count of one kernel (host outputs); reset != 0   */
 /* drops the records of every kernel.                                        */

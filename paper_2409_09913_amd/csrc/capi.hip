@@ -44,6 +44,7 @@ bool g_prof_stats = false;     // also count pass-C pairs (synchronises after ea
 const char* const kProfNames[PK_COUNT] = {"scan", "quantize", "rotate", "probe", "rerank",
                                           "scan_a", "scan_b", "scan_c"};
 int64_t g_redo_total = 0, g_redo_calls = 0;
+int64_t g_groups_total = 0, g_groups_skipped = 0;   // two-stage scan: groups, groups without full codes
 }  // namespace
 
 int prof_begin(int kernel, hipStream_t st)
@@ -57,18 +58,26 @@ int prof_begin(int kernel, hipStream_t st)
     return (int)g_prof.size() - 1;
 }
 
+bool prof_stats_on()
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    return g_prof_on && g_prof_stats;
+}
+
 void prof_note_redo(const int32_t* dev_count, hipStream_t st)
 {
     {
         std::lock_guard<std::mutex> lk(g_prof_mu);
         if (!g_prof_on || !g_prof_stats) return;
     }
-    int32_t h = 0;
-    if (hipMemcpyAsync(&h, dev_count, sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess) return;
+    int32_t h[3] = {0, 0, 0};
+    if (hipMemcpyAsync(h, dev_count, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess) return;
     if (hipStreamSynchronize(st) != hipSuccess) return;
     std::lock_guard<std::mutex> lk(g_prof_mu);
-    g_redo_total += h;
+    g_redo_total += h[0];
     g_redo_calls += 1;
+    g_groups_total += h[1];
+    g_groups_skipped += h[2];
 }
 
 void prof_end(int rec, hipStream_t st)
@@ -1290,6 +1299,13 @@ int erq_profile_read(const char* kernel, double* total_ms, int64_t* launches, in
         if (total_ms) *total_ms = (double)g_redo_total;
         if (launches) *launches = g_redo_calls;
         if (reset) { g_redo_total = 0; g_redo_calls = 0; }
+        return ERQ_OK;
+    }
+    if (std::strcmp(kernel, "scan2_groups") == 0) {           // two-stage scan: groups skipped / scanned
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        if (total_ms) *total_ms = (double)g_groups_skipped;
+        if (launches) *launches = g_groups_total;
+        if (reset) { g_groups_total = 0; g_groups_skipped = 0; }
         return ERQ_OK;
     }
     int kid = -1;

@@ -105,6 +105,8 @@ enum ProfKernel { PK_SCAN = 0, PK_QUANTIZE, PK_ROTATE, PK_PROBE, PK_RERANK, PK_S
                   PK_SCAN_C, PK_COUNT };
 // diagnostics of the last scan while profiling is on (pairs scanned by the exact fallback)
 void prof_note_redo(const int32_t* dev_count, hipStream_t st);
+// profiling with counters (erq_profile_enable(2)) is on
+bool prof_stats_on();
 // returns a started record (or -1 when profiling is off); prof_end closes it
 int prof_begin(int kernel, hipStream_t st);
 void prof_end(int rec, hipStream_t st);

@@ -530,8 +530,9 @@ __global__ __launch_bounds__(kThreads, 2) void scan2_kernel(
     const int64_t* __restrict__ ids, int dp, QArgs qa, const int32_t* __restrict__ pair_q,
     const int32_t* __restrict__ pair_slot, const int32_t* __restrict__ item_off, const int4* __restrict__ desc,
     int nlist, unsigned* __restrict__ tau_key, int32_t* __restrict__ gcnt, float* __restrict__ gbuf_e,
-    int32_t* __restrict__ gbuf_i, int32_t* __restrict__ work, float eps0)
+    int32_t* __restrict__ gbuf_i, int32_t* __restrict__ work, float eps0, int32_t* __restrict__ gstat)
 {
+    // gstat (or null): [0] groups scanned, [1] groups whose full codes were not read
     constexpr int QPI = kQT * NQT;
     constexpr int KC = 4;                          // K-blocks whose words are loaded together
     extern __shared__ __align__(16) char smem[];
@@ -673,7 +674,12 @@ __global__ __launch_bounds__(kThreads, 2) void scan2_kernel(
         bool anyq = false;
 #pragma unroll
         for (int qt = 0; qt < NQT; ++qt) anyq = anyq || pm[qt] != 0;
-        if (!__any(anyq)) continue;                     // the group's full codes are not read
+        const bool skip = !__any(anyq);                 // wave-uniform
+        if (gstat && lane == 0) {                       // counted only while profiling
+            atomicAdd(&gstat[0], 1);
+            if (skip) atomicAdd(&gstat[1], 1);
+        }
+        if (skip) continue;                             // the group's full codes are not read
         // stage 2: the full codes
 #pragma unroll
         for (int a = 0; a < 2; ++a)
@@ -1442,7 +1448,7 @@ __global__ void fill_dense_kernel(float* __restrict__ gbuf_e, int64_t nq, int32_
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     constexpr int W = kDenseR * kDenseV;
-    if (i == 0) *redo = 0;
+    if (i < 3) redo[i] = 0;                        // counters: fallback pairs, two-stage groups, skipped groups
     if (i >= nq * W) return;
     const int64_t q = i / W;
     gbuf_e[q * kCapQ + (i - q * W)] = __builtin_huge_valf();
@@ -1733,7 +1739,7 @@ struct ScanArgs {
 };
 
 struct BArgs { unsigned* tau_key; int32_t* gcnt; float* gbuf_e; int32_t* gbuf_i; int32_t* work;
-               int vch, dense, nprobe; };
+               int vch, dense, nprobe; int32_t* gstat; };
 
 template <int BITS, int NQT, int PD, bool DENSE>
 hipError_t launchB_d(const Index* ix, const ScanArgs& a, const BArgs& b, hipStream_t st)
@@ -1819,7 +1825,7 @@ hipError_t launch2_n(const Index* ix, const ScanArgs& a, const BArgs& b, hipStre
     hipLaunchKernelGGL((scan2_kernel<BITS, NQT>), dim3((unsigned)grid), dim3(kThreads), sm, st,
                        ix->codes, ix->msb, ix->tile_off, ix->list_off, ix->sfac, ix->fac1, ix->ids, ix->dc,
                        a.qa, a.pair_q, a.pair_slot, a.item_off, a.desc, (int)ix->nlist,
-                       b.tau_key, b.gcnt, b.gbuf_e, b.gbuf_i, b.work, ix->eps0);
+                       b.tau_key, b.gcnt, b.gbuf_e, b.gbuf_i, b.work, ix->eps0, b.gstat);
     return hipGetLastError();
 }
 
@@ -1948,7 +1954,7 @@ size_t scan_workspace_bytes(int64_t nq, int nprobe, int64_t nlist, int kk, int d
     b += 3 * align256(sizeof(int32_t));                    // pass-B work counter, two overflow flags
     b += align256(sizeof(float) * nq * kCapQ);             // candidate buffers
     b += align256(sizeof(int32_t) * nq * kCapQ);
-    b += align256(sizeof(int32_t));                        // fallback pair count
+    b += align256(sizeof(int32_t) * 3);                    // fallback pairs, two-stage group counts
     b += align256((size_t)nq * dp);                        // int8 queries
     b += 2 * align256(sizeof(float) * nq);                 // delta/2, sum of int8 values
     b += align256(sizeof(float) * P);                      // ||s||^2 per pair
@@ -1985,7 +1991,7 @@ int run_scan(Index* ix, const float* qrot, int64_t qld, int64_t nq, const int32_
     int32_t* anyf2 = (int32_t*)take(sizeof(int32_t));      // ... at the final selection
     float* gbe = (float*)take(sizeof(float) * nq * kCapQ);
     int32_t* gbi = (int32_t*)take(sizeof(int32_t) * nq * kCapQ);
-    int32_t* redo = (int32_t*)take(sizeof(int32_t));       // pairs scanned by the exact fallback
+    int32_t* redo = (int32_t*)take(sizeof(int32_t) * 3);   // fallback pairs; two-stage groups, skipped
     int8_t* qint = (int8_t*)take((size_t)nq * dp);
     float* qhd = (float*)take(sizeof(float) * nq);
     int32_t* qss = (int32_t*)take(sizeof(int32_t) * nq);
@@ -2069,7 +2075,7 @@ int run_scan(Index* ix, const float* qrot, int64_t qld, int64_t nq, const int32_
         hipError_t er = build_pairs(rlo, rhi, qmask, qpiB, vch, gate);
         if (er != hipSuccess) return er;
         ScanArgs b{qa, poff, pq, ps, ioff, desc, gridB, kk};
-        BArgs bb{tkey, gcnt, gbe, gbi, work, vch, dense, nprobe};
+        BArgs bb{tkey, gcnt, gbe, gbi, work, vch, dense, nprobe, prof_stats_on() ? redo + 1 : nullptr};
         const int rec = prof_begin(dense ? PK_SCAN_A : PK_SCAN_B, st);   // one record per launch
         er = (two && !dense) ? launch2(ix, b, bb, st) : launchB(ix, b, bb, st);
         prof_end(rec, st);
