@@ -265,9 +265,9 @@ class Server:
 def poisson_run(server: Server, queries: torch.Tensor, rate: float, n_requests: int, per_request: int,
                 k, nprobes, rerank_k=0, seed: int = 0):
     """Requests of `per_request` queries arrive as a Poisson process of `rate`
-    requests per second, each with an nprobe drawn from `nprobes` and a k
-    drawn from `k` (an int or a tuple); `rerank_k` is an int or a dict k ->
-    re-rank depth.  Returns the finished requests, (p50, p99) latency in ms
+    requests per second, each with a k drawn from `k` (an int or a tuple) and
+    an nprobe drawn from `nprobes` (a tuple, or a dict k -> nprobe); `rerank_k`
+    is an int or a dict k -> re-rank depth.  Returns the finished requests, (p50, p99) latency in ms
     and the sustained QPS."""
     g = np.random.default_rng(seed)
     gaps = g.exponential(1.0 / rate, n_requests)
@@ -279,8 +279,8 @@ def poisson_run(server: Server, queries: torch.Tensor, rate: float, n_requests: 
         lo = (i * per_request) % max(nq - per_request, 1)
         kr = int(g.choice(ks))
         rr = rerank_k.get(kr, 0) if isinstance(rerank_k, dict) else rerank_k
-        reqs.append(Request(i, queries[lo:lo + per_request], kr, int(g.choice(nprobes)), rr,
-                            arrival=float(arrivals[i])))
+        npr = int(nprobes[kr]) if isinstance(nprobes, dict) else int(g.choice(nprobes))
+        reqs.append(Request(i, queries[lo:lo + per_request], kr, npr, rr, arrival=float(arrivals[i])))
     torch.cuda.synchronize()
     server.t0 = time.perf_counter()
     i = 0
