@@ -52,6 +52,7 @@ def _load():
         lib.orc_encode.argtypes = [p, i64, i32, p, p, p, i32, p, p, p, p, p]
         lib.orc_encode.restype = i32
         lib.orc_query_quant.argtypes = [p, i32, p, p, p]
+        lib.orc_query_quant2.argtypes = [p, i32, p, p, p, p, p]
         lib.orc_est_paper.argtypes = [p, i32, i32, p, C.c_double, C.c_double]
         lib.orc_est_paper.restype = C.c_double
         lib.orc_probe.argtypes = [p, i64, p, i64, i32, i32, p, p]
@@ -174,6 +175,17 @@ def query_quant(s):
     return sq, d.value, t.value
 
 
+def query_quant2(s):
+    """The two int8 planes of one FP32 rotated query (erq_oracle.c,
+    orc_query_quant2); returns (q_hi, q_lo, delta, sum q_hi, sum q_lo)."""
+    s = _c(s, np.float32)
+    sh = np.empty(s.shape[0], np.int8)
+    sl = np.empty(s.shape[0], np.int8)
+    d, th, tl = C.c_float(), C.c_int32(), C.c_int32()
+    _load().orc_query_quant2(_p(s), s.shape[0], _p(sh), _p(sl), C.byref(d), C.byref(th), C.byref(tl))
+    return sh, sl, d.value, th.value, tl.value
+
+
 def est_paper(code, B, s, norm_r2, cos_oo):
     """Paper-form estimate of the squared distance with a float query (FP64)."""
     code = _c(code, np.uint8)
@@ -214,7 +226,8 @@ def encode_proj(x, cent, assign, P, B, dc):
 def search(list_off, ids, codes, f_add, f_rescale, crot, qrot, probes, B, kk,
            cos_oo=None, est_mode=0):
     """IVF scan + top-kk by (est, id); est_mode 0 = int8 query (factor form),
-    1 = float query (paper form, needs cos_oo), 2 = float query (factor form).
+    1 = float query (paper form, needs cos_oo), 2 = float query (factor form),
+    3 = int8 query in two planes (query_quant2).
     With codes narrower than qrot / crot (the projection of App. C) the codes
     use the first coordinates and ||s||^2 all of them."""
     list_off = _c(list_off, np.int64)

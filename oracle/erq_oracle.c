@@ -382,6 +382,48 @@ static double orc_est_int8(int64_t ip_u, int32_t qsum, int B, double delta, doub
     return f_add + ns2 + f_rescale * (0.5 * two_ip - ybc);
 }
 
+/* Two int8 planes of the query (this implementation's addition for large B,
+   where the one-plane rounding error Delta/2 per coordinate is as large as
+   the estimator's own error): with t_i = q'_i * inv (FP32, inv = 127/amax
+   as in orc_query_quant), q_hi = clamp(rint(t_i), +-127) is the one-plane
+   code, and the remainder t_i - q_hi (exact in FP32, in [-1/2, 1/2]) is
+   quantised again with 254 levels per unit, q_lo = rint((t_i - q_hi) * 254)
+   (in [-127, 127]), so that q' ~= delta * (q_hi + q_lo / 254), decided in
+   FP32 exactly as the kernel does. */
+void orc_query_quant2(const float* s, int dp, int8_t* sh, int8_t* sl, float* delta, int32_t* sum_hi,
+                      int32_t* sum_lo)
+{
+    orc_query_quant(s, dp, sh, delta, sum_hi);
+    int32_t sum = 0;
+    float amax = 0.0f;
+    for (int i = 0; i < dp; ++i) { float v = fabsf(s[i]); if (v > amax) amax = v; }
+    if (amax > 0.0f) {
+        const float inv = 127.0f / amax;
+        for (int i = 0; i < dp; ++i) {
+            const float t = s[i] * inv;
+            const float r = t - (float)sh[i];
+            int v = (int)rintf(r * 254.0f);
+            if (v > 127) v = 127;
+            if (v < -127) v = -127;
+            sl[i] = (int8_t)v;
+            sum += v;
+        }
+    } else {
+        for (int i = 0; i < dp; ++i) sl[i] = 0;
+    }
+    *sum_lo = sum;
+}
+
+/* The int8 estimator with the two query planes: 2<y, q'> ~= delta * ((2
+   ip_hi - (2^B-1) sum q_hi) + (2 ip_lo - (2^B-1) sum q_lo) / 254). */
+static double orc_est_int8x2(int64_t ip_hi, int64_t ip_lo, int32_t qs_hi, int32_t qs_lo, int B, double delta,
+                             double ybc, double ns2, double f_add, double f_rescale)
+{
+    const int64_t m = (1 << B) - 1;
+    const double two_ip = delta * ((double)(2 * ip_hi - m * qs_hi) + (double)(2 * ip_lo - m * qs_lo) / 254.0);
+    return f_add + ns2 + f_rescale * (0.5 * two_ip - ybc);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Ordering helpers: ascending (value, id).                                  */
 /* ------------------------------------------------------------------------ */
@@ -447,7 +489,8 @@ int orc_search_ld(const int64_t* list_off, const int64_t* ids, const uint8_t* co
    Queries: qrot[nq x dp] rotated (FP32), probes[nq x nprobe].  Every query
    is quantised to int8 once; for every probed list s' = q' - c' and ||s||^2
    in FP64 (exact differences of the FP32 inputs); every member gets an
-   estimate; the kk smallest (est, id) are returned.  est_mode 2 = float
+   estimate; the kk smallest (est, id) are returned.  est_mode 3 = the
+   int8 query in two planes (orc_query_quant2); est_mode 2 = float
    query with the stored factors (f_add + ||s||^2 + f_rescale <y, s'>, FP64);
    est_mode 0 = int8 query
    (factor form), 1 = float query (paper form, uses cos_oo). */
@@ -477,14 +520,16 @@ int orc_search_ld(const int64_t* list_off, const int64_t* ids, const uint8_t* co
     {
         double* sd = (double*)malloc(sizeof(double) * dp);
         int8_t* qq = (int8_t*)malloc((size_t)dp);
+        int8_t* ql = (int8_t*)malloc((size_t)dp);
         const double half = ((double)((1 << B) - 1)) / 2.0;
         int64_t cap = 1024;
         orc_cand* cand = (orc_cand*)malloc(sizeof(orc_cand) * (size_t)cap);
         #pragma omp for schedule(dynamic, 1)
         for (int64_t iq = 0; iq < nq; ++iq) {
             int64_t nc = 0;
-            float delta; int32_t qsum;
-            orc_query_quant(qrot + iq * (int64_t)ld, dp, qq, &delta, &qsum);
+            float delta; int32_t qsum, qsum_lo = 0;
+            if (est_mode == 3) orc_query_quant2(qrot + iq * (int64_t)ld, dp, qq, ql, &delta, &qsum, &qsum_lo);
+            else orc_query_quant(qrot + iq * (int64_t)ld, dp, qq, &delta, &qsum);
             for (int p = 0; p < nprobe; ++p) {
                 int32_t l = probes[iq * nprobe + p];
                 if (l < 0) continue;                 /* padding: the query probes fewer lists */
@@ -516,6 +561,16 @@ int orc_search_ld(const int64_t* list_off, const int64_t* ids, const uint8_t* co
                         }
                         est = orc_est_int8(ip, qsum, B, (double)delta, ybc, ns2,
                                            (double)f_add[v], (double)f_rescale[v]);
+                    } else if (est_mode == 3) {
+                        int64_t ih = 0, il = 0;
+                        double ybc = 0.0;
+                        for (int i = 0; i < dp; ++i) {
+                            ih += (int64_t)cd[i] * (int64_t)qq[i];
+                            il += (int64_t)cd[i] * (int64_t)ql[i];
+                            ybc += ((double)cd[i] - half) * (double)cv[i];
+                        }
+                        est = orc_est_int8x2(ih, il, qsum, qsum_lo, B, (double)delta, ybc, ns2,
+                                             (double)f_add[v], (double)f_rescale[v]);
                     } else {
                         est = orc_est_paper(cd, dp, B, sd, (double)f_add[v], cos_oo[v]);
                     }
@@ -524,7 +579,7 @@ int orc_search_ld(const int64_t* list_off, const int64_t* ids, const uint8_t* co
             }
             orc_take_k(cand, nc, kk, out_ids + iq * kk, out_d + iq * kk);
         }
-        free(sd); free(qq); free(cand);
+        free(sd); free(qq); free(ql); free(cand);
     }
     return bad ? -1 : 0;
 }

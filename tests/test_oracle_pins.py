@@ -425,3 +425,68 @@ def test_edge_rows_quantize():
                     c2 = codes[r].astype(int).copy(); c2[i] += dlt
                     if 0 <= c2[i] < (1 << B):
                         assert oracle.objective(rows[r], B, c2.astype(np.uint8)) <= base + 1e-12 * abs(base)
+
+
+def test_two_plane_query_within_its_bound():
+    """Two int8 planes, q' ~= delta (q_hi + q_lo / 254) (the implementation's
+    addition for large B): the planes reconstruct q' within delta/508 per
+    coordinate, and every estimate of the two-plane scan differs from the
+    float-query estimate by at most |f_rescale| * delta/508 * ||y_bar||_1 per
+    candidate, 254 times tighter than the one-plane bound, which the one-plane
+    scan does approach."""
+    B, dp, n, nl, nq = 8, 128, 3000, 12, 8
+    off, ids, codes, fa, fr, crot = synth.random_index(n, nl, dp, B, seed=13)
+    qrot = synth.random_rotated(nq, dp, seed=13)
+    probes = synth.random_probes(nq, nl, 4, seed=13)
+    Y = codes.astype(np.float64) - ((1 << B) - 1) / 2.0
+    pos = {int(v): i for i, v in enumerate(ids)}
+    kk = n
+    _, e2 = oracle.search(off, ids, codes, fa, fr, crot, qrot, probes, B, kk, est_mode=2)
+    i3, e3 = oracle.search(off, ids, codes, fa, fr, crot, qrot, probes, B, kk, est_mode=3)
+    i0, e0 = oracle.search(off, ids, codes, fa, fr, crot, qrot, probes, B, kk, est_mode=0)
+    worst3 = worst0 = 0.0
+    dev3, dev0 = [], []
+    for iq in range(nq):
+        hi, lo, d, _, _ = oracle.query_quant2(qrot[iq].astype(np.float32))
+        rec = d * (hi.astype(np.float64) + lo.astype(np.float64) / 254.0)
+        assert np.abs(rec - qrot[iq].astype(np.float64)).max() <= d * (1 / 508 + 1e-5)
+        ref = dict(zip(oracle.search(off, ids, codes, fa, fr, crot, qrot[iq:iq + 1], probes[iq:iq + 1], B, kk,
+                                     est_mode=2)[0][0].tolist(), e2[iq].tolist()))
+        for mode_ids, mode_e, unit in ((i3, e3, 508.0), (i0, e0, 2.0)):
+            for v, e in zip(mode_ids[iq].tolist(), mode_e[iq].tolist()):
+                if v < 0:
+                    continue
+                p = pos[v]
+                bound = abs(float(fr[p])) * d / unit * np.abs(Y[p]).sum() * (1 + 1e-4) + 1e-9
+                dev_ = abs(e - ref[v])
+                assert dev_ <= bound, (iq, v, dev_, bound, unit)
+                if unit == 508.0:
+                    worst3 = max(worst3, dev_ / bound)
+                    dev3.append(e - ref[v])
+                else:
+                    worst0 = max(worst0, dev_ / bound)
+                    dev0.append(e - ref[v])
+    assert worst0 > 0.05 and worst3 < 1.0
+    # the rounding errors of the planes are uniform over +-1/2 of their steps, so the rms errors
+    # of the two estimates stand in the ratio of the steps, 1/254
+    ratio = np.sqrt(np.mean(np.square(dev3)) / np.mean(np.square(dev0)))
+    assert 1 / 400 < ratio < 1 / 180, ratio
+
+
+def test_two_plane_equals_one_plane_on_grid_queries():
+    """On the int8 grid (q' = k * 2^-6, max |k| = 127) the low plane is zero and
+    the two-plane estimates equal the one-plane ones bit for bit."""
+    g = np.random.default_rng(6)
+    B, dp, n, nl, nq = 8, 64, 600, 6, 5
+    off, ids, codes, fa, fr, crot = synth.random_index(n, nl, dp, B, seed=48)
+    k = g.integers(-127, 128, (nq, dp))
+    k[:, 0] = 127
+    qrot = (k * 2.0 ** -6).astype(np.float32)
+    probes = np.array([g.choice(nl, 3, replace=False) for _ in range(nq)], np.int32)
+    for iq in range(nq):
+        _, lo, _, _, slo = oracle.query_quant2(qrot[iq])
+        assert not lo.any() and slo == 0
+    a = oracle.search(off, ids, codes, fa, fr, crot, qrot, probes, B, 600, est_mode=0)
+    b = oracle.search(off, ids, codes, fa, fr, crot, qrot, probes, B, 600, est_mode=3)
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
