@@ -165,6 +165,18 @@ int erq_index_set_projection(erq_index idx, int32_t dc, void* stream);
    index. */
 int erq_index_set_two_stage(erq_index idx, float eps0);
 
+/* Query planes of the scan.  1 (default): q' is quantised to int8 once,
+   q' ~= delta * q_int (reading C-13), whose rounding error (delta/2 per
+   coordinate) is as large as the estimator's own error at large B.  2:
+   a second int8 plane of the rounding remainder,
+     q_lo = rint((q' / delta - q_int) * 254),  q' ~= delta * (q_int + q_lo / 254),
+   products <y_u, q_int> and <y_u, q_lo> both exact in int32 on the matrix
+   cores, the error 254 times smaller, at twice the matrix-core work per
+   query (32 queries per work item instead of 64).  planes = 2 needs
+   bits >= 5 and no two-stage scan (ERQ_EUNSUPPORTED).  A query-time setting:
+   the codes do not change; saved with the index. */
+int erq_index_set_query_planes(erq_index idx, int32_t planes);
+
 /* The code dimension dc (dp without a projection). */
 int erq_index_code_dim(erq_index idx, int32_t* dc);
 
@@ -173,7 +185,7 @@ int erq_index_get_rotation(erq_index idx, float* P_out, void* stream);
 
 /* Writes the whole index to a file (host path): a versioned header (magic
    "ERQIDX", version 2, dp, bits, raw kept, metric, code dimension, nlist,
-   n, tiles, scan schedule, seed, two-stage flag and eps0),
+   n, tiles, scan schedule, seed, two-stage flag and eps0, query planes),
    then P, raw and rotated centroids, list offsets, ids, factors, scan
    factors, packed codes, when kept the raw vectors, and with the two-stage
    scan its bit planes and 1-bit factors, in native byte order.

@@ -391,6 +391,8 @@ struct FileHeader {
     uint64_t seed;
     int32_t two_stage;                               // 1: the two-stage scan's data follow the codes
     float eps0;
+    int32_t qplanes;                                 // int8 query planes of the scan (1 or 2)
+    int32_t reserved;                                // 0
 };
 
 // bytes of every array of an index file after the header, in file order
@@ -562,6 +564,7 @@ int erq_index_save(erq_index ix, const char* path, void* stream)
     h.seed = ix->seed;
     h.two_stage = ix->msb ? 1 : 0;
     h.eps0 = ix->eps0;
+    h.qplanes = ix->qplanes;
     FILE* f = std::fopen(path, "wb");
     if (!f) return fail(ERQ_EINVAL, std::string("erq_index_save: cannot open ") + path);
     struct Closer { FILE* f; ~Closer() { if (f) std::fclose(f); } } closer{f};
@@ -591,7 +594,8 @@ int erq_index_load(const char* path, void* stream, erq_index* out)
     if (h.dp < 64 || h.dp > kMaxDp || h.dp % 64 || h.bits < 1 || h.bits > 8 || h.nlist < 1 ||
         h.nlist > (1 << 24) || h.n < 0 || h.n > (1LL << 31) - 1 || h.ntiles < 0 || (h.has_raw != 0 && h.has_raw != 1) ||
         h.metric < ERQ_METRIC_L2 || h.metric > ERQ_METRIC_COSINE || h.dc < 64 || h.dc > h.dp || h.dc % 64 ||
-        (h.two_stage != 0 && h.two_stage != 1) || !(h.eps0 >= 0.0f) || !(h.eps0 < 1e30f))
+        (h.two_stage != 0 && h.two_stage != 1) || !(h.eps0 >= 0.0f) || !(h.eps0 < 1e30f) ||
+        (h.qplanes != 1 && h.qplanes != 2) || (h.qplanes == 2 && (h.bits < 5 || h.two_stage)))
         return fail(ERQ_EINVAL, "erq_index_load: bad header");
     const std::vector<size_t> sz = file_arrays(h);
     size_t total = sizeof(h);
@@ -615,7 +619,7 @@ int erq_index_load(const char* path, void* stream, erq_index* out)
     if (!ix) return fail(ERQ_ENOMEM, "erq_index_load: out of host memory");
     struct Owner { erq_index_s* p; ~Owner() { if (p) erq_index_destroy(p); } } owner{ix};
     ix->dp = dp; ix->bits = h.bits; ix->nlist = C; ix->seed = h.seed; ix->metric = h.metric; ix->dc = h.dc;
-    ix->two_stage = h.two_stage; ix->eps0 = h.eps0;
+    ix->two_stage = h.two_stage; ix->eps0 = h.eps0; ix->qplanes = h.qplanes;
     ix->tune_nqt = h.tune[0]; ix->tune_pd = h.tune[1]; ix->tune_round1 = h.tune[2]; ix->tune_round2 = h.tune[3];
     hipGetDevice(&ix->device);
     if (int rc = set_list_meta(ix, off, st)) return rc;
@@ -670,8 +674,9 @@ int erq_index_set_two_stage(erq_index ix, float eps0)
 {
     if (!ix) return fail(ERQ_EINVAL, "erq_index_set_two_stage: null index");
     if (!(eps0 >= 0.0f) || !(eps0 < 1e30f)) return fail(ERQ_EINVAL, "erq_index_set_two_stage: eps0 must be >= 0");
-    if (eps0 > 0.0f && (ix->metric != ERQ_METRIC_L2 || ix->bits < 2 || ix->dc != ix->dp))
-        return fail(ERQ_EUNSUPPORTED, "erq_index_set_two_stage: needs the L2 metric, bits >= 2, no projection");
+    if (eps0 > 0.0f && (ix->metric != ERQ_METRIC_L2 || ix->bits < 2 || ix->dc != ix->dp || ix->qplanes != 1))
+        return fail(ERQ_EUNSUPPORTED,
+                    "erq_index_set_two_stage: needs the L2 metric, bits >= 2, no projection, one query plane");
     if (!ix->list_off) {                             // empty: the build computes the 1-bit data
         ix->two_stage = eps0 > 0.0f ? 1 : 0;
         ix->eps0 = eps0;
@@ -680,6 +685,16 @@ int erq_index_set_two_stage(erq_index ix, float eps0)
     if (eps0 > 0.0f && !ix->msb)
         return fail(ERQ_EINVAL, "erq_index_set_two_stage: the index holds no 1-bit data (request it before the build)");
     ix->eps0 = eps0;
+    return ERQ_OK;
+}
+
+int erq_index_set_query_planes(erq_index ix, int32_t planes)
+{
+    if (!ix) return fail(ERQ_EINVAL, "erq_index_set_query_planes: null index");
+    if (planes != 1 && planes != 2) return fail(ERQ_EINVAL, "erq_index_set_query_planes: planes must be 1 or 2");
+    if (planes == 2 && (ix->bits < 5 || ix->two_stage))
+        return fail(ERQ_EUNSUPPORTED, "erq_index_set_query_planes: two planes need bits >= 5 and no two-stage scan");
+    ix->qplanes = planes;
     return ERQ_OK;
 }
 

@@ -153,6 +153,19 @@ __device__ inline void epi_consts(float hd, int ss, float& h2, float& hc) {
 __device__ inline float epi_e(float2 f, int acc, float h2, float hc) {
     return __fmaf_rn(f.y, __fmaf_rn(h2, (float)acc, hc), f.x);
 }
+// Two query planes: IP = <y, q_hi> + <y, q_lo> / 254, so
+// e = f_rescale * (h2 * IP_hi + (h2l * IP_lo + hc)) + g_add with h2l = h2 / 254
+// and hc = delta/2 * corr * (sum q_hi + sum q_lo / 254).
+template <int BITS>
+__device__ inline void epi_consts2(float hd, int ss, int ssl, float& h2, float& h2l, float& hc) {
+    constexpr int corr = 2 * (BITS == 8 ? 128 : 0) - ((1 << BITS) - 1);
+    h2 = 2.0f * hd;
+    h2l = __fdiv_rn(h2, 254.0f);
+    hc = __fmaf_rn(__fdiv_rn(hd, 254.0f), (float)(corr * ssl), hd * (float)(corr * ss));
+}
+__device__ inline float epi_e2(float2 f, int ah, int al, float h2, float h2l, float hc) {
+    return __fmaf_rn(f.y, __fmaf_rn(h2, (float)ah, __fmaf_rn(h2l, (float)al, hc)), f.x);
+}
 
 // Item of a pair table grouped by list: largest rank r with item_off[r] <= item.
 __device__ inline void decode_item(int item, const int32_t* item_off, const int32_t* list_order, int nlist,
@@ -167,12 +180,16 @@ __device__ inline void decode_item(int item, const int32_t* item_off, const int3
 // Queries of a scan, prepared once per batch: q' quantised to int8 (qint,
 // nq x dp), delta/2 (qhd) and the sum of the int8 values (qss) per query,
 // and ||s||^2 = ||q' - c'||^2 per (query, probe) pair (sdist).
+// With two query planes (large B) the low plane q_lo and its sums follow:
+// q' ~= delta * (q_int + q_lo / 254).
 struct QArgs {
     const int8_t* qint;
     const float* qhd;
     const int32_t* qss;
     const float* sdist;
     float s2_floor;          // 0 for L2 (a squared distance rounded below 0 is clamped), -inf otherwise
+    const int8_t* qlo;       // nq x dp, or null (one plane)
+    const int32_t* qss_lo;
 };
 
 // Prologue shared by the scan kernels, in two steps with a barrier between
@@ -201,9 +218,11 @@ __device__ inline void load_query_scalars(float* s_s2, float* s_hd, int* s_ss, i
 
 constexpr int kRowLoads = 12;
 
-template <int NQT>
+// With LO (NQT = 2), rows [kQT, 2 kQT) hold the low planes of the queries of
+// rows [0, kQT).
+template <int NQT, bool LO = false>
 __device__ inline void load_query_rows(int8_t* qs, int qstride, const int* s_q, const int8_t* __restrict__ qint,
-                                       int dp, int mq, int tid)
+                                       int dp, int mq, int tid, const int8_t* __restrict__ qlo = nullptr)
 {
     constexpr int QPI = kQT * NQT;
     const int nch = dp >> 4;                       // 16-byte chunks per row
@@ -217,7 +236,13 @@ __device__ inline void load_query_rows(int8_t* qs, int qstride, const int* s_q, 
             const int qi = (int)(((float)u + 0.5f) * rnch);
             const int c = u - qi * nch;
             w[k] = make_uint4(0, 0, 0, 0);
-            if (u < units && qi < mq) w[k] = *(const uint4*)(qint + (int64_t)s_q[qi] * dp + 16 * c);
+            if constexpr (LO) {
+                const int qq = qi < kQT ? qi : qi - kQT;
+                if (u < units && qq < mq)
+                    w[k] = *(const uint4*)((qi < kQT ? qint : qlo) + (int64_t)s_q[qq] * dp + 16 * c);
+            } else {
+                if (u < units && qi < mq) w[k] = *(const uint4*)(qint + (int64_t)s_q[qi] * dp + 16 * c);
+            }
         }
 #pragma unroll
         for (int k = 0; k < kRowLoads; ++k) {
@@ -236,7 +261,7 @@ __device__ inline void load_query_rows(int8_t* qs, int qstride, const int* s_q, 
 // with one compare; survivors go to the query's candidate buffer in HBM
 // (staged in LDS; straight to HBM once the LDS stage is full).
 // ---------------------------------------------------------------------------
-template <int BITS, int NQT, int PD, bool DENSE>
+template <int BITS, int NQT, int PD, bool DENSE, bool LO>
 __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
     const uint8_t* __restrict__ codes, const int64_t* __restrict__ tile_off,
     const int64_t* __restrict__ list_off, const float2* __restrict__ fac,
@@ -248,6 +273,10 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
     int vch, int nprobe)
 {
     constexpr bool dense = DENSE;
+    // LO (two query planes, NQT = 2): the item holds up to kQT queries; query
+    // tile 0 is their high planes, tile 1 their low planes, and the epilogue
+    // combines the two accumulators of a column into one estimate.
+    static_assert(!LO || NQT == 2, "two query planes use the two query tiles");
     // DENSE (first bound): only the first kDenseV members of each list,
     // no bound test, every estimate written to slot rank*kDenseV + member of
     // the query's buffer (rank = probe rank of the pair, < kDenseR)
@@ -305,7 +334,7 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
         }
     }
     __syncthreads();
-    load_query_rows<NQT>(qs, qstride, s_q, qa.qint, dp, mq, tid);
+    load_query_rows<NQT, LO>(qs, qstride, s_q, qa.qint, dp, mq, tid, qa.qlo);
     __syncthreads();
 
     const int nkb = dp / 64;
@@ -326,7 +355,7 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
     bool qok[NQT];
 #pragma unroll
     for (int qt = 0; qt < NQT; ++qt) {
-        const int qi = qt * kQT + j;
+        const int qi = LO ? j : qt * kQT + j;         // LO: both tiles are query j
         qok[qt] = qi < mq;
         qs2[qt] = qok[qt] ? s_s2[qi] : 0.0f;
         qhd[qt] = qok[qt] ? s_hd[qi] : 0.0f;
@@ -346,13 +375,15 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
     // compares the part before + s2 with AQ = tau - s2 rounded up by a margin
     // above the rounding of both subtractions, so it never drops a candidate
     // whose final estimate is <= tau.  Columns without a query take AQ = -inf.
-    float cH2[NQT], cHC[NQT], cAQ[NQT];
+    float cH2[NQT], cHC[NQT], cAQ[NQT], cH2L = 0.0f;
 #pragma unroll
     for (int qt = 0; qt < NQT; ++qt) {
         epi_consts<BITS>(qhd[qt], qss[qt], cH2[qt], cHC[qt]);
         const float aq = qtau[qt] - qs2[qt];
         cAQ[qt] = qok[qt] ? aq + (fabsf(qtau[qt]) + fabsf(qs2[qt])) * 0x1p-20f : -__builtin_huge_valf();
     }
+    if constexpr (LO)
+        epi_consts2<BITS>(qhd[0], qss[0], qok[0] ? qa.qss_lo[s_q[j]] : 0, cH2[0], cH2L, cHC[0]);
 
     // Wave wid takes the tiles [ta, tb) of the item (a contiguous quarter,
     // so the waves differ by at most one tile) and walks them in groups of
@@ -443,16 +474,24 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
                     const float2 f = fr[r];
                     float e[NQT];
                     bool pass[NQT], anyp = false;
+                    if constexpr (LO) {                     // one estimate from the two planes
+                        e[0] = epi_e2(f, acc[a][0][r], acc[a][1][r], cH2[0], cH2L, cHC[0]);
+                        pass[0] = e[0] <= cAQ[0];
+                        pass[1] = false;
+                        e[1] = 0.0f;
+                        anyp = pass[0];
+                    } else {
 #pragma unroll
-                    for (int qt = 0; qt < NQT; ++qt) {
-                        e[qt] = epi_e(f, acc[a][qt][r], cH2[qt], cHC[qt]);
-                        pass[qt] = e[qt] <= cAQ[qt];
-                        anyp = anyp || pass[qt];
+                        for (int qt = 0; qt < NQT; ++qt) {
+                            e[qt] = epi_e(f, acc[a][qt][r], cH2[qt], cHC[qt]);
+                            pass[qt] = e[qt] <= cAQ[qt];
+                            anyp = anyp || pass[qt];
+                        }
                     }
                     if constexpr (DENSE) {                  // first bound: keep every estimate
                         const bool ok = v < nl;
 #pragma unroll
-                        for (int qt = 0; qt < NQT; ++qt) {
+                        for (int qt = 0; qt < (LO ? 1 : NQT); ++qt) {
                             if (ok && qok[qt]) {
                                 gbuf_e[qslot0[qt] + v] = e[qt] + qs2[qt];
                                 gbuf_i[qslot0[qt] + v] = s_id[v];
@@ -462,7 +501,7 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
                     }
                     if (!__any(anyp)) continue;
 #pragma unroll
-                    for (int qt = 0; qt < NQT; ++qt) {
+                    for (int qt = 0; qt < (LO ? 1 : NQT); ++qt) {
                         if (!pass[qt]) continue;
                         const float est = e[qt] + qs2[qt];
                         const int qi = qt * kQT + j;
@@ -1176,7 +1215,7 @@ __device__ __attribute__((always_inline)) inline unsigned long long block_keep(
 // LDS: kCapE keys, the tile prefix over the probes (nprobe + 1 ints, rounded
 // up to 16 bytes) and the query's int8 row (dp bytes).  redo counts the
 // probed pairs of the flagged queries (diagnostics).
-template <int BITS>
+template <int BITS, bool LO>
 __global__ __launch_bounds__(256) void exact_kernel(
     const uint8_t* __restrict__ codes, const int64_t* __restrict__ tile_off, const int64_t* __restrict__ list_off,
     const float2* __restrict__ fac, const int64_t* __restrict__ ids, int dp, QArgs qa,
@@ -1195,11 +1234,15 @@ __global__ __launch_bounds__(256) void exact_kernel(
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int nkb = dp / 64;
     const int64_t tile_bytes = (int64_t)4 * dp * BITS;
-    const int8_t* qrow = qs + 16 * (lane >> 5);  // every MFMA column is the query itself
+    // every MFMA column is the query itself; LO: columns 16..31 its low plane (LDS row 2)
+    const int8_t* qrow = qs + 16 * (lane >> 5) + ((LO && (lane & 31) >= 16) ? dp : 0);
     for (int64_t q = blockIdx.x; q < nq; q += gridDim.x) {
         if (!ovf[q]) continue;                   // the same for the whole block
         __syncthreads();                         // LDS of the previous query is free
         for (int c = tid; c < dp / 16; c += 256) *(uint4*)(qs + 16 * c) = *(const uint4*)(qa.qint + q * dp + 16 * c);
+        if constexpr (LO)
+            for (int c = tid; c < dp / 16; c += 256)
+                *(uint4*)(qs + dp + 16 * c) = *(const uint4*)(qa.qlo + q * dp + 16 * c);
         // member tiles per probe (thread t: probes 4t .. 4t+3), exclusive prefix
         unsigned nt[4], sum = 0, npair = 0;
 #pragma unroll
@@ -1229,8 +1272,9 @@ __global__ __launch_bounds__(256) void exact_kernel(
         if (redo && npair) atomicAdd(redo, (int)npair);
         __syncthreads();
         const int total = tpref[nprobe];
-        float h2, hc;
-        epi_consts<BITS>(qa.qhd[q], qa.qss[q], h2, hc);
+        float h2, hc, h2l = 0.0f;
+        if constexpr (LO) epi_consts2<BITS>(qa.qhd[q], qa.qss[q], qa.qss_lo[q], h2, h2l, hc);
+        else epi_consts<BITS>(qa.qhd[q], qa.qss[q], h2, hc);
         for (int base = 0; base < total; base += 4) {
             const int g = base + wid;
             const unsigned long long T = s_T;
@@ -1260,13 +1304,16 @@ __global__ __launch_bounds__(256) void exact_kernel(
                 // lane (h, j < 16) takes output row out_row(lane, j): the 32
                 // lanes cover the tile's 32 members once
                 const int j = lane & 31;
-                if (j < 16) {
-                    int a = acc[0];
+                int a = acc[0];
 #pragma unroll
-                    for (int r = 1; r < 16; ++r) a = (r == j) ? acc[r] : a;
+                for (int r = 1; r < 16; ++r) a = (r == (j & 15)) ? acc[r] : a;
+                // LO: lane j + 16 holds the low plane's product of the same row
+                const int alo = LO ? __shfl_down(a, 16) : 0;
+                if (j < 16) {
                     const int v = tt * 32 + out_row(lane, j);
                     if (v < nl) {
-                        const float est = epi_e(fac[lb + v], a, h2, hc) + s2;
+                        const float est = (LO ? epi_e2(fac[lb + v], a, alo, h2, h2l, hc)
+                                              : epi_e(fac[lb + v], a, h2, hc)) + s2;
                         const unsigned long long key =
                             ((unsigned long long)f2key(est) << 32) | (unsigned)(int)ids[lb + v];
                         if (key < T) keys[atomicAdd(&s_cnt, 1)] = key;
@@ -1317,9 +1364,11 @@ __global__ __launch_bounds__(256) void exact_kernel(
 // q' -> int8 once per query (symmetric: inv = 127/max|q'|, round half to
 // even, clamp to +-127), delta/2 and the sum of the int8 values; one wave per query
 // (the first dp coordinates of each row of qrot, rows ld apart)
+// qlo (or null): the low plane, q_lo = rint((q' * inv - q_int) * 254), and its sums
 __global__ __launch_bounds__(256) void qprep_kernel(const float* __restrict__ qrot, int64_t nq, int dp, int ld,
                                                     int8_t* __restrict__ qint, float* __restrict__ qhd,
-                                                    int32_t* __restrict__ qss)
+                                                    int32_t* __restrict__ qss, int8_t* __restrict__ qlo,
+                                                    int32_t* __restrict__ qss_lo)
 {
     const int lane = threadIdx.x & 63;
     const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -1329,17 +1378,25 @@ __global__ __launch_bounds__(256) void qprep_kernel(const float* __restrict__ qr
     for (int i = lane; i < dp; i += 64) amax = fmaxf(amax, fabsf(qv[i]));
     for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o));
     const float inv = (amax > 0.0f) ? __fdiv_rn(127.0f, amax) : 0.0f;
-    int ssum = 0;
+    int ssum = 0, slo = 0;
     for (int i = lane; i < dp; i += 64) {
-        int v = (int)rintf(qv[i] * inv);
+        const float t = qv[i] * inv;
+        int v = (int)rintf(t);
         v = max(-127, min(127, v));
         qint[q * dp + i] = (int8_t)v;
         ssum += v;
+        if (qlo) {
+            int w = (int)rintf((t - (float)v) * 254.0f);
+            w = max(-127, min(127, w));
+            qlo[q * dp + i] = (int8_t)w;
+            slo += w;
+        }
     }
-    for (int o = 32; o > 0; o >>= 1) ssum += __shfl_xor(ssum, o);
+    for (int o = 32; o > 0; o >>= 1) { ssum += __shfl_xor(ssum, o); slo += __shfl_xor(slo, o); }
     if (lane == 0) {
         qhd[q] = 0.5f * ((amax > 0.0f) ? __fdiv_rn(amax, 127.0f) : 0.0f);
         qss[q] = ssum;
+        if (qss_lo) qss_lo[q] = slo;
     }
 }
 
@@ -1741,10 +1798,10 @@ struct ScanArgs {
 struct BArgs { unsigned* tau_key; int32_t* gcnt; float* gbuf_e; int32_t* gbuf_i; int32_t* work;
                int vch, dense, nprobe; int32_t* gstat; };
 
-template <int BITS, int NQT, int PD, bool DENSE>
+template <int BITS, int NQT, int PD, bool DENSE, bool LO>
 hipError_t launchB_d(const Index* ix, const ScanArgs& a, const BArgs& b, hipStream_t st)
 {
-    const void* kern = (const void*)scanB_kernel<BITS, NQT, PD, DENSE>;
+    const void* kern = (const void*)scanB_kernel<BITS, NQT, PD, DENSE, LO>;
     const size_t sm = (size_t)(ix->dc + 16) * kQT * NQT;
     if (sm > 48 * 1024) {
         hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
@@ -1757,38 +1814,42 @@ hipError_t launchB_d(const Index* ix, const ScanArgs& a, const BArgs& b, hipStre
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
     const int64_t grid = std::min<int64_t>(a.grid, (int64_t)std::max(per_cu, 1) * std::max(ncu, 1));
-    hipLaunchKernelGGL((scanB_kernel<BITS, NQT, PD, DENSE>), dim3((unsigned)grid), dim3(kThreads), sm, st,
+    hipLaunchKernelGGL((scanB_kernel<BITS, NQT, PD, DENSE, LO>), dim3((unsigned)grid), dim3(kThreads), sm, st,
                        ix->codes, ix->tile_off, ix->list_off, ix->sfac, ix->ids, ix->dc,
                        a.qa, a.pair_off, a.pair_q, a.pair_slot, a.item_off, a.desc, (int)ix->nlist,
                        a.kk, b.tau_key, b.gcnt, b.gbuf_e, b.gbuf_i, b.work, b.vch, b.nprobe);
     return hipGetLastError();
 }
 
-template <int BITS, int NQT, int PD>
+template <int BITS, int NQT, int PD, bool LO>
 hipError_t launchB_t(const Index* ix, const ScanArgs& a, const BArgs& b, hipStream_t st)
 {
-    if (b.dense) return launchB_d<BITS, NQT, PD, true>(ix, a, b, st);
-    return launchB_d<BITS, NQT, PD, false>(ix, a, b, st);
+    if (b.dense) return launchB_d<BITS, NQT, PD, true, LO>(ix, a, b, st);
+    return launchB_d<BITS, NQT, PD, false, LO>(ix, a, b, st);
 }
 
-template <int BITS, int NQT>
+template <int BITS, int NQT, bool LO = false>
 hipError_t launchB_n(const Index* ix, const ScanArgs& a, const BArgs& b, hipStream_t st)
 {
     switch (scan_pd(ix)) {
         case 6:
-            if constexpr (BITS <= 4) return launchB_t<BITS, NQT, 6>(ix, a, b, st);
+            if constexpr (BITS <= 4) return launchB_t<BITS, NQT, 6, LO>(ix, a, b, st);
             break;
-        case 4: return launchB_t<BITS, NQT, 4>(ix, a, b, st);
-        case 3: return launchB_t<BITS, NQT, 3>(ix, a, b, st);
-        case 2: return launchB_t<BITS, NQT, 2>(ix, a, b, st);
+        case 4: return launchB_t<BITS, NQT, 4, LO>(ix, a, b, st);
+        case 3: return launchB_t<BITS, NQT, 3, LO>(ix, a, b, st);
+        case 2: return launchB_t<BITS, NQT, 2, LO>(ix, a, b, st);
         default: break;
     }
-    return launchB_t<BITS, NQT, 1>(ix, a, b, st);
+    return launchB_t<BITS, NQT, 1, LO>(ix, a, b, st);
 }
 
 template <int BITS>
 hipError_t launchB_b(const Index* ix, const ScanArgs& a, const BArgs& b, hipStream_t st)
 {
+    if (ix->qplanes == 2) {                         // two query planes: B >= 5 only
+        if constexpr (BITS >= 5) return launchB_n<BITS, 2, true>(ix, a, b, st);
+        return hipErrorInvalidValue;
+    }
     if (scan_nqt(ix) == 2) return launchB_n<BITS, 2>(ix, a, b, st);
     return launchB_n<BITS, 1>(ix, a, b, st);
 }
@@ -1851,16 +1912,31 @@ hipError_t launch2(const Index* ix, const ScanArgs& a, const BArgs& b, hipStream
     }
 }
 
+template <int BITS, bool LO>
+hipError_t launch_exact_l(const Index* ix, const QArgs& qa, const int32_t* probes, int64_t nq, int nprobe, int kk,
+                          const int32_t* ovf, const int32_t* gate, int32_t* redo, int64_t* oi, float* oe,
+                          hipStream_t st)
+{
+    const size_t sm = sizeof(unsigned long long) * kCapE + sizeof(int) * ((nprobe + 4) & ~3) +
+                      (size_t)ix->dc * (LO ? 2 : 1);
+    const unsigned grid = (unsigned)std::min<int64_t>(nq, 1024);
+    hipLaunchKernelGGL((exact_kernel<BITS, LO>), dim3(grid), dim3(256), sm, st, ix->codes, ix->tile_off,
+                       ix->list_off, ix->sfac, ix->ids, ix->dc, qa, probes, nq, nprobe, (int)ix->nlist, kk, ovf, gate,
+                       redo, oi, oe);
+    return hipGetLastError();
+}
+
 template <int BITS>
 hipError_t launch_exact_b(const Index* ix, const QArgs& qa, const int32_t* probes, int64_t nq, int nprobe, int kk,
                           const int32_t* ovf, const int32_t* gate, int32_t* redo, int64_t* oi, float* oe,
                           hipStream_t st)
 {
-    const size_t sm = sizeof(unsigned long long) * kCapE + sizeof(int) * ((nprobe + 4) & ~3) + (size_t)ix->dc;
-    const unsigned grid = (unsigned)std::min<int64_t>(nq, 1024);
-    hipLaunchKernelGGL((exact_kernel<BITS>), dim3(grid), dim3(256), sm, st, ix->codes, ix->tile_off, ix->list_off,
-                       ix->sfac, ix->ids, ix->dc, qa, probes, nq, nprobe, (int)ix->nlist, kk, ovf, gate, redo, oi, oe);
-    return hipGetLastError();
+    if (ix->qplanes == 2) {
+        if constexpr (BITS >= 5)
+            return launch_exact_l<BITS, true>(ix, qa, probes, nq, nprobe, kk, ovf, gate, redo, oi, oe, st);
+        return hipErrorInvalidValue;
+    }
+    return launch_exact_l<BITS, false>(ix, qa, probes, nq, nprobe, kk, ovf, gate, redo, oi, oe, st);
 }
 
 // exact fallback for the flagged queries (returns at once on the device when
@@ -1955,7 +2031,8 @@ size_t scan_workspace_bytes(int64_t nq, int nprobe, int64_t nlist, int kk, int d
     b += align256(sizeof(float) * nq * kCapQ);             // candidate buffers
     b += align256(sizeof(int32_t) * nq * kCapQ);
     b += align256(sizeof(int32_t) * 3);                    // fallback pairs, two-stage group counts
-    b += align256((size_t)nq * dp);                        // int8 queries
+    b += 2 * align256((size_t)nq * dp);                    // int8 queries (high and low planes)
+    b += align256(sizeof(int32_t) * nq);                   // sums of the low planes
     b += 2 * align256(sizeof(float) * nq);                 // delta/2, sum of int8 values
     b += align256(sizeof(float) * P);                      // ||s||^2 per pair
     b += align256(sizeof(int32_t) * nq);                   // flagged queries of a gated pair build
@@ -1993,6 +2070,9 @@ int run_scan(Index* ix, const float* qrot, int64_t qld, int64_t nq, const int32_
     int32_t* gbi = (int32_t*)take(sizeof(int32_t) * nq * kCapQ);
     int32_t* redo = (int32_t*)take(sizeof(int32_t) * 3);   // fallback pairs; two-stage groups, skipped
     int8_t* qint = (int8_t*)take((size_t)nq * dp);
+    int8_t* qlo = (int8_t*)take((size_t)nq * dp);
+    int32_t* qss_lo = (int32_t*)take(sizeof(int32_t) * nq);
+    const bool lo = ix->qplanes == 2;
     float* qhd = (float*)take(sizeof(float) * nq);
     int32_t* qss = (int32_t*)take(sizeof(int32_t) * nq);
     float* sdist_ws = (float*)take(sizeof(float) * P);
@@ -2047,12 +2127,12 @@ int run_scan(Index* ix, const float* qrot, int64_t qld, int64_t nq, const int32_
                            gprev, gbe, gbi, nq, kk, mode, post, tkey, ovf, oi, oe, mode == 1 ? anyf2 : anyf);
         return hipGetLastError();
     };
-    const int qpiB = scan_nqt(ix) * kQT;            // queries per item of the launched kernel
+    const int qpiB = ix->qplanes == 2 ? kQT : scan_nqt(ix) * kQT;   // queries per item of the launched kernel
     const int pr = prof_begin(PK_SCAN, st);
     hipError_t e = hipSuccess;
     // queries to int8 once; ||s||^2 per pair from the probe distances, else computed
     hipLaunchKernelGGL(qprep_kernel, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, st, qrot, nq, dp, (int)qld, qint,
-                       qhd, qss);
+                       qhd, qss, lo ? qlo : nullptr, lo ? qss_lo : nullptr);
     const float* sdist = pdist;
     const bool ip = ix->metric != ERQ_METRIC_L2;
     if (!sdist && P > 0) {
@@ -2064,12 +2144,13 @@ int run_scan(Index* ix, const float* qrot, int64_t qld, int64_t nq, const int32_
                                ix->cent_rot, probes, P, nprobe, (int)nlist, ix->dp, sdist_ws);
         sdist = sdist_ws;
     }
-    const QArgs qa{qint, qhd, qss, sdist, ip ? -__builtin_huge_valf() : 0.0f};
+    const QArgs qa{qint, qhd, qss, sdist, ip ? -__builtin_huge_valf() : 0.0f, lo ? qlo : nullptr,
+                   lo ? qss_lo : nullptr};
     const int64_t gridB = 1 << 20;                    // capped at the resident blocks
     // a pass-B launch over the pairs of probe ranks [rlo, rhi) (of flagged
     // queries with qmask); dense = the first-bound mode
     // the two-stage scan (Sec. 4.2) replaces pass B when the index has its 1-bit data and eps0 > 0
-    const bool two = ix->eps0 > 0.0f && ix->msb && ix->fac1;
+    const bool two = ix->eps0 > 0.0f && ix->msb && ix->fac1 && ix->qplanes == 1;
     auto scan_round = [&](int rlo, int rhi, const int32_t* qmask, int dense, const int32_t* gate) {
         const int vch = dense ? 0 : (two ? kVch2 : kVch);
         hipError_t er = build_pairs(rlo, rhi, qmask, qpiB, vch, gate);

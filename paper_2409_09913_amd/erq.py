@@ -32,6 +32,7 @@ SIGNATURES = {
     "erq_index_destroy": (C.c_int, [_p]),
     "erq_index_set_projection": (C.c_int, [_p, _i32, _p]),
     "erq_index_set_two_stage": (C.c_int, [_p, C.c_float]),
+    "erq_index_set_query_planes": (C.c_int, [_p, _i32]),
     "erq_index_code_dim": (C.c_int, [_p, C.POINTER(_i32)]),
     "erq_index_get_rotation": (C.c_int, [_p, _p, _p]),
     "erq_index_save": (C.c_int, [_p, C.c_char_p, _p]),
@@ -202,6 +203,11 @@ class Index:
         on an empty index it makes the build store the 1-bit data, on a
         built one it sets eps0 (0 = the one-stage scan)."""
         _check(load().erq_index_set_two_stage(self.h, float(eps0)))
+
+    def set_query_planes(self, planes: int):
+        """1: one int8 query plane; 2: a second plane of the rounding remainder
+        (B >= 5), 254 times smaller query error at twice the matrix-core work."""
+        _check(load().erq_index_set_query_planes(self.h, planes))
 
     def code_dim(self) -> int:
         dc = C.c_int32()
