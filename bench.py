@@ -213,8 +213,13 @@ def main():
     best, rows = sweep(ix, "B=%d" % args.bits)
     nprobe, rr, rec, _ = best
     best2 = None
+    best2_lo = None
     if args.bits2:
         best2, _ = sweep(ix2, "B=%d" % args.bits2)
+        if args.bits2 >= 5:                     # the same sweep with the int8 query in two planes
+            ix2.set_query_planes(2)
+            best2_lo, _ = sweep(ix2, "B=%d two query planes" % args.bits2)
+            ix2.set_query_planes(1)
 
     # ---- scan schedule: the library's autotuner at the operating point ------------------
     tuned = None
@@ -372,8 +377,9 @@ def main():
         for index, B, npr in ((ix, args.bits, nprobe),) + (((ix2, args.bits2, best2[0]),) if args.bits2 else ()):
             r = estimator_recall(index, cent, q_np, P_np, truth_np, npr, args.k, B, args.est_queries)
             est_tab.append(r)
-            log("estimator recall B=%d nprobe %d (%d queries, no re-rank): int8 query %.4f, float query %.4f" %
-                (B, npr, r["queries"], r["recall_int8_query"], r["recall_float_query"]))
+            log("estimator recall B=%d nprobe %d (%d queries, no re-rank): int8 query %.4f, float query %.4f%s" %
+                (B, npr, r["queries"], r["recall_int8_query"], r["recall_float_query"],
+                 ", int8 two planes %.4f" % r["recall_int8_two_planes"] if "recall_int8_two_planes" in r else ""))
 
     # ---- CPU baseline: the oracle on a bounded sample ------------------------------------
     cpu = None
@@ -406,6 +412,9 @@ def main():
     if args.bits2:
         res["bits2"] = {"bits": args.bits2, "encode_codes_per_s": enc_rate2,
                         "best": {"nprobe": best2[0], "rerank_k": best2[1], "recall@10": best2[2], "qps": best2[3]}}
+        if best2_lo is not None:
+            res["bits2"]["best_two_query_planes"] = {"nprobe": best2_lo[0], "rerank_k": best2_lo[1],
+                                                     "recall@10": best2_lo[2], "qps": best2_lo[3]}
     log("total %.1fs" % (time.time() - t0))
     print(json.dumps(res), flush=True)
 
@@ -476,25 +485,33 @@ def run_batching(args):
         for rr in (0, 2 * k):
             ids, _ = ix.search(q, 256, k, rr, nprobe_q=npq)
             rec = recall_at(ids.cpu().numpy(), truth, k)
-            for bs in (1, 4, 16, 64, 256, 1024, 4096):
-                gph = serve.SearchGraph(ix, bs, 256, k, rr, per_query=True)
-                gph.q.copy_(q[:bs])
-                gph.params[0].copy_(npq[:bs])
-                with torch.cuda.stream(gph.stream):
-                    gph.graph.replay()
-                torch.cuda.synchronize()
-                reps = max(3, min(200, 8192 // bs))
-                ts = time.perf_counter()
-                with torch.cuda.stream(gph.stream):
-                    for _ in range(reps):
+            for bs in (1, 4, 16, 32, 64, 256, 1024, 4096):
+                row = {"rerank_k": rr, "batch": bs, "recall@10_full_batch": rec}
+                # batches of at most 32 queries take the small-batch scan path; the
+                # pair-grouped pipeline is timed beside it
+                for label, sq in (("", 32), ("_pipeline", 0)) if bs <= 32 else (("", 32),):
+                    ix.set_small_batch(sq)
+                    gph = serve.SearchGraph(ix, bs, 256, k, rr, per_query=True)
+                    gph.q.copy_(q[:bs])
+                    gph.params[0].copy_(npq[:bs])
+                    with torch.cuda.stream(gph.stream):
                         gph.graph.replay()
-                torch.cuda.synchronize()
-                dt = (time.perf_counter() - ts) / reps
-                rows.append({"rerank_k": rr, "batch": bs, "qps": bs / dt, "ms_per_batch": dt * 1e3,
-                             "recall@10_full_batch": rec})
-                del gph
-            log("batching B=%d rerank %d recall@10 %.4f; QPS by batch %s" %
-                (B, rr, rec, {r["batch"]: round(r["qps"]) for r in rows if r["rerank_k"] == rr}))
+                    torch.cuda.synchronize()
+                    reps = max(3, min(200, 8192 // bs))
+                    ts = time.perf_counter()
+                    with torch.cuda.stream(gph.stream):
+                        for _ in range(reps):
+                            gph.graph.replay()
+                    torch.cuda.synchronize()
+                    dt = (time.perf_counter() - ts) / reps
+                    row["qps" + label] = bs / dt
+                    row["ms_per_batch" + label] = dt * 1e3
+                    del gph
+                ix.set_small_batch(32)
+                rows.append(row)
+            log("batching B=%d rerank %d recall@10 %.4f; QPS by batch %s; pipeline path at small batches %s" %
+                (B, rr, rec, {r["batch"]: round(r["qps"]) for r in rows if r["rerank_k"] == rr},
+                 {r["batch"]: round(r["qps_pipeline"]) for r in rows if r["rerank_k"] == rr and "qps_pipeline" in r}))
         # pass-B launch time of the full batch for the roofline
         erq.profile_enable(True)
         erq.profile_read("scan_b", reset=True)
@@ -900,8 +917,14 @@ def estimator_recall(ix, cent, q_np, P_np, truth_np, nprobe, k, B, S):
     gi = gi.cpu().numpy()
     qrot = oracle.rotate(q_np[:S], P_np).astype(np.float32)
     fi, _ = oracle.search(off, ids, codes, fa, fr, crot, qrot, probes, B, k, est_mode=2)
-    return {"bits": B, "nprobe": nprobe, "queries": S, "recall_int8_query": recall_at(gi, truth_np[:S], k),
-            "recall_float_query": recall_at(fi, truth_np[:S], k)}
+    out = {"bits": B, "nprobe": nprobe, "queries": S, "recall_int8_query": recall_at(gi, truth_np[:S], k),
+           "recall_float_query": recall_at(fi, truth_np[:S], k)}
+    if B >= 5:                                  # the int8 query in two planes (GPU)
+        ix.set_query_planes(2)
+        g2, _ = ix.search(qs, nprobe, k, 0)
+        ix.set_query_planes(1)
+        out["recall_int8_two_planes"] = recall_at(g2.cpu().numpy(), truth_np[:S], k)
+    return out
 
 
 if __name__ == "__main__":

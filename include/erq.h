@@ -177,6 +177,16 @@ int erq_index_set_two_stage(erq_index idx, float eps0);
    the codes do not change; saved with the index. */
 int erq_index_set_query_planes(erq_index idx, int32_t planes);
 
+/* Batches of at most max_queries queries (default 32; 0 = never) take the
+   scan's small-batch path: each query's probed lists are split over up to
+   64 workgroups that keep exact top-kk lists, merged by one final select,
+   instead of the pair-grouped pipeline of large batches (first bound, rounds
+   of bounded scans, selects: about 35 launches).  Both give the exact top-kk
+   by (estimate, id); the small path reads each probed list once per query
+   rather than once per tile of its queries, so it suits batches whose
+   queries share few lists.  max_queries in [0, 1024]; saved with the index. */
+int erq_index_set_small_batch(erq_index idx, int32_t max_queries);
+
 /* The code dimension dc (dp without a projection). */
 int erq_index_code_dim(erq_index idx, int32_t* dc);
 
@@ -185,7 +195,8 @@ int erq_index_get_rotation(erq_index idx, float* P_out, void* stream);
 
 /* Writes the whole index to a file (host path): a versioned header (magic
    "ERQIDX", version 2, dp, bits, raw kept, metric, code dimension, nlist,
-   n, tiles, scan schedule, seed, two-stage flag and eps0, query planes),
+   n, tiles, scan schedule, seed, two-stage flag and eps0, query planes,
+   small-batch threshold),
    then P, raw and rotated centroids, list offsets, ids, factors, scan
    factors, packed codes, when kept the raw vectors, and with the two-stage
    scan its bit planes and 1-bit factors, in native byte order.

@@ -185,6 +185,7 @@ __global__ void query_params_kernel(int64_t nq, int nprobe, int kmax, int rrmax,
 }
 
 inline unsigned blocks(int64_t n, int th = 256) { return (unsigned)((n + th - 1) / th); }
+constexpr int kMaxSmallQ = 1024;               // largest threshold of the small-batch scan path
 constexpr int kBuildKmeansIters = 10;          // Lloyd rounds of erq_index_build without centroids
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -392,7 +393,7 @@ struct FileHeader {
     int32_t two_stage;                               // 1: the two-stage scan's data follow the codes
     float eps0;
     int32_t qplanes;                                 // int8 query planes of the scan (1 or 2)
-    int32_t reserved;                                // 0
+    int32_t small_q;                                 // largest batch of the small-batch scan path
 };
 
 // bytes of every array of an index file after the header, in file order
@@ -565,6 +566,7 @@ int erq_index_save(erq_index ix, const char* path, void* stream)
     h.two_stage = ix->msb ? 1 : 0;
     h.eps0 = ix->eps0;
     h.qplanes = ix->qplanes;
+    h.small_q = ix->small_q;
     FILE* f = std::fopen(path, "wb");
     if (!f) return fail(ERQ_EINVAL, std::string("erq_index_save: cannot open ") + path);
     struct Closer { FILE* f; ~Closer() { if (f) std::fclose(f); } } closer{f};
@@ -595,7 +597,8 @@ int erq_index_load(const char* path, void* stream, erq_index* out)
         h.nlist > (1 << 24) || h.n < 0 || h.n > (1LL << 31) - 1 || h.ntiles < 0 || (h.has_raw != 0 && h.has_raw != 1) ||
         h.metric < ERQ_METRIC_L2 || h.metric > ERQ_METRIC_COSINE || h.dc < 64 || h.dc > h.dp || h.dc % 64 ||
         (h.two_stage != 0 && h.two_stage != 1) || !(h.eps0 >= 0.0f) || !(h.eps0 < 1e30f) ||
-        (h.qplanes != 1 && h.qplanes != 2) || (h.qplanes == 2 && (h.bits < 5 || h.two_stage)))
+        (h.qplanes != 1 && h.qplanes != 2) || (h.qplanes == 2 && (h.bits < 5 || h.two_stage)) ||
+        h.small_q < 0 || h.small_q > kMaxSmallQ)
         return fail(ERQ_EINVAL, "erq_index_load: bad header");
     const std::vector<size_t> sz = file_arrays(h);
     size_t total = sizeof(h);
@@ -619,7 +622,7 @@ int erq_index_load(const char* path, void* stream, erq_index* out)
     if (!ix) return fail(ERQ_ENOMEM, "erq_index_load: out of host memory");
     struct Owner { erq_index_s* p; ~Owner() { if (p) erq_index_destroy(p); } } owner{ix};
     ix->dp = dp; ix->bits = h.bits; ix->nlist = C; ix->seed = h.seed; ix->metric = h.metric; ix->dc = h.dc;
-    ix->two_stage = h.two_stage; ix->eps0 = h.eps0; ix->qplanes = h.qplanes;
+    ix->two_stage = h.two_stage; ix->eps0 = h.eps0; ix->qplanes = h.qplanes; ix->small_q = h.small_q;
     ix->tune_nqt = h.tune[0]; ix->tune_pd = h.tune[1]; ix->tune_round1 = h.tune[2]; ix->tune_round2 = h.tune[3];
     hipGetDevice(&ix->device);
     if (int rc = set_list_meta(ix, off, st)) return rc;
@@ -695,6 +698,15 @@ int erq_index_set_query_planes(erq_index ix, int32_t planes)
     if (planes == 2 && (ix->bits < 5 || ix->two_stage))
         return fail(ERQ_EUNSUPPORTED, "erq_index_set_query_planes: two planes need bits >= 5 and no two-stage scan");
     ix->qplanes = planes;
+    return ERQ_OK;
+}
+
+int erq_index_set_small_batch(erq_index ix, int32_t max_queries)
+{
+    if (!ix) return fail(ERQ_EINVAL, "erq_index_set_small_batch: null index");
+    if (max_queries < 0 || max_queries > kMaxSmallQ)
+        return fail(ERQ_EINVAL, "erq_index_set_small_batch: max_queries must be in [0, 1024]");
+    ix->small_q = max_queries;
     return ERQ_OK;
 }
 

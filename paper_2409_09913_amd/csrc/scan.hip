@@ -46,6 +46,7 @@ constexpr int kDenseV = 256;   // ... and members per list (all estimates kept)
 constexpr int kRound1 = 8;     // pass B, round 1: probe ranks [0, kRound1)
 constexpr int kCapQ = 4096;    // candidate buffer per query (HBM)
 constexpr int kVch = 1024;     // pass-B members per item (long lists are split)
+constexpr int kSmallS = 64;    // small-batch path: at most this many workgroups per query
 
 __device__ inline unsigned f2key(float f) {
     unsigned u = __float_as_uint(f);
@@ -1211,19 +1212,32 @@ __device__ __attribute__((always_inline)) inline unsigned long long block_keep(
     return kth;
 }
 
-// One flagged query per workgroup (grid-stride over the queries).  Dynamic
-// LDS: kCapE keys, the tile prefix over the probes (nprobe + 1 ints, rounded
-// up to 16 bytes) and the query's int8 row (dp bytes).  redo counts the
-// probed pairs of the flagged queries (diagnostics).
+// Exact top-kk of one query over its probed lists by one workgroup, the
+// query replicated over the 32 MFMA columns (LO: columns 16..31 its low
+// plane).  Two uses:
+//  * fallback (slices == 0): the flagged queries (ovf) of a scan whose
+//    candidate buffer still overflowed; writes the sorted result;
+//  * small batches (slices = S > 0, ovf and gate null): workgroup (q, s)
+//    takes the s-th of S equal parts of query q's member tiles (over all its
+//    probed lists, in probe order) and appends its top-kk
+//    (unsorted) to the query's candidate buffer, whose count starts at 0
+//    (at most S kk <= kCapQ entries, all distinct members), for the final
+//    select; a search of a few queries then runs in a handful of launches.
+// Grid-stride over (query, slice).  Dynamic LDS: kCapE keys, the tile prefix
+// over the probes (nprobe + 1 ints, rounded up to 16 bytes) and the query's
+// int8 rows (dp bytes per plane).  redo counts the probed pairs of the
+// fallback's queries (diagnostics).
 template <int BITS, bool LO>
 __global__ __launch_bounds__(256) void exact_kernel(
     const uint8_t* __restrict__ codes, const int64_t* __restrict__ tile_off, const int64_t* __restrict__ list_off,
     const float2* __restrict__ fac, const int64_t* __restrict__ ids, int dp, QArgs qa,
     const int32_t* __restrict__ probes, int64_t nq, int nprobe, int nlist, int kk,
     const int32_t* __restrict__ ovf, const int32_t* __restrict__ gate, int32_t* __restrict__ redo,
-    int64_t* __restrict__ out_ids, float* __restrict__ out_est)
+    int64_t* __restrict__ out_ids, float* __restrict__ out_est, int slices, int32_t* __restrict__ gcnt,
+    float* __restrict__ gbuf_e, int32_t* __restrict__ gbuf_i)
 {
-    if (*gate == 0) return;
+    if (gate && *gate == 0) return;
+    const int S = slices > 0 ? slices : 1;
     extern __shared__ __align__(16) char smem[];
     unsigned long long* keys = (unsigned long long*)smem;
     int* tpref = (int*)(smem + sizeof(unsigned long long) * kCapE);
@@ -1236,8 +1250,10 @@ __global__ __launch_bounds__(256) void exact_kernel(
     const int64_t tile_bytes = (int64_t)4 * dp * BITS;
     // every MFMA column is the query itself; LO: columns 16..31 its low plane (LDS row 2)
     const int8_t* qrow = qs + 16 * (lane >> 5) + ((LO && (lane & 31) >= 16) ? dp : 0);
-    for (int64_t q = blockIdx.x; q < nq; q += gridDim.x) {
-        if (!ovf[q]) continue;                   // the same for the whole block
+    for (int64_t w = blockIdx.x; w < nq * S; w += gridDim.x) {
+        const int64_t q = w / S;
+        const int sl = (int)(w - q * S);
+        if (ovf && !ovf[q]) continue;            // the same for the whole block
         __syncthreads();                         // LDS of the previous query is free
         for (int c = tid; c < dp / 16; c += 256) *(uint4*)(qs + 16 * c) = *(const uint4*)(qa.qint + q * dp + 16 * c);
         if constexpr (LO)
@@ -1271,11 +1287,14 @@ __global__ __launch_bounds__(256) void exact_kernel(
         if (tid == 0) { s_cnt = 0; s_T = ~0ull; }
         if (redo && npair) atomicAdd(redo, (int)npair);
         __syncthreads();
-        const int total = tpref[nprobe];
+        // the slice's share of the query's tiles (all probes, in probe order): an
+        // even split, whatever the list lengths
+        const int64_t all = tpref[nprobe];
+        const int g0 = (int)(all * sl / S), total = (int)(all * (sl + 1) / S);
         float h2, hc, h2l = 0.0f;
         if constexpr (LO) epi_consts2<BITS>(qa.qhd[q], qa.qss[q], qa.qss_lo[q], h2, h2l, hc);
         else epi_consts<BITS>(qa.qhd[q], qa.qss[q], h2, hc);
-        for (int base = 0; base < total; base += 4) {
+        for (int base = g0; base < total; base += 4) {
             const int g = base + wid;
             const unsigned long long T = s_T;
             if (g < total) {
@@ -1293,13 +1312,24 @@ __global__ __launch_bounds__(256) void exact_kernel(
                 v16i acc;
 #pragma unroll
                 for (int r = 0; r < 16; ++r) acc[r] = 0;
-                for (int kb = 0; kb < nkb; ++kb) {
-                    v4i a0, a1;
-                    load_codes<BITS>(tp + (int64_t)kb * 256 * BITS, lane, a0, a1);
-                    const v4i b0 = *(const v4i*)(qrow + 64 * kb);
-                    const v4i b1 = *(const v4i*)(qrow + 64 * kb + 32);
-                    acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, b0, acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, b1, acc, 0, 0, 0);
+                // the packed words of KC K-blocks are loaded together, then used
+                constexpr int KC = 8;
+                for (int kb0 = 0; kb0 < nkb; kb0 += KC) {
+                    uint32_t wd[KC][BITS];
+#pragma unroll
+                    for (int p = 0; p < KC; ++p)
+                        load_raw<BITS>(tp + (int64_t)min(kb0 + p, nkb - 1) * 256 * BITS, lane, wd[p]);
+#pragma unroll
+                    for (int p = 0; p < KC; ++p) {
+                        const int kb = kb0 + p;
+                        if (kb >= nkb) break;            // wave-uniform
+                        v4i a0, a1;
+                        unpack_raw<BITS>(wd[p], a0, a1);
+                        const v4i b0 = *(const v4i*)(qrow + 64 * kb);
+                        const v4i b1 = *(const v4i*)(qrow + 64 * kb + 32);
+                        acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, b0, acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, b1, acc, 0, 0, 0);
+                    }
                 }
                 // lane (h, j < 16) takes output row out_row(lane, j): the 32
                 // lanes cover the tile's 32 members once
@@ -1332,6 +1362,18 @@ __global__ __launch_bounds__(256) void exact_kernel(
         if (c > kk) {
             block_keep(keys, c, kk, hist, s_w, s_bc);
             m = kk;
+        }
+        if (slices > 0) {                        // this slice's top-kk appended to the query's buffer
+            __syncthreads();                     // every thread has read the count
+            if (tid == 0) s_cnt = m > 0 ? atomicAdd(&gcnt[q], m) : 0;
+            __syncthreads();
+            const int base = s_cnt;
+            for (int t = tid; t < m; t += 256) {
+                const unsigned long long k = keys[t];
+                gbuf_e[q * kCapQ + base + t] = key2f((unsigned)(k >> 32));
+                gbuf_i[q * kCapQ + base + t] = (int32_t)(unsigned)(k & 0xFFFFFFFFull);
+            }
+            continue;
         }
         // ascending bitonic sort of keys[0, m), padded to a power of two (<= kk rounded up)
         int S = 1;
@@ -1912,48 +1954,52 @@ hipError_t launch2(const Index* ix, const ScanArgs& a, const BArgs& b, hipStream
     }
 }
 
+// slices (> 0) and the buffers: the small-batch mode of exact_kernel
+struct ExactOut { int slices; int32_t* gcnt; float* gbuf_e; int32_t* gbuf_i; };
+
 template <int BITS, bool LO>
 hipError_t launch_exact_l(const Index* ix, const QArgs& qa, const int32_t* probes, int64_t nq, int nprobe, int kk,
                           const int32_t* ovf, const int32_t* gate, int32_t* redo, int64_t* oi, float* oe,
-                          hipStream_t st)
+                          const ExactOut& xo, hipStream_t st)
 {
     const size_t sm = sizeof(unsigned long long) * kCapE + sizeof(int) * ((nprobe + 4) & ~3) +
                       (size_t)ix->dc * (LO ? 2 : 1);
-    const unsigned grid = (unsigned)std::min<int64_t>(nq, 1024);
+    const unsigned grid = (unsigned)std::min<int64_t>(nq * std::max(xo.slices, 1), 4096);
     hipLaunchKernelGGL((exact_kernel<BITS, LO>), dim3(grid), dim3(256), sm, st, ix->codes, ix->tile_off,
                        ix->list_off, ix->sfac, ix->ids, ix->dc, qa, probes, nq, nprobe, (int)ix->nlist, kk, ovf, gate,
-                       redo, oi, oe);
+                       redo, oi, oe, xo.slices, xo.gcnt, xo.gbuf_e, xo.gbuf_i);
     return hipGetLastError();
 }
 
 template <int BITS>
 hipError_t launch_exact_b(const Index* ix, const QArgs& qa, const int32_t* probes, int64_t nq, int nprobe, int kk,
                           const int32_t* ovf, const int32_t* gate, int32_t* redo, int64_t* oi, float* oe,
-                          hipStream_t st)
+                          const ExactOut& xo, hipStream_t st)
 {
     if (ix->qplanes == 2) {
         if constexpr (BITS >= 5)
-            return launch_exact_l<BITS, true>(ix, qa, probes, nq, nprobe, kk, ovf, gate, redo, oi, oe, st);
+            return launch_exact_l<BITS, true>(ix, qa, probes, nq, nprobe, kk, ovf, gate, redo, oi, oe, xo, st);
         return hipErrorInvalidValue;
     }
-    return launch_exact_l<BITS, false>(ix, qa, probes, nq, nprobe, kk, ovf, gate, redo, oi, oe, st);
+    return launch_exact_l<BITS, false>(ix, qa, probes, nq, nprobe, kk, ovf, gate, redo, oi, oe, xo, st);
 }
 
 // exact fallback for the flagged queries (returns at once on the device when
 // the gate is 0)
 hipError_t launch_exact(const Index* ix, const QArgs& qa, const int32_t* probes, int64_t nq, int nprobe, int kk,
-                        const int32_t* ovf, const int32_t* gate, int32_t* redo, int64_t* oi, float* oe, hipStream_t st)
+                        const int32_t* ovf, const int32_t* gate, int32_t* redo, int64_t* oi, float* oe, hipStream_t st,
+                        const ExactOut& xo = ExactOut{0, nullptr, nullptr, nullptr})
 {
     if (nq <= 0) return hipSuccess;
     switch (ix->bits) {
-        case 1: return launch_exact_b<1>(ix, qa, probes, nq, nprobe, kk, ovf, gate, redo, oi, oe, st);
-        case 2: return launch_exact_b<2>(ix, qa, probes, nq, nprobe, kk, ovf, gate, redo, oi, oe, st);
-        case 3: return launch_exact_b<3>(ix, qa, probes, nq, nprobe, kk, ovf, gate, redo, oi, oe, st);
-        case 4: return launch_exact_b<4>(ix, qa, probes, nq, nprobe, kk, ovf, gate, redo, oi, oe, st);
-        case 5: return launch_exact_b<5>(ix, qa, probes, nq, nprobe, kk, ovf, gate, redo, oi, oe, st);
-        case 6: return launch_exact_b<6>(ix, qa, probes, nq, nprobe, kk, ovf, gate, redo, oi, oe, st);
-        case 7: return launch_exact_b<7>(ix, qa, probes, nq, nprobe, kk, ovf, gate, redo, oi, oe, st);
-        default: return launch_exact_b<8>(ix, qa, probes, nq, nprobe, kk, ovf, gate, redo, oi, oe, st);
+        case 1: return launch_exact_b<1>(ix, qa, probes, nq, nprobe, kk, ovf, gate, redo, oi, oe, xo, st);
+        case 2: return launch_exact_b<2>(ix, qa, probes, nq, nprobe, kk, ovf, gate, redo, oi, oe, xo, st);
+        case 3: return launch_exact_b<3>(ix, qa, probes, nq, nprobe, kk, ovf, gate, redo, oi, oe, xo, st);
+        case 4: return launch_exact_b<4>(ix, qa, probes, nq, nprobe, kk, ovf, gate, redo, oi, oe, xo, st);
+        case 5: return launch_exact_b<5>(ix, qa, probes, nq, nprobe, kk, ovf, gate, redo, oi, oe, xo, st);
+        case 6: return launch_exact_b<6>(ix, qa, probes, nq, nprobe, kk, ovf, gate, redo, oi, oe, xo, st);
+        case 7: return launch_exact_b<7>(ix, qa, probes, nq, nprobe, kk, ovf, gate, redo, oi, oe, xo, st);
+        default: return launch_exact_b<8>(ix, qa, probes, nq, nprobe, kk, ovf, gate, redo, oi, oe, xo, st);
     }
 }
 
@@ -2146,6 +2192,28 @@ int run_scan(Index* ix, const float* qrot, int64_t qld, int64_t nq, const int32_
     }
     const QArgs qa{qint, qhd, qss, sdist, ip ? -__builtin_huge_valf() : 0.0f, lo ? qlo : nullptr,
                    lo ? qss_lo : nullptr};
+    // Small batches (at most ix->small_q queries): the pair-grouped pipeline
+    // (first bound, rounds, selects; about 35 launches) is set by its launch
+    // count, not by work.  Each query's probed lists are instead split over S
+    // workgroups that keep exact top-kk lists (exact_kernel, slice mode), and
+    // one final select merges them: the same exact top-kk by (est, id).
+    const int small_s = std::min(std::min(nprobe, kSmallS), std::max(1, kCapQ / kk));
+    if (nq <= ix->small_q) {
+        const int pc = prof_begin(PK_SCAN_C, st);
+        zero(gcnt, nq);
+        hipError_t e = launch_exact(ix, qa, probes, nq, nprobe, kk, nullptr, nullptr, nullptr, nullptr, nullptr, st,
+                                    ExactOut{small_s, gcnt, gbe, gbi});
+        if (e == hipSuccess) {
+            const size_t sel_lds0 = (size_t)kSelQ * sel_slots(kk) * (sizeof(float) + sizeof(int));
+            hipLaunchKernelGGL(buf_select_kernel, dim3((unsigned)((nq + kSelQ - 1) / kSelQ)), dim3(256), sel_lds0, st,
+                               gcnt, gprev, gbe, gbi, nq, kk, 1, 0, tkey, ovf, out_ids, out_est, anyf2);
+            e = hipGetLastError();
+        }
+        prof_end(pc, st);
+        prof_end(pr, st);
+        if (e != hipSuccess) return fail(ERQ_EDEVICE, std::string("scan launch: ") + hipGetErrorString(e));
+        return ERQ_OK;
+    }
     const int64_t gridB = 1 << 20;                    // capped at the resident blocks
     // a pass-B launch over the pairs of probe ranks [rlo, rhi) (of flagged
     // queries with qmask); dense = the first-bound mode

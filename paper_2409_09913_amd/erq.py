@@ -33,6 +33,7 @@ SIGNATURES = {
     "erq_index_set_projection": (C.c_int, [_p, _i32, _p]),
     "erq_index_set_two_stage": (C.c_int, [_p, C.c_float]),
     "erq_index_set_query_planes": (C.c_int, [_p, _i32]),
+    "erq_index_set_small_batch": (C.c_int, [_p, _i32]),
     "erq_index_code_dim": (C.c_int, [_p, C.POINTER(_i32)]),
     "erq_index_get_rotation": (C.c_int, [_p, _p, _p]),
     "erq_index_save": (C.c_int, [_p, C.c_char_p, _p]),
@@ -208,6 +209,11 @@ class Index:
         """1: one int8 query plane; 2: a second plane of the rounding remainder
         (B >= 5), 254 times smaller query error at twice the matrix-core work."""
         _check(load().erq_index_set_query_planes(self.h, planes))
+
+    def set_small_batch(self, max_queries: int):
+        """Batches of at most max_queries queries take the scan's small-batch
+        path (0 = never; default 32)."""
+        _check(load().erq_index_set_small_batch(self.h, max_queries))
 
     def code_dim(self) -> int:
         dc = C.c_int32()

@@ -210,17 +210,19 @@ def test_scan_edge_cases():
     assert (gi == -1).any()
 
 
+@pytest.mark.parametrize("small", [False, True], ids=["pipeline", "small-batch"])
 @pytest.mark.parametrize("kk,sizes", [(16, (300, 500, 40)), (32, (300, 500, 40)), (100, (300, 500, 40)),
                                       (10, (9000, 5000, 40)), (32, (9000, 5000, 40)), (100, (9000, 5000, 40)),
                                       (1000, (9000, 5000, 40))])
-def test_scan_exact_ties_by_id(kk, sizes):
+def test_scan_exact_ties_by_id(kk, sizes, small):
     """Every member of a list is a copy of one code row with the same factors,
     so all its estimates tie exactly (in FP32 and FP64): the top-kk must take
     the smallest ids of a tied group, in id order (reading C-16).  With lists
     of 9000 and 5000 tied members no bound can shrink a query's candidates
     below its buffer's 4096 entries, so the exact fallback runs (its pair
-    count is read back)."""
-    say("scan exact ties kk", kk, "sizes", sizes)
+    count is read back).  The small-batch path (12 queries) must give the
+    same ids."""
+    say("scan exact ties kk", kk, "sizes", sizes, "small", small)
     dp, B, nl = 64, 4, 3
     sizes = np.array(sizes)
     off, ids, codes, fa, fr, crot = synth.random_index(int(sizes.sum()), nl, dp, B, seed=40 + kk, sizes=sizes)
@@ -234,6 +236,7 @@ def test_scan_exact_ties_by_id(kk, sizes):
     P = synth.haar_orthogonal(dp, seed=2).astype(np.float32)
     ix = erq.Index(dp, B, nl, dev(P))
     ix.import_(dev(off), dev(ids), dev(codes), dev(fa), dev(fr), dev(np.zeros((nl, dp), np.float32)), dev(crot))
+    ix.set_small_batch(32 if small else 0)
     erq.profile_enable(2)
     erq.profile_read("scan_redo_pairs", reset=True)
     try:
@@ -251,7 +254,7 @@ def test_scan_exact_ties_by_id(kk, sizes):
     # the fallback must have run when some query has more than 4096
     # candidates at or below its kk-th estimate (a tied group no bound splits)
     _, all_e = oracle.search(off, ids, codes, fa, fr, crot, qrot, probes, B, int(sizes.sum()), est_mode=0)
-    if any((all_e[i] <= oe[i][min(kk, int(sizes.sum())) - 1]).sum() > 4096 for i in range(len(qrot))):
+    if not small and any((all_e[i] <= oe[i][min(kk, int(sizes.sum())) - 1]).sum() > 4096 for i in range(len(qrot))):
         assert redo > 0
     ix.close()
 
@@ -438,4 +441,35 @@ def test_end_to_end_tiny():
     say("  recall@10 no rerank", r0, "rerank32", r1)
     assert r0 > 0.55 and r1 > 0.93
     np.testing.assert_allclose(d1.cpu().numpy()[:, 0], td[:, 0], rtol=1e-4)
+    ix.close()
+
+
+@pytest.mark.parametrize("B,planes,nq,kk,nprobe", [(4, 1, 1, 10, 8), (4, 1, 7, 100, 12), (4, 1, 32, 1, 5),
+                                                   (3, 1, 20, 1024, 9), (8, 2, 13, 10, 8), (6, 2, 32, 64, 3),
+                                                   (1, 1, 5, 10, 4)])
+def test_small_batch_path_identical(B, planes, nq, kk, nprobe):
+    """The small-batch path (exact per-query top-kk over probe slices, one
+    merge) and the pair-grouped pipeline return the same ids and the same
+    FP32 estimates bit for bit, on Zipf lists with ragged tails and queries
+    that probe fewer lists; both match the oracle."""
+    say("small batch path B", B, "planes", planes, "nq", nq, "kk", kk)
+    dp, nl = 192, 16
+    sizes = synth.zipf_list_sizes(9000, nl, lo=1, seed=90 + B)
+    off, ids, codes, fa, fr, crot = synth.random_index(int(sizes.sum()), nl, dp, B, seed=91 + B, sizes=sizes)
+    qrot = synth.random_rotated(nq, dp, seed=92 + B)
+    probes = synth.random_probes(nq, nl, nprobe, seed=93 + B)
+    probes[: nq // 3, nprobe // 2:] = -1
+    P = synth.haar_orthogonal(dp, seed=2).astype(np.float32)
+    ix = erq.Index(dp, B, nl, dev(P))
+    ix.import_(dev(off), dev(ids), dev(codes), dev(fa), dev(fr), dev(np.zeros((nl, dp), np.float32)), dev(crot))
+    if planes == 2:
+        ix.set_query_planes(2)
+    ix.set_small_batch(0)
+    a_i, a_e = [t.cpu().numpy() for t in ix.scan(dev(qrot), dev(probes), kk)]
+    ix.set_small_batch(32)
+    b_i, b_e = [t.cpu().numpy() for t in ix.scan(dev(qrot), dev(probes), kk)]
+    np.testing.assert_array_equal(a_i, b_i)
+    np.testing.assert_array_equal(a_e.view(np.uint32), b_e.view(np.uint32))
+    oi, oe = oracle.search(off, ids, codes, fa, fr, crot, qrot, probes, B, kk, est_mode=3 if planes == 2 else 0)
+    _compare_topk(b_i, b_e, oi, oe, CandTerms(off, ids, codes, fa, fr, crot, qrot, probes, B))
     ix.close()

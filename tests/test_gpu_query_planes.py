@@ -82,6 +82,7 @@ def test_two_plane_exact_fallback_ties(kk):
     ix = erq.Index(dp, B, nl, dev(P))
     ix.import_(dev(off), dev(ids), dev(codes), dev(fa), dev(fr), dev(np.zeros((nl, dp), np.float32)), dev(crot))
     ix.set_query_planes(2)
+    ix.set_small_batch(0)                                  # the pair-grouped pipeline and its fallback
     erq.profile_enable(2)
     erq.profile_read("scan_redo_pairs", reset=True)
     try:

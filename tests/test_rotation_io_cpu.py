@@ -61,9 +61,9 @@ def test_load_rejects_bad_files(tmp_path):
     assert lib.erq_index_load(os.fsencode(str(p)), None, C.byref(h)) == erq.ERQ_EINVAL
     # a well-formed header of version 1 whose arrays are missing: size mismatch
     # (version, dp, bits, has_raw, metric, code dimension), (nlist, n, tiles), schedule, seed
-    # ..., schedule, seed, (two-stage flag, eps0), (query planes, reserved)
+    # ..., schedule, seed, (two-stage flag, eps0), (query planes, small-batch threshold)
     hdr = b"ERQIDX\0\0" + struct.pack("<Iiiiii", 2, 64, 4, 0, 0, 64) + struct.pack("<qqq", 2, 10, 2) + \
-        struct.pack("<iiii", 0, 0, 0, 0) + struct.pack("<Q", 0) + struct.pack("<if", 0, 0.0) + struct.pack("<ii", 1, 0)
+        struct.pack("<iiii", 0, 0, 0, 0) + struct.pack("<Q", 0) + struct.pack("<if", 0, 0.0) + struct.pack("<ii", 1, 32)
     p2 = tmp_path / "short.idx"
     p2.write_bytes(hdr)
     assert lib.erq_index_load(os.fsencode(str(p2)), None, C.byref(h)) == erq.ERQ_EINVAL
@@ -75,7 +75,7 @@ def test_load_rejects_bad_files(tmp_path):
         assert b"bad header" in lib.erq_last_error()
     for planes in (0, 3, 2):            # bad query planes; 2 with B = 4
         pb = tmp_path / "qp.idx"
-        pb.write_bytes(hdr[:88] + struct.pack("<ii", planes, 0))
+        pb.write_bytes(hdr[:88] + struct.pack("<ii", planes, 32))
         assert lib.erq_index_load(os.fsencode(str(pb)), None, C.byref(h)) == erq.ERQ_EINVAL
         assert b"bad header" in lib.erq_last_error()
     for dc in (0, 32, 96, 128):        # code dimension not a multiple of 64 in [64, dp]
