@@ -480,6 +480,7 @@ def run_batching(args):
         torch.cuda.synchronize()
         enc = n / (time.perf_counter() - ts)
         ix.set_raw(x)
+        small_default = ix.small_batch()
         tuned = ix.tune(q, 128, k, 2 * k, reps=2)
         rows = []
         for rr in (0, 2 * k):
@@ -487,10 +488,11 @@ def run_batching(args):
             rec = recall_at(ids.cpu().numpy(), truth, k)
             for bs in (1, 4, 16, 32, 64, 256, 1024, 4096):
                 row = {"rerank_k": rr, "batch": bs, "recall@10_full_batch": rec}
-                # batches of at most 32 queries take the small-batch scan path; the
-                # pair-grouped pipeline is timed beside it
-                for label, sq in (("", 32), ("_pipeline", 0)) if bs <= 32 else (("", 32),):
-                    ix.set_small_batch(sq)
+                # the index's default path, then (up to the small path's limit of 1024
+                # queries) the small-batch path and the pair-grouped pipeline forced
+                paths = (("", None), ("_small", 1024), ("_pipeline", 0)) if bs <= 1024 else (("", None),)
+                for label, sq in paths:
+                    ix.set_small_batch(small_default if sq is None else sq)
                     gph = serve.SearchGraph(ix, bs, 256, k, rr, per_query=True)
                     gph.q.copy_(q[:bs])
                     gph.params[0].copy_(npq[:bs])
@@ -507,7 +509,7 @@ def run_batching(args):
                     row["qps" + label] = bs / dt
                     row["ms_per_batch" + label] = dt * 1e3
                     del gph
-                ix.set_small_batch(32)
+                ix.set_small_batch(small_default)
                 rows.append(row)
             log("batching B=%d rerank %d recall@10 %.4f; QPS by batch %s; pipeline path at small batches %s" %
                 (B, rr, rec, {r["batch"]: round(r["qps"]) for r in rows if r["rerank_k"] == rr},
@@ -574,6 +576,7 @@ def run_two_stage(args):
             torch.cuda.synchronize()
             return o[0].cpu().numpy(), nq_b * reps / (time.perf_counter() - ts)
 
+        ix.set_small_batch(0)                          # the two-stage scan lives in the pair-grouped pipeline
         for eps in eps_list:
             ix.set_two_stage(eps)
             rows = []
@@ -671,7 +674,7 @@ def run_serving(args):
     sweep = []
     # isotropic clusters in 3072 dimensions: a query's neighbours spread over all the lists k-means cut its
     # cluster into (up to a few thousand for the Zipf-heavy clusters), so the recall target needs a wide probe
-    for kq, rrs in ((10, (0, 20, 50)), (100, (0, 200))):
+    for kq, rrs in ((10, (0, 50, 200, 1000)), (100, (0, 200, 1000))):
         for npr in (16, 64, 128, 256, 512, 1024):
             for rr in rrs:
                 ids, _ = ix.search(q, npr, kq, rr)

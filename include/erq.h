@@ -177,15 +177,20 @@ int erq_index_set_two_stage(erq_index idx, float eps0);
    the codes do not change; saved with the index. */
 int erq_index_set_query_planes(erq_index idx, int32_t planes);
 
-/* Batches of at most max_queries queries (default 32; 0 = never) take the
-   scan's small-batch path: each query's probed lists are split over up to
-   64 workgroups that keep exact top-kk lists, merged by one final select,
-   instead of the pair-grouped pipeline of large batches (first bound, rounds
-   of bounded scans, selects: about 35 launches).  Both give the exact top-kk
-   by (estimate, id); the small path reads each probed list once per query
-   rather than once per tile of its queries, so it suits batches whose
-   queries share few lists.  max_queries in [0, 1024]; saved with the index. */
+/* Batches of at most max_queries queries (default 128; 0 = never) take the
+   scan's small-batch path: the member tiles of each query's probed lists
+   are split evenly over up to 64 workgroups that keep exact top-kk lists,
+   merged by one final select, instead of the pair-grouped pipeline of large
+   batches (first bound, rounds of bounded scans, selects: about 35
+   launches).  Both give the exact top-kk by (estimate, id), bit for bit the
+   same; the small path reads each probed list once per query rather than
+   once per tile of its queries, so it suits batches whose queries share few
+   lists.  It always scans in one stage (a two-stage setting applies to the
+   pipeline only).  max_queries in [0, 1024]; saved with the index. */
 int erq_index_set_small_batch(erq_index idx, int32_t max_queries);
+
+/* The index's current small-batch threshold (see erq_index_set_small_batch). */
+int erq_index_small_batch(erq_index idx, int32_t* max_queries);
 
 /* The code dimension dc (dp without a projection). */
 int erq_index_code_dim(erq_index idx, int32_t* dc);

@@ -710,6 +710,13 @@ int erq_index_set_small_batch(erq_index ix, int32_t max_queries)
     return ERQ_OK;
 }
 
+int erq_index_small_batch(erq_index ix, int32_t* max_queries)
+{
+    if (!ix || !max_queries) return fail(ERQ_EINVAL, "erq_index_small_batch: null pointer");
+    *max_queries = ix->small_q;
+    return ERQ_OK;
+}
+
 int erq_index_code_dim(erq_index ix, int32_t* dc)
 {
     if (!ix || !dc) return fail(ERQ_EINVAL, "erq_index_code_dim: null pointer");

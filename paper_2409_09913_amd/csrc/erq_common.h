@@ -88,7 +88,7 @@ struct Index {
     // two-stage scan (Sec. 4.2): requested before the build; its data are the
     // most significant bit planes (ntiles * 4 * dc bytes, the 1-bit tile
     // layout) and the 1-bit factors (g1, f1, e1, 0) per member
-    int small_q = 32;              // batches of at most this many queries take the scan's small-batch path
+    int small_q = 128;             // batches of at most this many queries take the scan's small-batch path
     int qplanes = 1;               // int8 query planes of the scan: 1, or 2 (q' ~ delta (q_hi + q_lo / 254), B >= 5)
     int two_stage = 0;
     float eps0 = 0.0f;             // > 0: the scan prunes with the 1-bit bound at this eps0

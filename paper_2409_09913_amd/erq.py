@@ -34,6 +34,7 @@ SIGNATURES = {
     "erq_index_set_two_stage": (C.c_int, [_p, C.c_float]),
     "erq_index_set_query_planes": (C.c_int, [_p, _i32]),
     "erq_index_set_small_batch": (C.c_int, [_p, _i32]),
+    "erq_index_small_batch": (C.c_int, [_p, C.POINTER(_i32)]),
     "erq_index_code_dim": (C.c_int, [_p, C.POINTER(_i32)]),
     "erq_index_get_rotation": (C.c_int, [_p, _p, _p]),
     "erq_index_save": (C.c_int, [_p, C.c_char_p, _p]),
@@ -212,8 +213,14 @@ class Index:
 
     def set_small_batch(self, max_queries: int):
         """Batches of at most max_queries queries take the scan's small-batch
-        path (0 = never; default 32)."""
+        path (0 = never; default 128)."""
         _check(load().erq_index_set_small_batch(self.h, max_queries))
+
+    def small_batch(self) -> int:
+        """The current small-batch threshold."""
+        v = C.c_int32()
+        _check(load().erq_index_small_batch(self.h, C.byref(v)))
+        return v.value
 
     def code_dim(self) -> int:
         dc = C.c_int32()

@@ -63,3 +63,22 @@ def compare_topk(gi, ge, oi, oe, terms, rel=1e-4):
                 val = gmap[i] if i in gmap else omap[i]
                 tol = rel * terms(q, i) + t_kth
                 assert abs(val - kth) <= tol, (q, i, val, kth, tol)
+
+
+def both_paths(ix, run):
+    """Runs `run()` (returning numpy (ids, estimates or distances)) once on the
+    scan's pair-grouped pipeline and once on its small-batch path, asserts the
+    two results are bit-identical, restores the index's threshold and returns
+    the pipeline's result."""
+    keep = ix.small_batch()
+    try:
+        ix.set_small_batch(0)
+        a_i, a_e = run()
+        ix.set_small_batch(1024)
+        b_i, b_e = run()
+    finally:
+        ix.set_small_batch(keep)
+    np.testing.assert_array_equal(a_i, b_i, err_msg="small-batch path: ids differ from the pipeline's")
+    np.testing.assert_array_equal(np.asarray(a_e).view(np.uint32), np.asarray(b_e).view(np.uint32),
+                                  err_msg="small-batch path: values differ from the pipeline's")
+    return a_i, a_e

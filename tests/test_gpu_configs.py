@@ -30,7 +30,7 @@ import torch
 
 import oracle
 from paper_2409_09913_amd import erq, serve, synth
-from parity_util import CandTerms, compare_topk
+from parity_util import CandTerms, both_paths, compare_topk
 
 pytestmark = pytest.mark.gpu
 
@@ -161,10 +161,8 @@ def test_d3072_scan_and_serving():
     qrot = synth.random_rotated(40, dp, seed=951)
     probes = synth.random_probes(40, 24, 16, seed=952)
     ix = _import(off, ids, codes, fa, fr, crot, dp, B)
-    gi, ge = ix.scan(dev(qrot), dev(probes), 10)
-    torch.cuda.synchronize()
-    _check_sample(gi.cpu().numpy(), ge.cpu().numpy(), off, ids, codes, fa, fr, crot, qrot, probes, B, 10,
-                  np.arange(40))
+    gi, ge = both_paths(ix, lambda: [t.cpu().numpy() for t in ix.scan(dev(qrot), dev(probes), 10)])
+    _check_sample(gi, ge, off, ids, codes, fa, fr, crot, qrot, probes, B, 10, np.arange(40))
     ix.close()
     say("d3072 scan parity ok; serving")
     n, nl = 12000, 64
@@ -197,6 +195,7 @@ def test_scan_schedules_identical_results(B):
     qrot = synth.random_rotated(150, dp, seed=961)
     probes = synth.random_probes(150, nl, 24, seed=962)
     ix = _import(off, ids, codes, fa, fr, crot, dp, B)
+    ix.set_small_batch(0)                                # schedules of the pair-grouped pipeline
     ri, re = ix.scan(dev(qrot), dev(probes), kk)
     ri, re = ri.cpu().numpy(), re.cpu().numpy()
     pds = [p for p in (1, 2, 3, 4, 6) if (dp // 64) % p == 0 and (p != 6 or B <= 4)]

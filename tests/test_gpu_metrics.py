@@ -20,7 +20,7 @@ import torch
 
 import oracle
 from paper_2409_09913_amd import erq, synth
-from parity_util import CandTerms, compare_topk
+from parity_util import CandTerms, both_paths, compare_topk
 
 pytestmark = pytest.mark.gpu
 
@@ -49,9 +49,7 @@ def test_ip_scan_parity(B, kk):
     P = synth.haar_orthogonal(dp, seed=2).astype(np.float32)
     ix = erq.Index(dp, B, nl, dev(P), metric="ip")
     ix.import_(dev(off), dev(ids), dev(codes), dev(fa), dev(fr), dev(np.zeros((nl, dp), np.float32)), dev(crot))
-    gi, ge = ix.scan(dev(qrot), dev(probes), kk)
-    torch.cuda.synchronize()
-    gi, ge = gi.cpu().numpy(), ge.cpu().numpy()
+    gi, ge = both_paths(ix, lambda: [t.cpu().numpy() for t in ix.scan(dev(qrot), dev(probes), kk)])
     oi, oe = oracle.search_ip(off, ids, codes, fa, fr, crot, qrot, probes, B, kk, est_mode=0)
     compare_topk(gi, ge, oi, oe, CandTerms(off, ids, codes, fa, fr, crot, qrot, probes, B, metric="ip"))
     ix.close()
@@ -80,8 +78,7 @@ def built_ip():
 def test_ip_search_elementwise(built_ip):
     b = built_ip
     nprobe, k = 12, 20
-    gi, ge = b["ix"].search(b["qd"], nprobe, k, 0)
-    gi, ge = gi.cpu().numpy(), ge.cpu().numpy()
+    gi, ge = both_paths(b["ix"], lambda: [t.cpu().numpy() for t in b["ix"].search(b["qd"], nprobe, k, 0)])
     probes = erq.coarse_probe(b["qd"], dev(b["cent"]), nprobe, metric="ip").cpu().numpy()
     # the probe lists are the largest inner products with the centroids (up to near-ties)
     op, od = oracle.probe_ip(b["q"], b["cent"], nprobe)

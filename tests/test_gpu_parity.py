@@ -15,7 +15,7 @@ import torch
 
 import oracle
 from paper_2409_09913_amd import erq, synth
-from parity_util import CandTerms, compare_topk as _compare_topk
+from parity_util import CandTerms, both_paths, compare_topk as _compare_topk
 
 pytestmark = pytest.mark.gpu
 
@@ -157,9 +157,9 @@ def _scan_case(n, nl, dp, B, nq, nprobe, kk, seed, sizes=None, empty_lists=0, pa
     P = synth.haar_orthogonal(dp, seed=2).astype(np.float32)
     ix = erq.Index(dp, B, nl, dev(P))
     ix.import_(dev(off), dev(ids), dev(codes), dev(fa), dev(fr), dev(np.zeros((nl, dp), np.float32)), dev(crot))
-    gi, ge = ix.scan(dev(qrot), dev(probes), kk)
-    torch.cuda.synchronize()
-    gi, ge = gi.cpu().numpy(), ge.cpu().numpy()
+    # the pipeline and (up to 1024 queries) the small-batch path, bit-identical
+    run = lambda: [t.cpu().numpy() for t in ix.scan(dev(qrot), dev(probes), kk)]
+    gi, ge = both_paths(ix, run) if nq <= 1024 else run()
     oi, oe = oracle.search(off, ids, codes, fa, fr, crot, qrot, probes, B, kk, est_mode=0)
     _compare_topk(gi, ge, oi, oe, CandTerms(off, ids, codes, fa, fr, crot, qrot, probes, B))
     ix.close()
@@ -446,7 +446,7 @@ def test_end_to_end_tiny():
 
 @pytest.mark.parametrize("B,planes,nq,kk,nprobe", [(4, 1, 1, 10, 8), (4, 1, 7, 100, 12), (4, 1, 32, 1, 5),
                                                    (3, 1, 20, 1024, 9), (8, 2, 13, 10, 8), (6, 2, 32, 64, 3),
-                                                   (1, 1, 5, 10, 4)])
+                                                   (1, 1, 5, 10, 4), (4, 1, 300, 10, 16), (5, 2, 1024, 100, 6)])
 def test_small_batch_path_identical(B, planes, nq, kk, nprobe):
     """The small-batch path (exact per-query top-kk over probe slices, one
     merge) and the pair-grouped pipeline return the same ids and the same
@@ -466,7 +466,8 @@ def test_small_batch_path_identical(B, planes, nq, kk, nprobe):
         ix.set_query_planes(2)
     ix.set_small_batch(0)
     a_i, a_e = [t.cpu().numpy() for t in ix.scan(dev(qrot), dev(probes), kk)]
-    ix.set_small_batch(32)
+    ix.set_small_batch(max(nq, 32))
+    assert ix.small_batch() == max(nq, 32)
     b_i, b_e = [t.cpu().numpy() for t in ix.scan(dev(qrot), dev(probes), kk)]
     np.testing.assert_array_equal(a_i, b_i)
     np.testing.assert_array_equal(a_e.view(np.uint32), b_e.view(np.uint32))

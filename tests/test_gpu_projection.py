@@ -22,7 +22,7 @@ import torch
 
 import oracle
 from paper_2409_09913_amd import erq, synth
-from parity_util import CandTerms, compare_topk
+from parity_util import CandTerms, both_paths, compare_topk
 
 pytestmark = pytest.mark.gpu
 
@@ -95,8 +95,8 @@ def test_projection_scan_matches_oracle(built, nprobe, kk):
     b = built
     qrot = erq.rotate(dev(b["q"]), dev(b["P"]), precision=0)      # full width: ||s'||^2 over every dp
     probes = oracle.probe(b["q"], b["cent"], nprobe)[0].astype(np.int32)
-    gi, ge = b["ix"].scan(qrot, dev(probes), kk)
-    gi, ge, qr = gi.cpu().numpy(), ge.cpu().numpy(), qrot.cpu().numpy()
+    gi, ge = both_paths(b["ix"], lambda: [t.cpu().numpy() for t in b["ix"].scan(qrot, dev(probes), kk)])
+    qr = qrot.cpu().numpy()
     oi, oe = oracle.search(b["off"], b["ids"], b["codes"], b["fa"], b["fr"], b["crot"], qr, probes, b["B"], kk,
                            est_mode=0)
     compare_topk(gi, ge, oi, oe, CandTerms(b["off"], b["ids"], b["codes"], b["fa"], b["fr"], b["crot"], qr,
@@ -107,8 +107,7 @@ def test_projection_scan_matches_oracle(built, nprobe, kk):
 def test_projection_search_matches_oracle(built, nprobe, k):
     b = built
     qd = dev(b["q"])
-    gi, ge = b["ix"].search(qd, nprobe, k, 0)
-    gi, ge = gi.cpu().numpy(), ge.cpu().numpy()
+    gi, ge = both_paths(b["ix"], lambda: [t.cpu().numpy() for t in b["ix"].search(qd, nprobe, k, 0)])
     probes = erq.coarse_probe(qd, dev(b["cent"]), nprobe).cpu().numpy()     # the search's probes
     qrot = erq.rotate(qd, dev(b["P"]), precision=2).cpu().numpy()           # its first dc columns: the search's
     oi, oe = oracle.search(b["off"], b["ids"], b["codes"], b["fa"], b["fr"], b["crot"], qrot, probes, b["B"], k,

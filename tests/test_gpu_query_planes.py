@@ -2,7 +2,8 @@
 the device against the oracle's two-plane scan (est_mode 3).
 
 * Scan parity on imported random indexes, B = 5..8, dp 128 and 768, kk up to
-  1024, per candidate at the tolerance of reading C-15.
+  1024, per candidate at the tolerance of reading C-15; the pair-grouped
+  pipeline and the small-batch path bit-identical.
 * The exact fallback with two planes: lists of tied estimates too long for
   any bound, ids in the oracle's order.
 * erq_search on a device-built B = 8 index element by element against the
@@ -18,7 +19,7 @@ import torch
 
 import oracle
 from paper_2409_09913_amd import erq, synth
-from parity_util import CandTerms, compare_topk
+from parity_util import CandTerms, both_paths, compare_topk
 
 pytestmark = pytest.mark.gpu
 
@@ -55,8 +56,7 @@ def test_two_plane_scan_parity(B, dp, kk):
     qrot = synth.random_rotated(nq, dp, seed=701 + B)
     probes = synth.random_probes(nq, nl, nprobe, seed=702 + B)
     probes[:5, nprobe // 2:] = -1                         # some queries probe fewer lists
-    gi, ge = ix.scan(dev(qrot), dev(probes), kk)
-    gi, ge = gi.cpu().numpy(), ge.cpu().numpy()
+    gi, ge = both_paths(ix, lambda: [t.cpu().numpy() for t in ix.scan(dev(qrot), dev(probes), kk)])
     oi, oe = oracle.search(off, ids, codes, fa, fr, crot, qrot, probes, B, kk, est_mode=3)
     compare_topk(gi, ge, oi, oe, CandTerms(off, ids, codes, fa, fr, crot, qrot, probes, B))
     ix.close()
@@ -125,8 +125,7 @@ def test_two_plane_search_elementwise(built8, nprobe, k):
     b = built8
     ix = b["ix"]
     ix.set_query_planes(2)
-    gi, ge = ix.search(b["qd"], nprobe, k, 0)
-    gi, ge = gi.cpu().numpy(), ge.cpu().numpy()
+    gi, ge = both_paths(ix, lambda: [t.cpu().numpy() for t in ix.search(b["qd"], nprobe, k, 0)])
     probes = erq.coarse_probe(b["qd"], dev(b["cent"]), nprobe).cpu().numpy()
     args = (b["off"], b["ids"], b["codes"], b["fa"], b["fr"], b["crot"], b["qrot"], probes, 8)
     oi, oe = oracle.search(*args, k, est_mode=3)

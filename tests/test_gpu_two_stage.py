@@ -51,9 +51,11 @@ def built(request):
     cent = x[:nl].copy()
     assign = oracle.probe(x, cent, 1)[0][:, 0].astype(np.int32)
     ix = erq.Index(d, B, nl, dev(P))
+    ix.set_small_batch(0)                                # the two-stage scan runs in the pair-grouped pipeline
     ix.set_two_stage(8.0)
     ix.build(dev(x), dev(cent), dev(assign), precision=0, keep_raw=True)
     iy = erq.Index(d, B, nl, dev(P))                     # the same index without the 1-bit data
+    iy.set_small_batch(0)
     iy.build(dev(x), dev(cent), dev(assign), precision=0, keep_raw=True)
     torch.cuda.synchronize()
     off, ids, codes, fa, fr, _ = [t.cpu().numpy() for t in ix.export()]
