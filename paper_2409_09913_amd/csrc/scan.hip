@@ -31,6 +31,7 @@
 //  5. fallback: a query whose buffer still overflowed is scanned again in
 //     full by one workgroup that keeps its exact top-kk in LDS.
 #include <algorithm>
+#include <type_traits>
 
 #include "erq_common.h"
 
@@ -423,40 +424,59 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
         };
 #pragma unroll
         for (int p = 0; p < PD; ++p) load_step(ring[p]);
-        v16i acc[2][NQT];
-        int gi = 0, kb0 = 0;
-        for (int st0 = 0; st0 < total; st0 += PD) {
-            if (kb0 == 0) {
+        // query fragments of K-block kb (they do not depend on the group):
+        // those of the next K-block are read from LDS while this one's MFMAs run
+        auto read_b = [&](int kb, v4i (&b)[NQT][2]) {
 #pragma unroll
-                for (int a = 0; a < 2; ++a)
-#pragma unroll
-                    for (int qt = 0; qt < NQT; ++qt)
-#pragma unroll
-                        for (int r = 0; r < 16; ++r) acc[a][qt][r] = 0;
+            for (int qt = 0; qt < NQT; ++qt) {
+                b[qt][0] = *(const v4i*)(qrow + qt * kQT * qstride + 64 * kb);
+                b[qt][1] = *(const v4i*)(qrow + qt * kQT * qstride + 64 * kb + 32);
             }
-            const int gt0 = ta + 2 * gi;                // first tile of the current group
-            const bool two = gt0 + 1 < tb;              // wave-uniform
+        };
+        v4i bq[NQT][2];
+        read_b(0, bq);
+        v16i acc[2][NQT];
+        // the nkb K-steps of one group, for a group of two tiles or of one
+        // (the width is a compile-time constant of each loop body)
+        auto run_group = [&](auto two_c) {
+            constexpr bool TWO = decltype(two_c)::value;
 #pragma unroll
-            for (int p = 0; p < PD; ++p) {
-                v4i a00, a01, a10, a11;
-                unpack_raw<BITS>(ring[p], a00, a01);
-                if (two) unpack_raw<BITS>(ring[p] + BITS, a10, a11);
-                load_step(ring[p]);
-                const int kb = kb0 + p;
+            for (int a = 0; a < (TWO ? 2 : 1); ++a)
 #pragma unroll
-                for (int qt = 0; qt < NQT; ++qt) {
-                    const v4i b0 = *(const v4i*)(qrow + qt * kQT * qstride + 64 * kb);
-                    const v4i b1 = *(const v4i*)(qrow + qt * kQT * qstride + 64 * kb + 32);
-                    acc[0][qt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a00, b0, acc[0][qt], 0, 0, 0);
-                    if (two) acc[1][qt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a10, b0, acc[1][qt], 0, 0, 0);
-                    acc[0][qt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a01, b1, acc[0][qt], 0, 0, 0);
-                    if (two) acc[1][qt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a11, b1, acc[1][qt], 0, 0, 0);
+                for (int qt = 0; qt < NQT; ++qt)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) acc[a][qt][r] = 0;
+            for (int kb0 = 0; kb0 < nkb; kb0 += PD) {
+#pragma unroll
+                for (int p = 0; p < PD; ++p) {
+                    v4i a00, a01, a10, a11;
+                    unpack_raw<BITS>(ring[p], a00, a01);
+                    if constexpr (TWO) unpack_raw<BITS>(ring[p] + BITS, a10, a11);
+                    load_step(ring[p]);
+                    const int kb = kb0 + p;
+                    v4i bn[NQT][2];
+                    read_b(kb + 1 < nkb ? kb + 1 : 0, bn);
+#pragma unroll
+                    for (int qt = 0; qt < NQT; ++qt) {
+                        acc[0][qt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a00, bq[qt][0], acc[0][qt], 0, 0, 0);
+                        if constexpr (TWO)
+                            acc[1][qt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a10, bq[qt][0], acc[1][qt], 0, 0, 0);
+                    }
+#pragma unroll
+                    for (int qt = 0; qt < NQT; ++qt) {
+                        acc[0][qt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a01, bq[qt][1], acc[0][qt], 0, 0, 0);
+                        if constexpr (TWO)
+                            acc[1][qt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a11, bq[qt][1], acc[1][qt], 0, 0, 0);
+                    }
+#pragma unroll
+                    for (int qt = 0; qt < NQT; ++qt) { bq[qt][0] = bn[qt][0]; bq[qt][1] = bn[qt][1]; }
                 }
             }
-            kb0 += PD;
-            if (kb0 < nkb) continue;                // next K-steps of the same group
-            kb0 = 0;
-            ++gi;
+        };
+        for (int gi = 0; gi < ngw; ++gi) {
+            const int gt0 = ta + 2 * gi;                // first tile of the group
+            if (gt0 + 1 < tb) run_group(std::true_type{});
+            else run_group(std::false_type{});
             // epilogue of group g: estimates, bound test, survivors to the stage.
             // The tile's 16 factor pairs are read from LDS before any is used,
             // and nothing here touches global memory except the rare overflow
