@@ -336,6 +336,19 @@ def test_probe_selection_exact_ties(nl, nprobe):
         np.testing.assert_array_equal(dg[i], exact[i][order].astype(np.float32))
 
 
+@pytest.mark.parametrize("nl,nprobe", [(700, 84), (5000, 200), (9000, 40)])
+def test_probe_selection_all_equal(nl, nprobe):
+    """Every centroid is the same vector, so every distance of a row is the
+    same value (no radix pass has anything to split): the selection must
+    return the first nprobe columns in order."""
+    say("probe all equal", nl, nprobe)
+    g = np.random.default_rng(nl)
+    cent = np.tile(g.standard_normal((1, 64)).astype(np.float32), (nl, 1))
+    q = g.standard_normal((9, 64)).astype(np.float32)
+    pg = erq.coarse_probe(dev(q), dev(cent), nprobe).cpu().numpy()
+    np.testing.assert_array_equal(pg, np.tile(np.arange(nprobe, dtype=pg.dtype), (9, 1)))
+
+
 def test_rerank_parity():
     say("rerank")
     dp, n, nq, kc, k = 192, 2000, 30, 50, 10
