@@ -358,7 +358,12 @@ int erq_static_scratch_bytes(size_t* bytes);
 /*          (rule: 8);                                                       */
 /*   round2 end of a middle round [round1, round2), in [0, 1024]; it takes  */
 /*          effect only when round1 < round2 < nprobe (rule: no middle      */
-/*          round).  Each round ends with a select that lowers the bound.   */
+/*          round; then, while kk times the ranks left over the ranks       */
+/*          scanned exceeds 3/4 of (4096 - kk), the rest is cut at g times   */
+/*          the ranks scanned, g = 16 halved while kk * (g - 1) > 1024:      */
+/*          nprobe 1024 and kk 200 give [0, 4), [4, 16), [16, 64), [64, 256),*/
+/*          [256, 1024)).                                                    */
+/*          Each round ends with a select that lowers the bound.            */
 /* No value changes a result: estimates are computed pair by pair in the    */
 /* same arithmetic and the output is the exact top-kk by (estimate, id)      */
 /* under every schedule.  set_tune rejects invalid values (ERQ_EINVAL) and   */

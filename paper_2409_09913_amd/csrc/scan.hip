@@ -18,7 +18,8 @@
 //     candidate buffer; tau_q is the kk-th best of them (radix select).  Any
 //     subset of a query's candidates gives a valid bound: every member of the
 //     final top-kk has est <= tau_q.  The buffer is then emptied.
-//  3. pass B (the scan) in rounds of probe rank, [0, round1) and the rest:
+//  3. pass B (the scan) in rounds of probe rank, [0, round1) and the rest
+//     (cut further when kk * nprobe is large against a candidate buffer):
 //     64 vectors x 32 or 64 queries per wave step.  Estimates above tau_q are
 //     dropped with one compare; the rest are staged in a per-query LDS
 //     buffer (spilling straight to global memory when it is full) and
@@ -943,11 +944,12 @@ __device__ inline void wave_bitonic(float* se, int* si, int m, int lane) {
 
 // post (mode 0 only), applied on entry after the count is read: 1 empties the
 // buffer (count and count-before-round 0), 2 records the count as the
-// count before the next round
+// count before the next round (after dropping, from a buffer more than a
+// quarter full, the entries above the new bound)
 __global__ __launch_bounds__(256) void buf_select_kernel(int32_t* __restrict__ gcnt,
                                                          int32_t* __restrict__ gprev,
-                                                         const float* __restrict__ gbuf_e,
-                                                         const int32_t* __restrict__ gbuf_i, int64_t nq, int kk,
+                                                         float* __restrict__ gbuf_e,
+                                                         int32_t* __restrict__ gbuf_i, int64_t nq, int kk,
                                                          int mode, int post, unsigned* __restrict__ tau_key,
                                                          int32_t* __restrict__ ovf, int64_t* __restrict__ out_ids,
                                                          float* __restrict__ out_est, int32_t* __restrict__ any_over)
@@ -1002,6 +1004,39 @@ __global__ __launch_bounds__(256) void buf_select_kernel(int32_t* __restrict__ g
     }
     if (mode == 0) {
         if (lane == 0) atomicMin(&tau_key[q], kth);
+        if (post == 2 && c > kCapQ / 4) {
+            // between rounds: entries above the new bound can never reach the
+            // top-kk, so the buffer keeps only those at or below it (in place,
+            // in buffer order: every entry moves to a position at or before
+            // its own, and a chunk is read whole before any of it is written)
+            float* wbe = gbuf_e + q * kCapQ;
+            int32_t* wbi = gbuf_i + q * kCapQ;
+            const unsigned long long below = (1ull << lane) - 1ull;
+            unsigned run = 0;
+            for (int base = 0; base < c; base += 64 * kSelB) {
+                bool kv[kSelB];
+                float ev[kSelB];
+                int iv[kSelB];
+#pragma unroll
+                for (int k = 0; k < kSelB; ++k) {
+                    const int t = base + lane + 64 * k;
+                    kv[k] = t < c && (base == 0 ? key0[k] : key_at(t)) <= kth;
+                    ev[k] = kv[k] ? wbe[t] : 0.0f;
+                    iv[k] = kv[k] ? wbi[t] : 0;
+                }
+#pragma unroll
+                for (int k = 0; k < kSelB; ++k) {
+                    const unsigned long long bal = __ballot(kv[k]);
+                    if (kv[k]) {
+                        const unsigned p = run + (unsigned)__popcll(bal & below);
+                        wbe[p] = ev[k];
+                        wbi[p] = iv[k];
+                    }
+                    run += (unsigned)__popcll(bal);
+                }
+            }
+            if (lane == 0) { gcnt[q] = (int)run; gprev[q] = (int)run; }
+        }
         return;
     }
     if (mode == 2) {                                     // over: kCapQ >= kk entries were ranked
@@ -2260,12 +2295,30 @@ int run_scan(Index* ix, const float* qrot, int64_t qld, int64_t nq, const int32_
     // bound, then the buffer is emptied (the dense entries are found again by the rounds)
     if (e == hipSuccess) e = select(0, 1, nullptr, nullptr);
     // pass B in rounds of increasing probe rank, [0, round1), [round1, round2)
-    // when round2 lies between round1 and nprobe, and the rest; the count
-    // before each round is recorded by the select before it (0 after the
-    // dense bound)
+    // when round2 lies between round1 and nprobe, and the rest.  Without a
+    // middle round, the rest is cut further while the candidates it would
+    // let through exceed three quarters of what a candidate buffer holds
+    // beside the kk kept (a bound taken from hi ranks lets about
+    // kk * (rest / hi) candidates of the rest through): the next round ends
+    // at g * hi, g = 16 halved until kk * (g - 1) <= kCapQ / 4.  At nprobe 84
+    // and kk 24 this keeps the two rounds; at nprobe 1024 and kk 200 it gives
+    // [0, 4), [4, 16), [16, 64), [64, 256), [256, 1024).  The count before
+    // each round is recorded by the select before it (0 after the dense
+    // bound).
     const int r1 = std::min(nprobe, scan_round1(ix)), r2 = scan_round2(ix);
-    int bounds[4] = {0, r1, nprobe, nprobe}, nround = 2;
-    if (r2 > r1 && r2 < nprobe) { bounds[2] = r2; nround = 3; }
+    int bounds[16] = {0, r1}, nround = 1;
+    if (r2 > r1 && r2 < nprobe) {
+        bounds[++nround] = r2;
+    } else {
+        int g = 16;
+        while (g > 2 && (int64_t)kk * (g - 1) > kCapQ / 4) g >>= 1;
+        for (int hi = r1; hi > 0 && nround < 12 && (int64_t)4 * kk * (nprobe - hi) > (int64_t)3 * (kCapQ - kk) * hi;) {
+            hi *= g;
+            if (hi >= nprobe) break;
+            bounds[++nround] = hi;
+        }
+    }
+    bounds[++nround] = nprobe;
     for (int r = 0; r < nround && e == hipSuccess; ++r) {
         const int rlo = bounds[r], rhi = bounds[r + 1];
         if (rhi <= rlo) continue;

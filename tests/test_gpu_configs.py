@@ -186,6 +186,43 @@ def test_d3072_scan_and_serving():
     ix.close()
 
 
+@pytest.mark.parametrize("kk", [10, 200, 1000])
+def test_scan_many_probes_rounds(kk):
+    """nprobe far above the first round (300 of 320 lists, round 1 of 4
+    ranks): at kk 200 the built-in rule cuts the probe ranks into [0, 4),
+    [4, 16), [16, 64), [64, 300) (kk 10: [0, 4), [4, 300); kk 1000: doubling rounds,
+    the buffers cut to the entries under each new bound), so no query needs
+    the exact fallback; the result matches the oracle and is bit for bit the
+    one of an explicit middle round [4, 32), of a longer first round and of
+    a single round."""
+    dp, nl, B, nq, nprobe = 128, 320, 4, 40, 300
+    sizes = np.random.default_rng(970).integers(20, 160, nl)
+    off, ids, codes, fa, fr, crot = synth.random_index(int(sizes.sum()), nl, dp, B, seed=971, sizes=sizes)
+    qrot = synth.random_rotated(nq, dp, seed=972)
+    probes = synth.random_probes(nq, nl, nprobe, seed=973)
+    ix = _import(off, ids, codes, fa, fr, crot, dp, B)
+    ix.set_small_batch(0)
+    ix.set_tune(0, 0, 4, 0)
+    erq.profile_enable(2)
+    erq.profile_read("scan_redo_pairs", reset=True)
+    try:
+        gi, ge = [t.cpu().numpy() for t in ix.scan(dev(qrot), dev(probes), kk)]
+        redo, _ = erq.profile_read("scan_redo_pairs", reset=True)
+    finally:
+        erq.profile_read("scan", reset=True)
+        erq.profile_enable(False)
+    say("  kk %d: pairs rescanned by the exact fallback %d" % (kk, redo))
+    assert redo == 0
+    oi, oe = oracle.search(off, ids, codes, fa, fr, crot, qrot, probes, B, kk, est_mode=0)
+    compare_topk(gi, ge, oi, oe, CandTerms(off, ids, codes, fa, fr, crot, qrot, probes, B))
+    for r1, r2 in ((4, 32), (64, 0), (512, 0)):
+        ix.set_tune(0, 0, r1, r2)
+        hi, he = [t.cpu().numpy() for t in ix.scan(dev(qrot), dev(probes), kk)]
+        np.testing.assert_array_equal(hi, gi)
+        np.testing.assert_array_equal(he.view(np.uint32), ge.view(np.uint32))
+    ix.close()
+
+
 @pytest.mark.parametrize("B", [4, 5])
 def test_scan_schedules_identical_results(B):
     """Every scan schedule (query tiles per item, codes in flight, first
