@@ -80,10 +80,11 @@ def main():
                     help="N > 0: also run N Poisson-arrival requests per rate through the batching server "
                          "(p50/p99); 0 skips it")
     ap.add_argument("--workload", type=str, default="embed768",
-                    choices=("embed768", "batching", "serving", "two_stage"),
+                    choices=("embed768", "batching", "serving", "two_stage", "precision"),
                     help="embed768 (the default line); batching: 2M x 960, 8192 uneven lists, B=3/5/7, batches "
                          "1..4096 with mixed nprobe; serving: 5M x 3072, 16384 lists, B=4, Poisson arrivals; "
-                         "two_stage: embed768 with the MSB-first two-stage scan against the one-stage scan")
+                         "two_stage: embed768 with the MSB-first two-stage scan against the one-stage scan; "
+                         "precision: 1M x 1536 unit vectors, FP32 vs BF16 rotation, B=2..8, errors against FP64")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -102,6 +103,9 @@ def main():
         return
     if args.workload == "two_stage":
         run_two_stage(args)
+        return
+    if args.workload == "precision":
+        run_precision(args)
         return
 
     import torch
@@ -738,6 +742,82 @@ def run_serving(args):
            "encode_codes_per_s": enc, "kmeans_s": t_km, "sweep": sweep, "operating_points": op,
            "serving": {"by_rate": by_rate},
            "scan_batch256_np64": roof}
+    log("total %.1fs" % (time.time() - t0))
+    print(json.dumps(out), flush=True)
+
+
+def run_precision(args):
+    """Precision workload: N = 1,000,000 x D = 1536 unit vectors (256
+    clusters normalize(mu + g / sqrt(D)), mu uniform on the sphere); one
+    k-means of 2048 lists shared by every index; per rotation precision
+    (FP32, BF16 matrix cores) and B = 2..8 an index is built from the same
+    lists, and 500 queries of the same mixture are searched at nprobe 256
+    without re-rank.  Reported against FP64 exact squared distances (torch
+    float64 on the device): recall@10 of the estimated top-10 against the
+    exact top-10 over all N, and the relative error |est - d| / d of the
+    estimates of each query's 100 returned candidates (mean, 99th
+    percentile); for B >= 5 also with the two-plane int8 query."""
+    import torch
+    from paper_2409_09913_amd import erq, synth
+    dev = torch.device("cuda:0")
+    erq.load()
+    t0 = time.time()
+    n, dp, nl, nq, nprobe = 1_000_000, 1536, 2048, 500, 256
+    x = synth.spherical_clusters_device(n, dp, 256, 1.0, device=dev)
+    q = synth.spherical_clusters_device(nq, dp, 256, 1.0, stream=synth.S_QUERY, device=dev)
+    cent, assign = erq.kmeans(x, nl, iters=6)
+    torch.cuda.synchronize()
+    log("precision workload: %d x %d data and k-means in %.1fs" % (n, dp, time.time() - t0))
+    # FP64 exact squared distances: the top-10 over all rows per query
+    q64 = q.double()
+    best_d = torch.full((nq, 10), float("inf"), dtype=torch.float64, device=dev)
+    best_i = torch.zeros((nq, 10), dtype=torch.int64, device=dev)
+    for lo in range(0, n, 1 << 17):
+        xb = x[lo:lo + (1 << 17)].double()
+        d = (q64 * q64).sum(1, keepdim=True) + (xb * xb).sum(1)[None, :] - 2.0 * (q64 @ xb.T)
+        dd, ii = torch.topk(torch.cat([best_d, d], 1), 10, dim=1, largest=False)
+        best_i = torch.gather(torch.cat([best_i, torch.arange(lo, lo + xb.shape[0], device=dev)[None, :].expand(nq, -1)],
+                                        1), 1, ii)
+        best_d = dd
+    truth = best_i.cpu().numpy()
+    log("FP64 ground truth %.1fs" % (time.time() - t0))
+
+    def errors(ids, est):
+        """|est - d| / d over the returned candidates, d the FP64 exact squared distance."""
+        ok = ids >= 0
+        idx = torch.where(ok, ids, torch.zeros_like(ids))
+        xr = x[idx.reshape(-1)].double().reshape(nq, ids.shape[1], dp)
+        d = ((xr - q64[:, None, :]) ** 2).sum(-1)
+        rel = ((est.double() - d).abs() / d.clamp_min(1e-12))[ok]
+        return float(rel.mean()), float(torch.quantile(rel.float(), 0.99))
+
+    out = {"metric": "estimated-distance error and recall@10 against FP64, by rotation precision and B "
+                     "(precision workload)", "unit": "relative error",
+           "config": {"workload": "precision: N=%d x D=1536 unit vectors, 256 clusters, IVF %d lists, %d queries, "
+                                  "nprobe %d, no re-rank" % (n, nl, nq, nprobe)}, "rows": []}
+    for prec, pname in ((0, "fp32"), (1, "bf16")):
+        for B in range(2, 9):
+            ix = erq.Index(dp, B, nl, None, seed=240909913)
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            ix.build(x, cent, assign, precision=prec, keep_raw=False)
+            torch.cuda.synchronize()
+            enc = n / (time.perf_counter() - ts)
+            planes = (1, 2) if B >= 5 else (1,)
+            for pl in planes:
+                ix.set_query_planes(pl)
+                ids10, _ = ix.search(q, nprobe, 10, 0)
+                ids, est = ix.search(q, nprobe, 100, 0)
+                torch.cuda.synchronize()
+                rec = recall_at(ids10.cpu().numpy(), truth, 10)
+                mean_e, p99_e = errors(ids, est)
+                row = {"rotation": pname, "bits": B, "query_planes": pl, "recall@10": rec,
+                       "rel_err_mean": mean_e, "rel_err_p99": p99_e, "encode_codes_per_s": enc}
+                out["rows"].append(row)
+                log("precision %s B=%d planes %d: recall@10 %.4f, rel. error mean %.3g p99 %.3g, encode %.3g/s" %
+                    (pname, B, pl, rec, mean_e, p99_e, enc))
+            ix.close()
+            torch.cuda.empty_cache()
     log("total %.1fs" % (time.time() - t0))
     print(json.dumps(out), flush=True)
 

@@ -261,6 +261,25 @@ def gmm_device(n: int, d: int, ncomp: int, sigma: float = 0.3, zipf: bool = Fals
     return x, lab
 
 
+def spherical_clusters_device(n: int, d: int, ncomp: int, tau: float = 1.0, seed: int = SEED,
+                              stream: int = S_BASE, device="cuda", chunk: int = 1 << 18):
+    """n unit vectors normalize(mu_j + tau * g / sqrt(d)) of spherical_clusters()
+    (same centres mu_j, uniform on the sphere, equal weights), drawn on `device`
+    in chunks; returns rows float32."""
+    import torch
+    mu = rng(seed, S_MEANS).standard_normal((ncomp, d))
+    mu /= np.linalg.norm(mu, axis=1, keepdims=True)
+    mu = torch.from_numpy(mu.astype(np.float32)).to(device)
+    g = torch.Generator(device=device).manual_seed(int(seed) * 16 + stream)
+    x = torch.empty((n, d), dtype=torch.float32, device=device)
+    for lo in range(0, n, chunk):
+        m = min(chunk, n - lo)
+        lb = torch.randint(0, ncomp, (m,), device=device, generator=g)
+        y = mu[lb] + (tau / float(np.sqrt(d))) * torch.randn((m, d), device=device, generator=g)
+        x[lo:lo + m] = y / torch.linalg.vector_norm(y, dim=1, keepdim=True)
+    return x
+
+
 def clustered_anisotropic_device(sizes, d: int, noise: float = 0.5, seed: int = SEED, device="cuda",
                                  chunk: int = 1 << 18):
     """Clusters of the given sizes around centres drawn from the Gaussian with
