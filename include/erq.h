@@ -186,7 +186,9 @@ int erq_index_set_query_planes(erq_index idx, int32_t planes);
    same; the small path reads each probed list once per query rather than
    once per tile of its queries, so it suits batches whose queries share few
    lists.  It always scans in one stage (a two-stage setting applies to the
-   pipeline only).  max_queries in [0, 1024]; saved with the index. */
+   pipeline only), and it is not used when kk > 256 at nprobe >= 16 (fewer
+   than 16 workgroups per query).  max_queries in [0, 1024]; saved with the
+   index. */
 int erq_index_set_small_batch(erq_index idx, int32_t max_queries);
 
 /* The index's current small-batch threshold (see erq_index_set_small_batch). */

@@ -2252,8 +2252,11 @@ int run_scan(Index* ix, const float* qrot, int64_t qld, int64_t nq, const int32_
     // count, not by work.  Each query's probed lists are instead split over S
     // workgroups that keep exact top-kk lists (exact_kernel, slice mode), and
     // one final select merges them: the same exact top-kk by (est, id).
+    // With S below 16 (kk > 256 at nprobe >= 16) each workgroup would keep a
+    // long exact list over a large share of the probed members; such calls
+    // take the pipeline.
     const int small_s = std::min(std::min(nprobe, kSmallS), std::max(1, kCapQ / kk));
-    if (nq <= ix->small_q) {
+    if (nq <= ix->small_q && small_s >= std::min(nprobe, 16)) {
         const int pc = prof_begin(PK_SCAN_C, st);
         zero(gcnt, nq);
         hipError_t e = launch_exact(ix, qa, probes, nq, nprobe, kk, nullptr, nullptr, nullptr, nullptr, nullptr, st,

@@ -458,7 +458,7 @@ def test_end_to_end_tiny():
 
 
 @pytest.mark.parametrize("B,planes,nq,kk,nprobe", [(4, 1, 1, 10, 8), (4, 1, 7, 100, 12), (4, 1, 32, 1, 5),
-                                                   (3, 1, 20, 1024, 9), (8, 2, 13, 10, 8), (6, 2, 32, 64, 3),
+                                                   (3, 1, 20, 1024, 4), (8, 2, 13, 10, 8), (6, 2, 32, 64, 3),
                                                    (1, 1, 5, 10, 4), (4, 1, 300, 10, 16), (5, 2, 1024, 100, 6)])
 def test_small_batch_path_identical(B, planes, nq, kk, nprobe):
     """The small-batch path (exact per-query top-kk over probe slices, one
