@@ -302,7 +302,9 @@ def main():
     lists, pair_cnt = np.unique(probes, return_counts=True)
     nb = args.bits * dp // 8 + 8
     bytes_alg = float(sizes[lists].sum()) * nb
-    ops_alg = float((sizes[lists] * pair_cnt).sum()) * 2 * dp
+    # pass-B work: every probed (query, member) pair but those the first bound
+    # estimates (the first 256 members of each query's 4 nearest lists)
+    ops_alg = float((sizes[lists] * pair_cnt).sum() - dense_covered(probes, sizes)) * 2 * dp
     # dominant kernel: the pass-B scan (scanB_kernel), launched once per round of
     # probe ranks; over one search its launches cover every (query, list) pair once
     sb_ms, sb_n = raw["scan_b"]
@@ -435,11 +437,18 @@ def brute_topk(x, qb, k, chunk=256):
     return out
 
 
+def dense_covered(probes_np, sizes, ranks=4, members=256):
+    """(query, member) pairs the scan's first bound estimates and pass B then
+    skips: the first `members` members of each query's `ranks` nearest lists."""
+    p = probes_np[:, :ranks]
+    return float(np.minimum(sizes[p[p >= 0]], members).sum())
+
+
 def scan_roofline(ix, nq, dp, B, sizes, probes_np, launches_ms):
     """Algorithmic int8 ops and code bytes of one search over the probed pairs,
     against the pass-B launch time."""
     lists, cnt = np.unique(probes_np[probes_np >= 0], return_counts=True)
-    ops = float((sizes[lists] * cnt).sum()) * 2 * dp
+    ops = float((sizes[lists] * cnt).sum() - dense_covered(probes_np, sizes)) * 2 * dp
     byt = float(sizes[lists].sum()) * (B * dp / 8 + 8)
     ms, nl = launches_ms
     t = ms / 1000.0

@@ -356,8 +356,10 @@ int erq_static_scratch_bytes(size_t* bytes);
 /*          rule: 2 for dp <= 768);                                          */
 /*   pd     K-steps of packed codes in flight per wave, one of 1, 2, 3, 4, 6 */
 /*          dividing dp/64 (6 only for bits <= 4; rule: the largest);        */
-/*   round1 probe ranks of the first bounded round, in [1, 1024]            */
-/*          (rule: 8);                                                       */
+/*   round1 end of the first bounded rounds, in [1, 1024] (rule: 4): the    */
+/*          first round always covers the first bound's 4 nearest ranks     */
+/*          (their first 256 members are not scanned again), and round1 > 4  */
+/*          adds a round [4, round1);                                        */
 /*   round2 end of a middle round [round1, round2), in [0, 1024]; it takes  */
 /*          effect only when round1 < round2 < nprobe (rule: no middle      */
 /*          round; then, while kk times the ranks left over the ranks       */

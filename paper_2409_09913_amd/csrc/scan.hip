@@ -17,7 +17,8 @@
 //     nearest probed lists is written to fixed slots of the query's
 //     candidate buffer; tau_q is the kk-th best of them (radix select).  Any
 //     subset of a query's candidates gives a valid bound: every member of the
-//     final top-kk has est <= tau_q.  The buffer is then emptied.
+//     final top-kk has est <= tau_q.  The buffer keeps those estimates at
+//     or under tau_q, and the first round skips the members they cover.
 //  3. pass B (the scan) in rounds of probe rank, [0, round1) and the rest
 //     (cut further when kk * nprobe is large against a candidate buffer):
 //     64 vectors x 32 or 64 queries per wave step.  Estimates above tau_q are
@@ -45,7 +46,7 @@ constexpr int kQT = 32;        // queries per MFMA column tile
 constexpr int kCapB = 32;      // per-query survivor buffer of a pass-B item (LDS)
 constexpr int kDenseR = 4;     // first bound: nearest probes per query ...
 constexpr int kDenseV = 256;   // ... and members per list (all estimates kept)
-constexpr int kRound1 = 8;     // pass B, round 1: probe ranks [0, kRound1)
+constexpr int kRound1 = 4;     // pass B: the rounds up to probe rank kRound1 (the first is [0, kDenseR))
 constexpr int kCapQ = 4096;    // candidate buffer per query (HBM)
 constexpr int kVch = 1024;     // pass-B members per item (long lists are split)
 constexpr int kSmallS = 64;    // small-batch path: at most this many workgroups per query
@@ -945,7 +946,9 @@ __device__ inline void wave_bitonic(float* se, int* si, int m, int lane) {
 // post (mode 0 only), applied on entry after the count is read: 1 empties the
 // buffer (count and count-before-round 0), 2 records the count as the
 // count before the next round (after dropping, from a buffer more than a
-// quarter full, the entries above the new bound)
+// quarter full, the entries above the new bound), 3 (after the first bound)
+// keeps the entries at or under the new bound and drops the padding, and
+// records what is left as the count before the first round
 __global__ __launch_bounds__(256) void buf_select_kernel(int32_t* __restrict__ gcnt,
                                                          int32_t* __restrict__ gprev,
                                                          float* __restrict__ gbuf_e,
@@ -965,7 +968,7 @@ __global__ __launch_bounds__(256) void buf_select_kernel(int32_t* __restrict__ g
     if (q >= nq) return;                                // the whole wave
     const int craw = gcnt[q];
     const bool over = craw > kCapQ;
-    if (mode == 0 && post != 0 && lane == 0) {
+    if (mode == 0 && (post == 1 || post == 2) && lane == 0) {
         if (post == 1) { gcnt[q] = 0; gprev[q] = 0; }
         else gprev[q] = craw;
     }
@@ -978,7 +981,7 @@ __global__ __launch_bounds__(256) void buf_select_kernel(int32_t* __restrict__ g
         if (lane == 0) ovf[q] = 0;
         if (mode == 2) return;
     }
-    if (mode == 0 && (over || craw < kk)) return;       // no (new) bound from this buffer
+    if (mode == 0 && post != 3 && (over || craw < kk)) return;   // no (new) bound from this buffer
     const int c = over ? kCapQ : craw;
     const float* be = gbuf_e + q * kCapQ;
     const int* bi = gbuf_i + q * kCapQ;
@@ -1004,11 +1007,13 @@ __global__ __launch_bounds__(256) void buf_select_kernel(int32_t* __restrict__ g
     }
     if (mode == 0) {
         if (lane == 0) atomicMin(&tau_key[q], kth);
-        if (post == 2 && c > kCapQ / 4) {
+        if (post == 3 || (post == 2 && c > kCapQ / 4)) {
             // between rounds: entries above the new bound can never reach the
             // top-kk, so the buffer keeps only those at or below it (in place,
             // in buffer order: every entry moves to a position at or before
-            // its own, and a chunk is read whole before any of it is written)
+            // its own, and a chunk is read whole before any of it is written).
+            // The first bound's padding (+inf, no member) is dropped too.
+            constexpr unsigned kInfKey = 0xFF800000u;    // f2key(+inf)
             float* wbe = gbuf_e + q * kCapQ;
             int32_t* wbi = gbuf_i + q * kCapQ;
             const unsigned long long below = (1ull << lane) - 1ull;
@@ -1020,7 +1025,8 @@ __global__ __launch_bounds__(256) void buf_select_kernel(int32_t* __restrict__ g
 #pragma unroll
                 for (int k = 0; k < kSelB; ++k) {
                     const int t = base + lane + 64 * k;
-                    kv[k] = t < c && (base == 0 ? key0[k] : key_at(t)) <= kth;
+                    const unsigned kt = t >= c ? 0xFFFFFFFFu : (base == 0 ? key0[k] : key_at(t));
+                    kv[k] = kt <= kth && kt < kInfKey;
                     ev[k] = kv[k] ? wbe[t] : 0.0f;
                     iv[k] = kv[k] ? wbi[t] : 0;
                 }
@@ -1655,11 +1661,12 @@ __global__ void pair_scatter_kernel(const int32_t* __restrict__ probes, int64_t 
 // Items of list l: ceil(cnt/qpi) query tiles, times ceil(n_l/vch) member
 // chunks when vch > 0 (none for an empty list); with vch == 0 one item per
 // query tile, empty lists included (their pairs still get an output row).
-__device__ inline int items_of(const int32_t* cnt, const int64_t* list_off, int l, int qpi, int vch) {
+// vs: members [0, vs) of every list are skipped (already scanned)
+__device__ inline int items_of(const int32_t* cnt, const int64_t* list_off, int l, int qpi, int vch, int vs) {
     const int tiles = (cnt[l] + qpi - 1) / qpi;
     if (vch <= 0) return tiles;
-    const int nv = (int)(list_off[l + 1] - list_off[l]);
-    return tiles * ((nv + vch - 1) / vch);
+    const int nv = (int)(list_off[l + 1] - list_off[l]) - vs;
+    return nv > 0 ? tiles * ((nv + vch - 1) / vch) : 0;
 }
 
 // Counting sort of the selected pairs by list without global atomics, for
@@ -1748,7 +1755,7 @@ __global__ __launch_bounds__(1024) void pair_place_kernel(const int32_t* __restr
 }
 
 __device__ inline void list_scan(const int32_t* __restrict__ cnt, int nlist, const int32_t* __restrict__ list_order,
-                                 const int64_t* __restrict__ list_off, int qpi, int vch,
+                                 const int64_t* __restrict__ list_off, int qpi, int vch, int vs,
                                  int32_t* __restrict__ pair_off, int32_t* __restrict__ item_off);
 
 // single workgroup: pair_off (by list id) and item_off (by rank of list_order).
@@ -1757,7 +1764,7 @@ __device__ inline void list_scan(const int32_t* __restrict__ cnt, int nlist, con
 __global__ __launch_bounds__(1024) void pair_scan_kernel(const int32_t* __restrict__ cnt, int nlist,
                                                          const int32_t* __restrict__ list_order,
                                                          const int64_t* __restrict__ list_off, int qpi, int vch,
-                                                         int32_t* __restrict__ pair_off,
+                                                         int vs, int32_t* __restrict__ pair_off,
                                                          int32_t* __restrict__ item_off,
                                                          const int32_t* __restrict__ gate, int32_t* __restrict__ work,
                                                          int32_t* __restrict__ zf0, int32_t* __restrict__ zf1)
@@ -1772,13 +1779,13 @@ __global__ __launch_bounds__(1024) void pair_scan_kernel(const int32_t* __restri
         if (threadIdx.x == 0) { item_off[nlist] = 0; pair_off[nlist] = 0; }
         return;
     }
-    list_scan(cnt, nlist, list_order, list_off, qpi, vch, pair_off, item_off);
+    list_scan(cnt, nlist, list_order, list_off, qpi, vch, vs, pair_off, item_off);
 }
 
 // One workgroup of 1024: exclusive prefix of the pair counts (pair_off, by
 // list id) and of the item counts (item_off, by rank of list_order).
 __device__ inline void list_scan(const int32_t* __restrict__ cnt, int nlist, const int32_t* __restrict__ list_order,
-                                 const int64_t* __restrict__ list_off, int qpi, int vch,
+                                 const int64_t* __restrict__ list_off, int qpi, int vch, int vs,
                                  int32_t* __restrict__ pair_off, int32_t* __restrict__ item_off)
 {
     __shared__ int part_a[1024], part_b[1024];
@@ -1786,7 +1793,7 @@ __device__ inline void list_scan(const int32_t* __restrict__ cnt, int nlist, con
     const int chunk = (nlist + 1023) / 1024;
     const int beg = tid * chunk, end = min(nlist, beg + chunk);
     int sa = 0, sb = 0;
-    for (int i = beg; i < end; ++i) { sa += cnt[i]; sb += items_of(cnt, list_off, list_order[i], qpi, vch); }
+    for (int i = beg; i < end; ++i) { sa += cnt[i]; sb += items_of(cnt, list_off, list_order[i], qpi, vch, vs); }
     part_a[tid] = sa; part_b[tid] = sb;
     __syncthreads();
     for (int o = 1; o < 1024; o <<= 1) {
@@ -1799,7 +1806,7 @@ __device__ inline void list_scan(const int32_t* __restrict__ cnt, int nlist, con
     int ra = part_a[tid] - sa, rb = part_b[tid] - sb;
     for (int i = beg; i < end; ++i) {
         pair_off[i] = ra; ra += cnt[i];
-        item_off[i] = rb; rb += items_of(cnt, list_off, list_order[i], qpi, vch);
+        item_off[i] = rb; rb += items_of(cnt, list_off, list_order[i], qpi, vch, vs);
     }
     if (tid == 1023) { pair_off[nlist] = part_a[1023]; item_off[nlist] = part_b[1023]; }
 }
@@ -1808,25 +1815,25 @@ __device__ inline void list_scan(const int32_t* __restrict__ cnt, int nlist, con
 // that a scan kernel reads one int4 per item; one thread per item
 __device__ inline void item_desc_one(int64_t item, const int32_t* __restrict__ item_off,
                                      const int32_t* __restrict__ list_order, const int64_t* __restrict__ list_off,
-                                     const int32_t* __restrict__ pair_off, int nlist, int qpi, int vch,
+                                     const int32_t* __restrict__ pair_off, int nlist, int qpi, int vch, int vs,
                                      int4* __restrict__ desc)
 {
     int l, t;
     decode_item((int)item, item_off, list_order, nlist, &l, &t);
-    const int nv = (int)(list_off[l + 1] - list_off[l]);
+    const int nv = (int)(list_off[l + 1] - list_off[l]) - vs;
     const int nvc = (vch > 0) ? max(1, (nv + vch - 1) / vch) : 1;
     const int qtile = t / nvc, vc = t - qtile * nvc;
     const int p0 = pair_off[l] + qtile * qpi;
-    desc[item] = make_int4(l, p0, min(qpi, pair_off[l + 1] - p0), vc * vch);
+    desc[item] = make_int4(l, p0, min(qpi, pair_off[l + 1] - p0), vs + vc * vch);
 }
 
 __global__ void item_desc_kernel(const int32_t* __restrict__ item_off, const int32_t* __restrict__ list_order,
                                  const int64_t* __restrict__ list_off, const int32_t* __restrict__ pair_off,
-                                 int nlist, int qpi, int vch, int64_t cap, int4* __restrict__ desc)
+                                 int nlist, int qpi, int vch, int vs, int64_t cap, int4* __restrict__ desc)
 {
     const int64_t item = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // empty build: item_off[nlist] == 0
     if (item >= cap || item >= item_off[nlist]) return;
-    item_desc_one(item, item_off, list_order, list_off, pair_off, nlist, qpi, vch, desc);
+    item_desc_one(item, item_off, list_order, list_off, pair_off, nlist, qpi, vch, vs, desc);
 }
 
 // A gated pair build (the rescan of overflowed queries, the exact fallback)
@@ -1840,7 +1847,7 @@ __global__ void item_desc_kernel(const int32_t* __restrict__ item_off, const int
 __global__ __launch_bounds__(1024) void pair_build_gated_kernel(
     const int32_t* __restrict__ probes, int64_t nq, int nprobe, int nlist, int rlo, int rhi,
     const int32_t* __restrict__ qmask, const int32_t* __restrict__ list_order,
-    const int64_t* __restrict__ list_off, int qpi, int vch, int32_t* __restrict__ cnt,
+    const int64_t* __restrict__ list_off, int qpi, int vch, int vs, int32_t* __restrict__ cnt,
     int32_t* __restrict__ pair_off, int32_t* __restrict__ item_off, int32_t* __restrict__ pq,
     int32_t* __restrict__ pslot, int4* __restrict__ desc, int64_t cap, int32_t* __restrict__ work,
     const int32_t* __restrict__ gate, int32_t* __restrict__ qlist)
@@ -1866,7 +1873,7 @@ __global__ __launch_bounds__(1024) void pair_build_gated_kernel(
         if (l >= 0 && l < nlist) atomicAdd(&cnt[l], 1);
     }
     __syncthreads();
-    list_scan(cnt, nlist, list_order, list_off, qpi, vch, pair_off, item_off);
+    list_scan(cnt, nlist, list_order, list_off, qpi, vch, vs, pair_off, item_off);
     __syncthreads();
     for (int l = tid; l < nlist; l += 1024) cnt[l] = 0;     // placement counters
     __syncthreads();
@@ -1881,7 +1888,7 @@ __global__ __launch_bounds__(1024) void pair_build_gated_kernel(
     }
     const int64_t n_items = min<int64_t>(item_off[nlist], cap);
     for (int64_t item = tid; item < n_items; item += 1024)
-        item_desc_one(item, item_off, list_order, list_off, pair_off, nlist, qpi, vch, desc);
+        item_desc_one(item, item_off, list_order, list_off, pair_off, nlist, qpi, vch, vs, desc);
 }
 
 struct ScanArgs {
@@ -2189,10 +2196,10 @@ int run_scan(Index* ix, const float* qrot, int64_t qld, int64_t nq, const int32_
     const bool lds_sort = nlist <= kHistMax;
     // the pair scan also zeroes the work counter and, for a build that is not
     // gated, both overflow flags
-    auto build_pairs = [&](int rlo, int rhi, const int32_t* qmask, int qpi, int vch, const int32_t* gate) {
+    auto build_pairs = [&](int rlo, int rhi, const int32_t* qmask, int qpi, int vch, int vs, const int32_t* gate) {
         if (gate) {                                      // usually empty: one launch
             hipLaunchKernelGGL(pair_build_gated_kernel, dim3(1), dim3(1024), 0, st, probes, nq, nprobe, (int)nlist,
-                               rlo, rhi, qmask, ix->list_order, ix->list_off, qpi, vch, cnt, poff, ioff, pq, ps,
+                               rlo, rhi, qmask, ix->list_order, ix->list_off, qpi, vch, vs, cnt, poff, ioff, pq, ps,
                                desc, dcap, work, gate, qlist);
             return hipGetLastError();
         }
@@ -2208,10 +2215,10 @@ int run_scan(Index* ix, const float* qrot, int64_t qld, int64_t nq, const int32_
                                    rlo, rhi, qmask, cnt);
         }
         hipLaunchKernelGGL(pair_scan_kernel, dim3(1), dim3(1024), 0, st, cnt, (int)nlist, ix->list_order,
-                           ix->list_off, qpi, vch, poff, ioff, lds_sort ? gate : nullptr, work,
+                           ix->list_off, qpi, vch, vs, poff, ioff, lds_sort ? gate : nullptr, work,
                            gate ? nullptr : anyf, gate ? nullptr : anyf2);
         hipLaunchKernelGGL(item_desc_kernel, dim3((unsigned)((dcap + th - 1) / th)), dim3(th), 0, st, ioff,
-                           ix->list_order, ix->list_off, poff, (int)nlist, qpi, vch, dcap, desc);
+                           ix->list_order, ix->list_off, poff, (int)nlist, qpi, vch, vs, dcap, desc);
         if (lds_sort) {
             hipLaunchKernelGGL(pair_place_kernel, dim3(kPairBlocks), dim3(1024), 0, st, probes, P, nprobe,
                                (int)nlist, rlo, rhi, qmask, cnt2, poff, pq, ps, gate);
@@ -2277,9 +2284,11 @@ int run_scan(Index* ix, const float* qrot, int64_t qld, int64_t nq, const int32_
     // queries with qmask); dense = the first-bound mode
     // the two-stage scan (Sec. 4.2) replaces pass B when the index has its 1-bit data and eps0 > 0
     const bool two = ix->eps0 > 0.0f && ix->msb && ix->fac1 && ix->qplanes == 1;
-    auto scan_round = [&](int rlo, int rhi, const int32_t* qmask, int dense, const int32_t* gate) {
+    // vs: members [0, vs) of every list are skipped (the first round after
+    // the first bound, whose estimates of those members are kept)
+    auto scan_round = [&](int rlo, int rhi, const int32_t* qmask, int dense, const int32_t* gate, int vs) {
         const int vch = dense ? 0 : (two ? kVch2 : kVch);
-        hipError_t er = build_pairs(rlo, rhi, qmask, qpiB, vch, gate);
+        hipError_t er = build_pairs(rlo, rhi, qmask, qpiB, vch, dense ? 0 : vs, gate);
         if (er != hipSuccess) return er;
         ScanArgs b{qa, poff, pq, ps, ioff, desc, gridB, kk};
         BArgs bb{tkey, gcnt, gbe, gbi, work, vch, dense, nprobe, prof_stats_on() ? redo + 1 : nullptr};
@@ -2294,22 +2303,26 @@ int run_scan(Index* ix, const float* qrot, int64_t qld, int64_t nq, const int32_
     hipLaunchKernelGGL(fill_dense_kernel, dim3((unsigned)((nq * kDenseR * kDenseV + th - 1) / th)), dim3(th), 0, st,
                        gbe, nq, gcnt, tkey, redo);
     e = hipGetLastError();
-    if (e == hipSuccess) e = scan_round(0, r0, nullptr, 1, nullptr);
-    // bound, then the buffer is emptied (the dense entries are found again by the rounds)
-    if (e == hipSuccess) e = select(0, 1, nullptr, nullptr);
-    // pass B in rounds of increasing probe rank, [0, round1), [round1, round2)
-    // when round2 lies between round1 and nprobe, and the rest.  Without a
-    // middle round, the rest is cut further while the candidates it would
-    // let through exceed three quarters of what a candidate buffer holds
-    // beside the kk kept (a bound taken from hi ranks lets about
-    // kk * (rest / hi) candidates of the rest through): the next round ends
-    // at g * hi, g = 16 halved until kk * (g - 1) <= kCapQ / 4.  At nprobe 84
-    // and kk 24 this keeps the two rounds; at nprobe 1024 and kk 200 it gives
-    // [0, 4), [4, 16), [16, 64), [64, 256), [256, 1024).  The count before
-    // each round is recorded by the select before it (0 after the dense
-    // bound).
-    const int r1 = std::min(nprobe, scan_round1(ix)), r2 = scan_round2(ix);
-    int bounds[16] = {0, r1}, nround = 1;
+    if (e == hipSuccess) e = scan_round(0, r0, nullptr, 1, nullptr, 0);
+    // bound; the buffer keeps the dense estimates at or under it (padding
+    // dropped), so the first round skips the members [0, kDenseV) of the r0
+    // nearest lists instead of estimating them again
+    if (e == hipSuccess) e = select(0, 3, nullptr, nullptr);
+    // pass B in rounds of increasing probe rank: [0, r0) (the first bound's
+    // ranks, members past kDenseV only), [r0, round1) when round1 > r0,
+    // [round1, round2) when round2 lies between round1 and nprobe, and the
+    // rest.  Without a middle round, the rest is cut further while the
+    // candidates it would let through exceed three quarters of what a
+    // candidate buffer holds beside the kk kept (a bound taken from hi ranks
+    // lets about kk * (rest / hi) candidates of the rest through): the next
+    // round ends at g * hi, g = 16 halved until kk * (g - 1) <= kCapQ / 4.  At
+    // nprobe 84 and kk 24 this keeps one round after the first; at nprobe
+    // 1024 and kk 200 it gives [0, 4), [4, 16), [16, 64), [64, 256),
+    // [256, 1024).  The count before each round is recorded by the select
+    // before it.
+    const int r1 = std::max(r0, std::min(nprobe, scan_round1(ix))), r2 = scan_round2(ix);
+    int bounds[16] = {0, r0}, nround = 1;
+    if (r1 > r0) bounds[++nround] = r1;
     if (r2 > r1 && r2 < nprobe) {
         bounds[++nround] = r2;
     } else {
@@ -2325,11 +2338,12 @@ int run_scan(Index* ix, const float* qrot, int64_t qld, int64_t nq, const int32_
     for (int r = 0; r < nround && e == hipSuccess; ++r) {
         const int rlo = bounds[r], rhi = bounds[r + 1];
         if (rhi <= rlo) continue;
-        e = scan_round(rlo, rhi, nullptr, 0, nullptr);        // its pair scan zeroes both flags
+        const int vs = r == 0 ? kDenseV : 0;
+        e = scan_round(rlo, rhi, nullptr, 0, nullptr, vs);    // its pair scan zeroes both flags
         // queries that overflowed: back to their count before the round, tighter bound, rescan the
         // round (skipped on the device when no query overflowed)
         if (e == hipSuccess) e = select(2, 0, nullptr, nullptr);
-        if (e == hipSuccess) e = scan_round(rlo, rhi, ovf, 0, anyf);
+        if (e == hipSuccess) e = scan_round(rlo, rhi, ovf, 0, anyf, vs);
         if (e == hipSuccess && rhi < nprobe) e = select(0, 2, nullptr, nullptr);
     }
     // exact top-kk per query; queries whose buffer still overflowed: the exact fallback
