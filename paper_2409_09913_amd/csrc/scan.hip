@@ -1658,10 +1658,10 @@ __global__ void pair_scatter_kernel(const int32_t* __restrict__ probes, int64_t 
     pslot[pos] = (int32_t)i;
 }
 
-// Items of list l: ceil(cnt/qpi) query tiles, times ceil(n_l/vch) member
-// chunks when vch > 0 (none for an empty list); with vch == 0 one item per
-// query tile, empty lists included (their pairs still get an output row).
-// vs: members [0, vs) of every list are skipped (already scanned)
+// Items of list l: ceil(cnt/qpi) query tiles, times ceil((n_l - vs)/vch)
+// member chunks when vch > 0 (none when n_l <= vs; members [0, vs) are
+// skipped, already scanned); with vch == 0 one item per query tile, empty
+// lists included (their pairs still get an output row).
 __device__ inline int items_of(const int32_t* cnt, const int64_t* list_off, int l, int qpi, int vch, int vs) {
     const int tiles = (cnt[l] + qpi - 1) / qpi;
     if (vch <= 0) return tiles;
