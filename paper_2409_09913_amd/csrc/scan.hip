@@ -355,7 +355,6 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
     // and are excluded from the pass test by qok, not by their estimate.
     float qs2[NQT], qhd[NQT], qtau[NQT];
     int qss[NQT];
-    int64_t qslot0[NQT];
     bool qok[NQT];
 #pragma unroll
     for (int qt = 0; qt < NQT; ++qt) {
@@ -365,14 +364,6 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
         qhd[qt] = qok[qt] ? s_hd[qi] : 0.0f;
         qss[qt] = qok[qt] ? s_ss[qi] : 0;
         qtau[qt] = qok[qt] ? key2f(s_tau[qi]) : 0.0f;
-        // dense mode: first buffer slot of this pair, q * kCapQ + rank * kDenseV
-        int64_t sl = 0;
-        if (dense && qok[qt]) {
-            const int slot = s_slot[qi];
-            const int q = s_q[qi];
-            sl = (int64_t)q * kCapQ + (slot - q * nprobe) * kDenseV;
-        }
-        qslot0[qt] = sl;
     }
     // Epilogue constants per column: est = (g + fr * (H2 * acc + HC)) + s2 with
     // H2 = 2 delta/2 and HC = delta/2 * corr * sum(q_int); the bound test
@@ -438,6 +429,14 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
         v4i bq[NQT][2];
         read_b(0, bq);
         v16i acc[2][NQT];
+        // code x query products of a K-block; the first bound takes the
+        // transposed product (rows queries, columns members) so that its
+        // per-(query, member) stores run along members, 128 contiguous bytes
+        // per half-wave
+        auto mm = [](const v4i& a, const v4i& b, const v16i& c) -> v16i {
+            if constexpr (DENSE) return __builtin_amdgcn_mfma_i32_32x32x32_i8(b, a, c, 0, 0, 0);
+            else return __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, c, 0, 0, 0);
+        };
         // the nkb K-steps of one group, for a group of two tiles or of one
         // (the width is a compile-time constant of each loop body)
         auto run_group = [&](auto two_c) {
@@ -460,15 +459,13 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
                     read_b(kb + 1 < nkb ? kb + 1 : 0, bn);
 #pragma unroll
                     for (int qt = 0; qt < NQT; ++qt) {
-                        acc[0][qt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a00, bq[qt][0], acc[0][qt], 0, 0, 0);
-                        if constexpr (TWO)
-                            acc[1][qt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a10, bq[qt][0], acc[1][qt], 0, 0, 0);
+                        acc[0][qt] = mm(a00, bq[qt][0], acc[0][qt]);
+                        if constexpr (TWO) acc[1][qt] = mm(a10, bq[qt][0], acc[1][qt]);
                     }
 #pragma unroll
                     for (int qt = 0; qt < NQT; ++qt) {
-                        acc[0][qt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a01, bq[qt][1], acc[0][qt], 0, 0, 0);
-                        if constexpr (TWO)
-                            acc[1][qt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a11, bq[qt][1], acc[1][qt], 0, 0, 0);
+                        acc[0][qt] = mm(a01, bq[qt][1], acc[0][qt]);
+                        if constexpr (TWO) acc[1][qt] = mm(a11, bq[qt][1], acc[1][qt]);
                     }
 #pragma unroll
                     for (int qt = 0; qt < NQT; ++qt) { bq[qt][0] = bn[qt][0]; bq[qt][1] = bn[qt][1]; }
@@ -488,6 +485,39 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
             for (int a = 0; a < 2; ++a) {
                 const int tt = gt0 + a;
                 if (tt >= tb) break;
+                if constexpr (DENSE) {
+                    // first bound, transposed tile: this lane's member is
+                    // tt*32 + j, row r of query tile qt is query
+                    // qt*32 + out_row(lane, r); every estimate is kept, in the
+                    // same arithmetic as the bounded scan's
+                    const int v = tt * 32 + j;
+                    const float2 f = s_fac[v];
+                    const int id = s_id[v];
+                    if (v < nl) {
+#pragma unroll
+                        for (int qt = 0; qt < (LO ? 1 : NQT); ++qt) {
+#pragma unroll
+                            for (int r = 0; r < 16; ++r) {
+                                const int qi = qt * kQT + out_row(lane, r);
+                                if (qi >= mq) continue;
+                                float h2, hc, e;
+                                if constexpr (LO) {
+                                    float h2l;
+                                    epi_consts2<BITS>(s_hd[qi], s_ss[qi], qa.qss_lo[s_q[qi]], h2, h2l, hc);
+                                    e = epi_e2(f, acc[a][0][r], acc[a][1][r], h2, h2l, hc);
+                                } else {
+                                    epi_consts<BITS>(s_hd[qi], s_ss[qi], h2, hc);
+                                    e = epi_e(f, acc[a][qt][r], h2, hc);
+                                }
+                                const int q = s_q[qi];
+                                const int64_t sl = (int64_t)q * kCapQ + (int64_t)(s_slot[qi] - q * nprobe) * kDenseV;
+                                gbuf_e[sl + v] = e + s_s2[qi];
+                                gbuf_i[sl + v] = id;
+                            }
+                        }
+                    }
+                    continue;
+                }
                 float2 fr[16];
 #pragma unroll
                 for (int r = 0; r < 16; ++r) fr[r] = s_fac[tt * 32 + out_row(lane, r)];   // NaN past the end
@@ -510,17 +540,6 @@ __global__ __launch_bounds__(kThreads, 2) void scanB_kernel(
                             pass[qt] = e[qt] <= cAQ[qt];
                             anyp = anyp || pass[qt];
                         }
-                    }
-                    if constexpr (DENSE) {                  // first bound: keep every estimate
-                        const bool ok = v < nl;
-#pragma unroll
-                        for (int qt = 0; qt < (LO ? 1 : NQT); ++qt) {
-                            if (ok && qok[qt]) {
-                                gbuf_e[qslot0[qt] + v] = e[qt] + qs2[qt];
-                                gbuf_i[qslot0[qt] + v] = s_id[v];
-                            }
-                        }
-                        continue;
                     }
                     if (!__any(anyp)) continue;
 #pragma unroll
