@@ -2215,14 +2215,18 @@ int run_scan(Index* ix, const float* qrot, int64_t qld, int64_t nq, const int32_
     const bool lds_sort = nlist <= kHistMax;
     // the pair scan also zeroes the work counter and, for a build that is not
     // gated, both overflow flags
-    auto build_pairs = [&](int rlo, int rhi, const int32_t* qmask, int qpi, int vch, int vs, const int32_t* gate) {
+    // reuse: the pair table of these ranks is already built (the counts per
+    // list in cnt, the pairs placed): only the items are derived again
+    auto build_pairs = [&](int rlo, int rhi, const int32_t* qmask, int qpi, int vch, int vs, const int32_t* gate,
+                           bool reuse = false) {
         if (gate) {                                      // usually empty: one launch
             hipLaunchKernelGGL(pair_build_gated_kernel, dim3(1), dim3(1024), 0, st, probes, nq, nprobe, (int)nlist,
                                rlo, rhi, qmask, ix->list_order, ix->list_off, qpi, vch, vs, cnt, poff, ioff, pq, ps,
                                desc, dcap, work, gate, qlist);
             return hipGetLastError();
         }
-        if (lds_sort) {
+        if (reuse) {
+        } else if (lds_sort) {
             hipLaunchKernelGGL(pair_hist_kernel, dim3(kPairBlocks), dim3(1024), 0, st, probes, P, nprobe,
                                (int)nlist, rlo, rhi, qmask, cnt2, gate);
             hipLaunchKernelGGL(pair_colsum_kernel, dim3((unsigned)((nlist + 63) / 64)), dim3(256), 0, st, cnt2,
@@ -2238,7 +2242,8 @@ int run_scan(Index* ix, const float* qrot, int64_t qld, int64_t nq, const int32_
                            gate ? nullptr : anyf, gate ? nullptr : anyf2);
         hipLaunchKernelGGL(item_desc_kernel, dim3((unsigned)((dcap + th - 1) / th)), dim3(th), 0, st, ioff,
                            ix->list_order, ix->list_off, poff, (int)nlist, qpi, vch, vs, dcap, desc);
-        if (lds_sort) {
+        if (reuse) {
+        } else if (lds_sort) {
             hipLaunchKernelGGL(pair_place_kernel, dim3(kPairBlocks), dim3(1024), 0, st, probes, P, nprobe,
                                (int)nlist, rlo, rhi, qmask, cnt2, poff, pq, ps, gate);
         } else if (P > 0) {
@@ -2305,9 +2310,10 @@ int run_scan(Index* ix, const float* qrot, int64_t qld, int64_t nq, const int32_
     const bool two = ix->eps0 > 0.0f && ix->msb && ix->fac1 && ix->qplanes == 1;
     // vs: members [0, vs) of every list are skipped (the first round after
     // the first bound, whose estimates of those members are kept)
-    auto scan_round = [&](int rlo, int rhi, const int32_t* qmask, int dense, const int32_t* gate, int vs) {
+    auto scan_round = [&](int rlo, int rhi, const int32_t* qmask, int dense, const int32_t* gate, int vs,
+                          bool reuse = false) {
         const int vch = dense ? 0 : (two ? kVch2 : kVch);
-        hipError_t er = build_pairs(rlo, rhi, qmask, qpiB, vch, dense ? 0 : vs, gate);
+        hipError_t er = build_pairs(rlo, rhi, qmask, qpiB, vch, dense ? 0 : vs, gate, reuse);
         if (er != hipSuccess) return er;
         ScanArgs b{qa, poff, pq, ps, ioff, desc, gridB, kk};
         BArgs bb{tkey, gcnt, gbe, gbi, work, vch, dense, nprobe, prof_stats_on() ? redo + 1 : nullptr};
@@ -2358,7 +2364,8 @@ int run_scan(Index* ix, const float* qrot, int64_t qld, int64_t nq, const int32_
         const int rlo = bounds[r], rhi = bounds[r + 1];
         if (rhi <= rlo) continue;
         const int vs = r == 0 ? kDenseV : 0;
-        e = scan_round(rlo, rhi, nullptr, 0, nullptr, vs);    // its pair scan zeroes both flags
+        // the first round has the first bound's ranks: its pair table is reused
+        e = scan_round(rlo, rhi, nullptr, 0, nullptr, vs, r == 0);   // its pair scan zeroes both flags
         // queries that overflowed: back to their count before the round, tighter bound, rescan the
         // round (skipped on the device when no query overflowed)
         if (e == hipSuccess) e = select(2, 0, nullptr, nullptr);
