@@ -853,7 +853,9 @@ __global__ __launch_bounds__(kThreads, 2) void scan2_kernel(
 // the kk-th smallest estimate (4 passes of 8 bits).  One wave per query (4
 // per block); each pass re-reads the buffer (lane l: entries l, l + 64, ...,
 // just written, so from L2) into a wave-private LDS histogram; no block
-// barrier.
+// barrier.  For kk <= 64 a shorter route usually applies: a bound from the
+// lanes' minima picks at most 64 candidates that contain the top-kk, and one
+// bitonic sort of (key, id) across the wave ranks them.
 //   mode 0: lowers the query's bound to it (the kk-th best candidate so far).
 //   mode 1: writes the exact top-kk ascending by (est, id): every candidate
 //           with a smaller key, and of those whose key equals the kk-th the
@@ -931,6 +933,22 @@ __device__ __attribute__((always_inline)) inline void wave_digit(const unsigned 
     digit = __shfl(my_d, src);
     kr = __shfl(my_kr, src);
     wave_lds_sync();                        // the bins are read before the next pass clears them
+}
+
+// Ascending bitonic sort of one 64-bit value per lane across the wave
+// (lane r ends with the r-th smallest)
+__device__ inline unsigned long long wave_sort_u64(unsigned long long v, int lane) {
+#pragma unroll
+    for (int k = 2; k <= 64; k <<= 1)
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const unsigned plo = (unsigned)__shfl_xor((int)(unsigned)v, j);
+            const unsigned phi = (unsigned)__shfl_xor((int)(unsigned)(v >> 32), j);
+            const unsigned long long p = ((unsigned long long)phi << 32) | plo;
+            const bool take_min = ((lane & j) == 0) == ((lane & k) == 0);
+            v = take_min ? (p < v ? p : v) : (p > v ? p : v);
+        }
+    return v;
 }
 
 // LDS slots per wave for the selected entries of mode 1: a power of two >= kk
@@ -1012,7 +1030,75 @@ __global__ __launch_bounds__(256) void buf_select_kernel(int32_t* __restrict__ g
         key0[k] = (t < c) ? key_at(t) : 0u;
     }
     unsigned kth = 0xFFFFFFFFu, need_eq = 0;
-    if (c >= kk) {
+    // kk <= 64 and every key in registers: the kk-th smallest of the lanes'
+    // minima is at or above the kk-th smallest key (the kk lanes at or below
+    // it each hold a distinct key no larger), so the keys at or under it
+    // contain the top-kk; when they are at most 64, one sort across the wave
+    // of (key, id) ranks them directly.  Otherwise the radix select below.
+    bool fast = false;
+    if (kk <= 64 && c >= kk) {
+        // keys of batch `base` (the first from registers, the rest re-read
+        // from the buffer, just written, so from L2); past c all ones
+        auto batch = [&](int base, unsigned (&v)[kSelB]) {
+#pragma unroll
+            for (int k = 0; k < kSelB; ++k) {
+                const int t = base + lane + 64 * k;
+                v[k] = (base == 0) ? (t < c ? key0[k] : 0xFFFFFFFFu) : (t < c ? key_at(t) : 0xFFFFFFFFu);
+            }
+        };
+        unsigned mn = 0xFFFFFFFFu;
+        for (int base = 0; base < c; base += 64 * kSelB) {
+            unsigned v[kSelB];
+            batch(base, v);
+#pragma unroll
+            for (int k = 0; k < kSelB; ++k) mn = min(mn, v[k]);
+        }
+        const unsigned long long ms = wave_sort_u64(((unsigned long long)mn << 32) | (unsigned)lane, lane);
+        const unsigned T = (unsigned)__shfl((int)(unsigned)(ms >> 32), kk - 1);
+        unsigned m = 0;
+        for (int base = 0; base < c; base += 64 * kSelB) {
+            unsigned v[kSelB];
+            batch(base, v);
+#pragma unroll
+            for (int k = 0; k < kSelB; ++k) m += (unsigned)__popcll(__ballot(base + lane + 64 * k < c && v[k] <= T));
+        }
+        if (m <= 64) {
+            fast = true;
+            unsigned* ck = hist[w];                      // keys of the candidates [0, 64), positions [64, 128)
+            const unsigned long long below = (1ull << lane) - 1ull;
+            unsigned run = 0;
+            for (int base = 0; base < c; base += 64 * kSelB) {
+                unsigned v[kSelB];
+                batch(base, v);
+#pragma unroll
+                for (int k = 0; k < kSelB; ++k) {
+                    const bool p = base + lane + 64 * k < c && v[k] <= T;
+                    const unsigned long long bal = __ballot(p);
+                    if (p) {
+                        const unsigned pos = run + (unsigned)__popcll(bal & below);
+                        ck[pos] = v[k];
+                        ck[64 + pos] = (unsigned)(base + lane + 64 * k);
+                    }
+                    run += (unsigned)__popcll(bal);
+                }
+            }
+            wave_lds_sync();
+            unsigned long long cv = ~0ull;               // past the candidates: above every (key, id)
+            if (lane < (int)m)
+                cv = ((unsigned long long)ck[lane] << 32) | (mode == 1 ? (unsigned)bi[ck[64 + lane]] : (unsigned)lane);
+            wave_lds_sync();
+            cv = wave_sort_u64(cv, lane);
+            kth = (unsigned)__shfl((int)(unsigned)(cv >> 32), kk - 1);
+            if (mode == 1) {                             // the top-kk by (est, id), in order
+                if (lane < kk) {
+                    out_ids[q * kk + lane] = (int)(unsigned)cv;
+                    out_est[q * kk + lane] = key2f((unsigned)(cv >> 32));
+                }
+                return;
+            }
+        }
+    }
+    if (!fast && c >= kk) {
         unsigned prefix = 0, mask = 0, kr = (unsigned)kk;
         for (int pass = 0; pass < 4; ++pass) {
             const int shift = 24 - 8 * pass;

@@ -259,6 +259,38 @@ def test_scan_exact_ties_by_id(kk, sizes, small):
     ix.close()
 
 
+@pytest.mark.parametrize("small", [False, True], ids=["pipeline", "small-batch"])
+@pytest.mark.parametrize("kk", [1, 7, 22, 64])
+def test_scan_small_tie_groups(kk, small):
+    """Members come in groups of three copies of one code row with the same
+    factors, so estimates tie in threes and the kk-th often falls inside a
+    group: the top-kk must take its smallest ids (reading C-16).  Buffers
+    stay under 1024 entries and kk <= 64, the case the select ranks with
+    one sort across the wave."""
+    say("scan small tie groups kk", kk, "small", small)
+    dp, B, nl = 128, 4, 3
+    sizes = np.array([300, 240, 180])
+    off, ids, codes, fa, fr, crot = synth.random_index(int(sizes.sum()), nl, dp, B, seed=90 + kk, sizes=sizes)
+    for l in range(nl):
+        for lo in range(off[l], off[l + 1], 3):
+            hi = min(lo + 3, off[l + 1])
+            codes[lo:hi] = codes[lo]
+            fa[lo:hi] = fa[lo]
+            fr[lo:hi] = fr[lo]
+    qrot = synth.random_rotated(20, dp, seed=91)
+    probes = np.tile(np.arange(nl, dtype=np.int32), (20, 1))
+    P = synth.haar_orthogonal(dp, seed=3).astype(np.float32)
+    ix = erq.Index(dp, B, nl, dev(P))
+    ix.import_(dev(off), dev(ids), dev(codes), dev(fa), dev(fr), dev(np.zeros((nl, dp), np.float32)), dev(crot))
+    ix.set_small_batch(32 if small else 0)
+    gi, ge = ix.scan(dev(qrot), dev(probes), kk)
+    gi, ge = gi.cpu().numpy(), ge.cpu().numpy()
+    oi, oe = oracle.search(off, ids, codes, fa, fr, crot, qrot, probes, B, kk, est_mode=0)
+    np.testing.assert_array_equal(gi, oi)
+    _compare_topk(gi, ge, oi, oe, CandTerms(off, ids, codes, fa, fr, crot, qrot, probes, B))
+    ix.close()
+
+
 def test_scan_many_queries_per_list():
     """More than 32 queries per list (several query tiles per list)."""
     say("scan many queries")
