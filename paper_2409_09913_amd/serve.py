@@ -154,6 +154,7 @@ class Server:
                 pdev=torch.empty((3, max_batch), dtype=torch.int32, device=dev),
                 phost=torch.empty((3, max_batch), dtype=torch.int32).pin_memory()))
         self.queue: deque[Request] = deque()
+        self._need_memo: dict = {}             # workspace bytes by (queries, nprobe, k, rerank_k)
         self.t0 = time.perf_counter()
         self.batches = 0
         self.mixed_batches = 0                 # batches whose requests differ in (k, nprobe, rerank_k)
@@ -162,7 +163,13 @@ class Server:
         return time.perf_counter() - self.t0
 
     def _need(self, m: int, np_: int, k: int, rr: int) -> int:
-        return self.index.search_workspace_size(m, np_, k, rr)
+        key = (m, np_, k, rr)
+        n = self._need_memo.get(key)
+        if n is None:
+            if len(self._need_memo) > 65536:
+                self._need_memo.clear()
+            n = self._need_memo[key] = self.index.search_workspace_size(m, np_, k, rr)
+        return n
 
     def submit(self, req: Request):
         k, nprobe, rr = req.key
@@ -212,10 +219,11 @@ class Server:
         slot.stream.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(slot.stream):
             slot.pdev[:, :m].copy_(slot.phost[:, :m], non_blocking=True)
-            o2 = 0
-            for r in batch:
-                slot.qbuf[o2:o2 + r.q.shape[0]].copy_(r.q, non_blocking=True)
-                o2 += r.q.shape[0]
+            # the batch's queries gathered by one copy launch
+            if len(batch) == 1:
+                slot.qbuf[:m].copy_(batch[0].q, non_blocking=True)
+            else:
+                torch.cat([r.q for r in batch], dim=0, out=slot.qbuf[:m])
             # outputs come from torch's caching allocator (no device allocation
             # once warm); the workspace is the batch's block of the pool
             out = (torch.empty((m, k), dtype=torch.int64, device=slot.qbuf.device),
