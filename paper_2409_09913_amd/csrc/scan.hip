@@ -869,7 +869,7 @@ __global__ __launch_bounds__(kThreads, 2) void scan2_kernel(
 //           estimates of distinct members, so still a valid bound).
 // ---------------------------------------------------------------------------
 constexpr int kSelQ = 4;               // queries (waves) per block
-constexpr int kSelB = 16;              // entries per lane loaded together (1024 per wave)
+constexpr int kSelB = 8;               // entries per lane loaded together (512 per wave)
 
 // LDS written by some lanes of a wave and read by others: wait for the
 // wave's LDS operations and keep the compiler from moving accesses across
@@ -986,14 +986,16 @@ __device__ inline void wave_bitonic(float* se, int* si, int m, int lane) {
 // quarter full, the entries above the new bound), 3 (after the first bound)
 // keeps the entries at or under the new bound and drops the padding, and
 // records what is left as the count before the first round
+template <int MODE>
 __global__ __launch_bounds__(256) void buf_select_kernel(int32_t* __restrict__ gcnt,
                                                          int32_t* __restrict__ gprev,
                                                          float* __restrict__ gbuf_e,
                                                          int32_t* __restrict__ gbuf_i, int64_t nq, int kk,
-                                                         int mode, int post, unsigned* __restrict__ tau_key,
+                                                         int post, unsigned* __restrict__ tau_key,
                                                          int32_t* __restrict__ ovf, int64_t* __restrict__ out_ids,
                                                          float* __restrict__ out_est, int32_t* __restrict__ any_over)
 {
+    constexpr int mode = MODE;
     __shared__ unsigned hist[kSelQ][256];
     // mode 1: the selected entries of each wave, kS = pow2 >= max(kk, 64) slots
     extern __shared__ __align__(16) char sel_smem[];
@@ -2340,9 +2342,16 @@ int run_scan(Index* ix, const float* qrot, int64_t qld, int64_t nq, const int32_
     };
     const size_t sel_lds = (size_t)kSelQ * sel_slots(kk) * (sizeof(float) + sizeof(int));
     auto select = [&](int mode, int post, int64_t* oi, float* oe) {
-        hipLaunchKernelGGL(buf_select_kernel, dim3((unsigned)((nq + kSelQ - 1) / kSelQ)), dim3(256),
-                           mode == 1 ? sel_lds : 0, st, gcnt,
-                           gprev, gbe, gbi, nq, kk, mode, post, tkey, ovf, oi, oe, mode == 1 ? anyf2 : anyf);
+        const dim3 grid((unsigned)((nq + kSelQ - 1) / kSelQ));
+        if (mode == 1)
+            hipLaunchKernelGGL(buf_select_kernel<1>, grid, dim3(256), sel_lds, st, gcnt, gprev, gbe, gbi, nq, kk,
+                               post, tkey, ovf, oi, oe, anyf2);
+        else if (mode == 2)
+            hipLaunchKernelGGL(buf_select_kernel<2>, grid, dim3(256), 0, st, gcnt, gprev, gbe, gbi, nq, kk, post,
+                               tkey, ovf, oi, oe, anyf);
+        else
+            hipLaunchKernelGGL(buf_select_kernel<0>, grid, dim3(256), 0, st, gcnt, gprev, gbe, gbi, nq, kk, post,
+                               tkey, ovf, oi, oe, anyf);
         return hipGetLastError();
     };
     const int qpiB = ix->qplanes == 2 ? kQT : scan_nqt(ix) * kQT;   // queries per item of the launched kernel
@@ -2380,8 +2389,8 @@ int run_scan(Index* ix, const float* qrot, int64_t qld, int64_t nq, const int32_
                                     ExactOut{small_s, gcnt, gbe, gbi});
         if (e == hipSuccess) {
             const size_t sel_lds0 = (size_t)kSelQ * sel_slots(kk) * (sizeof(float) + sizeof(int));
-            hipLaunchKernelGGL(buf_select_kernel, dim3((unsigned)((nq + kSelQ - 1) / kSelQ)), dim3(256), sel_lds0, st,
-                               gcnt, gprev, gbe, gbi, nq, kk, 1, 0, tkey, ovf, out_ids, out_est, anyf2);
+            hipLaunchKernelGGL(buf_select_kernel<1>, dim3((unsigned)((nq + kSelQ - 1) / kSelQ)), dim3(256), sel_lds0,
+                               st, gcnt, gprev, gbe, gbi, nq, kk, 0, tkey, ovf, out_ids, out_est, anyf2);
             e = hipGetLastError();
         }
         prof_end(pc, st);
