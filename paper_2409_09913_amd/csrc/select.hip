@@ -42,8 +42,18 @@ __global__ __launch_bounds__(kSelThreads) void row_topk_kernel(
     constexpr int RR = R > 0 ? R : 1;
     unsigned kreg[RR];
     if constexpr (R > 0) {
+        if (end - beg == R && ((uintptr_t)(d + beg) & 15) == 0) {
+            // a whole chunk: 16-byte loads, 64 contiguous bytes per thread
+            static_assert(R % 4 == 0, "chunks of whole float4s");
 #pragma unroll
-        for (int u = 0; u < R; ++u) kreg[u] = (beg + u < end) ? f2key(d[beg + u]) : 0u;
+            for (int u = 0; u < R; u += 4) {
+                const float4 v = *(const float4*)(d + beg + u);
+                kreg[u] = f2key(v.x); kreg[u + 1] = f2key(v.y); kreg[u + 2] = f2key(v.z); kreg[u + 3] = f2key(v.w);
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < R; ++u) kreg[u] = (beg + u < end) ? f2key(d[beg + u]) : 0u;
+        }
     }
     auto key_at = [&](int64_t j, int u) -> unsigned {
         if constexpr (R > 0) return kreg[u];
