@@ -2061,7 +2061,9 @@ hipError_t launchB_b(const Index* ix, const ScanArgs& a, const BArgs& b, hipStre
         if constexpr (BITS >= 5) return launchB_n<BITS, 2, true>(ix, a, b, st);
         return hipErrorInvalidValue;
     }
-    if (scan_nqt(ix) == 2) return launchB_n<BITS, 2>(ix, a, b, st);
+    // the first bound takes one query tile per item: its items hold the few
+    // queries whose nearest lists coincide
+    if (scan_nqt(ix) == 2 && !b.dense) return launchB_n<BITS, 2>(ix, a, b, st);
     return launchB_n<BITS, 1>(ix, a, b, st);
 }
 
@@ -2408,7 +2410,8 @@ int run_scan(Index* ix, const float* qrot, int64_t qld, int64_t nq, const int32_
     auto scan_round = [&](int rlo, int rhi, const int32_t* qmask, int dense, const int32_t* gate, int vs,
                           bool reuse = false) {
         const int vch = dense ? 0 : (two ? kVch2 : kVch);
-        hipError_t er = build_pairs(rlo, rhi, qmask, qpiB, vch, dense ? 0 : vs, gate, reuse);
+        const int qpi = (dense && ix->qplanes != 2) ? kQT : qpiB;   // queries per item of the launched kernel
+        hipError_t er = build_pairs(rlo, rhi, qmask, qpi, vch, dense ? 0 : vs, gate, reuse);
         if (er != hipSuccess) return er;
         ScanArgs b{qa, poff, pq, ps, ioff, desc, gridB, kk};
         BArgs bb{tkey, gcnt, gbe, gbi, work, vch, dense, nprobe, prof_stats_on() ? redo + 1 : nullptr};
