@@ -81,13 +81,28 @@ class Request:
     nprobe: int
     rerank_k: int = 0
     arrival: float = 0.0       # seconds, on the server's clock
-    ids: torch.Tensor | None = None
-    dist: torch.Tensor | None = None
     done: float | None = None
+    _res: tuple | None = None  # (the batch's output tensors, first row, end row), set when the batch retires
 
     @property
     def key(self):
         return (self.k, self.nprobe, self.rerank_k)
+
+    # the request's rows of its batch's outputs, sliced on access (the
+    # serving loop does no tensor work per request when a batch retires)
+    @property
+    def ids(self) -> torch.Tensor | None:
+        if self._res is None:
+            return None
+        out, a, b = self._res
+        return out[0][a:b, :self.k]
+
+    @property
+    def dist(self) -> torch.Tensor | None:
+        if self._res is None:
+            return None
+        out, a, b = self._res
+        return out[1][a:b, :self.k]
 
 
 class _Pool:
@@ -247,8 +262,7 @@ class Server:
             if i == 0:
                 out[0].record_stream(cur)
                 out[1].record_stream(cur)
-            a, b = slot.offsets[i], slot.offsets[i + 1]
-            r.ids, r.dist, r.done = out[0][a:b, :r.k], out[1][a:b, :r.k], t
+            r._res, r.done = (out, int(slot.offsets[i]), int(slot.offsets[i + 1])), t
         self.pool.release(*slot.block)
         slot.reqs, slot.block, slot.busy = [], None, False
 
