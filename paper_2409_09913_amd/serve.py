@@ -21,6 +21,7 @@ only moves tensors and events.
 """
 from __future__ import annotations
 
+import gc
 import time
 from collections import deque
 from dataclasses import dataclass, field
@@ -304,15 +305,24 @@ def poisson_run(server: Server, queries: torch.Tensor, rate: float, n_requests: 
         npr = int(nprobes[kr]) if isinstance(nprobes, dict) else int(g.choice(nprobes))
         reqs.append(Request(i, queries[lo:lo + per_request], kr, npr, rr, arrival=float(arrivals[i])))
     torch.cuda.synchronize()
-    server.t0 = time.perf_counter()
-    i = 0
-    while i < len(reqs) or server.queue or any(s.busy for s in server.slots):
-        t = server.now()
-        while i < len(reqs) and reqs[i].arrival <= t:
-            server.submit(reqs[i])
-            i += 1
-        server.step()
-    torch.cuda.synchronize()
+    # no cyclic garbage collection inside the timed loop: a full collection
+    # over the live tensors and requests pauses the host for milliseconds
+    gc_on = gc.isenabled()
+    gc.collect()
+    gc.disable()
+    try:
+        server.t0 = time.perf_counter()
+        i = 0
+        while i < len(reqs) or server.queue or any(s.busy for s in server.slots):
+            t = server.now()
+            while i < len(reqs) and reqs[i].arrival <= t:
+                server.submit(reqs[i])
+                i += 1
+            server.step()
+        torch.cuda.synchronize()
+    finally:
+        if gc_on:
+            gc.enable()
     lat = np.array([(r.done - r.arrival) * 1e3 for r in reqs])
     span = max(r.done for r in reqs) - reqs[0].arrival
     return reqs, float(np.percentile(lat, 50)), float(np.percentile(lat, 99)), n_requests * per_request / span
