@@ -1584,11 +1584,42 @@ __global__ __launch_bounds__(256) void qprep_kernel(const float* __restrict__ qr
     const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (q >= nq) return;
     const float* qv = qrot + q * ld;
+    // rows of whole 256-float blocks, 16-byte aligned: four consecutive
+    // coordinates per lane and access (same arithmetic per coordinate)
+    const bool vec = (dp & 255) == 0 && (((uintptr_t)qv) & 15) == 0;
     float amax = 0.0f;
-    for (int i = lane; i < dp; i += 64) amax = fmaxf(amax, fabsf(qv[i]));
+    if (vec) {
+        for (int i = 4 * lane; i < dp; i += 256) {
+            const float4 v = *(const float4*)(qv + i);
+            amax = fmaxf(fmaxf(amax, fmaxf(fabsf(v.x), fabsf(v.y))), fmaxf(fabsf(v.z), fabsf(v.w)));
+        }
+    } else {
+        for (int i = lane; i < dp; i += 64) amax = fmaxf(amax, fabsf(qv[i]));
+    }
     for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o));
     const float inv = (amax > 0.0f) ? __fdiv_rn(127.0f, amax) : 0.0f;
     int ssum = 0, slo = 0;
+    if (vec) {
+        for (int i = 4 * lane; i < dp; i += 256) {
+            const float4 v = *(const float4*)(qv + i);
+            const float x[4] = {v.x, v.y, v.z, v.w};
+            uint32_t hi = 0, lo = 0;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const float t = x[c] * inv;
+                const int a = max(-127, min(127, (int)rintf(t)));
+                hi |= (uint32_t)(uint8_t)(int8_t)a << (8 * c);
+                ssum += a;
+                if (qlo) {
+                    const int b = max(-127, min(127, (int)rintf((t - (float)a) * 254.0f)));
+                    lo |= (uint32_t)(uint8_t)(int8_t)b << (8 * c);
+                    slo += b;
+                }
+            }
+            *(uint32_t*)(qint + q * dp + i) = hi;
+            if (qlo) *(uint32_t*)(qlo + q * dp + i) = lo;
+        }
+    } else
     for (int i = lane; i < dp; i += 64) {
         const float t = qv[i] * inv;
         int v = (int)rintf(t);
@@ -1713,13 +1744,14 @@ __global__ __launch_bounds__(256) void scan1_fac_kernel(const uint8_t* __restric
 __global__ void fill_dense_kernel(float* __restrict__ gbuf_e, int64_t nq, int32_t* __restrict__ gcnt,
                                   unsigned* __restrict__ tau_key, int32_t* __restrict__ redo)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // 4 slots per thread
     constexpr int W = kDenseR * kDenseV;
     if (i < 3) redo[i] = 0;                        // counters: fallback pairs, two-stage groups, skipped groups
-    if (i >= nq * W) return;
-    const int64_t q = i / W;
-    gbuf_e[q * kCapQ + (i - q * W)] = __builtin_huge_valf();
-    if (i - q * W == 0) { gcnt[q] = W; tau_key[q] = 0xFFFFFFFFu; }
+    if (4 * i >= nq * W) return;
+    const int64_t q = (4 * i) / W, o = 4 * i - q * W;
+    const float inf = __builtin_huge_valf();
+    *(float4*)(gbuf_e + q * kCapQ + o) = make_float4(inf, inf, inf, inf);
+    if (o == 0) { gcnt[q] = W; tau_key[q] = 0xFFFFFFFFu; }
 }
 
 
@@ -2423,8 +2455,8 @@ int run_scan(Index* ix, const float* qrot, int64_t qld, int64_t nq, const int32_
     // first bound: all estimates of the first kDenseV members of the r0
     // nearest lists, in fixed buffer slots (+inf where a list is shorter)
     const int r0 = std::min(nprobe, kDenseR);
-    hipLaunchKernelGGL(fill_dense_kernel, dim3((unsigned)((nq * kDenseR * kDenseV + th - 1) / th)), dim3(th), 0, st,
-                       gbe, nq, gcnt, tkey, redo);
+    hipLaunchKernelGGL(fill_dense_kernel, dim3((unsigned)((nq * kDenseR * kDenseV / 4 + th - 1) / th)), dim3(th), 0,
+                       st, gbe, nq, gcnt, tkey, redo);
     e = hipGetLastError();
     if (e == hipSuccess) e = scan_round(0, r0, nullptr, 1, nullptr, 0);
     // bound; the buffer keeps the dense estimates at or under it (padding
